@@ -1,0 +1,256 @@
+"""Python access to the FP64 CPU oracle (oracle/lqoracle.c).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the
+benchmark's CPU-baseline leg use this module; the GPU library never does.
+The shared object is compiled with gcc on first use (or by the build step).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lqoracle.c")
+_LIB = os.path.join(_HERE, "liblqoracle.so")
+_lock = threading.Lock()
+_lib = None
+
+ERR_NOT_PD = -2
+ERR_SINGULAR = -3
+ERR_NONFINITE = -4
+
+
+def build(force: bool = False) -> str:
+    """Compile lqoracle.c into liblqoracle.so with gcc (-O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-fno-fast-math",
+                        "-ffp-contract=off", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_P = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int)
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            L = ctypes.CDLL(_LIB)
+            i, d = ctypes.c_int, ctypes.c_double
+            L.oracle_lq_solve.argtypes = [i, i, i] + [_P] * 11 + [_P] * 7 + [_I]
+            L.oracle_lq_solve.restype = i
+            L.oracle_value_element.argtypes = [i, i] + [_P] * 8 + [_P]
+            L.oracle_value_element.restype = i
+            L.oracle_value_terminal.argtypes = [i, _P, _P, _P]
+            L.oracle_value_terminal.restype = None
+            L.oracle_value_combine.argtypes = [i, _P, _P, _P]
+            L.oracle_value_combine.restype = i
+            L.oracle_costate_combine.argtypes = [i, _P, _P, _P]
+            L.oracle_costate_combine.restype = None
+            L.oracle_stateprop_combine.argtypes = [i, _P, _P, _P]
+            L.oracle_stateprop_combine.restype = None
+            L.oracle_lq_adjoint.argtypes = [i, i, i] + [_P] * 11 + [_P] * 2 + [_P] * 11 + [_I]
+            L.oracle_lq_adjoint.restype = i
+            L.oracle_nmpc_cost.argtypes = [i, i, i, d] + [_P] * 7 + [d, d, d, _P]
+            L.oracle_nmpc_cost.restype = d
+            L.oracle_nmpc_expand.argtypes = [i, i, i, d] + [_P] * 6 + [d, d, d, _P, _P] + [_P] * 6
+            L.oracle_nmpc_expand.restype = None
+            L.oracle_nmpc_newton_step.argtypes = ([i, i, i, d] + [_P] * 7 + [d, d, d]
+                                                  + [_P, _P, _P, _P, _P, _P, _P])
+            L.oracle_nmpc_newton_step.restype = i
+            L.oracle_nmpc_solve.argtypes = ([i, i, i, d] + [_P] * 7 + [d, d, _P, i, i, d, d]
+                                            + [_P, _P, _P, _I, _P])
+            L.oracle_nmpc_solve.restype = i
+            _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_P)
+
+
+def _f(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, stage):
+        super().__init__(f"oracle status {code} at stage {stage}")
+        self.code, self.stage = code, stage
+
+
+def lq_solve(A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None, *, check=True):
+    """Sequential Riccati + rollout + co-states (FP64).
+
+    Returns dict with S [T+1,n,n], s [T+1,n], Gamma [T,m,n], gamma [T,m],
+    x [T+1,n], u [T,m], lam [T+1,n], status, fail_k.
+    """
+    A, B, c, Q, R, QT, x0, M, q, r, qT = map(_f, (A, B, c, Q, R, QT, x0, M, q, r, qT))
+    T, n, m = A.shape[0], A.shape[1], B.shape[2]
+    out = {"S": np.zeros((T + 1, n, n)), "s": np.zeros((T + 1, n)),
+           "Gamma": np.zeros((T, m, n)), "gamma": np.zeros((T, m)),
+           "x": np.zeros((T + 1, n)), "u": np.zeros((T, m)), "lam": np.zeros((T + 1, n))}
+    fk = ctypes.c_int(-1)
+    st = lib().oracle_lq_solve(n, m, T, _p(A), _p(B), _p(c), _p(Q), _p(R), _p(M), _p(q), _p(r),
+                               _p(QT), _p(qT), _p(x0), _p(out["S"]), _p(out["s"]),
+                               _p(out["Gamma"]), _p(out["gamma"]), _p(out["x"]), _p(out["u"]),
+                               _p(out["lam"]), ctypes.byref(fk))
+    out["status"], out["fail_k"] = st, fk.value
+    if check and st != 0:
+        raise OracleError(st, fk.value)
+    return out
+
+
+def elem_size(n):
+    return 3 * n * n + 2 * n
+
+
+def unpack_elem(e, n):
+    nn = n * n
+    return {"A": e[:nn].reshape(n, n), "b": e[nn:nn + n], "C": e[nn + n:2 * nn + n].reshape(n, n),
+            "eta": e[2 * nn + n:2 * nn + 2 * n], "J": e[2 * nn + 2 * n:].reshape(n, n)}
+
+
+def pack_elem(A, b, C, eta, J):
+    return np.concatenate([np.ravel(A), np.ravel(b), np.ravel(C), np.ravel(eta), np.ravel(J)]).astype(np.float64)
+
+
+def value_element(A, B, c, Q, R, M=None, q=None, r=None):
+    """eq:value-fun-elem-init (P^{-1}-free form) for one stage."""
+    A, B, c, Q, R, M, q, r = map(_f, (A, B, c, Q, R, M, q, r))
+    n, m = B.shape
+    e = np.zeros(elem_size(n))
+    st = lib().oracle_value_element(n, m, _p(A), _p(B), _p(c), _p(Q), _p(R), _p(M), _p(q), _p(r), _p(e))
+    if st != 0:
+        raise OracleError(st, 0)
+    return e
+
+
+def value_terminal(QT, qT=None):
+    QT, qT = _f(QT), _f(qT)
+    n = QT.shape[0]
+    e = np.zeros(elem_size(n))
+    lib().oracle_value_terminal(n, _p(QT), _p(qT), _p(e))
+    return e
+
+
+def value_combine(e1, e2, n):
+    """eq:value-fun-param: e1 (earlier) (x) e2 (later)."""
+    e1, e2 = _f(e1), _f(e2)
+    out = np.zeros(elem_size(n))
+    st = lib().oracle_value_combine(n, _p(e1), _p(e2), _p(out))
+    if st != 0:
+        raise OracleError(st, 0)
+    return out
+
+
+def costate_combine(e1, e2, n):
+    e1, e2 = _f(e1), _f(e2)
+    out = np.zeros(n + n * n)
+    lib().oracle_costate_combine(n, _p(e1), _p(e2), _p(out))
+    return out
+
+
+def stateprop_combine(e1, e2, n):
+    e1, e2 = _f(e1), _f(e2)
+    out = np.zeros(n + n * n)
+    lib().oracle_stateprop_combine(n, _p(e1), _p(e2), _p(out))
+    return out
+
+
+def lq_adjoint(A, B, c, Q, R, QT, x0, gx, gu, M=None, q=None, r=None, qT=None, *, check=True):
+    """Gradients of L(x, u) with dL/dx = gx [T+1,n], dL/du = gu [T,m] through the LQ solution."""
+    A, B, c, Q, R, QT, x0, gx, gu, M, q, r, qT = map(_f, (A, B, c, Q, R, QT, x0, gx, gu, M, q, r, qT))
+    T, n, m = A.shape[0], A.shape[1], B.shape[2]
+    g = {"A": np.zeros((T, n, n)), "B": np.zeros((T, n, m)), "c": np.zeros((T, n)),
+         "Q": np.zeros((T, n, n)), "R": np.zeros((T, m, m)), "M": np.zeros((T, n, m)),
+         "q": np.zeros((T, n)), "r": np.zeros((T, m)), "QT": np.zeros((n, n)), "qT": np.zeros(n),
+         "x0": np.zeros(n)}
+    fk = ctypes.c_int(-1)
+    st = lib().oracle_lq_adjoint(n, m, T, _p(A), _p(B), _p(c), _p(Q), _p(R), _p(M), _p(q), _p(r),
+                                 _p(QT), _p(qT), _p(x0), _p(gx), _p(gu),
+                                 *[_p(g[k]) for k in ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0")],
+                                 ctypes.byref(fk))
+    if check and st != 0:
+        raise OracleError(st, fk.value)
+    return g
+
+
+# ----------------------------------------------------------------------------
+# Newton / interior point for the tanh model
+# ----------------------------------------------------------------------------
+
+def _prob_args(p):
+    f = _f
+    return (p.nx, p.nu, p.T, float(p.h), _p(f(p.W)), _p(f(p.Bm)), _p(f(p.Q)), _p(f(p.R)),
+            _p(f(p.QT)), _p(f(p.xref)))
+
+
+def nmpc_cost(p, u, mu):
+    u = _f(u)
+    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
+    return lib().oracle_nmpc_cost(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT),
+                                  _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu), _p(u))
+
+
+def nmpc_expand(p, x, u, mu):
+    x, u = _f(x), _f(u)
+    W, Bm, Q, R, QT, xref = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref))
+    T, n, m = p.T, p.nx, p.nu
+    o = {"A": np.zeros((T, n, n)), "B": np.zeros((T, n, m)), "lam": np.zeros((T + 1, n)),
+         "P": np.zeros((T, n, n)), "Rh": np.zeros((T, m, m)), "d": np.zeros((T, m))}
+    lib().oracle_nmpc_expand(n, m, T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT), _p(xref),
+                             float(p.umin), float(p.umax), float(mu), _p(x), _p(u),
+                             _p(o["A"]), _p(o["B"]), _p(o["lam"]), _p(o["P"]), _p(o["Rh"]), _p(o["d"]))
+    return o
+
+
+def nmpc_rollout(p, u):
+    """Nonlinear rollout (pure numpy, for tests): x [T+1, nx]."""
+    x = np.zeros((p.T + 1, p.nx))
+    x[0] = p.x0
+    for k in range(p.T):
+        x[k + 1] = x[k] + p.h * (np.tanh(p.W @ x[k]) + p.Bm @ u[k])
+    return x
+
+
+def nmpc_newton_step(p, x, u, mu, alpha, nu_lm):
+    """One Alg. 4 iteration; returns (accepted, x, u, alpha, nu_lm, cost, pred, rho)."""
+    x, u = _f(x).copy(), _f(u).copy()
+    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
+    a, nl = ctypes.c_double(alpha), ctypes.c_double(nu_lm)
+    cost, pred, rho = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    acc = lib().oracle_nmpc_newton_step(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R),
+                                        _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax),
+                                        float(mu), ctypes.byref(a), ctypes.byref(nl), _p(x), _p(u),
+                                        ctypes.byref(cost), ctypes.byref(pred), ctypes.byref(rho))
+    return bool(acc), x, u, a.value, nl.value, cost.value, pred.value, rho.value
+
+
+def nmpc_solve(p, mu_levels, iters, alpha0, nu0):
+    """Full IP loop; returns dict(u, x, cost, accept, alpha)."""
+    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
+    u = _f(p.u0).copy()
+    x = np.zeros((p.T + 1, p.nx))
+    mus = np.asarray(mu_levels, np.float64)
+    n_it = len(mus) * iters
+    cost, alph = np.zeros(n_it), np.zeros(n_it)
+    acc = np.zeros(n_it, np.int32)
+    st = lib().oracle_nmpc_solve(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT),
+                                 _p(xref), _p(x0), float(p.umin), float(p.umax), _p(mus), len(mus),
+                                 iters, float(alpha0), float(nu0), _p(u), _p(x), _p(cost),
+                                 acc.ctypes.data_as(_I), _p(alph))
+    if st != 0:
+        raise OracleError(st, -1)
+    return {"u": u, "x": x, "cost": cost, "accept": acc.astype(bool), "alpha": alph}

@@ -1,0 +1,210 @@
+"""Seeded synthetic workloads for the LQ subproblem and the Newton/IP problem.
+
+This module only draws random numbers and packs arrays.  It holds none of the
+solver's arithmetic, so both the CPU oracle's tests and the GPU path's tests and
+benchmark can use it without sharing any method code.
+
+Index convention: stages k = 0..T-1, terminal state x_T (the paper's t = 1..N
+with terminal x_{N+1}; k = t - 1).  All arrays are float64, C-contiguous,
+stage-major with row-major matrices:
+
+    A [T, n, n]   B [T, n, m]   c [T, n]
+    Q [T, n, n]   R [T, m, m]   M [T, n, m] (optional)
+    q [T, n]      r [T, m]      (optional)
+    QT [n, n]     qT [n] (optional)   x0 [n]
+
+Recipe (one generator per instance, draws in this order):
+    Z  = standard_normal((T, n*n + n*m + n))  -> A = I + a_scale*Z_A,
+                                                 B = 0.1*Z_B, c = 0.01*Z_c
+    U  = random((T, n [+ m]))                 -> Q = diag(0.5 + 1.5*U_Q),
+                                                 R = diag(0.1 + 0.9*U_R)
+                                                 (or R = r_fixed*I, no draw)
+    x0 = standard_normal(n)
+    QT = 10*I (no draw)
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+LQ_FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r")
+
+
+@dataclasses.dataclass
+class LQInstance:
+    n: int
+    m: int
+    T: int
+    A: np.ndarray
+    B: np.ndarray
+    c: np.ndarray | None
+    Q: np.ndarray
+    R: np.ndarray
+    QT: np.ndarray
+    x0: np.ndarray
+    M: np.ndarray | None = None
+    q: np.ndarray | None = None
+    r: np.ndarray | None = None
+    qT: np.ndarray | None = None
+
+    def arrays(self):
+        return {k: getattr(self, k) for k in
+                ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0")}
+
+
+def lq_instance(rng: np.random.Generator, n: int, m: int, T: int, *,
+                a_scale: float = 0.05, r_fixed: float | None = None,
+                qt_scale: float = 10.0) -> LQInstance:
+    """One time-varying LQ instance drawn as described in the module docstring."""
+    nn, nm = n * n, n * m
+    Z = rng.standard_normal((T, nn + nm + n))
+    U = rng.random((T, n + (0 if r_fixed is not None else m)))
+    x0 = rng.standard_normal(n)
+    eye = np.eye(n)
+    A = eye[None] + a_scale * Z[:, :nn].reshape(T, n, n)
+    B = 0.1 * Z[:, nn:nn + nm].reshape(T, n, m)
+    c = 0.01 * Z[:, nn + nm:]
+    Q = np.zeros((T, n, n))
+    idx = np.arange(n)
+    Q[:, idx, idx] = 0.5 + 1.5 * U[:, :n]
+    R = np.zeros((T, m, m))
+    jdx = np.arange(m)
+    if r_fixed is not None:
+        R[:, jdx, jdx] = r_fixed
+    else:
+        R[:, jdx, jdx] = 0.1 + 0.9 * U[:, n:]
+    QT = qt_scale * np.eye(n)
+    return LQInstance(n, m, T, np.ascontiguousarray(A), np.ascontiguousarray(B),
+                      np.ascontiguousarray(c), Q, R, QT, np.ascontiguousarray(x0))
+
+
+def lq_instance_general(rng: np.random.Generator, n: int, m: int, T: int, *,
+                        a_scale: float = 0.1, cross: float = 0.2) -> LQInstance:
+    """A dense LQ instance with every optional term present (M, q, r, qT, c).
+
+    Q and R are drawn as random SPD matrices and the cross term M is scaled so
+    that the joint stage Hessian [[Q, M], [M^T, R]] stays positive definite.
+    """
+    inst = lq_instance(rng, n, m, T, a_scale=a_scale)
+    GQ = rng.standard_normal((T, n, n)) / math.sqrt(n)
+    GR = rng.standard_normal((T, m, m)) / math.sqrt(m)
+    Q = np.einsum("tij,tkj->tik", GQ, GQ) + np.eye(n)[None]
+    R = np.einsum("tij,tkj->tik", GR, GR) + 0.5 * np.eye(m)[None]
+    M = cross * rng.standard_normal((T, n, m)) / math.sqrt(n * m)
+    inst.Q = np.ascontiguousarray(Q)
+    inst.R = np.ascontiguousarray(R)
+    inst.M = np.ascontiguousarray(M)
+    inst.q = rng.standard_normal((T, n))
+    inst.r = rng.standard_normal((T, m))
+    GT = rng.standard_normal((n, n)) / math.sqrt(n)
+    inst.QT = GT @ GT.T + np.eye(n)
+    inst.qT = rng.standard_normal(n)
+    return inst
+
+
+# ---------------------------------------------------------------------------
+# Named workloads
+# ---------------------------------------------------------------------------
+
+def cfg0_small(seed: int = 0) -> LQInstance:
+    """n=2, m=1, T=64, A = I + 0.05 N(0,1)."""
+    return lq_instance(np.random.default_rng(seed), 2, 1, 64, a_scale=0.05)
+
+
+def cfg2_long(seed: int = 2, T: int = 16384) -> LQInstance:
+    """Quadrotor-sized long horizon: n=12, m=4, A = I + 0.02 N(0,1), R = 0.1 I."""
+    return lq_instance(np.random.default_rng(seed), 12, 4, T, a_scale=0.02, r_fixed=0.1)
+
+
+def cfg4_batch(seed: int = 4, batch: int = 256, T: int = 4096):
+    """Batch of identical-shape long-horizon instances (n=12, m=4)."""
+    rng = np.random.default_rng(seed)
+    return [lq_instance(rng, 12, 4, T, a_scale=0.02, r_fixed=0.1) for _ in range(batch)]
+
+
+def cfg3_ragged_sizes(seed: int = 3, count: int = 4096, tmin: int = 32, tmax: int = 2048):
+    """Sizes of the ragged batch: T ~ U{tmin..tmax}, n ~ U{2,4,12}, m = max(1, n//3)."""
+    rng = np.random.default_rng(seed)
+    Ts = rng.integers(tmin, tmax + 1, size=count)
+    ns = rng.choice(np.array([2, 4, 12]), size=count)
+    ms = np.maximum(1, ns // 3)
+    return rng, ns.astype(np.int32), ms.astype(np.int32), Ts.astype(np.int32)
+
+
+def cfg3_ragged(seed: int = 3, count: int = 4096, tmin: int = 32, tmax: int = 2048):
+    """The ragged batch itself: sizes from cfg3_ragged_sizes, then one instance each."""
+    rng, ns, ms, Ts = cfg3_ragged_sizes(seed, count, tmin, tmax)
+    return [lq_instance(rng, int(n), int(m), int(T), a_scale=0.05)
+            for n, m, T in zip(ns, ms, Ts)]
+
+
+# ---------------------------------------------------------------------------
+# Packing of a (possibly ragged) batch into the flat stage-major layout
+# ---------------------------------------------------------------------------
+
+def pack(instances) -> dict:
+    """Concatenate a list of LQInstance into the flat packed layout.
+
+    Optional fields are packed only if every instance has them; otherwise the
+    packed field is None.
+    """
+    out = {"n": np.array([i.n for i in instances], np.int32),
+           "m": np.array([i.m for i in instances], np.int32),
+           "T": np.array([i.T for i in instances], np.int32)}
+    for f in ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0"):
+        vals = [getattr(i, f) for i in instances]
+        if any(v is None for v in vals):
+            out[f] = None
+        else:
+            out[f] = np.ascontiguousarray(np.concatenate([v.reshape(-1) for v in vals]))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Newton / interior-point workload: x' = x + h (tanh(W x) + B u), |u| <= 1
+# ---------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class NMPCProblem:
+    nx: int
+    nu: int
+    T: int
+    h: float
+    W: np.ndarray      # [nx, nx]
+    Bm: np.ndarray     # [nx, nu]
+    Q: np.ndarray      # [nx, nx]
+    R: np.ndarray      # [nu, nu]
+    QT: np.ndarray     # [nx, nx]
+    xref: np.ndarray   # [T+1, nx]
+    x0: np.ndarray     # [nx]
+    u0: np.ndarray     # [T, nu] strictly feasible initial controls
+    umin: float = -1.0
+    umax: float = 1.0
+
+
+def nmpc_problem(seed: int = 1, nx: int = 4, nu: int = 1, T: int = 1024,
+                 h: float = 0.02) -> NMPCProblem:
+    """Synthetic tanh-network dynamics with a sinusoidal tracking reference.
+
+    Draw order: W ~ N(0, 1/nx), B ~ N(0, 1), x0 ~ N(0, 0.5^2), u0 ~ N(0, 0.1^2)
+    (clipped to |u| <= 0.9 so that the barrier starts strictly feasible).
+    Q = I, R = 0.1 I, QT = 10 I, ref[k, i] = 0.5 sin(2 pi k / 256 + pi i / 4).
+    """
+    rng = np.random.default_rng(seed)
+    W = rng.standard_normal((nx, nx)) / math.sqrt(nx)
+    Bm = rng.standard_normal((nx, nu))
+    x0 = 0.5 * rng.standard_normal(nx)
+    u0 = np.clip(0.1 * rng.standard_normal((T, nu)), -0.9, 0.9)
+    k = np.arange(T + 1)[:, None]
+    i = np.arange(nx)[None, :]
+    xref = 0.5 * np.sin(2 * math.pi * k / 256.0 + math.pi * i / 4.0)
+    return NMPCProblem(nx, nu, T, h, W, Bm, np.eye(nx), 0.1 * np.eye(nu), 10.0 * np.eye(nx),
+                       np.ascontiguousarray(xref), x0, np.ascontiguousarray(u0))
+
+
+NMPC_MU_LEVELS = (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
+NMPC_ITERS_PER_LEVEL = 10
+NMPC_ALPHA0 = 1e-3
+NMPC_NU0 = 2.0

@@ -1,0 +1,535 @@
+"""Pins of the FP64 CPU oracle against mathematics that does not come from the oracle.
+
+Each test checks the oracle against an independent fact: a dense KKT solve by
+LAPACK, a closed form derived by hand (tests/golden), the discrete algebraic
+Riccati equation solved by SciPy, the Lyapunov recursion, algebraic identities
+of the value-function operator, or central finite differences.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from paper_2409_20027_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def dense_kkt(inst):
+    """Solve the LQ by one dense KKT system (numpy / LAPACK).
+
+    Returns x [T+1,n], u [T,m], lam [T+1,n] with lam the co-states of the
+    Lagrangian in Sec. III-B (lam = -multiplier of G z = g).
+    """
+    n, m, T = inst.n, inst.m, inst.T
+    nz = (T + 1) * n + T * m
+    H = np.zeros((nz, nz))
+    h = np.zeros(nz)
+    xi = lambda k: slice(k * n, (k + 1) * n)
+    ui = lambda k: slice((T + 1) * n + k * m, (T + 1) * n + (k + 1) * m)
+    for k in range(T):
+        H[xi(k), xi(k)] += inst.Q[k]
+        H[ui(k), ui(k)] += inst.R[k]
+        if inst.M is not None:
+            H[xi(k), ui(k)] += inst.M[k]
+            H[ui(k), xi(k)] += inst.M[k].T
+        if inst.q is not None:
+            h[xi(k)] += inst.q[k]
+        if inst.r is not None:
+            h[ui(k)] += inst.r[k]
+    H[xi(T), xi(T)] += inst.QT
+    if inst.qT is not None:
+        h[xi(T)] += inst.qT
+    G = np.zeros(((T + 1) * n, nz))
+    g = np.zeros((T + 1) * n)
+    G[0:n, xi(0)] = np.eye(n)
+    g[0:n] = inst.x0
+    for k in range(T):
+        rows = slice((k + 1) * n, (k + 2) * n)
+        G[rows, xi(k + 1)] = np.eye(n)
+        G[rows, xi(k)] = -inst.A[k]
+        G[rows, ui(k)] = -inst.B[k]
+        if inst.c is not None:
+            g[rows] = inst.c[k]
+    K = np.block([[H, G.T], [G, np.zeros((G.shape[0], G.shape[0]))]])
+    sol = np.linalg.solve(K, np.concatenate([-h, g]))
+    x = sol[:(T + 1) * n].reshape(T + 1, n)
+    u = sol[(T + 1) * n:nz].reshape(T, m)
+    lam = -sol[nz:].reshape(T + 1, n)
+    return x, u, lam, K
+
+
+def solve(inst, **kw):
+    return oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                           M=inst.M, q=inst.q, r=inst.r, qT=inst.qT, **kw)
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+# --------------------------------------------------------------------------
+# P1: Riccati + rollout == dense KKT
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("T", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 1), (3, 2), (4, 4)])
+def test_riccati_matches_dense_kkt(T, n, m):
+    inst = W.lq_instance_general(np.random.default_rng(100 * T + 10 * n + m), n, m, T)
+    o = solve(inst)
+    x, u, lam, _ = dense_kkt(inst)
+    assert rel(o["x"], x) < 1e-12
+    assert rel(o["u"], u) < 1e-12
+    assert rel(o["lam"], lam) < 1e-11
+
+
+def test_riccati_matches_dense_kkt_plain_workload():
+    inst = W.lq_instance(np.random.default_rng(7), 2, 1, 8)
+    o = solve(inst)
+    x, u, lam, _ = dense_kkt(inst)
+    assert rel(o["x"], x) < 1e-12 and rel(o["u"], u) < 1e-12 and rel(o["lam"], lam) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# P2 / golden: closed forms
+# --------------------------------------------------------------------------
+
+def test_one_step_golden():
+    g = json.load(open(os.path.join(GOLDEN, "scalar_riccati.json")))["one_step"]
+    o = oracle.lq_solve(np.array([[[g["a"]]]]), np.array([[[g["b"]]]]), None,
+                        np.array([[[g["q"]]]]), np.array([[[g["r"]]]]), np.array([[g["QT"]]]),
+                        np.array([g["x0"]]))
+    assert o["u"][0, 0] == pytest.approx(g["u0"], abs=1e-15)
+    assert o["x"][1, 0] == pytest.approx(g["x1"], abs=1e-15)
+    assert o["S"][0, 0, 0] == pytest.approx(g["S0"], abs=1e-15)
+    assert o["lam"][0, 0] == pytest.approx(g["lambda0"], abs=1e-15)
+    assert o["lam"][1, 0] == pytest.approx(g["lambda1"], abs=1e-15)
+
+
+def test_stationary_scalar_golden_ratio():
+    g = json.load(open(os.path.join(GOLDEN, "scalar_riccati.json")))["stationary"]
+    T = 200
+    o = oracle.lq_solve(np.full((T, 1, 1), g["a"]), np.full((T, 1, 1), g["b"]), None,
+                        np.full((T, 1, 1), g["q"]), np.full((T, 1, 1), g["r"]), np.zeros((1, 1)),
+                        np.ones(1))
+    assert o["S"][0, 0, 0] == pytest.approx(g["S_inf"], rel=1e-14)
+    assert o["Gamma"][0, 0, 0] == pytest.approx(g["Gamma_inf"], rel=1e-14)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_T1_closed_form(seed):
+    """u_0 = -(R + B'Q_T B)^{-1}(r + B'Q_T(A x0 + c) + B'q_T) when M = 0."""
+    rng = np.random.default_rng(seed)
+    inst = W.lq_instance_general(rng, 3, 2, 1)
+    inst.M = None
+    o = solve(inst)
+    A, B, c, R, QT = inst.A[0], inst.B[0], inst.c[0], inst.R[0], inst.QT
+    u0 = -np.linalg.solve(R + B.T @ QT @ B, inst.r[0] + B.T @ QT @ (A @ inst.x0 + c) + B.T @ inst.qT)
+    assert rel(o["u"][0], u0) < 1e-13
+
+
+def test_dare_long_horizon():
+    """Time-invariant long horizon: S_0 converges to the DARE solution."""
+    rng = np.random.default_rng(11)
+    n, m, T = 4, 2, 3000
+    A = np.eye(n) + 0.3 * rng.standard_normal((n, n))
+    B = rng.standard_normal((n, m))
+    G = rng.standard_normal((n, n))
+    Q = G @ G.T + np.eye(n)
+    R = np.eye(m) * 0.5
+    o = oracle.lq_solve(np.tile(A, (T, 1, 1)), np.tile(B, (T, 1, 1)), None, np.tile(Q, (T, 1, 1)),
+                        np.tile(R, (T, 1, 1)), Q, np.zeros(n))
+    X = scipy.linalg.solve_discrete_are(A, B, Q, R)
+    assert rel(o["S"][0], X) < 1e-10
+    K = -np.linalg.solve(R + B.T @ X @ B, B.T @ X @ A)
+    assert rel(o["Gamma"][0], K) < 1e-9
+
+
+def test_lyapunov_when_B_is_zero():
+    """B = 0: S_k = Q_k + A_k' S_{k+1} A_k, u_k = -R_k^{-1} r_k."""
+    rng = np.random.default_rng(3)
+    inst = W.lq_instance_general(rng, 3, 2, 12)
+    inst.B = np.zeros_like(inst.B)
+    inst.M = None
+    o = solve(inst)
+    S = 0.5 * (inst.QT + inst.QT.T)
+    for k in range(inst.T - 1, -1, -1):
+        S = inst.Q[k] + inst.A[k].T @ S @ inst.A[k]
+        assert rel(o["S"][k], 0.5 * (S + S.T)) < 1e-13
+        assert rel(o["u"][k], -np.linalg.solve(inst.R[k], inst.r[k])) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P7: value matrices
+# --------------------------------------------------------------------------
+
+def test_value_matrices_symmetric_psd():
+    inst = W.cfg0_small()
+    o = solve(inst)
+    S = o["S"]
+    assert np.array_equal(S, np.transpose(S, (0, 2, 1)))
+    for k in range(inst.T + 1):
+        ev = np.linalg.eigvalsh(S[k])
+        assert ev.min() >= -1e-12 * np.abs(ev).max()
+    # lambda = S x + s
+    lam = np.einsum("kij,kj->ki", S, o["x"]) + o["s"]
+    assert rel(o["lam"], lam) < 1e-14
+
+
+def test_not_pd_reports_stage():
+    inst = W.lq_instance(np.random.default_rng(0), 2, 1, 10)
+    inst.R = inst.R.copy()
+    inst.R[6] = -1.0
+    o = solve(inst, check=False)
+    assert o["status"] == oracle.ERR_NOT_PD and o["fail_k"] == 6
+
+
+# --------------------------------------------------------------------------
+# P5 / P6: the value-function operator
+# --------------------------------------------------------------------------
+
+def stage_elements(inst):
+    els = []
+    for k in range(inst.T):
+        els.append(oracle.value_element(inst.A[k], inst.B[k], inst.c[k], inst.Q[k], inst.R[k],
+                                        None if inst.M is None else inst.M[k],
+                                        None if inst.q is None else inst.q[k],
+                                        None if inst.r is None else inst.r[k]))
+    els.append(oracle.value_terminal(inst.QT, inst.qT))
+    return els
+
+
+def random_element(rng, n):
+    G1 = rng.standard_normal((n, n))
+    G2 = rng.standard_normal((n, n))
+    return oracle.pack_elem(np.eye(n) + 0.3 * rng.standard_normal((n, n)), rng.standard_normal(n),
+                            G1 @ G1.T / n, rng.standard_normal(n), G2 @ G2.T / n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_combine_associative(n):
+    rng = np.random.default_rng(40 + n)
+    for _ in range(5):
+        a, b, c = (random_element(rng, n) for _ in range(3))
+        left = oracle.value_combine(oracle.value_combine(a, b, n), c, n)
+        right = oracle.value_combine(a, oracle.value_combine(b, c, n), n)
+        assert rel(left, right) < 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 3, 4])
+def test_combine_identity(n):
+    rng = np.random.default_rng(50 + n)
+    e = random_element(rng, n)
+    ident = oracle.pack_elem(np.eye(n), np.zeros(n), np.zeros((n, n)), np.zeros(n), np.zeros((n, n)))
+    assert np.array_equal(oracle.value_combine(ident, e, n), e)
+    assert np.array_equal(oracle.value_combine(e, ident, n), e)
+
+
+def test_printed_b_rule_is_not_associative():
+    """The b-rule as printed (ending in b_{j,i}) cannot hold: dropping the later
+    element's b breaks the suffix fold == Riccati identity whenever c != 0."""
+    inst = W.lq_instance_general(np.random.default_rng(9), 2, 1, 3)
+    els = stage_elements(inst)
+    n = inst.n
+    acc = els[-1]
+    for e in reversed(els[:-1]):
+        acc = oracle.value_combine(e, acc, n)
+    ok = oracle.unpack_elem(acc, n)
+    # with the later b dropped in the first combine, the linear term changes
+    e1, e2 = els[-3], els[-2]
+    good = oracle.unpack_elem(oracle.value_combine(e1, e2, n), n)
+    bad_b = good["b"] - oracle.unpack_elem(e2, n)["b"]
+    assert np.max(np.abs(bad_b - good["b"])) > 1e-6
+    assert np.isfinite(ok["J"]).all()
+
+
+@pytest.mark.parametrize("n,m,T", [(2, 1, 9), (3, 2, 7), (4, 1, 6)])
+def test_suffix_fold_equals_riccati_on_every_suffix(n, m, T):
+    inst = W.lq_instance_general(np.random.default_rng(60 + n), n, m, T)
+    o = solve(inst)
+    els = stage_elements(inst)
+    acc = els[-1]
+    for k in range(T, -1, -1):
+        if k < T:
+            acc = oracle.value_combine(els[k], acc, n)
+        u = oracle.unpack_elem(acc, n)
+        assert rel(u["J"], o["S"][k]) < 1e-12, k
+        assert rel(-u["eta"], o["s"][k]) < 1e-12, k
+
+
+def test_tree_fold_equals_sequential_fold():
+    """Any association order gives the same suffix (the basis of the scan)."""
+    inst = W.lq_instance_general(np.random.default_rng(77), 3, 2, 15)
+    n = inst.n
+    els = stage_elements(inst)
+    o = solve(inst)
+
+    def tree(lo, hi):
+        if hi - lo == 1:
+            return els[lo]
+        mid = (lo + hi) // 2
+        return oracle.value_combine(tree(lo, mid), tree(mid, hi), n)
+
+    for k in range(0, inst.T + 1, 4):
+        u = oracle.unpack_elem(tree(k, inst.T + 1), n)
+        assert rel(u["J"], o["S"][k]) < 1e-12
+        assert rel(-u["eta"], o["s"][k]) < 1e-12
+
+
+def test_element_equals_paper_inverse_form():
+    """eq:value-fun-elem-init literally (with P^{-1} in q_t and r_t) equals the
+    P^{-1}-free element, for the paper's LQ (c = q = 0, linear u-term d)."""
+    rng = np.random.default_rng(5)
+    n, m = 3, 2
+    for _ in range(5):
+        A = np.eye(n) + 0.2 * rng.standard_normal((n, n))
+        B = rng.standard_normal((n, m))
+        G = rng.standard_normal((n, n))
+        P = G @ G.T + np.eye(n)
+        H = rng.standard_normal((m, m))
+        Rt = H @ H.T + np.eye(m)
+        M = 0.3 * rng.standard_normal((n, m))
+        d = rng.standard_normal(m)
+        Ri = np.linalg.inv(Rt)
+        qt = -np.linalg.solve(Rt - M.T @ np.linalg.solve(P, M), d)
+        rt = -np.linalg.solve(P, M @ qt)
+        paper = {"A": A - B @ Ri @ M.T, "J": P - M @ Ri @ M.T, "C": B @ Ri @ B.T,
+                 "eta": (P - M @ Ri @ M.T) @ rt, "b": B @ Ri @ M.T @ rt + B @ qt}
+        mine = oracle.unpack_elem(oracle.value_element(A, B, None, P, Rt, M, None, d), n)
+        for key in paper:
+            assert rel(mine[key], paper[key]) < 1e-12, key
+
+
+# --------------------------------------------------------------------------
+# Co-state and state-propagation operators (Sec. III-B, III-D)
+# --------------------------------------------------------------------------
+
+def test_costate_scan_equals_recursion():
+    rng = np.random.default_rng(8)
+    n, T = 3, 10
+    F = np.eye(n)[None] + 0.2 * rng.standard_normal((T, n, n))
+    g = rng.standard_normal((T, n))
+    lamT = rng.standard_normal(n)
+    lam = np.zeros((T + 1, n))
+    lam[T] = lamT
+    for k in range(T - 1, -1, -1):
+        lam[k] = g[k] + F[k].T @ lam[k + 1]
+    # elements; the last folds in lam_T with F = 0 (eq:co-state-final-elem-init)
+    els = [np.concatenate([g[k], F[k].ravel()]) for k in range(T - 1)]
+    els.append(np.concatenate([g[T - 1] + F[T - 1].T @ lamT, np.zeros(n * n)]))
+    acc = els[-1]
+    for k in range(T - 1, -1, -1):
+        if k < T - 1:
+            acc = oracle.costate_combine(els[k], acc, n)
+        assert rel(acc[:n], lam[k]) < 1e-13
+
+
+def test_stateprop_scan_equals_rollout():
+    rng = np.random.default_rng(9)
+    n, T = 3, 12
+    F = np.eye(n)[None] + 0.2 * rng.standard_normal((T, n, n))
+    e = rng.standard_normal((T, n))
+    x0 = rng.standard_normal(n)
+    x = [x0]
+    for k in range(T):
+        x.append(F[k] @ x[-1] + e[k])
+    els = [np.concatenate([np.zeros(n * n), F[0] @ x0 + e[0]])]  # eq:state-prop-init-elem-init
+    els += [np.concatenate([F[k].ravel(), e[k]]) for k in range(1, T)]
+    acc = els[0]
+    for k in range(1, T + 1):
+        if k > 1:
+            acc = oracle.stateprop_combine(acc, els[k - 1], n)
+        assert rel(acc[n * n:], x[k]) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# P8: adjoint
+# --------------------------------------------------------------------------
+
+FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0")
+
+
+def loss_of(inst):
+    o = solve(inst)
+    return float(np.sum(o["x"] ** 2) + np.sum(o["u"] ** 2))
+
+
+def perturb(inst, dirs, eps):
+    import copy
+    p = copy.deepcopy(inst)
+    for f in FIELDS:
+        setattr(p, f, getattr(inst, f) + eps * dirs[f])
+    return p
+
+
+def random_dirs(rng, inst):
+    dirs = {}
+    for f in FIELDS:
+        d = rng.standard_normal(getattr(inst, f).shape)
+        if f in ("Q", "R", "QT"):
+            d = 0.5 * (d + np.swapaxes(d, -1, -2))
+        dirs[f] = d
+    nrm = np.sqrt(sum(np.sum(v * v) for v in dirs.values()))
+    return {f: v / nrm for f, v in dirs.items()}
+
+
+def grads(inst):
+    o = solve(inst)
+    return oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                             2 * o["x"], 2 * o["u"], M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+
+
+def test_adjoint_matches_central_fd():
+    inst = W.lq_instance_general(np.random.default_rng(21), 3, 2, 6)
+    g = grads(inst)
+    rng = np.random.default_rng(22)
+    for _ in range(16):
+        d = random_dirs(rng, inst)
+        h = 1e-6
+        fd = (loss_of(perturb(inst, d, h)) - loss_of(perturb(inst, d, -h))) / (2 * h)
+        an = sum(np.sum(g[f] * d[f]) for f in FIELDS)
+        assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)
+
+
+def test_adjoint_matches_dense_kkt_adjoint():
+    """dL/dtheta = -w' dF/dtheta with K w = grad_z L (K symmetric), by LAPACK."""
+    inst = W.lq_instance_general(np.random.default_rng(23), 2, 2, 4)
+    n, m, T = inst.n, inst.m, inst.T
+    x, u, lam, K = dense_kkt(inst)
+    nz = (T + 1) * n + T * m
+    gz = np.concatenate([2 * x.ravel(), 2 * u.ravel(), np.zeros((T + 1) * n)])
+    w = np.linalg.solve(K, gz)
+    wx = w[:(T + 1) * n].reshape(T + 1, n)
+    wnu = w[nz:].reshape(T + 1, n)   # multiplier block (lam = -nu)
+    g = grads(inst)
+    # c_k enters the dynamics row k+1 as -g -> dF/dc = -I in rows of G z - g
+    assert rel(g["c"], -(-wnu[1:])) < 1e-10
+    assert rel(g["x0"], -(-wnu[0])) < 1e-10
+    assert rel(g["q"], -wx[:T]) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# P9-P11: Newton / interior point
+# --------------------------------------------------------------------------
+
+def small_nmpc(T=40):
+    return W.nmpc_problem(seed=1, T=T)
+
+
+def grad_fd(p, u, mu, h=1e-6):
+    g = np.zeros_like(u)
+    for k in range(u.shape[0]):
+        for i in range(u.shape[1]):
+            up, um = u.copy(), u.copy()
+            up[k, i] += h
+            um[k, i] -= h
+            g[k, i] = (oracle.nmpc_cost(p, up, mu) - oracle.nmpc_cost(p, um, mu)) / (2 * h)
+    return g
+
+
+def test_costate_gradient_is_fd_gradient():
+    """d_k = dH_k/du_k from the co-state pass is the gradient of J_mu(u)."""
+    p = small_nmpc()
+    mu = 1e-2
+    x = oracle.nmpc_rollout(p, p.u0)
+    e = oracle.nmpc_expand(p, x, p.u0, mu)
+    g = grad_fd(p, p.u0, mu)
+    assert rel(e["d"], g) < 1e-7
+
+
+def test_newton_step_solves_regularised_newton_system():
+    """The LQ step du satisfies (Hess J_mu + alpha I) du = -grad J_mu, with the
+    Hessian-vector product taken by central differences of the exact gradient."""
+    p = small_nmpc(T=30)
+    mu, alpha = 1e-2, 0.3
+    u = p.u0
+    x = oracle.nmpc_rollout(p, u)
+    e = oracle.nmpc_expand(p, x, u, mu)
+    Ra = e["Rh"] + alpha * np.eye(p.nu)[None]
+    o = oracle.lq_solve(e["A"], e["B"], None, e["P"], Ra, p.QT, np.zeros(p.nx), r=e["d"])
+    du = o["u"]
+
+    def grad(uu):
+        xx = oracle.nmpc_rollout(p, uu)
+        return oracle.nmpc_expand(p, xx, uu, mu)["d"]
+
+    h = 1e-5
+    Hv = (grad(u + h * du) - grad(u - h * du)) / (2 * h)
+    resid = Hv + alpha * du + e["d"]
+    assert np.max(np.abs(resid)) < 1e-6 * np.max(np.abs(e["d"]))
+
+
+def test_quadraticisation_matches_fd_second_derivative():
+    """P_k (with the lam' d2f/dx2 contraction) is the x-Hessian of H_k."""
+    p = small_nmpc(T=5)
+    u = p.u0
+    x = oracle.nmpc_rollout(p, u)
+    e = oracle.nmpc_expand(p, x, u, 1e-2)
+    k = 2
+    lam1 = e["lam"][k + 1]
+
+    def H(xk):
+        f = xk + p.h * (np.tanh(p.W @ xk) + p.Bm @ u[k])
+        return 0.5 * (xk - p.xref[k]) @ p.Q @ (xk - p.xref[k]) + lam1 @ f
+
+    h = 1e-4
+    n = p.nx
+    Hfd = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            ei, ej = np.eye(n)[i] * h, np.eye(n)[j] * h
+            Hfd[i, j] = (H(x[k] + ei + ej) - H(x[k] + ei - ej) - H(x[k] - ei + ej) + H(x[k] - ei - ej)) / (4 * h * h)
+    assert rel(e["P"][k], Hfd) < 1e-6
+
+
+def test_interior_point_loop_feasible_and_decreasing():
+    """On the benchmark-like tanh problem (unstable open loop, saturating
+    controls) the barrier keeps every iterate strictly feasible and the
+    accepted cost never increases within a barrier level."""
+    p = W.nmpc_problem(seed=1, T=128)
+    out = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    assert np.all(np.abs(out["u"]) < 1.0)
+    c = out["cost"].reshape(len(W.NMPC_MU_LEVELS), -1)
+    assert np.all(np.diff(c, axis=1) <= 1e-12 * np.abs(c[:, 1:]))
+    assert out["accept"].sum() > len(out["accept"]) // 3
+
+
+def benign_nmpc(T=200):
+    import dataclasses
+    p = W.nmpc_problem(seed=1, T=T)
+    return dataclasses.replace(p, W=-np.eye(4) + 0.3 * p.W, Bm=np.ones((4, 1)))
+
+
+def test_interior_point_loop_converges_on_benign_instance():
+    """Stable dynamics, inactive bounds: the loop reaches a stationary point
+    of J_mu at the last barrier level."""
+    p = benign_nmpc()
+    out = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    assert np.all(np.abs(out["u"]) < 1.0)
+    x = oracle.nmpc_rollout(p, out["u"])
+    d = oracle.nmpc_expand(p, x, out["u"], W.NMPC_MU_LEVELS[-1])["d"]
+    assert np.max(np.abs(d)) < 1e-7
+
+
+def test_newton_converges_quadratically_near_solution():
+    """At fixed mu with alpha -> 0, successive gradient norms contract superlinearly."""
+    p = benign_nmpc(T=64)
+    mu = 1e-2
+    u = p.u0.copy()
+    x = oracle.nmpc_rollout(p, u)
+    alpha, nu = 1e-3, 2.0
+    norms = []
+    for _ in range(12):
+        acc, x, u, alpha, nu, *_ = oracle.nmpc_newton_step(p, x, u, mu, alpha, nu)
+        d = oracle.nmpc_expand(p, x, u, mu)["d"]
+        norms.append(np.max(np.abs(d)))
+    small = []
+    for v in norms:   # accepted steps only (a rejected step repeats the value)
+        if 1e-12 < v < 1e-1 and (not small or v != small[-1]):
+            small.append(v)
+    assert len(small) >= 3
+    ratios = [small[i + 1] / small[i] ** 1.5 for i in range(len(small) - 1)]
+    assert max(ratios) < 50.0, norms
