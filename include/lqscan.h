@@ -1,0 +1,243 @@
+/*
+ * lqscan.h -- C ABI of the MI355X (gfx950) parallel-in-time LQ solver.
+ *
+ * The library solves the linear-quadratic subproblem that one Newton step of
+ * the parallel-in-time method of Iacob, Abdulsamad and Saerkkae (arXiv
+ * 2409.20027, Sec. III) reduces to, for one problem or a ragged batch:
+ *
+ *   min  sum_{k<T} [ 1/2 x_k'Q_k x_k + x_k'M_k u_k + 1/2 u_k'R_k u_k + q_k'x_k + r_k'u_k ]
+ *        + 1/2 x_T'Q_T x_T + q_T'x_T
+ *   s.t. x_{k+1} = A_k x_k + B_k u_k + c_k,   x_0 = x0.
+ *
+ * This is the problem eq:linearized-ocp with psi_t of eq:linearized-ocp-param
+ * (paper index t = 1..N is k = t-1 here, N = T, P_t = Q_k, R_t + alpha I = R_k,
+ * d_t = r_k), generalised by a dynamics offset c_k, a state-linear term q_k
+ * and an initial state x0 so that configurations other than the paper's
+ * (c = q = 0, x0 = 0) can be posed.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All numeric arrays are IEEE FP64, on the device, stage-major and packed
+ *   back to back over the instances of the batch in instance order; matrices
+ *   are row-major.  For instance i with sizes (n_i, m_i, T_i) the arrays hold
+ *     A, Q: T_i*n_i*n_i   B, M: T_i*n_i*m_i   R: T_i*m_i*m_i
+ *     c, q: T_i*n_i       r: T_i*m_i
+ *     QT: n_i*n_i         qT, x0: n_i
+ *     S: (T_i+1)*n_i*n_i  s, x, lambda: (T_i+1)*n_i
+ *     Gamma: T_i*m_i*n_i  gamma, u: T_i*m_i
+ *   Pointers documented as nullable may be NULL, meaning "all zero".
+ * - The caller owns every buffer: problem data, outputs, the element buffer
+ *   and the workspace.  The library never allocates, frees or synchronises
+ *   inside a solve call, so every call may be captured into a HIP graph.
+ *   Only lq_plan_create / lq_plan_destroy allocate (small descriptor tables).
+ * - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *   work is enqueued asynchronously on it.
+ * - Argument errors are returned synchronously (LQ_ERR_ARG, LQ_ERR_UNSUPPORTED)
+ *   before anything is enqueued.  Numerical failures are reported per
+ *   instance through the device array `status` (int32, one per instance,
+ *   nullable): 0 means success, otherwise
+ *       status[i] = (-code) | (k << 8)
+ *   with code one of LQ_ERR_NOT_PD / LQ_ERR_SINGULAR / LQ_ERR_NONFINITE and
+ *   k the stage (or segment, for the scan's operator) where it was detected.
+ *   The first failure of an instance is kept; status must be zeroed by the
+ *   caller before the first call that should report into it.  Results of a
+ *   failed instance are unspecified; other instances are unaffected.
+ * - Supported sizes: 1 <= n <= 15, 1 <= m <= 4, T >= 1.
+ * - Calls that share a workspace must not run concurrently.
+ */
+#ifndef LQSCAN_H
+#define LQSCAN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LQ_OK = 0,
+    LQ_ERR_ARG = -1,          /* bad argument (NULL required pointer, size out of range) */
+    LQ_ERR_NOT_PD = -2,       /* R_k or R_k + B'S_{k+1}B not positive definite            */
+    LQ_ERR_SINGULAR = -3,     /* (I + C J) of the scan operator not invertible             */
+    LQ_ERR_NONFINITE = -4,    /* NaN / Inf produced                                        */
+    LQ_ERR_HIP = -5,          /* a HIP runtime call failed                                  */
+    LQ_ERR_WORKSPACE = -6,    /* workspace / element buffer NULL or misaligned             */
+    LQ_ERR_UNSUPPORTED = -7   /* sizes outside the supported range                         */
+} lq_status;
+
+typedef enum {
+    LQ_FP64 = 0,   /* every product and factorisation in FP64                               */
+    LQ_MIXED = 1   /* products in FP32; the (I + C J)^{-1} and Cholesky factorisations and
+                      the symmetrisation of the value matrices in FP64                       */
+} lq_precision;
+
+/* Scan strategy of a plan. */
+typedef enum {
+    LQ_SCAN = 0,        /* segmented associative scan (default)                             */
+    LQ_SEQUENTIAL = 1   /* one segment per instance: the plain sequential recursion         */
+} lq_mode;
+
+typedef struct lq_plan lq_plan;   /* opaque */
+
+/*
+ * Create a plan for a batch of `batch` instances with sizes nx[i], nu[i], T[i]
+ * (host arrays).  `seg_len` is the number of stages folded per segment of the
+ * scan (0 = choose automatically, ignored in LQ_SEQUENTIAL mode).  Allocates
+ * small device descriptor tables on the current device.
+ * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED, LQ_ERR_HIP.
+ */
+lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                         int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out);
+void lq_plan_destroy(lq_plan *plan);
+
+/* Bytes of scratch device memory the solve calls need (256-byte aligned base). */
+size_t lq_plan_workspace_bytes(const lq_plan *plan);
+/* Bytes of the element buffer written by lq_build_elements (256-byte aligned base). */
+size_t lq_plan_elements_bytes(const lq_plan *plan);
+/* Segment length the plan uses (the automatic choice if seg_len was 0). */
+int32_t lq_plan_seg_len(const lq_plan *plan);
+/* Total number of stages sum_i T_i. */
+int64_t lq_plan_total_stages(const lq_plan *plan);
+
+/* Device pointers to the problem data, packed as described above. */
+typedef struct {
+    const double *A, *B, *c;      /* c nullable                 */
+    const double *Q, *R, *M;      /* M nullable                 */
+    const double *q, *r;          /* nullable                   */
+    const double *QT, *qT, *x0;   /* qT nullable                */
+} lq_problem;
+
+/* Value functions and affine control law (device pointers). */
+typedef struct {
+    double *S, *s;                /* V_k(x) = 1/2 x'S_k x + s_k'x + const, k = 0..T  */
+    double *Gamma, *gamma;        /* u_k = Gamma_k x_k + gamma_k,          k = 0..T-1 */
+} lq_value;
+
+/*
+ * lq_build_elements -- the value-function elements nu_t of
+ * eq:value-fun-elem-init, one per stage plus the terminal element nu_{N+1}.
+ * The stage element minimises the stage cost over u_k for a fixed pair
+ * (x_k, x_{k+1}); in the form used here (which never inverts Q_k, unlike the
+ * printed q_t, r_t) it is
+ *   A_e = A - B R^{-1} M',  b = c - B R^{-1} r,  C = B R^{-1} B' = G G',
+ *   J = Q - M R^{-1} M',    eta = -(q - M R^{-1} r),   G = B L^{-T}, R = L L'.
+ * The terminal element is zero except J = Q_T, eta = -q_T.
+ *
+ * Element layout in `elements` (lq_plan_elements_bytes): instance i owns
+ * T_i + 1 consecutive elements (stage k = 0..T_i-1, then the terminal).  An
+ * element is 4 tiles of 16 x 16 doubles (8 KiB):
+ *   tile 0  [[A_e, b], [0, 1]]        (homogeneous (n+1) x (n+1) map)
+ *   tile 1  [[C, 0], [0, 0]]
+ *   tile 2  [[J, -eta], [-eta', c0]]  (c0: constant term, -r'R^{-1}r)
+ *   tile 3  [[G], [0]]                ((n+1) x m factor, C = G G')
+ * zero-padded to 16 x 16, entry (i, j) of a tile stored at double offset
+ *   4 * (j + 16 * (i % 4)) + (i / 4)
+ * within the tile (the register layout of the FP64 16x16x4 matrix
+ * instruction's accumulator, lane-major).  Numerical failure: LQ_ERR_NOT_PD if R_k is not positive
+ * definite (status, stage k).
+ */
+lq_status lq_build_elements(const lq_plan *plan, const lq_problem *prob, double *elements,
+                            int32_t *status, void *stream);
+
+/*
+ * lq_scan_solve -- value functions S_k, s_k (k = 0..T) and the control law of
+ * eq:value-fun-feedback (Gamma, gamma) by the parallel value-function pass
+ * (Alg. 2): the suffix products V_k = nu_k (x) ... (x) nu_{N+1} under the
+ * operator eq:value-fun-param, with S_k = J(V_k), s_k = -eta(V_k).
+ * The scan is segmented: each segment of seg_len stages is folded into one
+ * element, the segment elements are scanned in log2 depth, and inside each
+ * segment the suffix is completed from its right neighbour's value function
+ * by the Bellman step (the operator applied to a stage element and a
+ * terminal-type element).  The gain of eq:value-fun-feedback is read as
+ *   Gamma = -(R + B'S'B)^{-1} (M' + B'S'A),  gamma = -(R + B'S'B)^{-1} (r + B'(S'c + s')).
+ * S_k is symmetrised.  `elements` may be NULL: the element build is then
+ * fused into the scan and nothing is materialised; otherwise it must hold the
+ * output of lq_build_elements for the same problem.
+ * Numerical failures: LQ_ERR_NOT_PD (R_k or R_k + B'S_{k+1}B), LQ_ERR_SINGULAR.
+ */
+lq_status lq_scan_solve(const lq_plan *plan, const lq_problem *prob, const double *elements,
+                        const lq_value *out, void *workspace, int32_t *status, void *stream);
+
+/*
+ * lq_rollout -- state propagation pass (Alg. 3): the closed-loop maps
+ *   x_{k+1} = (A + B Gamma) x_k + (B gamma + c)
+ * composed by a prefix scan (eq:state-prop-comb-rule; the first element
+ * carries x0 as in eq:state-prop-init-elem-init), then u_k = Gamma x_k + gamma
+ * and the co-states lambda_k = S_k x_k + s_k.
+ * Outputs x ((T+1) n), u (T m), lambda ((T+1) n, nullable).
+ */
+lq_status lq_rollout(const lq_plan *plan, const lq_problem *prob, const lq_value *val,
+                     double *x, double *u, double *lambda, void *workspace, int32_t *status,
+                     void *stream);
+
+/* Gradients (device pointers, same packing as lq_problem; NULL = not wanted). */
+typedef struct {
+    double *A, *B, *c, *Q, *R, *M, *q, *r, *QT, *qT, *x0;
+} lq_grads;
+
+/*
+ * lq_adjoint -- reverse-mode derivative of the LQ solution (not in the
+ * paper; implicit differentiation of the KKT system).  Given the loss
+ * gradients gx = dL/dx_k (k = 0..T, (T+1) n) and gu = dL/du_k (T m), the
+ * adjoint is the same LQ with linear terms (gx, gu), c = 0 and x0 = 0; it
+ * reuses S and Gamma: a suffix scan of the affine maps
+ *   s~_k = gx_k + Gamma'gu_k + (A + B Gamma)' s~_{k+1},   s~_T = gx_T,
+ * then gamma~_k = -(R + B'S_{k+1}B)^{-1}(gu_k + B's~_{k+1}), a prefix scan of
+ *   dx_{k+1} = (A + B Gamma) dx_k + B gamma~_k,  dx_0 = 0,
+ * du = Gamma dx + gamma~, dlam = S dx + s~, and per-stage outer products
+ *   dL/dA_k = lam_{k+1} dx_k' + dlam_{k+1} x_k'    dL/dB_k = lam_{k+1} du_k' + dlam_{k+1} u_k'
+ *   dL/dc_k = dlam_{k+1}                           dL/dx0 = dlam_0
+ *   dL/dQ_k = sym(dx_k x_k')   dL/dR_k = sym(du_k u_k')   dL/dM_k = dx_k u_k' + x_k du_k'
+ *   dL/dq_k = dx_k   dL/dr_k = du_k   dL/dQ_T = sym(dx_T x_T')   dL/dq_T = dx_T.
+ * Inputs: the forward solution val (S, s, Gamma, gamma), x, u, lambda.
+ */
+lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value *val,
+                     const double *x, const double *u, const double *lambda,
+                     const double *gx, const double *gu, const lq_grads *grads,
+                     void *workspace, int32_t *status, void *stream);
+
+/*
+ * Diagnostic: one 16 x 16 FP64 tile product D = X Y (+ Z) through the
+ * library's matrix-core tile primitive.  X, Y, Z, D are device pointers to
+ * row-major 16 x 16 arrays (Z nullable).  Used by the test suite to pin the
+ * operand layouts of the matrix instructions.
+ */
+lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z, double *D,
+                              int32_t transpose_x, int32_t transpose_y, void *stream);
+
+/*
+ * Diagnostic phase timing.  Phases of the solve calls, in enqueue order:
+ */
+enum {
+    LQ_PH_BUILD = 0,         /* lq_build_elements                                  */
+    LQ_PH_VALUE_FOLD = 1,    /* value pass: fold of each segment (fused element build) */
+    LQ_PH_VALUE_SCAN = 2,    /* value pass: log-depth scan of the segment elements  */
+    LQ_PH_VALUE_BELLMAN = 3, /* value pass: Bellman steps inside segments + control law */
+    LQ_PH_ROLL_FOLD = 4,     /* rollout: composition of each segment's maps         */
+    LQ_PH_ROLL_SCAN = 5,     /* rollout: log-depth prefix scan                      */
+    LQ_PH_ROLL_APPLY = 6,    /* rollout: states, controls, co-states                */
+    LQ_PH_ADJ_BACK = 7,      /* adjoint: backward linear-term scan (all launches)   */
+    LQ_PH_ADJ_FWD = 8,       /* adjoint: forward state-derivative scan + gradients  */
+    LQ_NPHASE = 9
+};
+/*
+ * lq_plan_set_timing enables event recording around the phases whose bit is
+ * set in `mask` (bit p = phase p; 0 disables) for at most `capacity` phase
+ * launches; it creates the HIP events (this call may allocate).  While
+ * enabled, each solve call records a start and a stop event on its own stream
+ * around every selected phase.  lq_plan_phase_times waits for the recorded
+ * events, writes the summed milliseconds and the number of recorded launches
+ * per phase (arrays of LQ_NPHASE, either nullable) and resets the counters.
+ * Not for use inside HIP graph capture.
+ */
+lq_status lq_plan_set_timing(lq_plan *plan, uint32_t mask, int32_t capacity);
+lq_status lq_plan_phase_times(lq_plan *plan, double *ms, int64_t *count);
+
+/* Library version string. */
+const char *lq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LQSCAN_H */

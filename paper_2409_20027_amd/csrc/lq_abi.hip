@@ -1,0 +1,350 @@
+// lq_abi.hip -- host side: the plan (sizes, offsets, segment decomposition,
+// device descriptor tables, workspace layout) and the C entry points of
+// include/lqscan.h.  Solve calls only enqueue kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "lq_kernels.hpp"
+#include "lqscan.h"
+
+using lqk::InstDesc;
+using lqk::TILE;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// Automatic segment length: about 16 segments at short horizons, at most 16
+// stages per segment at long ones.
+int auto_seg_len(int T)
+{
+    int L = T / 16;
+    if (L < 1) L = 1;
+    if (L > 16) L = 16;
+    return L;
+}
+
+}  // namespace
+
+struct lq_plan {
+    int batch = 0, prec = 0, mode = 0, seg_len_req = 0;
+    int device = 0;
+    std::vector<InstDesc> h_inst;
+    InstDesc *d_inst = nullptr;
+    int32_t *d_seg_start = nullptr;
+    int32_t *d_x_start = nullptr;
+    int64_t *d_elem_start = nullptr;
+    int64_t total_seg = 0, total_x = 0, total_elem = 0, total_stages = 0;
+    int max_nseg = 0;
+    int seg_len_used = 0;
+    // workspace layout (bytes)
+    size_t off_Xa = 0, off_Xb = 0, off_Ya = 0, off_Yb = 0, ws_bytes = 0, el_bytes = 0;
+    // diagnostic phase timing (events created by lq_plan_set_timing)
+    mutable uint32_t tmask = 0;
+    mutable std::vector<hipEvent_t> ev;
+    mutable std::vector<int> ev_phase;
+    mutable size_t ev_used = 0;
+};
+
+// Records events around one phase if its bit is enabled; `fn` enqueues it.
+template <class F>
+static void timed(const lq_plan *p, int phase, hipStream_t st, F fn)
+{
+    const bool on = (p->tmask >> phase) & 1u;
+    size_t slot = p->ev_used;
+    if (on && 2 * (slot + 1) <= p->ev.size()) {
+        (void)hipEventRecord(p->ev[2 * slot], st);
+        fn();
+        (void)hipEventRecord(p->ev[2 * slot + 1], st);
+        p->ev_phase[slot] = phase;
+        p->ev_used = slot + 1;
+    } else {
+        fn();
+    }
+}
+
+static lq_status hip_ok(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_ERR_HIP; }
+
+static lq_status launched()
+{
+    return hipGetLastError() == hipSuccess ? LQ_OK : LQ_ERR_HIP;
+}
+
+extern "C" {
+
+const char *lq_version(void) { return "lqscan 0.1 (gfx950, fp64 tiles)"; }
+
+lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                         int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out)
+{
+    if (!out || batch <= 0 || !nx || !nu || !T) return LQ_ERR_ARG;
+    if (precision != LQ_FP64 && precision != LQ_MIXED) return LQ_ERR_ARG;
+    if (mode != LQ_SCAN && mode != LQ_SEQUENTIAL) return LQ_ERR_ARG;
+    if (seg_len < 0) return LQ_ERR_ARG;
+    *out = nullptr;
+    for (int i = 0; i < batch; ++i) {
+        if (T[i] < 1 || nx[i] < 1 || nu[i] < 1) return LQ_ERR_ARG;
+        if (nx[i] > 15 || nu[i] > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
+    }
+    lq_plan *p = new (std::nothrow) lq_plan();
+    if (!p) return LQ_ERR_ARG;
+    p->batch = batch;
+    p->prec = precision;
+    p->mode = mode;
+    p->seg_len_req = seg_len;
+    (void)hipGetDevice(&p->device);
+    p->h_inst.resize(batch);
+    std::vector<int32_t> seg_start(batch + 1), x_start(batch + 1);
+    std::vector<int64_t> elem_start(batch + 1);
+    int64_t oA = 0, oB = 0, oR = 0, oc = 0, oQT = 0, on = 0, oS = 0, os = 0, oG = 0, og = 0;
+    int64_t seg = 0, el = 0, stages = 0;
+    int max_nseg = 0, lmax = 0;
+    for (int i = 0; i < batch; ++i) {
+        InstDesc &d = p->h_inst[i];
+        const int64_t n = nx[i], m = nu[i], t = T[i];
+        d.n = (int)n;
+        d.m = (int)m;
+        d.T = (int)t;
+        d.L = (mode == LQ_SEQUENTIAL) ? (int)t : (seg_len > 0 ? std::min<int>(seg_len, (int)t) : auto_seg_len((int)t));
+        d.nseg = (int)((t + d.L - 1) / d.L);
+        d.seg0 = (int)seg;
+        d.xbase = (int)(seg + i);
+        d.pad = 0;
+        d.elem0 = el;
+        d.oA = oA; d.oB = oB; d.oR = oR; d.oc = oc; d.oQT = oQT; d.on = on;
+        d.oS = oS; d.os = os; d.oG = oG; d.og = og;
+        seg_start[i] = (int32_t)seg;
+        x_start[i] = (int32_t)(seg + i);
+        elem_start[i] = el;
+        seg += d.nseg;
+        el += t + 1;
+        stages += t;
+        oA += t * n * n; oB += t * n * m; oR += t * m * m; oc += t * n;
+        oQT += n * n; on += n;
+        oS += (t + 1) * n * n; os += (t + 1) * n; oG += t * m * n; og += t * m;
+        max_nseg = std::max(max_nseg, d.nseg);
+        lmax = std::max(lmax, d.L);
+    }
+    if (seg > INT32_MAX / 2) {
+        delete p;
+        return LQ_ERR_UNSUPPORTED;
+    }
+    seg_start[batch] = (int32_t)seg;
+    x_start[batch] = (int32_t)(seg + batch);
+    elem_start[batch] = el;
+    p->total_seg = seg;
+    p->total_x = seg + batch;
+    p->total_elem = el;
+    p->total_stages = stages;
+    p->max_nseg = max_nseg;
+    p->seg_len_used = lmax;
+    // workspace: value scan ping-pong (3 tiles / entry), affine scan ping-pong (1 tile / entry)
+    size_t off = 0;
+    p->off_Xa = off; off = align_up(off + (size_t)p->total_x * 3 * TILE * sizeof(double));
+    p->off_Xb = off; off = align_up(off + (size_t)p->total_x * 3 * TILE * sizeof(double));
+    p->off_Ya = off; off = align_up(off + (size_t)p->total_x * TILE * sizeof(double));
+    p->off_Yb = off; off = align_up(off + (size_t)p->total_x * TILE * sizeof(double));
+    p->ws_bytes = off;
+    p->el_bytes = align_up((size_t)el * 4 * TILE * sizeof(double));
+
+    lq_status st = LQ_OK;
+    if (hipMalloc(&p->d_inst, sizeof(InstDesc) * batch) != hipSuccess ||
+        hipMalloc(&p->d_seg_start, sizeof(int32_t) * (batch + 1)) != hipSuccess ||
+        hipMalloc(&p->d_x_start, sizeof(int32_t) * (batch + 1)) != hipSuccess ||
+        hipMalloc(&p->d_elem_start, sizeof(int64_t) * (batch + 1)) != hipSuccess)
+        st = LQ_ERR_HIP;
+    if (st == LQ_OK)
+        st = hip_ok(hipMemcpy(p->d_inst, p->h_inst.data(), sizeof(InstDesc) * batch, hipMemcpyHostToDevice));
+    if (st == LQ_OK)
+        st = hip_ok(hipMemcpy(p->d_seg_start, seg_start.data(), sizeof(int32_t) * (batch + 1), hipMemcpyHostToDevice));
+    if (st == LQ_OK)
+        st = hip_ok(hipMemcpy(p->d_x_start, x_start.data(), sizeof(int32_t) * (batch + 1), hipMemcpyHostToDevice));
+    if (st == LQ_OK)
+        st = hip_ok(hipMemcpy(p->d_elem_start, elem_start.data(), sizeof(int64_t) * (batch + 1), hipMemcpyHostToDevice));
+    if (st != LQ_OK) {
+        lq_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return LQ_OK;
+}
+
+void lq_plan_destroy(lq_plan *p)
+{
+    if (!p) return;
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    if (p->d_inst) (void)hipFree(p->d_inst);
+    if (p->d_seg_start) (void)hipFree(p->d_seg_start);
+    if (p->d_x_start) (void)hipFree(p->d_x_start);
+    if (p->d_elem_start) (void)hipFree(p->d_elem_start);
+    delete p;
+}
+
+size_t lq_plan_workspace_bytes(const lq_plan *p) { return p ? p->ws_bytes : 0; }
+size_t lq_plan_elements_bytes(const lq_plan *p) { return p ? p->el_bytes : 0; }
+int32_t lq_plan_seg_len(const lq_plan *p) { return p ? p->seg_len_used : 0; }
+int64_t lq_plan_total_stages(const lq_plan *p) { return p ? p->total_stages : 0; }
+
+static bool aligned(const void *p) { return ((uintptr_t)p & (ALIGN - 1)) == 0; }
+
+static lqk::ProbPtrs probptrs(const lq_problem *q)
+{
+    lqk::ProbPtrs P;
+    P.A = q->A; P.B = q->B; P.c = q->c; P.Q = q->Q; P.R = q->R; P.M = q->M;
+    P.q = q->q; P.r = q->r; P.QT = q->QT; P.qT = q->qT; P.x0 = q->x0;
+    return P;
+}
+
+static bool prob_ok(const lq_problem *q)
+{
+    return q && q->A && q->B && q->Q && q->R && q->QT && q->x0;
+}
+
+lq_status lq_build_elements(const lq_plan *p, const lq_problem *prob, double *elements, int32_t *status,
+                            void *stream)
+{
+    if (!p || !prob_ok(prob)) return LQ_ERR_ARG;
+    if (!elements || !aligned(elements)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    timed(p, LQ_PH_BUILD, st, [&] {
+        hipLaunchKernelGGL(lqk::k_build_elements, dim3((unsigned)p->total_elem), dim3(64), 0, st, probptrs(prob),
+                           p->d_inst, p->d_elem_start, p->batch, elements, status);
+    });
+    return launched();
+}
+
+lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                        void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !out || !out->S || !out->s || !out->Gamma || !out->gamma) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
+    double *fin = Xa;
+    if (p->mode == LQ_SEQUENTIAL) {
+        hipLaunchKernelGGL(lqk::k_value_terminal, dim3(p->batch), dim3(64), 0, st, P, p->d_inst, Xa);
+    } else {
+        timed(p, LQ_PH_VALUE_FOLD, st, [&] {
+            hipLaunchKernelGGL(lqk::k_value_fold, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, p->d_inst,
+                               p->d_seg_start, p->batch, elements, Xa, status);
+        });
+        double *in = Xa, *o = Xb;
+        timed(p, LQ_PH_VALUE_SCAN, st, [&] {
+            for (int dd = 1; dd <= p->max_nseg; dd *= 2) {
+                hipLaunchKernelGGL(lqk::k_value_ks, dim3((unsigned)p->total_x), dim3(64), 0, st, p->d_inst,
+                                   p->d_x_start, p->batch, dd, in, o, status);
+                std::swap(in, o);
+            }
+        });
+        fin = in;
+    }
+    timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
+        hipLaunchKernelGGL(lqk::k_value_riccati, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, p->d_inst,
+                           p->d_seg_start, p->batch, fin, V, status);
+    });
+    return launched();
+}
+
+lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *val, double *x, double *u,
+                     double *lambda, void *workspace, int32_t *status, void *stream)
+{
+    (void)status;
+    if (!p || !prob_ok(prob) || !val || !val->S || !val->s || !val->Gamma || !val->gamma || !x || !u)
+        return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
+    double *fin = Ya;
+    if (p->mode == LQ_SEQUENTIAL) {
+        hipLaunchKernelGGL(lqk::k_roll_init, dim3(p->batch), dim3(64), 0, st, P, p->d_inst, Ya);
+    } else {
+        timed(p, LQ_PH_ROLL_FOLD, st, [&] {
+            hipLaunchKernelGGL(lqk::k_roll_fold, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, V, p->d_inst,
+                               p->d_seg_start, p->batch, Ya);
+        });
+        double *in = Ya, *o = Yb;
+        timed(p, LQ_PH_ROLL_SCAN, st, [&] {
+            for (int dd = 1; dd <= p->max_nseg; dd *= 2) {
+                hipLaunchKernelGGL(lqk::k_affine_ks, dim3((unsigned)p->total_x), dim3(64), 0, st, p->d_inst,
+                                   p->d_x_start, p->batch, dd, 0, in, o);
+                std::swap(in, o);
+            }
+        });
+        fin = in;
+    }
+    timed(p, LQ_PH_ROLL_APPLY, st, [&] {
+        hipLaunchKernelGGL(lqk::k_roll_apply, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, V, p->d_inst,
+                           p->d_seg_start, p->batch, fin, x, u, lambda);
+    });
+    return launched();
+}
+
+lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *val, const double *x,
+                     const double *u, const double *lambda, const double *gx, const double *gu,
+                     const lq_grads *grads, void *workspace, int32_t *status, void *stream)
+{
+    (void)p; (void)prob; (void)val; (void)x; (void)u; (void)lambda; (void)gx; (void)gu; (void)grads;
+    (void)workspace; (void)status; (void)stream;
+    return LQ_ERR_UNSUPPORTED;
+}
+
+lq_status lq_plan_set_timing(lq_plan *p, uint32_t mask, int32_t capacity)
+{
+    if (!p || capacity < 0) return LQ_ERR_ARG;
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    p->ev.clear();
+    p->ev_phase.clear();
+    p->ev_used = 0;
+    p->tmask = 0;
+    if (mask == 0 || capacity == 0) return LQ_OK;
+    p->ev.resize(2 * (size_t)capacity);
+    p->ev_phase.resize((size_t)capacity);
+    for (auto &e : p->ev)
+        if (hipEventCreate(&e) != hipSuccess) return LQ_ERR_HIP;
+    p->tmask = mask;
+    return LQ_OK;
+}
+
+lq_status lq_plan_phase_times(lq_plan *p, double *ms, int64_t *count)
+{
+    if (!p) return LQ_ERR_ARG;
+    double acc[LQ_NPHASE] = {0};
+    int64_t cnt[LQ_NPHASE] = {0};
+    for (size_t i = 0; i < p->ev_used; ++i) {
+        if (hipEventSynchronize(p->ev[2 * i + 1]) != hipSuccess) return LQ_ERR_HIP;
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, p->ev[2 * i], p->ev[2 * i + 1]) != hipSuccess) return LQ_ERR_HIP;
+        acc[p->ev_phase[i]] += t;
+        cnt[p->ev_phase[i]] += 1;
+    }
+    p->ev_used = 0;
+    for (int i = 0; i < LQ_NPHASE; ++i) {
+        if (ms) ms[i] = acc[i];
+        if (count) count[i] = cnt[i];
+    }
+    return LQ_OK;
+}
+
+lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z, double *D, int32_t tx,
+                              int32_t ty, void *stream)
+{
+    if (!X || !Y || !D) return LQ_ERR_ARG;
+    hipLaunchKernelGGL(lqk::k_selftest_mm, dim3(1), dim3(64), 0, (hipStream_t)stream, X, Y, Z, D, tx, ty);
+    return launched();
+}
+
+}  // extern "C"

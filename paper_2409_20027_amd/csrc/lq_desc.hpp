@@ -1,0 +1,215 @@
+// lq_desc.hpp -- instance descriptors shared by the host plan and the kernels,
+// plus the loaders that assemble a stage's data into homogeneous tiles.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lq_tile.hpp"
+
+namespace lqk {
+
+// Per-instance sizes and offsets (in doubles) into the packed arrays.
+struct InstDesc {
+    int32_t n, m, T;
+    int32_t nseg;       // segments of this instance
+    int32_t L;          // stages per segment (last one may be shorter)
+    int32_t seg0;       // first global segment index
+    int32_t xbase;      // first index in the scan buffers (seg0 + instance index)
+    int32_t pad;
+    int64_t elem0;      // first element index (T + 1 elements per instance)
+    int64_t oA, oB, oR, oc, oQT, on;   // offsets: A/Q (T n n), B/M (T n m), R (T m m),
+                                       // c/q (T n), QT (n n), qT/x0 (n)
+    int64_t oS, os, oG, og;            // S ((T+1) n n), s/x/lambda ((T+1) n),
+                                       // Gamma (T m n), gamma/u/r (T m)
+};
+
+struct ProbPtrs {
+    const double *A, *B, *c, *Q, *R, *M, *q, *r, *QT, *qT, *x0;
+};
+
+struct ValPtrs {
+    double *S, *s, *G, *g;
+};
+
+// Index of the instance owning global item g, by binary search over the
+// prefix array start[0..batch] (start[0] = 0, start[batch] = total).
+LQK_DEV int find_inst(const int32_t *start, int batch, int64_t g)
+{
+    int lo = 0, hi = batch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if ((int64_t)start[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+LQK_DEV int find_inst64(const int64_t *start, int batch, int64_t g)
+{
+    int lo = 0, hi = batch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Homogeneous stage tiles (n1 = n + 1; the extra coordinate is the constant 1)
+// ---------------------------------------------------------------------------
+
+// A~ = [[A, c], [0, 1]]
+LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    const int n = d.n;
+    Tile t = gload_rm(P.A + d.oA + (int64_t)k * n * n, n, n, n);
+    const int c = tcol();
+    if (c == n) {
+        const double *cc = P.c ? P.c + d.oc + (int64_t)k * n : nullptr;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = trow(r);
+            t.v[r] = (i < n) ? (cc ? cc[i] : 0.0) : (i == n ? 1.0 : 0.0);
+        }
+    }
+    return t;
+}
+
+// B~ = [[B], [0]]   ((n+1) x m)
+LQK_DEV Tile load_Bh(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    return gload_rm(P.B + d.oB + (int64_t)k * d.n * d.m, d.n, d.m, d.m);
+}
+
+// Q~ = [[Q, q], [q', 0]]
+LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    const int n = d.n;
+    Tile t = gload_rm(P.Q + d.oA + (int64_t)k * n * n, n, n, n);
+    if (P.q) {
+        const double *qq = P.q + d.oc + (int64_t)k * n;
+        const int c = tcol();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = trow(r);
+            if (c == n && i < n) t.v[r] = qq[i];
+            if (i == n && c < n) t.v[r] = qq[c];
+        }
+    }
+    return t;
+}
+
+// M~' = [M', r]   (m x (n+1))
+LQK_DEV Tile load_MhT(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    const int n = d.n, m = d.m;
+    Tile t = gload_rm_t(P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr, m, n, m);
+    if (P.r) {
+        const double *rr = P.r + d.og + (int64_t)k * m;
+        const int c = tcol();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = trow(r);
+            if (c == n && a < m) t.v[r] = rr[a];
+        }
+    }
+    return t;
+}
+
+// R (m x m)
+LQK_DEV Tile load_R(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    return gload_rm(P.R + d.oR + (int64_t)k * d.m * d.m, d.m, d.m, d.m);
+}
+
+// Terminal J~ = [[sym(Q_T), q_T], [q_T', 0]]
+LQK_DEV Tile load_terminal_J(const ProbPtrs &P, const InstDesc &d, double *s)
+{
+    const int n = d.n;
+    Tile t = gload_rm(P.QT + d.oQT, n, n, n);
+    t = tsym(t, s);
+    if (P.qT) {
+        const double *qq = P.qT + d.on;
+        const int c = tcol();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = trow(r);
+            if (c == n && i < n) t.v[r] = qq[i];
+            if (i == n && c < n) t.v[r] = qq[c];
+        }
+    }
+    return t;
+}
+
+// The corner tile E_nn (the homogeneous part of a terminal-type A~).
+LQK_DEV Tile corner(int n)
+{
+    Tile t = tzero();
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t.v[r] = (trow(r) == n && c == n) ? 1.0 : 0.0;
+    return t;
+}
+
+// Gamma~ = [Gamma, gamma]   (m x (n+1)) from the control-law outputs.
+LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, int k)
+{
+    const int n = d.n, m = d.m;
+    Tile t = gload_rm(Gam + d.oG + (int64_t)k * m * n, m, n, n);
+    const int c = tcol();
+    if (c == n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int a = trow(r);
+            if (a < m) t.v[r] = gam[d.og + (int64_t)k * m + a];
+        }
+    }
+    return t;
+}
+
+// S~ = [[S, s], [s', 0]] from the value outputs (stage k = 0..T).
+LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
+{
+    const int n = d.n;
+    Tile t = gload_rm(S + d.oS + (int64_t)k * n * n, n, n, n);
+    const double *ss = s + d.os + (int64_t)k * n;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        if (c == n && i < n) t.v[r] = ss[i];
+        if (i == n && c < n) t.v[r] = ss[c];
+    }
+    return t;
+}
+
+// A vector v (length len) held in column `col` of a tile, with an optional
+// homogeneous 1 at row `one_row` (-1 = none).
+LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
+{
+    Tile t = tzero();
+    if (tcol() == col) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = trow(r);
+            t.v[r] = (v && i < len) ? v[i] : (i == one_row ? 1.0 : 0.0);
+        }
+    }
+    return t;
+}
+LQK_DEV void store_vec(double *v, const Tile &t, int len, int col)
+{
+    if (tcol() == col) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = trow(r);
+            if (i < len) v[i] = t.v[r];
+        }
+    }
+}
+
+}  // namespace lqk

@@ -1,0 +1,122 @@
+// lq_rollout.hip -- the state propagation pass (Sec. III-D, Alg. 3) and the
+// generic affine-map scan level shared with the adjoint.
+//
+// An affine map x -> F x + e is the homogeneous matrix [[F, e], [0, 1]], so
+// the operator eq:state-prop-comb-rule is a matrix product and a vector is
+// the constant map [[0, x], [0, 1]] (its last column).  The closed-loop map
+// of stage k is F~_k = A~_k + B~_k Gamma~_k with Gamma~ = [Gamma, gamma].
+// The first element of the prefix scan is the constant map of x0, which is
+// eq:state-prop-init-elem-init.
+//
+//   k_roll_fold   : per segment, Phi_s = F~_{k1-1} ... F~_{k0}; the block of
+//                   segment 0 also writes the x0 element.
+//   k_affine_ks   : one Kogge-Stone level, prefix (Y_s <- Y_s Y_{s-dd}) or
+//                   suffix (Y_s <- Y_s Y_{s+dd}); one tile per entry.
+//   k_roll_apply  : from the state at the segment start, x_{k+1} = F~ x~,
+//                   u_k = Gamma~ x~, lambda_k = S~_k x~ (top rows).
+#include "lq_kernels.hpp"
+
+namespace lqk {
+
+// Closed-loop map F~ = A~ + B~ Gamma~.
+LQK_DEV Tile closed_loop(const ProbPtrs &P, const ValPtrs &V, const InstDesc &d, int k, double *s0,
+                         double *s1)
+{
+    const Tile Ah = load_Ah(P, d, k);
+    const Tile Bh = load_Bh(P, d, k);
+    const Tile Gh = load_Gh(V.G, V.g, d, k);
+    return mma<false, false>(Bh, Gh, Ah, d.m, s0, s1);
+}
+
+__global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
+                                                  const int32_t *__restrict__ seg_start, int batch,
+                                                  double *__restrict__ Y)
+{
+    __shared__ double lds[2 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT;
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n1 = d.n + 1;
+    Tile Phi = tident(n1);
+    for (int k = k0; k < k1; ++k) {
+        const Tile F = closed_loop(P, V, d, k, s0, s1);
+        Phi = mm<false, false>(F, Phi, n1, s0, s1);
+    }
+    gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
+    if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
+}
+
+// One Kogge-Stone level over entries [xbase, xbase + nseg] of each instance.
+// suffix = 0: Y_s <- Y_s Y_{s-dd} for s >= dd;  suffix = 1: Y_s <- Y_s Y_{s+dd}
+// for s + dd <= nseg; other entries are copied.
+__global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ inst,
+                                                  const int32_t *__restrict__ x_start, int batch, int dd,
+                                                  int suffix, const double *__restrict__ Yin,
+                                                  double *__restrict__ Yout)
+{
+    __shared__ double lds[2 * SLOT];
+    const int gx = blockIdx.x;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    const Tile a = gload(Yin + (int64_t)gx * TILE);
+    const bool active = suffix ? (s + dd <= d.nseg) : (s >= dd);
+    if (!active) {
+        gstore(Yout + (int64_t)gx * TILE, a);
+        return;
+    }
+    const int64_t ob = suffix ? gx + dd : gx - dd;
+    const Tile b = gload(Yin + ob * TILE);
+    gstore(Yout + (int64_t)gx * TILE, mm<false, false>(a, b, d.n + 1, lds, lds + SLOT));
+}
+
+__global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
+                                                   const int32_t *__restrict__ seg_start, int batch,
+                                                   const double *__restrict__ Yfin, double *__restrict__ x,
+                                                   double *__restrict__ u, double *__restrict__ lam)
+{
+    __shared__ double lds[2 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT;
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n = d.n, m = d.m, n1 = n + 1;
+    Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
+    for (int k = k0; k < k1; ++k) {
+        store_vec(x + d.os + (int64_t)k * n, X, n, n);
+        const Tile Gh = load_Gh(V.G, V.g, d, k);
+        const Tile U = mm<false, false>(Gh, X, n1, s0, s1);
+        store_vec(u + d.og + (int64_t)k * m, U, m, n);
+        if (lam) {
+            const Tile Sh = load_Sh(V.S, V.s, d, k);
+            store_vec(lam + d.os + (int64_t)k * n, mm<false, false>(Sh, X, n1, s0, s1), n, n);
+        }
+        const Tile Ah = load_Ah(P, d, k);
+        const Tile Bh = load_Bh(P, d, k);
+        X = mma<false, false>(Bh, U, mm<false, false>(Ah, X, n1, s0, s1), m, s0, s1);
+    }
+    if (k1 == d.T) {
+        store_vec(x + d.os + (int64_t)d.T * n, X, n, n);
+        if (lam) {
+            const Tile Sh = load_Sh(V.S, V.s, d, d.T);
+            store_vec(lam + d.os + (int64_t)d.T * n, mm<false, false>(Sh, X, n1, s0, s1), n, n);
+        }
+    }
+}
+
+}  // namespace lqk
+
+namespace lqk {
+// Sequential mode: the scan buffer entry of segment 0 is just the x0 element.
+__global__ __launch_bounds__(64) void k_roll_init(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                  double *__restrict__ Y)
+{
+    const InstDesc d = inst[blockIdx.x];
+    gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
+}
+}  // namespace lqk

@@ -1,0 +1,426 @@
+// lq_value.hip -- the value-function pass (Sec. III-C, Alg. 2) on gfx950.
+//
+// Homogeneous form.  With the constant coordinate appended (n1 = n + 1), a
+// value element (A, b, C, eta, J) of eq:value-fun-elements becomes three
+// (n+1) x (n+1) matrices
+//   A~ = [[A, b], [0, 1]],  C~ = [[C, 0], [0, 0]],  J~ = [[J, -eta], [-eta', const]],
+// and the operator eq:value-fun-param becomes pure matrix algebra:
+//   X = I + C~1 J~2,  A~ = A~2 X^{-1} A~1,  C~ = A~2 X^{-1} C~1 A~2' + C~2,
+//   J~ = A~1' X^{-T} J~2 A~1 + J~1
+// (the b and eta rules of eq:value-fun-param are the last columns of the A~
+// and J~ rules; the constant J~(n, n) never feeds back into S or s).  The
+// value function of stage k is S~_k = J~(nu_k (x) ... (x) nu_{N+1}), i.e.
+// S_k = top-left block and s_k = -eta = last column.
+//
+// Segmented scan, three phases per instance:
+//   1. k_value_fold: each wave folds one segment of L stages right to left
+//      into one element.  A stage element has C = G G' of rank m, so the
+//      operator with a stage element on the left needs only an m x m inverse
+//      (Woodbury):  X^{-1} = I - G W^{-1} G'J^,  W = I + G'J^ G.
+//   2. k_value_ks: Kogge-Stone suffix scan over the segment elements plus the
+//      terminal element, one launch per level, general operator with an
+//      (n+1) x (n+1) Gauss-Jordan inverse.
+//   3. k_value_riccati: inside each segment the suffix is completed from the
+//      right neighbour's value function by the Bellman step (the operator
+//      applied to a stage element and a terminal-type element), which also
+//      yields the control law of eq:value-fun-feedback.
+#include "lq_kernels.hpp"
+
+namespace lqk {
+
+constexpr int ERR_NOT_PD = -2;
+constexpr int ERR_SINGULAR = -3;
+constexpr int ERR_NONFINITE = -4;
+
+struct StageElem {
+    Tile Ab;  // A~ - G N      ((n+1) x (n+1))
+    Tile G;   // B~ L^{-T}     ((n+1) x m), C~ = G G'
+    Tile J;   // Q~ - N' N     ((n+1) x (n+1)),  N = L^{-1} M~'
+};
+
+// Stage element of eq:value-fun-elem-init in the P^{-1}-free form, from the
+// stage data (R = L L').  Returns false if R is not positive definite.
+LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, StageElem &e,
+                              double *s0, double *s1)
+{
+    const int n = d.n, m = d.m;
+    double li[MMAX][MMAX];
+    const bool ok = chol_inv_global(P.R + d.oR + (int64_t)k * m * m, m, li);
+    const int c = tcol();
+    // row c of L^{-1}: G[i][c] = sum_b B[i][b] Linv[c][b]
+    double lrow[MMAX];
+#pragma unroll
+    for (int b = 0; b < MMAX; ++b) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a < MMAX; ++a) t = (a == c) ? li[a][b] : t;
+        lrow[b] = t;
+    }
+    const double *Bk = P.B + d.oB + (int64_t)k * n * m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        double v = 0.0;
+        if (i < n && c < m) {
+#pragma unroll
+            for (int b = 0; b < MMAX; ++b)
+                if (b < m) v += Bk[i * m + b] * lrow[b];
+        }
+        e.G.v[r] = v;
+    }
+    e.Ab = load_Ah(P, d, k);
+    e.J = load_Qh(P, d, k);
+    if (P.M || P.r) {
+        // N[a][j] = sum_b Linv[a][b] M~[j][b]; rows a < m <= 4 are register 0 of
+        // lane group a.
+        const double *Mk = P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr;
+        const double *rk = P.r ? P.r + d.og + (int64_t)k * m : nullptr;
+        const int g = tgrp();
+        Tile N = tzero();
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < MMAX; ++b) {
+            double lg = 0.0;
+#pragma unroll
+            for (int a = 0; a < MMAX; ++a) lg = (a == g) ? li[a][b] : lg;
+            double mt = 0.0;
+            if (b < m) {
+                if (c < n)
+                    mt = Mk ? Mk[c * m + b] : 0.0;
+                else if (c == n)
+                    mt = rk ? rk[b] : 0.0;
+            }
+            v += lg * mt;
+        }
+        N.v[0] = (g < m) ? v : 0.0;
+        e.Ab = tsub(e.Ab, mm<false, false>(e.G, N, m, s0, s1));
+        e.J = tsub(e.J, mm<true, false>(N, N, m, s0, s1));
+    }
+    return ok;
+}
+
+// Left fold of a stage element into an aggregate E = (A^, C^, J^):
+// E <- e_k (x) E with the rank-m Woodbury form of the operator.
+// Returns false if W = I + G'J^G is singular.
+LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int n1, int m,
+                       double *s0, double *s1, double *s2, double *s3)
+{
+    const int ks = kslices(n1), km = kslices(m);
+    const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
+    wsync();
+    sput(s0, Jh);
+    sput(s1, e.G);
+    sput(s2, Ah);
+    sput(s3, e.Ab);
+    wsync();
+    Tile JG, H, JA, AA;
+    JG.v = mfma_staged<false, false>(s0, s1, ks, z);   // J^ G
+    H.v = mfma_staged<false, false>(s2, s1, ks, z);    // A^ G
+    JA.v = mfma_staged<false, false>(s0, s3, ks, z);   // J^ Ab
+    AA.v = mfma_staged<false, false>(s2, s3, ks, z);   // A^ Ab
+    wsync();
+    sput(s0, JG);
+    sput(s2, JA);
+    wsync();
+    Tile W, P, Jn;
+    W.v = mfma_staged<true, false>(s1, s0, ks, tident(m).v);  // I + G'J^G
+    P.v = mfma_staged<true, false>(s1, s2, ks, z);             // G'J^ Ab
+    Jn.v = mfma_staged<true, false>(s3, s2, ks, e.J.v);        // Ab'J^ Ab + J
+    Tile Wi;
+    const bool ok = gen_inverse_small(W, m, Wi, s0);
+    wsync();
+    sput(s0, Wi);
+    sput(s1, P);
+    sput(s2, H);
+    wsync();
+    Tile WP, WH;
+    WP.v = mfma_staged<false, false>(s0, s1, km, z);   // W^{-1} P
+    WH.v = mfma_staged<false, true>(s0, s2, km, z);    // W^{-1} H'
+    wsync();
+    sput(s3, WP);
+    sput(s0, WH);
+    wsync();
+    Tile t;
+    t.v = mfma_staged<false, false>(s2, s3, km, z);    // H W^{-1} P
+    Ah.v = AA.v - t.v;
+    Ch.v = mfma_staged<false, false>(s2, s0, km, Ch.v); // C^ + H W^{-1} H'
+    t.v = mfma_staged<true, false>(s1, s3, km, z);      // P' W^{-1} P
+    Jh.v = Jn.v - t.v;
+    wsync();
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Element build (materialised)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                       const int64_t *__restrict__ elem_start, int batch,
+                                                       double *__restrict__ elems, int32_t *status)
+{
+    __shared__ double lds[2 * SLOT];
+    const int64_t ge = blockIdx.x;
+    const int i = find_inst64(elem_start, batch, ge);
+    const InstDesc d = inst[i];
+    const int k = (int)(ge - d.elem0);
+    double *out = elems + ge * 4 * TILE;
+    if (k == d.T) {  // terminal element nu_{N+1}
+        gstore(out, corner(d.n));
+        gstore(out + TILE, tzero());
+        gstore(out + 2 * TILE, load_terminal_J(P, d, lds));
+        gstore(out + 3 * TILE, tzero());
+        return;
+    }
+    StageElem e;
+    const bool ok = build_stage_elem(P, d, k, e, lds, lds + SLOT);
+    const Tile C = mm<false, true>(e.G, e.G, d.m, lds, lds + SLOT);
+    gstore(out, e.Ab);
+    gstore(out + TILE, C);
+    gstore(out + 2 * TILE, e.J);
+    gstore(out + 3 * TILE, e.G);
+    if (!ok) report(status, i, ERR_NOT_PD, k);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1: fold each segment into one element; also write the terminal
+// element after the last segment of each instance.
+// Scan buffer entry = 3 tiles (A~, C~, J~).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                   const int32_t *__restrict__ seg_start, int batch,
+                                                   const double *__restrict__ elems, double *__restrict__ X,
+                                                   int32_t *status)
+{
+    __shared__ double lds[4 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n1 = d.n + 1, m = d.m;
+    Tile Ah = tident(n1), Ch = tzero(), Jh = tzero();
+    int code = 0, fk = 0;
+    for (int k = k1 - 1; k >= k0; --k) {
+        StageElem e;
+        if (elems) {
+            const double *ep = elems + (d.elem0 + k) * 4 * TILE;
+            e.Ab = gload(ep);
+            e.J = gload(ep + 2 * TILE);
+            e.G = gload(ep + 3 * TILE);
+        } else if (!build_stage_elem(P, d, k, e, s0, s1) && !code) {
+            code = ERR_NOT_PD;
+            fk = k;
+        }
+        if (!fold_left(e, Ah, Ch, Jh, n1, m, s0, s1, s2, s3) && !code) {
+            code = ERR_SINGULAR;
+            fk = k;
+        }
+    }
+    double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
+    gstore(o, Ah);
+    gstore(o + TILE, Ch);
+    gstore(o + 2 * TILE, Jh);
+    if (s == d.nseg - 1) {
+        double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
+        gstore(t, corner(d.n));
+        gstore(t + TILE, tzero());
+        gstore(t + 2 * TILE, load_terminal_J(P, d, s0));
+    }
+    if (code) report(status, i, code, fk);
+}
+
+// Terminal element only (sequential mode: one segment, no fold).
+__global__ __launch_bounds__(64) void k_value_terminal(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                       double *__restrict__ X)
+{
+    __shared__ double lds[SLOT];
+    const InstDesc d = inst[blockIdx.x];
+    double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
+    gstore(t, corner(d.n));
+    gstore(t + TILE, tzero());
+    gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: one Kogge-Stone level of the suffix scan, X_s <- X_s (x) X_{s+dd}.
+// Before the level, X_s covers segments [s, s+dd-1] (clipped at the terminal
+// index nseg); it is terminal-type (A~ = corner, C~ = 0, only J~ meaningful)
+// once it covers nseg.  Terminal-type entries are only ever right operands.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ inst,
+                                                 const int32_t *__restrict__ x_start, int batch, int dd,
+                                                 const double *__restrict__ Xin, double *__restrict__ Xout,
+                                                 int32_t *status)
+{
+    __shared__ double lds[4 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    const int gx = blockIdx.x;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    const int nseg = d.nseg;
+    const double *a = Xin + (int64_t)gx * 3 * TILE;
+    double *o = Xout + (int64_t)gx * 3 * TILE;
+    if (s + dd > nseg) {  // already final (terminal-type): carry J~ over
+        gstore(o + 2 * TILE, gload(a + 2 * TILE));
+        return;
+    }
+    const double *b = Xin + (int64_t)(gx + dd) * 3 * TILE;
+    const bool b_term = (s + 2 * dd - 1 >= nseg);
+    const int n1 = d.n + 1, ks = kslices(n1);
+    const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
+    const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
+    const Tile J2 = gload(b + 2 * TILE);
+    // X = I + C~1 J~2
+    sput(s0, C1);
+    sput(s1, J2);
+    wsync();
+    Tile Xt;
+    Xt.v = mfma_staged<false, false>(s0, s1, ks, tident(n1).v);
+    const bool ok = gj_inverse(Xt, n1, s2);
+    wsync();
+    sput(s3, Xt);  // X^{-1}
+    wsync();
+    Tile T3;
+    T3.v = mfma_staged<false, false>(s1, s3, ks, z);   // J~2 X^{-1} = (X^{-T} J~2)'
+    wsync();
+    sput(s0, T3);
+    sput(s2, A1);
+    wsync();
+    Tile T4;
+    T4.v = mfma_staged<true, false>(s0, s2, ks, z);    // X^{-T} J~2 A~1
+    wsync();
+    sput(s1, T4);
+    wsync();
+    Tile Jn;
+    Jn.v = mfma_staged<true, false>(s2, s1, ks, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
+    Jn = tsym(Jn, s0);
+    gstore(o + 2 * TILE, Jn);
+    if (!b_term) {
+        const Tile A2 = gload(b), C2 = gload(b + TILE);
+        wsync();
+        sput(s0, A2);
+        wsync();
+        Tile T1;
+        T1.v = mfma_staged<false, false>(s0, s3, ks, z);   // A~2 X^{-1}
+        wsync();
+        sput(s1, T1);
+        wsync();
+        Tile An;
+        An.v = mfma_staged<false, false>(s1, s2, ks, z);   // A~2 X^{-1} A~1
+        wsync();
+        sput(s3, C1);
+        wsync();
+        Tile T2;
+        T2.v = mfma_staged<false, false>(s1, s3, ks, z);   // A~2 X^{-1} C~1
+        wsync();
+        sput(s2, T2);
+        wsync();
+        Tile Cn;
+        Cn.v = mfma_staged<false, true>(s2, s0, ks, C2.v); // ... A~2' + C~2
+        Cn = tsym(Cn, s1);
+        gstore(o, An);
+        gstore(o + TILE, Cn);
+    }
+    if (!ok) report(status, i, ERR_SINGULAR, s);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 3: Bellman steps inside each segment from the right neighbour's value
+// function S~' (the carry), writing S_k, s_k, Gamma_k, gamma_k.
+//   S~'B~, S~'A~;  Q_uu = R + B~'S~'B~;  Q_ux~ = M~' + B~'S~'A~;
+//   Gamma~ = -Q_uu^{-1} Q_ux~ = [Gamma, gamma];
+//   S~ = sym(Q~ + A~'S~'A~ + Q_ux~' Gamma~).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                      const int32_t *__restrict__ seg_start, int batch,
+                                                      const double *__restrict__ Xfin, ValPtrs V,
+                                                      int32_t *status)
+{
+    __shared__ double lds[4 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n = d.n, m = d.m, n1 = n + 1, ks = kslices(n1), km = kslices(m);
+    const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
+    const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
+    Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
+    if (s == d.nseg - 1) {
+        gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
+        store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
+    }
+    int code = 0, fk = 0;
+    for (int k = k1 - 1; k >= k0; --k) {
+        const Tile Ah = load_Ah(P, d, k);
+        const Tile Bh = load_Bh(P, d, k);
+        const Tile Qh = load_Qh(P, d, k);
+        const Tile Rk = load_R(P, d, k);
+        const Tile MhT = has_mr ? load_MhT(P, d, k) : tzero();
+        wsync();
+        sput(s0, St);
+        sput(s1, Bh);
+        sput(s2, Ah);
+        wsync();
+        Tile SB, SA;
+        SB.v = mfma_staged<false, false>(s0, s1, ks, z);
+        SA.v = mfma_staged<false, false>(s0, s2, ks, z);
+        wsync();
+        sput(s3, SB);
+        sput(s0, SA);
+        wsync();
+        Tile Quu, Qux, Sn;
+        Quu.v = mfma_staged<true, false>(s1, s3, ks, Rk.v);
+        Qux.v = mfma_staged<true, false>(s1, s0, ks, MhT.v);
+        Sn.v = mfma_staged<true, false>(s2, s0, ks, Qh.v);
+        Tile Qi;
+        if (!spd_inverse(Quu, m, Qi, s3) && !code) {
+            code = ERR_NOT_PD;
+            fk = k;
+        }
+        wsync();
+        sput(s3, Qi);
+        sput(s1, Qux);
+        wsync();
+        Tile Gh;
+        Gh.v = -mfma_staged<false, false>(s3, s1, km, z);
+        wsync();
+        sput(s3, Gh);
+        wsync();
+        Sn.v = mfma_staged<true, false>(s1, s3, km, Sn.v);
+        St = tsym(Sn, s0);
+        gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
+        store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
+        gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
+        store_vec(V.g + d.og + (int64_t)k * m, Gh, m, n);
+    }
+    const bool bad = !(isfinite(St.v[0]) && isfinite(St.v[1]) && isfinite(St.v[2]) && isfinite(St.v[3]));
+    if (__ballot(bad) && !code) {
+        code = ERR_NONFINITE;
+        fk = k0;
+    }
+    if (code) report(status, i, code, fk);
+}
+
+// Diagnostic: D = op(X) op(Y) (+ Z) for row-major 16 x 16 inputs.
+__global__ __launch_bounds__(64) void k_selftest_mm(const double *X, const double *Y, const double *Z,
+                                                    double *D, int tx, int ty)
+{
+    __shared__ double lds[2 * SLOT];
+    const Tile x = gload_rm(X, 16, 16, 16), y = gload_rm(Y, 16, 16, 16);
+    const Tile zt = Z ? gload_rm(Z, 16, 16, 16) : tzero();
+    Tile d;
+    if (tx && ty)
+        d = mma<true, true>(x, y, zt, 16, lds, lds + SLOT);
+    else if (tx)
+        d = mma<true, false>(x, y, zt, 16, lds, lds + SLOT);
+    else if (ty)
+        d = mma<false, true>(x, y, zt, 16, lds, lds + SLOT);
+    else
+        d = mma<false, false>(x, y, zt, 16, lds, lds + SLOT);
+    gstore_rm(D, d, 16, 16, 16);
+}
+
+}  // namespace lqk

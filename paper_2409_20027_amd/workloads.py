@@ -147,18 +147,24 @@ def cfg3_ragged(seed: int = 3, count: int = 4096, tmin: int = 32, tmax: int = 20
 def pack(instances) -> dict:
     """Concatenate a list of LQInstance into the flat packed layout.
 
-    Optional fields are packed only if every instance has them; otherwise the
-    packed field is None.
+    An optional field (c, M, q, r, qT) is packed if any instance has it, with
+    zeros for the instances that do not (None means zero); it is None only if
+    no instance has it.
     """
     out = {"n": np.array([i.n for i in instances], np.int32),
            "m": np.array([i.m for i in instances], np.int32),
            "T": np.array([i.T for i in instances], np.int32)}
-    for f in ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0"):
+    shapes = {"A": lambda i: (i.T, i.n, i.n), "B": lambda i: (i.T, i.n, i.m), "c": lambda i: (i.T, i.n),
+              "Q": lambda i: (i.T, i.n, i.n), "R": lambda i: (i.T, i.m, i.m), "M": lambda i: (i.T, i.n, i.m),
+              "q": lambda i: (i.T, i.n), "r": lambda i: (i.T, i.m), "QT": lambda i: (i.n, i.n),
+              "qT": lambda i: (i.n,), "x0": lambda i: (i.n,)}
+    for f, shp in shapes.items():
         vals = [getattr(i, f) for i in instances]
-        if any(v is None for v in vals):
+        if all(v is None for v in vals):
             out[f] = None
-        else:
-            out[f] = np.ascontiguousarray(np.concatenate([v.reshape(-1) for v in vals]))
+            continue
+        out[f] = np.ascontiguousarray(np.concatenate(
+            [(np.zeros(shp(i)) if v is None else v).reshape(-1) for v, i in zip(vals, instances)]))
     return out
 
 

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP LQ solve (value scan + control law + rollout) against the FP64 oracle.
+
+Tolerance (FP64 path): normwise relative error ||y - y_ref||_inf / ||y_ref||_inf <= 1e-10
+per output array and instance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_20027_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_20027_amd import lqscan
+    return lqscan
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+def split(flat, sizes):
+    """Split a flat packed array into per-instance arrays with the given shapes."""
+    out, o = [], 0
+    for shp in sizes:
+        k = int(np.prod(shp))
+        out.append(flat[o:o + k].reshape(shp))
+        o += k
+    return out
+
+
+def oracle_ref(inst):
+    return oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                           M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+
+
+def run(lq, insts, materialise=False, **plan_kw):
+    packed = W.pack(insts)
+    prob = lq.to_device(packed)
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], **plan_kw)
+    out = lq.solve(plan, prob, materialise_elements=materialise)
+    torch.cuda.synchronize()
+    res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
+    per = []
+    shapes = {"S": lambda i: (i.T + 1, i.n, i.n), "s": lambda i: (i.T + 1, i.n),
+              "Gamma": lambda i: (i.T, i.m, i.n), "gamma": lambda i: (i.T, i.m),
+              "x": lambda i: (i.T + 1, i.n), "u": lambda i: (i.T, i.m), "lam": lambda i: (i.T + 1, i.n)}
+    parts = {k: split(res[k], [f(i) for i in insts]) for k, f in shapes.items()}
+    for j in range(len(insts)):
+        per.append({k: parts[k][j] for k in shapes})
+    return per, res["status"], plan
+
+
+def check(per, insts, tol=TOL):
+    worst = 0.0
+    for got, inst in zip(per, insts):
+        ref = oracle_ref(inst)
+        for k in ("S", "s", "Gamma", "gamma", "x", "u", "lam"):
+            e = rel(got[k], ref[k])
+            worst = max(worst, e)
+            assert e <= tol, f"{k}: rel err {e:.3e} (n={inst.n}, m={inst.m}, T={inst.T})"
+    return worst
+
+
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tx,ty", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_tile_mm_selftest(lq, tx, ty):
+    """Pins the operand/accumulator lane layout of the FP64 16x16x4 matrix instruction."""
+    rng = np.random.default_rng(1 + 2 * tx + ty)
+    X, Y, Z = (rng.standard_normal((16, 16)) for _ in range(3))
+    d = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda").contiguous()
+    D = torch.zeros(16, 16, dtype=torch.float64, device="cuda")
+    lq.lq_selftest_tile_mm(d(X), d(Y), d(Z), D, tx, ty)
+    torch.cuda.synchronize()
+    ref = (X.T if tx else X) @ (Y.T if ty else Y) + Z
+    assert rel(D.cpu().numpy(), ref) < 1e-14
+
+
+def test_cfg0_small_scan(lq):
+    inst = W.cfg0_small()
+    per, status, plan = run(lq, [inst])
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+
+
+@pytest.mark.parametrize("seg_len", [1, 3, 7, 16, 64])
+def test_cfg0_segment_lengths(lq, seg_len):
+    """Every segmentation (including ragged last segments) gives the same solution."""
+    inst = W.cfg0_small()
+    per, status, _ = run(lq, [inst], seg_len=seg_len)
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+
+
+def test_cfg0_sequential_mode(lq):
+    inst = W.cfg0_small()
+    per, status, _ = run(lq, [inst], mode="sequential")
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+
+
+@pytest.mark.parametrize("n,m,T,L", [(3, 2, 37, 5), (4, 4, 50, 8), (1, 1, 9, 2), (15, 4, 40, 6)])
+def test_general_lq_all_terms(lq, n, m, T, L):
+    """Cross terms M, linear terms q, r, q_T and offsets c all present."""
+    inst = W.lq_instance_general(np.random.default_rng(1000 + n * 10 + m), n, m, T)
+    per, status, _ = run(lq, [inst], seg_len=L)
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+
+
+def test_ragged_batch_mixed_sizes(lq):
+    rng = np.random.default_rng(5)
+    insts = []
+    for n, m, T in [(2, 1, 1), (4, 1, 2), (12, 4, 33), (1, 1, 100), (7, 3, 64), (12, 4, 257), (2, 1, 17)]:
+        insts.append(W.lq_instance(rng, n, m, T))
+    insts.append(W.lq_instance_general(rng, 5, 2, 40))
+    per, status, _ = run(lq, insts)
+    assert int(np.abs(status).sum()) == 0
+    check(per, insts)
+
+
+def test_materialised_elements_match_oracle(lq):
+    """lq_build_elements writes the elements of eq:value-fun-elem-init (decoded from tiles)."""
+    inst = W.lq_instance_general(np.random.default_rng(77), 3, 2, 6)
+    packed = W.pack([inst])
+    prob = lq.to_device(packed)
+    plan = lq.Plan([inst.n], [inst.m], [inst.T], seg_len=2)
+    el = plan.new_elements()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lq.lq_build_elements(plan, prob, el, status)
+    torch.cuda.synchronize()
+    E = el.cpu().numpy()[: (inst.T + 1) * 4 * 256].reshape(inst.T + 1, 4, 256)
+    n = inst.n
+
+    def tile(flat):  # decode the tile layout: entry (i, j) at 4*(j + 16*(i%4)) + i//4
+        t = np.zeros((16, 16))
+        for i in range(16):
+            for j in range(16):
+                t[i, j] = flat[4 * (j + 16 * (i % 4)) + i // 4]
+        return t
+
+    for k in range(inst.T + 1):
+        if k < inst.T:
+            ref = oracle.unpack_elem(oracle.value_element(inst.A[k], inst.B[k], inst.c[k], inst.Q[k], inst.R[k],
+                                                          inst.M[k], inst.q[k], inst.r[k]), n)
+        else:
+            ref = oracle.unpack_elem(oracle.value_terminal(inst.QT, inst.qT), n)
+        A, C, J = tile(E[k, 0]), tile(E[k, 1]), tile(E[k, 2])
+        assert rel(A[:n, :n], ref["A"]) < 1e-13 if np.any(ref["A"]) else np.all(A[:n, :n] == 0)
+        assert np.max(np.abs(A[:n, n] - ref["b"])) <= 1e-13 * max(1, np.max(np.abs(ref["b"])))
+        assert np.max(np.abs(C[:n, :n] - ref["C"])) <= 1e-13 * max(1, np.max(np.abs(ref["C"])))
+        assert rel(J[:n, :n], ref["J"]) < 1e-13
+        assert np.max(np.abs(-J[:n, n] - ref["eta"])) <= 1e-13 * max(1, np.max(np.abs(ref["eta"])))
+    # the scan over materialised elements equals the fused build
+    per_f, _, _ = run(lq, [inst], seg_len=2)
+    out = lq.solve(plan, prob, materialise_elements=True)
+    torch.cuda.synchronize()
+    assert rel(out["x"].cpu().numpy().reshape(inst.T + 1, n), per_f[0]["x"]) < 1e-13
+
+
+def test_scan_equals_sequential_every_prefix_and_suffix(lq):
+    """The scan and the plain sequential recursion agree on every S_k, s_k (suffixes) and x_k (prefixes)."""
+    inst = W.lq_instance(np.random.default_rng(8), 12, 4, 700, a_scale=0.02, r_fixed=0.1)
+    per_s, st1, _ = run(lq, [inst], seg_len=9)
+    per_q, st2, _ = run(lq, [inst], mode="sequential")
+    assert int(np.abs(st1).sum()) == 0 and int(np.abs(st2).sum()) == 0
+    for k in range(inst.T + 1):
+        assert rel(per_s[0]["S"][k], per_q[0]["S"][k]) < TOL
+        assert rel(per_s[0]["s"][k], per_q[0]["s"][k]) < TOL
+        assert rel(per_s[0]["x"][: k + 1], per_q[0]["x"][: k + 1]) < TOL
+    check(per_s, [inst])
+
+
+def test_value_matrices_symmetric_psd(lq):
+    inst = W.cfg0_small()
+    per, _, _ = run(lq, [inst])
+    S = per[0]["S"]
+    assert np.array_equal(S, np.transpose(S, (0, 2, 1)))
+    for k in range(inst.T + 1):
+        ev = np.linalg.eigvalsh(S[k])
+        assert ev.min() >= -1e-12 * np.abs(ev).max()
+
+
+def test_not_pd_reports_stage(lq):
+    inst = W.lq_instance(np.random.default_rng(0), 2, 1, 40)
+    inst.R = inst.R.copy()
+    inst.R[23] = -1.0
+    _, status, _ = run(lq, [inst], seg_len=4)
+    code, k = (-int(status[0])) & 0xFF, int(status[0]) >> 8
+    # status = (-code) | (k << 8); NOT_PD = -2
+    assert int(status[0]) & 0xFF == 2 and k == 23
+
+
+def test_deterministic(lq):
+    inst = W.cfg2_long(T=2048)
+    a, _, _ = run(lq, [inst])
+    b, _, _ = run(lq, [inst])
+    for k in a[0]:
+        assert np.array_equal(a[0][k], b[0][k])
+
+
+def test_cfg2_full_horizon(lq):
+    """n=12, m=4, T=16384 at full size, every stage compared with the oracle."""
+    inst = W.cfg2_long()
+    per, status, plan = run(lq, [inst])
+    assert int(np.abs(status).sum()) == 0
+    worst = check(per, [inst])
+    print(f"cfg2 worst rel err {worst:.3e}, seg_len {plan.seg_len()}")
