@@ -2,17 +2,20 @@
 
 Workload: one long-horizon time-varying LQ problem, n=12, m=4, T=16384, FP64,
 drawn by paper_2409_20027_amd.workloads.cfg2_long (synthetic, seeded).
-One step = the whole hot path over that input: value pass (fused element
-build + segment fold, log-depth scan, Bellman steps with the control law),
-rollout (segment maps, prefix scan, states/controls/co-states) and, when
-available, the adjoint (backward linear-term scan, forward derivative scan,
-per-stage gradients).  Inputs are resident in HBM before timing starts.
+One step = the whole hot path over that input, forward and adjoint:
+  value pass   (fused element build + segment fold, log-depth scan of the
+                segment elements, Bellman steps with the control law),
+  rollout      (segment maps, prefix scan, states / controls / co-states),
+  adjoint      (backward linear-term scan, forward derivative scan, per-stage
+                gradients of L = sum ||x||^2 + ||u||^2 w.r.t. A, B, c, Q, R,
+                Q_T, x0).
+Inputs (and the loss gradients 2x, 2u) are resident in HBM before timing.
 
 Prints one JSON line.  The metric is stage-steps per second (T stages per
-step).  Also reported: the forward-solve latency at T = 16384 as the median of
-graph replays, the plain sequential path on the same GPU, the error of a
-sample against the FP64 oracle, the roofline of the dominant kernel and the
-oracle timed on the host.
+step).  Also reported: the forward-solve latency at T = 16384 (median of graph
+replays), the plain sequential path on the same GPU, the error of the result
+against the FP64 oracle, a per-kernel breakdown, the roofline of the dominant
+kernel and the oracle timed on the host.
 """
 from __future__ import annotations
 
@@ -29,37 +32,60 @@ if ROOT not in sys.path:
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
-FP64_MFMA_PEAK_TFLOPS = 78.6
+FP64_PEAK_TFLOPS = 78.6   # FP64 matrix cores (dense) = FP64 vector
+
+# ---------------------------------------------------------------------------
+# Per-stage algorithmic cost models of the kernels (n1 = n + 1, homogeneous
+# form).  Flops count only the products the method needs (no tile padding);
+# bytes count the HBM traffic a perfect kernel would do (read each input once,
+# write each output once).
+# ---------------------------------------------------------------------------
 
 
-def fold_flops_per_stage(n: int, m: int) -> float:
-    """Useful flops of one segment-fold step (stage element built on the fly and
-    left-folded into the segment element), in the homogeneous form n1 = n+1:
-    J^G, A^G (2 n1^2 m each), J^Ab, A^Ab, Ab'J^Ab (2 n1^3 each), G'J^G (2 n1 m^2),
-    G'J^Ab (2 m n1^2), W^{-1}P, W^{-1}H' (2 m^2 n1 each), three rank-m updates
-    (2 n1^2 m each)."""
+def kernel_models(n, m):
     n1 = n + 1
-    return 6 * n1 ** 3 + 12 * n1 ** 2 * m + 6 * n1 * m ** 2
-
-
-def fold_bytes_per_stage(n: int, m: int) -> float:
-    """Algorithmic HBM bytes per stage of the fold: A, B, c, Q, R read once."""
-    return 8.0 * (n * n + n * m + n + n * n + m * m)
+    d = 8.0
+    return {
+        # element build + rank-m left fold: J^G, A^G, J^Ab, A^Ab, Ab'J^Ab, G'J^G, G'J^Ab, two W^{-1}
+        # products and three rank-m updates
+        "value_fold": {"flops": 6 * n1 ** 3 + 12 * n1 ** 2 * m + 6 * n1 * m ** 2,
+                       "bytes": d * (2 * n * n + n * m + n + m * m)},
+        # Bellman step: S'B, S'A, B'S'B, B'S'A, A'S'A, Q_uu^{-1} Q_ux, Q_ux' Gamma
+        "value_bellman": {"flops": 4 * n1 ** 3 + 6 * n1 ** 2 * m + 4 * n1 * m ** 2,
+                          "bytes": d * (2 * n * n + n * m + n + m * m + n * n + n + m * n + m)},
+        "roll_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m,
+                      "bytes": d * (n * n + n * m + n + m * n + m)},
+        "roll_apply": {"flops": 4 * n1 ** 2 + 4 * m * n1,
+                       "bytes": d * (2 * n * n + 2 * m * n + 4 * n + 2 * m)},
+        "adj_back_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m + 2 * n1 * m,
+                          "bytes": d * (n * n + 2 * n * m + 2 * m + n)},
+        "adj_back_apply": {"flops": 2 * n1 ** 3 + 6 * n1 ** 2 * m + 4 * n1 * m ** 2 + 2 * n1 ** 2,
+                           "bytes": d * (2 * n * n + 2 * n * m + m * m + 3 * n + 3 * m)},
+        "adj_fwd_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m,
+                         "bytes": d * (n * n + 2 * n * m + m)},
+        "adj_fwd_apply": {"flops": 6 * n1 ** 2 + 4 * m * n1 + 8 * n * n + 8 * n * m + 2 * m * m,
+                          "bytes": d * (3 * n * n + 2 * n * m + 4 * n + 2 * m
+                                        + 2 * n * n + 2 * n * m + 2 * n + m * m + m)},
+    }
 
 
 def cpu_baseline(inst, budget_s: float = 10.0) -> dict:
     import oracle
+    o = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
+    gx, gu = 2 * o["x"], 2 * o["u"]
     t0 = time.perf_counter()
     reps = 0
     while True:
         r = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
+        oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, gx, gu)
         reps += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = time.perf_counter() - t0
     return {"value": inst.T * reps / dt, "unit": "stage-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"the same n=12 m=4 T={inst.T} instance, sequential Riccati + rollout + co-states "
-                      f"(forward solve), repeated {reps} times in {dt:.1f} s on one host core"}
+            "sample": f"the same n=12 m=4 T={inst.T} instance: sequential Riccati + rollout + co-states, "
+                      f"then the KKT adjoint (forward + adjoint, as one GPU step), repeated {reps} times "
+                      f"in {dt:.1f} s on one host core"}
 
 
 def main():
@@ -70,11 +96,12 @@ def main():
     ap.add_argument("--T", type=int, default=16384)
     ap.add_argument("--seg-len", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--replays", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the solver's multi-GPU sharding is a design, not a built path "
-              "(run with --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU only: sharding the horizon or the batch over several GPUs is a "
+              "design in this repository, not a built path (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -92,15 +119,38 @@ def main():
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     val = lqscan.value_buffers(plan, dev)
     st = lqscan.state_buffers(plan, dev)
+    gnames = ("A", "B", "c", "Q", "R", "QT", "x0")
+    grads = lqscan.grad_buffers(plan, gnames, dev)
 
-    def step():
+    def forward():
         lqscan.lq_scan_solve(plan, prob, None, val, ws, status)
         lqscan.lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+
+    forward()
+    torch.cuda.synchronize()
+    gx, gu = 2 * st["x"], 2 * st["u"]   # loss gradients, fixed inputs of the adjoint
+
+    def step():
+        forward()
+        lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, ws, status)
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_timing(["value_fold"], capacity=args.steps + 8)
+
+    # profiling pass: every phase timed with events (not the headline number)
+    prof_steps = min(args.steps, 10)
+    plan.set_timing(list(lqscan.PHASES), capacity=prof_steps * len(lqscan.PHASES) + 8)
+    for _ in range(prof_steps):
+        step()
+    phases = plan.phase_times()
+    plan.set_timing([], 0)
+    breakdown = {k: v[0] / prof_steps for k, v in phases.items()}
+    models = kernel_models(n, m)
+    dominant = max((k for k in breakdown if k in models), key=lambda k: breakdown[k])
+
+    # timed pass: events only around the dominant kernel
+    plan.set_timing([dominant], capacity=args.steps + 8)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     ev0.record()
@@ -109,32 +159,37 @@ def main():
     ev1.record()
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
-    phases = plan.phase_times()
+    dom_ms, dom_launches = plan.phase_times()[dominant]
     plan.set_timing([], 0)
     ms_per_step = total_ms / args.steps
     assert int(status.abs().sum()) == 0, "numerical failure reported"
 
-    # error against the oracle on a sample of stages
+    # error of this run's result against the FP64 oracle (every stage)
     import oracle
     ref = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
-    x = st["x"].cpu().numpy().reshape(T + 1, n)
-    u = st["u"].cpu().numpy().reshape(T, m)
-    S = val["S"].cpu().numpy().reshape(T + 1, n, n)
-    err = max(np.max(np.abs(x - ref["x"])) / np.max(np.abs(ref["x"])),
-              np.max(np.abs(u - ref["u"])) / np.max(np.abs(ref["u"])),
-              np.max(np.abs(S - ref["S"])) / np.max(np.abs(ref["S"])))
+    gref = oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, 2 * ref["x"], 2 * ref["u"])
 
-    # forward latency: median of graph replays (the whole forward solve captured once)
+    def rel(a, b):
+        return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+    err = {"x": rel(st["x"].cpu().numpy().reshape(T + 1, n), ref["x"]),
+           "u": rel(st["u"].cpu().numpy().reshape(T, m), ref["u"]),
+           "S": rel(val["S"].cpu().numpy().reshape(T + 1, n, n), ref["S"]),
+           "grad_A": rel(grads["A"].cpu().numpy().reshape(T, n, n), gref["A"]),
+           "grad_Q": rel(grads["Q"].cpu().numpy().reshape(T, n, n), gref["Q"]),
+           "grad_x0": rel(grads["x0"].cpu().numpy(), gref["x0"])}
+
+    # forward latency at T: median of graph replays of the captured forward solve
     lat_us = None
     try:
         g = torch.cuda.CUDAGraph()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            step()
+            forward()
             torch.cuda.synchronize()
             with torch.cuda.graph(g, stream=s):
-                step()
+                forward()
         torch.cuda.synchronize()
         times = []
         for i in range(10 + args.replays):
@@ -146,52 +201,60 @@ def main():
             if i >= 10:
                 times.append(a.elapsed_time(b) * 1e3)
         lat_us = float(np.median(times))
-    except Exception as e:  # graph capture unavailable: report eager latency instead
+    except Exception as e:
         print(f"graph replay failed: {e!r}", file=sys.stderr)
 
-    # the plain sequential path on the same GPU (forward solve)
-    seq = {}
-    splan = lqscan.Plan([n], [m], [T], mode="sequential")
-    sws = splan.new_workspace(dev)
+    # the plain sequential path on the same GPU (one segment per instance)
+    seq = None
+    if not args.no_seq:
+        splan = lqscan.Plan([n], [m], [T], mode="sequential")
+        sws = splan.new_workspace(dev)
 
-    def sstep():
-        lqscan.lq_scan_solve(splan, prob, None, val, sws, status)
-        lqscan.lq_rollout(splan, prob, val, st["x"], st["u"], st["lam"], sws, status)
+        def sstep():
+            lqscan.lq_scan_solve(splan, prob, None, val, sws, status)
+            lqscan.lq_rollout(splan, prob, val, st["x"], st["u"], st["lam"], sws, status)
+            lqscan.lq_adjoint(splan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, sws, status)
 
-    sstep()
-    torch.cuda.synchronize()
-    reps = 3
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
         sstep()
-    b.record()
-    torch.cuda.synchronize()
-    seq_ms = a.elapsed_time(b) / reps
-    seq = {"ms_per_step": seq_ms, "value": T / (seq_ms * 1e-3), "unit": "stage-steps/s",
-           "what": "forward solve, one segment (sequential Bellman recursion + sequential rollout)"}
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 2
+        a.record()
+        for _ in range(reps):
+            sstep()
+        b.record()
+        torch.cuda.synchronize()
+        seq_ms = a.elapsed_time(b) / reps
+        seq = {"ms_per_step": seq_ms, "value": T / (seq_ms * 1e-3), "unit": "stage-steps/s",
+               "what": "same step (forward + adjoint) with one segment: sequential recursions on the GPU"}
 
-    fold_ms, fold_launches = phases.get("value_fold", (float("nan"), 0))
-    fold_avg_s = fold_ms / max(fold_launches, 1) * 1e-3
-    flops = fold_flops_per_stage(n, m) * T
-    achieved = flops / fold_avg_s / 1e12
-    roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-            "kernel": "k_value_fold", "avg_launch_us": fold_avg_s * 1e6,
-            "flops_per_launch": flops, "flops_per_stage": fold_flops_per_stage(n, m),
-            "hbm_bytes_per_launch": fold_bytes_per_stage(n, m) * T}
+    mdl = models[dominant]
+    avg_s = dom_ms / max(dom_launches, 1) * 1e-3
+    flops = mdl["flops"] * T
+    nbytes = mdl["bytes"] * T
+    tf = flops / avg_s / 1e12
+    gbs = nbytes / avg_s / 1e9
+    if tf / FP64_PEAK_TFLOPS >= gbs / HBM_PEAK_GBS:
+        roof = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP64_PEAK_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    roof.update({"traffic": None, "kernel": dominant, "avg_launch_us": avg_s * 1e6,
+                 "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                 "flops_per_stage": mdl["flops"], "bytes_per_stage": mdl["bytes"], "units_per_launch": T})
 
-    out = {"metric": "LQ stage-steps/sec (n=12, m=4, T=16384 solve, FP64)",
+    out = {"metric": "LQ stage-steps/sec (forward + adjoint, n=12, m=4, T=16384, FP64)",
            "value": T * args.steps / (total_ms * 1e-3), "unit": "stage-steps/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
            "data": "synthetic",
-           "config": {"workload": f"time-varying LQ, n={n}, m={m}, T={T}, one instance, value scan + rollout",
-                      "seg_len": plan.seg_len(), "step": "forward"},
-           "latency_us_T16384_forward_graph": lat_us,
+           "config": {"workload": f"time-varying LQ, n={n}, m={m}, T={T}, one instance; value scan + rollout "
+                                  f"+ adjoint per step", "seg_len": plan.seg_len()},
+           "latency_us_T16384_forward": lat_us,
            "err_vs_oracle": err,
            "sequential_gpu": seq,
-           "phase_ms_per_step": {k: v[0] / max(v[1], 1) for k, v in phases.items()},
+           "kernel_ms_per_step": breakdown,
            "roofline": roof}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)

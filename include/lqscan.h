@@ -89,6 +89,13 @@ typedef struct lq_plan lq_plan;   /* opaque */
  */
 lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
                          int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out);
+/*
+ * Same with one segment length per instance (host array seg_len[batch]; 0 =
+ * automatic, >= T[i] = the sequential recursion for that instance).  Used by
+ * the segment-length autotuner, which picks a length per (n, m, T) class.
+ */
+lq_status lq_plan_create_seg(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                             int32_t precision, const int32_t *seg_len, lq_plan **out);
 void lq_plan_destroy(lq_plan *plan);
 
 /* Bytes of scratch device memory the solve calls need (256-byte aligned base). */
@@ -198,6 +205,66 @@ lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value
                      void *workspace, int32_t *status, void *stream);
 
 /*
+ * ---------------------------------------------------------------------------
+ * Newton / interior-point step (Alg. 4 inside the log-barrier method of
+ * Sec. II-B) for the dynamics x_{k+1} = x_k + h (tanh(W x_k) + B u_k),
+ * l_k = 1/2 (x - ref_k)'Q(x - ref_k) + 1/2 u'R u, l_T = 1/2 (x - ref_T)'Q_T(x - ref_T),
+ * and the control box umin < u < umax as 2 nu inequalities with the barrier
+ * -mu sum [log(umax - u) + log(u - umin)].
+ * ---------------------------------------------------------------------------
+ */
+typedef struct {
+    int32_t nx, nu, T;
+    double h;
+    const double *W, *Bm;          /* nx*nx, nx*nu                    (device) */
+    const double *Q, *R, *QT;      /* nx*nx, nu*nu, nx*nx             (device) */
+    const double *xref, *x0;       /* (T+1)*nx, nx                    (device) */
+    double umin, umax;
+} nmpc_problem;
+
+/* Indices of the device scalar array nmpc_state.scal (NMPC_NSCAL doubles). */
+enum {
+    NMPC_MU = 0,          /* barrier weight (set by the caller)                      */
+    NMPC_ALPHA = 1,       /* Levenberg-Marquardt weight alpha (updated by the step)   */
+    NMPC_NU = 2,          /* growth factor of alpha after a rejection                 */
+    NMPC_COST = 3,        /* J_mu of the nominal after the step                       */
+    NMPC_PRED = 4,        /* predicted decrease of the step                           */
+    NMPC_RHO = 5,         /* gain ratio (-inf if rejected before it could be formed)  */
+    NMPC_ACCEPTED = 6,    /* 1.0 if the step was accepted                             */
+    NMPC_COST_NEW = 7,    /* J_mu of the candidate                                    */
+    NMPC_NSCAL = 8
+};
+
+typedef struct {
+    double *x, *u;   /* nominal trajectory (T+1)*nx and T*nu (device), replaced on acceptance */
+    double *scal;    /* NMPC_NSCAL device scalars                                             */
+} nmpc_state;
+
+/* Workspace of newton_step / nmpc_init for a plan with batch 1 and the same
+ * (nx, nu, T) (the plan's segment length is used by every scan). */
+size_t nmpc_workspace_bytes(const lq_plan *plan);
+
+/* x <- nonlinear rollout of u from x0 (call once before the first step). */
+lq_status nmpc_init(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
+                    void *stream);
+
+/*
+ * One Newton iteration at the barrier weight scal[NMPC_MU]:
+ * linearisation and co-states (parallel co-state pass, Alg. 1), second-order
+ * expansion, the LQ step (lq_scan_solve + lq_rollout, value pass and state
+ * propagation of Alg. 2-3), the nonlinear rollout of u + du and the
+ * acceptance test with the damping update (see lq_newton.hip): the nominal is
+ * replaced by (rollout(u + du), u + du) if the gain ratio is positive.  A
+ * rejected step (including an LQ step whose R + B'S'B is not positive
+ * definite) leaves the nominal unchanged and increases alpha.  Everything is
+ * enqueued on `stream`; decisions are taken on the device.  `status` is not
+ * written (rejections are part of the method).  Errors: LQ_ERR_ARG if the
+ * plan does not match the problem.
+ */
+lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
+                      int32_t *status, void *stream);
+
+/*
  * Diagnostic: one 16 x 16 FP64 tile product D = X Y (+ Z) through the
  * library's matrix-core tile primitive.  X, Y, Z, D are device pointers to
  * row-major 16 x 16 arrays (Z nullable).  Used by the test suite to pin the
@@ -207,7 +274,8 @@ lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z,
                               int32_t transpose_x, int32_t transpose_y, void *stream);
 
 /*
- * Diagnostic phase timing.  Phases of the solve calls, in enqueue order:
+ * Diagnostic phase timing.  Phases of the solve calls, in enqueue order (a
+ * phase is one kernel launch, except the scans: one launch per level):
  */
 enum {
     LQ_PH_BUILD = 0,         /* lq_build_elements                                  */
@@ -217,9 +285,13 @@ enum {
     LQ_PH_ROLL_FOLD = 4,     /* rollout: composition of each segment's maps         */
     LQ_PH_ROLL_SCAN = 5,     /* rollout: log-depth prefix scan                      */
     LQ_PH_ROLL_APPLY = 6,    /* rollout: states, controls, co-states                */
-    LQ_PH_ADJ_BACK = 7,      /* adjoint: backward linear-term scan (all launches)   */
-    LQ_PH_ADJ_FWD = 8,       /* adjoint: forward state-derivative scan + gradients  */
-    LQ_NPHASE = 9
+    LQ_PH_ADJ_BACK_FOLD = 7,  /* adjoint: composition of each segment's backward maps */
+    LQ_PH_ADJ_BACK_SCAN = 8,  /* adjoint: log-depth suffix scan                      */
+    LQ_PH_ADJ_BACK_APPLY = 9, /* adjoint: s~ and gamma~ inside segments              */
+    LQ_PH_ADJ_FWD_FOLD = 10,  /* adjoint: composition of each segment's forward maps  */
+    LQ_PH_ADJ_FWD_SCAN = 11,  /* adjoint: log-depth prefix scan                      */
+    LQ_PH_ADJ_FWD_APPLY = 12, /* adjoint: dx, du, dlambda and the gradients          */
+    LQ_NPHASE = 13
 };
 /*
  * lq_plan_set_timing enables event recording around the phases whose bit is

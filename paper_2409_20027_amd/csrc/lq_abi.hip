@@ -44,8 +44,9 @@ struct lq_plan {
     int64_t total_seg = 0, total_x = 0, total_elem = 0, total_stages = 0;
     int max_nseg = 0;
     int seg_len_used = 0;
+    int nk = 1;   // contraction slices of (n_max + 1)-long products
     // workspace layout (bytes)
-    size_t off_Xa = 0, off_Xb = 0, off_Ya = 0, off_Yb = 0, ws_bytes = 0, el_bytes = 0;
+    size_t off_Xa = 0, off_Xb = 0, off_Ya = 0, off_Yb = 0, off_st = 0, off_gt = 0, ws_bytes = 0, el_bytes = 0;
     // diagnostic phase timing (events created by lq_plan_set_timing)
     mutable uint32_t tmask = 0;
     mutable std::vector<hipEvent_t> ev;
@@ -81,14 +82,18 @@ extern "C" {
 
 const char *lq_version(void) { return "lqscan 0.1 (gfx950, fp64 tiles)"; }
 
-lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
-                         int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out)
+static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                             int32_t precision, int32_t mode, int32_t seg_len, const int32_t *seg_lens,
+                             lq_plan **out)
 {
     if (!out || batch <= 0 || !nx || !nu || !T) return LQ_ERR_ARG;
     if (precision != LQ_FP64 && precision != LQ_MIXED) return LQ_ERR_ARG;
     if (mode != LQ_SCAN && mode != LQ_SEQUENTIAL) return LQ_ERR_ARG;
     if (seg_len < 0) return LQ_ERR_ARG;
     *out = nullptr;
+    if (seg_lens)
+        for (int i = 0; i < batch; ++i)
+            if (seg_lens[i] < 0) return LQ_ERR_ARG;
     for (int i = 0; i < batch; ++i) {
         if (T[i] < 1 || nx[i] < 1 || nu[i] < 1) return LQ_ERR_ARG;
         if (nx[i] > 15 || nu[i] > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
@@ -105,14 +110,15 @@ lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, co
     std::vector<int64_t> elem_start(batch + 1);
     int64_t oA = 0, oB = 0, oR = 0, oc = 0, oQT = 0, on = 0, oS = 0, os = 0, oG = 0, og = 0;
     int64_t seg = 0, el = 0, stages = 0;
-    int max_nseg = 0, lmax = 0;
+    int max_nseg = 0, lmax = 0, nmax = 0;
     for (int i = 0; i < batch; ++i) {
         InstDesc &d = p->h_inst[i];
         const int64_t n = nx[i], m = nu[i], t = T[i];
         d.n = (int)n;
         d.m = (int)m;
         d.T = (int)t;
-        d.L = (mode == LQ_SEQUENTIAL) ? (int)t : (seg_len > 0 ? std::min<int>(seg_len, (int)t) : auto_seg_len((int)t));
+        const int req = seg_lens ? seg_lens[i] : seg_len;
+        d.L = (mode == LQ_SEQUENTIAL) ? (int)t : (req > 0 ? std::min<int>(req, (int)t) : auto_seg_len((int)t));
         d.nseg = (int)((t + d.L - 1) / d.L);
         d.seg0 = (int)seg;
         d.xbase = (int)(seg + i);
@@ -131,6 +137,7 @@ lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, co
         oS += (t + 1) * n * n; os += (t + 1) * n; oG += t * m * n; og += t * m;
         max_nseg = std::max(max_nseg, d.nseg);
         lmax = std::max(lmax, d.L);
+        nmax = std::max(nmax, d.n);
     }
     if (seg > INT32_MAX / 2) {
         delete p;
@@ -145,12 +152,15 @@ lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, co
     p->total_stages = stages;
     p->max_nseg = max_nseg;
     p->seg_len_used = lmax;
+    p->nk = (nmax + 1 + 3) / 4;
     // workspace: value scan ping-pong (3 tiles / entry), affine scan ping-pong (1 tile / entry)
     size_t off = 0;
     p->off_Xa = off; off = align_up(off + (size_t)p->total_x * 3 * TILE * sizeof(double));
     p->off_Xb = off; off = align_up(off + (size_t)p->total_x * 3 * TILE * sizeof(double));
     p->off_Ya = off; off = align_up(off + (size_t)p->total_x * TILE * sizeof(double));
     p->off_Yb = off; off = align_up(off + (size_t)p->total_x * TILE * sizeof(double));
+    p->off_st = off; off = align_up(off + (size_t)os * sizeof(double));     // adjoint s~
+    p->off_gt = off; off = align_up(off + (size_t)og * sizeof(double));     // adjoint gamma~
     p->ws_bytes = off;
     p->el_bytes = align_up((size_t)el * 4 * TILE * sizeof(double));
 
@@ -174,6 +184,19 @@ lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, co
     }
     *out = p;
     return LQ_OK;
+}
+
+lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                         int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out)
+{
+    return plan_create(batch, nx, nu, T, precision, mode, seg_len, nullptr, out);
+}
+
+lq_status lq_plan_create_seg(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                             int32_t precision, const int32_t *seg_len, lq_plan **out)
+{
+    if (!seg_len) return LQ_ERR_ARG;
+    return plan_create(batch, nx, nu, T, precision, LQ_SCAN, 0, seg_len, out);
 }
 
 void lq_plan_destroy(lq_plan *p)
@@ -231,27 +254,23 @@ lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *
     double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
-    double *fin = Xa;
-    if (p->mode == LQ_SEQUENTIAL) {
-        hipLaunchKernelGGL(lqk::k_value_terminal, dim3(p->batch), dim3(64), 0, st, P, p->d_inst, Xa);
-    } else {
-        timed(p, LQ_PH_VALUE_FOLD, st, [&] {
-            hipLaunchKernelGGL(lqk::k_value_fold, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, p->d_inst,
-                               p->d_seg_start, p->batch, elements, Xa, status);
-        });
-        double *in = Xa, *o = Xb;
+    timed(p, LQ_PH_VALUE_FOLD, st, [&] {
+        lqk::launch_value_fold(p->nk, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
+                               Xa, status);
+    });
+    double *in = Xa, *o = Xb;
+    if (p->max_nseg > 1)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
-            for (int dd = 1; dd <= p->max_nseg; dd *= 2) {
-                hipLaunchKernelGGL(lqk::k_value_ks, dim3((unsigned)p->total_x), dim3(64), 0, st, p->d_inst,
-                                   p->d_x_start, p->batch, dd, in, o, status);
+            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+                lqk::launch_value_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,
+                                     status);
                 std::swap(in, o);
             }
         });
-        fin = in;
-    }
+    double *fin = in;
     timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
-        hipLaunchKernelGGL(lqk::k_value_riccati, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, p->d_inst,
-                           p->d_seg_start, p->batch, fin, V, status);
+        lqk::launch_value_riccati(p->nk, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
+                                  V, status);
     });
     return launched();
 }
@@ -268,27 +287,22 @@ lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *v
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
-    double *fin = Ya;
-    if (p->mode == LQ_SEQUENTIAL) {
-        hipLaunchKernelGGL(lqk::k_roll_init, dim3(p->batch), dim3(64), 0, st, P, p->d_inst, Ya);
-    } else {
-        timed(p, LQ_PH_ROLL_FOLD, st, [&] {
-            hipLaunchKernelGGL(lqk::k_roll_fold, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, V, p->d_inst,
-                               p->d_seg_start, p->batch, Ya);
-        });
-        double *in = Ya, *o = Yb;
+    timed(p, LQ_PH_ROLL_FOLD, st, [&] {
+        lqk::launch_roll_fold(p->nk, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
+    });
+    double *in = Ya, *o = Yb;
+    if (p->max_nseg > 1)
         timed(p, LQ_PH_ROLL_SCAN, st, [&] {
-            for (int dd = 1; dd <= p->max_nseg; dd *= 2) {
-                hipLaunchKernelGGL(lqk::k_affine_ks, dim3((unsigned)p->total_x), dim3(64), 0, st, p->d_inst,
-                                   p->d_x_start, p->batch, dd, 0, in, o);
+            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+                lqk::launch_affine_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
+                                      o);
                 std::swap(in, o);
             }
         });
-        fin = in;
-    }
+    double *fin = in;
     timed(p, LQ_PH_ROLL_APPLY, st, [&] {
-        hipLaunchKernelGGL(lqk::k_roll_apply, dim3((unsigned)p->total_seg), dim3(64), 0, st, P, V, p->d_inst,
-                           p->d_seg_start, p->batch, fin, x, u, lambda);
+        lqk::launch_roll_apply(p->nk, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
+                               u, lambda);
     });
     return launched();
 }
@@ -297,9 +311,167 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
                      const double *u, const double *lambda, const double *gx, const double *gu,
                      const lq_grads *grads, void *workspace, int32_t *status, void *stream)
 {
-    (void)p; (void)prob; (void)val; (void)x; (void)u; (void)lambda; (void)gx; (void)gu; (void)grads;
-    (void)workspace; (void)status; (void)stream;
-    return LQ_ERR_UNSUPPORTED;
+    if (!p || !prob_ok(prob) || !val || !val->S || !val->s || !val->Gamma || !val->gamma) return LQ_ERR_ARG;
+    if (!x || !u || !lambda || !gx || !gu || !grads) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::AdjPtrs J{val->S, val->s, val->Gamma, val->gamma, x, u, lambda, gx, gu,
+                   (double *)(ws + p->off_st), (double *)(ws + p->off_gt)};
+    lqk::GradPtrs G{grads->A, grads->B, grads->c, grads->Q, grads->R, grads->M,
+                    grads->q, grads->r, grads->QT, grads->qT, grads->x0};
+    const unsigned nseg = (unsigned)p->total_seg, nx = (unsigned)p->total_x;
+    // backward linear-term scan
+    timed(p, LQ_PH_ADJ_BACK_FOLD, st, [&] {
+        lqk::launch_adj_back_fold(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
+    });
+    double *in = Ya, *o = Yb;
+    if (p->max_nseg > 1)
+        timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] {
+            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+                lqk::launch_affine_ks(p->nk, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
+                std::swap(in, o);
+            }
+        });
+    double *fin = in;
+    timed(p, LQ_PH_ADJ_BACK_APPLY, st, [&] {
+        lqk::launch_adj_back_apply(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, status);
+    });
+    // forward derivative scan + gradients
+    timed(p, LQ_PH_ADJ_FWD_FOLD, st, [&] {
+        lqk::launch_adj_fwd_fold(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
+    });
+    in = Ya;
+    o = Yb;
+    if (p->max_nseg > 1)
+        timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] {
+            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+                lqk::launch_affine_ks(p->nk, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in, o);
+                std::swap(in, o);
+            }
+        });
+    double *ffin = in;
+    timed(p, LQ_PH_ADJ_FWD_APPLY, st, [&] {
+        lqk::launch_adj_fwd_apply(p->nk, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
+    });
+    return launched();
+}
+
+// ---------------------------------------------------------------------------
+// Newton / interior point
+// ---------------------------------------------------------------------------
+
+// Layout of the Newton workspace after the plan's LQ workspace.
+struct NmpcLayout {
+    size_t A, B, P, Rt, Rh, d, th, g, lam, lamT, S, s, G, gm, dx, du, xc, uc, zero, status, total;
+};
+
+static NmpcLayout nmpc_layout(const lq_plan *p)
+{
+    const InstDesc &d = p->h_inst[0];
+    const size_t n = d.n, m = d.m, T = d.T, D = sizeof(double);
+    NmpcLayout L{};
+    size_t off = align_up(p->ws_bytes);
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.A = take(T * n * n * D); L.B = take(T * n * m * D); L.P = take(T * n * n * D);
+    L.Rt = take(T * m * m * D); L.Rh = take(T * m * m * D); L.d = take(T * m * D);
+    L.th = take(T * n * D); L.g = take(T * n * D); L.lam = take((T + 1) * n * D); L.lamT = take(n * D);
+    L.S = take((T + 1) * n * n * D); L.s = take((T + 1) * n * D); L.G = take(T * m * n * D);
+    L.gm = take(T * m * D); L.dx = take((T + 1) * n * D); L.du = take(T * m * D);
+    L.xc = take((T + 1) * n * D); L.uc = take(T * m * D); L.zero = take(n * D); L.status = take(64);
+    L.total = off;
+    return L;
+}
+
+static bool nmpc_matches(const lq_plan *p, const nmpc_problem *q)
+{
+    if (!p || !q || p->batch != 1) return false;
+    const InstDesc &d = p->h_inst[0];
+    return d.n == q->nx && d.m == q->nu && d.T == q->T && q->W && q->Bm && q->Q && q->R && q->QT && q->xref &&
+           q->x0 && q->umin < q->umax;
+}
+
+static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
+{
+    lqk::NmpcPtrs N;
+    N.nx = q->nx; N.nu = q->nu; N.T = q->T; N.h = q->h;
+    N.W = q->W; N.Bm = q->Bm; N.Q = q->Q; N.R = q->R; N.QT = q->QT; N.xref = q->xref; N.x0 = q->x0;
+    N.umin = q->umin; N.umax = q->umax;
+    return N;
+}
+
+static lqk::NmpcWork nmpc_work(const lq_plan *p, void *workspace)
+{
+    const NmpcLayout L = nmpc_layout(p);
+    char *w = (char *)workspace;
+    auto D = [&](size_t o) { return (double *)(w + o); };
+    lqk::NmpcWork Wk;
+    Wk.A = D(L.A); Wk.B = D(L.B); Wk.P = D(L.P); Wk.Rt = D(L.Rt); Wk.Rh = D(L.Rh); Wk.d = D(L.d);
+    Wk.th = D(L.th); Wk.g = D(L.g); Wk.lam = D(L.lam); Wk.lamT = D(L.lamT); Wk.S = D(L.S); Wk.s = D(L.s);
+    Wk.G = D(L.G); Wk.gm = D(L.gm); Wk.dx = D(L.dx); Wk.du = D(L.du); Wk.xc = D(L.xc); Wk.uc = D(L.uc);
+    Wk.zero = D(L.zero);
+    Wk.status = (int32_t *)(w + L.status);
+    return Wk;
+}
+
+size_t nmpc_workspace_bytes(const lq_plan *p)
+{
+    if (!p || p->batch != 1) return 0;
+    return nmpc_layout(p).total;
+}
+
+lq_status nmpc_init(const lq_plan *p, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
+                    void *stream)
+{
+    if (!nmpc_matches(p, prob) || !state || !state->x || !state->u || !state->scal) return LQ_ERR_ARG;
+    if (prob->nx > 15 || prob->nu > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
+    (void)workspace;
+    lqk::launch_nmpc_init((hipStream_t)stream, nmpc_ptrs(prob), state->x, state->u);
+    return launched();
+}
+
+lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
+                      int32_t *status, void *stream)
+{
+    (void)status;
+    if (!nmpc_matches(p, prob) || !state || !state->x || !state->u || !state->scal) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    const lqk::NmpcPtrs N = nmpc_ptrs(prob);
+    const lqk::NmpcWork Wk = nmpc_work(p, workspace);
+    char *ws = (char *)workspace;
+    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
+    lqk::launch_nmpc_clear(st, Wk.status, Wk.zero, prob->nx);
+    // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
+    lqk::launch_nmpc_linearise(st, N, Wk, state->x);
+    lqk::launch_costate_fold(p->nk, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
+    double *in = Ya, *o = Yb;
+    for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+        lqk::launch_affine_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
+        std::swap(in, o);
+    }
+    lqk::launch_costate_apply(p->nk, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
+    lqk::launch_nmpc_quadraticise(st, N, Wk, state->u, state->scal);
+    // the LQ step
+    lq_problem lp{};
+    lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt; lp.M = nullptr;
+    lp.q = nullptr; lp.r = Wk.d; lp.QT = prob->QT; lp.qT = nullptr; lp.x0 = Wk.zero;
+    lq_value val{Wk.S, Wk.s, Wk.G, Wk.gm};
+    lq_status r = lq_scan_solve(p, &lp, nullptr, &val, workspace, Wk.status, stream);
+    if (r != LQ_OK) return r;
+    r = lq_rollout(p, &lp, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);
+    if (r != LQ_OK) return r;
+    // candidate, decision, commit
+    lqk::launch_nmpc_candidate(st, N, Wk, state->x, state->u, state->scal);
+    lqk::launch_nmpc_accept(st, state->scal);
+    lqk::launch_nmpc_commit(st, N, Wk, state->x, state->u, state->scal);
+    return launched();
 }
 
 lq_status lq_plan_set_timing(lq_plan *p, uint32_t mask, int32_t capacity)

@@ -31,6 +31,37 @@ struct ValPtrs {
     double *S, *s, *G, *g;
 };
 
+// Adjoint inputs (forward solution, loss gradients) and its workspace vectors
+// s~ (same packing as s) and gamma~ (same packing as gamma).
+struct AdjPtrs {
+    const double *S, *s, *G, *g;
+    const double *x, *u, *lam;
+    const double *gx, *gu;
+    double *st, *gt;
+};
+
+struct GradPtrs {
+    double *A, *B, *c, *Q, *R, *M, *q, *r, *QT, *qT, *x0;
+};
+
+// Newton / interior-point: device scalars (indices match include/lqscan.h).
+enum { NMPC_MU = 0, NMPC_ALPHA = 1, NMPC_NU = 2, NMPC_COST = 3, NMPC_PRED = 4, NMPC_RHO = 5,
+       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_NSCAL = 8 };
+
+struct NmpcPtrs {
+    int nx, nu, T;
+    double h;
+    const double *W, *Bm, *Q, *R, *QT, *xref, *x0;
+    double umin, umax;
+};
+
+// Newton workspace arrays (stage-major like the LQ problem arrays).
+struct NmpcWork {
+    double *A, *B, *P, *Rt, *Rh, *d, *th, *g, *lam, *lamT;
+    double *S, *s, *G, *gm, *dx, *du, *xc, *uc, *zero;
+    int32_t *status;
+};
+
 // Index of the instance owning global item g, by binary search over the
 // prefix array start[0..batch] (start[0] = 0, start[batch] = total).
 LQK_DEV int find_inst(const int32_t *start, int batch, int64_t g)
@@ -68,13 +99,12 @@ LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k)
     const int n = d.n;
     Tile t = gload_rm(P.A + d.oA + (int64_t)k * n * n, n, n, n);
     const int c = tcol();
-    if (c == n) {
-        const double *cc = P.c ? P.c + d.oc + (int64_t)k * n : nullptr;
+    const double *cc = P.c ? P.c + d.oc + (int64_t)k * n : nullptr;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = trow(r);
-            t.v[r] = (i < n) ? (cc ? cc[i] : 0.0) : (i == n ? 1.0 : 0.0);
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double cv = cc ? ldz(cc, i, i < n && c == n) : 0.0;
+        if (c == n) t.v[r] = (i < n) ? cv : (i == n ? 1.0 : 0.0);
     }
     return t;
 }
@@ -96,8 +126,9 @@ LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = trow(r);
-            if (c == n && i < n) t.v[r] = qq[i];
-            if (i == n && c < n) t.v[r] = qq[c];
+            const bool col = (c == n && i < n), row = (i == n && c < n);
+            const double v = ldz(qq, col ? i : c, col || row);
+            if (col || row) t.v[r] = v;
         }
     }
     return t;
@@ -114,7 +145,8 @@ LQK_DEV Tile load_MhT(const ProbPtrs &P, const InstDesc &d, int k)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int a = trow(r);
-            if (c == n && a < m) t.v[r] = rr[a];
+            const double v = ldz(rr, a, c == n && a < m);
+            if (c == n && a < m) t.v[r] = v;
         }
     }
     return t;
@@ -138,8 +170,9 @@ LQK_DEV Tile load_terminal_J(const ProbPtrs &P, const InstDesc &d, double *s)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = trow(r);
-            if (c == n && i < n) t.v[r] = qq[i];
-            if (i == n && c < n) t.v[r] = qq[c];
+            const bool col = (c == n && i < n), row = (i == n && c < n);
+            const double v = ldz(qq, col ? i : c, col || row);
+            if (col || row) t.v[r] = v;
         }
     }
     return t;
@@ -161,12 +194,12 @@ LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, in
     const int n = d.n, m = d.m;
     Tile t = gload_rm(Gam + d.oG + (int64_t)k * m * n, m, n, n);
     const int c = tcol();
-    if (c == n) {
+    const double *gg = gam + d.og + (int64_t)k * m;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int a = trow(r);
-            if (a < m) t.v[r] = gam[d.og + (int64_t)k * m + a];
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int a = trow(r);
+        const double v = ldz(gg, a, c == n && a < m);
+        if (c == n && a < m) t.v[r] = v;
     }
     return t;
 }
@@ -181,8 +214,9 @@ LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
-        if (c == n && i < n) t.v[r] = ss[i];
-        if (i == n && c < n) t.v[r] = ss[c];
+        const bool col = (c == n && i < n), row = (i == n && c < n);
+        const double v = ldz(ss, col ? i : c, col || row);
+        if (col || row) t.v[r] = v;
     }
     return t;
 }
@@ -192,12 +226,11 @@ LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
 LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
 {
     Tile t = tzero();
-    if (tcol() == col) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = trow(r);
-            t.v[r] = (v && i < len) ? v[i] : (i == one_row ? 1.0 : 0.0);
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double x = v ? ldz(v, i, i < len && tcol() == col) : 0.0;
+        if (tcol() == col) t.v[r] = (i < len) ? x : (i == one_row ? 1.0 : 0.0);
     }
     return t;
 }

@@ -1,0 +1,365 @@
+// lq_newton.hip -- one iteration of the parallel-in-time Newton method (Alg. 4)
+// inside the primal log-barrier method (Sec. II-B), for the dynamics
+//   x_{k+1} = x_k + h (tanh(W x_k) + B u_k),
+// tracking costs l_k = 1/2 (x - ref_k)'Q(x - ref_k) + 1/2 u'R u,
+// l_T = 1/2 (x - ref_T)'Q_T(x - ref_T), and the box |u| bounds written as
+// 2 nu inequalities u - umax <= 0, umin - u <= 0 with the barrier
+//   c(u) = -mu sum_i [log(umax - u_i) + log(u_i - umin)].
+//
+// Steps (all enqueued on the caller's stream, decisions taken on the device):
+//   1. k_nmpc_linearise      A_k = I + h diag(1 - tanh^2 z) W, B_k = h B, z = W x_k,
+//                            g_k = Q (x_k - ref_k)
+//   2. co-state suffix scan  lambda_T = Q_T(x_T - ref_T),
+//                            lambda_k = g_k + A_k' lambda_{k+1}   (eq:co-state-eq;
+//                            homogeneous maps [[A_k', g_k], [0, 1]], Alg. 1)
+//   3. k_nmpc_quadraticise   P_k = Q + sum_i lambda_{k+1,i} h tanh''(z_i) w_i w_i',
+//                            R~_k = R + d2c/du2 + alpha I, d_k = R u + dc/du + B_k' lambda_{k+1}
+//   4. the LQ step           eq:linearized-ocp with psi_t of eq:linearized-ocp-param
+//                            (delta x_0 = 0) by lq_scan_solve + lq_rollout
+//   5. k_nmpc_candidate      predicted decrease of the expansion (without alpha),
+//                            candidate u + du, its nonlinear rollout and J_mu
+//   6. k_nmpc_accept         gain ratio rho = (J_mu(u) - J_mu(u + du)) / pred;
+//                            accept if pred > 0 and rho > 0: alpha *= max(1/3,
+//                            1 - (2 rho - 1)^3), nu = 2; else alpha *= nu, nu *= 2
+//   7. k_nmpc_commit         on acceptance the candidate replaces the nominal.
+#include <algorithm>
+
+#include "lq_kernels.hpp"
+
+namespace lqk {
+
+// Sequential pieces run on one lane; the state dimension is at most 15.
+constexpr int NXMAX = 15;
+constexpr int NUMAX = MMAX;
+
+// Nonlinear step x' = x + h (tanh(W x) + B u).
+LQK_DEV void f_step(const NmpcPtrs &N, int n, int m, const double *x, const double *u, double *xn)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = 0.0, bu = 0.0;
+        for (int j = 0; j < n; ++j) z += N.W[i * n + j] * x[j];
+        for (int j = 0; j < m; ++j) bu += N.Bm[i * m + j] * u[j];
+        xn[i] = x[i] + N.h * (tanh(z) + bu);
+    }
+}
+
+// Stage cost plus barrier at stage k (returns +inf if u is infeasible).
+LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, const double *xk, const double *uk, double mu)
+{
+    const double *rk = N.xref + (int64_t)k * n;
+    double J = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) J += 0.5 * (xk[i] - rk[i]) * N.Q[i * n + j] * (xk[j] - rk[j]);
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < m; ++j) J += 0.5 * uk[i] * N.R[i * m + j] * uk[j];
+        const double a = N.umax - uk[i], b = uk[i] - N.umin;
+        if (!(a > 0.0 && b > 0.0)) return INFINITY;
+        J += -mu * (log(a) + log(b));
+    }
+    return J;
+}
+
+LQK_DEV double terminal_cost(const NmpcPtrs &N, int n, int T, const double *xT)
+{
+    const double *rT = N.xref + (int64_t)T * n;
+    double J = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) J += 0.5 * (xT[i] - rT[i]) * N.QT[i * n + j] * (xT[j] - rT[j]);
+    return J;
+}
+
+// Initial nonlinear rollout of the nominal controls (one lane).
+__global__ __launch_bounds__(64) void k_nmpc_init(NmpcPtrs N, double *x, const double *u)
+{
+    if (threadIdx.x != 0) return;
+    const int n = N.nx, m = N.nu;
+    double xc[NXMAX];
+    for (int i = 0; i < n; ++i) xc[i] = x[i] = N.x0[i];
+    for (int k = 0; k < N.T; ++k) {
+        double xn[NXMAX];
+        f_step(N, n, m, xc, u + (int64_t)k * m, xn);
+        for (int i = 0; i < n; ++i) x[(int64_t)(k + 1) * n + i] = xc[i] = xn[i];
+    }
+}
+
+// Step 0: clear the internal LQ status and the LQ's zero initial state.
+__global__ void k_nmpc_clear(int32_t *st, double *zero, int n)
+{
+    if (threadIdx.x == 0) st[0] = 0;
+    if (threadIdx.x < n) zero[threadIdx.x] = 0.0;
+}
+
+// Step 1 (one lane per stage).
+__global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = N.nx, m = N.nu;
+    if (k > N.T) return;
+    const double *xk = x + (int64_t)k * n;
+    const double *rk = N.xref + (int64_t)k * n;
+    if (k == N.T) {   // terminal co-state lambda_T = Q_T (x_T - ref_T)
+        for (int i = 0; i < n; ++i) {
+            double v = 0.0;
+            for (int j = 0; j < n; ++j) v += N.QT[i * n + j] * (xk[j] - rk[j]);
+            Wk.lamT[i] = v;
+        }
+        return;
+    }
+    double th[NXMAX];
+    for (int i = 0; i < n; ++i) {
+        double z = 0.0;
+        for (int j = 0; j < n; ++j) z += N.W[i * n + j] * xk[j];
+        th[i] = tanh(z);
+        Wk.th[(int64_t)k * n + i] = th[i];
+    }
+    double *A = Wk.A + (int64_t)k * n * n;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[i * n + j] = (i == j ? 1.0 : 0.0) + N.h * (1.0 - th[i] * th[i]) * N.W[i * n + j];
+    double *B = Wk.B + (int64_t)k * n * m;
+    for (int i = 0; i < n * m; ++i) B[i] = N.h * N.Bm[i];
+    for (int i = 0; i < n; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < n; ++j) v += N.Q[i * n + j] * (xk[j] - rk[j]);
+        Wk.g[(int64_t)k * n + i] = v;
+    }
+}
+
+// Co-state map [[A_k', g_k], [0, 1]] from the linearisation.
+LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k, double *s0)
+{
+    const int n = d.n;
+    Tile t = gload_rm_t(Wk.A + (int64_t)k * n * n, n, n, n);   // A_k'
+    const Tile gv = load_vec(Wk.g + (int64_t)k * n, n, n, n);
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (c == n) t.v[r] = gv.v[r];
+    (void)s0;
+    return t;
+}
+
+// Step 2a: segment fold of the co-state maps (suffix); the block of the last
+// segment writes the terminal element [[0, lambda_T], [0, 1]].
+template <int NK>
+__global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst, double *Y)
+{
+    __shared__ double lds[2 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT;
+    const InstDesc d = inst[0];
+    const int s = blockIdx.x;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT, d.n, d.n, d.n));
+    if (s == 0) return;
+    Tile Psi = tident(d.n + 1);
+    for (int k = k0; k < k1; ++k) Psi = mmk<NK, false, false>(Psi, costate_map(Wk, d, k, s0), s0, s1);
+    gstore(Y + (int64_t)(d.xbase + s) * TILE, Psi);
+}
+
+// Step 2c: co-states inside each segment from lambda at its right end.
+template <int NK>
+__global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDesc *__restrict__ inst,
+                                                      const double *__restrict__ Yfin)
+{
+    __shared__ double lds[2 * SLOT];
+    double *s0 = lds, *s1 = lds + SLOT;
+    const InstDesc d = inst[0];
+    const int s = blockIdx.x;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n = d.n;
+    Tile L = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);
+    if (s == d.nseg - 1) store_vec(Wk.lam + (int64_t)d.T * n, L, n, n);
+    for (int k = k1 - 1; k >= k0; --k) {
+        L = mmk<NK, false, false>(costate_map(Wk, d, k, s0), L, s0, s1);
+        store_vec(Wk.lam + (int64_t)k * n, L, n, n);
+    }
+}
+
+// Step 3 (one lane per stage): second-order terms of the Hamiltonian.
+__global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *u,
+                                                           const double *scal)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = N.nx, m = N.nu;
+    if (k >= N.T) return;
+    const double mu = scal[NMPC_MU], alpha = scal[NMPC_ALPHA];
+    const double *th = Wk.th + (int64_t)k * n;
+    const double *l1 = Wk.lam + (int64_t)(k + 1) * n;
+    double *P = Wk.P + (int64_t)k * n * n;
+    for (int i = 0; i < n * n; ++i) P[i] = N.Q[i];
+    for (int i = 0; i < n; ++i) {
+        const double t = th[i];
+        const double w = l1[i] * N.h * (-2.0 * t * (1.0 - t * t));
+        for (int a = 0; a < n; ++a)
+            for (int b = 0; b < n; ++b) P[a * n + b] += w * N.W[i * n + a] * N.W[i * n + b];
+    }
+    const double *uk = u + (int64_t)k * m;
+    double *Rt = Wk.Rt + (int64_t)k * m * m;
+    double *Rh = Wk.Rh + (int64_t)k * m * m;
+    for (int i = 0; i < m * m; ++i) Rh[i] = N.R[i];
+    for (int i = 0; i < m; ++i) {
+        const double a = N.umax - uk[i], b = uk[i] - N.umin;
+        Rh[i * m + i] += mu * (1.0 / (a * a) + 1.0 / (b * b));
+    }
+    for (int i = 0; i < m * m; ++i) Rt[i] = Rh[i];
+    for (int i = 0; i < m; ++i) Rt[i * m + i] += alpha;
+    const double *B = Wk.B + (int64_t)k * n * m;
+    for (int i = 0; i < m; ++i) {
+        double v = 0.0;
+        for (int j = 0; j < m; ++j) v += N.R[i * m + j] * uk[j];
+        const double uu = uk[i];
+        v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
+        for (int j = 0; j < n; ++j) v += B[j * m + i] * l1[j];
+        Wk.d[(int64_t)k * m + i] = v;
+    }
+}
+
+// Step 5 (one lane): predicted decrease, candidate controls, their nonlinear
+// rollout, J_mu of the nominal and of the candidate.
+__global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
+                                                       double *scal)
+{
+    if (threadIdx.x != 0) return;
+    const int n = N.nx, m = N.nu, T = N.T;
+    const double mu = scal[NMPC_MU];
+    const bool lq_ok = (Wk.status[0] == 0);
+    // predicted decrease (alpha excluded)
+    double pred = 0.0;
+    for (int k = 0; k < T; ++k) {
+        const double *dxk = Wk.dx + (int64_t)k * n, *duk = Wk.du + (int64_t)k * m;
+        for (int i = 0; i < m; ++i) pred += Wk.d[(int64_t)k * m + i] * duk[i];
+        double qf = 0.0;
+        const double *P = Wk.P + (int64_t)k * n * n, *Rh = Wk.Rh + (int64_t)k * m * m;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) qf += dxk[i] * P[i * n + j] * dxk[j];
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) qf += duk[i] * Rh[i * m + j] * duk[j];
+        pred += 0.5 * qf;
+    }
+    {
+        const double *dxT = Wk.dx + (int64_t)T * n;
+        double qf = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) qf += dxT[i] * N.QT[i * n + j] * dxT[j];
+        pred += 0.5 * qf;
+    }
+    pred = -pred;
+    // J_mu of the nominal
+    double J0 = 0.0;
+    for (int k = 0; k < T; ++k) J0 += stage_cost(N, n, m, k, x + (int64_t)k * n, u + (int64_t)k * m, mu);
+    J0 += terminal_cost(N, n, T, x + (int64_t)T * n);
+    // candidate
+    double xc[NXMAX];
+    for (int i = 0; i < n; ++i) xc[i] = Wk.xc[i] = N.x0[i];
+    double J1 = 0.0;
+    bool feas = true;
+    for (int k = 0; k < T; ++k) {
+        double uk[NUMAX];
+        for (int i = 0; i < m; ++i) {
+            uk[i] = u[(int64_t)k * m + i] + Wk.du[(int64_t)k * m + i];
+            Wk.uc[(int64_t)k * m + i] = uk[i];
+            feas = feas && (uk[i] < N.umax) && (uk[i] > N.umin);
+        }
+        const double c = stage_cost(N, n, m, k, xc, uk, mu);
+        J1 += c;
+        double xn[NXMAX];
+        f_step(N, n, m, xc, uk, xn);
+        for (int i = 0; i < n; ++i) Wk.xc[(int64_t)(k + 1) * n + i] = xc[i] = xn[i];
+    }
+    J1 += terminal_cost(N, n, T, xc);
+    if (!feas) J1 = INFINITY;
+    scal[NMPC_PRED] = lq_ok ? pred : 0.0;
+    scal[NMPC_COST] = J0;
+    scal[NMPC_COST_NEW] = lq_ok ? J1 : INFINITY;
+}
+
+// Step 6 (one lane): accept / reject and the damping update.
+__global__ void k_nmpc_accept(double *scal)
+{
+    if (threadIdx.x != 0) return;
+    const double pred = scal[NMPC_PRED], J0 = scal[NMPC_COST], J1 = scal[NMPC_COST_NEW];
+    double alpha = scal[NMPC_ALPHA], nu = scal[NMPC_NU];
+    double rho = -INFINITY;
+    bool acc = false;
+    if (pred > 0.0 && isfinite(J1)) {
+        rho = (J0 - J1) / pred;
+        acc = rho > 0.0;
+    }
+    if (acc) {
+        const double t = 2.0 * rho - 1.0;
+        const double f = 1.0 - t * t * t;
+        alpha *= (f > 1.0 / 3.0 ? f : 1.0 / 3.0);
+        nu = 2.0;
+        scal[NMPC_COST] = J1;
+    } else {
+        alpha *= nu;
+        nu *= 2.0;
+    }
+    scal[NMPC_ALPHA] = alpha;
+    scal[NMPC_NU] = nu;
+    scal[NMPC_RHO] = rho;
+    scal[NMPC_ACCEPTED] = acc ? 1.0 : 0.0;
+}
+
+// Step 7: on acceptance the candidate becomes the nominal.
+__global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork Wk, double *x, double *u,
+                                                     const double *scal)
+{
+    if (scal[NMPC_ACCEPTED] == 0.0) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nx = (int64_t)(N.T + 1) * N.nx, nu = (int64_t)N.T * N.nu;
+    if (i < nx) x[i] = Wk.xc[i];
+    if (i < nu) u[i] = Wk.uc[i];
+}
+
+#define LQK_NK_SWITCH(nk, CALL) \
+    switch (nk) {               \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    default: CALL(4); break;    \
+    }
+
+void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
+{
+    hipLaunchKernelGGL(k_nmpc_init, dim3(1), dim3(64), 0, st, N, x, u);
+}
+void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
+{
+    hipLaunchKernelGGL(k_nmpc_clear, dim3(1), dim3(64), 0, st, status, zero, n);
+}
+void launch_nmpc_linearise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x)
+{
+    hipLaunchKernelGGL(k_nmpc_linearise, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
+}
+void launch_costate_fold(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
+{
+#define CALL(K) hipLaunchKernelGGL(k_costate_fold<K>, dim3(grid), dim3(64), 0, st, Wk, inst, Y)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+void launch_costate_apply(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                          const double *Yfin)
+{
+#define CALL(K) hipLaunchKernelGGL(k_costate_apply<K>, dim3(grid), dim3(64), 0, st, Wk, inst, Yfin)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+void launch_nmpc_quadraticise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal)
+{
+    hipLaunchKernelGGL(k_nmpc_quadraticise, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
+}
+void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
+{
+    hipLaunchKernelGGL(k_nmpc_candidate, dim3(1), dim3(64), 0, st, N, Wk, x, u, scal);
+}
+void launch_nmpc_accept(hipStream_t st, double *scal)
+{
+    hipLaunchKernelGGL(k_nmpc_accept, dim3(1), dim3(64), 0, st, scal);
+}
+void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal)
+{
+    const int64_t cnt = std::max((int64_t)(N.T + 1) * N.nx, (int64_t)N.T * N.nu);
+    hipLaunchKernelGGL(k_nmpc_commit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, Wk, x, u, scal);
+}
+
+}  // namespace lqk

@@ -25,9 +25,10 @@ LQK_DEV Tile closed_loop(const ProbPtrs &P, const ValPtrs &V, const InstDesc &d,
     const Tile Ah = load_Ah(P, d, k);
     const Tile Bh = load_Bh(P, d, k);
     const Tile Gh = load_Gh(V.G, V.g, d, k);
-    return mma<false, false>(Bh, Gh, Ah, d.m, s0, s1);
+    return mmak<1, false, false>(Bh, Gh, Ah, s0, s1);
 }
 
+template <int NK>
 __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                   const int32_t *__restrict__ seg_start, int batch,
                                                   double *__restrict__ Y)
@@ -39,19 +40,23 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    const int n1 = d.n + 1;
-    Tile Phi = tident(n1);
+    if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
+    // The map of the last segment is never read: segment s starts from the
+    // scanned entry s.
+    if (s == d.nseg - 1) return;
+    Tile Phi = tident(d.n + 1);
     for (int k = k0; k < k1; ++k) {
         const Tile F = closed_loop(P, V, d, k, s0, s1);
-        Phi = mm<false, false>(F, Phi, n1, s0, s1);
+        Phi = mmk<NK, false, false>(F, Phi, s0, s1);
     }
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
-    if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
 }
 
 // One Kogge-Stone level over entries [xbase, xbase + nseg] of each instance.
 // suffix = 0: Y_s <- Y_s Y_{s-dd} for s >= dd;  suffix = 1: Y_s <- Y_s Y_{s+dd}
-// for s + dd <= nseg; other entries are copied.
+// for s + dd <= nseg; other entries are copied.  The entry that no segment
+// reads (the last of a prefix scan, the first of a suffix scan) is skipped.
+template <int NK>
 __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ inst,
                                                   const int32_t *__restrict__ x_start, int batch, int dd,
                                                   int suffix, const double *__restrict__ Yin,
@@ -62,6 +67,7 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     const int i = find_inst(x_start, batch, gx);
     const InstDesc d = inst[i];
     const int s = gx - d.xbase;
+    if (suffix ? (s == 0) : (s == d.nseg)) return;   // entries that are never read
     const Tile a = gload(Yin + (int64_t)gx * TILE);
     const bool active = suffix ? (s + dd <= d.nseg) : (s >= dd);
     if (!active) {
@@ -70,9 +76,10 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     }
     const int64_t ob = suffix ? gx + dd : gx - dd;
     const Tile b = gload(Yin + ob * TILE);
-    gstore(Yout + (int64_t)gx * TILE, mm<false, false>(a, b, d.n + 1, lds, lds + SLOT));
+    gstore(Yout + (int64_t)gx * TILE, mmk<NK, false, false>(a, b, lds, lds + SLOT));
 }
 
+template <int NK>
 __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ Yfin, double *__restrict__ x,
@@ -85,26 +92,26 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    const int n = d.n, m = d.m, n1 = n + 1;
+    const int n = d.n, m = d.m;
     Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
     for (int k = k0; k < k1; ++k) {
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
         const Tile Gh = load_Gh(V.G, V.g, d, k);
-        const Tile U = mm<false, false>(Gh, X, n1, s0, s1);
+        const Tile U = mmk<NK, false, false>(Gh, X, s0, s1);
         store_vec(u + d.og + (int64_t)k * m, U, m, n);
         if (lam) {
             const Tile Sh = load_Sh(V.S, V.s, d, k);
-            store_vec(lam + d.os + (int64_t)k * n, mm<false, false>(Sh, X, n1, s0, s1), n, n);
+            store_vec(lam + d.os + (int64_t)k * n, mmk<NK, false, false>(Sh, X, s0, s1), n, n);
         }
         const Tile Ah = load_Ah(P, d, k);
         const Tile Bh = load_Bh(P, d, k);
-        X = mma<false, false>(Bh, U, mm<false, false>(Ah, X, n1, s0, s1), m, s0, s1);
+        X = mmak<1, false, false>(Bh, U, mmk<NK, false, false>(Ah, X, s0, s1), s0, s1);
     }
     if (k1 == d.T) {
         store_vec(x + d.os + (int64_t)d.T * n, X, n, n);
         if (lam) {
             const Tile Sh = load_Sh(V.S, V.s, d, d.T);
-            store_vec(lam + d.os + (int64_t)d.T * n, mm<false, false>(Sh, X, n1, s0, s1), n, n);
+            store_vec(lam + d.os + (int64_t)d.T * n, mmk<NK, false, false>(Sh, X, s0, s1), n, n);
         }
     }
 }
@@ -112,11 +119,35 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
 }  // namespace lqk
 
 namespace lqk {
-// Sequential mode: the scan buffer entry of segment 0 is just the x0 element.
-__global__ __launch_bounds__(64) void k_roll_init(ProbPtrs P, const InstDesc *__restrict__ inst,
-                                                  double *__restrict__ Y)
+#define LQK_NK_SWITCH(nk, CALL) \
+    switch (nk) {               \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    default: CALL(4); break;    \
+    }
+
+void launch_roll_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                      const int32_t *seg_start, int batch, double *Y)
 {
-    const InstDesc d = inst[blockIdx.x];
-    gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
+#define CALL(K) hipLaunchKernelGGL(k_roll_fold<K>, dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Y)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+
+void launch_affine_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
+                      int dd, int suffix, const double *Yin, double *Yout)
+{
+#define CALL(K) hipLaunchKernelGGL(k_affine_ks<K>, dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, suffix, Yin, Yout)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+
+void launch_roll_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                       const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u, double *lam)
+{
+#define CALL(K) hipLaunchKernelGGL(k_roll_apply<K>, dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Yfin, x, u, lam)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
 }
 }  // namespace lqk

@@ -39,8 +39,16 @@ LQK_DEV int tgrp() { return (threadIdx.x >> 4) & 3; }
 // Row of register r of this lane.
 LQK_DEV int trow(int r) { return 4 * r + tgrp(); }
 
-// Wave-level barrier for LDS hand-offs between lanes (blocks are one wave).
-LQK_DEV void wsync() { __syncthreads(); }
+// Ordering point for LDS hand-offs between the lanes of one wave.  LDS
+// instructions of a wave are executed in order, so a wavefront-scope fence
+// (which keeps the compiler from moving LDS accesses across it) is enough;
+// unlike a workgroup barrier it does not wait for outstanding global loads.
+LQK_DEV void wsync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 LQK_DEV Tile tzero()
 {
@@ -86,28 +94,39 @@ LQK_DEV Tile gload(const double *p)
 }
 LQK_DEV void gstore(double *p, const Tile &t) { *reinterpret_cast<d4 *>(p + 4 * lane()) = t.v; }
 
+// Load p[idx] if ok, else 0; the load itself is unconditional (index clamped
+// to 0, which must be valid) so that independent loads issue back to back
+// instead of one branch-and-wait each.
+LQK_DEV double ldz(const double *p, int64_t idx, bool ok)
+{
+    const double v = p[ok ? idx : 0];
+    return ok ? v : 0.0;
+}
+
 // Global memory, row-major rows x cols block with leading dimension ld,
 // placed at tile offset (i0, j0); everything else zero.
 LQK_DEV Tile gload_rm(const double *src, int rows, int cols, int ld, int i0 = 0, int j0 = 0)
 {
-    Tile t;
+    Tile t = tzero();
+    if (!src) return t;
     const int c = tcol() - j0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r) - i0;
-        t.v[r] = (src && i >= 0 && i < rows && c >= 0 && c < cols) ? src[i * ld + c] : 0.0;
+        t.v[r] = ldz(src, (int64_t)i * ld + c, i >= 0 && i < rows && c >= 0 && c < cols);
     }
     return t;
 }
 // Transposed placement: tile(i0 + i, j0 + j) = src[j * ld + i].
 LQK_DEV Tile gload_rm_t(const double *src, int rows, int cols, int ld, int i0 = 0, int j0 = 0)
 {
-    Tile t;
+    Tile t = tzero();
+    if (!src) return t;
     const int c = tcol() - j0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r) - i0;
-        t.v[r] = (src && i >= 0 && i < rows && c >= 0 && c < cols) ? src[c * ld + i] : 0.0;
+        t.v[r] = ldz(src, (int64_t)c * ld + i, i >= 0 && i < rows && c >= 0 && c < cols);
     }
     return t;
 }
@@ -146,7 +165,22 @@ LQK_DEV Tile sget_t(const double *s)
     return t;
 }
 
-// acc + op(X) op(Y) over contraction length 4*ks, operands already staged.
+// acc + op(X) op(Y) over contraction length 4*KS, operands already staged.
+template <int KS, bool TX, bool TY>
+LQK_DEV d4 mfma_k(const double *sx, const double *sy, d4 acc)
+{
+    const int c = tcol(), g = tgrp();
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int kk = 4 * k + g;
+        const double a = TX ? sx[kk * LD + c] : sx[c * LD + kk];
+        const double b = TY ? sy[c * LD + kk] : sy[kk * LD + c];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Same with a run-time slice count (small auxiliary products only).
 template <bool TX, bool TY>
 LQK_DEV d4 mfma_staged(const double *sx, const double *sy, int ks, d4 acc)
 {
@@ -187,6 +221,51 @@ LQK_DEV Tile mma(const Tile &X, const Tile &Y, const Tile &acc, int K, double *s
     d.v = mfma_staged<TX, TY>(sx, sy, kslices(K), acc.v);
     wsync();
     return d;
+}
+
+// Compile-time slice-count versions of mm / mma.
+template <int KS, bool TX, bool TY>
+LQK_DEV Tile mmk(const Tile &X, const Tile &Y, double *sx, double *sy)
+{
+    wsync();
+    sput(sx, X);
+    sput(sy, Y);
+    wsync();
+    Tile d;
+    d.v = mfma_k<KS, TX, TY>(sx, sy, (d4){0.0, 0.0, 0.0, 0.0});
+    return d;
+}
+template <int KS, bool TX, bool TY>
+LQK_DEV Tile mmak(const Tile &X, const Tile &Y, const Tile &acc, double *sx, double *sy)
+{
+    wsync();
+    sput(sx, X);
+    sput(sy, Y);
+    wsync();
+    Tile d;
+    d.v = mfma_k<KS, TX, TY>(sx, sy, acc.v);
+    return d;
+}
+
+// A vector v held in column `col` of a tile (v[i] in lane col + 16*(i%4),
+// register i/4).  vrows returns v at this lane's four rows, vcol returns
+// v at this lane's column; both by lane shuffles, no LDS.
+LQK_DEV d4 vrows(const Tile &V, int col)
+{
+    const int src = col + 16 * tgrp();
+    d4 o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[r] = __shfl(V.v[r], src);
+    return o;
+}
+LQK_DEV double vcol(const Tile &V, int col)
+{
+    const int c = tcol();
+    const int src = col + 16 * (c & 3);
+    const double x0 = __shfl(V.v[0], src), x1 = __shfl(V.v[1], src);
+    const double x2 = __shfl(V.v[2], src), x3 = __shfl(V.v[3], src);
+    const int rr = c >> 2;
+    return rr == 0 ? x0 : (rr == 1 ? x1 : (rr == 2 ? x2 : x3));
 }
 
 // Symmetric part 1/2 (X + X').
@@ -292,7 +371,10 @@ LQK_DEV void small_read(const double *s, int m, double a[MMAX][MMAX])
 #pragma unroll
     for (int i = 0; i < MMAX; ++i)
 #pragma unroll
-        for (int j = 0; j < MMAX; ++j) a[i][j] = (i < m && j < m) ? s[i * LD + j] : (i == j ? 1.0 : 0.0);
+        for (int j = 0; j < MMAX; ++j) {
+            const double v = s[i * LD + j];  // in the slot for every i, j < MMAX
+            a[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
+        }
 }
 
 // In-register Cholesky a = L L' (lower, into a).  False if not PD.
@@ -469,7 +551,12 @@ LQK_DEV bool chol_inv_global(const double *R, int m, double li[MMAX][MMAX])
 #pragma unroll
     for (int i = 0; i < MMAX; ++i)
 #pragma unroll
-        for (int j = 0; j < MMAX; ++j) li[i][j] = (i < m && j < m) ? R[i * m + j] : (i == j ? 1.0 : 0.0);
+        for (int j = 0; j < MMAX; ++j) {
+            // clamped indices keep every load in bounds and unconditional
+            const int ii = i < m ? i : 0, jj = j < m ? j : 0;
+            const double v = R[ii * m + jj];
+            li[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
+        }
     const bool ok = small_chol(li);
     small_tri_inv(li);
     return ok;

@@ -61,12 +61,9 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
         double v = 0.0;
-        if (i < n && c < m) {
 #pragma unroll
-            for (int b = 0; b < MMAX; ++b)
-                if (b < m) v += Bk[i * m + b] * lrow[b];
-        }
-        e.G.v[r] = v;
+        for (int b = 0; b < MMAX; ++b) v += ldz(Bk, (int64_t)i * m + b, i < n && b < m) * lrow[b];
+        e.G.v[r] = (i < n && c < m) ? v : 0.0;
     }
     e.Ab = load_Ah(P, d, k);
     e.J = load_Qh(P, d, k);
@@ -83,18 +80,13 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
             double lg = 0.0;
 #pragma unroll
             for (int a = 0; a < MMAX; ++a) lg = (a == g) ? li[a][b] : lg;
-            double mt = 0.0;
-            if (b < m) {
-                if (c < n)
-                    mt = Mk ? Mk[c * m + b] : 0.0;
-                else if (c == n)
-                    mt = rk ? rk[b] : 0.0;
-            }
+            const double mt = (Mk ? ldz(Mk, (int64_t)c * m + b, c < n && b < m) : 0.0) +
+                              (rk ? ldz(rk, b, c == n && b < m) : 0.0);
             v += lg * mt;
         }
         N.v[0] = (g < m) ? v : 0.0;
-        e.Ab = tsub(e.Ab, mm<false, false>(e.G, N, m, s0, s1));
-        e.J = tsub(e.J, mm<true, false>(N, N, m, s0, s1));
+        e.Ab = tsub(e.Ab, mmk<1, false, false>(e.G, N, s0, s1));
+        e.J = tsub(e.J, mmk<1, true, false>(N, N, s0, s1));
     }
     return ok;
 }
@@ -102,10 +94,10 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
 // Left fold of a stage element into an aggregate E = (A^, C^, J^):
 // E <- e_k (x) E with the rank-m Woodbury form of the operator.
 // Returns false if W = I + G'J^G is singular.
-LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int n1, int m,
+template <int NK>
+LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int m,
                        double *s0, double *s1, double *s2, double *s3)
 {
-    const int ks = kslices(n1), km = kslices(m);
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     wsync();
     sput(s0, Jh);
@@ -114,18 +106,18 @@ LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int n1,
     sput(s3, e.Ab);
     wsync();
     Tile JG, H, JA, AA;
-    JG.v = mfma_staged<false, false>(s0, s1, ks, z);   // J^ G
-    H.v = mfma_staged<false, false>(s2, s1, ks, z);    // A^ G
-    JA.v = mfma_staged<false, false>(s0, s3, ks, z);   // J^ Ab
-    AA.v = mfma_staged<false, false>(s2, s3, ks, z);   // A^ Ab
+    JG.v = mfma_k<NK, false, false>(s0, s1, z);   // J^ G
+    H.v = mfma_k<NK, false, false>(s2, s1, z);    // A^ G
+    JA.v = mfma_k<NK, false, false>(s0, s3, z);   // J^ Ab
+    AA.v = mfma_k<NK, false, false>(s2, s3, z);   // A^ Ab
     wsync();
     sput(s0, JG);
     sput(s2, JA);
     wsync();
     Tile W, P, Jn;
-    W.v = mfma_staged<true, false>(s1, s0, ks, tident(m).v);  // I + G'J^G
-    P.v = mfma_staged<true, false>(s1, s2, ks, z);             // G'J^ Ab
-    Jn.v = mfma_staged<true, false>(s3, s2, ks, e.J.v);        // Ab'J^ Ab + J
+    W.v = mfma_k<NK, true, false>(s1, s0, tident(m).v);  // I + G'J^G
+    P.v = mfma_k<NK, true, false>(s1, s2, z);             // G'J^ Ab
+    Jn.v = mfma_k<NK, true, false>(s3, s2, e.J.v);        // Ab'J^ Ab + J
     Tile Wi;
     const bool ok = gen_inverse_small(W, m, Wi, s0);
     wsync();
@@ -134,17 +126,17 @@ LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int n1,
     sput(s2, H);
     wsync();
     Tile WP, WH;
-    WP.v = mfma_staged<false, false>(s0, s1, km, z);   // W^{-1} P
-    WH.v = mfma_staged<false, true>(s0, s2, km, z);    // W^{-1} H'
+    WP.v = mfma_k<1, false, false>(s0, s1, z);   // W^{-1} P
+    WH.v = mfma_k<1, false, true>(s0, s2, z);    // W^{-1} H'
     wsync();
     sput(s3, WP);
     sput(s0, WH);
     wsync();
     Tile t;
-    t.v = mfma_staged<false, false>(s2, s3, km, z);    // H W^{-1} P
+    t.v = mfma_k<1, false, false>(s2, s3, z);    // H W^{-1} P
     Ah.v = AA.v - t.v;
-    Ch.v = mfma_staged<false, false>(s2, s0, km, Ch.v); // C^ + H W^{-1} H'
-    t.v = mfma_staged<true, false>(s1, s3, km, z);      // P' W^{-1} P
+    Ch.v = mfma_k<1, false, false>(s2, s0, Ch.v); // C^ + H W^{-1} H'
+    t.v = mfma_k<1, true, false>(s1, s3, z);      // P' W^{-1} P
     Jh.v = Jn.v - t.v;
     wsync();
     return ok;
@@ -172,7 +164,7 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
     }
     StageElem e;
     const bool ok = build_stage_elem(P, d, k, e, lds, lds + SLOT);
-    const Tile C = mm<false, true>(e.G, e.G, d.m, lds, lds + SLOT);
+    const Tile C = mmk<1, false, true>(e.G, e.G, lds, lds + SLOT);
     gstore(out, e.Ab);
     gstore(out + TILE, C);
     gstore(out + 2 * TILE, e.J);
@@ -185,6 +177,7 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
 // element after the last segment of each instance.
 // Scan buffer entry = 3 tiles (A~, C~, J~).
 // ---------------------------------------------------------------------------
+template <int NK>
 __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ elems, double *__restrict__ X,
@@ -200,6 +193,16 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     const int n1 = d.n + 1, m = d.m;
     Tile Ah = tident(n1), Ch = tzero(), Jh = tzero();
     int code = 0, fk = 0;
+    (void)n1;
+    if (s == d.nseg - 1) {  // terminal element after the last segment
+        double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
+        gstore(t, corner(d.n));
+        gstore(t + TILE, tzero());
+        gstore(t + 2 * TILE, load_terminal_J(P, d, s0));
+    }
+    // The element of segment 0 is never read: the Bellman steps of segment s
+    // start from the scanned element s + 1.
+    if (s == 0) return;
     for (int k = k1 - 1; k >= k0; --k) {
         StageElem e;
         if (elems) {
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             code = ERR_NOT_PD;
             fk = k;
         }
-        if (!fold_left(e, Ah, Ch, Jh, n1, m, s0, s1, s2, s3) && !code) {
+        if (!fold_left<NK>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
             code = ERR_SINGULAR;
             fk = k;
         }
@@ -220,25 +223,7 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     gstore(o, Ah);
     gstore(o + TILE, Ch);
     gstore(o + 2 * TILE, Jh);
-    if (s == d.nseg - 1) {
-        double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
-        gstore(t, corner(d.n));
-        gstore(t + TILE, tzero());
-        gstore(t + 2 * TILE, load_terminal_J(P, d, s0));
-    }
     if (code) report(status, i, code, fk);
-}
-
-// Terminal element only (sequential mode: one segment, no fold).
-__global__ __launch_bounds__(64) void k_value_terminal(ProbPtrs P, const InstDesc *__restrict__ inst,
-                                                       double *__restrict__ X)
-{
-    __shared__ double lds[SLOT];
-    const InstDesc d = inst[blockIdx.x];
-    double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
-    gstore(t, corner(d.n));
-    gstore(t + TILE, tzero());
-    gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
 }
 
 // ---------------------------------------------------------------------------
@@ -247,6 +232,7 @@ __global__ __launch_bounds__(64) void k_value_terminal(ProbPtrs P, const InstDes
 // index nseg); it is terminal-type (A~ = corner, C~ = 0, only J~ meaningful)
 // once it covers nseg.  Terminal-type entries are only ever right operands.
 // ---------------------------------------------------------------------------
+template <int NK>
 __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ inst,
                                                  const int32_t *__restrict__ x_start, int batch, int dd,
                                                  const double *__restrict__ Xin, double *__restrict__ Xout,
@@ -261,13 +247,14 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const int nseg = d.nseg;
     const double *a = Xin + (int64_t)gx * 3 * TILE;
     double *o = Xout + (int64_t)gx * 3 * TILE;
+    if (s == 0) return;   // never read (see k_value_fold)
     if (s + dd > nseg) {  // already final (terminal-type): carry J~ over
         gstore(o + 2 * TILE, gload(a + 2 * TILE));
         return;
     }
     const double *b = Xin + (int64_t)(gx + dd) * 3 * TILE;
     const bool b_term = (s + 2 * dd - 1 >= nseg);
-    const int n1 = d.n + 1, ks = kslices(n1);
+    const int n1 = d.n + 1;
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
     const Tile J2 = gload(b + 2 * TILE);
@@ -276,24 +263,24 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     sput(s1, J2);
     wsync();
     Tile Xt;
-    Xt.v = mfma_staged<false, false>(s0, s1, ks, tident(n1).v);
+    Xt.v = mfma_k<NK, false, false>(s0, s1, tident(n1).v);
     const bool ok = gj_inverse(Xt, n1, s2);
     wsync();
     sput(s3, Xt);  // X^{-1}
     wsync();
     Tile T3;
-    T3.v = mfma_staged<false, false>(s1, s3, ks, z);   // J~2 X^{-1} = (X^{-T} J~2)'
+    T3.v = mfma_k<NK, false, false>(s1, s3, z);   // J~2 X^{-1} = (X^{-T} J~2)'
     wsync();
     sput(s0, T3);
     sput(s2, A1);
     wsync();
     Tile T4;
-    T4.v = mfma_staged<true, false>(s0, s2, ks, z);    // X^{-T} J~2 A~1
+    T4.v = mfma_k<NK, true, false>(s0, s2, z);    // X^{-T} J~2 A~1
     wsync();
     sput(s1, T4);
     wsync();
     Tile Jn;
-    Jn.v = mfma_staged<true, false>(s2, s1, ks, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
+    Jn.v = mfma_k<NK, true, false>(s2, s1, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
     Jn = tsym(Jn, s0);
     gstore(o + 2 * TILE, Jn);
     if (!b_term) {
@@ -302,22 +289,22 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
         sput(s0, A2);
         wsync();
         Tile T1;
-        T1.v = mfma_staged<false, false>(s0, s3, ks, z);   // A~2 X^{-1}
+        T1.v = mfma_k<NK, false, false>(s0, s3, z);   // A~2 X^{-1}
         wsync();
         sput(s1, T1);
         wsync();
         Tile An;
-        An.v = mfma_staged<false, false>(s1, s2, ks, z);   // A~2 X^{-1} A~1
+        An.v = mfma_k<NK, false, false>(s1, s2, z);   // A~2 X^{-1} A~1
         wsync();
         sput(s3, C1);
         wsync();
         Tile T2;
-        T2.v = mfma_staged<false, false>(s1, s3, ks, z);   // A~2 X^{-1} C~1
+        T2.v = mfma_k<NK, false, false>(s1, s3, z);   // A~2 X^{-1} C~1
         wsync();
         sput(s2, T2);
         wsync();
         Tile Cn;
-        Cn.v = mfma_staged<false, true>(s2, s0, ks, C2.v); // ... A~2' + C~2
+        Cn.v = mfma_k<NK, false, true>(s2, s0, C2.v); // ... A~2' + C~2
         Cn = tsym(Cn, s1);
         gstore(o, An);
         gstore(o + TILE, Cn);
@@ -332,6 +319,7 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
 //   Gamma~ = -Q_uu^{-1} Q_ux~ = [Gamma, gamma];
 //   S~ = sym(Q~ + A~'S~'A~ + Q_ux~' Gamma~).
 // ---------------------------------------------------------------------------
+template <int NK>
 __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Xfin, ValPtrs V,
@@ -344,7 +332,7 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    const int n = d.n, m = d.m, n1 = n + 1, ks = kslices(n1), km = kslices(m);
+    const int n = d.n, m = d.m;
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
     Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
@@ -365,16 +353,16 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         sput(s2, Ah);
         wsync();
         Tile SB, SA;
-        SB.v = mfma_staged<false, false>(s0, s1, ks, z);
-        SA.v = mfma_staged<false, false>(s0, s2, ks, z);
+        SB.v = mfma_k<NK, false, false>(s0, s1, z);
+        SA.v = mfma_k<NK, false, false>(s0, s2, z);
         wsync();
         sput(s3, SB);
         sput(s0, SA);
         wsync();
         Tile Quu, Qux, Sn;
-        Quu.v = mfma_staged<true, false>(s1, s3, ks, Rk.v);
-        Qux.v = mfma_staged<true, false>(s1, s0, ks, MhT.v);
-        Sn.v = mfma_staged<true, false>(s2, s0, ks, Qh.v);
+        Quu.v = mfma_k<NK, true, false>(s1, s3, Rk.v);
+        Qux.v = mfma_k<NK, true, false>(s1, s0, MhT.v);
+        Sn.v = mfma_k<NK, true, false>(s2, s0, Qh.v);
         Tile Qi;
         if (!spd_inverse(Quu, m, Qi, s3) && !code) {
             code = ERR_NOT_PD;
@@ -385,11 +373,11 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         sput(s1, Qux);
         wsync();
         Tile Gh;
-        Gh.v = -mfma_staged<false, false>(s3, s1, km, z);
+        Gh.v = -mfma_k<1, false, false>(s3, s1, z);
         wsync();
         sput(s3, Gh);
         wsync();
-        Sn.v = mfma_staged<true, false>(s1, s3, km, Sn.v);
+        Sn.v = mfma_k<1, true, false>(s1, s3, Sn.v);
         St = tsym(Sn, s0);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
@@ -402,6 +390,42 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         fk = k0;
     }
     if (code) report(status, i, code, fk);
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers (the contraction slice count NK = ceil((n_max + 1) / 4) is a
+// template parameter so that every product is fully unrolled).
+// ---------------------------------------------------------------------------
+#define LQK_NK_SWITCH(nk, CALL) \
+    switch (nk) {               \
+    case 1: CALL(1); break;     \
+    case 2: CALL(2); break;     \
+    case 3: CALL(3); break;     \
+    default: CALL(4); break;    \
+    }
+
+void launch_value_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                       const int32_t *seg_start, int batch, const double *elems, double *X, int32_t *status)
+{
+#define CALL(K) hipLaunchKernelGGL(k_value_fold<K>, dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, elems, X, status)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+
+void launch_value_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+                     int batch, int dd, const double *Xin, double *Xout, int32_t *status)
+{
+#define CALL(K) hipLaunchKernelGGL(k_value_ks<K>, dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, Xin, Xout, status)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
+}
+
+void launch_value_riccati(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                          const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, int32_t *status)
+{
+#define CALL(K) hipLaunchKernelGGL(k_value_riccati<K>, dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, status)
+    LQK_NK_SWITCH(nk, CALL)
+#undef CALL
 }
 
 // Diagnostic: D = op(X) op(Y) (+ Z) for row-major 16 x 16 inputs.

@@ -49,6 +49,9 @@ _lib.lq_version.restype = ctypes.c_char_p
 _lib.lq_plan_create.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, ctypes.c_int32,
                                 ctypes.c_int32, ctypes.POINTER(_plan_p)]
 _lib.lq_plan_create.restype = ctypes.c_int
+_lib.lq_plan_create_seg.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p,
+                                    ctypes.POINTER(_plan_p)]
+_lib.lq_plan_create_seg.restype = ctypes.c_int
 _lib.lq_plan_destroy.argtypes = [_plan_p]
 _lib.lq_plan_destroy.restype = None
 for _f, _rt in (("lq_plan_workspace_bytes", ctypes.c_size_t), ("lq_plan_elements_bytes", ctypes.c_size_t),
@@ -71,12 +74,12 @@ _lib.lq_plan_phase_times.restype = ctypes.c_int
 _lib.lq_selftest_tile_mm.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]
 _lib.lq_selftest_tile_mm.restype = ctypes.c_int
 
-EXPORTED = ("lq_plan_create", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
+EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout",
             "lq_adjoint", "lq_selftest_tile_mm", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
-          "adj_back", "adj_fwd")
+          "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply")
 
 
 class LQError(RuntimeError):
@@ -127,18 +130,24 @@ def lq_version() -> str:
 class Plan:
     """Owns an lq_plan* (sizes, segment decomposition, device descriptor tables)."""
 
-    def __init__(self, nx, nu, T, *, precision: str = "fp64", mode: str = "scan", seg_len: int = 0):
+    def __init__(self, nx, nu, T, *, precision: str = "fp64", mode: str = "scan", seg_len: int = 0,
+                 seg_lens=None):
         nx, nu, T = (list(map(int, v)) if hasattr(v, "__len__") else [int(v)] for v in (nx, nu, T))
         self.batch = len(T)
         self.nx, self.nu, self.T = nx, nu, T
         self.precision, self.mode = precision, mode
         arr = ctypes.c_int32 * self.batch
+        prec = {"fp64": LQ_FP64, "mixed": LQ_MIXED}[precision]
         h = _plan_p()
-        code = _lib.lq_plan_create(self.batch, arr(*nx), arr(*nu), arr(*T),
-                                   {"fp64": LQ_FP64, "mixed": LQ_MIXED}[precision],
-                                   {"scan": LQ_SCAN, "sequential": LQ_SEQUENTIAL}[mode], int(seg_len),
-                                   ctypes.byref(h))
-        _check("lq_plan_create", code)
+        if seg_lens is not None:
+            code = _lib.lq_plan_create_seg(self.batch, arr(*nx), arr(*nu), arr(*T), prec,
+                                           arr(*[int(v) for v in seg_lens]), ctypes.byref(h))
+            _check("lq_plan_create_seg", code)
+        else:
+            code = _lib.lq_plan_create(self.batch, arr(*nx), arr(*nu), arr(*T), prec,
+                                       {"scan": LQ_SCAN, "sequential": LQ_SEQUENTIAL}[mode], int(seg_len),
+                                       ctypes.byref(h))
+            _check("lq_plan_create", code)
         self._h = h
 
     @property
@@ -280,3 +289,148 @@ def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, workspa
     out["status"] = status
     out["elements"] = el
     return out
+
+
+def grad_buffers(plan: Plan, which, device="cuda") -> dict:
+    """Gradient output buffers (same packing as the problem) for the named fields."""
+    n = torch.tensor(plan.nx, dtype=torch.int64)
+    m = torch.tensor(plan.nu, dtype=torch.int64)
+    T = torch.tensor(plan.T, dtype=torch.int64)
+    size = {"A": (T * n * n).sum(), "B": (T * n * m).sum(), "c": (T * n).sum(), "Q": (T * n * n).sum(),
+            "R": (T * m * m).sum(), "M": (T * n * m).sum(), "q": (T * n).sum(), "r": (T * m).sum(),
+            "QT": (n * n).sum(), "qT": n.sum(), "x0": n.sum()}
+    return {f: torch.empty(int(size[f]), dtype=torch.float64, device=device) for f in which}
+
+
+class LQSolveFunction(torch.autograd.Function):
+    """(x, u) = LQ solution of the packed problem; gradients by lq_adjoint.
+
+    Inputs are flat packed float64 device tensors (lq_problem layout); c, M, q,
+    r, qT may be None.  The forward pass is lq_scan_solve + lq_rollout, the
+    backward pass one lq_adjoint call; both run in the HIP library.
+    """
+
+    @staticmethod
+    def forward(ctx, plan, A, B, c, Q, R, QT, x0, M, q, r, qT):
+        prob = {"A": A, "B": B, "c": c, "Q": Q, "R": R, "QT": QT, "x0": x0, "M": M, "q": q, "r": r, "qT": qT}
+        dev = A.device
+        ws = plan.new_workspace(dev)
+        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
+        val = value_buffers(plan, dev)
+        st = state_buffers(plan, dev)
+        lq_scan_solve(plan, prob, None, val, ws, status)
+        lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+        ctx.plan, ctx.prob, ctx.val, ctx.st, ctx.ws, ctx.status = plan, prob, val, st, ws, status
+        ctx.mark_non_differentiable(status)
+        return st["x"], st["u"], status
+
+    @staticmethod
+    def backward(ctx, gx, gu, _gstatus):
+        plan, prob = ctx.plan, ctx.prob
+        names = ("A", "B", "c", "Q", "R", "QT", "x0", "M", "q", "r", "qT")
+        want = [f for i, f in enumerate(names) if ctx.needs_input_grad[i + 1]]
+        dev = prob["A"].device
+        gx = torch.zeros_like(ctx.st["x"]) if gx is None else gx.contiguous()
+        gu = torch.zeros_like(ctx.st["u"]) if gu is None else gu.contiguous()
+        g = grad_buffers(plan, want, dev)
+        lq_adjoint(plan, prob, ctx.val, ctx.st["x"], ctx.st["u"], ctx.st["lam"], gx, gu, g, ctx.ws, ctx.status)
+        return (None,) + tuple(g.get(f) for f in names)
+
+
+def lq_solve(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None):
+    """Differentiable LQ solve on packed device tensors; returns (x, u, status)."""
+    return LQSolveFunction.apply(plan, A, B, c, Q, R, QT, x0, M, q, r, qT)
+
+
+# ---------------------------------------------------------------------------
+# Newton / interior point (newton_step)
+# ---------------------------------------------------------------------------
+
+NMPC_MU, NMPC_ALPHA, NMPC_NU, NMPC_COST, NMPC_PRED, NMPC_RHO, NMPC_ACCEPTED, NMPC_COST_NEW, NMPC_NSCAL = range(9)
+
+
+class NMPCProblemC(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("T", ctypes.c_int32), ("h", ctypes.c_double),
+                ("W", _P), ("Bm", _P), ("Q", _P), ("R", _P), ("QT", _P), ("xref", _P), ("x0", _P),
+                ("umin", ctypes.c_double), ("umax", ctypes.c_double)]
+
+
+class NMPCStateC(ctypes.Structure):
+    _fields_ = [("x", _P), ("u", _P), ("scal", _P)]
+
+
+_lib.nmpc_workspace_bytes.argtypes = [_plan_p]
+_lib.nmpc_workspace_bytes.restype = ctypes.c_size_t
+_lib.nmpc_init.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), _P, _P]
+_lib.nmpc_init.restype = ctypes.c_int
+_lib.newton_step.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), _P, _P, _P]
+_lib.newton_step.restype = ctypes.c_int
+EXPORTED = EXPORTED + ("nmpc_workspace_bytes", "nmpc_init", "newton_step")
+
+
+def nmpc_workspace_bytes(plan: Plan) -> int:
+    return int(_lib.nmpc_workspace_bytes(plan.handle))
+
+
+def nmpc_init(plan, prob_c, state_c, workspace, stream=None):
+    _check("nmpc_init", _lib.nmpc_init(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c), _ptr(workspace),
+                                       _stream(stream)))
+
+
+def newton_step(plan, prob_c, state_c, workspace, status=None, stream=None):
+    _check("newton_step", _lib.newton_step(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c),
+                                           _ptr(workspace), _ptr(status), _stream(stream)))
+
+
+class NewtonMPC:
+    """Interior-point Newton solver for x' = x + h (tanh(W x) + B u), |u| bounded.
+
+    `p` has numpy fields nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, u0, umin, umax.
+    All iterations run on the GPU through newton_step; the host only sets the
+    barrier weight between levels and reads the traces at the end.
+    """
+
+    def __init__(self, p, device="cuda", seg_len=0):
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+        self.p = p
+        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len)
+        self.dev = {k: t(getattr(p, k)) for k in ("W", "Bm", "Q", "R", "QT", "xref", "x0")}
+        self.x = torch.zeros((p.T + 1) * p.nx, dtype=torch.float64, device=device)
+        self.u = t(p.u0).reshape(-1).clone()
+        self.scal = torch.zeros(NMPC_NSCAL, dtype=torch.float64, device=device)
+        self.ws = torch.empty(nmpc_workspace_bytes(self.plan), dtype=torch.uint8, device=device)
+        d = self.dev
+        self.prob_c = NMPCProblemC(p.nx, p.nu, p.T, float(p.h), _f64(d["W"]), _f64(d["Bm"]), _f64(d["Q"]),
+                                   _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(d["x0"]),
+                                   float(p.umin), float(p.umax))
+        self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
+
+    def init(self, alpha0, nu0):
+        self.scal.zero_()
+        self.scal[NMPC_ALPHA] = alpha0
+        self.scal[NMPC_NU] = nu0
+        nmpc_init(self.plan, self.prob_c, self.state_c, self.ws)
+
+    def step(self, mu):
+        self.scal[NMPC_MU] = mu
+        newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+
+    def run(self, mu_levels, iters, alpha0, nu0):
+        self.init(alpha0, nu0)
+        n_it = len(mu_levels) * iters
+        before = torch.zeros(n_it, NMPC_NSCAL, dtype=torch.float64, device=self.x.device)
+        after = torch.zeros_like(before)
+        it = 0
+        for mu in mu_levels:
+            for _ in range(iters):
+                self.scal[NMPC_MU] = mu
+                before[it].copy_(self.scal)
+                newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+                after[it].copy_(self.scal)
+                it += 1
+        torch.cuda.synchronize()
+        a = after.cpu().numpy()
+        return {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
+                "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
+                "cost": a[:, NMPC_COST], "accept": a[:, NMPC_ACCEPTED] > 0.5,
+                "alpha": before.cpu().numpy()[:, NMPC_ALPHA], "pred": a[:, NMPC_PRED], "rho": a[:, NMPC_RHO]}

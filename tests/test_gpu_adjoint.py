@@ -1,0 +1,140 @@
+"""GPU parity of the adjoint (lq_adjoint and the autograd wrapper) against the
+oracle's KKT adjoint and against central finite differences.
+
+Loss: L = sum_k ||x_k||^2 + sum_k ||u_k||^2 (gx = 2x, gu = 2u).
+Tolerance: 1e-10 normwise relative per gradient array (FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_20027_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0")
+SHAPES = {"A": lambda i: (i.T, i.n, i.n), "B": lambda i: (i.T, i.n, i.m), "c": lambda i: (i.T, i.n),
+          "Q": lambda i: (i.T, i.n, i.n), "R": lambda i: (i.T, i.m, i.m), "M": lambda i: (i.T, i.n, i.m),
+          "q": lambda i: (i.T, i.n), "r": lambda i: (i.T, i.m), "QT": lambda i: (i.n, i.n),
+          "qT": lambda i: (i.n,), "x0": lambda i: (i.n,)}
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_20027_amd import lqscan
+    return lqscan
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+def split(flat, shapes):
+    out, o = [], 0
+    for shp in shapes:
+        k = int(np.prod(shp))
+        out.append(flat[o:o + k].reshape(shp))
+        o += k
+    return out
+
+
+def gpu_grads(lq, insts, **plan_kw):
+    packed = W.pack(insts)
+    prob = lq.to_device(packed)
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], **plan_kw)
+    out = lq.solve(plan, prob)
+    gx, gu = 2 * out["x"], 2 * out["u"]
+    want = [f for f in FIELDS if prob.get(f) is not None or f in ("M", "q", "r", "qT", "c")]
+    g = lq.grad_buffers(plan, want)
+    ws = plan.new_workspace()
+    lq.lq_adjoint(plan, prob, {k: out[k] for k in ("S", "s", "Gamma", "gamma")}, out["x"], out["u"], out["lam"],
+                  gx, gu, g, ws, out["status"])
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    per = [dict() for _ in insts]
+    for f, t in g.items():
+        for j, a in enumerate(split(t.cpu().numpy(), [SHAPES[f](i) for i in insts])):
+            per[j][f] = a
+    return per
+
+
+def oracle_grads(inst):
+    o = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                        M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+    return oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, 2 * o["x"], 2 * o["u"],
+                             M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+
+
+def check(per, insts, tol=1e-10):
+    worst = 0.0
+    for got, inst in zip(per, insts):
+        ref = oracle_grads(inst)
+        for f, a in got.items():
+            e = rel(a, ref[f])
+            worst = max(worst, e)
+            assert e <= tol, f"grad {f}: rel err {e:.3e} (n={inst.n}, m={inst.m}, T={inst.T})"
+    return worst
+
+
+@pytest.mark.parametrize("seg_len", [0, 1, 4, 7])
+def test_adjoint_general_lq(lq, seg_len):
+    inst = W.lq_instance_general(np.random.default_rng(31), 3, 2, 29)
+    check(gpu_grads(lq, [inst], seg_len=seg_len), [inst])
+
+
+def test_adjoint_sequential_mode(lq):
+    inst = W.lq_instance_general(np.random.default_rng(32), 4, 1, 40)
+    check(gpu_grads(lq, [inst], mode="sequential"), [inst])
+
+
+def test_adjoint_ragged_batch(lq):
+    rng = np.random.default_rng(33)
+    insts = [W.lq_instance(rng, n, m, T) for n, m, T in [(2, 1, 5), (12, 4, 70), (4, 1, 1), (7, 3, 33)]]
+    insts.append(W.lq_instance_general(rng, 5, 2, 21))
+    check(gpu_grads(lq, insts), insts)
+
+
+def test_adjoint_long_horizon_batch_sample(lq):
+    """Sample of the differentiated-solve workload: n=12, m=4, T=4096, a few instances."""
+    insts = W.cfg4_batch(batch=3, T=4096)
+    check(gpu_grads(lq, insts), insts)
+
+
+def test_autograd_function_matches_oracle_and_fd(lq):
+    inst = W.lq_instance_general(np.random.default_rng(34), 3, 2, 17)
+    packed = W.pack([inst])
+    prob = lq.to_device(packed)
+    plan = lq.Plan([inst.n], [inst.m], [inst.T], seg_len=4)
+    names = ("A", "B", "c", "Q", "R", "QT", "x0", "M", "q", "r", "qT")
+    leaves = {f: prob[f].clone().requires_grad_(True) for f in names}
+
+    def loss_of(t):
+        x, u, _ = lq.lq_solve(plan, *[t[f] for f in names])
+        return (x * x).sum() + (u * u).sum()
+
+    L = loss_of(leaves)
+    grads = torch.autograd.grad(L, [leaves[f] for f in names])
+    ref = oracle_grads(inst)
+    for f, g in zip(names, grads):
+        assert rel(g.detach().cpu().numpy().reshape(ref[f].shape), ref[f]) < 1e-10, f
+    # central finite differences of the GPU forward along random directions
+    rng = np.random.default_rng(35)
+    with torch.no_grad():
+        for _ in range(16):
+            d = {f: torch.tensor(rng.standard_normal(prob[f].shape), dtype=torch.float64, device="cuda")
+                 for f in names}
+            for f in ("Q", "R", "QT"):   # symmetric perturbations of symmetric inputs
+                shp = SHAPES[f](inst)
+                v = d[f].reshape(shp)
+                d[f] = (0.5 * (v + v.transpose(-1, -2))).reshape(-1).contiguous()
+            nrm = torch.sqrt(sum((v * v).sum() for v in d.values()))
+            h = 1e-6
+            plus = loss_of({f: prob[f] + h * d[f] / nrm for f in names})
+            minus = loss_of({f: prob[f] - h * d[f] / nrm for f in names})
+            fd = float((plus - minus) / (2 * h))
+            an = float(sum((g * d[f] / nrm).sum() for f, g in zip(names, grads)))
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (fd, an)

@@ -216,3 +216,21 @@ def test_cfg2_full_horizon(lq):
     assert int(np.abs(status).sum()) == 0
     worst = check(per, [inst])
     print(f"cfg2 worst rel err {worst:.3e}, seg_len {plan.seg_len()}")
+
+
+def test_per_instance_segment_lengths(lq):
+    """One plan mixing the scan (various segment lengths) and the sequential recursion (L = T)."""
+    rng = np.random.default_rng(12)
+    insts = [W.lq_instance(rng, n, m, T) for n, m, T in [(12, 4, 300), (4, 1, 77), (2, 1, 50), (12, 4, 64)]]
+    seg = [7, 77, 1, 0]   # scan L=7, sequential, L=1, automatic
+    packed = W.pack(insts)
+    prob = lq.to_device(packed)
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], seg_lens=seg)
+    out = lq.solve(plan, prob)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    x = split(out["x"].cpu().numpy(), [(i.T + 1, i.n) for i in insts])
+    S = split(out["S"].cpu().numpy(), [(i.T + 1, i.n, i.n) for i in insts])
+    for inst, xi, Si in zip(insts, x, S):
+        ref = oracle_ref(inst)
+        assert rel(xi, ref["x"]) < TOL and rel(Si, ref["S"]) < TOL

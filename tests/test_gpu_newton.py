@@ -1,0 +1,70 @@
+"""GPU parity of the interior-point Newton step (newton_step) with the oracle.
+
+FP64: every accept/reject decision identical to the oracle's, costs and the
+final trajectory within 1e-10 (normwise relative).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_20027_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_20027_amd import lqscan
+    return lqscan
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+@pytest.mark.parametrize("seg_len", [0, 5])
+def test_single_newton_step(lq, seg_len):
+    p = W.nmpc_problem(seed=1, T=96)
+    mu, alpha, nu = 0.1, 0.05, 2.0
+    x0 = oracle.nmpc_rollout(p, p.u0)
+    acc, x1, u1, a1, nu1, cost, pred, rho = oracle.nmpc_newton_step(p, x0, p.u0, mu, alpha, nu)
+    s = lq.NewtonMPC(p, seg_len=seg_len)
+    s.init(alpha, nu)
+    s.step(mu)
+    torch.cuda.synchronize()
+    sc = s.scal.cpu().numpy()
+    assert bool(sc[lq.NMPC_ACCEPTED] > 0.5) == acc
+    assert abs(sc[lq.NMPC_PRED] - pred) <= 1e-10 * abs(pred)
+    assert abs(sc[lq.NMPC_COST] - cost) <= 1e-10 * abs(cost)
+    assert abs(sc[lq.NMPC_ALPHA] - a1) <= 1e-10 * abs(a1) and sc[lq.NMPC_NU] == nu1
+    assert rel(s.u.cpu().numpy().reshape(p.T, p.nu), u1) < 1e-10
+    assert rel(s.x.cpu().numpy().reshape(p.T + 1, p.nx), x1) < 1e-10
+
+
+def test_full_interior_point_run_matches_oracle(lq):
+    """The benchmark-like problem (n=4, m=1, T=1024), 6 barrier levels x 10 steps."""
+    p = W.nmpc_problem(seed=1, T=1024)
+    ref = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    got = lq.NewtonMPC(p).run(W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    assert np.array_equal(got["accept"], ref["accept"]), (got["accept"].astype(int), ref["accept"].astype(int))
+    assert rel(got["alpha"], ref["alpha"]) < 1e-9
+    assert rel(got["cost"], ref["cost"]) < 1e-10
+    assert rel(got["u"], ref["u"]) < 1e-10
+    assert rel(got["x"], ref["x"]) < 1e-10
+    assert np.all(np.abs(got["u"]) < 1.0)
+
+
+def test_benign_instance_converges(lq):
+    import dataclasses
+    p0 = W.nmpc_problem(seed=1, T=200)
+    p = dataclasses.replace(p0, W=-np.eye(4) + 0.3 * p0.W, Bm=np.ones((4, 1)))
+    ref = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    got = lq.NewtonMPC(p, seg_len=8).run(W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
+    # decisions taken on round-off-sized steps near convergence may differ; compare
+    # the decisions of the first 40 iterations and the converged solution
+    assert np.array_equal(got["accept"][:40], ref["accept"][:40])
+    assert rel(got["u"], ref["u"]) < 1e-8
