@@ -265,13 +265,15 @@ lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_
                       int32_t *status, void *stream);
 
 /*
- * Diagnostic: one 16 x 16 FP64 tile product D = X Y (+ Z) through the
- * library's matrix-core tile primitive.  X, Y, Z, D are device pointers to
- * row-major 16 x 16 arrays (Z nullable).  Used by the test suite to pin the
- * operand layouts of the matrix instructions.
+ * Diagnostic: one 16 x 16 tile product D = op(X) op(Y) (+ Z) through the
+ * library's matrix-core tile primitive, with FP64 products (precision
+ * LQ_FP64) or FP32 products added to Z in FP64 (LQ_MIXED).  X, Y, Z, D are
+ * device pointers to row-major 16 x 16 FP64 arrays (Z nullable).  Used by the
+ * test suite to pin the operand and accumulator layouts of the matrix
+ * instructions.
  */
 lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z, double *D,
-                              int32_t transpose_x, int32_t transpose_y, void *stream);
+                              int32_t transpose_x, int32_t transpose_y, int32_t precision, void *stream);
 
 /*
  * Diagnostic phase timing.  Phases of the solve calls, in enqueue order (a

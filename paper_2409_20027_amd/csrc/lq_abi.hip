@@ -237,8 +237,8 @@ lq_status lq_build_elements(const lq_plan *p, const lq_problem *prob, double *el
     if (!elements || !aligned(elements)) return LQ_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     timed(p, LQ_PH_BUILD, st, [&] {
-        hipLaunchKernelGGL(lqk::k_build_elements, dim3((unsigned)p->total_elem), dim3(64), 0, st, probptrs(prob),
-                           p->d_inst, p->d_elem_start, p->batch, elements, status);
+        lqk::launch_build_elements(p->prec, (unsigned)p->total_elem, st, probptrs(prob), p->d_inst, p->d_elem_start,
+                                   p->batch, elements, status);
     });
     return launched();
 }
@@ -255,21 +255,21 @@ lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
     timed(p, LQ_PH_VALUE_FOLD, st, [&] {
-        lqk::launch_value_fold(p->nk, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
+        lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
                                Xa, status);
     });
     double *in = Xa, *o = Xb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_value_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,
+                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,
                                      status);
                 std::swap(in, o);
             }
         });
     double *fin = in;
     timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
-        lqk::launch_value_riccati(p->nk, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
+        lqk::launch_value_riccati(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
                                   V, status);
     });
     return launched();
@@ -288,20 +288,20 @@ lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *v
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
     timed(p, LQ_PH_ROLL_FOLD, st, [&] {
-        lqk::launch_roll_fold(p->nk, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
+        lqk::launch_roll_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
     });
     double *in = Ya, *o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ROLL_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_affine_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
+                lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
                                       o);
                 std::swap(in, o);
             }
         });
     double *fin = in;
     timed(p, LQ_PH_ROLL_APPLY, st, [&] {
-        lqk::launch_roll_apply(p->nk, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
+        lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
                                u, lambda);
     });
     return launched();
@@ -325,36 +325,36 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
     const unsigned nseg = (unsigned)p->total_seg, nx = (unsigned)p->total_x;
     // backward linear-term scan
     timed(p, LQ_PH_ADJ_BACK_FOLD, st, [&] {
-        lqk::launch_adj_back_fold(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
+        lqk::launch_adj_back_fold(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
     });
     double *in = Ya, *o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_affine_ks(p->nk, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
+                lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
                 std::swap(in, o);
             }
         });
     double *fin = in;
     timed(p, LQ_PH_ADJ_BACK_APPLY, st, [&] {
-        lqk::launch_adj_back_apply(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, status);
+        lqk::launch_adj_back_apply(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, status);
     });
     // forward derivative scan + gradients
     timed(p, LQ_PH_ADJ_FWD_FOLD, st, [&] {
-        lqk::launch_adj_fwd_fold(p->nk, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
+        lqk::launch_adj_fwd_fold(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
     });
     in = Ya;
     o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_affine_ks(p->nk, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in, o);
+                lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in, o);
                 std::swap(in, o);
             }
         });
     double *ffin = in;
     timed(p, LQ_PH_ADJ_FWD_APPLY, st, [&] {
-        lqk::launch_adj_fwd_apply(p->nk, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
+        lqk::launch_adj_fwd_apply(p->nk, p->prec, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
     });
     return launched();
 }
@@ -449,15 +449,15 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     lqk::launch_nmpc_clear(st, Wk.status, Wk.zero, prob->nx);
     // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
-    lqk::launch_nmpc_linearise(st, N, Wk, state->x);
-    lqk::launch_costate_fold(p->nk, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
+    lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x);
+    lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
     double *in = Ya, *o = Yb;
     for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-        lqk::launch_affine_ks(p->nk, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
+        lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
         std::swap(in, o);
     }
-    lqk::launch_costate_apply(p->nk, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
-    lqk::launch_nmpc_quadraticise(st, N, Wk, state->u, state->scal);
+    lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
+    lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->u, state->scal);
     // the LQ step
     lq_problem lp{};
     lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt; lp.M = nullptr;
@@ -512,10 +512,10 @@ lq_status lq_plan_phase_times(lq_plan *p, double *ms, int64_t *count)
 }
 
 lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z, double *D, int32_t tx,
-                              int32_t ty, void *stream)
+                              int32_t ty, int32_t precision, void *stream)
 {
-    if (!X || !Y || !D) return LQ_ERR_ARG;
-    hipLaunchKernelGGL(lqk::k_selftest_mm, dim3(1), dim3(64), 0, (hipStream_t)stream, X, Y, Z, D, tx, ty);
+    if (!X || !Y || !D || (precision != LQ_FP64 && precision != LQ_MIXED)) return LQ_ERR_ARG;
+    lqk::launch_selftest_mm(precision, (hipStream_t)stream, X, Y, Z, D, tx, ty);
     return launched();
 }
 

@@ -32,15 +32,15 @@ LQK_DEV Tile load_A_noc(const ProbPtrs &P, const InstDesc &d, int k)
 }
 
 // Backward map Y~_k = [[F_k', h_k], [0, 1]].
-template <int NK>
+template <int NK, int PR>
 LQK_DEV Tile back_map(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k, double *s0, double *s1)
 {
     const int n = d.n, m = d.m;
     const Tile Gh = load_Gh(J.G, J.g, d, k);
-    const Tile F = mmak<1, false, false>(load_Bh(P, d, k), Gh, load_A_noc(P, d, k), s0, s1);
+    const Tile F = mmak<1, PR, false, false>(load_Bh(P, d, k), Gh, load_A_noc(P, d, k), s0, s1);
     Tile Ft = ttrans(F, s0);
     const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
-    const Tile H = mmk<1, true, false>(Gh, GU, s0, s1);  // column n: Gamma' gu (rows < n)
+    const Tile H = mmk<1, PR, true, false>(Gh, GU, s0, s1);  // column n: Gamma' gu (rows < n)
     const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
     const int c = tcol();
 #pragma unroll
@@ -56,7 +56,7 @@ LQK_DEV Tile back_map(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, in
 
 // Segment fold of the backward maps: Psi_s = Y~_{k0} ... Y~_{k1-1}; the block
 // of the last segment also writes the terminal vector map [[0, gx_T], [0, 1]].
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       double *__restrict__ Y)
@@ -72,12 +72,12 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
         gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * d.n, d.n, d.n, d.n));
     if (s == 0) return;   // never read: segment s starts from entry s + 1
     Tile Psi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Psi = mmk<NK, false, false>(Psi, back_map<NK>(P, J, d, k, s0, s1), s0, s1);
+    for (int k = k0; k < k1; ++k) Psi = mmk<NK, PR, false, false>(Psi, back_map<NK, PR>(P, J, d, k, s0, s1), s0, s1);
     gstore(Y + (int64_t)(d.xbase + s) * TILE, Psi);
 }
 
 // Inside each segment, from s~ at its right end: s~_k and gamma~_k.
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                        const int32_t *__restrict__ seg_start, int batch,
                                                        const double *__restrict__ Yfin, int32_t *status)
@@ -95,30 +95,31 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     int code = 0, fk = 0;
     for (int k = k1 - 1; k >= k0; --k) {
         const Tile Bh = load_Bh(P, d, k);
-        const Tile SB = mmk<NK, false, false>(load_Sh(J.S, J.s, d, k + 1), Bh, s0, s1);
-        const Tile Quu = mmak<NK, true, false>(Bh, SB, load_R(P, d, k), s0, s1);
+        const Tile SB = mmk<NK, PR, false, false>(load_Sh(J.S, J.s, d, k + 1), Bh, s0, s1);
+        const Tile Quu = mmak<NK, PR, true, false>(Bh, SB, load_R(P, d, k), s0, s1);
         Tile Qi;
         if (!spd_inverse(Quu, m, Qi, s2) && !code) {
             code = ADJ_ERR_NOT_PD;
             fk = k;
         }
-        const Tile BS = mmak<NK, true, false>(Bh, SV, load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1), s0, s1);
-        Tile Gt = mmk<1, false, false>(Qi, BS, s0, s1);
+        const Tile BS = mmak<NK, PR, true, false>(Bh, SV, load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1), s0, s1);
+        Tile Gt = mmk<1, PR, false, false>(Qi, BS, s0, s1);
         Gt.v = -Gt.v;
         store_vec(J.gt + d.og + (int64_t)k * m, Gt, m, n);
-        SV = mmk<NK, false, false>(back_map<NK>(P, J, d, k, s0, s1), SV, s0, s1);
+        SV = mmk<NK, PR, false, false>(back_map<NK, PR>(P, J, d, k, s0, s1), SV, s0, s1);
         store_vec(J.st + d.os + (int64_t)k * n, SV, n, n);
     }
     if (code) report(status, i, code, fk);
 }
 
 // Closed-loop map of the derivative: [[A + B Gamma, B gamma~], [0, 1]].
+template <int PR>
 LQK_DEV Tile fwd_map(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k, double *s0, double *s1)
 {
-    return mmak<1, false, false>(load_Bh(P, d, k), load_Gh(J.G, J.gt, d, k), load_A_noc(P, d, k), s0, s1);
+    return mmak<1, PR, false, false>(load_Bh(P, d, k), load_Gh(J.G, J.gt, d, k), load_A_noc(P, d, k), s0, s1);
 }
 
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_fwd_fold(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                      const int32_t *__restrict__ seg_start, int batch,
                                                      double *__restrict__ Y)
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(64) void k_adj_fwd_fold(ProbPtrs P, AdjPtrs J, cons
     if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(nullptr, d.n, d.n, d.n));   // dx_0 = 0
     if (s == d.nseg - 1) return;   // never read: segment s starts from entry s
     Tile Phi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Phi = mmk<NK, false, false>(fwd_map(P, J, d, k, s0, s1), Phi, s0, s1);
+    for (int k = k0; k < k1; ++k) Phi = mmk<NK, PR, false, false>(fwd_map<PR>(P, J, d, k, s0, s1), Phi, s0, s1);
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
 
@@ -145,7 +146,7 @@ LQK_DEV Tile outer(const d4 &ar, double bc)
     return o;
 }
 
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, GradPtrs Gr,
                                                       const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
@@ -161,15 +162,15 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int n = d.n, m = d.m;
     Tile DX = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, dx_k0], [0, 1]]
     if (s == 0 && Gr.x0) {
-        const Tile DL0 = mmk<NK, false, false>(load_Sh(J.S, J.st, d, 0), DX, s0, s1);
+        const Tile DL0 = mmk<NK, PR, false, false>(load_Sh(J.S, J.st, d, 0), DX, s0, s1);
         store_vec(Gr.x0 + d.on, DL0, n, n);
     }
     for (int k = k0; k < k1; ++k) {
         const Tile Gh = load_Gh(J.G, J.gt, d, k);
         const Tile Bh = load_Bh(P, d, k);
-        const Tile DU = mmk<NK, false, false>(Gh, DX, s0, s1);
-        const Tile DXn = mmak<1, false, false>(Bh, DU, mmk<NK, false, false>(load_A_noc(P, d, k), DX, s0, s1), s0, s1);
-        const Tile DL1 = mmk<NK, false, false>(load_Sh(J.S, J.st, d, k + 1), DXn, s0, s1);
+        const Tile DU = mmk<NK, PR, false, false>(Gh, DX, s0, s1);
+        const Tile DXn = mmak<1, PR, false, false>(Bh, DU, mmk<NK, PR, false, false>(load_A_noc(P, d, k), DX, s0, s1), s0, s1);
+        const Tile DL1 = mmk<NK, PR, false, false>(load_Sh(J.S, J.st, d, k + 1), DXn, s0, s1);
         const Tile X = load_vec(J.x + d.os + (int64_t)k * n, n, n, -1);
         const Tile U = load_vec(J.u + d.og + (int64_t)k * m, m, n, -1);
         const Tile L1 = load_vec(J.lam + d.os + (int64_t)(k + 1) * n, n, n, -1);
@@ -219,40 +220,33 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     }
 }
 
-#define LQK_NK_SWITCH(nk, CALL) \
-    switch (nk) {               \
-    case 1: CALL(1); break;     \
-    case 2: CALL(2); break;     \
-    case 3: CALL(3); break;     \
-    default: CALL(4); break;    \
-    }
 
-void launch_adj_back_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_back_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                           const int32_t *seg_start, int batch, double *Y)
 {
-#define CALL(K) hipLaunchKernelGGL(k_adj_back_fold<K>, dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Y)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_adj_back_fold<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Y)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_adj_back_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_back_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                            const int32_t *seg_start, int batch, const double *Yfin, int32_t *status)
 {
-#define CALL(K) hipLaunchKernelGGL(k_adj_back_apply<K>, dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Yfin, status)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_adj_back_apply<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Yfin, status)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_adj_fwd_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_fwd_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                          const int32_t *seg_start, int batch, double *Y)
 {
-#define CALL(K) hipLaunchKernelGGL(k_adj_fwd_fold<K>, dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Y)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_adj_fwd_fold<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Y)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_adj_fwd_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
+void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
                           const InstDesc *inst, const int32_t *seg_start, int batch, const double *Yfin)
 {
-#define CALL(K) hipLaunchKernelGGL(k_adj_fwd_apply<K>, dim3(grid), dim3(64), 0, st, P, J, Gr, inst, seg_start, batch, Yfin)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_adj_fwd_apply<K, R>), dim3(grid), dim3(64), 0, st, P, J, Gr, inst, seg_start, batch, Yfin)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 }  // namespace lqk

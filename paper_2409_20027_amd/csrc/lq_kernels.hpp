@@ -6,39 +6,40 @@
 
 namespace lqk {
 
-__global__ void k_build_elements(ProbPtrs P, const InstDesc *inst, const int64_t *elem_start, int batch,
-                                 double *elems, int32_t *status);
-__global__ void k_selftest_mm(const double *X, const double *Y, const double *Z, double *D, int tx, int ty);
+void launch_build_elements(int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                           const int64_t *elem_start, int batch, double *elems, int32_t *status);
+void launch_selftest_mm(int pr, hipStream_t st, const double *X, const double *Y, const double *Z, double *D, int tx,
+                        int ty);
 
-void launch_value_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+void launch_value_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                        const int32_t *seg_start, int batch, const double *elems, double *X, int32_t *status);
-void launch_value_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                      int batch, int dd, const double *Xin, double *Xout, int32_t *status);
-void launch_value_riccati(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                           const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, int32_t *status);
-void launch_roll_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                       const int32_t *seg_start, int batch, double *Y);
-void launch_affine_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
+void launch_affine_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
                       int dd, int suffix, const double *Yin, double *Yout);
-void launch_roll_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+void launch_roll_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                        const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u, double *lam);
 
-void launch_adj_back_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_back_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                           const int32_t *seg_start, int batch, double *Y);
-void launch_adj_back_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_back_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                            const int32_t *seg_start, int batch, const double *Yfin, int32_t *status);
-void launch_adj_fwd_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
+void launch_adj_fwd_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                          const int32_t *seg_start, int batch, double *Y);
-void launch_adj_fwd_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
+void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
                           const InstDesc *inst, const int32_t *seg_start, int batch, const double *Yfin);
 
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u);
 void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n);
-void launch_nmpc_linearise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x);
-void launch_costate_fold(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y);
-void launch_costate_apply(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x);
+void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y);
+void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
                           const double *Yfin);
-void launch_nmpc_quadraticise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal);
+void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal);
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal);
 void launch_nmpc_accept(hipStream_t st, double *scal);
 void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal);

@@ -89,7 +89,9 @@ __global__ void k_nmpc_clear(int32_t *st, double *zero, int n)
     if (threadIdx.x < n) zero[threadIdx.x] = 0.0;
 }
 
-// Step 1 (one lane per stage).
+// Step 1 (one lane per stage).  RT is the arithmetic type of the expansion
+// (float in mixed precision); results are stored in FP64.
+template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -99,28 +101,30 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
     const double *rk = N.xref + (int64_t)k * n;
     if (k == N.T) {   // terminal co-state lambda_T = Q_T (x_T - ref_T)
         for (int i = 0; i < n; ++i) {
-            double v = 0.0;
-            for (int j = 0; j < n; ++j) v += N.QT[i * n + j] * (xk[j] - rk[j]);
-            Wk.lamT[i] = v;
+            RT v = 0;
+            for (int j = 0; j < n; ++j) v += (RT)N.QT[i * n + j] * ((RT)xk[j] - (RT)rk[j]);
+            Wk.lamT[i] = (double)v;
         }
         return;
     }
-    double th[NXMAX];
+    RT th[NXMAX];
+    const RT h = (RT)N.h;
     for (int i = 0; i < n; ++i) {
-        double z = 0.0;
-        for (int j = 0; j < n; ++j) z += N.W[i * n + j] * xk[j];
+        RT z = 0;
+        for (int j = 0; j < n; ++j) z += (RT)N.W[i * n + j] * (RT)xk[j];
         th[i] = tanh(z);
-        Wk.th[(int64_t)k * n + i] = th[i];
+        Wk.th[(int64_t)k * n + i] = (double)th[i];
     }
     double *A = Wk.A + (int64_t)k * n * n;
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) A[i * n + j] = (i == j ? 1.0 : 0.0) + N.h * (1.0 - th[i] * th[i]) * N.W[i * n + j];
+        for (int j = 0; j < n; ++j)
+            A[i * n + j] = (double)((i == j ? (RT)1 : (RT)0) + h * ((RT)1 - th[i] * th[i]) * (RT)N.W[i * n + j]);
     double *B = Wk.B + (int64_t)k * n * m;
-    for (int i = 0; i < n * m; ++i) B[i] = N.h * N.Bm[i];
+    for (int i = 0; i < n * m; ++i) B[i] = (double)(h * (RT)N.Bm[i]);
     for (int i = 0; i < n; ++i) {
-        double v = 0.0;
-        for (int j = 0; j < n; ++j) v += N.Q[i * n + j] * (xk[j] - rk[j]);
-        Wk.g[(int64_t)k * n + i] = v;
+        RT v = 0;
+        for (int j = 0; j < n; ++j) v += (RT)N.Q[i * n + j] * ((RT)xk[j] - (RT)rk[j]);
+        Wk.g[(int64_t)k * n + i] = (double)v;
     }
 }
 
@@ -140,7 +144,7 @@ LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k, double *s
 
 // Step 2a: segment fold of the co-state maps (suffix); the block of the last
 // segment writes the terminal element [[0, lambda_T], [0, 1]].
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst, double *Y)
 {
     __shared__ double lds[2 * SLOT];
@@ -151,12 +155,12 @@ __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc
     if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT, d.n, d.n, d.n));
     if (s == 0) return;
     Tile Psi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Psi = mmk<NK, false, false>(Psi, costate_map(Wk, d, k, s0), s0, s1);
+    for (int k = k0; k < k1; ++k) Psi = mmk<NK, PR, false, false>(Psi, costate_map(Wk, d, k, s0), s0, s1);
     gstore(Y + (int64_t)(d.xbase + s) * TILE, Psi);
 }
 
 // Step 2c: co-states inside each segment from lambda at its right end.
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDesc *__restrict__ inst,
                                                       const double *__restrict__ Yfin)
 {
@@ -169,12 +173,14 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
     Tile L = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);
     if (s == d.nseg - 1) store_vec(Wk.lam + (int64_t)d.T * n, L, n, n);
     for (int k = k1 - 1; k >= k0; --k) {
-        L = mmk<NK, false, false>(costate_map(Wk, d, k, s0), L, s0, s1);
+        L = mmk<NK, PR, false, false>(costate_map(Wk, d, k, s0), L, s0, s1);
         store_vec(Wk.lam + (int64_t)k * n, L, n, n);
     }
 }
 
-// Step 3 (one lane per stage): second-order terms of the Hamiltonian.
+// Step 3 (one lane per stage): second-order terms of the Hamiltonian in RT
+// (the barrier terms and alpha stay FP64: they set the step's feasibility).
+template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *u,
                                                            const double *scal)
 {
@@ -185,13 +191,15 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     const double *th = Wk.th + (int64_t)k * n;
     const double *l1 = Wk.lam + (int64_t)(k + 1) * n;
     double *P = Wk.P + (int64_t)k * n * n;
-    for (int i = 0; i < n * n; ++i) P[i] = N.Q[i];
+    RT Pl[NXMAX * NXMAX];
+    for (int i = 0; i < n * n; ++i) Pl[i] = (RT)N.Q[i];
     for (int i = 0; i < n; ++i) {
-        const double t = th[i];
-        const double w = l1[i] * N.h * (-2.0 * t * (1.0 - t * t));
+        const RT t = (RT)th[i];
+        const RT w = (RT)l1[i] * (RT)N.h * ((RT)-2 * t * ((RT)1 - t * t));
         for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b) P[a * n + b] += w * N.W[i * n + a] * N.W[i * n + b];
+            for (int b = 0; b < n; ++b) Pl[a * n + b] += w * (RT)N.W[i * n + a] * (RT)N.W[i * n + b];
     }
+    for (int i = 0; i < n * n; ++i) P[i] = (double)Pl[i];
     const double *uk = u + (int64_t)k * m;
     double *Rt = Wk.Rt + (int64_t)k * m * m;
     double *Rh = Wk.Rh + (int64_t)k * m * m;
@@ -204,12 +212,11 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     for (int i = 0; i < m; ++i) Rt[i * m + i] += alpha;
     const double *B = Wk.B + (int64_t)k * n * m;
     for (int i = 0; i < m; ++i) {
-        double v = 0.0;
-        for (int j = 0; j < m; ++j) v += N.R[i * m + j] * uk[j];
+        RT v = 0;
+        for (int j = 0; j < m; ++j) v += (RT)N.R[i * m + j] * (RT)uk[j];
+        for (int j = 0; j < n; ++j) v += (RT)B[j * m + i] * (RT)l1[j];
         const double uu = uk[i];
-        v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
-        for (int j = 0; j < n; ++j) v += B[j * m + i] * l1[j];
-        Wk.d[(int64_t)k * m + i] = v;
+        Wk.d[(int64_t)k * m + i] = (double)v + mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
     }
 }
 
@@ -311,13 +318,6 @@ __global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork 
     if (i < nu) u[i] = Wk.uc[i];
 }
 
-#define LQK_NK_SWITCH(nk, CALL) \
-    switch (nk) {               \
-    case 1: CALL(1); break;     \
-    case 2: CALL(2); break;     \
-    case 3: CALL(3); break;     \
-    default: CALL(4); break;    \
-    }
 
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
 {
@@ -327,26 +327,32 @@ void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
 {
     hipLaunchKernelGGL(k_nmpc_clear, dim3(1), dim3(64), 0, st, status, zero, n);
 }
-void launch_nmpc_linearise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x)
+void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x)
 {
-    hipLaunchKernelGGL(k_nmpc_linearise, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
+    if (pr)
+        hipLaunchKernelGGL(k_nmpc_linearise<float>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
+    else
+        hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
 }
-void launch_costate_fold(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
+void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
 {
-#define CALL(K) hipLaunchKernelGGL(k_costate_fold<K>, dim3(grid), dim3(64), 0, st, Wk, inst, Y)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_costate_fold<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, Y)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_costate_apply(int nk, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
                           const double *Yfin)
 {
-#define CALL(K) hipLaunchKernelGGL(k_costate_apply<K>, dim3(grid), dim3(64), 0, st, Wk, inst, Yfin)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_costate_apply<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, Yfin)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_nmpc_quadraticise(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal)
+void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal)
 {
-    hipLaunchKernelGGL(k_nmpc_quadraticise, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
+    if (pr)
+        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
+    else
+        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {

@@ -19,16 +19,17 @@
 namespace lqk {
 
 // Closed-loop map F~ = A~ + B~ Gamma~.
+template <int PR>
 LQK_DEV Tile closed_loop(const ProbPtrs &P, const ValPtrs &V, const InstDesc &d, int k, double *s0,
                          double *s1)
 {
     const Tile Ah = load_Ah(P, d, k);
     const Tile Bh = load_Bh(P, d, k);
     const Tile Gh = load_Gh(V.G, V.g, d, k);
-    return mmak<1, false, false>(Bh, Gh, Ah, s0, s1);
+    return mmak<1, PR, false, false>(Bh, Gh, Ah, s0, s1);
 }
 
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                   const int32_t *__restrict__ seg_start, int batch,
                                                   double *__restrict__ Y)
@@ -46,8 +47,8 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     if (s == d.nseg - 1) return;
     Tile Phi = tident(d.n + 1);
     for (int k = k0; k < k1; ++k) {
-        const Tile F = closed_loop(P, V, d, k, s0, s1);
-        Phi = mmk<NK, false, false>(F, Phi, s0, s1);
+        const Tile F = closed_loop<PR>(P, V, d, k, s0, s1);
+        Phi = mmk<NK, PR, false, false>(F, Phi, s0, s1);
     }
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
 // suffix = 0: Y_s <- Y_s Y_{s-dd} for s >= dd;  suffix = 1: Y_s <- Y_s Y_{s+dd}
 // for s + dd <= nseg; other entries are copied.  The entry that no segment
 // reads (the last of a prefix scan, the first of a suffix scan) is skipped.
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ inst,
                                                   const int32_t *__restrict__ x_start, int batch, int dd,
                                                   int suffix, const double *__restrict__ Yin,
@@ -76,10 +77,10 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     }
     const int64_t ob = suffix ? gx + dd : gx - dd;
     const Tile b = gload(Yin + ob * TILE);
-    gstore(Yout + (int64_t)gx * TILE, mmk<NK, false, false>(a, b, lds, lds + SLOT));
+    gstore(Yout + (int64_t)gx * TILE, mmk<NK, PR, false, false>(a, b, lds, lds + SLOT));
 }
 
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ Yfin, double *__restrict__ x,
@@ -97,21 +98,21 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     for (int k = k0; k < k1; ++k) {
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
         const Tile Gh = load_Gh(V.G, V.g, d, k);
-        const Tile U = mmk<NK, false, false>(Gh, X, s0, s1);
+        const Tile U = mmk<NK, PR, false, false>(Gh, X, s0, s1);
         store_vec(u + d.og + (int64_t)k * m, U, m, n);
         if (lam) {
             const Tile Sh = load_Sh(V.S, V.s, d, k);
-            store_vec(lam + d.os + (int64_t)k * n, mmk<NK, false, false>(Sh, X, s0, s1), n, n);
+            store_vec(lam + d.os + (int64_t)k * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
         }
         const Tile Ah = load_Ah(P, d, k);
         const Tile Bh = load_Bh(P, d, k);
-        X = mmak<1, false, false>(Bh, U, mmk<NK, false, false>(Ah, X, s0, s1), s0, s1);
+        X = mmak<1, PR, false, false>(Bh, U, mmk<NK, PR, false, false>(Ah, X, s0, s1), s0, s1);
     }
     if (k1 == d.T) {
         store_vec(x + d.os + (int64_t)d.T * n, X, n, n);
         if (lam) {
             const Tile Sh = load_Sh(V.S, V.s, d, d.T);
-            store_vec(lam + d.os + (int64_t)d.T * n, mmk<NK, false, false>(Sh, X, s0, s1), n, n);
+            store_vec(lam + d.os + (int64_t)d.T * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
         }
     }
 }
@@ -119,35 +120,28 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
 }  // namespace lqk
 
 namespace lqk {
-#define LQK_NK_SWITCH(nk, CALL) \
-    switch (nk) {               \
-    case 1: CALL(1); break;     \
-    case 2: CALL(2); break;     \
-    case 3: CALL(3); break;     \
-    default: CALL(4); break;    \
-    }
 
-void launch_roll_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                       const int32_t *seg_start, int batch, double *Y)
 {
-#define CALL(K) hipLaunchKernelGGL(k_roll_fold<K>, dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Y)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_roll_fold<K, R>), dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Y)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
-void launch_affine_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
+void launch_affine_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
                       int dd, int suffix, const double *Yin, double *Yout)
 {
-#define CALL(K) hipLaunchKernelGGL(k_affine_ks<K>, dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, suffix, Yin, Yout)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_affine_ks<K, R>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, suffix, Yin, Yout)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
-void launch_roll_apply(int nk, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+void launch_roll_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                        const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u, double *lam)
 {
-#define CALL(K) hipLaunchKernelGGL(k_roll_apply<K>, dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Yfin, x, u, lam)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_roll_apply<K, R>), dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Yfin, x, u, lam)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 }  // namespace lqk

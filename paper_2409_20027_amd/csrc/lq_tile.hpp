@@ -165,19 +165,58 @@ LQK_DEV Tile sget_t(const double *s)
     return t;
 }
 
+// Row permutation that makes the FP32 16x16x4 instruction's accumulator (row
+// 4g + r in lane j + 16g, register r) coincide with the FP64 tile layout (row
+// 4r + g): feed row pi4(a) of the A operand as its row a.
+LQK_DEV int pi4(int a) { return 4 * (a & 3) + (a >> 2); }
+
+// Stage a tile for products of precision PR (0: FP64, 1: FP32 operands).
+template <int PR>
+LQK_DEV void sputp(double *s, const Tile &t)
+{
+    if constexpr (PR == 0) {
+        sput(s, t);
+    } else {
+        float *f = reinterpret_cast<float *>(s);
+        const int c = tcol();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) f[trow(r) * LD + c] = (float)t.v[r];
+    }
+}
+
 // acc + op(X) op(Y) over contraction length 4*KS, operands already staged.
-template <int KS, bool TX, bool TY>
+// PR = 0: FP64 products and accumulation.  PR = 1: FP32 products accumulated
+// in FP32, the result added to the FP64 accumulator in FP64.
+template <int KS, int PR, bool TX, bool TY>
 LQK_DEV d4 mfma_k(const double *sx, const double *sy, d4 acc)
 {
     const int c = tcol(), g = tgrp();
+    if constexpr (PR == 0) {
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        const int kk = 4 * k + g;
-        const double a = TX ? sx[kk * LD + c] : sx[c * LD + kk];
-        const double b = TY ? sy[c * LD + kk] : sy[kk * LD + c];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        for (int k = 0; k < KS; ++k) {
+            const int kk = 4 * k + g;
+            const double a = TX ? sx[kk * LD + c] : sx[c * LD + kk];
+            const double b = TY ? sy[c * LD + kk] : sy[kk * LD + c];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+        return acc;
+    } else {
+        const float *fx = reinterpret_cast<const float *>(sx);
+        const float *fy = reinterpret_cast<const float *>(sy);
+        const int pc = pi4(c);
+        f4 a4 = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int kk = 4 * k + g;
+            const float a = TX ? fx[kk * LD + pc] : fx[pc * LD + kk];
+            const float b = TY ? fy[c * LD + kk] : fy[kk * LD + c];
+            a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, a4, 0, 0, 0);
+        }
+        d4 o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) o[r] = acc[r] + (double)a4[r];
+        return o;
     }
-    return acc;
 }
 
 // Same with a run-time slice count (small auxiliary products only).
@@ -224,26 +263,26 @@ LQK_DEV Tile mma(const Tile &X, const Tile &Y, const Tile &acc, int K, double *s
 }
 
 // Compile-time slice-count versions of mm / mma.
-template <int KS, bool TX, bool TY>
+template <int KS, int PR, bool TX, bool TY>
 LQK_DEV Tile mmk(const Tile &X, const Tile &Y, double *sx, double *sy)
 {
     wsync();
-    sput(sx, X);
-    sput(sy, Y);
+    sputp<PR>(sx, X);
+    sputp<PR>(sy, Y);
     wsync();
     Tile d;
-    d.v = mfma_k<KS, TX, TY>(sx, sy, (d4){0.0, 0.0, 0.0, 0.0});
+    d.v = mfma_k<KS, PR, TX, TY>(sx, sy, (d4){0.0, 0.0, 0.0, 0.0});
     return d;
 }
-template <int KS, bool TX, bool TY>
+template <int KS, int PR, bool TX, bool TY>
 LQK_DEV Tile mmak(const Tile &X, const Tile &Y, const Tile &acc, double *sx, double *sy)
 {
     wsync();
-    sput(sx, X);
-    sput(sy, Y);
+    sputp<PR>(sx, X);
+    sputp<PR>(sy, Y);
     wsync();
     Tile d;
-    d.v = mfma_k<KS, TX, TY>(sx, sy, acc.v);
+    d.v = mfma_k<KS, PR, TX, TY>(sx, sy, acc.v);
     return d;
 }
 
@@ -561,6 +600,24 @@ LQK_DEV bool chol_inv_global(const double *R, int m, double li[MMAX][MMAX])
     small_tri_inv(li);
     return ok;
 }
+
+// Launch a kernel template <NK, PR> for the run-time slice count and precision.
+#define LQK_DISPATCH(nk, pr, CALL)   \
+    if (pr) {                        \
+        switch (nk) {                \
+        case 1: CALL(1, 1); break;   \
+        case 2: CALL(2, 1); break;   \
+        case 3: CALL(3, 1); break;   \
+        default: CALL(4, 1); break;  \
+        }                            \
+    } else {                         \
+        switch (nk) {                \
+        case 1: CALL(1, 0); break;   \
+        case 2: CALL(2, 0); break;   \
+        case 3: CALL(3, 0); break;   \
+        default: CALL(4, 0); break;  \
+        }                            \
+    }
 
 // Report the first failure of an instance: status = (-code) | (k << 8).
 LQK_DEV void report(int32_t *status, int inst, int code, int k)

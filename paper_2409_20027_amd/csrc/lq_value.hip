@@ -40,6 +40,7 @@ struct StageElem {
 
 // Stage element of eq:value-fun-elem-init in the P^{-1}-free form, from the
 // stage data (R = L L').  Returns false if R is not positive definite.
+template <int PR>
 LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, StageElem &e,
                               double *s0, double *s1)
 {
@@ -85,8 +86,8 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
             v += lg * mt;
         }
         N.v[0] = (g < m) ? v : 0.0;
-        e.Ab = tsub(e.Ab, mmk<1, false, false>(e.G, N, s0, s1));
-        e.J = tsub(e.J, mmk<1, true, false>(N, N, s0, s1));
+        e.Ab = tsub(e.Ab, mmk<1, PR, false, false>(e.G, N, s0, s1));
+        e.J = tsub(e.J, mmk<1, PR, true, false>(N, N, s0, s1));
     }
     return ok;
 }
@@ -94,49 +95,49 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
 // Left fold of a stage element into an aggregate E = (A^, C^, J^):
 // E <- e_k (x) E with the rank-m Woodbury form of the operator.
 // Returns false if W = I + G'J^G is singular.
-template <int NK>
+template <int NK, int PR>
 LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int m,
                        double *s0, double *s1, double *s2, double *s3)
 {
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     wsync();
-    sput(s0, Jh);
-    sput(s1, e.G);
-    sput(s2, Ah);
-    sput(s3, e.Ab);
+    sputp<PR>(s0, Jh);
+    sputp<PR>(s1, e.G);
+    sputp<PR>(s2, Ah);
+    sputp<PR>(s3, e.Ab);
     wsync();
     Tile JG, H, JA, AA;
-    JG.v = mfma_k<NK, false, false>(s0, s1, z);   // J^ G
-    H.v = mfma_k<NK, false, false>(s2, s1, z);    // A^ G
-    JA.v = mfma_k<NK, false, false>(s0, s3, z);   // J^ Ab
-    AA.v = mfma_k<NK, false, false>(s2, s3, z);   // A^ Ab
+    JG.v = mfma_k<NK, PR, false, false>(s0, s1, z);   // J^ G
+    H.v = mfma_k<NK, PR, false, false>(s2, s1, z);    // A^ G
+    JA.v = mfma_k<NK, PR, false, false>(s0, s3, z);   // J^ Ab
+    AA.v = mfma_k<NK, PR, false, false>(s2, s3, z);   // A^ Ab
     wsync();
-    sput(s0, JG);
-    sput(s2, JA);
+    sputp<PR>(s0, JG);
+    sputp<PR>(s2, JA);
     wsync();
     Tile W, P, Jn;
-    W.v = mfma_k<NK, true, false>(s1, s0, tident(m).v);  // I + G'J^G
-    P.v = mfma_k<NK, true, false>(s1, s2, z);             // G'J^ Ab
-    Jn.v = mfma_k<NK, true, false>(s3, s2, e.J.v);        // Ab'J^ Ab + J
+    W.v = mfma_k<NK, PR, true, false>(s1, s0, tident(m).v);  // I + G'J^G
+    P.v = mfma_k<NK, PR, true, false>(s1, s2, z);             // G'J^ Ab
+    Jn.v = mfma_k<NK, PR, true, false>(s3, s2, e.J.v);        // Ab'J^ Ab + J
     Tile Wi;
     const bool ok = gen_inverse_small(W, m, Wi, s0);
     wsync();
-    sput(s0, Wi);
-    sput(s1, P);
-    sput(s2, H);
+    sputp<PR>(s0, Wi);
+    sputp<PR>(s1, P);
+    sputp<PR>(s2, H);
     wsync();
     Tile WP, WH;
-    WP.v = mfma_k<1, false, false>(s0, s1, z);   // W^{-1} P
-    WH.v = mfma_k<1, false, true>(s0, s2, z);    // W^{-1} H'
+    WP.v = mfma_k<1, PR, false, false>(s0, s1, z);   // W^{-1} P
+    WH.v = mfma_k<1, PR, false, true>(s0, s2, z);    // W^{-1} H'
     wsync();
-    sput(s3, WP);
-    sput(s0, WH);
+    sputp<PR>(s3, WP);
+    sputp<PR>(s0, WH);
     wsync();
     Tile t;
-    t.v = mfma_k<1, false, false>(s2, s3, z);    // H W^{-1} P
+    t.v = mfma_k<1, PR, false, false>(s2, s3, z);    // H W^{-1} P
     Ah.v = AA.v - t.v;
-    Ch.v = mfma_k<1, false, false>(s2, s0, Ch.v); // C^ + H W^{-1} H'
-    t.v = mfma_k<1, true, false>(s1, s3, z);      // P' W^{-1} P
+    Ch.v = mfma_k<1, PR, false, false>(s2, s0, Ch.v); // C^ + H W^{-1} H'
+    t.v = mfma_k<1, PR, true, false>(s1, s3, z);      // P' W^{-1} P
     Jh.v = Jn.v - t.v;
     wsync();
     return ok;
@@ -145,6 +146,7 @@ LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int m,
 // ---------------------------------------------------------------------------
 // Element build (materialised)
 // ---------------------------------------------------------------------------
+template <int PR>
 __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                        const int64_t *__restrict__ elem_start, int batch,
                                                        double *__restrict__ elems, int32_t *status)
@@ -163,8 +165,8 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
         return;
     }
     StageElem e;
-    const bool ok = build_stage_elem(P, d, k, e, lds, lds + SLOT);
-    const Tile C = mmk<1, false, true>(e.G, e.G, lds, lds + SLOT);
+    const bool ok = build_stage_elem<PR>(P, d, k, e, lds, lds + SLOT);
+    const Tile C = mmk<1, PR, false, true>(e.G, e.G, lds, lds + SLOT);
     gstore(out, e.Ab);
     gstore(out + TILE, C);
     gstore(out + 2 * TILE, e.J);
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
 // element after the last segment of each instance.
 // Scan buffer entry = 3 tiles (A~, C~, J~).
 // ---------------------------------------------------------------------------
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ elems, double *__restrict__ X,
@@ -210,11 +212,11 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             e.Ab = gload(ep);
             e.J = gload(ep + 2 * TILE);
             e.G = gload(ep + 3 * TILE);
-        } else if (!build_stage_elem(P, d, k, e, s0, s1) && !code) {
+        } else if (!build_stage_elem<PR>(P, d, k, e, s0, s1) && !code) {
             code = ERR_NOT_PD;
             fk = k;
         }
-        if (!fold_left<NK>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
+        if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
             code = ERR_SINGULAR;
             fk = k;
         }
@@ -232,7 +234,7 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
 // index nseg); it is terminal-type (A~ = corner, C~ = 0, only J~ meaningful)
 // once it covers nseg.  Terminal-type entries are only ever right operands.
 // ---------------------------------------------------------------------------
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ inst,
                                                  const int32_t *__restrict__ x_start, int batch, int dd,
                                                  const double *__restrict__ Xin, double *__restrict__ Xout,
@@ -259,52 +261,52 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
     const Tile J2 = gload(b + 2 * TILE);
     // X = I + C~1 J~2
-    sput(s0, C1);
-    sput(s1, J2);
+    sputp<PR>(s0, C1);
+    sputp<PR>(s1, J2);
     wsync();
     Tile Xt;
-    Xt.v = mfma_k<NK, false, false>(s0, s1, tident(n1).v);
+    Xt.v = mfma_k<NK, PR, false, false>(s0, s1, tident(n1).v);
     const bool ok = gj_inverse(Xt, n1, s2);
     wsync();
-    sput(s3, Xt);  // X^{-1}
+    sputp<PR>(s3, Xt);  // X^{-1}
     wsync();
     Tile T3;
-    T3.v = mfma_k<NK, false, false>(s1, s3, z);   // J~2 X^{-1} = (X^{-T} J~2)'
+    T3.v = mfma_k<NK, PR, false, false>(s1, s3, z);   // J~2 X^{-1} = (X^{-T} J~2)'
     wsync();
-    sput(s0, T3);
-    sput(s2, A1);
+    sputp<PR>(s0, T3);
+    sputp<PR>(s2, A1);
     wsync();
     Tile T4;
-    T4.v = mfma_k<NK, true, false>(s0, s2, z);    // X^{-T} J~2 A~1
+    T4.v = mfma_k<NK, PR, true, false>(s0, s2, z);    // X^{-T} J~2 A~1
     wsync();
-    sput(s1, T4);
+    sputp<PR>(s1, T4);
     wsync();
     Tile Jn;
-    Jn.v = mfma_k<NK, true, false>(s2, s1, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
+    Jn.v = mfma_k<NK, PR, true, false>(s2, s1, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
     Jn = tsym(Jn, s0);
     gstore(o + 2 * TILE, Jn);
     if (!b_term) {
         const Tile A2 = gload(b), C2 = gload(b + TILE);
         wsync();
-        sput(s0, A2);
+        sputp<PR>(s0, A2);
         wsync();
         Tile T1;
-        T1.v = mfma_k<NK, false, false>(s0, s3, z);   // A~2 X^{-1}
+        T1.v = mfma_k<NK, PR, false, false>(s0, s3, z);   // A~2 X^{-1}
         wsync();
-        sput(s1, T1);
+        sputp<PR>(s1, T1);
         wsync();
         Tile An;
-        An.v = mfma_k<NK, false, false>(s1, s2, z);   // A~2 X^{-1} A~1
+        An.v = mfma_k<NK, PR, false, false>(s1, s2, z);   // A~2 X^{-1} A~1
         wsync();
-        sput(s3, C1);
+        sputp<PR>(s3, C1);
         wsync();
         Tile T2;
-        T2.v = mfma_k<NK, false, false>(s1, s3, z);   // A~2 X^{-1} C~1
+        T2.v = mfma_k<NK, PR, false, false>(s1, s3, z);   // A~2 X^{-1} C~1
         wsync();
-        sput(s2, T2);
+        sputp<PR>(s2, T2);
         wsync();
         Tile Cn;
-        Cn.v = mfma_k<NK, false, true>(s2, s0, C2.v); // ... A~2' + C~2
+        Cn.v = mfma_k<NK, PR, false, true>(s2, s0, C2.v); // ... A~2' + C~2
         Cn = tsym(Cn, s1);
         gstore(o, An);
         gstore(o + TILE, Cn);
@@ -319,7 +321,7 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
 //   Gamma~ = -Q_uu^{-1} Q_ux~ = [Gamma, gamma];
 //   S~ = sym(Q~ + A~'S~'A~ + Q_ux~' Gamma~).
 // ---------------------------------------------------------------------------
-template <int NK>
+template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Xfin, ValPtrs V,
@@ -348,36 +350,36 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         const Tile Rk = load_R(P, d, k);
         const Tile MhT = has_mr ? load_MhT(P, d, k) : tzero();
         wsync();
-        sput(s0, St);
-        sput(s1, Bh);
-        sput(s2, Ah);
+        sputp<PR>(s0, St);
+        sputp<PR>(s1, Bh);
+        sputp<PR>(s2, Ah);
         wsync();
         Tile SB, SA;
-        SB.v = mfma_k<NK, false, false>(s0, s1, z);
-        SA.v = mfma_k<NK, false, false>(s0, s2, z);
+        SB.v = mfma_k<NK, PR, false, false>(s0, s1, z);
+        SA.v = mfma_k<NK, PR, false, false>(s0, s2, z);
         wsync();
-        sput(s3, SB);
-        sput(s0, SA);
+        sputp<PR>(s3, SB);
+        sputp<PR>(s0, SA);
         wsync();
         Tile Quu, Qux, Sn;
-        Quu.v = mfma_k<NK, true, false>(s1, s3, Rk.v);
-        Qux.v = mfma_k<NK, true, false>(s1, s0, MhT.v);
-        Sn.v = mfma_k<NK, true, false>(s2, s0, Qh.v);
+        Quu.v = mfma_k<NK, PR, true, false>(s1, s3, Rk.v);
+        Qux.v = mfma_k<NK, PR, true, false>(s1, s0, MhT.v);
+        Sn.v = mfma_k<NK, PR, true, false>(s2, s0, Qh.v);
         Tile Qi;
         if (!spd_inverse(Quu, m, Qi, s3) && !code) {
             code = ERR_NOT_PD;
             fk = k;
         }
         wsync();
-        sput(s3, Qi);
-        sput(s1, Qux);
+        sputp<PR>(s3, Qi);
+        sputp<PR>(s1, Qux);
         wsync();
         Tile Gh;
-        Gh.v = -mfma_k<1, false, false>(s3, s1, z);
+        Gh.v = -mfma_k<1, PR, false, false>(s3, s1, z);
         wsync();
-        sput(s3, Gh);
+        sputp<PR>(s3, Gh);
         wsync();
-        Sn.v = mfma_k<1, true, false>(s1, s3, Sn.v);
+        Sn.v = mfma_k<1, PR, true, false>(s1, s3, Sn.v);
         St = tsym(Sn, s0);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
@@ -396,39 +398,33 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
 // Host launchers (the contraction slice count NK = ceil((n_max + 1) / 4) is a
 // template parameter so that every product is fully unrolled).
 // ---------------------------------------------------------------------------
-#define LQK_NK_SWITCH(nk, CALL) \
-    switch (nk) {               \
-    case 1: CALL(1); break;     \
-    case 2: CALL(2); break;     \
-    case 3: CALL(3); break;     \
-    default: CALL(4); break;    \
-    }
 
-void launch_value_fold(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+void launch_value_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                        const int32_t *seg_start, int batch, const double *elems, double *X, int32_t *status)
 {
-#define CALL(K) hipLaunchKernelGGL(k_value_fold<K>, dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, elems, X, status)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_value_fold<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, elems, X, status)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
-void launch_value_ks(int nk, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                      int batch, int dd, const double *Xin, double *Xout, int32_t *status)
 {
-#define CALL(K) hipLaunchKernelGGL(k_value_ks<K>, dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, Xin, Xout, status)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_value_ks<K, R>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, Xin, Xout, status)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
-void launch_value_riccati(int nk, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                           const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, int32_t *status)
 {
-#define CALL(K) hipLaunchKernelGGL(k_value_riccati<K>, dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, status)
-    LQK_NK_SWITCH(nk, CALL)
+#define CALL(K, R) hipLaunchKernelGGL((k_value_riccati<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, status)
+    LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
 // Diagnostic: D = op(X) op(Y) (+ Z) for row-major 16 x 16 inputs.
+template <int PR>
 __global__ __launch_bounds__(64) void k_selftest_mm(const double *X, const double *Y, const double *Z,
                                                     double *D, int tx, int ty)
 {
@@ -437,14 +433,32 @@ __global__ __launch_bounds__(64) void k_selftest_mm(const double *X, const doubl
     const Tile zt = Z ? gload_rm(Z, 16, 16, 16) : tzero();
     Tile d;
     if (tx && ty)
-        d = mma<true, true>(x, y, zt, 16, lds, lds + SLOT);
+        d = mmak<4, PR, true, true>(x, y, zt, lds, lds + SLOT);
     else if (tx)
-        d = mma<true, false>(x, y, zt, 16, lds, lds + SLOT);
+        d = mmak<4, PR, true, false>(x, y, zt, lds, lds + SLOT);
     else if (ty)
-        d = mma<false, true>(x, y, zt, 16, lds, lds + SLOT);
+        d = mmak<4, PR, false, true>(x, y, zt, lds, lds + SLOT);
     else
-        d = mma<false, false>(x, y, zt, 16, lds, lds + SLOT);
+        d = mmak<4, PR, false, false>(x, y, zt, lds, lds + SLOT);
     gstore_rm(D, d, 16, 16, 16);
+}
+
+void launch_build_elements(int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                           const int64_t *elem_start, int batch, double *elems, int32_t *status)
+{
+    if (pr)
+        hipLaunchKernelGGL(k_build_elements<1>, dim3(grid), dim3(64), 0, st, P, inst, elem_start, batch, elems, status);
+    else
+        hipLaunchKernelGGL(k_build_elements<0>, dim3(grid), dim3(64), 0, st, P, inst, elem_start, batch, elems, status);
+}
+
+void launch_selftest_mm(int pr, hipStream_t st, const double *X, const double *Y, const double *Z, double *D, int tx,
+                        int ty)
+{
+    if (pr)
+        hipLaunchKernelGGL(k_selftest_mm<1>, dim3(1), dim3(64), 0, st, X, Y, Z, D, tx, ty);
+    else
+        hipLaunchKernelGGL(k_selftest_mm<0>, dim3(1), dim3(64), 0, st, X, Y, Z, D, tx, ty);
 }
 
 }  // namespace lqk

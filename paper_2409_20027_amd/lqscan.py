@@ -71,7 +71,7 @@ _lib.lq_plan_set_timing.argtypes = [_plan_p, ctypes.c_uint32, ctypes.c_int32]
 _lib.lq_plan_set_timing.restype = ctypes.c_int
 _lib.lq_plan_phase_times.argtypes = [_plan_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
 _lib.lq_plan_phase_times.restype = ctypes.c_int
-_lib.lq_selftest_tile_mm.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, _P]
+_lib.lq_selftest_tile_mm.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]
 _lib.lq_selftest_tile_mm.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
@@ -236,8 +236,9 @@ def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: di
                                          _stream(stream)))
 
 
-def lq_selftest_tile_mm(X, Y, Z, D, tx=False, ty=False, stream=None):
+def lq_selftest_tile_mm(X, Y, Z, D, tx=False, ty=False, precision="fp64", stream=None):
     _check("lq_selftest_tile_mm", _lib.lq_selftest_tile_mm(_f64(X), _f64(Y), _f64(Z), _f64(D), int(tx), int(ty),
+                                                           {"fp64": LQ_FP64, "mixed": LQ_MIXED}[precision],
                                                            _stream(stream)))
 
 
@@ -390,10 +391,10 @@ class NewtonMPC:
     barrier weight between levels and reads the traces at the end.
     """
 
-    def __init__(self, p, device="cuda", seg_len=0):
+    def __init__(self, p, device="cuda", seg_len=0, precision="fp64"):
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
         self.p = p
-        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len)
+        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len, precision=precision)
         self.dev = {k: t(getattr(p, k)) for k in ("W", "Bm", "Q", "R", "QT", "xref", "x0")}
         self.x = torch.zeros((p.T + 1) * p.nx, dtype=torch.float64, device=device)
         self.u = t(p.u0).reshape(-1).clone()

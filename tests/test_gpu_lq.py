@@ -73,17 +73,18 @@ def check(per, insts, tol=TOL):
 
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-14), ("mixed", 1e-6)])
 @pytest.mark.parametrize("tx,ty", [(0, 0), (1, 0), (0, 1), (1, 1)])
-def test_tile_mm_selftest(lq, tx, ty):
-    """Pins the operand/accumulator lane layout of the FP64 16x16x4 matrix instruction."""
+def test_tile_mm_selftest(lq, tx, ty, prec, tol):
+    """Pins the operand/accumulator lane layouts of the FP64 and FP32 16x16x4 matrix instructions."""
     rng = np.random.default_rng(1 + 2 * tx + ty)
     X, Y, Z = (rng.standard_normal((16, 16)) for _ in range(3))
     d = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda").contiguous()
     D = torch.zeros(16, 16, dtype=torch.float64, device="cuda")
-    lq.lq_selftest_tile_mm(d(X), d(Y), d(Z), D, tx, ty)
+    lq.lq_selftest_tile_mm(d(X), d(Y), d(Z), D, tx, ty, precision=prec)
     torch.cuda.synchronize()
     ref = (X.T if tx else X) @ (Y.T if ty else Y) + Z
-    assert rel(D.cpu().numpy(), ref) < 1e-14
+    assert rel(D.cpu().numpy(), ref) < tol
 
 
 def test_cfg0_small_scan(lq):
