@@ -96,15 +96,21 @@ LQK_DEV int find_inst64(const int64_t *start, int batch, int64_t g)
 // A~ = [[A, c], [0, 1]]
 LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k)
 {
-    const int n = d.n;
-    Tile t = gload_rm(P.A + d.oA + (int64_t)k * n * n, n, n, n);
-    const int c = tcol();
+    const int n = d.n, c = tcol();
+    const double *A = P.A + d.oA + (int64_t)k * n * n;
     const double *cc = P.c ? P.c + d.oc + (int64_t)k * n : nullptr;
+    Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
-        const double cv = cc ? ldz(cc, i, i < n && c == n) : 0.0;
-        if (c == n) t.v[r] = (i < n) ? cv : (i == n ? 1.0 : 0.0);
+        const double *a = zptr();
+        if (i < n && c < n)
+            a = A + i * n + c;
+        else if (c == n && i < n && cc)
+            a = cc + i;
+        else if (c == n && i == n)
+            a = optr();
+        t.v[r] = *a;
     }
     return t;
 }
@@ -118,18 +124,21 @@ LQK_DEV Tile load_Bh(const ProbPtrs &P, const InstDesc &d, int k)
 // Q~ = [[Q, q], [q', 0]]
 LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
 {
-    const int n = d.n;
-    Tile t = gload_rm(P.Q + d.oA + (int64_t)k * n * n, n, n, n);
-    if (P.q) {
-        const double *qq = P.q + d.oc + (int64_t)k * n;
-        const int c = tcol();
+    const int n = d.n, c = tcol();
+    const double *Q = P.Q + d.oA + (int64_t)k * n * n;
+    const double *qq = P.q ? P.q + d.oc + (int64_t)k * n : nullptr;
+    Tile t;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = trow(r);
-            const bool col = (c == n && i < n), row = (i == n && c < n);
-            const double v = ldz(qq, col ? i : c, col || row);
-            if (col || row) t.v[r] = v;
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double *a = zptr();
+        if (i < n && c < n)
+            a = Q + i * n + c;
+        else if (qq && c == n && i < n)
+            a = qq + i;
+        else if (qq && i == n && c < n)
+            a = qq + c;
+        t.v[r] = *a;
     }
     return t;
 }
@@ -137,17 +146,19 @@ LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
 // M~' = [M', r]   (m x (n+1))
 LQK_DEV Tile load_MhT(const ProbPtrs &P, const InstDesc &d, int k)
 {
-    const int n = d.n, m = d.m;
-    Tile t = gload_rm_t(P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr, m, n, m);
-    if (P.r) {
-        const double *rr = P.r + d.og + (int64_t)k * m;
-        const int c = tcol();
+    const int n = d.n, m = d.m, c = tcol();
+    const double *M = P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr;
+    const double *rr = P.r ? P.r + d.og + (int64_t)k * m : nullptr;
+    Tile t;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int a = trow(r);
-            const double v = ldz(rr, a, c == n && a < m);
-            if (c == n && a < m) t.v[r] = v;
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int a = trow(r);
+        const double *p = zptr();
+        if (M && a < m && c < n)
+            p = M + c * m + a;
+        else if (rr && a < m && c == n)
+            p = rr + a;
+        t.v[r] = *p;
     }
     return t;
 }
@@ -171,8 +182,7 @@ LQK_DEV Tile load_terminal_J(const ProbPtrs &P, const InstDesc &d, double *s)
         for (int r = 0; r < 4; ++r) {
             const int i = trow(r);
             const bool col = (c == n && i < n), row = (i == n && c < n);
-            const double v = ldz(qq, col ? i : c, col || row);
-            if (col || row) t.v[r] = v;
+            if (col || row) t.v[r] = qq[col ? i : c];
         }
     }
     return t;
@@ -191,15 +201,19 @@ LQK_DEV Tile corner(int n)
 // Gamma~ = [Gamma, gamma]   (m x (n+1)) from the control-law outputs.
 LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, int k)
 {
-    const int n = d.n, m = d.m;
-    Tile t = gload_rm(Gam + d.oG + (int64_t)k * m * n, m, n, n);
-    const int c = tcol();
+    const int n = d.n, m = d.m, c = tcol();
+    const double *G = Gam + d.oG + (int64_t)k * m * n;
     const double *gg = gam + d.og + (int64_t)k * m;
+    Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int a = trow(r);
-        const double v = ldz(gg, a, c == n && a < m);
-        if (c == n && a < m) t.v[r] = v;
+        const double *p = zptr();
+        if (a < m && c < n)
+            p = G + a * n + c;
+        else if (a < m && c == n)
+            p = gg + a;
+        t.v[r] = *p;
     }
     return t;
 }
@@ -207,16 +221,21 @@ LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, in
 // S~ = [[S, s], [s', 0]] from the value outputs (stage k = 0..T).
 LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
 {
-    const int n = d.n;
-    Tile t = gload_rm(S + d.oS + (int64_t)k * n * n, n, n, n);
+    const int n = d.n, c = tcol();
+    const double *Sk = S + d.oS + (int64_t)k * n * n;
     const double *ss = s + d.os + (int64_t)k * n;
-    const int c = tcol();
+    Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
-        const bool col = (c == n && i < n), row = (i == n && c < n);
-        const double v = ldz(ss, col ? i : c, col || row);
-        if (col || row) t.v[r] = v;
+        const double *p = zptr();
+        if (i < n && c < n)
+            p = Sk + i * n + c;
+        else if (c == n && i < n)
+            p = ss + i;
+        else if (i == n && c < n)
+            p = ss + c;
+        t.v[r] = *p;
     }
     return t;
 }
@@ -225,12 +244,17 @@ LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
 // homogeneous 1 at row `one_row` (-1 = none).
 LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
 {
-    Tile t = tzero();
+    const int c = tcol();
+    Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
-        const double x = v ? ldz(v, i, i < len && tcol() == col) : 0.0;
-        if (tcol() == col) t.v[r] = (i < len) ? x : (i == one_row ? 1.0 : 0.0);
+        const double *p = zptr();
+        if (c == col && i < len && v)
+            p = v + i;
+        else if (c == col && i == one_row)
+            p = optr();
+        t.v[r] = *p;
     }
     return t;
 }

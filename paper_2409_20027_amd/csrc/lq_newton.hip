@@ -89,8 +89,7 @@ __global__ void k_nmpc_clear(int32_t *st, double *zero, int n)
     if (threadIdx.x < n) zero[threadIdx.x] = 0.0;
 }
 
-// Step 1 (one lane per stage).  RT is the arithmetic type of the expansion
-// (float in mixed precision); results are stored in FP64.
+// Step 1 (one lane per stage), arithmetic type RT, results stored in FP64.
 template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x)
 {
@@ -178,8 +177,9 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
     }
 }
 
-// Step 3 (one lane per stage): second-order terms of the Hamiltonian in RT
-// (the barrier terms and alpha stay FP64: they set the step's feasibility).
+// Step 3 (one lane per stage): second-order terms of the Hamiltonian.  In
+// mixed precision the lambda' d2f contraction of P is formed in RT = float;
+// the gradient d, the barrier terms and alpha stay FP64.
 template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *u,
                                                            const double *scal)
@@ -210,13 +210,15 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     }
     for (int i = 0; i < m * m; ++i) Rt[i] = Rh[i];
     for (int i = 0; i < m; ++i) Rt[i * m + i] += alpha;
+    // the gradient d_k stays FP64 (mixed precision only approximates the Hessian)
     const double *B = Wk.B + (int64_t)k * n * m;
     for (int i = 0; i < m; ++i) {
-        RT v = 0;
-        for (int j = 0; j < m; ++j) v += (RT)N.R[i * m + j] * (RT)uk[j];
-        for (int j = 0; j < n; ++j) v += (RT)B[j * m + i] * (RT)l1[j];
+        double v = 0.0;
+        for (int j = 0; j < m; ++j) v += N.R[i * m + j] * uk[j];
         const double uu = uk[i];
-        Wk.d[(int64_t)k * m + i] = (double)v + mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
+        v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
+        for (int j = 0; j < n; ++j) v += B[j * m + i] * l1[j];
+        Wk.d[(int64_t)k * m + i] = v;
     }
 }
 
@@ -329,10 +331,10 @@ void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
 }
 void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x)
 {
-    if (pr)
-        hipLaunchKernelGGL(k_nmpc_linearise<float>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
-    else
-        hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
+    // The Jacobians define the co-states and hence the gradient, which sets
+    // the point Newton converges to: FP64 in every precision mode.
+    (void)pr;
+    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
 }
 void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
 {

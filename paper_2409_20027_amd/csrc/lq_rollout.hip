@@ -95,17 +95,21 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
     Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
+    // stage data of stage k+1 is loaded while stage k is processed
+    Tile nGh = load_Gh(V.G, V.g, d, k0), nAh = load_Ah(P, d, k0), nBh = load_Bh(P, d, k0);
+    Tile nSh = lam ? load_Sh(V.S, V.s, d, k0) : tzero();
     for (int k = k0; k < k1; ++k) {
+        const Tile Gh = nGh, Ah = nAh, Bh = nBh, Sh = nSh;
+        if (k + 1 < k1) {
+            nGh = load_Gh(V.G, V.g, d, k + 1);
+            nAh = load_Ah(P, d, k + 1);
+            nBh = load_Bh(P, d, k + 1);
+            if (lam) nSh = load_Sh(V.S, V.s, d, k + 1);
+        }
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
-        const Tile Gh = load_Gh(V.G, V.g, d, k);
         const Tile U = mmk<NK, PR, false, false>(Gh, X, s0, s1);
         store_vec(u + d.og + (int64_t)k * m, U, m, n);
-        if (lam) {
-            const Tile Sh = load_Sh(V.S, V.s, d, k);
-            store_vec(lam + d.os + (int64_t)k * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
-        }
-        const Tile Ah = load_Ah(P, d, k);
-        const Tile Bh = load_Bh(P, d, k);
+        if (lam) store_vec(lam + d.os + (int64_t)k * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
         X = mmak<1, PR, false, false>(Bh, U, mmk<NK, PR, false, false>(Ah, X, s0, s1), s0, s1);
     }
     if (k1 == d.T) {

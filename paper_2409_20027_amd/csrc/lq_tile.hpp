@@ -94,14 +94,17 @@ LQK_DEV Tile gload(const double *p)
 }
 LQK_DEV void gstore(double *p, const Tile &t) { *reinterpret_cast<d4 *>(p + 4 * lane()) = t.v; }
 
-// Load p[idx] if ok, else 0; the load itself is unconditional (index clamped
-// to 0, which must be valid) so that independent loads issue back to back
-// instead of one branch-and-wait each.
-LQK_DEV double ldz(const double *p, int64_t idx, bool ok)
-{
-    const double v = p[ok ? idx : 0];
-    return ok ? v : 0.0;
-}
+// Constants read by lanes whose tile entry is not backed by an input array.
+__device__ double kConst01[2] = {0.0, 1.0};   // global address space: loads stay global_load
+LQK_DEV const double *zptr() { return &kConst01[0]; }
+LQK_DEV const double *optr() { return &kConst01[1]; }
+
+// Address of p[idx] if ok, else of a constant zero.  Every tile entry is one
+// load from a per-lane address chosen before the load, so nothing depends on a
+// loaded value until it is used: independent loads issue back to back and a
+// load issued one stage ahead is only waited for where it is consumed.
+LQK_DEV const double *at(const double *p, int64_t idx, bool ok) { return ok ? p + idx : zptr(); }
+LQK_DEV double ldz(const double *p, int64_t idx, bool ok) { return *at(p, idx, ok); }
 
 // Global memory, row-major rows x cols block with leading dimension ld,
 // placed at tile offset (i0, j0); everything else zero.

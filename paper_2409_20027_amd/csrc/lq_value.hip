@@ -38,16 +38,56 @@ struct StageElem {
     Tile J;   // Q~ - N' N     ((n+1) x (n+1)),  N = L^{-1} M~'
 };
 
+// Raw stage data of the element build, loaded one stage ahead of its use.
+struct StageRaw {
+    Tile A, Q;                // A~ and Q~ (homogeneous)
+    double brow[4][MMAX];     // B at this lane's four rows
+    double R[MMAX][MMAX];     // R (identity-padded)
+    double mt[MMAX];          // M~ at this lane's column: M[c][b] (c < n) or r[b] (c == n)
+};
+
+LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, StageRaw &w)
+{
+    const int n = d.n, m = d.m, c = tcol();
+    w.A = load_Ah(P, d, k);
+    w.Q = load_Qh(P, d, k);
+    const double *Bk = P.B + d.oB + (int64_t)k * n * m;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+#pragma unroll
+        for (int b = 0; b < MMAX; ++b) w.brow[r][b] = ldz(Bk, (int64_t)i * m + b, i < n && b < m);
+    }
+    const double *Rk = P.R + d.oR + (int64_t)k * m * m;
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i)
+#pragma unroll
+        for (int j = 0; j < MMAX; ++j) {
+            const int ii = i < m ? i : 0, jj = j < m ? j : 0;
+            const double v = Rk[ii * m + jj];
+            w.R[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
+        }
+    const double *Mk = P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr;
+    const double *rk = P.r ? P.r + d.og + (int64_t)k * m : nullptr;
+#pragma unroll
+    for (int b = 0; b < MMAX; ++b)
+        w.mt[b] = *(Mk && c < n && b < m ? Mk + c * m + b : (rk && c == n && b < m ? rk + b : zptr()));
+}
+
 // Stage element of eq:value-fun-elem-init in the P^{-1}-free form, from the
 // stage data (R = L L').  Returns false if R is not positive definite.
 template <int PR>
-LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, StageElem &e,
-                              double *s0, double *s1)
+LQK_DEV bool build_from_raw(const StageRaw &w, const InstDesc &d, bool has_mr, StageElem &e, double *s0,
+                            double *s1)
 {
-    const int n = d.n, m = d.m;
+    const int n = d.n, m = d.m, c = tcol();
     double li[MMAX][MMAX];
-    const bool ok = chol_inv_global(P.R + d.oR + (int64_t)k * m * m, m, li);
-    const int c = tcol();
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i)
+#pragma unroll
+        for (int j = 0; j < MMAX; ++j) li[i][j] = w.R[i][j];
+    const bool ok = small_chol(li);
+    small_tri_inv(li);
     // row c of L^{-1}: G[i][c] = sum_b B[i][b] Linv[c][b]
     double lrow[MMAX];
 #pragma unroll
@@ -57,22 +97,18 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
         for (int a = 0; a < MMAX; ++a) t = (a == c) ? li[a][b] : t;
         lrow[b] = t;
     }
-    const double *Bk = P.B + d.oB + (int64_t)k * n * m;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r);
         double v = 0.0;
 #pragma unroll
-        for (int b = 0; b < MMAX; ++b) v += ldz(Bk, (int64_t)i * m + b, i < n && b < m) * lrow[b];
+        for (int b = 0; b < MMAX; ++b) v += w.brow[r][b] * lrow[b];
         e.G.v[r] = (i < n && c < m) ? v : 0.0;
     }
-    e.Ab = load_Ah(P, d, k);
-    e.J = load_Qh(P, d, k);
-    if (P.M || P.r) {
-        // N[a][j] = sum_b Linv[a][b] M~[j][b]; rows a < m <= 4 are register 0 of
-        // lane group a.
-        const double *Mk = P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr;
-        const double *rk = P.r ? P.r + d.og + (int64_t)k * m : nullptr;
+    e.Ab = w.A;
+    e.J = w.Q;
+    if (has_mr) {
+        // N[a][j] = sum_b Linv[a][b] M~[j][b]; rows a < m <= 4 are register 0 of lane group a.
         const int g = tgrp();
         Tile N = tzero();
         double v = 0.0;
@@ -81,15 +117,21 @@ LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, Stage
             double lg = 0.0;
 #pragma unroll
             for (int a = 0; a < MMAX; ++a) lg = (a == g) ? li[a][b] : lg;
-            const double mt = (Mk ? ldz(Mk, (int64_t)c * m + b, c < n && b < m) : 0.0) +
-                              (rk ? ldz(rk, b, c == n && b < m) : 0.0);
-            v += lg * mt;
+            v += lg * w.mt[b];
         }
         N.v[0] = (g < m) ? v : 0.0;
         e.Ab = tsub(e.Ab, mmk<1, PR, false, false>(e.G, N, s0, s1));
         e.J = tsub(e.J, mmk<1, PR, true, false>(N, N, s0, s1));
     }
     return ok;
+}
+
+template <int PR>
+LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, StageElem &e, double *s0, double *s1)
+{
+    StageRaw w;
+    load_stage_raw(P, d, k, w);
+    return build_from_raw<PR>(w, d, (P.M != nullptr) || (P.r != nullptr), e, s0, s1);
 }
 
 // Left fold of a stage element into an aggregate E = (A^, C^, J^):
@@ -205,20 +247,35 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     // The element of segment 0 is never read: the Bellman steps of segment s
     // start from the scanned element s + 1.
     if (s == 0) return;
-    for (int k = k1 - 1; k >= k0; --k) {
-        StageElem e;
-        if (elems) {
+    if (elems) {
+        for (int k = k1 - 1; k >= k0; --k) {
+            StageElem e;
             const double *ep = elems + (d.elem0 + k) * 4 * TILE;
             e.Ab = gload(ep);
             e.J = gload(ep + 2 * TILE);
             e.G = gload(ep + 3 * TILE);
-        } else if (!build_stage_elem<PR>(P, d, k, e, s0, s1) && !code) {
-            code = ERR_NOT_PD;
-            fk = k;
+            if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
+                code = ERR_SINGULAR;
+                fk = k;
+            }
         }
-        if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
-            code = ERR_SINGULAR;
-            fk = k;
+    } else {
+        // fused element build; the raw data of stage k-1 is loaded while stage k is folded
+        const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
+        StageRaw cur, nxt;
+        load_stage_raw(P, d, k1 - 1, cur);
+        for (int k = k1 - 1; k >= k0; --k) {
+            if (k > k0) load_stage_raw(P, d, k - 1, nxt);
+            StageElem e;
+            if (!build_from_raw<PR>(cur, d, has_mr, e, s0, s1) && !code) {
+                code = ERR_NOT_PD;
+                fk = k;
+            }
+            if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
+                code = ERR_SINGULAR;
+                fk = k;
+            }
+            if (k > k0) cur = nxt;
         }
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
@@ -343,12 +400,18 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
     }
     int code = 0, fk = 0;
+    // stage data of stage k-1 is loaded while stage k is processed
+    Tile nAh = load_Ah(P, d, k1 - 1), nBh = load_Bh(P, d, k1 - 1), nQh = load_Qh(P, d, k1 - 1);
+    Tile nRk = load_R(P, d, k1 - 1), nMhT = has_mr ? load_MhT(P, d, k1 - 1) : tzero();
     for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Ah = load_Ah(P, d, k);
-        const Tile Bh = load_Bh(P, d, k);
-        const Tile Qh = load_Qh(P, d, k);
-        const Tile Rk = load_R(P, d, k);
-        const Tile MhT = has_mr ? load_MhT(P, d, k) : tzero();
+        const Tile Ah = nAh, Bh = nBh, Qh = nQh, Rk = nRk, MhT = nMhT;
+        if (k > k0) {
+            nAh = load_Ah(P, d, k - 1);
+            nBh = load_Bh(P, d, k - 1);
+            nQh = load_Qh(P, d, k - 1);
+            nRk = load_R(P, d, k - 1);
+            if (has_mr) nMhT = load_MhT(P, d, k - 1);
+        }
         wsync();
         sputp<PR>(s0, St);
         sputp<PR>(s1, Bh);

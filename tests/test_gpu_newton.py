@@ -64,7 +64,12 @@ def test_benign_instance_converges(lq):
     p = dataclasses.replace(p0, W=-np.eye(4) + 0.3 * p0.W, Bm=np.ones((4, 1)))
     ref = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
     got = lq.NewtonMPC(p, seg_len=8).run(W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
-    # decisions taken on round-off-sized steps near convergence may differ; compare
-    # the decisions of the first 40 iterations and the converged solution
-    assert np.array_equal(got["accept"][:40], ref["accept"][:40])
+    # Near convergence the predicted decrease falls to round-off level and the
+    # gain ratio is the ratio of two rounding errors: decisions there are not
+    # determined by the arithmetic and may differ.  Decisions are compared
+    # while the step is well above round-off; the converged solutions agree.
+    ok = np.abs(got["pred"]) > 1e-11 * np.abs(got["cost"])
+    first_noise = int(np.argmin(ok)) if not ok.all() else len(ok)
+    assert first_noise >= 3
+    assert np.array_equal(got["accept"][:first_noise], ref["accept"][:first_noise])
     assert rel(got["u"], ref["u"]) < 1e-8
