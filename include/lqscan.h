@@ -38,8 +38,11 @@
  *   nullable): 0 means success, otherwise
  *       status[i] = (-code) | (k << 8)
  *   with code one of LQ_ERR_NOT_PD / LQ_ERR_SINGULAR / LQ_ERR_NONFINITE and
- *   k the stage (or segment, for the scan's operator) where it was detected.
- *   The first failure of an instance is kept; status must be zeroed by the
+ *   k the stage where it was detected (for the scan's operator: the first
+ *   stage of the segment whose combination failed).  Of several failures the
+ *   one with the largest status value, i.e. at the largest stage, is kept (a
+ *   backward sweep over the stages meets it first), independently of the
+ *   order in which the device work finishes; status must be zeroed by the
  *   caller before the first call that should report into it.  Results of a
  *   failed instance are unspecified; other instances are unaffected.
  * - Supported sizes: 1 <= n <= 15, 1 <= m <= 4, T >= 1.
@@ -161,7 +164,12 @@ lq_status lq_build_elements(const lq_plan *plan, const lq_problem *prob, double 
  * S_k is symmetrised.  `elements` may be NULL: the element build is then
  * fused into the scan and nothing is materialised; otherwise it must hold the
  * output of lq_build_elements for the same problem.
- * Numerical failures: LQ_ERR_NOT_PD (R_k or R_k + B'S_{k+1}B), LQ_ERR_SINGULAR.
+ * Numerical failures: LQ_ERR_NOT_PD (R_k + B'S_{k+1}B not positive definite;
+ * with cross terms M or r also R_k, whose inverse forms the Schur complement),
+ * LQ_ERR_SINGULAR.  Without cross terms R_k itself is never factorised: it
+ * enters the fused fold only through R_k + B'J B (J the aggregate's value
+ * matrix), so a singular or indefinite R_k is accepted wherever
+ * R_k + B'S_{k+1}B is positive definite.
  */
 lq_status lq_scan_solve(const lq_plan *plan, const lq_problem *prob, const double *elements,
                         const lq_value *out, void *workspace, int32_t *status, void *stream);
@@ -266,7 +274,8 @@ lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_
 
 /*
  * Diagnostic: one 16 x 16 tile product D = op(X) op(Y) (+ Z) through the
- * library's matrix-core tile primitive, with FP64 products (precision
+ * library's matrix-core tile primitive (P'Q of register tiles, with the LDS
+ * transpose the solver uses where op needs it), with FP64 products (precision
  * LQ_FP64) or FP32 products added to Z in FP64 (LQ_MIXED).  X, Y, Z, D are
  * device pointers to row-major 16 x 16 FP64 arrays (Z nullable).  Used by the
  * test suite to pin the operand and accumulator layouts of the matrix

@@ -19,71 +19,46 @@ namespace lqk {
 
 constexpr int ADJ_ERR_NOT_PD = -2;
 
-// [[A, 0], [0, 1]]: the dynamics without their offset.
-LQK_DEV Tile load_A_noc(const ProbPtrs &P, const InstDesc &d, int k)
-{
-    const int n = d.n;
-    Tile t = gload_rm(P.A + d.oA + (int64_t)k * n * n, n, n, n);
-    const int c = tcol();
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (trow(r) == n && c == n) t.v[r] = 1.0;
-    return t;
-}
-
-// Backward map Y~_k = [[F_k', h_k], [0, 1]].
-template <int NK, int PR>
-LQK_DEV Tile back_map(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k, double *s0, double *s1)
-{
-    const int n = d.n, m = d.m;
-    const Tile Gh = load_Gh(J.G, J.g, d, k);
-    const Tile F = mmak<1, PR, false, false>(load_Bh(P, d, k), Gh, load_A_noc(P, d, k), s0, s1);
-    Tile Ft = ttrans(F, s0);
-    const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
-    const Tile H = mmk<1, PR, true, false>(Gh, GU, s0, s1);  // column n: Gamma' gu (rows < n)
-    const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
-    const int c = tcol();
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = trow(r);
-        if (i == n)
-            Ft.v[r] = (c == n) ? 1.0 : 0.0;
-        else if (c == n)
-            Ft.v[r] = (i < n) ? GX.v[r] + H.v[r] : 0.0;
-    }
-    return Ft;
-}
-
-// Segment fold of the backward maps: Psi_s = Y~_{k0} ... Y~_{k1-1}; the block
-// of the last segment also writes the terminal vector map [[0, gx_T], [0, 1]].
+// Segment fold of the backward maps, Psi_s = Y~_{k0} ... Y~_{k1-1}, kept as
+// Psi' (Psi' <- Y~_k' Psi' is a register product); the block of the last
+// segment also writes the terminal vector map [[0, gx_T], [0, 1]].
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       double *__restrict__ Y)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
+    __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n = d.n, m = d.m;
     if (s == d.nseg - 1)
-        gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * d.n, d.n, d.n, d.n));
+        gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * n, n, n, n));
     if (s == 0) return;   // never read: segment s starts from entry s + 1
-    Tile Psi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Psi = mmk<NK, PR, false, false>(Psi, back_map<NK, PR>(P, J, d, k, s0, s1), s0, s1);
-    gstore(Y + (int64_t)(d.xbase + s) * TILE, Psi);
+    Tile PsiT = tident(n + 1);
+    for (int k = k0; k < k1; ++k) {
+        // R(Y~_k) = A_noc~' + Gamma_0~'(B~' + [gu in column n]) + [gx in column n]
+        const Tile AnT = load_AhT(P, d, k, false);
+        const Tile G0 = load_Gh(J.G, nullptr, d, k);
+        const Tile BhT = load_BhT(P, d, k);
+        const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
+        const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
+        const Tile Yk = tna<1, PR>(G0, tadd(BhT, GU), tadd(AnT, GX));
+        PsiT = tnz<NK, PR>(Yk, PsiT);   // (Psi Y~_k)' = Y~_k' Psi'
+    }
+    gstore(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds));
 }
 
 // Inside each segment, from s~ at its right end: s~_k and gamma~_k.
+//   s~_k = F_k' s~_{k+1} + gx_k + Gamma_k' gu_k,
+//   gamma~_k = -(R_k + B~'S~_{k+1}B~)^{-1} (gu_k + B~' s~_{k+1}).
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                        const int32_t *__restrict__ seg_start, int batch,
                                                        const double *__restrict__ Yfin, int32_t *status)
 {
-    __shared__ double lds[3 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -93,30 +68,47 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     Tile SV = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);   // [[0, s~_{k1}], [0, 1]]
     if (s == d.nseg - 1) store_vec(J.st + d.os + (int64_t)d.T * n, SV, n, n);
     int code = 0, fk = 0;
+    // stage data of stage k-1 is loaded while stage k is processed
+    Tile nB = load_Bh(P, d, k1 - 1), nBT = load_BhT(P, d, k1 - 1), nS = load_Sh(J.S, J.s, d, k1);
+    Tile nR = load_R(P, d, k1 - 1), nA = load_Ah(P, d, k1 - 1, false), nG = load_Gh(J.G, nullptr, d, k1 - 1);
+    Tile nGU = load_vec(J.gu + d.og + (int64_t)(k1 - 1) * m, m, n, -1);
+    Tile nGX = load_vec(J.gx + d.os + (int64_t)(k1 - 1) * n, n, n, -1);
     for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Bh = load_Bh(P, d, k);
-        const Tile SB = mmk<NK, PR, false, false>(load_Sh(J.S, J.s, d, k + 1), Bh, s0, s1);
-        const Tile Quu = mmak<NK, PR, true, false>(Bh, SB, load_R(P, d, k), s0, s1);
-        Tile Qi;
-        if (!spd_inverse(Quu, m, Qi, s2) && !code) {
+        const Tile Bh = nB, BhT = nBT, Sh = nS, Rk = nR, An = nA, G0 = nG, GU = nGU, GX = nGX;
+        if (k > k0) {
+            nB = load_Bh(P, d, k - 1);
+            nBT = load_BhT(P, d, k - 1);
+            nS = load_Sh(J.S, J.s, d, k);
+            nR = load_R(P, d, k - 1);
+            nA = load_Ah(P, d, k - 1, false);
+            nG = load_Gh(J.G, nullptr, d, k - 1);
+            nGU = load_vec(J.gu + d.og + (int64_t)(k - 1) * m, m, n, -1);
+            nGX = load_vec(J.gx + d.os + (int64_t)(k - 1) * n, n, n, -1);
+        }
+        const Tile SB = tnz<NK, PR>(Sh, Bh);                 // S~_{k+1} B~
+        const Tile Quu = tna<NK, PR>(Bh, SB, Rk);            // R + B~'S~B~
+        Tile QiT;
+        if (!spd_inverse_t(Quu, m, QiT) && !code) {
             code = ADJ_ERR_NOT_PD;
             fk = k;
         }
-        const Tile BS = mmak<NK, PR, true, false>(Bh, SV, load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1), s0, s1);
-        Tile Gt = mmk<1, PR, false, false>(Qi, BS, s0, s1);
+        const Tile BS = tna<NK, PR>(Bh, SV, GU);             // gu + B~'s~_{k+1}
+        Tile Gt = tnz<1, PR>(QiT, BS);
         Gt.v = -Gt.v;
         store_vec(J.gt + d.og + (int64_t)k * m, Gt, m, n);
-        SV = mmk<NK, PR, false, false>(back_map<NK, PR>(P, J, d, k, s0, s1), SV, s0, s1);
+        // F~ = A_noc~ + B~ Gamma_0~;  s~_k = F~'s~_{k+1} + gx + Gamma_0~'gu
+        const Tile F = tna<1, PR>(BhT, G0, An);
+        SV = tna<NK, PR>(F, SV, tna<1, PR>(G0, GU, GX));
         store_vec(J.st + d.os + (int64_t)k * n, SV, n, n);
     }
     if (code) report(status, i, code, fk);
 }
 
-// Closed-loop map of the derivative: [[A + B Gamma, B gamma~], [0, 1]].
+// R(F~') of the derivative's closed-loop map F~ = [[A + B Gamma, B gamma~], [0, 1]].
 template <int PR>
-LQK_DEV Tile fwd_map(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k, double *s0, double *s1)
+LQK_DEV Tile fwd_map_t(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k)
 {
-    return mmak<1, PR, false, false>(load_Bh(P, d, k), load_Gh(J.G, J.gt, d, k), load_A_noc(P, d, k), s0, s1);
+    return tna<1, PR>(load_Gh(J.G, J.gt, d, k), load_BhT(P, d, k), load_AhT(P, d, k, false));
 }
 
 template <int NK, int PR>
@@ -124,8 +116,6 @@ __global__ __launch_bounds__(64) void k_adj_fwd_fold(ProbPtrs P, AdjPtrs J, cons
                                                      const int32_t *__restrict__ seg_start, int batch,
                                                      double *__restrict__ Y)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -134,16 +124,13 @@ __global__ __launch_bounds__(64) void k_adj_fwd_fold(ProbPtrs P, AdjPtrs J, cons
     if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(nullptr, d.n, d.n, d.n));   // dx_0 = 0
     if (s == d.nseg - 1) return;   // never read: segment s starts from entry s
     Tile Phi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Phi = mmk<NK, PR, false, false>(fwd_map<PR>(P, J, d, k, s0, s1), Phi, s0, s1);
+    Tile nF = fwd_map_t<PR>(P, J, d, k0);
+    for (int k = k0; k < k1; ++k) {
+        const Tile FT = nF;
+        if (k + 1 < k1) nF = fwd_map_t<PR>(P, J, d, k + 1);
+        Phi = tnz<NK, PR>(FT, Phi);
+    }
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
-}
-
-// Outer product a b' of two vectors held in column `col`, rows from a, columns from b.
-LQK_DEV Tile outer(const d4 &ar, double bc)
-{
-    Tile o;
-    o.v = ar * bc;
-    return o;
 }
 
 template <int NK, int PR>
@@ -152,8 +139,6 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Yfin)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -161,19 +146,26 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
     Tile DX = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, dx_k0], [0, 1]]
-    if (s == 0 && Gr.x0) {
-        const Tile DL0 = mmk<NK, PR, false, false>(load_Sh(J.S, J.st, d, 0), DX, s0, s1);
-        store_vec(Gr.x0 + d.on, DL0, n, n);
-    }
+    if (s == 0 && Gr.x0) store_vec(Gr.x0 + d.on, tnz<NK, PR>(load_Sh(J.S, J.st, d, 0), DX), n, n);
+    // stage data of stage k+1 is loaded while stage k is processed
+    Tile nGT = load_GhT(J.G, J.gt, d, k0), nBT = load_BhT(P, d, k0), nAT = load_AhT(P, d, k0, false);
+    Tile nS = load_Sh(J.S, J.st, d, k0 + 1);
+    Tile nX = load_vec(J.x + d.os + (int64_t)k0 * n, n, n, -1), nU = load_vec(J.u + d.og + (int64_t)k0 * m, m, n, -1);
+    Tile nL = load_vec(J.lam + d.os + (int64_t)(k0 + 1) * n, n, n, -1);
     for (int k = k0; k < k1; ++k) {
-        const Tile Gh = load_Gh(J.G, J.gt, d, k);
-        const Tile Bh = load_Bh(P, d, k);
-        const Tile DU = mmk<NK, PR, false, false>(Gh, DX, s0, s1);
-        const Tile DXn = mmak<1, PR, false, false>(Bh, DU, mmk<NK, PR, false, false>(load_A_noc(P, d, k), DX, s0, s1), s0, s1);
-        const Tile DL1 = mmk<NK, PR, false, false>(load_Sh(J.S, J.st, d, k + 1), DXn, s0, s1);
-        const Tile X = load_vec(J.x + d.os + (int64_t)k * n, n, n, -1);
-        const Tile U = load_vec(J.u + d.og + (int64_t)k * m, m, n, -1);
-        const Tile L1 = load_vec(J.lam + d.os + (int64_t)(k + 1) * n, n, n, -1);
+        const Tile GhT = nGT, BhT = nBT, AnT = nAT, S1 = nS, X = nX, U = nU, L1 = nL;
+        if (k + 1 < k1) {
+            nGT = load_GhT(J.G, J.gt, d, k + 1);
+            nBT = load_BhT(P, d, k + 1);
+            nAT = load_AhT(P, d, k + 1, false);
+            nS = load_Sh(J.S, J.st, d, k + 2);
+            nX = load_vec(J.x + d.os + (int64_t)(k + 1) * n, n, n, -1);
+            nU = load_vec(J.u + d.og + (int64_t)(k + 1) * m, m, n, -1);
+            nL = load_vec(J.lam + d.os + (int64_t)(k + 2) * n, n, n, -1);
+        }
+        const Tile DU = tnz<NK, PR>(GhT, DX);                          // Gamma dx + gamma~
+        const Tile DXn = tna<1, PR>(BhT, DU, tnz<NK, PR>(AnT, DX));    // A dx + B du
+        const Tile DL1 = tnz<NK, PR>(S1, DXn);                         // S dx' + s~'
         const d4 dx_r = vrows(DX, n), x_r = vrows(X, n), du_r = vrows(DU, n), u_r = vrows(U, n);
         const d4 l1_r = vrows(L1, n), dl1_r = vrows(DL1, n);
         const double dx_c = vcol(DX, n), x_c = vcol(X, n), du_c = vcol(DU, n), u_c = vcol(U, n);

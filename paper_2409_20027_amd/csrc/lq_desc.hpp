@@ -93,12 +93,12 @@ LQK_DEV int find_inst64(const int64_t *start, int batch, int64_t g)
 // Homogeneous stage tiles (n1 = n + 1; the extra coordinate is the constant 1)
 // ---------------------------------------------------------------------------
 
-// A~ = [[A, c], [0, 1]]
-LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k)
+// A~ = [[A, c], [0, 1]]; with_c = false drops the offset: [[A, 0], [0, 1]].
+LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k, bool with_c = true)
 {
     const int n = d.n, c = tcol();
     const double *A = P.A + d.oA + (int64_t)k * n * n;
-    const double *cc = P.c ? P.c + d.oc + (int64_t)k * n : nullptr;
+    const double *cc = (with_c && P.c) ? P.c + d.oc + (int64_t)k * n : nullptr;
     Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -113,6 +113,34 @@ LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k)
         t.v[r] = *a;
     }
     return t;
+}
+
+// A~' = [[A', 0], [c', 1]]; with_c = false drops the offset: [[A', 0], [0, 1]].
+LQK_DEV Tile load_AhT(const ProbPtrs &P, const InstDesc &d, int k, bool with_c = true)
+{
+    const int n = d.n, c = tcol();
+    const double *A = P.A + d.oA + (int64_t)k * n * n;
+    const double *cc = (with_c && P.c) ? P.c + d.oc + (int64_t)k * n : nullptr;
+    Tile t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double *a = zptr();
+        if (i < n && c < n)
+            a = A + c * n + i;
+        else if (i == n && c < n && cc)
+            a = cc + c;
+        else if (i == n && c == n)
+            a = optr();
+        t.v[r] = *a;
+    }
+    return t;
+}
+
+// B~' = [B', 0]   (m x (n+1))
+LQK_DEV Tile load_BhT(const ProbPtrs &P, const InstDesc &d, int k)
+{
+    return gload_rm_t(P.B + d.oB + (int64_t)k * d.n * d.m, d.m, d.n, d.m);
 }
 
 // B~ = [[B], [0]]   ((n+1) x m)
@@ -198,12 +226,13 @@ LQK_DEV Tile corner(int n)
     return t;
 }
 
-// Gamma~ = [Gamma, gamma]   (m x (n+1)) from the control-law outputs.
+// Gamma~ = [Gamma, gamma]   (m x (n+1)) from the control-law outputs
+// (gam = nullptr: [Gamma, 0]).
 LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, int k)
 {
     const int n = d.n, m = d.m, c = tcol();
     const double *G = Gam + d.oG + (int64_t)k * m * n;
-    const double *gg = gam + d.og + (int64_t)k * m;
+    const double *gg = gam ? gam + d.og + (int64_t)k * m : nullptr;
     Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -211,8 +240,28 @@ LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, in
         const double *p = zptr();
         if (a < m && c < n)
             p = G + a * n + c;
-        else if (a < m && c == n)
+        else if (a < m && c == n && gg)
             p = gg + a;
+        t.v[r] = *p;
+    }
+    return t;
+}
+
+// Gamma~' = [[Gamma'], [gamma']]   ((n+1) x m)
+LQK_DEV Tile load_GhT(const double *Gam, const double *gam, const InstDesc &d, int k)
+{
+    const int n = d.n, m = d.m, c = tcol();
+    const double *G = Gam + d.oG + (int64_t)k * m * n;
+    const double *gg = gam ? gam + d.og + (int64_t)k * m : nullptr;
+    Tile t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double *p = zptr();
+        if (c < m && i < n)
+            p = G + c * n + i;
+        else if (c < m && i == n && gg)
+            p = gg + c;
         t.v[r] = *p;
     }
     return t;

@@ -127,35 +127,63 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
     }
 }
 
-// Co-state map [[A_k', g_k], [0, 1]] from the linearisation.
-LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k, double *s0)
+// Co-state map M_k = [[A_k', g_k], [0, 1]] from the linearisation: R(M_k).
+LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k)
 {
-    const int n = d.n;
-    Tile t = gload_rm_t(Wk.A + (int64_t)k * n * n, n, n, n);   // A_k'
-    const Tile gv = load_vec(Wk.g + (int64_t)k * n, n, n, n);
-    const int c = tcol();
+    const int n = d.n, c = tcol();
+    const double *A = Wk.A + (int64_t)k * n * n, *g = Wk.g + (int64_t)k * n;
+    Tile t;
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (c == n) t.v[r] = gv.v[r];
-    (void)s0;
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double *p = zptr();
+        if (i < n && c < n)
+            p = A + c * n + i;
+        else if (i < n && c == n)
+            p = g + i;
+        else if (i == n && c == n)
+            p = optr();
+        t.v[r] = *p;
+    }
     return t;
 }
 
-// Step 2a: segment fold of the co-state maps (suffix); the block of the last
-// segment writes the terminal element [[0, lambda_T], [0, 1]].
+// R(M_k') = [[A_k, 0], [g_k', 1]].
+LQK_DEV Tile costate_map_t(const NmpcWork &Wk, const InstDesc &d, int k)
+{
+    const int n = d.n, c = tcol();
+    const double *A = Wk.A + (int64_t)k * n * n, *g = Wk.g + (int64_t)k * n;
+    Tile t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double *p = zptr();
+        if (i < n && c < n)
+            p = A + i * n + c;
+        else if (i == n && c < n)
+            p = g + c;
+        else if (i == n && c == n)
+            p = optr();
+        t.v[r] = *p;
+    }
+    return t;
+}
+
+// Step 2a: segment fold of the co-state maps (suffix), Psi_s = M_{k0} ...
+// M_{k1-1} kept as Psi'; the block of the last segment writes the terminal
+// element [[0, lambda_T], [0, 1]].
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst, double *Y)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
+    __shared__ double lds[SLOT];
     const InstDesc d = inst[0];
     const int s = blockIdx.x;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT, d.n, d.n, d.n));
     if (s == 0) return;
-    Tile Psi = tident(d.n + 1);
-    for (int k = k0; k < k1; ++k) Psi = mmk<NK, PR, false, false>(Psi, costate_map(Wk, d, k, s0), s0, s1);
-    gstore(Y + (int64_t)(d.xbase + s) * TILE, Psi);
+    Tile PsiT = tident(d.n + 1);
+    for (int k = k0; k < k1; ++k) PsiT = tnz<NK, PR>(costate_map(Wk, d, k), PsiT);   // (Psi M_k)'
+    gstore(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds));
 }
 
 // Step 2c: co-states inside each segment from lambda at its right end.
@@ -163,8 +191,6 @@ template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDesc *__restrict__ inst,
                                                       const double *__restrict__ Yfin)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
     const InstDesc d = inst[0];
     const int s = blockIdx.x;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
@@ -172,7 +198,7 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
     Tile L = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);
     if (s == d.nseg - 1) store_vec(Wk.lam + (int64_t)d.T * n, L, n, n);
     for (int k = k1 - 1; k >= k0; --k) {
-        L = mmk<NK, PR, false, false>(costate_map(Wk, d, k, s0), L, s0, s1);
+        L = tnz<NK, PR>(costate_map_t(Wk, d, k), L);   // M_k L
         store_vec(Wk.lam + (int64_t)k * n, L, n, n);
     }
 }

@@ -18,15 +18,11 @@
 
 namespace lqk {
 
-// Closed-loop map F~ = A~ + B~ Gamma~.
+// R(F~') of the closed-loop map F~ = A~ + B~ Gamma~:  A~' + Gamma~' B~'.
 template <int PR>
-LQK_DEV Tile closed_loop(const ProbPtrs &P, const ValPtrs &V, const InstDesc &d, int k, double *s0,
-                         double *s1)
+LQK_DEV Tile closed_loop_t(const Tile &AhT, const Tile &Gh, const Tile &BhT)
 {
-    const Tile Ah = load_Ah(P, d, k);
-    const Tile Bh = load_Bh(P, d, k);
-    const Tile Gh = load_Gh(V.G, V.g, d, k);
-    return mmak<1, PR, false, false>(Bh, Gh, Ah, s0, s1);
+    return tna<1, PR>(Gh, BhT, AhT);
 }
 
 template <int NK, int PR>
@@ -34,8 +30,6 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
                                                   const int32_t *__restrict__ seg_start, int batch,
                                                   double *__restrict__ Y)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -46,9 +40,16 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     // scanned entry s.
     if (s == d.nseg - 1) return;
     Tile Phi = tident(d.n + 1);
+    // stage data of stage k+1 is loaded while stage k is folded
+    Tile nA = load_AhT(P, d, k0), nG = load_Gh(V.G, V.g, d, k0), nB = load_BhT(P, d, k0);
     for (int k = k0; k < k1; ++k) {
-        const Tile F = closed_loop<PR>(P, V, d, k, s0, s1);
-        Phi = mmk<NK, PR, false, false>(F, Phi, s0, s1);
+        const Tile AhT = nA, Gh = nG, BhT = nB;
+        if (k + 1 < k1) {
+            nA = load_AhT(P, d, k + 1);
+            nG = load_Gh(V.G, V.g, d, k + 1);
+            nB = load_BhT(P, d, k + 1);
+        }
+        Phi = tnz<NK, PR>(closed_loop_t<PR>(AhT, Gh, BhT), Phi);   // F~ Phi
     }
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
@@ -63,7 +64,7 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
                                                   int suffix, const double *__restrict__ Yin,
                                                   double *__restrict__ Yout)
 {
-    __shared__ double lds[2 * SLOT];
+    __shared__ double lds[SLOT];
     const int gx = blockIdx.x;
     const int i = find_inst(x_start, batch, gx);
     const InstDesc d = inst[i];
@@ -77,17 +78,17 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     }
     const int64_t ob = suffix ? gx + dd : gx - dd;
     const Tile b = gload(Yin + ob * TILE);
-    gstore(Yout + (int64_t)gx * TILE, mmk<NK, PR, false, false>(a, b, lds, lds + SLOT));
+    gstore(Yout + (int64_t)gx * TILE, tnz<NK, PR>(ttrans(a, lds), b));
 }
 
+// From the state at the segment start: u_k = Gamma~ x~, lambda_k = S~_k x~,
+// x~_{k+1} = A~ x~ + B~ u_k (x~ = [x; 1] in the last column of X).
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ Yfin, double *__restrict__ x,
                                                    double *__restrict__ u, double *__restrict__ lam)
 {
-    __shared__ double lds[2 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -96,28 +97,25 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     const int n = d.n, m = d.m;
     Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
     // stage data of stage k+1 is loaded while stage k is processed
-    Tile nGh = load_Gh(V.G, V.g, d, k0), nAh = load_Ah(P, d, k0), nBh = load_Bh(P, d, k0);
-    Tile nSh = lam ? load_Sh(V.S, V.s, d, k0) : tzero();
+    Tile nG = load_GhT(V.G, V.g, d, k0), nA = load_AhT(P, d, k0), nB = load_BhT(P, d, k0);
+    Tile nS = lam ? load_Sh(V.S, V.s, d, k0) : tzero();
     for (int k = k0; k < k1; ++k) {
-        const Tile Gh = nGh, Ah = nAh, Bh = nBh, Sh = nSh;
+        const Tile GhT = nG, AhT = nA, BhT = nB, Sh = nS;
         if (k + 1 < k1) {
-            nGh = load_Gh(V.G, V.g, d, k + 1);
-            nAh = load_Ah(P, d, k + 1);
-            nBh = load_Bh(P, d, k + 1);
-            if (lam) nSh = load_Sh(V.S, V.s, d, k + 1);
+            nG = load_GhT(V.G, V.g, d, k + 1);
+            nA = load_AhT(P, d, k + 1);
+            nB = load_BhT(P, d, k + 1);
+            if (lam) nS = load_Sh(V.S, V.s, d, k + 1);
         }
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
-        const Tile U = mmk<NK, PR, false, false>(Gh, X, s0, s1);
-        store_vec(u + d.og + (int64_t)k * m, U, m, n);
-        if (lam) store_vec(lam + d.os + (int64_t)k * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
-        X = mmak<1, PR, false, false>(Bh, U, mmk<NK, PR, false, false>(Ah, X, s0, s1), s0, s1);
+        const Tile Uk = tnz<NK, PR>(GhT, X);                       // Gamma~ x~
+        store_vec(u + d.og + (int64_t)k * m, Uk, m, n);
+        if (lam) store_vec(lam + d.os + (int64_t)k * n, tnz<NK, PR>(Sh, X), n, n);
+        X = tna<1, PR>(BhT, Uk, tnz<NK, PR>(AhT, X));              // A~ x~ + B~ u
     }
     if (k1 == d.T) {
         store_vec(x + d.os + (int64_t)d.T * n, X, n, n);
-        if (lam) {
-            const Tile Sh = load_Sh(V.S, V.s, d, d.T);
-            store_vec(lam + d.os + (int64_t)d.T * n, mmk<NK, PR, false, false>(Sh, X, s0, s1), n, n);
-        }
+        if (lam) store_vec(lam + d.os + (int64_t)d.T * n, tnz<NK, PR>(load_Sh(V.S, V.s, d, d.T), X), n, n);
     }
 }
 

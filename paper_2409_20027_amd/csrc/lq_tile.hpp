@@ -1,13 +1,17 @@
 // lq_tile.hpp -- wave-level 16x16 FP64 tile algebra for gfx950.
 //
-// One wave64 owns one tile.  The register layout is the accumulator layout of
-// the FP64 16x16x4 matrix instruction on gfx950: lane l holds rows
-// 4*r + l/16, r = 0..3, of column l%16 (rows interleaved across the four
-// 16-lane groups; measured with one-hot operands).  The A operand of the
-// instruction is A[l%16][l/16] and the B operand B[l/16][l%16].  Products stage both operands through a
-// wave-private LDS slot (row-major, padded row stride of 17 doubles so that
-// column reads do not collide on the same banks) and issue ceil(K/4) matrix
-// instructions, K being the contraction length actually needed.
+// One wave64 owns one tile.  The register layout R(X) of a tile X is the
+// accumulator layout of the FP64 16x16x4 matrix instruction on gfx950: lane l
+// holds rows 4*r + l/16, r = 0..3, of column l%16 in its register r (rows
+// interleaved across the four 16-lane groups; measured with one-hot operands).
+// The instruction takes its A operand as A[l%16][l/16] and its B operand as
+// B[l/16][l%16], so for the K-slice s of a product P'Q the A operand is
+// register s of R(P) and the B operand register s of R(Q): P'Q is formed
+// straight from registers (tn below), with no data movement.  Every product of
+// the solver is written as P'Q of tiles held in the right form (a matrix, or
+// its transpose, loaded transposed from memory or kept transposed across a
+// recursion); the few remaining transposes and symmetrisations go through a
+// wave-private LDS slot (row stride 17 doubles).
 //
 // Every small dense object of the solver (an (n+1)x(n+1) homogeneous matrix,
 // an (n+1)xm factor, an mxm block) is a zero-padded tile, so n <= 15 and
@@ -173,47 +177,24 @@ LQK_DEV Tile sget_t(const double *s)
 // 4r + g): feed row pi4(a) of the A operand as its row a.
 LQK_DEV int pi4(int a) { return 4 * (a & 3) + (a >> 2); }
 
-// Stage a tile for products of precision PR (0: FP64, 1: FP32 operands).
-template <int PR>
-LQK_DEV void sputp(double *s, const Tile &t)
-{
-    if constexpr (PR == 0) {
-        sput(s, t);
-    } else {
-        float *f = reinterpret_cast<float *>(s);
-        const int c = tcol();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) f[trow(r) * LD + c] = (float)t.v[r];
-    }
-}
-
-// acc + op(X) op(Y) over contraction length 4*KS, operands already staged.
+// acc + P'Q over the contraction length 4*KS, both operands from registers.
 // PR = 0: FP64 products and accumulation.  PR = 1: FP32 products accumulated
-// in FP32, the result added to the FP64 accumulator in FP64.
-template <int KS, int PR, bool TX, bool TY>
-LQK_DEV d4 mfma_k(const double *sx, const double *sy, d4 acc)
+// in FP32 (the A operand rows permuted by pi4 with one lane shuffle per
+// slice), the result added to the FP64 accumulator in FP64.
+template <int KS, int PR>
+LQK_DEV d4 tn(const Tile &P, const Tile &Q, d4 acc)
 {
-    const int c = tcol(), g = tgrp();
     if constexpr (PR == 0) {
 #pragma unroll
-        for (int k = 0; k < KS; ++k) {
-            const int kk = 4 * k + g;
-            const double a = TX ? sx[kk * LD + c] : sx[c * LD + kk];
-            const double b = TY ? sy[c * LD + kk] : sy[kk * LD + c];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
+        for (int k = 0; k < KS; ++k) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(P.v[k], Q.v[k], acc, 0, 0, 0);
         return acc;
     } else {
-        const float *fx = reinterpret_cast<const float *>(sx);
-        const float *fy = reinterpret_cast<const float *>(sy);
-        const int pc = pi4(c);
+        const int src = pi4(tcol()) + 16 * tgrp();
         f4 a4 = (f4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const int kk = 4 * k + g;
-            const float a = TX ? fx[kk * LD + pc] : fx[pc * LD + kk];
-            const float b = TY ? fy[c * LD + kk] : fy[kk * LD + c];
-            a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, a4, 0, 0, 0);
+            const float a = __shfl((float)P.v[k], src);
+            a4 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, (float)Q.v[k], a4, 0, 0, 0);
         }
         d4 o;
 #pragma unroll
@@ -221,72 +202,21 @@ LQK_DEV d4 mfma_k(const double *sx, const double *sy, d4 acc)
         return o;
     }
 }
-
-// Same with a run-time slice count (small auxiliary products only).
-template <bool TX, bool TY>
-LQK_DEV d4 mfma_staged(const double *sx, const double *sy, int ks, d4 acc)
+// P'Q
+template <int KS, int PR>
+LQK_DEV Tile tnz(const Tile &P, const Tile &Q)
 {
-    const int c = tcol(), g = tgrp();
-    for (int k = 0; k < ks; ++k) {
-        const int kk = 4 * k + g;
-        const double a = TX ? sx[kk * LD + c] : sx[c * LD + kk];
-        const double b = TY ? sy[c * LD + kk] : sy[kk * LD + c];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-    }
-    return acc;
+    Tile t;
+    t.v = tn<KS, PR>(P, Q, (d4){0.0, 0.0, 0.0, 0.0});
+    return t;
 }
-
-// Contraction slices for a contraction length K.
-LQK_DEV int kslices(int K) { return (K + 3) >> 2; }
-
-// D = op(X) op(Y) (+ acc).  Stages X into sx and Y into sy (two slots).
-template <bool TX, bool TY>
-LQK_DEV Tile mm(const Tile &X, const Tile &Y, int K, double *sx, double *sy)
+// acc + P'Q
+template <int KS, int PR>
+LQK_DEV Tile tna(const Tile &P, const Tile &Q, const Tile &acc)
 {
-    wsync();
-    sput(sx, X);
-    sput(sy, Y);
-    wsync();
-    Tile d;
-    d.v = mfma_staged<TX, TY>(sx, sy, kslices(K), (d4){0.0, 0.0, 0.0, 0.0});
-    wsync();
-    return d;
-}
-template <bool TX, bool TY>
-LQK_DEV Tile mma(const Tile &X, const Tile &Y, const Tile &acc, int K, double *sx, double *sy)
-{
-    wsync();
-    sput(sx, X);
-    sput(sy, Y);
-    wsync();
-    Tile d;
-    d.v = mfma_staged<TX, TY>(sx, sy, kslices(K), acc.v);
-    wsync();
-    return d;
-}
-
-// Compile-time slice-count versions of mm / mma.
-template <int KS, int PR, bool TX, bool TY>
-LQK_DEV Tile mmk(const Tile &X, const Tile &Y, double *sx, double *sy)
-{
-    wsync();
-    sputp<PR>(sx, X);
-    sputp<PR>(sy, Y);
-    wsync();
-    Tile d;
-    d.v = mfma_k<KS, PR, TX, TY>(sx, sy, (d4){0.0, 0.0, 0.0, 0.0});
-    return d;
-}
-template <int KS, int PR, bool TX, bool TY>
-LQK_DEV Tile mmak(const Tile &X, const Tile &Y, const Tile &acc, double *sx, double *sy)
-{
-    wsync();
-    sputp<PR>(sx, X);
-    sputp<PR>(sy, Y);
-    wsync();
-    Tile d;
-    d.v = mfma_k<KS, PR, TX, TY>(sx, sy, acc.v);
-    return d;
+    Tile t;
+    t.v = tn<KS, PR>(P, Q, acc.v);
+    return t;
 }
 
 // A vector v held in column `col` of a tile (v[i] in lane col + 16*(i%4),
@@ -332,140 +262,216 @@ LQK_DEV Tile ttrans(const Tile &X, double *s)
     return t;
 }
 
-// Inverse of the leading n1 x n1 block (zero elsewhere) by in-place
-// Gauss-Jordan elimination with partial (row) pivoting; the column order is
-// restored at the end.  Returns false if a pivot is zero or not finite.
-LQK_DEV bool gj_inverse(Tile &X, int n1, double *s)
+// ---------------------------------------------------------------------------
+// Cross-lane helpers.
+// ---------------------------------------------------------------------------
+
+// x of lane l (l uniform), on every lane.
+LQK_DEV double rlane(double x, int l)
 {
-    const int l = lane(), c = tcol(), g = tgrp();
-    wsync();
-    sput(s, X);
-    wsync();
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// x of lane P of this lane's 16-lane row (DPP row broadcast).
+template <int P>
+LQK_DEV double rowbcast(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x150 + P, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x150 + P, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Register r of a tile for a uniform run-time r.
+LQK_DEV double treg(const d4 &v, int r) { return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3])); }
+
+// ---------------------------------------------------------------------------
+// Gauss-Jordan inverse of the leading n1 x n1 block, in registers.
+//
+// In-place elimination with partial (row) pivoting: for pivot p the largest
+// |X[i][p]|, i >= p, is found over the four lanes holding column p, rows p and
+// piv are exchanged through two lane shuffles, column p reaches every lane of
+// its row by a DPP row broadcast, and the update is one FMA per register.  The
+// row exchanges turn into a column permutation of the result, undone at the
+// end by one gather.  Rows and columns >= n1 stay zero.  Returns false if a
+// pivot is zero or not finite.
+// ---------------------------------------------------------------------------
+template <int P>
+LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
+{
+    const int c = tcol(), g = tgrp();
+    double best = -1.0;
+    int bi = P;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + g;
+        const double a = fabs(v[r]);
+        if (c == P && i >= P && i < n1 && a > best) {
+            best = a;
+            bi = i;
+        }
+    }
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    const int piv = __builtin_amdgcn_readlane(bi, P);
+    const double pmax = rlane(best, P);
+    ok = ok && (pmax > 0.0) && (pmax < INFINITY);
+    constexpr int gp = P & 3, rp = P >> 2;
+    const int gq = piv & 3, rq = piv >> 2;
+    const double rowP = __shfl(v[rp], c + 16 * gp);
+    const double rowQ = __shfl(treg(v, rq), c + 16 * gq);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (g == gq && r == rq) v[r] = rowP;
+    if (g == gp) v[rp] = rowQ;
+    const double pinv = 1.0 / rlane(rowQ, P);
+    const double prow = (c == P) ? pinv : rowQ * pinv;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const double cp = rowbcast<P>(v[r]);
+        const int i = 4 * r + g;
+        v[r] = (i == P) ? prow : ((c == P) ? -cp * pinv : fma(-cp, prow, v[r]));
+    }
+    piv_out = piv;
+}
+
+template <int P, int PMAX>
+LQK_DEV void gj_steps(d4 &v, int n1, bool &ok, int *perm)
+{
+    if constexpr (P < PMAX) {
+        if (P < n1) {
+            gj_step<P>(v, n1, ok, perm[P]);
+            gj_steps<P + 1, PMAX>(v, n1, ok, perm);
+        }
+    }
+}
+
+// Inverse of the leading n1 x n1 block of X (n1 <= 4 * NK), zero elsewhere.
+template <int NK>
+LQK_DEV bool gj_inverse(Tile &X, int n1)
+{
     bool ok = true;
-    int perm = 0;
-    for (int p = 0; p < n1; ++p) {
-        double v = (l >= p && l < n1) ? fabs(s[l * LD + p]) : -1.0;
-        int idx = l;
+    int perm[4 * NK];
 #pragma unroll
-        for (int off = 8; off >= 1; off >>= 1) {
-            const double ov = __shfl_xor(v, off, 16);
-            const int oi = __shfl_xor(idx, off, 16);
-            if (ov > v || (ov == v && oi < idx)) {
-                v = ov;
-                idx = oi;
-            }
-        }
-        const int piv = __shfl(idx, 0);
-        const double pmax = __shfl(v, 0);
-        ok = ok && (pmax > 0.0) && (pmax < INFINITY);
-        if (l == p) perm = piv;
-        if (piv != p && l < TE) {
-            const double a = s[p * LD + l], b = s[piv * LD + l];
-            s[p * LD + l] = b;
-            s[piv * LD + l] = a;
-        }
-        wsync();
-        const double pinv = 1.0 / s[p * LD + p];
-        const double rowp = s[p * LD + c] * pinv;
-        double colp[4], cur[4];
+    for (int p = 0; p < 4 * NK; ++p) perm[p] = p;
+    gj_steps<0, 4 * NK>(X.v, n1, ok, perm);
+    // result column j is column src(j) of the eliminated matrix, src being the
+    // composition of the row exchanges taken in order
+    int x = tcol();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            colp[r] = s[trow(r) * LD + p];
-            cur[r] = s[trow(r) * LD + c];
-        }
-        wsync();
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = trow(r);
-            double nv;
-            if (i == p)
-                nv = (c == p) ? pinv : rowp;
-            else
-                nv = (c == p) ? -colp[r] * pinv : cur[r] - colp[r] * rowp;
-            s[i * LD + c] = nv;
-        }
-        wsync();
+    for (int p = 0; p < 4 * NK; ++p) {
+        const int q = perm[p];
+        x = (x == p) ? q : ((x == q) ? p : x);
     }
-    for (int p = n1 - 1; p >= 0; --p) {
-        const int q = __shfl(perm, p);
-        if (q != p && l < TE) {
-            const double a = s[l * LD + p], b = s[l * LD + q];
-            s[l * LD + p] = b;
-            s[l * LD + q] = a;
-        }
-        wsync();
-    }
-    X = sget(s);
-    wsync();
+    const int src = x + 16 * tgrp();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) X.v[r] = __shfl(X.v[r], src);
     return ok;
 }
 
 // ---------------------------------------------------------------------------
-// Per-lane small (m <= MMAX) factorisations.  Every lane reads the whole m x m
-// block and factorises it redundantly in registers; the result goes back into
-// tile layout through lane 0 and the LDS slot.
+// Per-lane small (m <= MMAX) factorisations.  The m x m block of a tile lives
+// in register 0 of lanes j + 16 i; every lane reads all of it (readlane) and
+// factorises it redundantly in registers, and the result goes back into tile
+// layout by a per-lane select.
 // ---------------------------------------------------------------------------
 
-// Read the leading m x m block of a staged slot into a register array,
-// identity-padded to MMAX.
-LQK_DEV void small_read(const double *s, int m, double a[MMAX][MMAX])
+// The leading m x m block of W on every lane, identity-padded to MMAX.
+LQK_DEV void small_from_tile(const Tile &W, int m, double a[MMAX][MMAX])
 {
 #pragma unroll
     for (int i = 0; i < MMAX; ++i)
 #pragma unroll
         for (int j = 0; j < MMAX; ++j) {
-            const double v = s[i * LD + j];  // in the slot for every i, j < MMAX
+            const double v = rlane(W.v[0], j + 16 * i);
             a[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
         }
 }
 
-// In-register Cholesky a = L L' (lower, into a).  False if not PD.
-LQK_DEV bool small_chol(double a[MMAX][MMAX])
+// Tile holding the leading m x m block of a (TR: of a'), zero elsewhere.  The
+// entries are the same on every lane; register 0 of lane j + 16 i takes entry
+// (i, j) by a chain of selects on the lane's row and column (two conditions,
+// so the chain stays in registers instead of becoming an indexed table).
+template <bool TR>
+LQK_DEV Tile small_to_tile(const double a[MMAX][MMAX], int m)
+{
+    const int c = tcol(), g = tgrp();
+    double v = 0.0;
+#pragma unroll
+    for (int i = 0; i < MMAX; ++i)
+#pragma unroll
+        for (int j = 0; j < MMAX; ++j) v = (g == i && c == j) ? (TR ? a[j][i] : a[i][j]) : v;
+    Tile t = tzero();
+    t.v[0] = (c < m && g < m) ? v : 0.0;
+    return t;
+}
+
+// In-register LDL' of a symmetric a (lower triangle used): a <- unit lower L
+// below the diagonal and 1/D on it.  Returns false unless every D_j > 0.
+LQK_DEV bool small_ldl(double a[MMAX][MMAX])
 {
     bool ok = true;
+    double dv[MMAX];
 #pragma unroll
     for (int j = 0; j < MMAX; ++j) {
         double d = a[j][j];
 #pragma unroll
-        for (int p = 0; p < j; ++p) d -= a[j][p] * a[j][p];
+        for (int p = 0; p < j; ++p) d -= a[j][p] * a[j][p] * dv[p];
         ok = ok && (d > 0.0) && (d < INFINITY);
-        const double ljj = sqrt(d > 0.0 ? d : 1.0);
-        a[j][j] = ljj;
-        const double inv = 1.0 / ljj;
+        dv[j] = d;
+        const double dinv = 1.0 / d;
 #pragma unroll
         for (int i = j + 1; i < MMAX; ++i) {
-            double v = a[i][j];
+            double w = a[i][j];
 #pragma unroll
-            for (int p = 0; p < j; ++p) v -= a[i][p] * a[j][p];
-            a[i][j] = v * inv;
+            for (int p = 0; p < j; ++p) w -= a[i][p] * a[j][p] * dv[p];
+            a[i][j] = w * dinv;
         }
-#pragma unroll
-        for (int i = 0; i < j; ++i) a[i][j] = 0.0;
+        a[j][j] = dinv;
     }
     return ok;
 }
 
-// Inverse of a lower-triangular L (in place).
-LQK_DEV void small_tri_inv(double a[MMAX][MMAX])
+// Inverse of a symmetric positive definite a (in place) through LDL'.
+// Returns false if a is not positive definite.
+LQK_DEV bool small_spd_inv(double a[MMAX][MMAX])
 {
-    double li[MMAX][MMAX];
+    const bool ok = small_ldl(a);
+    // Y = L^{-1} (unit lower)
+    double y[MMAX][MMAX];
 #pragma unroll
-    for (int j = 0; j < MMAX; ++j) {
+    for (int j = 0; j < MMAX; ++j)
 #pragma unroll
-        for (int i = 0; i < MMAX; ++i) li[i][j] = 0.0;
-        li[j][j] = 1.0 / a[j][j];
+        for (int i = 0; i < MMAX; ++i) {
+            double v = (i == j) ? 1.0 : 0.0;
+            if (i > j) {
 #pragma unroll
-        for (int i = j + 1; i < MMAX; ++i) {
-            double v = 0.0;
-#pragma unroll
-            for (int p = j; p < i; ++p) v += a[i][p] * li[p][j];
-            li[i][j] = -v / a[i][i];
+                for (int p = j; p < i; ++p) v -= a[i][p] * (p == j ? 1.0 : y[p][j]);
+            }
+            y[i][j] = (i >= j) ? v : 0.0;
         }
-    }
+    // a^{-1} = Y' D^{-1} Y
 #pragma unroll
     for (int i = 0; i < MMAX; ++i)
 #pragma unroll
-        for (int j = 0; j < MMAX; ++j) a[i][j] = li[i][j];
+        for (int j = 0; j <= i; ++j) {
+            double v = 0.0;
+#pragma unroll
+            for (int p = i; p < MMAX; ++p) v += y[p][i] * a[p][p] * y[p][j];
+            a[i][j] = v;
+            a[j][i] = v;
+        }
+    return ok;
 }
 
 // In-register Gauss-Jordan inverse with partial pivoting (general matrix).
@@ -527,80 +533,80 @@ LQK_DEV bool small_gj_inv(double a[MMAX][MMAX])
     return ok;
 }
 
-// Write the leading m x m block of a (registers, identical on every lane) into
-// tile layout (zero elsewhere), through slot s.
-LQK_DEV Tile small_to_tile(const double a[MMAX][MMAX], int m, double *s)
+// R(W^{-1}') for an SPD m x m block W (returned transposed so that
+// tn(result, X) = W^{-1} X).  False if W is not positive definite.
+LQK_DEV bool spd_inverse_t(const Tile &W, int m, Tile &WiT)
 {
-    const int c = tcol();
-    Tile t;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = trow(r);
-        double v = 0.0;
-#pragma unroll
-        for (int ii = 0; ii < MMAX; ++ii)
-#pragma unroll
-            for (int jj = 0; jj < MMAX; ++jj) v = (i == ii && c == jj && ii < m && jj < m) ? a[ii][jj] : v;
-        t.v[r] = v;
-    }
-    (void)s;
-    return t;
+    double a[MMAX][MMAX];
+    small_from_tile(W, m, a);
+    const bool ok = small_spd_inv(a);
+    WiT = small_to_tile<true>(a, m);
+    return ok;
 }
 
-// Inverse of an m x m SPD block through Cholesky (every lane redundantly).
-LQK_DEV bool spd_inverse(const Tile &W, int m, Tile &Winv, double *s)
+// R(W^{-1}') for a general m x m block W: LDL' when W is positive definite
+// (the usual case), pivoted Gauss-Jordan otherwise (a uniform branch: every
+// lane holds the same values).  False if W is singular.
+LQK_DEV bool gen_inverse_t(const Tile &W, int m, Tile &WiT)
 {
-    wsync();
-    sput(s, W);
-    wsync();
-    double a[MMAX][MMAX];
-    small_read(s, m, a);
-    wsync();
-    const bool ok = small_chol(a);
-    small_tri_inv(a);  // a = L^{-1}
-    double w[MMAX][MMAX];
+    double a[MMAX][MMAX], b[MMAX][MMAX];
+    small_from_tile(W, m, a);
+    bool sym = true;
 #pragma unroll
     for (int i = 0; i < MMAX; ++i)
 #pragma unroll
         for (int j = 0; j < MMAX; ++j) {
+            b[i][j] = a[i][j];
+            sym = sym && (a[i][j] == a[j][i]);
+        }
+    bool ok = sym && small_spd_inv(b);
+    if (!ok) {
+#pragma unroll
+        for (int i = 0; i < MMAX; ++i)
+#pragma unroll
+            for (int j = 0; j < MMAX; ++j) b[i][j] = a[i][j];
+        ok = small_gj_inv(b);
+    }
+    WiT = small_to_tile<true>(b, m);
+    return ok;
+}
+
+// L^{-1} of the Cholesky factor of an SPD m x m block given on every lane
+// (identity-padded), in place.  False if not positive definite.
+LQK_DEV bool small_chol_inv(double a[MMAX][MMAX])
+{
+    bool ok = true;
+    double l[MMAX][MMAX];
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) {
+        double d = a[j][j];
+#pragma unroll
+        for (int p = 0; p < j; ++p) d -= l[j][p] * l[j][p];
+        ok = ok && (d > 0.0) && (d < INFINITY);
+        const double ljj = sqrt(d > 0.0 ? d : 1.0);
+        l[j][j] = ljj;
+        const double inv = 1.0 / ljj;
+#pragma unroll
+        for (int i = j + 1; i < MMAX; ++i) {
+            double v = a[i][j];
+#pragma unroll
+            for (int p = 0; p < j; ++p) v -= l[i][p] * l[j][p];
+            l[i][j] = v * inv;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < MMAX; ++j) {
+#pragma unroll
+        for (int i = 0; i < MMAX; ++i) a[i][j] = 0.0;
+        a[j][j] = 1.0 / l[j][j];
+#pragma unroll
+        for (int i = j + 1; i < MMAX; ++i) {
             double v = 0.0;
 #pragma unroll
-            for (int p = 0; p < MMAX; ++p) v += a[p][i] * a[p][j];  // L^{-T} L^{-1}
-            w[i][j] = v;
+            for (int p = j; p < i; ++p) v += l[i][p] * a[p][j];
+            a[i][j] = -v / l[i][i];
         }
-    Winv = small_to_tile(w, m, s);
-    return ok;
-}
-
-// Inverse of a general m x m block (every lane redundantly, pivoted).
-LQK_DEV bool gen_inverse_small(const Tile &W, int m, Tile &Winv, double *s)
-{
-    wsync();
-    sput(s, W);
-    wsync();
-    double a[MMAX][MMAX];
-    small_read(s, m, a);
-    wsync();
-    const bool ok = small_gj_inv(a);
-    Winv = small_to_tile(a, m, s);
-    return ok;
-}
-
-// Lower Cholesky factor inverse L^{-1} of an m x m SPD block held in global
-// memory (row-major, ld = m); every lane redundantly.  Returns false if not PD.
-LQK_DEV bool chol_inv_global(const double *R, int m, double li[MMAX][MMAX])
-{
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j) {
-            // clamped indices keep every load in bounds and unconditional
-            const int ii = i < m ? i : 0, jj = j < m ? j : 0;
-            const double v = R[ii * m + jj];
-            li[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
-        }
-    const bool ok = small_chol(li);
-    small_tri_inv(li);
+    }
     return ok;
 }
 
@@ -622,10 +628,12 @@ LQK_DEV bool chol_inv_global(const double *R, int m, double li[MMAX][MMAX])
         }                            \
     }
 
-// Report the first failure of an instance: status = (-code) | (k << 8).
+// Report a failure of an instance: status = (-code) | (k << 8).  Of several
+// failures the one at the largest stage index is kept (the first one a
+// backward sweep over the stages meets), whatever the order the waves finish in.
 LQK_DEV void report(int32_t *status, int inst, int code, int k)
 {
-    if (status && lane() == 0) atomicCAS(&status[inst], 0, (int32_t)((-code) | (k << 8)));
+    if (status && lane() == 0) atomicMax(&status[inst], (int32_t)((-code) | (k << 8)));
 }
 
 }  // namespace lqk

@@ -14,186 +14,112 @@
 //
 // Segmented scan, three phases per instance:
 //   1. k_value_fold: each wave folds one segment of L stages right to left
-//      into one element.  A stage element has C = G G' of rank m, so the
-//      operator with a stage element on the left needs only an m x m inverse
-//      (Woodbury):  X^{-1} = I - G W^{-1} G'J^,  W = I + G'J^ G.
+//      into one element.  A stage element has C~ = B~ R^{-1} B~' of rank m, so
+//      the operator with a stage element on the left needs only an m x m
+//      inverse (Woodbury):  X^{-1} = I - B~ W^{-1} B~'J^,  W = R + B~'J^ B~,
+//      and no factorisation of R itself (R enters only through W).
 //   2. k_value_ks: Kogge-Stone suffix scan over the segment elements plus the
 //      terminal element, one launch per level, general operator with an
-//      (n+1) x (n+1) Gauss-Jordan inverse.
+//      (n+1) x (n+1) Gauss-Jordan inverse (of X', which is what the products
+//      need).
 //   3. k_value_riccati: inside each segment the suffix is completed from the
 //      right neighbour's value function by the Bellman step (the operator
 //      applied to a stage element and a terminal-type element), which also
 //      yields the control law of eq:value-fun-feedback.
 #include "lq_kernels.hpp"
 
+// Every product is P'Q of register tiles (tn in lq_tile.hpp); the fold keeps
+// the aggregate A^ transposed so that none of its products needs a transpose.
 namespace lqk {
 
 constexpr int ERR_NOT_PD = -2;
 constexpr int ERR_SINGULAR = -3;
 constexpr int ERR_NONFINITE = -4;
 
+// Stage element of eq:value-fun-elem-init for the fold, in the form
+// C~ = B~ W0^{-1} B~' (W0 = R from the problem data, W0 = I for a stored
+// element whose B~ is already B~ L^{-T}).
 struct StageElem {
-    Tile Ab;  // A~ - G N      ((n+1) x (n+1))
-    Tile G;   // B~ L^{-T}     ((n+1) x m), C~ = G G'
-    Tile J;   // Q~ - N' N     ((n+1) x (n+1)),  N = L^{-1} M~'
+    Tile Ab;  // A~ - B~ R^{-1} M~'   ((n+1) x (n+1))
+    Tile B;   // B~                    ((n+1) x m)
+    Tile J;   // Q~ - M~ R^{-1} M~'    ((n+1) x (n+1))
+    Tile W0;  // R                     (m x m)
 };
 
-// Raw stage data of the element build, loaded one stage ahead of its use.
+// Stage data of the fused element build, loaded one stage ahead of its use.
 struct StageRaw {
-    Tile A, Q;                // A~ and Q~ (homogeneous)
-    double brow[4][MMAX];     // B at this lane's four rows
-    double R[MMAX][MMAX];     // R (identity-padded)
-    double mt[MMAX];          // M~ at this lane's column: M[c][b] (c < n) or r[b] (c == n)
+    Tile A, Q, B, R;   // A~, Q~, B~, R
+    Tile MT, BT;       // M~' = [M', r] and B~' (only with cross terms)
 };
 
-LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, StageRaw &w)
+LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, bool has_mr, StageRaw &w)
 {
-    const int n = d.n, m = d.m, c = tcol();
     w.A = load_Ah(P, d, k);
     w.Q = load_Qh(P, d, k);
-    const double *Bk = P.B + d.oB + (int64_t)k * n * m;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = trow(r);
-#pragma unroll
-        for (int b = 0; b < MMAX; ++b) w.brow[r][b] = ldz(Bk, (int64_t)i * m + b, i < n && b < m);
+    w.B = load_Bh(P, d, k);
+    w.R = load_R(P, d, k);
+    if (has_mr) {
+        w.MT = load_MhT(P, d, k);
+        w.BT = load_BhT(P, d, k);
     }
-    const double *Rk = P.R + d.oR + (int64_t)k * m * m;
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j) {
-            const int ii = i < m ? i : 0, jj = j < m ? j : 0;
-            const double v = Rk[ii * m + jj];
-            w.R[i][j] = (i < m && j < m) ? v : (i == j ? 1.0 : 0.0);
-        }
-    const double *Mk = P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr;
-    const double *rk = P.r ? P.r + d.og + (int64_t)k * m : nullptr;
-#pragma unroll
-    for (int b = 0; b < MMAX; ++b)
-        w.mt[b] = *(Mk && c < n && b < m ? Mk + c * m + b : (rk && c == n && b < m ? rk + b : zptr()));
 }
 
-// Stage element of eq:value-fun-elem-init in the P^{-1}-free form, from the
-// stage data (R = L L').  Returns false if R is not positive definite.
+// The stage element from its data.  With cross terms (M or r) the Schur
+// complement needs R^{-1}: false if R is not positive definite.
 template <int PR>
-LQK_DEV bool build_from_raw(const StageRaw &w, const InstDesc &d, bool has_mr, StageElem &e, double *s0,
-                            double *s1)
+LQK_DEV bool build_from_raw(const StageRaw &w, const InstDesc &d, bool has_mr, StageElem &e)
 {
-    const int n = d.n, m = d.m, c = tcol();
-    double li[MMAX][MMAX];
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j) li[i][j] = w.R[i][j];
-    const bool ok = small_chol(li);
-    small_tri_inv(li);
-    // row c of L^{-1}: G[i][c] = sum_b B[i][b] Linv[c][b]
-    double lrow[MMAX];
-#pragma unroll
-    for (int b = 0; b < MMAX; ++b) {
-        double t = 0.0;
-#pragma unroll
-        for (int a = 0; a < MMAX; ++a) t = (a == c) ? li[a][b] : t;
-        lrow[b] = t;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = trow(r);
-        double v = 0.0;
-#pragma unroll
-        for (int b = 0; b < MMAX; ++b) v += w.brow[r][b] * lrow[b];
-        e.G.v[r] = (i < n && c < m) ? v : 0.0;
-    }
     e.Ab = w.A;
+    e.B = w.B;
     e.J = w.Q;
+    e.W0 = w.R;
+    bool ok = true;
     if (has_mr) {
-        // N[a][j] = sum_b Linv[a][b] M~[j][b]; rows a < m <= 4 are register 0 of lane group a.
-        const int g = tgrp();
-        Tile N = tzero();
-        double v = 0.0;
-#pragma unroll
-        for (int b = 0; b < MMAX; ++b) {
-            double lg = 0.0;
-#pragma unroll
-            for (int a = 0; a < MMAX; ++a) lg = (a == g) ? li[a][b] : lg;
-            v += lg * w.mt[b];
-        }
-        N.v[0] = (g < m) ? v : 0.0;
-        e.Ab = tsub(e.Ab, mmk<1, PR, false, false>(e.G, N, s0, s1));
-        e.J = tsub(e.J, mmk<1, PR, true, false>(N, N, s0, s1));
+        Tile RiT;
+        ok = spd_inverse_t(w.R, d.m, RiT);
+        const Tile K = tnz<1, PR>(RiT, w.MT);   // R^{-1} M~'
+        e.Ab.v -= tn<1, PR>(w.BT, K, (d4){0.0, 0.0, 0.0, 0.0});
+        e.J.v -= tn<1, PR>(w.MT, K, (d4){0.0, 0.0, 0.0, 0.0});
     }
     return ok;
 }
 
-template <int PR>
-LQK_DEV bool build_stage_elem(const ProbPtrs &P, const InstDesc &d, int k, StageElem &e, double *s0, double *s1)
-{
-    StageRaw w;
-    load_stage_raw(P, d, k, w);
-    return build_from_raw<PR>(w, d, (P.M != nullptr) || (P.r != nullptr), e, s0, s1);
-}
-
-// Left fold of a stage element into an aggregate E = (A^, C^, J^):
-// E <- e_k (x) E with the rank-m Woodbury form of the operator.
-// Returns false if W = I + G'J^G is singular.
+// Left fold of a stage element into an aggregate E = (A^, C^, J^), A^ held as
+// U = A^': E <- e_k (x) E with the rank-m Woodbury form of the operator:
+//   W = W0 + B~'J^B~,  P = B~'J^A~,  H = A^B~,
+//   A^ <- A^A~ - H W^{-1} P,  C^ <- C^ + H W^{-1} H',  J^ <- J~ + A~'J^A~ - P'W^{-1}P.
+// Returns false if W is singular.
 template <int NK, int PR>
-LQK_DEV bool fold_left(const StageElem &e, Tile &Ah, Tile &Ch, Tile &Jh, int m,
-                       double *s0, double *s1, double *s2, double *s3)
+LQK_DEV bool fold_left(const StageElem &e, Tile &U, Tile &Ch, Tile &Jh, int m)
 {
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
-    wsync();
-    sputp<PR>(s0, Jh);
-    sputp<PR>(s1, e.G);
-    sputp<PR>(s2, Ah);
-    sputp<PR>(s3, e.Ab);
-    wsync();
-    Tile JG, H, JA, AA;
-    JG.v = mfma_k<NK, PR, false, false>(s0, s1, z);   // J^ G
-    H.v = mfma_k<NK, PR, false, false>(s2, s1, z);    // A^ G
-    JA.v = mfma_k<NK, PR, false, false>(s0, s3, z);   // J^ Ab
-    AA.v = mfma_k<NK, PR, false, false>(s2, s3, z);   // A^ Ab
-    wsync();
-    sputp<PR>(s0, JG);
-    sputp<PR>(s2, JA);
-    wsync();
-    Tile W, P, Jn;
-    W.v = mfma_k<NK, PR, true, false>(s1, s0, tident(m).v);  // I + G'J^G
-    P.v = mfma_k<NK, PR, true, false>(s1, s2, z);             // G'J^ Ab
-    Jn.v = mfma_k<NK, PR, true, false>(s3, s2, e.J.v);        // Ab'J^ Ab + J
-    Tile Wi;
-    const bool ok = gen_inverse_small(W, m, Wi, s0);
-    wsync();
-    sputp<PR>(s0, Wi);
-    sputp<PR>(s1, P);
-    sputp<PR>(s2, H);
-    wsync();
-    Tile WP, WH;
-    WP.v = mfma_k<1, PR, false, false>(s0, s1, z);   // W^{-1} P
-    WH.v = mfma_k<1, PR, false, true>(s0, s2, z);    // W^{-1} H'
-    wsync();
-    sputp<PR>(s3, WP);
-    sputp<PR>(s0, WH);
-    wsync();
-    Tile t;
-    t.v = mfma_k<1, PR, false, false>(s2, s3, z);    // H W^{-1} P
-    Ah.v = AA.v - t.v;
-    Ch.v = mfma_k<1, PR, false, false>(s2, s0, Ch.v); // C^ + H W^{-1} H'
-    t.v = mfma_k<1, PR, true, false>(s1, s3, z);      // P' W^{-1} P
-    Jh.v = Jn.v - t.v;
-    wsync();
+    const Tile JG = tnz<NK, PR>(Jh, e.B);         // J^ B~
+    const Tile JA = tnz<NK, PR>(Jh, e.Ab);        // J^ A~
+    const Tile W = tna<NK, PR>(e.B, JG, e.W0);    // W0 + B~'J^B~
+    const Tile Pm = tnz<NK, PR>(e.B, JA);         // B~'J^A~
+    const Tile Jn = tna<NK, PR>(e.Ab, JA, e.J);   // J~ + A~'J^A~
+    const Tile Ht = tnz<NK, PR>(e.B, U);          // H' = B~'A^'
+    const Tile AAt = tnz<NK, PR>(e.Ab, U);        // (A^A~)'
+    Tile WiT;
+    const bool ok = gen_inverse_t(W, m, WiT);
+    const Tile WP = tnz<1, PR>(WiT, Pm);          // W^{-1} P
+    const Tile WHt = tnz<1, PR>(WiT, Ht);         // W^{-1} H'
+    U.v = AAt.v - tn<1, PR>(WP, Ht, z);           // (A^A~ - H W^{-1} P)'
+    Ch = tna<1, PR>(Ht, WHt, Ch);                 // C^ + H W^{-1} H'
+    Jh.v = Jn.v - tn<1, PR>(Pm, WP, z);           // ... - P'W^{-1}P
     return ok;
 }
 
 // ---------------------------------------------------------------------------
-// Element build (materialised)
+// Element build (materialised): A~ - G N, C~ = G G', J~ - N'N, G = B~ L^{-T},
+// N = L^{-1} M~', R = L L'.
 // ---------------------------------------------------------------------------
 template <int PR>
 __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                        const int64_t *__restrict__ elem_start, int batch,
                                                        double *__restrict__ elems, int32_t *status)
 {
-    __shared__ double lds[2 * SLOT];
+    __shared__ double lds[SLOT];
     const int64_t ge = blockIdx.x;
     const int i = find_inst64(elem_start, batch, ge);
     const InstDesc d = inst[i];
@@ -206,13 +132,24 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
         gstore(out + 3 * TILE, tzero());
         return;
     }
-    StageElem e;
-    const bool ok = build_stage_elem<PR>(P, d, k, e, lds, lds + SLOT);
-    const Tile C = mmk<1, PR, false, true>(e.G, e.G, lds, lds + SLOT);
-    gstore(out, e.Ab);
-    gstore(out + TILE, C);
-    gstore(out + 2 * TILE, e.J);
-    gstore(out + 3 * TILE, e.G);
+    const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
+    const Tile BT = load_BhT(P, d, k);
+    double li[MMAX][MMAX];
+    small_from_tile(load_R(P, d, k), d.m, li);
+    const bool ok = small_chol_inv(li);
+    const Tile Lt = small_to_tile<true>(li, d.m);   // L^{-T}
+    const Tile G = tnz<1, PR>(BT, Lt);              // B~ L^{-T}
+    const Tile GT = tnz<1, PR>(Lt, BT);             // L^{-1} B~'
+    Tile Ab = load_Ah(P, d, k), J = load_Qh(P, d, k);
+    if (has_mr) {
+        const Tile N = tnz<1, PR>(Lt, load_MhT(P, d, k));
+        Ab.v -= tn<1, PR>(GT, N, (d4){0.0, 0.0, 0.0, 0.0});
+        J.v -= tn<1, PR>(N, N, (d4){0.0, 0.0, 0.0, 0.0});
+    }
+    gstore(out, Ab);
+    gstore(out + TILE, tnz<1, PR>(GT, GT));
+    gstore(out + 2 * TILE, J);
+    gstore(out + 3 * TILE, G);
     if (!ok) report(status, i, ERR_NOT_PD, k);
 }
 
@@ -227,22 +164,20 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
                                                    const double *__restrict__ elems, double *__restrict__ X,
                                                    int32_t *status)
 {
-    __shared__ double lds[4 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n1 = d.n + 1, m = d.m;
-    Tile Ah = tident(n1), Ch = tzero(), Jh = tzero();
+    Tile U = tident(n1), Ch = tzero(), Jh = tzero();
     int code = 0, fk = 0;
-    (void)n1;
     if (s == d.nseg - 1) {  // terminal element after the last segment
         double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
         gstore(t, corner(d.n));
         gstore(t + TILE, tzero());
-        gstore(t + 2 * TILE, load_terminal_J(P, d, s0));
+        gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
     }
     // The element of segment 0 is never read: the Bellman steps of segment s
     // start from the scanned element s + 1.
@@ -253,25 +188,26 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             const double *ep = elems + (d.elem0 + k) * 4 * TILE;
             e.Ab = gload(ep);
             e.J = gload(ep + 2 * TILE);
-            e.G = gload(ep + 3 * TILE);
-            if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
+            e.B = gload(ep + 3 * TILE);
+            e.W0 = tident(m);
+            if (!fold_left<NK, PR>(e, U, Ch, Jh, m) && !code) {
                 code = ERR_SINGULAR;
                 fk = k;
             }
         }
     } else {
-        // fused element build; the raw data of stage k-1 is loaded while stage k is folded
+        // fused element build; the data of stage k-1 is loaded while stage k is folded
         const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
         StageRaw cur, nxt;
-        load_stage_raw(P, d, k1 - 1, cur);
+        load_stage_raw(P, d, k1 - 1, has_mr, cur);
         for (int k = k1 - 1; k >= k0; --k) {
-            if (k > k0) load_stage_raw(P, d, k - 1, nxt);
+            if (k > k0) load_stage_raw(P, d, k - 1, has_mr, nxt);
             StageElem e;
-            if (!build_from_raw<PR>(cur, d, has_mr, e, s0, s1) && !code) {
+            if (!build_from_raw<PR>(cur, d, has_mr, e) && !code) {
                 code = ERR_NOT_PD;
                 fk = k;
             }
-            if (!fold_left<NK, PR>(e, Ah, Ch, Jh, m, s0, s1, s2, s3) && !code) {
+            if (!fold_left<NK, PR>(e, U, Ch, Jh, m) && !code) {
                 code = ERR_SINGULAR;
                 fk = k;
             }
@@ -279,9 +215,9 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
         }
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
-    gstore(o, Ah);
-    gstore(o + TILE, Ch);
-    gstore(o + 2 * TILE, Jh);
+    gstore(o, ttrans(U, lds));
+    gstore(o + TILE, tsym(Ch, lds));
+    gstore(o + 2 * TILE, tsym(Jh, lds));
     if (code) report(status, i, code, fk);
 }
 
@@ -290,6 +226,10 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
 // Before the level, X_s covers segments [s, s+dd-1] (clipped at the terminal
 // index nseg); it is terminal-type (A~ = corner, C~ = 0, only J~ meaningful)
 // once it covers nseg.  Terminal-type entries are only ever right operands.
+// With Y = X^{-1}, the products are
+//   Z = Y A~1,  J~ = Z'(J~2 A~1) + J~1,  A~ = A~2 Z,  C~ = A~2 (Y C~1) A~2' + C~2,
+// all P'Q of register tiles given R(Y') (the inverse of X' = I + J~2 C~1) and
+// R(A~2') (one LDS transpose).
 // ---------------------------------------------------------------------------
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ inst,
@@ -297,8 +237,7 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
                                                  const double *__restrict__ Xin, double *__restrict__ Xout,
                                                  int32_t *status)
 {
-    __shared__ double lds[4 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    __shared__ double lds[SLOT];
     const int gx = blockIdx.x;
     const int i = find_inst(x_start, batch, gx);
     const InstDesc d = inst[i];
@@ -314,61 +253,22 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const double *b = Xin + (int64_t)(gx + dd) * 3 * TILE;
     const bool b_term = (s + 2 * dd - 1 >= nseg);
     const int n1 = d.n + 1;
-    const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
-    const Tile J2 = gload(b + 2 * TILE);
-    // X = I + C~1 J~2
-    sputp<PR>(s0, C1);
-    sputp<PR>(s1, J2);
-    wsync();
-    Tile Xt;
-    Xt.v = mfma_k<NK, PR, false, false>(s0, s1, tident(n1).v);
-    const bool ok = gj_inverse(Xt, n1, s2);
-    wsync();
-    sputp<PR>(s3, Xt);  // X^{-1}
-    wsync();
-    Tile T3;
-    T3.v = mfma_k<NK, PR, false, false>(s1, s3, z);   // J~2 X^{-1} = (X^{-T} J~2)'
-    wsync();
-    sputp<PR>(s0, T3);
-    sputp<PR>(s2, A1);
-    wsync();
-    Tile T4;
-    T4.v = mfma_k<NK, PR, true, false>(s0, s2, z);    // X^{-T} J~2 A~1
-    wsync();
-    sputp<PR>(s1, T4);
-    wsync();
-    Tile Jn;
-    Jn.v = mfma_k<NK, PR, true, false>(s2, s1, J1.v); // A~1' X^{-T} J~2 A~1 + J~1
-    Jn = tsym(Jn, s0);
-    gstore(o + 2 * TILE, Jn);
+    const Tile A2 = gload(b), C2 = gload(b + TILE), J2 = gload(b + 2 * TILE);
+    Tile YT = tna<NK, PR>(J2, C1, tident(n1));   // X' = I + J~2 C~1
+    const bool ok = gj_inverse<NK>(YT, n1);      // X^{-T}
+    const Tile Z = tnz<NK, PR>(YT, A1);          // X^{-1} A~1
+    const Tile JA = tnz<NK, PR>(J2, A1);         // J~2 A~1
+    const Tile Jn = tna<NK, PR>(Z, JA, J1);      // A~1'X^{-T}J~2 A~1 + J~1
+    gstore(o + 2 * TILE, tsym(Jn, lds));
     if (!b_term) {
-        const Tile A2 = gload(b), C2 = gload(b + TILE);
-        wsync();
-        sputp<PR>(s0, A2);
-        wsync();
-        Tile T1;
-        T1.v = mfma_k<NK, PR, false, false>(s0, s3, z);   // A~2 X^{-1}
-        wsync();
-        sputp<PR>(s1, T1);
-        wsync();
-        Tile An;
-        An.v = mfma_k<NK, PR, false, false>(s1, s2, z);   // A~2 X^{-1} A~1
-        wsync();
-        sputp<PR>(s3, C1);
-        wsync();
-        Tile T2;
-        T2.v = mfma_k<NK, PR, false, false>(s1, s3, z);   // A~2 X^{-1} C~1
-        wsync();
-        sputp<PR>(s2, T2);
-        wsync();
-        Tile Cn;
-        Cn.v = mfma_k<NK, PR, false, true>(s2, s0, C2.v); // ... A~2' + C~2
-        Cn = tsym(Cn, s1);
-        gstore(o, An);
-        gstore(o + TILE, Cn);
+        const Tile A2T = ttrans(A2, lds);
+        const Tile Y = tnz<NK, PR>(YT, C1);      // X^{-1} C~1
+        const Tile Vt = tnz<NK, PR>(Y, A2T);     // (A~2 X^{-1} C~1)'
+        gstore(o, tnz<NK, PR>(A2T, Z));          // A~2 X^{-1} A~1
+        gstore(o + TILE, tsym(tna<NK, PR>(Vt, A2T, C2), lds));
     }
-    if (!ok) report(status, i, ERR_SINGULAR, s);
+    if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
 }
 
 // ---------------------------------------------------------------------------
@@ -384,15 +284,13 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
                                                       const double *__restrict__ Xfin, ValPtrs V,
                                                       int32_t *status)
 {
-    __shared__ double lds[4 * SLOT];
-    double *s0 = lds, *s1 = lds + SLOT, *s2 = lds + 2 * SLOT, *s3 = lds + 3 * SLOT;
+    __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
-    const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
     const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
     Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
     if (s == d.nseg - 1) {
@@ -412,38 +310,20 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
             nRk = load_R(P, d, k - 1);
             if (has_mr) nMhT = load_MhT(P, d, k - 1);
         }
-        wsync();
-        sputp<PR>(s0, St);
-        sputp<PR>(s1, Bh);
-        sputp<PR>(s2, Ah);
-        wsync();
-        Tile SB, SA;
-        SB.v = mfma_k<NK, PR, false, false>(s0, s1, z);
-        SA.v = mfma_k<NK, PR, false, false>(s0, s2, z);
-        wsync();
-        sputp<PR>(s3, SB);
-        sputp<PR>(s0, SA);
-        wsync();
-        Tile Quu, Qux, Sn;
-        Quu.v = mfma_k<NK, PR, true, false>(s1, s3, Rk.v);
-        Qux.v = mfma_k<NK, PR, true, false>(s1, s0, MhT.v);
-        Sn.v = mfma_k<NK, PR, true, false>(s2, s0, Qh.v);
-        Tile Qi;
-        if (!spd_inverse(Quu, m, Qi, s3) && !code) {
+        const Tile SB = tnz<NK, PR>(St, Bh);          // S~'B~
+        const Tile SA = tnz<NK, PR>(St, Ah);          // S~'A~
+        const Tile Quu = tna<NK, PR>(Bh, SB, Rk);     // R + B~'S~'B~
+        const Tile Qux = tna<NK, PR>(Bh, SA, MhT);    // M~' + B~'S~'A~
+        Tile Sn = tna<NK, PR>(Ah, SA, Qh);            // Q~ + A~'S~'A~
+        Tile QiT;
+        if (!spd_inverse_t(Quu, m, QiT) && !code) {
             code = ERR_NOT_PD;
             fk = k;
         }
-        wsync();
-        sputp<PR>(s3, Qi);
-        sputp<PR>(s1, Qux);
-        wsync();
-        Tile Gh;
-        Gh.v = -mfma_k<1, PR, false, false>(s3, s1, z);
-        wsync();
-        sputp<PR>(s3, Gh);
-        wsync();
-        Sn.v = mfma_k<1, PR, true, false>(s1, s3, Sn.v);
-        St = tsym(Sn, s0);
+        Tile Gh = tnz<1, PR>(QiT, Qux);
+        Gh.v = -Gh.v;                                 // -Q_uu^{-1} Q_ux~
+        Sn = tna<1, PR>(Qux, Gh, Sn);                 // + Q_ux~' Gamma~
+        St = tsym(Sn, lds);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
@@ -486,24 +366,18 @@ void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtr
 #undef CALL
 }
 
-// Diagnostic: D = op(X) op(Y) (+ Z) for row-major 16 x 16 inputs.
+// Diagnostic: D = op(X) op(Y) (+ Z) for row-major 16 x 16 inputs, through the
+// same register product and LDS transpose as the solver.
 template <int PR>
 __global__ __launch_bounds__(64) void k_selftest_mm(const double *X, const double *Y, const double *Z,
                                                     double *D, int tx, int ty)
 {
-    __shared__ double lds[2 * SLOT];
+    __shared__ double lds[SLOT];
     const Tile x = gload_rm(X, 16, 16, 16), y = gload_rm(Y, 16, 16, 16);
     const Tile zt = Z ? gload_rm(Z, 16, 16, 16) : tzero();
-    Tile d;
-    if (tx && ty)
-        d = mmak<4, PR, true, true>(x, y, zt, lds, lds + SLOT);
-    else if (tx)
-        d = mmak<4, PR, true, false>(x, y, zt, lds, lds + SLOT);
-    else if (ty)
-        d = mmak<4, PR, false, true>(x, y, zt, lds, lds + SLOT);
-    else
-        d = mmak<4, PR, false, false>(x, y, zt, lds, lds + SLOT);
-    gstore_rm(D, d, 16, 16, 16);
+    const Tile xf = tx ? x : ttrans(x, lds);   // R(op(X)')
+    const Tile yf = ty ? ttrans(y, lds) : y;   // R(op(Y))
+    gstore_rm(D, tna<4, PR>(xf, yf, zt), 16, 16, 16);
 }
 
 void launch_build_elements(int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
