@@ -4,8 +4,9 @@ Workload: one long-horizon time-varying LQ problem, n=12, m=4, T=16384, FP64,
 drawn by paper_2409_20027_amd.workloads.cfg2_long (synthetic, seeded).
 One step = the whole hot path over that input, forward and adjoint:
   value pass   (fused element build + segment fold, log-depth scan of the
-                segment elements, Bellman steps with the control law),
-  rollout      (segment maps, prefix scan, states / controls / co-states),
+                segment elements, Bellman steps with the control law and the
+                rollout's segment maps),
+  rollout      (prefix scan of the segment maps, states / controls / co-states),
   adjoint      (backward linear-term scan, forward derivative scan, per-stage
                 gradients of L = sum ||x||^2 + ||u||^2 w.r.t. A, B, c, Q, R,
                 Q_T, x0).
@@ -33,6 +34,42 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6   # FP64 matrix cores (dense) = FP64 vector
+CSRC = os.path.join(ROOT, "paper_2409_20027_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+CALIB_BYTES = 256 << 20   # the plain copy launched by --calib (read and written once)
+
+
+def source_hash() -> str:
+    """SHA-256 over the HIP sources, so that a stored counter reading is only
+    used while the kernels it was taken from are unchanged."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from profiles/traffic_<kernel>.md (two
+    rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by the readings of
+    a plain copy of known size), or None if absent or taken from other sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("|", "#")):
+                k, v = line.split(":", 1)
+                rec[k.strip().strip("`*")] = v.strip().strip("`")
+    if rec.get("source_sha256") != source_hash():
+        return None
+    try:
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 # ---------------------------------------------------------------------------
 # Per-stage algorithmic cost models of the kernels (n1 = n + 1, homogeneous
@@ -98,6 +135,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--replays", type=int, default=100)
+    ap.add_argument("--calib", action="store_true",
+                    help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: sharding the horizon or the batch over several GPUs is a "
@@ -123,8 +162,7 @@ def main():
     grads = lqscan.grad_buffers(plan, gnames, dev)
 
     def forward():
-        lqscan.lq_scan_solve(plan, prob, None, val, ws, status)
-        lqscan.lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
 
     forward()
     torch.cuda.synchronize()
@@ -137,6 +175,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    if args.calib:
+        src = torch.ones(CALIB_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads and writes 256 MiB once
+        torch.cuda.synchronize()
+        del src, dst
 
     # profiling pass: every phase timed with events (not the headline number)
     prof_steps = min(args.steps, 10)
@@ -211,8 +255,7 @@ def main():
         sws = splan.new_workspace(dev)
 
         def sstep():
-            lqscan.lq_scan_solve(splan, prob, None, val, sws, status)
-            lqscan.lq_rollout(splan, prob, val, st["x"], st["u"], st["lam"], sws, status)
+            lqscan.lq_solve(splan, prob, None, val, st["x"], st["u"], st["lam"], sws, status)
             lqscan.lq_adjoint(splan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, sws, status)
 
         sstep()
@@ -240,7 +283,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
-    roof.update({"traffic": None, "kernel": dominant, "avg_launch_us": avg_s * 1e6,
+    roof.update({"traffic": stored_traffic(dominant), "kernel": dominant, "avg_launch_us": avg_s * 1e6,
                  "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                  "flops_per_stage": mdl["flops"], "bytes_per_stage": mdl["bytes"], "units_per_launch": T})
 

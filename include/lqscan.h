@@ -167,9 +167,11 @@ lq_status lq_build_elements(const lq_plan *plan, const lq_problem *prob, double 
  * Numerical failures: LQ_ERR_NOT_PD (R_k + B'S_{k+1}B not positive definite;
  * with cross terms M or r also R_k, whose inverse forms the Schur complement),
  * LQ_ERR_SINGULAR.  Without cross terms R_k itself is never factorised: it
- * enters the fused fold only through R_k + B'J B (J the aggregate's value
- * matrix), so a singular or indefinite R_k is accepted wherever
- * R_k + B'S_{k+1}B is positive definite.
+ * enters the fused fold only through W = R_k + B'J B (J the aggregate's value
+ * matrix), so an indefinite R_k is accepted wherever R_k + B'S_{k+1}B is
+ * positive definite.  R_k must still be invertible (the stage element's
+ * C = B R_k^{-1} B' needs it): a singular R_k can make W singular
+ * (LQ_ERR_SINGULAR at that stage).
  */
 lq_status lq_scan_solve(const lq_plan *plan, const lq_problem *prob, const double *elements,
                         const lq_value *out, void *workspace, int32_t *status, void *stream);
@@ -190,6 +192,19 @@ lq_status lq_rollout(const lq_plan *plan, const lq_problem *prob, const lq_value
 typedef struct {
     double *A, *B, *c, *Q, *R, *M, *q, *r, *QT, *qT, *x0;
 } lq_grads;
+
+/*
+ * lq_solve -- lq_scan_solve followed by lq_rollout, as one call: the same
+ * value pass and state propagation (Alg. 2 then Alg. 3), with the rollout's
+ * segment fold done inside the value pass's Bellman sweep, where the gains
+ * Gamma_k, gamma_k are formed (the closed-loop map F_k = A_k + B_k Gamma_k of
+ * eq:state-prop-comb-rule needs nothing else), so the stage data is read once
+ * less.  Arguments, layouts, ownership and errors are those of lq_scan_solve
+ * (elements, out) and lq_rollout (x, u, lambda); the results are the same up to
+ * rounding order.
+ */
+lq_status lq_solve(const lq_plan *plan, const lq_problem *prob, const double *elements, const lq_value *out,
+                   double *x, double *u, double *lambda, void *workspace, int32_t *status, void *stream);
 
 /*
  * lq_adjoint -- reverse-mode derivative of the LQ solution (not in the

@@ -7,7 +7,7 @@ depth T).  The best L depends on the state size, the horizon and on how many
 instances share the GPU, so it is measured instead of assumed.
 
 Instances are grouped into classes (n, m, T bucket).  For each class the tuner
-times the forward solve (lq_scan_solve + lq_rollout) of the class's instances
+times the forward solve (lq_solve) of the class's instances
 for every candidate L with HIP events and keeps the fastest.  Results are cached
 in a JSON file keyed by class, batch-size bucket and precision, and returned as
 one segment length per instance for lq_plan_create_seg.
@@ -42,8 +42,7 @@ def _time_forward(lq, insts, seg, precision, reps, torch):
     st = lq.state_buffers(plan)
 
     def fwd():
-        lq.lq_scan_solve(plan, prob, None, val, ws, status)
-        lq.lq_rollout(plan, prob, val, st["x"], st["u"], None, ws, status)
+        lq.lq_solve(plan, prob, None, val, st["x"], st["u"], None, ws, status)
 
     fwd()
     torch.cuda.synchronize()

@@ -243,17 +243,12 @@ lq_status lq_build_elements(const lq_plan *p, const lq_problem *prob, double *el
     return launched();
 }
 
-lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
-                        void *workspace, int32_t *status, void *stream)
+// Value pass: fold, log-depth scan, Bellman sweep.  With Yroll the sweep also
+// writes the rollout scan's entries (its segment fold fused in).
+static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *elements, const lqk::ValPtrs &V,
+                       char *ws, double *Yroll, int32_t *status, hipStream_t st)
 {
-    if (!p || !prob_ok(prob) || !out || !out->S || !out->s || !out->Gamma || !out->gamma) return LQ_ERR_ARG;
-    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
-    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
     double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
-    const lqk::ProbPtrs P = probptrs(prob);
-    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
     timed(p, LQ_PH_VALUE_FOLD, st, [&] {
         lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
                                Xa, status);
@@ -270,26 +265,14 @@ lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *
     double *fin = in;
     timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
         lqk::launch_value_riccati(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
-                                  V, status);
+                                  V, Yroll, status);
     });
-    return launched();
 }
 
-lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *val, double *x, double *u,
-                     double *lambda, void *workspace, int32_t *status, void *stream)
+// Rollout from its scan entries in Ya (Yb: ping-pong): prefix scan, then states.
+static void rollout_scan_apply(const lq_plan *p, const lqk::ProbPtrs &P, const lqk::ValPtrs &V, double *Ya, double *Yb,
+                               double *x, double *u, double *lambda, hipStream_t st)
 {
-    (void)status;
-    if (!p || !prob_ok(prob) || !val || !val->S || !val->s || !val->Gamma || !val->gamma || !x || !u)
-        return LQ_ERR_ARG;
-    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
-    const lqk::ProbPtrs P = probptrs(prob);
-    lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
-    timed(p, LQ_PH_ROLL_FOLD, st, [&] {
-        lqk::launch_roll_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
-    });
     double *in = Ya, *o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ROLL_SCAN, st, [&] {
@@ -304,6 +287,52 @@ lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *v
         lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
                                u, lambda);
     });
+}
+
+static bool value_ok(const lq_value *v) { return v && v->S && v->s && v->Gamma && v->gamma; }
+
+lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                        void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(out)) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
+    value_pass(p, probptrs(prob), elements, V, (char *)workspace, nullptr, status, (hipStream_t)stream);
+    return launched();
+}
+
+lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *val, double *x, double *u,
+                     double *lambda, void *workspace, int32_t *status, void *stream)
+{
+    (void)status;
+    if (!p || !prob_ok(prob) || !value_ok(val) || !x || !u) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
+    timed(p, LQ_PH_ROLL_FOLD, st, [&] {
+        lqk::launch_roll_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
+    });
+    rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
+    return launched();
+}
+
+lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out, double *x,
+                   double *u, double *lambda, void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(out) || !x || !u) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
+    value_pass(p, P, elements, V, ws, Ya, status, st);
+    rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
     return launched();
 }
 
@@ -336,15 +365,14 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
             }
         });
     double *fin = in;
+    // the backward sweep also writes the forward scan's entries (its segment fold fused in)
+    double *fwd = (fin == Ya) ? Yb : Ya, *fwd2 = fin;
     timed(p, LQ_PH_ADJ_BACK_APPLY, st, [&] {
-        lqk::launch_adj_back_apply(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, status);
+        lqk::launch_adj_back_apply(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, fwd, status);
     });
     // forward derivative scan + gradients
-    timed(p, LQ_PH_ADJ_FWD_FOLD, st, [&] {
-        lqk::launch_adj_fwd_fold(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
-    });
-    in = Ya;
-    o = Yb;
+    in = fwd;
+    o = fwd2;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
@@ -463,9 +491,7 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt; lp.M = nullptr;
     lp.q = nullptr; lp.r = Wk.d; lp.QT = prob->QT; lp.qT = nullptr; lp.x0 = Wk.zero;
     lq_value val{Wk.S, Wk.s, Wk.G, Wk.gm};
-    lq_status r = lq_scan_solve(p, &lp, nullptr, &val, workspace, Wk.status, stream);
-    if (r != LQ_OK) return r;
-    r = lq_rollout(p, &lp, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);
+    const lq_status r = lq_solve(p, &lp, nullptr, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);
     if (r != LQ_OK) return r;
     // candidate, decision, commit
     lqk::launch_nmpc_candidate(st, N, Wk, state->x, state->u, state->scal);

@@ -54,11 +54,18 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
 // Inside each segment, from s~ at its right end: s~_k and gamma~_k.
 //   s~_k = F_k' s~_{k+1} + gx_k + Gamma_k' gu_k,
 //   gamma~_k = -(R_k + B~'S~_{k+1}B~)^{-1} (gu_k + B~' s~_{k+1}).
+// gamma~_k completes the derivative's closed-loop map of stage k,
+// F'_k = [[A + B Gamma, B gamma~], [0, 1]], so the same sweep folds the
+// forward scan's segment maps Phi_s = F'_{k1-1} ... F'_{k0} (kept as Phi') and
+// writes the forward scan's entries into Yfwd: Phi_s at s + 1 (s < nseg - 1)
+// and the zero map of dx_0 at 0.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
                                                        const int32_t *__restrict__ seg_start, int batch,
-                                                       const double *__restrict__ Yfin, int32_t *status)
+                                                       const double *__restrict__ Yfin, double *__restrict__ Yfwd,
+                                                       int32_t *status)
 {
+    __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -73,6 +80,7 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     Tile nR = load_R(P, d, k1 - 1), nA = load_Ah(P, d, k1 - 1, false), nG = load_Gh(J.G, nullptr, d, k1 - 1);
     Tile nGU = load_vec(J.gu + d.og + (int64_t)(k1 - 1) * m, m, n, -1);
     Tile nGX = load_vec(J.gx + d.os + (int64_t)(k1 - 1) * n, n, n, -1);
+    Tile PhiT = tident(n + 1);
     for (int k = k1 - 1; k >= k0; --k) {
         const Tile Bh = nB, BhT = nBT, Sh = nS, Rk = nR, An = nA, G0 = nG, GU = nGU, GX = nGX;
         if (k > k0) {
@@ -98,39 +106,13 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
         store_vec(J.gt + d.og + (int64_t)k * m, Gt, m, n);
         // F~ = A_noc~ + B~ Gamma_0~;  s~_k = F~'s~_{k+1} + gx + Gamma_0~'gu
         const Tile F = tna<1, PR>(BhT, G0, An);
+        PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gt, F), PhiT);   // (Phi F'_k)' = F'_k' Phi'
         SV = tna<NK, PR>(F, SV, tna<1, PR>(G0, GU, GX));
         store_vec(J.st + d.os + (int64_t)k * n, SV, n, n);
     }
+    if (s == 0) gstore(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n));   // dx_0 = 0
+    if (s < d.nseg - 1) gstore(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds));
     if (code) report(status, i, code, fk);
-}
-
-// R(F~') of the derivative's closed-loop map F~ = [[A + B Gamma, B gamma~], [0, 1]].
-template <int PR>
-LQK_DEV Tile fwd_map_t(const ProbPtrs &P, const AdjPtrs &J, const InstDesc &d, int k)
-{
-    return tna<1, PR>(load_Gh(J.G, J.gt, d, k), load_BhT(P, d, k), load_AhT(P, d, k, false));
-}
-
-template <int NK, int PR>
-__global__ __launch_bounds__(64) void k_adj_fwd_fold(ProbPtrs P, AdjPtrs J, const InstDesc *__restrict__ inst,
-                                                     const int32_t *__restrict__ seg_start, int batch,
-                                                     double *__restrict__ Y)
-{
-    const int gs = blockIdx.x;
-    const int i = find_inst(seg_start, batch, gs);
-    const InstDesc d = inst[i];
-    const int s = gs - d.seg0;
-    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(nullptr, d.n, d.n, d.n));   // dx_0 = 0
-    if (s == d.nseg - 1) return;   // never read: segment s starts from entry s
-    Tile Phi = tident(d.n + 1);
-    Tile nF = fwd_map_t<PR>(P, J, d, k0);
-    for (int k = k0; k < k1; ++k) {
-        const Tile FT = nF;
-        if (k + 1 < k1) nF = fwd_map_t<PR>(P, J, d, k + 1);
-        Phi = tnz<NK, PR>(FT, Phi);
-    }
-    gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
 
 template <int NK, int PR>
@@ -221,16 +203,9 @@ void launch_adj_back_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtr
 #undef CALL
 }
 void launch_adj_back_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
-                           const int32_t *seg_start, int batch, const double *Yfin, int32_t *status)
+                           const int32_t *seg_start, int batch, const double *Yfin, double *Yfwd, int32_t *status)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_adj_back_apply<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Yfin, status)
-    LQK_DISPATCH(nk, pr, CALL)
-#undef CALL
-}
-void launch_adj_fwd_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
-                         const int32_t *seg_start, int batch, double *Y)
-{
-#define CALL(K, R) hipLaunchKernelGGL((k_adj_fwd_fold<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Y)
+#define CALL(K, R) hipLaunchKernelGGL((k_adj_back_apply<K, R>), dim3(grid), dim3(64), 0, st, P, J, inst, seg_start, batch, Yfin, Yfwd, status)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }

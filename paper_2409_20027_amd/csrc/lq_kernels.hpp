@@ -16,7 +16,8 @@ void launch_value_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P
 void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                      int batch, int dd, const double *Xin, double *Xout, int32_t *status);
 void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
-                          const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, int32_t *status);
+                          const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
+                          int32_t *status);
 void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                       const int32_t *seg_start, int batch, double *Y);
 void launch_affine_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
@@ -27,9 +28,7 @@ void launch_roll_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P
 void launch_adj_back_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
                           const int32_t *seg_start, int batch, double *Y);
 void launch_adj_back_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
-                           const int32_t *seg_start, int batch, const double *Yfin, int32_t *status);
-void launch_adj_fwd_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, const InstDesc *inst,
-                         const int32_t *seg_start, int batch, double *Y);
+                           const int32_t *seg_start, int batch, const double *Yfin, double *Yfwd, int32_t *status);
 void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
                           const InstDesc *inst, const int32_t *seg_start, int batch, const double *Yfin);
 

@@ -278,11 +278,16 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
 //   Gamma~ = -Q_uu^{-1} Q_ux~ = [Gamma, gamma];
 //   S~ = sym(Q~ + A~'S~'A~ + Q_ux~' Gamma~).
 // ---------------------------------------------------------------------------
+//
+// With Yroll != nullptr the sweep also folds the segment's closed-loop maps
+// for the rollout, Phi_s = F~_{k1-1} ... F~_{k0} with F~_k = A~_k + B~_k Gamma~_k
+// (kept as Phi' across the sweep), and writes the rollout scan's entries:
+// Phi_s at s + 1 (s < nseg - 1) and the constant map of x0 at 0.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Xfin, ValPtrs V,
-                                                      int32_t *status)
+                                                      double *__restrict__ Yroll, int32_t *status)
 {
     __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
@@ -301,14 +306,18 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     // stage data of stage k-1 is loaded while stage k is processed
     Tile nAh = load_Ah(P, d, k1 - 1), nBh = load_Bh(P, d, k1 - 1), nQh = load_Qh(P, d, k1 - 1);
     Tile nRk = load_R(P, d, k1 - 1), nMhT = has_mr ? load_MhT(P, d, k1 - 1) : tzero();
+    const bool roll = (Yroll != nullptr);
+    Tile nBT = roll ? load_BhT(P, d, k1 - 1) : tzero();
+    Tile PhiT = tident(n + 1);
     for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Ah = nAh, Bh = nBh, Qh = nQh, Rk = nRk, MhT = nMhT;
+        const Tile Ah = nAh, Bh = nBh, Qh = nQh, Rk = nRk, MhT = nMhT, BhT = nBT;
         if (k > k0) {
             nAh = load_Ah(P, d, k - 1);
             nBh = load_Bh(P, d, k - 1);
             nQh = load_Qh(P, d, k - 1);
             nRk = load_R(P, d, k - 1);
             if (has_mr) nMhT = load_MhT(P, d, k - 1);
+            if (roll) nBT = load_BhT(P, d, k - 1);
         }
         const Tile SB = tnz<NK, PR>(St, Bh);          // S~'B~
         const Tile SA = tnz<NK, PR>(St, Ah);          // S~'A~
@@ -323,11 +332,16 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         Tile Gh = tnz<1, PR>(QiT, Qux);
         Gh.v = -Gh.v;                                 // -Q_uu^{-1} Q_ux~
         Sn = tna<1, PR>(Qux, Gh, Sn);                 // + Q_ux~' Gamma~
+        if (roll) PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gh, Ah), PhiT);   // (Phi F~_k)' = F~_k' Phi'
         St = tsym(Sn, lds);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
         store_vec(V.g + d.og + (int64_t)k * m, Gh, m, n);
+    }
+    if (roll) {
+        if (s == 0) gstore(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n));
+        if (s < d.nseg - 1) gstore(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds));
     }
     const bool bad = !(isfinite(St.v[0]) && isfinite(St.v[1]) && isfinite(St.v[2]) && isfinite(St.v[3]));
     if (__ballot(bad) && !code) {
@@ -359,9 +373,10 @@ void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDe
 }
 
 void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
-                          const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, int32_t *status)
+                          const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
+                          int32_t *status)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_value_riccati<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, status)
+#define CALL(K, R) hipLaunchKernelGGL((k_value_riccati<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, Yroll, status)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }

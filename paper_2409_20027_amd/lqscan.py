@@ -64,6 +64,8 @@ _lib.lq_scan_solve.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.P
 _lib.lq_scan_solve.restype = ctypes.c_int
 _lib.lq_rollout.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P, _P]
 _lib.lq_rollout.restype = ctypes.c_int
+_lib.lq_solve.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P, _P]
+_lib.lq_solve.restype = ctypes.c_int
 _lib.lq_adjoint.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P,
                             ctypes.POINTER(LQGradsC), _P, _P, _P]
 _lib.lq_adjoint.restype = ctypes.c_int
@@ -76,7 +78,7 @@ _lib.lq_selftest_tile_mm.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout",
-            "lq_adjoint", "lq_selftest_tile_mm", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
+            "lq_solve", "lq_adjoint", "lq_selftest_tile_mm", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
           "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply")
@@ -227,6 +229,12 @@ def lq_rollout(plan: Plan, prob: dict, value: dict, x, u, lam, workspace, status
                                          _ptr(workspace), _ptr(status), _stream(stream)))
 
 
+def lq_solve(plan: Plan, prob: dict, elements, value: dict, x, u, lam, workspace, status=None, stream=None):
+    _check("lq_solve", _lib.lq_solve(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(elements),
+                                     ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
+                                     _ptr(workspace), _ptr(status), _stream(stream)))
+
+
 def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: dict, workspace, status=None,
                stream=None):
     g = LQGradsC(*[_f64(grads.get(f)) for f in _PROBLEM_FIELDS])
@@ -272,8 +280,10 @@ def state_buffers(plan: Plan, device="cuda") -> dict:
     return {"x": z(((T + 1) * n).sum()), "u": z((T * m).sum()), "lam": z(((T + 1) * n).sum())}
 
 
-def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, workspace=None, stream=None) -> dict:
-    """lq_scan_solve + lq_rollout; returns flat packed device tensors and the status array."""
+def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, fused: bool = True, workspace=None,
+          stream=None) -> dict:
+    """lq_solve (fused = False: lq_scan_solve then lq_rollout); returns flat
+    packed device tensors and the status array."""
     dev = prob["A"].device
     ws = workspace if workspace is not None else plan.new_workspace(dev)
     status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
@@ -283,8 +293,11 @@ def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, workspa
     if materialise_elements:
         el = plan.new_elements(dev)
         lq_build_elements(plan, prob, el, status, stream)
-    lq_scan_solve(plan, prob, el, val, ws, status, stream)
-    lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status, stream)
+    if fused:
+        lq_solve(plan, prob, el, val, st["x"], st["u"], st["lam"], ws, status, stream)
+    else:
+        lq_scan_solve(plan, prob, el, val, ws, status, stream)
+        lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status, stream)
     out = dict(val)
     out.update(st)
     out["status"] = status
@@ -307,8 +320,8 @@ class LQSolveFunction(torch.autograd.Function):
     """(x, u) = LQ solution of the packed problem; gradients by lq_adjoint.
 
     Inputs are flat packed float64 device tensors (lq_problem layout); c, M, q,
-    r, qT may be None.  The forward pass is lq_scan_solve + lq_rollout, the
-    backward pass one lq_adjoint call; both run in the HIP library.
+    r, qT may be None.  The forward pass is one lq_solve call, the backward
+    pass one lq_adjoint call; both run in the HIP library.
     """
 
     @staticmethod
@@ -319,8 +332,7 @@ class LQSolveFunction(torch.autograd.Function):
         status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
         val = value_buffers(plan, dev)
         st = state_buffers(plan, dev)
-        lq_scan_solve(plan, prob, None, val, ws, status)
-        lq_rollout(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+        lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
         ctx.plan, ctx.prob, ctx.val, ctx.st, ctx.ws, ctx.status = plan, prob, val, st, ws, status
         ctx.mark_non_differentiable(status)
         return st["x"], st["u"], status

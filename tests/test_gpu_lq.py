@@ -43,11 +43,11 @@ def oracle_ref(inst):
                            M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
 
 
-def run(lq, insts, materialise=False, **plan_kw):
+def run(lq, insts, materialise=False, fused=True, **plan_kw):
     packed = W.pack(insts)
     prob = lq.to_device(packed)
     plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], **plan_kw)
-    out = lq.solve(plan, prob, materialise_elements=materialise)
+    out = lq.solve(plan, prob, materialise_elements=materialise, fused=fused)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if v is not None else None) for k, v in out.items()}
     per = []
@@ -94,11 +94,12 @@ def test_cfg0_small_scan(lq):
     check(per, [inst])
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("seg_len", [1, 3, 7, 16, 64])
-def test_cfg0_segment_lengths(lq, seg_len):
+def test_cfg0_segment_lengths(lq, seg_len, fused):
     """Every segmentation (including ragged last segments) gives the same solution."""
     inst = W.cfg0_small()
-    per, status, _ = run(lq, [inst], seg_len=seg_len)
+    per, status, _ = run(lq, [inst], seg_len=seg_len, fused=fused)
     assert int(np.abs(status).sum()) == 0
     check(per, [inst])
 
@@ -110,11 +111,13 @@ def test_cfg0_sequential_mode(lq):
     check(per, [inst])
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("n,m,T,L", [(3, 2, 37, 5), (4, 4, 50, 8), (1, 1, 9, 2), (15, 4, 40, 6)])
-def test_general_lq_all_terms(lq, n, m, T, L):
-    """Cross terms M, linear terms q, r, q_T and offsets c all present."""
+def test_general_lq_all_terms(lq, n, m, T, L, fused):
+    """Cross terms M, linear terms q, r, q_T and offsets c all present; through
+    lq_solve and through lq_scan_solve + lq_rollout."""
     inst = W.lq_instance_general(np.random.default_rng(1000 + n * 10 + m), n, m, T)
-    per, status, _ = run(lq, [inst], seg_len=L)
+    per, status, _ = run(lq, [inst], seg_len=L, fused=fused)
     assert int(np.abs(status).sum()) == 0
     check(per, [inst])
 
@@ -190,6 +193,24 @@ def test_value_matrices_symmetric_psd(lq):
     for k in range(inst.T + 1):
         ev = np.linalg.eigvalsh(S[k])
         assert ev.min() >= -1e-12 * np.abs(ev).max()
+
+
+@pytest.mark.parametrize("seg_len", [1, 4, 16])
+def test_indefinite_R_with_positive_definite_Quu(lq, seg_len):
+    """Without cross terms R_k enters the fused fold only through
+    W = R_k + B~'J^B~, so an invertible but indefinite R_k is solved whenever
+    R_k + B'S_{k+1}B is positive definite, as by the sequential recursion (the
+    fold's m x m inverse then takes its pivoted Gauss-Jordan branch)."""
+    inst = W.lq_instance(np.random.default_rng(5), 4, 2, 96)
+    inst.B = inst.B * 20.0            # B'S B dominates R
+    inst.R = inst.R.copy()
+    for k in (10, 40, 41, 95):
+        inst.R[k] = np.diag([0.3, -0.02])
+    ref = oracle_ref(inst)            # raises if some R_k + B'S_{k+1}B is not positive definite
+    assert ref is not None
+    per, status, _ = run(lq, [inst], seg_len=seg_len)
+    assert int(status[0]) == 0
+    check(per, [inst], tol=1e-9)
 
 
 def test_not_pd_reports_stage(lq):
