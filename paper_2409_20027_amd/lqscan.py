@@ -350,7 +350,7 @@ class LQSolveFunction(torch.autograd.Function):
         return (None,) + tuple(g.get(f) for f in names)
 
 
-def lq_solve(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None):
+def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None):
     """Differentiable LQ solve on packed device tensors; returns (x, u, status)."""
     return LQSolveFunction.apply(plan, A, B, c, Q, R, QT, x0, M, q, r, qT)
 

@@ -113,7 +113,7 @@ def test_autograd_function_matches_oracle_and_fd(lq):
     leaves = {f: prob[f].clone().requires_grad_(True) for f in names}
 
     def loss_of(t):
-        x, u, _ = lq.lq_solve(plan, *[t[f] for f in names])
+        x, u, _ = lq.solve_diff(plan, *[t[f] for f in names])
         return (x * x).sum() + (u * u).sum()
 
     L = loss_of(leaves)

@@ -58,18 +58,40 @@ def test_full_interior_point_run_matches_oracle(lq):
     assert np.all(np.abs(got["u"]) < 1.0)
 
 
-def test_benign_instance_converges(lq):
+def barrier_gradient(p, u, mu):
+    """max |dJ_mu/du| at u (the oracle's expansion: R u + grad c + B' lambda)."""
+    x = oracle.nmpc_rollout(p, u)
+    return float(np.abs(oracle.nmpc_expand(p, x, u, mu)["d"]).max())
+
+
+def benign_problem():
     import dataclasses
     p0 = W.nmpc_problem(seed=1, T=200)
-    p = dataclasses.replace(p0, W=-np.eye(4) + 0.3 * p0.W, Bm=np.ones((4, 1)))
+    return dataclasses.replace(p0, W=-np.eye(4) + 0.3 * p0.W, Bm=np.ones((4, 1)))
+
+
+def test_benign_instance_converges(lq):
+    """On a stable instance the loop converges.  Near convergence the predicted
+    decrease falls to round-off of the cost and the gain ratio is the ratio of
+    two rounding errors, so decisions there are not determined by the
+    arithmetic: they are compared while the step is well above round-off.  The
+    final iterate is then fixed only up to the flat bottom of J_mu (a cost
+    change of eps |J| moves u by about sqrt(eps) = 1.5e-8 times the
+    conditioning; 20 more oracle steps at the last barrier weight move the
+    oracle's own u by 9.4e-8).  Asserted: stationarity, |dJ_mu/du| reduced
+    below 1e-8 of its value at u0 (the oracle reaches 6.0e-9), and agreement
+    with the oracle to 1e-6."""
+    p = benign_problem()
     ref = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
     got = lq.NewtonMPC(p, seg_len=8).run(W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
-    # Near convergence the predicted decrease falls to round-off level and the
-    # gain ratio is the ratio of two rounding errors: decisions there are not
-    # determined by the arithmetic and may differ.  Decisions are compared
-    # while the step is well above round-off; the converged solutions agree.
     ok = np.abs(got["pred"]) > 1e-11 * np.abs(got["cost"])
     first_noise = int(np.argmin(ok)) if not ok.all() else len(ok)
     assert first_noise >= 3
     assert np.array_equal(got["accept"][:first_noise], ref["accept"][:first_noise])
-    assert rel(got["u"], ref["u"]) < 1e-8
+    mu = W.NMPC_MU_LEVELS[-1]
+    g0 = barrier_gradient(p, p.u0, mu)
+    g_got = barrier_gradient(p, got["u"].reshape(p.T, p.nu), mu)
+    eu = rel(got["u"], ref["u"])
+    print(f"benign instance: |dJ/du| {g_got:.2e} (u0: {g0:.2e}), u rel diff to oracle {eu:.2e}")
+    assert g_got <= 1e-8 * g0
+    assert eu < 1e-6
