@@ -96,10 +96,10 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
         const Tile SB = tnz<NK, PR>(Sh, Bh);                 // S~_{k+1} B~
         const Tile Quu = tna<NK, PR>(Bh, SB, Rk);            // R + B~'S~B~
         Tile QiT;
-        if (!spd_inverse_t(Quu, m, QiT) && !code) {
-            code = ADJ_ERR_NOT_PD;
-            fk = k;
-        }
+        const bool okq = spd_inverse_t(Quu, m, QiT);
+        const bool first = !okq && (code == 0);
+        code = first ? ADJ_ERR_NOT_PD : code;
+        fk = first ? k : fk;
         const Tile BS = tna<NK, PR>(Bh, SV, GU);             // gu + B~'s~_{k+1}
         Tile Gt = tnz<1, PR>(QiT, BS);
         Gt.v = -Gt.v;

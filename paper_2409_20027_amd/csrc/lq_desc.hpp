@@ -110,7 +110,7 @@ LQK_DEV Tile load_Ah(const ProbPtrs &P, const InstDesc &d, int k, bool with_c = 
             a = cc + i;
         else if (c == n && i == n)
             a = optr();
-        t.v[r] = *a;
+        t.v[r] = ldg(a);
     }
     return t;
 }
@@ -132,7 +132,7 @@ LQK_DEV Tile load_AhT(const ProbPtrs &P, const InstDesc &d, int k, bool with_c =
             a = cc + c;
         else if (i == n && c == n)
             a = optr();
-        t.v[r] = *a;
+        t.v[r] = ldg(a);
     }
     return t;
 }
@@ -166,7 +166,7 @@ LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
             a = qq + i;
         else if (qq && i == n && c < n)
             a = qq + c;
-        t.v[r] = *a;
+        t.v[r] = ldg(a);
     }
     return t;
 }
@@ -186,7 +186,7 @@ LQK_DEV Tile load_MhT(const ProbPtrs &P, const InstDesc &d, int k)
             p = M + c * m + a;
         else if (rr && a < m && c == n)
             p = rr + a;
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }
@@ -242,7 +242,7 @@ LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, in
             p = G + a * n + c;
         else if (a < m && c == n && gg)
             p = gg + a;
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }
@@ -262,7 +262,7 @@ LQK_DEV Tile load_GhT(const double *Gam, const double *gam, const InstDesc &d, i
             p = G + c * n + i;
         else if (c < m && i == n && gg)
             p = gg + c;
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }
@@ -284,7 +284,7 @@ LQK_DEV Tile load_Sh(const double *S, const double *s, const InstDesc &d, int k)
             p = ss + i;
         else if (i == n && c < n)
             p = ss + c;
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }
@@ -303,7 +303,7 @@ LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
             p = v + i;
         else if (c == col && i == one_row)
             p = optr();
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }

@@ -143,7 +143,7 @@ LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k)
             p = g + i;
         else if (i == n && c == n)
             p = optr();
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }
@@ -164,7 +164,7 @@ LQK_DEV Tile costate_map_t(const NmpcWork &Wk, const InstDesc &d, int k)
             p = g + c;
         else if (i == n && c == n)
             p = optr();
-        t.v[r] = *p;
+        t.v[r] = ldg(p);
     }
     return t;
 }

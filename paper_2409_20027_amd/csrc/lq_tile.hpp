@@ -103,12 +103,21 @@ __device__ double kConst01[2] = {0.0, 1.0};   // global address space: loads sta
 LQK_DEV const double *zptr() { return &kConst01[0]; }
 LQK_DEV const double *optr() { return &kConst01[1]; }
 
-// Address of p[idx] if ok, else of a constant zero.  Every tile entry is one
-// load from a per-lane address chosen before the load, so nothing depends on a
-// loaded value until it is used: independent loads issue back to back and a
-// load issued one stage ahead is only waited for where it is consumed.
+// One global load from a per-lane address that was chosen before the load.
+// The address goes through an empty asm so that the compiler sees one load of
+// an opaque address: it cannot duplicate the load into the branches of the
+// address selection, and nothing depends on a loaded value until it is used.
+// Independent loads then issue back to back and a load issued one stage ahead
+// is only waited for where it is consumed.
+LQK_DEV double ldg(const double *p)
+{
+    uint64_t a = (uint64_t)p;
+    asm("" : "+v"(a));
+    return *(const __attribute__((address_space(1))) double *)a;
+}
+// p[idx] if ok, else 0 (from a constant in memory).
 LQK_DEV const double *at(const double *p, int64_t idx, bool ok) { return ok ? p + idx : zptr(); }
-LQK_DEV double ldz(const double *p, int64_t idx, bool ok) { return *at(p, idx, ok); }
+LQK_DEV double ldz(const double *p, int64_t idx, bool ok) { return ldg(at(p, idx, ok)); }
 
 // Global memory, row-major rows x cols block with leading dimension ld,
 // placed at tile offset (i0, j0); everything else zero.
@@ -288,16 +297,71 @@ LQK_DEV double rowbcast(double x)
 // Register r of a tile for a uniform run-time r.
 LQK_DEV double treg(const d4 &v, int r) { return r == 0 ? v[0] : (r == 1 ? v[1] : (r == 2 ? v[2] : v[3])); }
 
+// Exchanges between the four 16-lane rows with the gfx950 lane-swap
+// instructions (VALU, no LDS).  permlane16_swap(x, x) returns the even rows'
+// content in both rows of each row pair ([0]) and the odd rows' content ([1]);
+// permlane32_swap(x, x) returns the low half's content in both halves ([0]) and
+// the high half's ([1]).
+LQK_DEV uint32_t xor16_u(uint32_t x)
+{
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    return (tgrp() & 1) ? s[0] : s[1];
+}
+LQK_DEV uint32_t xor32_u(uint32_t x)
+{
+    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return (tgrp() & 2) ? s[0] : s[1];
+}
+// x of lane l ^ 16 (OFF = 16) or l ^ 32 (OFF = 32).
+template <int OFF>
+LQK_DEV double xor_row(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+    const uint32_t l2 = OFF == 16 ? xor16_u(lo) : xor32_u(lo), h2 = OFF == 16 ? xor16_u(hi) : xor32_u(hi);
+    return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
+}
+template <int OFF>
+LQK_DEV int xor_row_i(int x)
+{
+    return (int)(OFF == 16 ? xor16_u((uint32_t)x) : xor32_u((uint32_t)x));
+}
+// x of row gq (uniform) at this lane's column, on every lane.
+LQK_DEV uint32_t rowsel_u(uint32_t x, int gq)
+{
+    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    const uint32_t pair = (gq & 1) ? s[1] : s[0];
+    const auto t = __builtin_amdgcn_permlane32_swap(pair, pair, false, false);
+    return (gq & 2) ? t[1] : t[0];
+}
+LQK_DEV double rowsel(double x, int gq)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = rowsel_u((uint32_t)b, gq), hi = rowsel_u((uint32_t)(b >> 32), gq);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// 1/d from the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - d r) (each squares the relative error).
+LQK_DEV double recip(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
 // ---------------------------------------------------------------------------
 // Gauss-Jordan inverse of the leading n1 x n1 block, in registers.
 //
 // In-place elimination with partial (row) pivoting: for pivot p the largest
-// |X[i][p]|, i >= p, is found over the four lanes holding column p, rows p and
-// piv are exchanged through two lane shuffles, column p reaches every lane of
-// its row by a DPP row broadcast, and the update is one FMA per register.  The
-// row exchanges turn into a column permutation of the result, undone at the
-// end by one gather.  Rows and columns >= n1 stay zero.  Returns false if a
-// pivot is zero or not finite.
+// |X[i][p]|, i >= p, is found over the four lanes holding column p (lane-swap
+// reductions), rows p and piv are exchanged by row selects, column p reaches
+// every lane of its row by a DPP row broadcast, and the update is one FMA per
+// register.  The row exchanges turn into a column permutation of the result,
+// undone at the end by one gather.  Rows and columns >= n1 stay zero.  Returns
+// false if a pivot is zero or not finite.
 // ---------------------------------------------------------------------------
 template <int P>
 LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
@@ -314,10 +378,17 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
             bi = i;
         }
     }
-#pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
-        const double ob = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
+    {
+        const double ob = xor_row<16>(best);
+        const int oi = xor_row_i<16>(bi);
+        if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+        }
+    }
+    {
+        const double ob = xor_row<32>(best);
+        const int oi = xor_row_i<32>(bi);
         if (ob > best || (ob == best && oi < bi)) {
             best = ob;
             bi = oi;
@@ -328,13 +399,13 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
     ok = ok && (pmax > 0.0) && (pmax < INFINITY);
     constexpr int gp = P & 3, rp = P >> 2;
     const int gq = piv & 3, rq = piv >> 2;
-    const double rowP = __shfl(v[rp], c + 16 * gp);
-    const double rowQ = __shfl(treg(v, rq), c + 16 * gq);
+    const double rowP = rowsel(v[rp], gp);
+    const double rowQ = rowsel(treg(v, rq), gq);
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (g == gq && r == rq) v[r] = rowP;
     if (g == gp) v[rp] = rowQ;
-    const double pinv = 1.0 / rlane(rowQ, P);
+    const double pinv = recip(rlane(rowQ, P));
     const double prow = (c == P) ? pinv : rowQ * pinv;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -380,10 +451,11 @@ LQK_DEV bool gj_inverse(Tile &X, int n1)
 }
 
 // ---------------------------------------------------------------------------
-// Per-lane small (m <= MMAX) factorisations.  The m x m block of a tile lives
-// in register 0 of lanes j + 16 i; every lane reads all of it (readlane) and
-// factorises it redundantly in registers, and the result goes back into tile
-// layout by a per-lane select.
+// Small (m <= MMAX) blocks.  The m x m block of a tile lives in register 0 of
+// lanes j + 16 i.  The solver's inverses work on it in place across those
+// lanes; the element build (not on the hot path) reads it on every lane
+// (readlane), factorises it redundantly and writes the result back by a
+// per-lane select.
 // ---------------------------------------------------------------------------
 
 // The leading m x m block of W on every lane, identity-padded to MMAX.
@@ -416,159 +488,55 @@ LQK_DEV Tile small_to_tile(const double a[MMAX][MMAX], int m)
     return t;
 }
 
-// In-register LDL' of a symmetric a (lower triangle used): a <- unit lower L
-// below the diagonal and 1/D on it.  Returns false unless every D_j > 0.
-LQK_DEV bool small_ldl(double a[MMAX][MMAX])
+// One unpivoted Gauss-Jordan step on the leading 4 x 4 block, which lives in
+// register 0 (row i in lane group i).  The pivots of the unpivoted elimination
+// are the D of W = L D L', so they are all positive iff W is positive definite.
+template <int P>
+LQK_DEV void small_gj_step(double &v0, bool &ok)
 {
-    bool ok = true;
-    double dv[MMAX];
-#pragma unroll
-    for (int j = 0; j < MMAX; ++j) {
-        double d = a[j][j];
-#pragma unroll
-        for (int p = 0; p < j; ++p) d -= a[j][p] * a[j][p] * dv[p];
-        ok = ok && (d > 0.0) && (d < INFINITY);
-        dv[j] = d;
-        const double dinv = 1.0 / d;
-#pragma unroll
-        for (int i = j + 1; i < MMAX; ++i) {
-            double w = a[i][j];
-#pragma unroll
-            for (int p = 0; p < j; ++p) w -= a[i][p] * a[j][p] * dv[p];
-            a[i][j] = w * dinv;
-        }
-        a[j][j] = dinv;
-    }
-    return ok;
+    const int c = tcol(), g = tgrp();
+    const double piv = rlane(v0, P + 16 * P);
+    ok = ok && (piv > 0.0) && (piv < INFINITY);
+    const double pinv = recip(piv);
+    const double rowP = rowsel(v0, P);     // W[P][c]
+    const double cp = rowbcast<P>(v0);     // W[g][P]
+    const double prow = (c == P) ? pinv : rowP * pinv;
+    v0 = (g == P) ? prow : ((c == P) ? -cp * pinv : fma(-cp, prow, v0));
 }
 
-// Inverse of a symmetric positive definite a (in place) through LDL'.
-// Returns false if a is not positive definite.
-LQK_DEV bool small_spd_inv(double a[MMAX][MMAX])
-{
-    const bool ok = small_ldl(a);
-    // Y = L^{-1} (unit lower)
-    double y[MMAX][MMAX];
-#pragma unroll
-    for (int j = 0; j < MMAX; ++j)
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i) {
-            double v = (i == j) ? 1.0 : 0.0;
-            if (i > j) {
-#pragma unroll
-                for (int p = j; p < i; ++p) v -= a[i][p] * (p == j ? 1.0 : y[p][j]);
-            }
-            y[i][j] = (i >= j) ? v : 0.0;
-        }
-    // a^{-1} = Y' D^{-1} Y
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) {
-            double v = 0.0;
-#pragma unroll
-            for (int p = i; p < MMAX; ++p) v += y[p][i] * a[p][p] * y[p][j];
-            a[i][j] = v;
-            a[j][i] = v;
-        }
-    return ok;
-}
-
-// In-register Gauss-Jordan inverse with partial pivoting (general matrix).
-LQK_DEV bool small_gj_inv(double a[MMAX][MMAX])
-{
-    bool ok = true;
-    int perm[MMAX];
-#pragma unroll
-    for (int p = 0; p < MMAX; ++p) {
-        int piv = p;
-        double best = fabs(a[p][p]);
-#pragma unroll
-        for (int i = p + 1; i < MMAX; ++i)
-            if (fabs(a[i][p]) > best) {
-                best = fabs(a[i][p]);
-                piv = i;
-            }
-        ok = ok && (best > 0.0) && (best < INFINITY);
-        perm[p] = piv;
-#pragma unroll
-        for (int i = p + 1; i < MMAX; ++i) {
-            const bool sw = (piv == i);
-#pragma unroll
-            for (int j = 0; j < MMAX; ++j) {
-                const double t = a[p][j];
-                a[p][j] = sw ? a[i][j] : a[p][j];
-                a[i][j] = sw ? t : a[i][j];
-            }
-        }
-        const double pinv = 1.0 / (best > 0.0 ? a[p][p] : 1.0);
-        double rowp[MMAX], colp[MMAX];
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j) rowp[j] = a[p][j] * pinv;
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i) colp[i] = a[i][p];
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-            for (int j = 0; j < MMAX; ++j) {
-                if (i == p)
-                    a[i][j] = (j == p) ? pinv : rowp[j];
-                else
-                    a[i][j] = (j == p) ? -colp[i] * pinv : a[i][j] - colp[i] * rowp[j];
-            }
-    }
-#pragma unroll
-    for (int p = MMAX - 1; p >= 0; --p) {
-#pragma unroll
-        for (int q = 0; q < MMAX; ++q) {
-            const bool sw = (perm[p] == q) && (q != p);
-#pragma unroll
-            for (int i = 0; i < MMAX; ++i) {
-                const double t = a[i][p];
-                a[i][p] = sw ? a[i][q] : a[i][p];
-                a[i][q] = sw ? t : a[i][q];
-            }
-        }
-    }
-    return ok;
-}
-
-// R(W^{-1}') for an SPD m x m block W (returned transposed so that
-// tn(result, X) = W^{-1} X).  False if W is not positive definite.
+// Inverse of a symmetric positive definite m x m block W (m <= 4) across the
+// lanes that hold it (no per-lane copy of the block).  The block is padded to
+// 4 x 4 with an identity, so the four steps run without branches and the
+// padding steps change nothing.  W^{-1} is symmetric, so the result also
+// serves as R(W^{-1}'): tn(WiT, X) = W^{-1} X.  False if W is not positive
+// definite.
 LQK_DEV bool spd_inverse_t(const Tile &W, int m, Tile &WiT)
 {
-    double a[MMAX][MMAX];
-    small_from_tile(W, m, a);
-    const bool ok = small_spd_inv(a);
-    WiT = small_to_tile<true>(a, m);
+    const int c = tcol(), g = tgrp();
+    const bool in = (c < m) && (g < m);
+    double v0 = in ? W.v[0] : ((c == g) ? 1.0 : 0.0);
+    bool ok = true;
+    small_gj_step<0>(v0, ok);
+    small_gj_step<1>(v0, ok);
+    small_gj_step<2>(v0, ok);
+    small_gj_step<3>(v0, ok);
+    WiT = tzero();
+    WiT.v[0] = in ? v0 : 0.0;
     return ok;
 }
 
-// R(W^{-1}') for a general m x m block W: LDL' when W is positive definite
-// (the usual case), pivoted Gauss-Jordan otherwise (a uniform branch: every
-// lane holds the same values).  False if W is singular.
+// Pivoted register Gauss-Jordan for an m x m block, kept out of line: it is
+// the rare branch of gen_inverse_t.
+__device__ __noinline__ bool small_pivoted_inverse(Tile &W, int m) { return gj_inverse<1>(W, m); }
+
+// Same for a symmetric m x m block that may be indefinite: the unpivoted
+// elimination when W is positive definite (the usual case), the pivoted
+// register Gauss-Jordan otherwise (a uniform branch).  False if W is singular.
 LQK_DEV bool gen_inverse_t(const Tile &W, int m, Tile &WiT)
 {
-    double a[MMAX][MMAX], b[MMAX][MMAX];
-    small_from_tile(W, m, a);
-    bool sym = true;
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-        for (int j = 0; j < MMAX; ++j) {
-            b[i][j] = a[i][j];
-            sym = sym && (a[i][j] == a[j][i]);
-        }
-    bool ok = sym && small_spd_inv(b);
-    if (!ok) {
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i)
-#pragma unroll
-            for (int j = 0; j < MMAX; ++j) b[i][j] = a[i][j];
-        ok = small_gj_inv(b);
-    }
-    WiT = small_to_tile<true>(b, m);
-    return ok;
+    if (spd_inverse_t(W, m, WiT)) return true;
+    WiT = W;
+    return small_pivoted_inverse(WiT, m);
 }
 
 // L^{-1} of the Cholesky factor of an SPD m x m block given on every lane

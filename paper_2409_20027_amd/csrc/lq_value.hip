@@ -46,35 +46,38 @@ struct StageElem {
     Tile W0;  // R                     (m x m)
 };
 
-// Stage data of the fused element build, loaded one stage ahead of its use.
+// Stage data of the fused element build, loaded ahead of its use.  MR: the
+// cross-term tiles M~' and B~' are needed (M or r present).
+template <bool MR>
 struct StageRaw {
     Tile A, Q, B, R;   // A~, Q~, B~, R
-    Tile MT, BT;       // M~' = [M', r] and B~' (only with cross terms)
+    Tile MT, BT;       // M~' = [M', r] and B~' (MR only)
 };
 
-LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, bool has_mr, StageRaw &w)
+template <bool MR>
+LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, StageRaw<MR> &w)
 {
     w.A = load_Ah(P, d, k);
     w.Q = load_Qh(P, d, k);
     w.B = load_Bh(P, d, k);
     w.R = load_R(P, d, k);
-    if (has_mr) {
+    if constexpr (MR) {
         w.MT = load_MhT(P, d, k);
         w.BT = load_BhT(P, d, k);
     }
 }
 
-// The stage element from its data.  With cross terms (M or r) the Schur
-// complement needs R^{-1}: false if R is not positive definite.
-template <int PR>
-LQK_DEV bool build_from_raw(const StageRaw &w, const InstDesc &d, bool has_mr, StageElem &e)
+// The stage element from its data.  With cross terms the Schur complement
+// needs R^{-1}: false if R is not positive definite.
+template <int PR, bool MR>
+LQK_DEV bool build_from_raw(const StageRaw<MR> &w, const InstDesc &d, StageElem &e)
 {
     e.Ab = w.A;
     e.B = w.B;
     e.J = w.Q;
     e.W0 = w.R;
     bool ok = true;
-    if (has_mr) {
+    if constexpr (MR) {
         Tile RiT;
         ok = spd_inverse_t(w.R, d.m, RiT);
         const Tile K = tnz<1, PR>(RiT, w.MT);   // R^{-1} M~'
@@ -108,6 +111,48 @@ LQK_DEV bool fold_left(const StageElem &e, Tile &U, Tile &Ch, Tile &Jh, int m)
     Ch = tna<1, PR>(Ht, WHt, Ch);                 // C^ + H W^{-1} H'
     Jh.v = Jn.v - tn<1, PR>(Pm, WP, z);           // ... - P'W^{-1}P
     return ok;
+}
+
+// First failure of a segment, recorded without branching: code/fk keep the
+// first (largest k, the fold runs right to left) failing stage.
+LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
+{
+    const bool first = !ok && (code == 0);
+    code = first ? err : code;
+    fk = first ? k : fk;
+}
+
+// One stage of the fused fold: build the element of stage k from b, then
+// refill b with stage kn (loads issued before the fold, consumed a pair later).
+template <int NK, int PR, bool MR>
+LQK_DEV void fold_stage(const ProbPtrs &P, const InstDesc &d, int k, int kn, StageRaw<MR> &b, Tile &U, Tile &Ch,
+                        Tile &Jh, int &code, int &fk)
+{
+    StageElem e;
+    note(build_from_raw<PR, MR>(b, d, e), ERR_NOT_PD, k, code, fk);
+    load_stage_raw<MR>(P, d, kn, b);
+    note(fold_left<NK, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
+}
+
+// Fused element build + fold over stages k1-1 .. k0 (right to left).  Two
+// stage buffers in ping-pong, each refilled two stages ahead right after it
+// has been consumed: a stage's loads are waited for only when that stage is
+// folded.  The loop body is straight-line (refills are unconditional, with
+// the stage index clamped into the segment) so that the buffers stay in place
+// instead of being copied between iterations.
+template <int NK, int PR, bool MR>
+LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
+                        int &code, int &fk)
+{
+    StageRaw<MR> b0, b1;
+    int k = k1 - 1;
+    load_stage_raw<MR>(P, d, k, b0);
+    load_stage_raw<MR>(P, d, max(k - 1, k0), b1);
+    for (; k - 1 >= k0; k -= 2) {
+        fold_stage<NK, PR, MR>(P, d, k, max(k - 2, k0), b0, U, Ch, Jh, code, fk);
+        fold_stage<NK, PR, MR>(P, d, k - 1, max(k - 3, k0), b1, U, Ch, Jh, code, fk);
+    }
+    if (k >= k0) fold_stage<NK, PR, MR>(P, d, k, k0, b0, U, Ch, Jh, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -190,29 +235,14 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             e.J = gload(ep + 2 * TILE);
             e.B = gload(ep + 3 * TILE);
             e.W0 = tident(m);
-            if (!fold_left<NK, PR>(e, U, Ch, Jh, m) && !code) {
-                code = ERR_SINGULAR;
-                fk = k;
-            }
+            note(fold_left<NK, PR>(e, U, Ch, Jh, m), ERR_SINGULAR, k, code, fk);
         }
     } else {
-        // fused element build; the data of stage k-1 is loaded while stage k is folded
-        const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
-        StageRaw cur, nxt;
-        load_stage_raw(P, d, k1 - 1, has_mr, cur);
-        for (int k = k1 - 1; k >= k0; --k) {
-            if (k > k0) load_stage_raw(P, d, k - 1, has_mr, nxt);
-            StageElem e;
-            if (!build_from_raw<PR>(cur, d, has_mr, e) && !code) {
-                code = ERR_NOT_PD;
-                fk = k;
-            }
-            if (!fold_left<NK, PR>(e, U, Ch, Jh, m) && !code) {
-                code = ERR_SINGULAR;
-                fk = k;
-            }
-            if (k > k0) cur = nxt;
-        }
+        // fused element build
+        if ((P.M != nullptr) || (P.r != nullptr))
+            fold_fused<NK, PR, true>(P, d, k0, k1, U, Ch, Jh, code, fk);
+        else
+            fold_fused<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk);
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
     gstore(o, ttrans(U, lds));
@@ -325,10 +355,7 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         const Tile Qux = tna<NK, PR>(Bh, SA, MhT);    // M~' + B~'S~'A~
         Tile Sn = tna<NK, PR>(Ah, SA, Qh);            // Q~ + A~'S~'A~
         Tile QiT;
-        if (!spd_inverse_t(Quu, m, QiT) && !code) {
-            code = ERR_NOT_PD;
-            fk = k;
-        }
+        note(spd_inverse_t(Quu, m, QiT), ERR_NOT_PD, k, code, fk);
         Tile Gh = tnz<1, PR>(QiT, Qux);
         Gh.v = -Gh.v;                                 // -Q_uu^{-1} Q_ux~
         Sn = tna<1, PR>(Qux, Gh, Sn);                 // + Q_ux~' Gamma~
