@@ -20,6 +20,9 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # packed FP32 instructions are kept out of generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # matrix-instruction accumulators in ordinary VGPRs: no copies between
+         # register files and fewer registers per wave (more waves per SIMD)
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 

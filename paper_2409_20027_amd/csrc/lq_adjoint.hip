@@ -75,24 +75,12 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     Tile SV = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);   // [[0, s~_{k1}], [0, 1]]
     if (s == d.nseg - 1) store_vec(J.st + d.os + (int64_t)d.T * n, SV, n, n);
     int code = 0, fk = 0;
-    // stage data of stage k-1 is loaded while stage k is processed
-    Tile nB = load_Bh(P, d, k1 - 1), nBT = load_BhT(P, d, k1 - 1), nS = load_Sh(J.S, J.s, d, k1);
-    Tile nR = load_R(P, d, k1 - 1), nA = load_Ah(P, d, k1 - 1, false), nG = load_Gh(J.G, nullptr, d, k1 - 1);
-    Tile nGU = load_vec(J.gu + d.og + (int64_t)(k1 - 1) * m, m, n, -1);
-    Tile nGX = load_vec(J.gx + d.os + (int64_t)(k1 - 1) * n, n, n, -1);
     Tile PhiT = tident(n + 1);
     for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Bh = nB, BhT = nBT, Sh = nS, Rk = nR, An = nA, G0 = nG, GU = nGU, GX = nGX;
-        if (k > k0) {
-            nB = load_Bh(P, d, k - 1);
-            nBT = load_BhT(P, d, k - 1);
-            nS = load_Sh(J.S, J.s, d, k);
-            nR = load_R(P, d, k - 1);
-            nA = load_Ah(P, d, k - 1, false);
-            nG = load_Gh(J.G, nullptr, d, k - 1);
-            nGU = load_vec(J.gu + d.og + (int64_t)(k - 1) * m, m, n, -1);
-            nGX = load_vec(J.gx + d.os + (int64_t)(k - 1) * n, n, n, -1);
-        }
+        const Tile Bh = load_Bh(P, d, k), BhT = load_BhT(P, d, k), Sh = load_Sh(J.S, J.s, d, k + 1);
+        const Tile Rk = load_R(P, d, k), An = load_Ah(P, d, k, false), G0 = load_Gh(J.G, nullptr, d, k);
+        const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
+        const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
         const Tile SB = tnz<NK, PR>(Sh, Bh);                 // S~_{k+1} B~
         const Tile Quu = tna<NK, PR>(Bh, SB, Rk);            // R + B~'S~B~
         Tile QiT;
@@ -129,22 +117,11 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int n = d.n, m = d.m;
     Tile DX = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, dx_k0], [0, 1]]
     if (s == 0 && Gr.x0) store_vec(Gr.x0 + d.on, tnz<NK, PR>(load_Sh(J.S, J.st, d, 0), DX), n, n);
-    // stage data of stage k+1 is loaded while stage k is processed
-    Tile nGT = load_GhT(J.G, J.gt, d, k0), nBT = load_BhT(P, d, k0), nAT = load_AhT(P, d, k0, false);
-    Tile nS = load_Sh(J.S, J.st, d, k0 + 1);
-    Tile nX = load_vec(J.x + d.os + (int64_t)k0 * n, n, n, -1), nU = load_vec(J.u + d.og + (int64_t)k0 * m, m, n, -1);
-    Tile nL = load_vec(J.lam + d.os + (int64_t)(k0 + 1) * n, n, n, -1);
     for (int k = k0; k < k1; ++k) {
-        const Tile GhT = nGT, BhT = nBT, AnT = nAT, S1 = nS, X = nX, U = nU, L1 = nL;
-        if (k + 1 < k1) {
-            nGT = load_GhT(J.G, J.gt, d, k + 1);
-            nBT = load_BhT(P, d, k + 1);
-            nAT = load_AhT(P, d, k + 1, false);
-            nS = load_Sh(J.S, J.st, d, k + 2);
-            nX = load_vec(J.x + d.os + (int64_t)(k + 1) * n, n, n, -1);
-            nU = load_vec(J.u + d.og + (int64_t)(k + 1) * m, m, n, -1);
-            nL = load_vec(J.lam + d.os + (int64_t)(k + 2) * n, n, n, -1);
-        }
+        const Tile GhT = load_GhT(J.G, J.gt, d, k), BhT = load_BhT(P, d, k), AnT = load_AhT(P, d, k, false);
+        const Tile S1 = load_Sh(J.S, J.st, d, k + 1);
+        const Tile X = load_vec(J.x + d.os + (int64_t)k * n, n, n, -1), U = load_vec(J.u + d.og + (int64_t)k * m, m, n, -1);
+        const Tile L1 = load_vec(J.lam + d.os + (int64_t)(k + 1) * n, n, n, -1);
         const Tile DU = tnz<NK, PR>(GhT, DX);                          // Gamma dx + gamma~
         const Tile DXn = tna<1, PR>(BhT, DU, tnz<NK, PR>(AnT, DX));    // A dx + B du
         const Tile DL1 = tnz<NK, PR>(S1, DXn);                         // S dx' + s~'

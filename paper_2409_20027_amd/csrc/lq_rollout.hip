@@ -40,17 +40,8 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     // scanned entry s.
     if (s == d.nseg - 1) return;
     Tile Phi = tident(d.n + 1);
-    // stage data of stage k+1 is loaded while stage k is folded
-    Tile nA = load_AhT(P, d, k0), nG = load_Gh(V.G, V.g, d, k0), nB = load_BhT(P, d, k0);
-    for (int k = k0; k < k1; ++k) {
-        const Tile AhT = nA, Gh = nG, BhT = nB;
-        if (k + 1 < k1) {
-            nA = load_AhT(P, d, k + 1);
-            nG = load_Gh(V.G, V.g, d, k + 1);
-            nB = load_BhT(P, d, k + 1);
-        }
-        Phi = tnz<NK, PR>(closed_loop_t<PR>(AhT, Gh, BhT), Phi);   // F~ Phi
-    }
+    for (int k = k0; k < k1; ++k)
+        Phi = tnz<NK, PR>(closed_loop_t<PR>(load_AhT(P, d, k), load_Gh(V.G, V.g, d, k), load_BhT(P, d, k)), Phi);   // F~ Phi
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
 
@@ -96,17 +87,9 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
     Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
-    // stage data of stage k+1 is loaded while stage k is processed
-    Tile nG = load_GhT(V.G, V.g, d, k0), nA = load_AhT(P, d, k0), nB = load_BhT(P, d, k0);
-    Tile nS = lam ? load_Sh(V.S, V.s, d, k0) : tzero();
     for (int k = k0; k < k1; ++k) {
-        const Tile GhT = nG, AhT = nA, BhT = nB, Sh = nS;
-        if (k + 1 < k1) {
-            nG = load_GhT(V.G, V.g, d, k + 1);
-            nA = load_AhT(P, d, k + 1);
-            nB = load_BhT(P, d, k + 1);
-            if (lam) nS = load_Sh(V.S, V.s, d, k + 1);
-        }
+        const Tile GhT = load_GhT(V.G, V.g, d, k), AhT = load_AhT(P, d, k), BhT = load_BhT(P, d, k);
+        const Tile Sh = lam ? load_Sh(V.S, V.s, d, k) : tzero();
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
         const Tile Uk = tnz<NK, PR>(GhT, X);                       // Gamma~ x~
         store_vec(u + d.og + (int64_t)k * m, Uk, m, n);

@@ -527,7 +527,7 @@ LQK_DEV bool spd_inverse_t(const Tile &W, int m, Tile &WiT)
 
 // Pivoted register Gauss-Jordan for an m x m block, kept out of line: it is
 // the rare branch of gen_inverse_t.
-__device__ __noinline__ bool small_pivoted_inverse(Tile &W, int m) { return gj_inverse<1>(W, m); }
+LQK_DEV bool small_pivoted_inverse(Tile &W, int m) { return gj_inverse<1>(W, m); }
 
 // Same for a symmetric m x m block that may be indefinite: the unpivoted
 // elimination when W is positive definite (the usual case), the pivoted

@@ -122,37 +122,21 @@ LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
     fk = first ? k : fk;
 }
 
-// One stage of the fused fold: build the element of stage k from b, then
-// refill b with stage kn (loads issued before the fold, consumed a pair later).
-template <int NK, int PR, bool MR>
-LQK_DEV void fold_stage(const ProbPtrs &P, const InstDesc &d, int k, int kn, StageRaw<MR> &b, Tile &U, Tile &Ch,
-                        Tile &Jh, int &code, int &fk)
-{
-    StageElem e;
-    note(build_from_raw<PR, MR>(b, d, e), ERR_NOT_PD, k, code, fk);
-    load_stage_raw<MR>(P, d, kn, b);
-    note(fold_left<NK, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
-}
-
-// Fused element build + fold over stages k1-1 .. k0 (right to left).  Two
-// stage buffers in ping-pong, each refilled two stages ahead right after it
-// has been consumed: a stage's loads are waited for only when that stage is
-// folded.  The loop body is straight-line (refills are unconditional, with
-// the stage index clamped into the segment) so that the buffers stay in place
-// instead of being copied between iterations.
+// Fused element build + fold over stages k1-1 .. k0 (right to left).  Each
+// stage's data is loaded at the top of its own step: the fold keeps few
+// registers, so several waves share a SIMD and cover each other's load
+// latency, which pays more than a prefetch buffer held across steps.
 template <int NK, int PR, bool MR>
 LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
                         int &code, int &fk)
 {
-    StageRaw<MR> b0, b1;
-    int k = k1 - 1;
-    load_stage_raw<MR>(P, d, k, b0);
-    load_stage_raw<MR>(P, d, max(k - 1, k0), b1);
-    for (; k - 1 >= k0; k -= 2) {
-        fold_stage<NK, PR, MR>(P, d, k, max(k - 2, k0), b0, U, Ch, Jh, code, fk);
-        fold_stage<NK, PR, MR>(P, d, k - 1, max(k - 3, k0), b1, U, Ch, Jh, code, fk);
+    for (int k = k1 - 1; k >= k0; --k) {
+        StageRaw<MR> b;
+        load_stage_raw<MR>(P, d, k, b);
+        StageElem e;
+        note(build_from_raw<PR, MR>(b, d, e), ERR_NOT_PD, k, code, fk);
+        note(fold_left<NK, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
     }
-    if (k >= k0) fold_stage<NK, PR, MR>(P, d, k, k0, b0, U, Ch, Jh, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -333,22 +317,12 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
     }
     int code = 0, fk = 0;
-    // stage data of stage k-1 is loaded while stage k is processed
-    Tile nAh = load_Ah(P, d, k1 - 1), nBh = load_Bh(P, d, k1 - 1), nQh = load_Qh(P, d, k1 - 1);
-    Tile nRk = load_R(P, d, k1 - 1), nMhT = has_mr ? load_MhT(P, d, k1 - 1) : tzero();
     const bool roll = (Yroll != nullptr);
-    Tile nBT = roll ? load_BhT(P, d, k1 - 1) : tzero();
     Tile PhiT = tident(n + 1);
     for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Ah = nAh, Bh = nBh, Qh = nQh, Rk = nRk, MhT = nMhT, BhT = nBT;
-        if (k > k0) {
-            nAh = load_Ah(P, d, k - 1);
-            nBh = load_Bh(P, d, k - 1);
-            nQh = load_Qh(P, d, k - 1);
-            nRk = load_R(P, d, k - 1);
-            if (has_mr) nMhT = load_MhT(P, d, k - 1);
-            if (roll) nBT = load_BhT(P, d, k - 1);
-        }
+        const Tile Ah = load_Ah(P, d, k), Bh = load_Bh(P, d, k), Qh = load_Qh(P, d, k), Rk = load_R(P, d, k);
+        const Tile MhT = has_mr ? load_MhT(P, d, k) : tzero();
+        const Tile BhT = roll ? load_BhT(P, d, k) : tzero();
         const Tile SB = tnz<NK, PR>(St, Bh);          // S~'B~
         const Tile SA = tnz<NK, PR>(St, Ah);          // S~'A~
         const Tile Quu = tna<NK, PR>(Bh, SB, Rk);     // R + B~'S~'B~
