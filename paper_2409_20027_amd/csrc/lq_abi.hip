@@ -276,7 +276,7 @@ static void rollout_scan_apply(const lq_plan *p, const lqk::ProbPtrs &P, const l
     double *in = Ya, *o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ROLL_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
                 lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
                                       o);
                 std::swap(in, o);
@@ -359,7 +359,7 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
     double *in = Ya, *o = Yb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
                 lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
                 std::swap(in, o);
             }
@@ -375,7 +375,7 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
     o = fwd2;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
                 lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in, o);
                 std::swap(in, o);
             }
@@ -480,7 +480,7 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x);
     lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
     double *in = Ya, *o = Yb;
-    for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+    for (int dd = 1; dd < p->max_nseg; dd *= 4) {
         lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
         std::swap(in, o);
     }

@@ -45,9 +45,15 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
 
-// One Kogge-Stone level over entries [xbase, xbase + nseg] of each instance.
-// suffix = 0: Y_s <- Y_s Y_{s-dd} for s >= dd;  suffix = 1: Y_s <- Y_s Y_{s+dd}
-// for s + dd <= nseg; other entries are copied.  The entry that no segment
+// One radix-4 Kogge-Stone level over entries [xbase, xbase + nseg] of each
+// instance, distance dd:
+//   prefix (suffix = 0): Y_s <- Y_s Y_{s-dd} Y_{s-2dd} Y_{s-3dd}
+//   suffix (suffix = 1): Y_s <- Y_s Y_{s+dd} Y_{s+2dd} Y_{s+3dd}
+// with the terms that fall outside [0, nseg] left out; after the level with
+// distance dd an entry covers 4 dd entries, so dd = 1, 4, 16, ... reaches
+// every prefix (suffix) in ceil(log4(nseg + 1)) levels.  The product is
+// carried transposed (P' <- Y_j' P' is a register product), so a level takes
+// two LDS transposes whatever the number of terms.  The entry that no segment
 // reads (the last of a prefix scan, the first of a suffix scan) is skipped.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ inst,
@@ -62,14 +68,21 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     const int s = gx - d.xbase;
     if (suffix ? (s == 0) : (s == d.nseg)) return;   // entries that are never read
     const Tile a = gload(Yin + (int64_t)gx * TILE);
-    const bool active = suffix ? (s + dd <= d.nseg) : (s >= dd);
-    if (!active) {
+    const int avail = suffix ? (d.nseg - s) / dd : s / dd;   // terms that exist on that side
+    const int terms = min(3, avail);
+    if (terms == 0) {
         gstore(Yout + (int64_t)gx * TILE, a);
         return;
     }
-    const int64_t ob = suffix ? gx + dd : gx - dd;
-    const Tile b = gload(Yin + ob * TILE);
-    gstore(Yout + (int64_t)gx * TILE, tnz<NK, PR>(ttrans(a, lds), b));
+    const int64_t step = suffix ? dd : -dd;
+    // issue every term's load before the first product
+    const Tile b1 = gload(Yin + (gx + step) * TILE);
+    const Tile b2 = terms >= 2 ? gload(Yin + (gx + 2 * step) * TILE) : tzero();
+    const Tile b3 = terms >= 3 ? gload(Yin + (gx + 3 * step) * TILE) : tzero();
+    Tile PT = tnz<NK, PR>(b1, ttrans(a, lds));     // (a b1)'
+    if (terms >= 2) PT = tnz<NK, PR>(b2, PT);      // (a b1 b2)'
+    if (terms >= 3) PT = tnz<NK, PR>(b3, PT);      // (a b1 b2 b3)'
+    gstore(Yout + (int64_t)gx * TILE, ttrans(PT, lds));
 }
 
 // From the state at the segment start: u_k = Gamma~ x~, lambda_k = S~_k x~,

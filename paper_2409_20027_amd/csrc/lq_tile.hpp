@@ -326,6 +326,27 @@ LQK_DEV int xor_row_i(int x)
 {
     return (int)(OFF == 16 ? xor16_u((uint32_t)x) : xor32_u((uint32_t)x));
 }
+// max of x over each pair of rows {0,1}, {2,3} (OFF = 16) or over the two
+// halves (OFF = 32), on every lane: one swap leaves one row's values in one
+// register and the other row's in the other, so no select is needed.
+template <int OFF>
+LQK_DEV double rowmax(double x)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+    uint32_t l0, l1, h0, h1;
+    if constexpr (OFF == 16) {
+        const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = sl[0]; l1 = sl[1]; h0 = sh[0]; h1 = sh[1];
+    } else {
+        const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = sl[0]; l1 = sl[1]; h0 = sh[0]; h1 = sh[1];
+    }
+    return fmax(__builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0), __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1));
+}
+
 // x of row gq (uniform) at this lane's column, on every lane.
 LQK_DEV uint32_t rowsel_u(uint32_t x, int gq)
 {
@@ -367,52 +388,44 @@ template <int P>
 LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
 {
     const int c = tcol(), g = tgrp();
-    double best = -1.0;
-    int bi = P;
+    // pivot search over rows P..n1-1 of column P: max |x| over the lane's four
+    // registers and then over the four lanes of the column (lane swaps)
+    double a[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + g;
-        const double a = fabs(v[r]);
-        if (c == P && i >= P && i < n1 && a > best) {
-            best = a;
-            bi = i;
-        }
+        a[r] = (c == P && i >= P && i < n1) ? fabs(v[r]) : -1.0;
     }
-    {
-        const double ob = xor_row<16>(best);
-        const int oi = xor_row_i<16>(bi);
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
-    }
-    {
-        const double ob = xor_row<32>(best);
-        const int oi = xor_row_i<32>(bi);
-        if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-        }
-    }
-    const int piv = __builtin_amdgcn_readlane(bi, P);
-    const double pmax = rlane(best, P);
+    double mx = fmax(fmax(a[0], a[1]), fmax(a[2], a[3]));
+    mx = rowmax<32>(rowmax<16>(mx));
+    const double pmax = rlane(mx, P);
     ok = ok && (pmax > 0.0) && (pmax < INFINITY);
+    // the lowest row holding the maximum: one ballot per register; row 4r + g
+    // of column P is bit P + 16 g of register r's ballot
+    uint32_t rows = 0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t bal = __ballot(a[r] == pmax);
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) rows |= (uint32_t)((bal >> (P + 16 * gg)) & 1u) << (4 * r + gg);
+    }
+    const int piv = rows ? __builtin_ctz(rows) : P;
     constexpr int gp = P & 3, rp = P >> 2;
     const int gq = piv & 3, rq = piv >> 2;
-    const double rowP = rowsel(v[rp], gp);
-    const double rowQ = rowsel(treg(v, rq), gq);
+    const double rowQ = rowsel(treg(v, rq), gq);   // pivot row
+    const double rowP = rowsel(v[rp], gp);          // row P, moves to the pivot row's place
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        if (g == gq && r == rq) v[r] = rowP;
-    if (g == gp) v[rp] = rowQ;
+        if (r == rq && g == gq) v[r] = rowP;
     const double pinv = recip(rlane(rowQ, P));
-    const double prow = (c == P) ? pinv : rowQ * pinv;
+    const double prow = rowQ * pinv;
+    // v - colp (x) w is the whole elimination step for every row but P: with
+    // w[P] = 1 + 1/pivot, column P becomes -colp/pivot.  Row P becomes wP.
+    const double w = (c == P) ? 1.0 + pinv : prow;
+    const double wP = (c == P) ? pinv : prow;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const double cp = rowbcast<P>(v[r]);
-        const int i = 4 * r + g;
-        v[r] = (i == P) ? prow : ((c == P) ? -cp * pinv : fma(-cp, prow, v[r]));
-    }
+    for (int r = 0; r < 4; ++r) v[r] = fma(-rowbcast<P>(v[r]), w, v[r]);
+    if (g == gp) v[rp] = wP;
     piv_out = piv;
 }
 
