@@ -347,6 +347,16 @@ LQK_DEV double rowmax(double x)
     return fmax(__builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0), __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1));
 }
 
+// min of an int over row pairs (OFF = 16) or halves (OFF = 32), like rowmax.
+template <int OFF>
+LQK_DEV int rowmin_i(int x)
+{
+    const uint32_t u = (uint32_t)x;
+    const auto sw = OFF == 16 ? __builtin_amdgcn_permlane16_swap(u, u, false, false)
+                              : __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return min((int)sw[0], (int)sw[1]);
+}
+
 // x of row gq (uniform) at this lane's column, on every lane.
 LQK_DEV uint32_t rowsel_u(uint32_t x, int gq)
 {
@@ -400,16 +410,13 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
     mx = rowmax<32>(rowmax<16>(mx));
     const double pmax = rlane(mx, P);
     ok = ok && (pmax > 0.0) && (pmax < INFINITY);
-    // the lowest row holding the maximum: one ballot per register; row 4r + g
-    // of column P is bit P + 16 g of register r's ballot
-    uint32_t rows = 0;
+    // the lowest row holding the maximum (min of the candidate row indices
+    // over the lane's registers, then over the column's four lanes)
+    int ri = 64;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t bal = __ballot(a[r] == pmax);
-#pragma unroll
-        for (int gg = 0; gg < 4; ++gg) rows |= (uint32_t)((bal >> (P + 16 * gg)) & 1u) << (4 * r + gg);
-    }
-    const int piv = rows ? __builtin_ctz(rows) : P;
+    for (int r = 3; r >= 0; --r) ri = (a[r] == pmax) ? 4 * r + g : ri;
+    ri = rowmin_i<32>(rowmin_i<16>(ri));
+    const int piv = __builtin_amdgcn_readlane(ri, P);
     constexpr int gp = P & 3, rp = P >> 2;
     const int gq = piv & 3, rq = piv >> 2;
     const double rowQ = rowsel(treg(v, rq), gq);   // pivot row
@@ -430,25 +437,29 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
 }
 
 template <int P, int PMAX>
-LQK_DEV void gj_steps(d4 &v, int n1, bool &ok, int *perm)
+LQK_DEV void gj_steps(d4 &v, int n1, int steps, bool &ok, int *perm)
 {
     if constexpr (P < PMAX) {
-        if (P < n1) {
+        if (P < steps) {
             gj_step<P>(v, n1, ok, perm[P]);
-            gj_steps<P + 1, PMAX>(v, n1, ok, perm);
+            gj_steps<P + 1, PMAX>(v, n1, steps, ok, perm);
         }
     }
 }
 
 // Inverse of the leading n1 x n1 block of X (n1 <= 4 * NK), zero elsewhere.
+// homog: X has the form [[M, 0], [r, 1]] (last column e_n, as I + J~ C~ for a
+// homogeneous C~ with zero last row and column); pivots are then taken among
+// the first n1 - 1 rows and the last step, a no-op, is skipped.
 template <int NK>
-LQK_DEV bool gj_inverse(Tile &X, int n1)
+LQK_DEV bool gj_inverse(Tile &X, int n1, bool homog = false)
 {
     bool ok = true;
     int perm[4 * NK];
 #pragma unroll
     for (int p = 0; p < 4 * NK; ++p) perm[p] = p;
-    gj_steps<0, 4 * NK>(X.v, n1, ok, perm);
+    const int rows = homog ? n1 - 1 : n1;
+    gj_steps<0, 4 * NK>(X.v, rows, rows, ok, perm);
     // result column j is column src(j) of the eliminated matrix, src being the
     // composition of the row exchanges taken in order
     int x = tcol();

@@ -269,8 +269,8 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const int n1 = d.n + 1;
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
     const Tile A2 = gload(b), C2 = gload(b + TILE), J2 = gload(b + 2 * TILE);
-    Tile YT = tna<NK, PR>(J2, C1, tident(n1));   // X' = I + J~2 C~1
-    const bool ok = gj_inverse<NK>(YT, n1);      // X^{-T}
+    Tile YT = tna<NK, PR>(J2, C1, tident(n1));   // X' = I + J~2 C~1 = [[I + J C, 0], [-eta' C, 1]]
+    const bool ok = gj_inverse<NK>(YT, n1, true);   // X^{-T}
     const Tile Z = tnz<NK, PR>(YT, A1);          // X^{-1} A~1
     const Tile JA = tnz<NK, PR>(J2, A1);         // J~2 A~1
     const Tile Jn = tna<NK, PR>(Z, JA, J1);      // A~1'X^{-T}J~2 A~1 + J~1
