@@ -79,31 +79,63 @@ def stored_traffic(kernel: str):
 # ---------------------------------------------------------------------------
 
 
-def kernel_models(n, m):
+def kernel_models(n, m, T=16384, L=16):
+    """Per-step algorithmic cost of each timed phase: flops, bytes and the
+    number of kernel launches it takes (scans: one launch per level)."""
     n1 = n + 1
     d = 8.0
-    return {
-        # element build + rank-m left fold: J^G, A^G, J^Ab, A^Ab, Ab'J^Ab, G'J^G, G'J^Ab, two W^{-1}
-        # products and three rank-m updates
+    per_stage = {
+        # element build + rank-m left fold: J^B, J^A, B'J^B, B'J^A, A'J^A, B'A^', A'A^', the m x m
+        # inverse and four rank-m products
         "value_fold": {"flops": 6 * n1 ** 3 + 12 * n1 ** 2 * m + 6 * n1 * m ** 2,
                        "bytes": d * (2 * n * n + n * m + n + m * m)},
-        # Bellman step: S'B, S'A, B'S'B, B'S'A, A'S'A, Q_uu^{-1} Q_ux, Q_ux' Gamma
-        "value_bellman": {"flops": 4 * n1 ** 3 + 6 * n1 ** 2 * m + 4 * n1 * m ** 2,
+        # Bellman step: S'B, S'A, B'S'B, B'S'A, A'S'A, Q_uu^{-1} Q_ux, Q_ux' Gamma, plus the
+        # rollout's segment map (F = A + B Gamma, Phi F)
+        "value_bellman": {"flops": 4 * n1 ** 3 + 6 * n1 ** 2 * m + 4 * n1 * m ** 2 + 2 * n1 ** 3 + 2 * n1 ** 2 * m,
                           "bytes": d * (2 * n * n + n * m + n + m * m + n * n + n + m * n + m)},
-        "roll_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m,
-                      "bytes": d * (n * n + n * m + n + m * n + m)},
         "roll_apply": {"flops": 4 * n1 ** 2 + 4 * m * n1,
                        "bytes": d * (2 * n * n + 2 * m * n + 4 * n + 2 * m)},
         "adj_back_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m + 2 * n1 * m,
                           "bytes": d * (n * n + 2 * n * m + 2 * m + n)},
-        "adj_back_apply": {"flops": 2 * n1 ** 3 + 6 * n1 ** 2 * m + 4 * n1 * m ** 2 + 2 * n1 ** 2,
+        "adj_back_apply": {"flops": 4 * n1 ** 3 + 8 * n1 ** 2 * m + 4 * n1 * m ** 2 + 2 * n1 ** 2,
                            "bytes": d * (2 * n * n + 2 * n * m + m * m + 3 * n + 3 * m)},
-        "adj_fwd_fold": {"flops": 2 * n1 ** 3 + 2 * n1 ** 2 * m,
-                         "bytes": d * (n * n + 2 * n * m + m)},
         "adj_fwd_apply": {"flops": 6 * n1 ** 2 + 4 * m * n1 + 8 * n * n + 8 * n * m + 2 * m * m,
                           "bytes": d * (3 * n * n + 2 * n * m + 4 * n + 2 * m
                                         + 2 * n * n + 2 * n * m + 2 * n + m * m + m)},
     }
+    out = {k: {"flops": v["flops"] * T, "bytes": v["bytes"] * T, "launches": 1, "units": T,
+               "unit_name": "stages"} for k, v in per_stage.items()}
+    # value scan: radix-2 Kogge-Stone over the nseg segment elements plus the
+    # terminal; per level each entry s >= 1 either combines with s + dd (a full
+    # combine, or a J-only one when the right operand already covers the
+    # terminal) or carries its J over.  A combine reads 6 (n1 x n1) matrices
+    # and writes 3; its flops: X' (2 n1^2 n), the n x n Gauss-Jordan inverse
+    # (2 n^3), Z, J2 A1, the J rule (3 x 2 n1^3), A2 Z, X^{-1} C1, two C
+    # products (2 n1^3 + 2 n1^2 n + 2 x 2 n1^3).
+    nseg = -(-T // L)
+    full_f = 2 * n1 * n1 * n + 2 * n ** 3 + 6 * n1 ** 3 + 2 * n1 ** 3 + 2 * n1 * n1 * n + 4 * n1 ** 3
+    jonly_f = 2 * n1 * n1 * n + 2 * n ** 3 + 6 * n1 ** 3
+    mat = d * n1 * n1
+    fl = by = 0.0
+    lev = combines = 0
+    dd = 1
+    while dd < nseg:
+        lev += 1
+        for s_ in range(1, nseg + 1):
+            if s_ + dd > nseg:
+                by += 2 * mat
+            elif s_ + 2 * dd - 1 >= nseg:
+                fl += jonly_f
+                by += 5 * mat
+                combines += 1
+            else:
+                fl += full_f
+                by += 9 * mat
+                combines += 1
+        dd *= 2
+    out["value_scan"] = {"flops": fl, "bytes": by, "launches": max(lev, 1), "units": combines,
+                         "unit_name": "element combines"}
+    return out
 
 
 def cpu_baseline(inst, budget_s: float = 10.0) -> dict:
@@ -190,7 +222,7 @@ def main():
     phases = plan.phase_times()
     plan.set_timing([], 0)
     breakdown = {k: v[0] / prof_steps for k, v in phases.items()}
-    models = kernel_models(n, m)
+    models = kernel_models(n, m, T, plan.seg_len())
     dominant = max((k for k in breakdown if k in models), key=lambda k: breakdown[k])
 
     # timed pass: events only around the dominant kernel
@@ -272,9 +304,11 @@ def main():
                "what": "same step (forward + adjoint) with one segment: sequential recursions on the GPU"}
 
     mdl = models[dominant]
-    avg_s = dom_ms / max(dom_launches, 1) * 1e-3
-    flops = mdl["flops"] * T
-    nbytes = mdl["bytes"] * T
+    # average duration of one kernel launch of the dominant phase (a scan phase
+    # is timed as a whole: its time divided by its number of levels)
+    avg_s = dom_ms / max(dom_launches, 1) / mdl["launches"] * 1e-3
+    flops = mdl["flops"] / mdl["launches"]
+    nbytes = mdl["bytes"] / mdl["launches"]
     tf = flops / avg_s / 1e12
     gbs = nbytes / avg_s / 1e9
     if tf / FP64_PEAK_TFLOPS >= gbs / HBM_PEAK_GBS:
@@ -284,8 +318,13 @@ def main():
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": gbs / HBM_PEAK_GBS}
     roof.update({"traffic": stored_traffic(dominant), "kernel": dominant, "avg_launch_us": avg_s * 1e6,
-                 "flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                 "flops_per_stage": mdl["flops"], "bytes_per_stage": mdl["bytes"], "units_per_launch": T})
+                 "launches_per_step": mdl["launches"], "flops_per_launch": flops,
+                 "algorithmic_bytes_per_launch": nbytes,
+                 "units_per_step": mdl["units"], "unit": roof["unit"], "unit_of_work": mdl["unit_name"],
+                 "other_bound": ({"achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+                                 if roof["bound"] == "mfma" else
+                                 {"achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": tf / FP64_PEAK_TFLOPS})})
 
     out = {"metric": "LQ stage-steps/sec (forward + adjoint, n=12, m=4, T=16384, FP64)",
            "value": T * args.steps / (total_ms * 1e-3), "unit": "stage-steps/s", "n_gpus": 1,
