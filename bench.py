@@ -157,6 +157,103 @@ def cpu_baseline(inst, budget_s: float = 10.0) -> dict:
                       f"in {dt:.1f} s on one host core"}
 
 
+def batched(lqscan, workloads, dev, steps: int, warmup: int) -> dict:
+    """Throughput of the batched workloads (inputs generated on the device):
+    the differentiated batch (256 instances, n=12, m=4, T=4096, forward +
+    adjoint) and the ragged batch (4096 instances, T ~ U{32..2048},
+    n in {2, 4, 12}, m = max(1, n/3), forward), each with the plain sequential
+    path (one segment per instance) beside it."""
+    import torch
+
+    def timeit(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    res = {}
+    # differentiated batch
+    sizes = [(12, 4, 4096)] * 256
+    prob = workloads.device_batch(sizes, seed=4, a_scale=0.02, r_fixed=0.1, device=dev)
+    stages = 256 * 4096
+    for mode in ("scan", "sequential"):
+        plan = lqscan.Plan([12] * 256, [4] * 256, [4096] * 256, mode=mode)
+        ws = plan.new_workspace(dev)
+        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
+        val = lqscan.value_buffers(plan, dev)
+        st = lqscan.state_buffers(plan, dev)
+        grads = lqscan.grad_buffers(plan, ("A", "B", "c", "Q", "R", "QT", "x0"), dev)
+        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+        torch.cuda.synchronize()
+        gx, gu = 2 * st["x"], 2 * st["u"]
+
+        def step():
+            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+            lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, ws, status)
+
+        ms = timeit(step, steps if mode == "scan" else 2)
+        assert int(status.abs().sum()) == 0
+        res[f"batch256_T4096_fwd_adj_{mode}"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3),
+                                                 "unit": "stage-steps/s", "seg_len": plan.seg_len()}
+        del ws, val, st, grads, gx, gu
+    del prob
+    torch.cuda.empty_cache()
+    # ragged batch, ordered by size class
+    _, ns, ms_, Ts = workloads.cfg3_ragged_sizes()
+    order = np.lexsort((Ts, ns))
+    sizes = [(int(ns[i]), int(ms_[i]), int(Ts[i])) for i in order]
+    prob = workloads.device_batch(sizes, seed=3, a_scale=0.05, device=dev)
+    stages = int(sum(t for _, _, t in sizes))
+    for mode in ("scan", "sequential"):
+        plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], mode=mode)
+        ws = plan.new_workspace(dev)
+        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
+        val = lqscan.value_buffers(plan, dev)
+        st = lqscan.state_buffers(plan, dev)
+
+        def fwd():
+            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+
+        ms = timeit(fwd, steps if mode == "scan" else 2)
+        assert int(status.abs().sum()) == 0
+        res[f"ragged4096_fwd_{mode}"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3), "unit": "stage-steps/s",
+                                         "stages": stages}
+        del ws, val, st
+    # the same batch with per-class segment lengths from the autotuner
+    from paper_2409_20027_amd import autotune
+
+    def make_prob(sel):
+        sub = [sizes[j] for j in sel]
+        return workloads.device_batch(sub, seed=5, a_scale=0.05, device=dev)
+
+    t0 = time.perf_counter()
+    seg, _ = autotune.tune_sizes(sizes, make_prob, reps=2)
+    tune_s = time.perf_counter() - t0
+    plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], seg_lens=seg)
+    ws = plan.new_workspace(dev)
+    status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
+    val = lqscan.value_buffers(plan, dev)
+    st = lqscan.state_buffers(plan, dev)
+
+    def fwd_t():
+        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+
+    ms = timeit(fwd_t, steps)
+    assert int(status.abs().sum()) == 0
+    res["ragged4096_fwd_autotuned"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3), "unit": "stage-steps/s",
+                                       "tuning_s": tune_s, "choice": autotune.seg_lens_summary(sizes, seg)}
+    del ws, val, st
+    del prob
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +264,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--replays", type=int, default=100)
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -338,6 +436,8 @@ def main():
            "sequential_gpu": seq,
            "kernel_ms_per_step": breakdown,
            "roofline": roof}
+    if not args.no_batch:
+        out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out))

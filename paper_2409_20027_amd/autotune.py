@@ -8,9 +8,13 @@ instances share the GPU, so it is measured instead of assumed.
 
 Instances are grouped into classes (n, m, T bucket).  For each class the tuner
 times the forward solve (lq_solve) of the class's instances
-for every candidate L with HIP events and keeps the fastest.  Results are cached
-in a JSON file keyed by class, batch-size bucket and precision, and returned as
-one segment length per instance for lq_plan_create_seg.
+for every candidate L with HIP events and keeps the fastest.  A class timed
+alone can prefer the scan where, inside the whole batch, the GPU is already
+full and the sequential recursion (least work) is faster; so the per-class
+choice is then refined on the whole batch, switching classes to L = T while
+that makes the batch faster.  Results are cached in a JSON file keyed by
+class, batch-size bucket and precision, and returned as one segment length per
+instance for lq_plan_create_seg.
 """
 from __future__ import annotations
 
@@ -31,11 +35,13 @@ def class_key(n, m, T, count, precision):
     return f"n{n}_m{m}_T{_bucket(T)}_B{_bucket(count)}_{precision}"
 
 
-def _time_forward(lq, insts, seg, precision, reps, torch):
-    from . import workloads
-    prob = lq.to_device(workloads.pack(insts))
-    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], precision=precision,
-                   seg_lens=[i.T if seg < 0 else seg for i in insts])
+def _time_forward(lq, prob, sizes, seg, precision, reps, torch):
+    return _time_forward_lens(lq, prob, sizes, [z[2] if seg < 0 else seg for z in sizes], precision, reps, torch)
+
+
+def _time_forward_lens(lq, prob, sizes, seg_lens, precision, reps, torch):
+    plan = lq.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], precision=precision,
+                   seg_lens=seg_lens)
     ws = plan.new_workspace()
     status = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
     val = lq.value_buffers(plan)
@@ -55,13 +61,17 @@ def _time_forward(lq, insts, seg, precision, reps, torch):
     return a.elapsed_time(b) / reps
 
 
-def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cache_path=None,
-         sample_per_class=None):
-    """Per-instance segment lengths for a ragged batch (list of LQInstance).
+def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cache_path=None,
+               sample_per_class=None, refine=True):
+    """Per-instance segment lengths for a batch given as (n, m, T) sizes.
 
-    Classes already in the cache are not re-timed.  `sample_per_class` limits
-    the number of instances of a class that are timed (the whole class when
-    None).  Returns (seg_lens, report) where report maps class -> {L: ms}.
+    make_prob(list of indices) returns the packed device problem of those
+    instances (in that order).  Classes already in the cache are not
+    re-timed; `sample_per_class` limits the number of instances of a class
+    that are timed (the whole class when None).  Returns (seg_lens, report)
+    where report maps class -> {L: ms}.  With refine, classes are then
+    switched to the sequential recursion where that makes the whole batch
+    faster (timed on the whole batch).
     """
     import torch
 
@@ -72,8 +82,8 @@ def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cach
         with open(cache_path) as f:
             cache = json.load(f)
     classes = {}
-    for idx, i in enumerate(insts):
-        classes.setdefault((i.n, i.m, _bucket(i.T)), []).append(idx)
+    for idx, (n, m, T) in enumerate(sizes):
+        classes.setdefault((n, m, _bucket(T)), []).append(idx)
     report, choice = {}, {}
     for (n, m, tb), members in classes.items():
         key = class_key(n, m, tb, len(members), precision)
@@ -81,30 +91,81 @@ def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cach
             choice[(n, m, tb)] = cache[key]["L"]
             continue
         sel = members if sample_per_class is None else members[:sample_per_class]
-        group = [insts[j] for j in sel]
-        times = {}
-        for L in candidates:
-            times[L] = _time_forward(lq, group, L, precision, reps, torch)
+        prob = make_prob(sel)
+        sub = [sizes[j] for j in sel]
+        times = {L: _time_forward(lq, prob, sub, L, precision, reps, torch) for L in candidates}
+        del prob
         best = min(times, key=times.get)
         choice[(n, m, tb)] = best
         report[key] = {str(k): v for k, v in times.items()}
         cache[key] = {"L": best, "ms": report[key]}
+    if refine and report and len(classes) > 1:   # (a batch answered from the cache is final)
+        # A class timed alone may prefer the scan where, inside the whole batch
+        # (enough instances to fill the GPU), the sequential recursion is
+        # faster: try switching each class (largest first) to L = T on the
+        # whole batch and keep a switch if the batch gets faster.
+        prob = make_prob(list(range(len(sizes))))
+
+        def seglens(ch):
+            return [T if ch[(n, m, _bucket(T))] < 0 else ch[(n, m, _bucket(T))] for n, m, T in sizes]
+
+        def run(ch):
+            return _time_forward_lens(lq, prob, sizes, seglens(ch), precision, reps, torch)
+
+        best_t = run(choice)
+        order = sorted(classes, key=lambda k: -sum(sizes[j][2] for j in classes[k]))
+        for key3 in order:
+            if choice[key3] < 0:
+                continue
+            trial = dict(choice)
+            trial[key3] = -1
+            t = run(trial)
+            if t < best_t:
+                best_t, choice = t, trial
+                ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
+                cache[ck] = {"L": -1, "ms": cache.get(ck, {}).get("ms", {}), "refined_on_batch": True}
+        # and the plain sequential recursion for every class
+        allseq = {k: -1 for k in choice}
+        t = run(allseq)
+        if t < best_t:
+            best_t, choice = t, allseq
+            for key3 in classes:
+                ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
+                cache[ck] = {"L": -1, "ms": cache.get(ck, {}).get("ms", {}), "refined_on_batch": True}
+        report["batch_ms"] = best_t
+        del prob
     if cache_path:
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1, sort_keys=True)
     seg_lens = []
-    for i in insts:
-        L = choice[(i.n, i.m, _bucket(i.T))]
-        seg_lens.append(i.T if L < 0 else L)
+    for n, m, T in sizes:
+        L = choice[(n, m, _bucket(T))]
+        seg_lens.append(T if L < 0 else L)
     return seg_lens, report
 
 
+def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cache_path=None,
+         sample_per_class=None, refine=True):
+    """tune_sizes for a list of LQInstance (host arrays, packed and uploaded per class)."""
+    from . import lqscan as lq
+    from . import workloads
+
+    sizes = [(i.n, i.m, i.T) for i in insts]
+
+    def make_prob(sel):
+        return lq.to_device(workloads.pack([insts[j] for j in sel]))
+
+    return tune_sizes(sizes, make_prob, precision=precision, candidates=candidates, reps=reps,
+                      cache_path=cache_path, sample_per_class=sample_per_class, refine=refine)
+
+
 def seg_lens_summary(insts, seg_lens):
-    """Text summary: chosen L per (n, T-bucket)."""
+    """Text summary: chosen L per (n, T-bucket); insts are LQInstance or (n, m, T)."""
     rows = {}
     for i, L in zip(insts, seg_lens):
-        rows.setdefault((i.n, _bucket(i.T)), set()).add("seq" if L >= i.T else L)
+        n, T = (i[0], i[2]) if isinstance(i, tuple) else (i.n, i.T)
+        rows.setdefault((n, _bucket(T)), set()).add("seq" if L >= T else L)
     return {f"n={n},T<={tb}": sorted(map(str, v)) for (n, tb), v in sorted(rows.items())}
 
 
-__all__ = ["tune", "class_key", "seg_lens_summary", "DEFAULT_CANDIDATES", "np"]
+__all__ = ["tune", "tune_sizes", "class_key", "seg_lens_summary", "DEFAULT_CANDIDATES", "np"]

@@ -140,6 +140,50 @@ def cfg3_ragged(seed: int = 3, count: int = 4096, tmin: int = 32, tmax: int = 20
             for n, m, T in zip(ns, ms, Ts)]
 
 
+def device_batch(sizes, *, seed: int, a_scale: float = 0.05, r_fixed: float | None = None,
+                 qt_scale: float = 10.0, device="cuda"):
+    """A batch drawn like lq_instance, generated on the device and packed.
+
+    sizes: list of (n, m, T) in packing order; consecutive instances of equal
+    (n, m) are drawn as one block, so order a ragged batch by size class.
+    The distributions are those of lq_instance (A = I + a N(0,1), B ~ 0.1 N,
+    c ~ 0.01 N, Q = diag(U[0.5, 2]), R = diag(U[0.1, 1]) or r_fixed I,
+    Q_T = qt_scale I, x0 ~ N(0, 1)); the numbers come from torch's generator,
+    not from the numpy stream, so this serves throughput measurement, not
+    parity.  Returns the packed dict of device tensors (lq_problem fields).
+    """
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    f64 = dict(dtype=torch.float64, device=device)
+    parts = {k: [] for k in ("A", "B", "c", "Q", "R", "QT", "x0")}
+    i = 0
+    while i < len(sizes):
+        n, m, _ = sizes[i]
+        j = i
+        while j < len(sizes) and sizes[j][0] == n and sizes[j][1] == m:
+            j += 1
+        Ts = sum(int(t) for _, _, t in sizes[i:j])
+        cnt = j - i
+        eye = torch.eye(n, **f64)
+        parts["A"].append((eye + a_scale * torch.randn(Ts, n, n, generator=g, **f64)).reshape(-1))
+        parts["B"].append((0.1 * torch.randn(Ts, n, m, generator=g, **f64)).reshape(-1))
+        parts["c"].append((0.01 * torch.randn(Ts, n, generator=g, **f64)).reshape(-1))
+        qd = 0.5 + 1.5 * torch.rand(Ts, n, generator=g, **f64)
+        parts["Q"].append(torch.diag_embed(qd).reshape(-1))
+        if r_fixed is not None:
+            rd = torch.full((Ts, m), float(r_fixed), **f64)
+        else:
+            rd = 0.1 + 0.9 * torch.rand(Ts, m, generator=g, **f64)
+        parts["R"].append(torch.diag_embed(rd).reshape(-1))
+        parts["QT"].append((qt_scale * eye).repeat(cnt, 1, 1).reshape(-1))
+        parts["x0"].append(torch.randn(cnt, n, generator=g, **f64).reshape(-1))
+        i = j
+    out = {k: torch.cat(v).contiguous() for k, v in parts.items()}
+    out.update({"M": None, "q": None, "r": None, "qT": None})
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Packing of a (possibly ragged) batch into the flat stage-major layout
 # ---------------------------------------------------------------------------
