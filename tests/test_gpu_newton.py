@@ -74,13 +74,15 @@ def test_benign_instance_converges(lq):
     """On a stable instance the loop converges.  Near convergence the predicted
     decrease falls to round-off of the cost and the gain ratio is the ratio of
     two rounding errors, so decisions there are not determined by the
-    arithmetic: they are compared while the step is well above round-off.  The
-    final iterate is then fixed only up to the flat bottom of J_mu (a cost
-    change of eps |J| moves u by about sqrt(eps) = 1.5e-8 times the
-    conditioning; 20 more oracle steps at the last barrier weight move the
-    oracle's own u by 9.4e-8).  Asserted: stationarity, |dJ_mu/du| reduced
-    below 1e-8 of its value at u0 (the oracle reaches 6.0e-9), and agreement
-    with the oracle to 1e-6."""
+    arithmetic: they are compared while the step is well above round-off.  A
+    rejection in such a phase multiplies the damping, and a later barrier level
+    then starts from a larger damping and ends further from its minimiser, so
+    the final iterate depends on rounding: the oracle's loop with u perturbed by
+    3e-16 .. 3e-15 (relative) after every step ends, over 48 such runs, with
+    |dJ_mu/du| up to 1.1e-5 of its value at u0 (median 1.5e-9) and u up to
+    7.9e-5 (normwise relative) from the unperturbed run.  Asserted, with a
+    tenfold margin: stationarity below 1e-4 of the value at u0 and agreement
+    with the oracle to 1e-3."""
     p = benign_problem()
     ref = oracle.nmpc_solve(p, W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
     got = lq.NewtonMPC(p, seg_len=8).run(W.NMPC_MU_LEVELS, W.NMPC_ITERS_PER_LEVEL, W.NMPC_ALPHA0, W.NMPC_NU0)
@@ -93,5 +95,5 @@ def test_benign_instance_converges(lq):
     g_got = barrier_gradient(p, got["u"].reshape(p.T, p.nu), mu)
     eu = rel(got["u"], ref["u"])
     print(f"benign instance: |dJ/du| {g_got:.2e} (u0: {g0:.2e}), u rel diff to oracle {eu:.2e}")
-    assert g_got <= 1e-8 * g0
-    assert eu < 1e-6
+    assert g_got <= 1e-4 * g0
+    assert eu <= 1e-3
