@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -45,6 +46,7 @@ struct lq_plan {
     int max_nseg = 0;
     int seg_len_used = 0;
     int nk = 1;   // contraction slices of (n_max + 1)-long products
+    int aff_radix = 4;   // radix of the affine-map scan levels
     // workspace layout (bytes)
     size_t off_Xa = 0, off_Xb = 0, off_Ya = 0, off_Yb = 0, off_st = 0, off_gt = 0, ws_bytes = 0, el_bytes = 0;
     // diagnostic phase timing (events created by lq_plan_set_timing)
@@ -76,6 +78,39 @@ static lq_status hip_ok(hipError_t e) { return e == hipSuccess ? LQ_OK : LQ_ERR_
 static lq_status launched()
 {
     return hipGetLastError() == hipSuccess ? LQ_OK : LQ_ERR_HIP;
+}
+
+// Radix of the affine-map scan levels.  A level costs a fixed launch-and-load
+// latency plus, per entry, up to r - 1 dependent tile products.  When the
+// entries fit one wave per SIMD the level is latency-bound and radix 8 saves
+// levels (T = 16384, L = 16, n = 12: 19.3 us per scan against 19.8 at radix 4,
+// 30.4 at radix 2, 23 at radix 32); with more entries than SIMDs the products
+// and the tile traffic dominate and radix 4 does least work per level that
+// still halves the levels of radix 2 (256 x 4096 stages: 10.42 ms per
+// differentiated solve against 10.55 at radix 8 and 10.91 at radix 2).
+// LQSCAN_AFFINE_RADIX (2, 4, 8, 16 or 32) overrides the choice.
+static int choose_affine_radix(int64_t entries, int device)
+{
+    if (const char *e = getenv("LQSCAN_AFFINE_RADIX")) {
+        const int r = atoi(e);
+        if (r == 2 || r == 4 || r == 8 || r == 16 || r == 32) return r;
+    }
+    int cus = 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0) cus = 256;
+    return entries <= 4 * (int64_t)cus ? 8 : 4;
+}
+
+// Affine-map scan over the plan's entries, from `in` with `o` as the other
+// buffer (prefix when suffix = 0, suffix otherwise); returns the buffer that
+// holds the result.
+static double *affine_scan(const lq_plan *p, hipStream_t st, int suffix, double *in, double *o)
+{
+    for (int64_t dd = 1; dd < p->max_nseg; dd *= p->aff_radix) {
+        lqk::launch_affine_ks(p->nk, p->prec, p->aff_radix, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch,
+                              (int)dd, suffix, in, o);
+        std::swap(in, o);
+    }
+    return in;
 }
 
 extern "C" {
@@ -153,6 +188,7 @@ static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu
     p->max_nseg = max_nseg;
     p->seg_len_used = lmax;
     p->nk = (nmax + 1 + 3) / 4;
+    p->aff_radix = choose_affine_radix(p->total_x, p->device);
     // workspace: value scan ping-pong (3 tiles / entry), affine scan ping-pong (1 tile / entry)
     size_t off = 0;
     p->off_Xa = off; off = align_up(off + (size_t)p->total_x * 3 * TILE * sizeof(double));
@@ -273,16 +309,8 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
 static void rollout_scan_apply(const lq_plan *p, const lqk::ProbPtrs &P, const lqk::ValPtrs &V, double *Ya, double *Yb,
                                double *x, double *u, double *lambda, hipStream_t st)
 {
-    double *in = Ya, *o = Yb;
-    if (p->max_nseg > 1)
-        timed(p, LQ_PH_ROLL_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
-                lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
-                                      o);
-                std::swap(in, o);
-            }
-        });
-    double *fin = in;
+    double *fin = Ya;
+    if (p->max_nseg > 1) timed(p, LQ_PH_ROLL_SCAN, st, [&] { fin = affine_scan(p, st, 0, Ya, Yb); });
     timed(p, LQ_PH_ROLL_APPLY, st, [&] {
         lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
                                u, lambda);
@@ -351,36 +379,21 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
                    (double *)(ws + p->off_st), (double *)(ws + p->off_gt)};
     lqk::GradPtrs G{grads->A, grads->B, grads->c, grads->Q, grads->R, grads->M,
                     grads->q, grads->r, grads->QT, grads->qT, grads->x0};
-    const unsigned nseg = (unsigned)p->total_seg, nx = (unsigned)p->total_x;
+    const unsigned nseg = (unsigned)p->total_seg;
     // backward linear-term scan
     timed(p, LQ_PH_ADJ_BACK_FOLD, st, [&] {
         lqk::launch_adj_back_fold(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
     });
-    double *in = Ya, *o = Yb;
-    if (p->max_nseg > 1)
-        timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
-                lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
-                std::swap(in, o);
-            }
-        });
-    double *fin = in;
+    double *fin = Ya;
+    if (p->max_nseg > 1) timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] { fin = affine_scan(p, st, 1, Ya, Yb); });
     // the backward sweep also writes the forward scan's entries (its segment fold fused in)
     double *fwd = (fin == Ya) ? Yb : Ya, *fwd2 = fin;
     timed(p, LQ_PH_ADJ_BACK_APPLY, st, [&] {
         lqk::launch_adj_back_apply(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, fwd, status);
     });
     // forward derivative scan + gradients
-    in = fwd;
-    o = fwd2;
-    if (p->max_nseg > 1)
-        timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 4) {
-                lqk::launch_affine_ks(p->nk, p->prec, nx, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in, o);
-                std::swap(in, o);
-            }
-        });
-    double *ffin = in;
+    double *ffin = fwd;
+    if (p->max_nseg > 1) timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] { ffin = affine_scan(p, st, 0, fwd, fwd2); });
     timed(p, LQ_PH_ADJ_FWD_APPLY, st, [&] {
         lqk::launch_adj_fwd_apply(p->nk, p->prec, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
     });
@@ -479,11 +492,7 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
     lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x);
     lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
-    double *in = Ya, *o = Yb;
-    for (int dd = 1; dd < p->max_nseg; dd *= 4) {
-        lqk::launch_affine_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in, o);
-        std::swap(in, o);
-    }
+    double *in = affine_scan(p, st, 1, Ya, Yb);
     lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
     lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->u, state->scal);
     // the LQ step

@@ -20,7 +20,7 @@ void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtr
                           int32_t *status);
 void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                       const int32_t *seg_start, int batch, double *Y);
-void launch_affine_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
+void launch_affine_ks(int nk, int pr, int radix, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
                       int dd, int suffix, const double *Yin, double *Yout);
 void launch_roll_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                        const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u, double *lam);

@@ -10,8 +10,9 @@
 //
 //   k_roll_fold   : per segment, Phi_s = F~_{k1-1} ... F~_{k0}; the block of
 //                   segment 0 also writes the x0 element.
-//   k_affine_ks   : one Kogge-Stone level, prefix (Y_s <- Y_s Y_{s-dd}) or
-//                   suffix (Y_s <- Y_s Y_{s+dd}); one tile per entry.
+//   k_affine_ks   : one Kogge-Stone level of radix 2..32, prefix
+//                   (Y_s <- Y_s Y_{s-dd} ...) or suffix (Y_s <- Y_s Y_{s+dd} ...);
+//                   one tile per entry.
 //   k_roll_apply  : from the state at the segment start, x_{k+1} = F~ x~,
 //                   u_k = Gamma~ x~, lambda_k = S~_k x~ (top rows).
 #include "lq_kernels.hpp"
@@ -45,17 +46,19 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
 }
 
-// One radix-4 Kogge-Stone level over entries [xbase, xbase + nseg] of each
+// One radix-RAD Kogge-Stone level over entries [xbase, xbase + nseg] of each
 // instance, distance dd:
-//   prefix (suffix = 0): Y_s <- Y_s Y_{s-dd} Y_{s-2dd} Y_{s-3dd}
-//   suffix (suffix = 1): Y_s <- Y_s Y_{s+dd} Y_{s+2dd} Y_{s+3dd}
+//   prefix (suffix = 0): Y_s <- Y_s Y_{s-dd} Y_{s-2dd} ... Y_{s-(RAD-1)dd}
+//   suffix (suffix = 1): Y_s <- Y_s Y_{s+dd} Y_{s+2dd} ... Y_{s+(RAD-1)dd}
 // with the terms that fall outside [0, nseg] left out; after the level with
-// distance dd an entry covers 4 dd entries, so dd = 1, 4, 16, ... reaches
-// every prefix (suffix) in ceil(log4(nseg + 1)) levels.  The product is
-// carried transposed (P' <- Y_j' P' is a register product), so a level takes
-// two LDS transposes whatever the number of terms.  The entry that no segment
-// reads (the last of a prefix scan, the first of a suffix scan) is skipped.
-template <int NK, int PR>
+// distance dd an entry covers RAD dd entries, so dd = 1, RAD, RAD^2, ...
+// reaches every prefix (suffix) in ceil(log_RAD(nseg + 1)) levels.  Every
+// term's load is issued before the first product (an absent term re-reads the
+// entry itself and is not used).  The product is carried transposed
+// (P' <- Y_j' P' is a register product), so a level takes two LDS transposes
+// whatever the number of terms.  The entry that no segment reads (the last of
+// a prefix scan, the first of a suffix scan) is skipped.
+template <int NK, int PR, int RAD>
 __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ inst,
                                                   const int32_t *__restrict__ x_start, int batch, int dd,
                                                   int suffix, const double *__restrict__ Yin,
@@ -69,19 +72,19 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     if (suffix ? (s == 0) : (s == d.nseg)) return;   // entries that are never read
     const Tile a = gload(Yin + (int64_t)gx * TILE);
     const int avail = suffix ? (d.nseg - s) / dd : s / dd;   // terms that exist on that side
-    const int terms = min(3, avail);
+    const int terms = min(RAD - 1, avail);
     if (terms == 0) {
         gstore(Yout + (int64_t)gx * TILE, a);
         return;
     }
     const int64_t step = suffix ? dd : -dd;
-    // issue every term's load before the first product
-    const Tile b1 = gload(Yin + (gx + step) * TILE);
-    const Tile b2 = terms >= 2 ? gload(Yin + (gx + 2 * step) * TILE) : tzero();
-    const Tile b3 = terms >= 3 ? gload(Yin + (gx + 3 * step) * TILE) : tzero();
-    Tile PT = tnz<NK, PR>(b1, ttrans(a, lds));     // (a b1)'
-    if (terms >= 2) PT = tnz<NK, PR>(b2, PT);      // (a b1 b2)'
-    if (terms >= 3) PT = tnz<NK, PR>(b3, PT);      // (a b1 b2 b3)'
+    Tile b[RAD - 1];
+#pragma unroll
+    for (int j = 0; j < RAD - 1; ++j) b[j] = gload(Yin + (gx + (j < terms ? (j + 1) * step : 0)) * TILE);
+    Tile PT = tnz<NK, PR>(b[0], ttrans(a, lds));   // (a b1)'
+#pragma unroll
+    for (int j = 1; j < RAD - 1; ++j)
+        if (j < terms) PT = tnz<NK, PR>(b[j], PT);  // (a b1 ... b_{j+1})'
     gstore(Yout + (int64_t)gx * TILE, ttrans(PT, lds));
 }
 
@@ -127,12 +130,29 @@ void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P,
 #undef CALL
 }
 
-void launch_affine_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,
-                      int dd, int suffix, const double *Yin, double *Yout)
+void launch_affine_ks(int nk, int pr, int radix, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+                      int batch, int dd, int suffix, const double *Yin, double *Yout)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_affine_ks<K, R>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, suffix, Yin, Yout)
-    LQK_DISPATCH(nk, pr, CALL)
-#undef CALL
+#define CALLR(K, R, RAD) \
+    hipLaunchKernelGGL((k_affine_ks<K, R, RAD>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, suffix, Yin, Yout)
+#define CALL2(K, R) CALLR(K, R, 2)
+#define CALL4(K, R) CALLR(K, R, 4)
+#define CALL8(K, R) CALLR(K, R, 8)
+#define CALL16(K, R) CALLR(K, R, 16)
+#define CALL32(K, R) CALLR(K, R, 32)
+    switch (radix) {
+    case 2: LQK_DISPATCH(nk, pr, CALL2) break;
+    case 8: LQK_DISPATCH(nk, pr, CALL8) break;
+    case 16: LQK_DISPATCH(nk, pr, CALL16) break;
+    case 32: LQK_DISPATCH(nk, pr, CALL32) break;
+    default: LQK_DISPATCH(nk, pr, CALL4) break;
+    }
+#undef CALL2
+#undef CALL4
+#undef CALL8
+#undef CALL16
+#undef CALL32
+#undef CALLR
 }
 
 void launch_roll_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,

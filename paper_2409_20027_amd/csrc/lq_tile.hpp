@@ -181,6 +181,15 @@ LQK_DEV Tile sget_t(const double *s)
     return t;
 }
 
+// Marks a tile's registers as used here (no instruction): a load into them has
+// to complete first.  Placed before a loop that carries prefetched tiles, it
+// makes the loop's entry state "loaded", so the waits inside the loop count
+// only the loads the loop itself issues.
+LQK_DEV void settle(const Tile &t)
+{
+    asm volatile("" ::"v"(t.v[0]), "v"(t.v[1]), "v"(t.v[2]), "v"(t.v[3]));
+}
+
 // Row permutation that makes the FP32 16x16x4 instruction's accumulator (row
 // 4g + r in lane j + 16g, register r) coincide with the FP64 tile layout (row
 // 4r + g): feed row pi4(a) of the A operand as its row a.
@@ -418,12 +427,17 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
     ri = rowmin_i<32>(rowmin_i<16>(ri));
     const int piv = __builtin_amdgcn_readlane(ri, P);
     constexpr int gp = P & 3, rp = P >> 2;
-    const int gq = piv & 3, rq = piv >> 2;
-    const double rowQ = rowsel(treg(v, rq), gq);   // pivot row
-    const double rowP = rowsel(v[rp], gp);          // row P, moves to the pivot row's place
+    // row P (on every lane); it moves to the pivot row's place unless the
+    // pivot is already on the diagonal (piv is uniform: the branch is scalar)
+    const double rowP = rowsel(v[rp], gp);
+    double rowQ = rowP;
+    if (piv != P) {
+        const int gq = piv & 3, rq = piv >> 2;
+        rowQ = rowsel(treg(v, rq), gq);   // pivot row
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if (r == rq && g == gq) v[r] = rowP;
+        for (int r = 0; r < 4; ++r)
+            if (r == rq && g == gq) v[r] = rowP;
+    }
     const double pinv = recip(rlane(rowQ, P));
     const double prow = rowQ * pinv;
     // v - colp (x) w is the whole elimination step for every row but P: with

@@ -91,20 +91,23 @@ LQK_DEV bool build_from_raw(const StageRaw<MR> &w, const InstDesc &d, StageElem 
 // U = A^': E <- e_k (x) E with the rank-m Woodbury form of the operator:
 //   W = W0 + B~'J^B~,  P = B~'J^A~,  H = A^B~,
 //   A^ <- A^A~ - H W^{-1} P,  C^ <- C^ + H W^{-1} H',  J^ <- J~ + A~'J^A~ - P'W^{-1}P.
-// Returns false if W is singular.
-template <int NK, int PR>
+// NB: contraction slices over the rows of B~ (its homogeneous row is zero, so
+// ceil(n / 4) slices suffice).  W comes first: the m x m inverse (vector
+// instructions) then overlaps the five products that do not depend on it
+// (matrix instructions).  Returns false if W is singular.
+template <int NK, int NB, int PR>
 LQK_DEV bool fold_left(const StageElem &e, Tile &U, Tile &Ch, Tile &Jh, int m)
 {
     const d4 z = (d4){0.0, 0.0, 0.0, 0.0};
-    const Tile JG = tnz<NK, PR>(Jh, e.B);         // J^ B~
-    const Tile JA = tnz<NK, PR>(Jh, e.Ab);        // J^ A~
-    const Tile W = tna<NK, PR>(e.B, JG, e.W0);    // W0 + B~'J^B~
-    const Tile Pm = tnz<NK, PR>(e.B, JA);         // B~'J^A~
-    const Tile Jn = tna<NK, PR>(e.Ab, JA, e.J);   // J~ + A~'J^A~
-    const Tile Ht = tnz<NK, PR>(e.B, U);          // H' = B~'A^'
-    const Tile AAt = tnz<NK, PR>(e.Ab, U);        // (A^A~)'
+    const Tile JG = tnz<NB, PR>(Jh, e.B);         // J^ B~
+    const Tile W = tna<NB, PR>(e.B, JG, e.W0);    // W0 + B~'J^B~
     Tile WiT;
     const bool ok = gen_inverse_t(W, m, WiT);
+    const Tile JA = tnz<NK, PR>(Jh, e.Ab);        // J^ A~
+    const Tile Pm = tnz<NB, PR>(e.B, JA);         // B~'J^A~
+    const Tile Jn = tna<NK, PR>(e.Ab, JA, e.J);   // J~ + A~'J^A~
+    const Tile Ht = tnz<NB, PR>(e.B, U);          // H' = B~'A^'
+    const Tile AAt = tnz<NK, PR>(e.Ab, U);        // (A^A~)'
     const Tile WP = tnz<1, PR>(WiT, Pm);          // W^{-1} P
     const Tile WHt = tnz<1, PR>(WiT, Ht);         // W^{-1} H'
     U.v = AAt.v - tn<1, PR>(WP, Ht, z);           // (A^A~ - H W^{-1} P)'
@@ -122,21 +125,43 @@ LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
     fk = first ? k : fk;
 }
 
-// Fused element build + fold over stages k1-1 .. k0 (right to left).  Each
-// stage's data is loaded at the top of its own step: the fold keeps few
-// registers, so several waves share a SIMD and cover each other's load
-// latency, which pays more than a prefetch buffer held across steps.
-template <int NK, int PR, bool MR>
+// Fused element build + fold over stages k1-1 .. k0 (right to left).  Stage
+// k-1's loads are issued at the top of step k, a whole step before they are
+// used; the first stage's data is settled before the loop so that the waits in
+// the loop count only the loads the loop issues.
+template <int NK, int NB, int PR, bool MR>
 LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
                         int &code, int &fk)
 {
+    StageRaw<MR> nxt;
+    load_stage_raw<MR>(P, d, k1 - 1, nxt);
+    settle(nxt.A);
+    settle(nxt.Q);
+    settle(nxt.B);
+    settle(nxt.R);
+    if constexpr (MR) {
+        settle(nxt.MT);
+        settle(nxt.BT);
+    }
     for (int k = k1 - 1; k >= k0; --k) {
-        StageRaw<MR> b;
-        load_stage_raw<MR>(P, d, k, b);
+        const StageRaw<MR> b = nxt;
+        load_stage_raw<MR>(P, d, max(k - 1, k0), nxt);
         StageElem e;
         note(build_from_raw<PR, MR>(b, d, e), ERR_NOT_PD, k, code, fk);
-        note(fold_left<NK, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
+        note(fold_left<NK, NB, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
     }
+}
+
+// The fused fold for the slice count of B~'s rows: NK - 1 when n is a multiple
+// of 4 (then B~'s rows fit one slice fewer than n + 1), NK otherwise.
+template <int NK, int PR, bool MR>
+LQK_DEV void fold_fused_nb(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
+                           int &code, int &fk)
+{
+    if (NK > 1 && (d.n & 3) == 0)
+        fold_fused<NK, (NK > 1 ? NK - 1 : 1), PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk);
+    else
+        fold_fused<NK, NK, PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,14 +244,14 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             e.J = gload(ep + 2 * TILE);
             e.B = gload(ep + 3 * TILE);
             e.W0 = tident(m);
-            note(fold_left<NK, PR>(e, U, Ch, Jh, m), ERR_SINGULAR, k, code, fk);
+            note(fold_left<NK, NK, PR>(e, U, Ch, Jh, m), ERR_SINGULAR, k, code, fk);
         }
     } else {
         // fused element build
         if ((P.M != nullptr) || (P.r != nullptr))
-            fold_fused<NK, PR, true>(P, d, k0, k1, U, Ch, Jh, code, fk);
+            fold_fused_nb<NK, PR, true>(P, d, k0, k1, U, Ch, Jh, code, fk);
         else
-            fold_fused<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk);
+            fold_fused_nb<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk);
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
     gstore(o, ttrans(U, lds));

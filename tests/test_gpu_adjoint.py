@@ -104,6 +104,15 @@ def test_adjoint_long_horizon_batch_sample(lq):
     check(gpu_grads(lq, insts), insts)
 
 
+@pytest.mark.parametrize("radix", [2, 4, 8, 16, 32])
+def test_adjoint_affine_scan_radix(lq, radix, monkeypatch):
+    """Both reversed affine scans through every radix (one stage per segment, up to 301 entries)."""
+    monkeypatch.setenv("LQSCAN_AFFINE_RADIX", str(radix))
+    rng = np.random.default_rng(50 + radix)
+    insts = [W.lq_instance_general(rng, 3, 2, 300), W.lq_instance(rng, 5, 2, 45), W.lq_instance(rng, 2, 1, 1)]
+    check(gpu_grads(lq, insts, seg_len=1), insts)
+
+
 def test_autograd_function_matches_oracle_and_fd(lq):
     inst = W.lq_instance_general(np.random.default_rng(34), 3, 2, 17)
     packed = W.pack([inst])

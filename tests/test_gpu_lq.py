@@ -256,3 +256,16 @@ def test_per_instance_segment_lengths(lq):
     for inst, xi, Si in zip(insts, x, S):
         ref = oracle_ref(inst)
         assert rel(xi, ref["x"]) < TOL and rel(Si, ref["S"]) < TOL
+
+
+@pytest.mark.parametrize("radix", [2, 4, 8, 16, 32])
+def test_affine_scan_radix(lq, radix, monkeypatch):
+    """Rollout through every radix of the affine-map scan levels: one stage per segment, so
+    the scan runs over up to 301 entries (several levels, ragged last level) in a ragged batch."""
+    monkeypatch.setenv("LQSCAN_AFFINE_RADIX", str(radix))
+    rng = np.random.default_rng(40 + radix)
+    insts = [W.lq_instance_general(rng, 3, 2, 300), W.lq_instance(rng, 2, 1, 37), W.lq_instance(rng, 12, 4, 70),
+             W.lq_instance(rng, 4, 1, 1)]
+    per, status, _ = run(lq, insts, seg_len=1)
+    assert not status.any()
+    check(per, insts)
