@@ -293,14 +293,12 @@ LQK_DEV double rlane(double x, int l)
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// x of lane P of this lane's 16-lane row (DPP row broadcast).
+// x of lane P of this lane's 16-lane row (one 64-bit DPP row broadcast; every
+// lane is written, so the old value is irrelevant).
 template <int P>
 LQK_DEV double rowbcast(double x)
 {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x150 + P, 0xf, 0xf, false);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x150 + P, 0xf, 0xf, false);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_update_dpp(x, x, 0x150 + P, 0xf, 0xf, true);
 }
 
 // Register r of a tile for a uniform run-time r.
@@ -311,59 +309,16 @@ LQK_DEV double treg(const d4 &v, int r) { return r == 0 ? v[0] : (r == 1 ? v[1] 
 // content in both rows of each row pair ([0]) and the odd rows' content ([1]);
 // permlane32_swap(x, x) returns the low half's content in both halves ([0]) and
 // the high half's ([1]).
-LQK_DEV uint32_t xor16_u(uint32_t x)
-{
-    const auto s = __builtin_amdgcn_permlane16_swap(x, x, false, false);
-    return (tgrp() & 1) ? s[0] : s[1];
-}
-LQK_DEV uint32_t xor32_u(uint32_t x)
-{
-    const auto s = __builtin_amdgcn_permlane32_swap(x, x, false, false);
-    return (tgrp() & 2) ? s[0] : s[1];
-}
-// x of lane l ^ 16 (OFF = 16) or l ^ 32 (OFF = 32).
-template <int OFF>
-LQK_DEV double xor_row(double x)
-{
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
-    const uint32_t l2 = OFF == 16 ? xor16_u(lo) : xor32_u(lo), h2 = OFF == 16 ? xor16_u(hi) : xor32_u(hi);
-    return __builtin_bit_cast(double, ((uint64_t)h2 << 32) | l2);
-}
-template <int OFF>
-LQK_DEV int xor_row_i(int x)
-{
-    return (int)(OFF == 16 ? xor16_u((uint32_t)x) : xor32_u((uint32_t)x));
-}
-// max of x over each pair of rows {0,1}, {2,3} (OFF = 16) or over the two
-// halves (OFF = 32), on every lane: one swap leaves one row's values in one
-// register and the other row's in the other, so no select is needed.
-template <int OFF>
-LQK_DEV double rowmax(double x)
-{
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
-    uint32_t l0, l1, h0, h1;
-    if constexpr (OFF == 16) {
-        const auto sl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
-        const auto sh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-        l0 = sl[0]; l1 = sl[1]; h0 = sh[0]; h1 = sh[1];
-    } else {
-        const auto sl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-        const auto sh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-        l0 = sl[0]; l1 = sl[1]; h0 = sh[0]; h1 = sh[1];
-    }
-    return fmax(__builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0), __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1));
-}
 
-// min of an int over row pairs (OFF = 16) or halves (OFF = 32), like rowmax.
+// max of an unsigned over each pair of rows {0,1}, {2,3} (OFF = 16) or over
+// the two halves (OFF = 32), on every lane: one swap leaves one row's values
+// in one register and the other row's in the other.
 template <int OFF>
-LQK_DEV int rowmin_i(int x)
+LQK_DEV uint32_t rowmax_u(uint32_t x)
 {
-    const uint32_t u = (uint32_t)x;
-    const auto sw = OFF == 16 ? __builtin_amdgcn_permlane16_swap(u, u, false, false)
-                              : __builtin_amdgcn_permlane32_swap(u, u, false, false);
-    return min((int)sw[0], (int)sw[1]);
+    const auto sw = OFF == 16 ? __builtin_amdgcn_permlane16_swap(x, x, false, false)
+                              : __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    return max((uint32_t)sw[0], (uint32_t)sw[1]);
 }
 
 // x of row gq (uniform) at this lane's column, on every lane.
@@ -407,25 +362,26 @@ template <int P>
 LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
 {
     const int c = tcol(), g = tgrp();
-    // pivot search over rows P..n1-1 of column P: max |x| over the lane's four
-    // registers and then over the four lanes of the column (lane swaps)
-    double a[4];
+    // Pivot search over rows P..n1-1 of column P with one integer key per
+    // candidate: the high word of |x| (sign, exponent and 20 mantissa bits,
+    // ordered like |x| for finite and infinite values) with its low 4 bits
+    // replaced by 15 - row.  The largest key is a pivot within 2^-16 of the
+    // largest |x| (the lowest row among equal keys); a maximum over the lane's
+    // registers, then over the column's four lanes (lane swaps), finds it.
+    uint32_t key = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + g;
-        a[r] = (c == P && i >= P && i < n1) ? fabs(v[r]) : -1.0;
+        const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, v[r]) >> 32);
+        const uint32_t k = (hi & 0x7ffffff0u) | (uint32_t)(15 - i);
+        key = (c == P && i >= P && i < n1) ? max(key, k) : key;
     }
-    double mx = fmax(fmax(a[0], a[1]), fmax(a[2], a[3]));
-    mx = rowmax<32>(rowmax<16>(mx));
-    const double pmax = rlane(mx, P);
-    ok = ok && (pmax > 0.0) && (pmax < INFINITY);
-    // the lowest row holding the maximum (min of the candidate row indices
-    // over the lane's registers, then over the column's four lanes)
-    int ri = 64;
-#pragma unroll
-    for (int r = 3; r >= 0; --r) ri = (a[r] == pmax) ? 4 * r + g : ri;
-    ri = rowmin_i<32>(rowmin_i<16>(ri));
-    const int piv = __builtin_amdgcn_readlane(ri, P);
+    key = rowmax_u<32>(rowmax_u<16>(key));
+    const uint32_t kp = (uint32_t)__builtin_amdgcn_readlane((int)key, P);
+    const int piv = 15 - (int)(kp & 15u);
+    // a pivot column that is zero to the key's resolution, or a pivot that is
+    // not finite
+    ok = ok && (kp >= 16u) && ((kp & 0x7ff00000u) != 0x7ff00000u);
     constexpr int gp = P & 3, rp = P >> 2;
     // row P (on every lane); it moves to the pivot row's place unless the
     // pivot is already on the diagonal (piv is uniform: the branch is scalar)
