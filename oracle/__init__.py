@@ -59,16 +59,23 @@ def lib():
             L.oracle_stateprop_combine.restype = None
             L.oracle_lq_adjoint.argtypes = [i, i, i] + [_P] * 11 + [_P] * 2 + [_P] * 11 + [_I]
             L.oracle_lq_adjoint.restype = i
-            L.oracle_nmpc_cost.argtypes = [i, i, i, d] + [_P] * 7 + [d, d, d, _P]
+            L.oracle_nmpc_cost.argtypes = [i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, _P]
             L.oracle_nmpc_cost.restype = d
-            L.oracle_nmpc_expand.argtypes = [i, i, i, d] + [_P] * 6 + [d, d, d, _P, _P] + [_P] * 6
+            L.oracle_nmpc_rollout.argtypes = [i, i, i, d, i, _P, _P, _P, _P, _P, _P]
+            L.oracle_nmpc_rollout.restype = i
+            L.oracle_nmpc_f.argtypes = [i, _P, i, i, _P, _P, _P]
+            L.oracle_nmpc_f.restype = i
+            L.oracle_nmpc_expand.argtypes = [i, i, i, d, i, _P] + [_P] * 6 + [d, d, d, _P, _P] + [_P] * 7
             L.oracle_nmpc_expand.restype = None
-            L.oracle_nmpc_newton_step.argtypes = ([i, i, i, d] + [_P] * 7 + [d, d, d]
-                                                  + [_P, _P, _P, _P, _P, _P, _P])
+            L.oracle_nmpc_newton_step.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d]
+                                                  + [_P, _P, _P, _P, _P, _P, _P, _P])
             L.oracle_nmpc_newton_step.restype = i
-            L.oracle_nmpc_solve.argtypes = ([i, i, i, d] + [_P] * 7 + [d, d, _P, i, i, d, d]
+            L.oracle_nmpc_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, _P, i, i, d, d]
                                             + [_P, _P, _P, _I, _P])
             L.oracle_nmpc_solve.restype = i
+            L.oracle_nmpc_ip_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, d, d, d, i, d, d]
+                                               + [_P, _P, i, _P, _P, _P, _I, _I])
+            L.oracle_nmpc_ip_solve.restype = i
             _lib = L
     return _lib
 
@@ -188,69 +195,131 @@ def lq_adjoint(A, B, c, Q, R, QT, x0, gx, gu, M=None, q=None, r=None, qT=None, *
 
 
 # ----------------------------------------------------------------------------
-# Newton / interior point for the tanh model
+# Newton / interior point (tanh network, pendulum, cart-pole)
 # ----------------------------------------------------------------------------
 
-def _prob_args(p):
-    f = _f
-    return (p.nx, p.nu, p.T, float(p.h), _p(f(p.W)), _p(f(p.Bm)), _p(f(p.Q)), _p(f(p.R)),
-            _p(f(p.QT)), _p(f(p.xref)))
+def _model(p):
+    """(model id, parameter array or None) of a problem (tanh when unset)."""
+    model = int(getattr(p, "model", 0))
+    prm = getattr(p, "param", None)
+    return model, (None if prm is None else _f(np.asarray(prm, np.float64)))
+
+
+def _wb(p):
+    return _f(getattr(p, "W", None)), _f(getattr(p, "Bm", None))
+
+
+def nmpc_f(p, x, u):
+    """Continuous-time right-hand side f(x, u) of the pendulum / cart-pole."""
+    model, prm = _model(p)
+    x, u = _f(x), _f(u)
+    f = np.zeros(p.nx)
+    if lib().oracle_nmpc_f(model, _p(prm), p.nx, p.nu, _p(x), _p(u), _p(f)) != 0:
+        raise ValueError("nmpc_f: pendulum or cart-pole model expected")
+    return f
 
 
 def nmpc_cost(p, u, mu):
+    model, prm = _model(p)
     u = _f(u)
-    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
-    return lib().oracle_nmpc_cost(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT),
-                                  _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu), _p(u))
+    W, Bm = _wb(p)
+    Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
+    return lib().oracle_nmpc_cost(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
+                                  _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu), _p(u))
 
 
 def nmpc_expand(p, x, u, mu):
+    model, prm = _model(p)
     x, u = _f(x), _f(u)
-    W, Bm, Q, R, QT, xref = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref))
+    W, Bm = _wb(p)
+    Q, R, QT, xref = map(_f, (p.Q, p.R, p.QT, p.xref))
     T, n, m = p.T, p.nx, p.nu
     o = {"A": np.zeros((T, n, n)), "B": np.zeros((T, n, m)), "lam": np.zeros((T + 1, n)),
-         "P": np.zeros((T, n, n)), "Rh": np.zeros((T, m, m)), "d": np.zeros((T, m))}
-    lib().oracle_nmpc_expand(n, m, T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT), _p(xref),
+         "P": np.zeros((T, n, n)), "Rh": np.zeros((T, m, m)), "d": np.zeros((T, m)), "M": np.zeros((T, n, m))}
+    lib().oracle_nmpc_expand(n, m, T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R), _p(QT), _p(xref),
                              float(p.umin), float(p.umax), float(mu), _p(x), _p(u),
-                             _p(o["A"]), _p(o["B"]), _p(o["lam"]), _p(o["P"]), _p(o["Rh"]), _p(o["d"]))
+                             _p(o["A"]), _p(o["B"]), _p(o["lam"]), _p(o["P"]), _p(o["Rh"]), _p(o["d"]),
+                             _p(o["M"]))
     return o
 
 
 def nmpc_rollout(p, u):
-    """Nonlinear rollout (pure numpy, for tests): x [T+1, nx]."""
+    """Nonlinear rollout x [T+1, nx] of the controls u (no feasibility check)."""
+    model, prm = _model(p)
+    u = _f(np.asarray(u).reshape(p.T, p.nu))
+    W, Bm = _wb(p)
     x = np.zeros((p.T + 1, p.nx))
-    x[0] = p.x0
-    for k in range(p.T):
-        x[k + 1] = x[k] + p.h * (np.tanh(p.W @ x[k]) + p.Bm @ u[k])
+    if lib().oracle_nmpc_rollout(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(_f(p.x0)),
+                                 _p(u), _p(x)) != 0:
+        raise ValueError("nmpc_rollout: unknown model")
     return x
 
 
-def nmpc_newton_step(p, x, u, mu, alpha, nu_lm):
-    """One Alg. 4 iteration; returns (accepted, x, u, alpha, nu_lm, cost, pred, rho)."""
+def nmpc_newton_step(p, x, u, mu, alpha, nu_lm, *, with_grad=False):
+    """One Alg. 4 iteration; returns (accepted, x, u, alpha, nu_lm, cost, pred, rho)
+    (plus |dJ_mu/du|_inf at the starting nominal when with_grad)."""
+    model, prm = _model(p)
     x, u = _f(x).copy(), _f(u).copy()
-    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
+    W, Bm = _wb(p)
+    Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
     a, nl = ctypes.c_double(alpha), ctypes.c_double(nu_lm)
-    cost, pred, rho = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    acc = lib().oracle_nmpc_newton_step(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R),
-                                        _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax),
+    cost, pred, rho, grad = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    acc = lib().oracle_nmpc_newton_step(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q),
+                                        _p(R), _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax),
                                         float(mu), ctypes.byref(a), ctypes.byref(nl), _p(x), _p(u),
-                                        ctypes.byref(cost), ctypes.byref(pred), ctypes.byref(rho))
-    return bool(acc), x, u, a.value, nl.value, cost.value, pred.value, rho.value
+                                        ctypes.byref(cost), ctypes.byref(pred), ctypes.byref(rho),
+                                        ctypes.byref(grad))
+    if acc < 0:
+        raise ValueError("nmpc_newton_step: unknown model")
+    out = (bool(acc), x, u, a.value, nl.value, cost.value, pred.value, rho.value)
+    return out + (grad.value,) if with_grad else out
 
 
 def nmpc_solve(p, mu_levels, iters, alpha0, nu0):
-    """Full IP loop; returns dict(u, x, cost, accept, alpha)."""
-    W, Bm, Q, R, QT, xref, x0 = map(_f, (p.W, p.Bm, p.Q, p.R, p.QT, p.xref, p.x0))
+    """IP loop with a fixed iteration count per level; returns dict(u, x, cost, accept, alpha)."""
+    model, prm = _model(p)
+    W, Bm = _wb(p)
+    Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
     u = _f(p.u0).copy()
     x = np.zeros((p.T + 1, p.nx))
     mus = np.asarray(mu_levels, np.float64)
     n_it = len(mus) * iters
     cost, alph = np.zeros(n_it), np.zeros(n_it)
     acc = np.zeros(n_it, np.int32)
-    st = lib().oracle_nmpc_solve(p.nx, p.nu, p.T, float(p.h), _p(W), _p(Bm), _p(Q), _p(R), _p(QT),
+    st = lib().oracle_nmpc_solve(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R), _p(QT),
                                  _p(xref), _p(x0), float(p.umin), float(p.umax), _p(mus), len(mus),
                                  iters, float(alpha0), float(nu0), _p(u), _p(x), _p(cost),
                                  acc.ctypes.data_as(_I), _p(alph))
     if st != 0:
         raise OracleError(st, -1)
     return {"u": u, "x": x, "cost": cost, "accept": acc.astype(bool), "alpha": alph}
+
+
+def nmpc_ip_solve(p, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, cap=4096):
+    """Interior-point method with converged inner Newton loops (Sec. II-B, Alg. 4).
+
+    Returns dict(u, x, iters, level_iters, mu, cost, grad, accept) with
+    per-iteration traces (grad: |dJ_mu/du|_inf at the nominal each iteration starts from).
+    """
+    model, prm = _model(p)
+    W, Bm = _wb(p)
+    Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
+    u = _f(p.u0).copy()
+    x = np.zeros((p.T + 1, p.nx))
+    mu_t, cost_t, grad_t = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    acc_t = np.zeros(cap, np.int32)
+    lv = np.zeros(64, np.int32)
+    it = lib().oracle_nmpc_ip_solve(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
+                                    _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu0),
+                                    float(zeta), float(mu_min), float(tol), int(max_iter), float(alpha0),
+                                    float(nu0), _p(u), _p(x), cap, _p(mu_t), _p(cost_t), _p(grad_t),
+                                    acc_t.ctypes.data_as(_I), lv.ctypes.data_as(_I))
+    if it < 0:
+        raise OracleError(it, -1)
+    n_lv = 0
+    mu = float(mu0)
+    while mu > mu_min:
+        n_lv += 1
+        mu *= zeta
+    return {"u": u, "x": x, "iters": it, "level_iters": lv[:n_lv].copy(), "mu": mu_t[:it].copy(),
+            "cost": cost_t[:it].copy(), "grad": grad_t[:it].copy(), "accept": acc_t[:it].astype(bool)}

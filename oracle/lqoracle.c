@@ -30,7 +30,10 @@
  *                          system (not in the paper): a second LQ solve with
  *                          the loss gradients as linear terms.
  *   oracle_nmpc_*          the interior-point Newton method of Alg. 4 with
- *                          the log barrier of Sec. II-B for the tanh model.
+ *                          the log barrier of Sec. II-B, for a synthetic
+ *                          tanh-network model and the torque-limited
+ *                          pendulum and force-limited cart-pole of Sec. V
+ *                          (hand-derived Jacobians and second derivatives).
  *
  * Error codes: 0 ok, -2 not positive definite (stage in *fail_k),
  * -3 singular, -4 non-finite.
@@ -542,31 +545,202 @@ done:
 }
 
 /* ------------------------------------------------------------------ */
-/* Interior-point Newton method for x' = x + h (tanh(W x) + B u)       */
+/* Interior-point Newton method for x' = x + h f(x, u)                 */
 /* ------------------------------------------------------------------ */
 /*
+ * Models (one explicit Euler step F(x, u) = x + h f(x, u) of Sec. V):
+ *   NMPC_TANH      f = tanh(W x) + B u (synthetic network dynamics);
+ *   NMPC_PENDULUM  x = (theta, omega), u = tau, prm = (g, l, m, b):
+ *                  theta'' = -(g/l) sin theta + (tau - b omega)/(m l^2);
+ *   NMPC_CARTPOLE  x = (p, theta, v, omega), u = F, prm = (g, l, m_c, m_p):
+ *                  p''     = (F + m_p s (l omega^2 + g c)) / D,
+ *                  theta'' = (-F c - m_p l omega^2 c s - (m_c + m_p) g s) / (l D),
+ *                  s = sin theta, c = cos theta, D = m_c + m_p s^2
+ *                  (the omega^2 in p'' is the textbook cart-pole's; the
+ *                  printed p'' has omega to the first power).
  * Costs: l_k = 1/2 (x - ref_k)'Q(x - ref_k) + 1/2 u'R u,
  *        l_T = 1/2 (x - ref_T)'Q_T(x - ref_T).
  * Box |u_i| bounds as 2 nu inequality constraints (u - umax <= 0,
  * umin - u <= 0) with the log barrier of Sec. II-B:
  *        c(u) = -mu sum_i [log(umax - u_i) + log(u_i - umin)].
  */
+#define NMPC_TANH 0
+#define NMPC_PENDULUM 1
+#define NMPC_CARTPOLE 2
+
 typedef struct {
     int nx, nu, T;
     double h;
+    int model;
+    const double *prm;
     const double *W, *Bm, *Q, *R, *QT, *xref, *x0;
     double umin, umax;
 } nmpc_prob;
 
+/* Value and derivatives over (theta, omega, F) of a cart-pole quantity. */
+typedef struct {
+    double v, t, w, F, tt, tw, tF, ww, wF, FF;
+} cp_d2;
+
+/* q = N / D with D a function of theta alone (quotient rule, first and
+ * second derivatives). */
+static cp_d2 cp_quot(cp_d2 N, double D, double Dt, double Dtt)
+{
+    cp_d2 q;
+    const double D2 = D * D, D3 = D2 * D;
+    q.v = N.v / D;
+    q.t = N.t / D - N.v * Dt / D2;
+    q.w = N.w / D;
+    q.F = N.F / D;
+    q.tt = N.tt / D - 2.0 * N.t * Dt / D2 - N.v * Dtt / D2 + 2.0 * N.v * Dt * Dt / D3;
+    q.tw = N.tw / D - N.w * Dt / D2;
+    q.tF = N.tF / D - N.F * Dt / D2;
+    q.ww = N.ww / D;
+    q.wF = N.wF / D;
+    q.FF = N.FF / D;
+    return q;
+}
+
+/* The cart-pole accelerations a3 = p'' and a4 = theta'' with their
+ * derivatives over (theta, omega, F). */
+static void cp_accel(const double *prm, const double *x, const double *u, cp_d2 *a3, cp_d2 *a4)
+{
+    const double g = prm[0], l = prm[1], mc = prm[2], mp = prm[3];
+    const double s = sin(x[1]), c = cos(x[1]), w = x[3], F = u[0];
+    const double D = mc + mp * s * s, Dt = 2.0 * mp * s * c, Dtt = 2.0 * mp * (c * c - s * s);
+    cp_d2 N3, N4;
+    /* N3 = F + m_p l w^2 s + m_p g s c */
+    N3.v = F + mp * l * w * w * s + mp * g * s * c;
+    N3.t = mp * l * w * w * c + mp * g * (c * c - s * s);
+    N3.w = 2.0 * mp * l * w * s;
+    N3.F = 1.0;
+    N3.tt = -mp * l * w * w * s - 4.0 * mp * g * s * c;
+    N3.tw = 2.0 * mp * l * w * c;
+    N3.tF = 0.0;
+    N3.ww = 2.0 * mp * l * s;
+    N3.wF = 0.0;
+    N3.FF = 0.0;
+    /* N4 = -F c - m_p l w^2 c s - (m_c + m_p) g s   (theta'' = N4 / (l D)) */
+    N4.v = -F * c - mp * l * w * w * c * s - (mc + mp) * g * s;
+    N4.t = F * s - mp * l * w * w * (c * c - s * s) - (mc + mp) * g * c;
+    N4.w = -2.0 * mp * l * w * c * s;
+    N4.F = -c;
+    N4.tt = F * c + 4.0 * mp * l * w * w * s * c + (mc + mp) * g * s;
+    N4.tw = -2.0 * mp * l * w * (c * c - s * s);
+    N4.tF = s;
+    N4.ww = -2.0 * mp * l * c * s;
+    N4.wF = 0.0;
+    N4.FF = 0.0;
+    *a3 = cp_quot(N3, D, Dt, Dtt);
+    cp_d2 q = cp_quot(N4, D, Dt, Dtt);
+    q.v /= l; q.t /= l; q.w /= l; q.F /= l;
+    q.tt /= l; q.tw /= l; q.tF /= l; q.ww /= l; q.wF /= l; q.FF /= l;
+    *a4 = q;
+}
+
+/* Continuous-time right-hand side f(x, u) of the pendulum and cart-pole. */
+static void model_f(const nmpc_prob *P, const double *x, const double *u, double *f)
+{
+    if (P->model == NMPC_PENDULUM) {
+        const double g = P->prm[0], l = P->prm[1], m = P->prm[2], b = P->prm[3];
+        f[0] = x[1];
+        f[1] = -g / l * sin(x[0]) + (u[0] - b * x[1]) / (m * l * l);
+    } else {
+        cp_d2 a3, a4;
+        cp_accel(P->prm, x, u, &a3, &a4);
+        f[0] = x[2];
+        f[1] = x[3];
+        f[2] = a3.v;
+        f[3] = a4.v;
+    }
+}
+
+/* Jacobians fx = df/dx (n x n), fu = df/du (n x m) of the pendulum and
+ * cart-pole right-hand sides. */
+static void model_jac(const nmpc_prob *P, const double *x, const double *u, double *fx, double *fu)
+{
+    const int n = P->nx, m = P->nu;
+    memset(fx, 0, sizeof(double) * n * n);
+    memset(fu, 0, sizeof(double) * n * m);
+    if (P->model == NMPC_PENDULUM) {
+        const double g = P->prm[0], l = P->prm[1], mm = P->prm[2], b = P->prm[3];
+        fx[0 * 2 + 1] = 1.0;
+        fx[1 * 2 + 0] = -g / l * cos(x[0]);
+        fx[1 * 2 + 1] = -b / (mm * l * l);
+        fu[1] = 1.0 / (mm * l * l);
+    } else {
+        cp_d2 a3, a4;
+        cp_accel(P->prm, x, u, &a3, &a4);
+        fx[0 * 4 + 2] = 1.0;
+        fx[1 * 4 + 3] = 1.0;
+        fx[2 * 4 + 1] = a3.t;
+        fx[2 * 4 + 3] = a3.w;
+        fx[3 * 4 + 1] = a4.t;
+        fx[3 * 4 + 3] = a4.w;
+        fu[2] = a3.F;
+        fu[3] = a4.F;
+    }
+}
+
+/* Contraction of the second derivatives of f with a co-state lam:
+ * Hxx = sum_i lam_i d2f_i/dx2 (n x n), Hxu = sum_i lam_i d2f_i/dxdu (n x m),
+ * Huu = sum_i lam_i d2f_i/du2 (m x m). */
+static void model_hess(const nmpc_prob *P, const double *x, const double *u, const double *lam, double *Hxx,
+                       double *Hxu, double *Huu)
+{
+    const int n = P->nx, m = P->nu;
+    memset(Hxx, 0, sizeof(double) * n * n);
+    memset(Hxu, 0, sizeof(double) * n * m);
+    memset(Huu, 0, sizeof(double) * m * m);
+    if (P->model == NMPC_PENDULUM) {
+        const double g = P->prm[0], l = P->prm[1];
+        Hxx[0] = lam[1] * (g / l) * sin(x[0]);   /* d2/dtheta2 of -(g/l) sin theta */
+    } else {
+        cp_d2 a3, a4;
+        cp_accel(P->prm, x, u, &a3, &a4);
+        const double l3 = lam[2], l4 = lam[3];
+        Hxx[1 * 4 + 1] = l3 * a3.tt + l4 * a4.tt;
+        Hxx[1 * 4 + 3] = Hxx[3 * 4 + 1] = l3 * a3.tw + l4 * a4.tw;
+        Hxx[3 * 4 + 3] = l3 * a3.ww + l4 * a4.ww;
+        Hxu[1] = l3 * a3.tF + l4 * a4.tF;
+        Hxu[3] = l3 * a3.wF + l4 * a4.wF;
+        Huu[0] = l3 * a3.FF + l4 * a4.FF;
+    }
+}
+
 static void f_step(const nmpc_prob *P, const double *x, const double *u, double *xn)
 {
     const int n = P->nx, m = P->nu;
-    for (int i = 0; i < n; ++i) {
-        double z = 0, bu = 0;
-        for (int j = 0; j < n; ++j) z += P->W[i * n + j] * x[j];
-        for (int j = 0; j < m; ++j) bu += P->Bm[i * m + j] * u[j];
-        xn[i] = x[i] + P->h * (tanh(z) + bu);
+    if (P->model == NMPC_TANH) {
+        for (int i = 0; i < n; ++i) {
+            double z = 0, bu = 0;
+            for (int j = 0; j < n; ++j) z += P->W[i * n + j] * x[j];
+            for (int j = 0; j < m; ++j) bu += P->Bm[i * m + j] * u[j];
+            xn[i] = x[i] + P->h * (tanh(z) + bu);
+        }
+    } else {
+        double f[4];
+        model_f(P, x, u, f);
+        for (int i = 0; i < n; ++i) xn[i] = x[i] + P->h * f[i];
     }
+}
+
+/* Model check: 0 if (model, n, m) is a known combination. */
+static int model_ok(int model, int n, int m, const double *prm)
+{
+    if (model == NMPC_TANH) return 0;
+    if (model == NMPC_PENDULUM) return (n == 2 && m == 1 && prm) ? 0 : -1;
+    if (model == NMPC_CARTPOLE) return (n == 4 && m == 1 && prm) ? 0 : -1;
+    return -1;
+}
+
+/* f(x, u) for tests (pendulum and cart-pole only); returns -1 otherwise. */
+int oracle_nmpc_f(int model, const double *prm, int nx, int nu, const double *x, const double *u, double *f)
+{
+    if (model == NMPC_TANH || model_ok(model, nx, nu, prm) != 0) return -1;
+    nmpc_prob P = {nx, nu, 0, 0.0, model, prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0.0, 0.0};
+    model_f(&P, x, u, f);
+    return 0;
 }
 
 /* Nonlinear rollout from x0 under u; returns 0, or -1 if u is infeasible. */
@@ -602,49 +776,79 @@ static double cost_mu(const nmpc_prob *P, const double *u, const double *x, doub
     return J;
 }
 
-double oracle_nmpc_cost(int nx, int nu, int T, double h, const double *W, const double *Bm,
-                        const double *Q, const double *R, const double *QT, const double *xref,
+double oracle_nmpc_cost(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                        const double *Bm, const double *Q, const double *R, const double *QT, const double *xref,
                         const double *x0, double umin, double umax, double mu, const double *u)
 {
-    nmpc_prob P = {nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    if (model_ok(model, nx, nu, prm) != 0) return NAN;
+    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
     double *x = malloc(sizeof(double) * (size_t)(T + 1) * nx);
     double J = rollout(&P, u, x) == 0 ? cost_mu(&P, u, x, mu) : INFINITY;
     free(x);
     return J;
 }
 
+/* Nonlinear rollout x [T+1][nx] of u (feasibility not checked). */
+int oracle_nmpc_rollout(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                        const double *Bm, const double *x0, const double *u, double *x)
+{
+    if (model_ok(model, nx, nu, prm) != 0) return -1;
+    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, NULL, NULL, NULL, NULL, x0, 0.0, 0.0};
+    memcpy(x, x0, sizeof(double) * nx);
+    for (int k = 0; k < T; ++k) f_step(&P, x + (size_t)k * nx, u + (size_t)k * nu, x + (size_t)(k + 1) * nx);
+    return 0;
+}
+
 /*
  * Linearisation, co-states and quadraticisation at the nominal (x, u)
- * (Alg. 1 and the expansion of Sec. III-C):
- *   z = W x,  A_k = df/dx = I + h diag(1 - tanh^2 z) W,  B_k = df/du = h B,
+ * (Alg. 1 and the expansion of Sec. III-C), with F = x + h f:
+ *   A_k = dF/dx = I + h df/dx,  B_k = dF/du = h df/du,
  *   lam_T = Q_T(x_T - ref_T),  lam_k = Q(x_k - ref_k) + A_k' lam_{k+1}
  *     (eq:co-state-eq; the barrier has no x-dependence),
- *   P_k = Q + sum_i lam_{k+1,i} h tanh''(z_i) w_i w_i'    (w_i = row i of W),
- *   Rh_k = R + d2c/du2 = R + mu diag(1/(umax-u)^2 + 1/(u-umin)^2),
- *   M_k = 0,  d_k = R u + dc/du + B_k' lam_{k+1},  P_T = Q_T.
+ *   P_k = Q + h lam_{k+1}' d2f/dx2,  M_k = h lam_{k+1}' d2f/dxdu,
+ *   Rh_k = R + d2c/du2 + h lam_{k+1}' d2f/du2
+ *        = ... + mu diag(1/(umax-u)^2 + 1/(u-umin)^2),
+ *   d_k = R u + dc/du + B_k' lam_{k+1},  P_T = Q_T.
+ * For the tanh model z = W x, df/dx = diag(1 - tanh^2 z) W, df/du = B,
+ * lam' d2f/dx2 = sum_i lam_i tanh''(z_i) w_i w_i' (w_i = row i of W), and
+ * the mixed and control second derivatives vanish.
  * Outputs: A [T][n][n], Bl [T][n][m], lam [T+1][n], P [T][n][n],
- * Rh [T][m][m], d [T][m].  Any may be NULL except where a later one needs it.
+ * Rh [T][m][m], d [T][m], M [T][n][m].  Any may be NULL except where a later
+ * one needs it.
  */
-void oracle_nmpc_expand(int nx, int nu, int T, double h, const double *W, const double *Bm,
-                        const double *Q, const double *R, const double *QT, const double *xref,
-                        double umin, double umax, double mu, const double *x, const double *u,
-                        double *A, double *Bl, double *lam, double *P, double *Rh, double *d)
+void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                        const double *Bm, const double *Q, const double *R, const double *QT,
+                        const double *xref, double umin, double umax, double mu, const double *x,
+                        const double *u, double *A, double *Bl, double *lam, double *P, double *Rh, double *d,
+                        double *M)
 {
     const int n = nx, m = nu;
+    if (model_ok(model, nx, nu, prm) != 0) return;
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, NULL, umin, umax};
     double *th = malloc(sizeof(double) * (size_t)T * n);
-    for (int k = 0; k < T; ++k)
-        for (int i = 0; i < n; ++i) {
-            double z = 0;
-            for (int j = 0; j < n; ++j) z += W[i * n + j] * x[(size_t)k * n + j];
-            th[(size_t)k * n + i] = tanh(z);
-        }
-    for (int k = 0; k < T; ++k) {
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                double t = th[(size_t)k * n + i];
-                A[(size_t)k * n * n + i * n + j] = (i == j ? 1.0 : 0.0) + h * (1.0 - t * t) * W[i * n + j];
+    if (model == NMPC_TANH) {
+        for (int k = 0; k < T; ++k)
+            for (int i = 0; i < n; ++i) {
+                double z = 0;
+                for (int j = 0; j < n; ++j) z += W[i * n + j] * x[(size_t)k * n + j];
+                th[(size_t)k * n + i] = tanh(z);
             }
-        for (int i = 0; i < n * m; ++i) Bl[(size_t)k * n * m + i] = h * Bm[i];
+        for (int k = 0; k < T; ++k) {
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) {
+                    double t = th[(size_t)k * n + i];
+                    A[(size_t)k * n * n + i * n + j] = (i == j ? 1.0 : 0.0) + h * (1.0 - t * t) * W[i * n + j];
+                }
+            for (int i = 0; i < n * m; ++i) Bl[(size_t)k * n * m + i] = h * Bm[i];
+        }
+    } else {
+        double fx[16], fu[4];
+        for (int k = 0; k < T; ++k) {
+            model_jac(&Pb, x + (size_t)k * n, u + (size_t)k * m, fx, fu);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) A[(size_t)k * n * n + i * n + j] = (i == j ? 1.0 : 0.0) + h * fx[i * n + j];
+            for (int i = 0; i < n * m; ++i) Bl[(size_t)k * n * m + i] = h * fu[i];
+        }
     }
     /* co-states */
     for (int i = 0; i < n; ++i) {
@@ -661,15 +865,26 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, const double *W, const 
         }
     /* second-order terms */
     for (int k = 0; k < T; ++k) {
+        double Hxx[16], Hxu[4], Huu[1] = {0.0};
+        if (model != NMPC_TANH)
+            model_hess(&Pb, x + (size_t)k * n, u + (size_t)k * m, lam + (size_t)(k + 1) * n, Hxx, Hxu, Huu);
         if (P) {
             double *Pk = P + (size_t)k * n * n;
             memcpy(Pk, Q, sizeof(double) * n * n);
-            for (int i = 0; i < n; ++i) {
-                double t = th[(size_t)k * n + i];
-                double w = lam[(size_t)(k + 1) * n + i] * h * (-2.0 * t * (1.0 - t * t));
-                for (int a = 0; a < n; ++a)
-                    for (int b = 0; b < n; ++b) Pk[a * n + b] += w * W[i * n + a] * W[i * n + b];
+            if (model == NMPC_TANH) {
+                for (int i = 0; i < n; ++i) {
+                    double t = th[(size_t)k * n + i];
+                    double w = lam[(size_t)(k + 1) * n + i] * h * (-2.0 * t * (1.0 - t * t));
+                    for (int a = 0; a < n; ++a)
+                        for (int b = 0; b < n; ++b) Pk[a * n + b] += w * W[i * n + a] * W[i * n + b];
+                }
+            } else {
+                for (int i = 0; i < n * n; ++i) Pk[i] += h * Hxx[i];
             }
+        }
+        if (M) {
+            double *Mk = M + (size_t)k * n * m;
+            for (int i = 0; i < n * m; ++i) Mk[i] = (model == NMPC_TANH) ? 0.0 : h * Hxu[i];
         }
         if (Rh) {
             double *Rk = Rh + (size_t)k * m * m;
@@ -678,6 +893,8 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, const double *W, const 
                 double uu = u[(size_t)k * m + i], a = umax - uu, b = uu - umin;
                 Rk[i * m + i] += mu * (1.0 / (a * a) + 1.0 / (b * b));
             }
+            if (model != NMPC_TANH)
+                for (int i = 0; i < m * m; ++i) Rk[i] += h * Huu[i];
         }
         if (d)
             for (int i = 0; i < m; ++i) {
@@ -697,41 +914,47 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, const double *W, const 
  * alpha and growth factor nu_lm (both updated in place):
  *   1-3. linearise, co-states, quadraticise (oracle_nmpc_expand);
  *   4.   LQ step: eq:linearized-ocp with psi_k of eq:linearized-ocp-param
- *        (R + alpha I), delta x_0 = 0, solved by oracle_lq_solve;
+ *        (R + alpha I, cross term M), delta x_0 = 0, solved by oracle_lq_solve;
  *   5.   predicted decrease of the expansion without the alpha term,
- *        pred = -[sum d'du + 1/2 sum (dx'P dx + du'Rh du) + 1/2 dx_T'P_T dx_T];
+ *        pred = -[sum d'du + 1/2 sum (dx'P dx + 2 dx'M du + du'Rh du)
+ *                 + 1/2 dx_T'P_T dx_T];
  *   6.   candidate u + du, nonlinear rollout, gain ratio
  *        rho = (J_mu(u) - J_mu(u + du)) / pred;
  *   7.   accept if pred > 0 and rho > 0 (finite): alpha *= max(1/3, 1-(2 rho-1)^3),
  *        nu_lm = 2; else alpha *= nu_lm, nu_lm *= 2.
  * x, u hold the nominal and are replaced on acceptance.  Returns 1 if
- * accepted, 0 if rejected; *cost gets J_mu of the (possibly new) nominal.
+ * accepted, 0 if rejected, -1 for an unknown model; *cost gets J_mu of the
+ * (possibly new) nominal, *grad_out max_k,i |d_k,i| = |dJ_mu/du|_inf at the
+ * nominal the iteration started from.
  */
-int oracle_nmpc_newton_step(int nx, int nu, int T, double h, const double *W, const double *Bm,
-                            const double *Q, const double *R, const double *QT,
+int oracle_nmpc_newton_step(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                            const double *Bm, const double *Q, const double *R, const double *QT,
                             const double *xref, const double *x0, double umin, double umax,
                             double mu, double *alpha, double *nu_lm, double *x, double *u,
-                            double *cost, double *pred_out, double *rho_out)
+                            double *cost, double *pred_out, double *rho_out, double *grad_out)
 {
     const int n = nx, m = nu;
-    nmpc_prob Pb = {nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    if (model_ok(model, nx, nu, prm) != 0) return -1;
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
     size_t Tn = (size_t)T * n, Tnn = Tn * n, Tm = (size_t)T * m;
     double *A = malloc(sizeof(double) * Tnn), *Bl = malloc(sizeof(double) * Tn * m);
     double *lam = malloc(sizeof(double) * (Tn + n)), *P = malloc(sizeof(double) * Tnn);
     double *Rh = malloc(sizeof(double) * Tm * m), *d = malloc(sizeof(double) * Tm);
+    double *Mx = malloc(sizeof(double) * Tn * m);
     double *Ra = malloc(sizeof(double) * Tm * m);
     double *dx = malloc(sizeof(double) * (Tn + n)), *du = malloc(sizeof(double) * Tm);
     double *un = malloc(sizeof(double) * Tm), *xn = malloc(sizeof(double) * (Tn + n));
     double *zero = calloc((size_t)n, sizeof(double));
     int accepted = 0;
     double J0 = cost_mu(&Pb, u, x, mu), pred = 0, rho = -INFINITY;
-    oracle_nmpc_expand(nx, nu, T, h, W, Bm, Q, R, QT, xref, umin, umax, mu, x, u, A, Bl, lam, P, Rh, d);
+    oracle_nmpc_expand(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, umin, umax, mu, x, u, A, Bl, lam, P, Rh, d,
+                       Mx);
     for (size_t k = 0; k < (size_t)T; ++k)
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j)
                 Ra[k * m * m + i * m + j] = Rh[k * m * m + i * m + j] + (i == j ? *alpha : 0.0);
     int fk;
-    int st = oracle_lq_solve(n, m, T, A, Bl, NULL, P, Ra, NULL, NULL, d, QT, NULL, zero,
+    int st = oracle_lq_solve(n, m, T, A, Bl, NULL, P, Ra, model == NMPC_TANH ? NULL : Mx, NULL, d, QT, NULL, zero,
                              NULL, NULL, NULL, NULL, dx, du, NULL, &fk);
     if (st == OK) {
         for (size_t k = 0; k < (size_t)T; ++k) {
@@ -740,6 +963,9 @@ int oracle_nmpc_newton_step(int nx, int nu, int T, double h, const double *W, co
             double qf = 0;
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < n; ++j) qf += dxk[i] * P[k * n * n + i * n + j] * dxk[j];
+            if (model != NMPC_TANH)
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < m; ++j) qf += 2.0 * dxk[i] * Mx[k * n * m + i * m + j] * duk[j];
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j < m; ++j) qf += duk[i] * Rh[k * m * m + i * m + j] * duk[j];
             pred += 0.5 * qf;
@@ -774,39 +1000,92 @@ int oracle_nmpc_newton_step(int nx, int nu, int T, double h, const double *W, co
     if (cost) *cost = J0;
     if (pred_out) *pred_out = pred;
     if (rho_out) *rho_out = rho;
-    free(A); free(Bl); free(lam); free(P); free(Rh); free(d); free(Ra);
+    if (grad_out) {
+        double g = 0.0;
+        for (size_t i = 0; i < Tm; ++i) g = fmax(g, fabs(d[i]));
+        *grad_out = g;
+    }
+    free(A); free(Bl); free(lam); free(P); free(Rh); free(d); free(Mx); free(Ra);
     free(dx); free(du); free(un); free(xn); free(zero);
     return accepted;
 }
 
 /*
- * The interior-point outer loop of Sec. II-B around Alg. 4: for each barrier
- * level mu in mu_levels (decreasing), run iters Newton iterations.  u holds
- * the strictly feasible initial controls and is overwritten by the result;
- * x gets the final nonlinear rollout.  Traces (length n_levels * iters, any
- * may be NULL) record the cost after each iteration, the accept flag and the
- * Levenberg-Marquardt weight used in it.  Returns 0, or -1 if u starts
- * infeasible.
+ * The interior-point outer loop of Sec. II-B around Alg. 4 with a fixed
+ * number of Newton iterations per barrier level: for each mu in mu_levels
+ * (decreasing), run iters iterations.  u holds the strictly feasible initial
+ * controls and is overwritten by the result; x gets the final nonlinear
+ * rollout.  Traces (length n_levels * iters, any may be NULL) record the
+ * cost after each iteration, the accept flag and the Levenberg-Marquardt
+ * weight used in it.  Returns 0, or -1 if u starts infeasible or the model
+ * is unknown.
  */
-int oracle_nmpc_solve(int nx, int nu, int T, double h, const double *W, const double *Bm,
-                      const double *Q, const double *R, const double *QT, const double *xref,
+int oracle_nmpc_solve(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                      const double *Bm, const double *Q, const double *R, const double *QT, const double *xref,
                       const double *x0, double umin, double umax,
                       const double *mu_levels, int n_levels, int iters,
                       double alpha0, double nu0, double *u, double *x,
                       double *cost_trace, int *accept_trace, double *alpha_trace)
 {
-    nmpc_prob Pb = {nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    if (model_ok(model, nx, nu, prm) != 0) return -1;
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
     if (rollout(&Pb, u, x) != 0) return -1;
     double alpha = alpha0, nu_lm = nu0;
     int it = 0;
     for (int lv = 0; lv < n_levels; ++lv)
         for (int i = 0; i < iters; ++i, ++it) {
             double a_used = alpha, cst;
-            int acc = oracle_nmpc_newton_step(nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, umin, umax,
-                                              mu_levels[lv], &alpha, &nu_lm, x, u, &cst, NULL, NULL);
+            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax,
+                                              mu_levels[lv], &alpha, &nu_lm, x, u, &cst, NULL, NULL, NULL);
             if (cost_trace) cost_trace[it] = cst;
             if (accept_trace) accept_trace[it] = acc;
             if (alpha_trace) alpha_trace[it] = a_used;
         }
     return 0;
+}
+
+/*
+ * The interior-point method of Sec. II-B with Alg. 4 as its inner solver,
+ * as run in the experiments of Sec. V: barrier levels mu = mu0, mu0 zeta,
+ * mu0 zeta^2, ... while mu > mu_min, each solved by Newton iterations until
+ * one that starts from a nominal with |dJ_mu/du|_inf <= tol (that
+ * iteration's step is still taken), or max_iter iterations.  The nominal,
+ * alpha and nu_lm carry over from level to level.  Traces of capacity cap
+ * (any NULL): barrier weight, cost after, gradient norm before and accept
+ * flag of every iteration; level_iters gets the iteration count of each
+ * level.  Returns the total number of iterations, -1 if u starts infeasible
+ * or the model is unknown, -2 if cap is too small.
+ */
+int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                         const double *Bm, const double *Q, const double *R, const double *QT,
+                         const double *xref, const double *x0, double umin, double umax, double mu0,
+                         double zeta, double mu_min, double tol, int max_iter, double alpha0, double nu0,
+                         double *u, double *x, int cap, double *mu_trace, double *cost_trace,
+                         double *grad_trace, int *accept_trace, int *level_iters)
+{
+    if (model_ok(model, nx, nu, prm) != 0 || !(zeta > 0.0 && zeta < 1.0) || !(mu0 > 0.0)) return -1;
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    if (rollout(&Pb, u, x) != 0) return -1;
+    double alpha = alpha0, nu_lm = nu0;
+    int it = 0, lv = 0;
+    for (double mu = mu0; mu > mu_min; mu *= zeta, ++lv) {
+        int li = 0;
+        for (; li < max_iter; ++li) {
+            double cst, grad;
+            if (it >= cap) return -2;
+            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, mu,
+                                              &alpha, &nu_lm, x, u, &cst, NULL, NULL, &grad);
+            if (mu_trace) mu_trace[it] = mu;
+            if (cost_trace) cost_trace[it] = cst;
+            if (grad_trace) grad_trace[it] = grad;
+            if (accept_trace) accept_trace[it] = acc;
+            ++it;
+            if (grad <= tol) {
+                ++li;
+                break;
+            }
+        }
+        if (level_iters) level_iters[lv] = li;
+    }
+    return it;
 }

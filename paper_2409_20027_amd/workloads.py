@@ -232,6 +232,8 @@ class NMPCProblem:
     u0: np.ndarray     # [T, nu] strictly feasible initial controls
     umin: float = -1.0
     umax: float = 1.0
+    model: int = 0                  # NMPC_TANH, NMPC_PENDULUM or NMPC_CARTPOLE
+    param: np.ndarray | None = None  # model constants (pendulum g, l, m, b; cart-pole g, l, m_c, m_p)
 
 
 def nmpc_problem(seed: int = 1, nx: int = 4, nu: int = 1, T: int = 1024,
@@ -252,6 +254,61 @@ def nmpc_problem(seed: int = 1, nx: int = 4, nu: int = 1, T: int = 1024,
     xref = 0.5 * np.sin(2 * math.pi * k / 256.0 + math.pi * i / 4.0)
     return NMPCProblem(nx, nu, T, h, W, Bm, np.eye(nx), 0.1 * np.eye(nu), 10.0 * np.eye(nx),
                        np.ascontiguousarray(xref), x0, np.ascontiguousarray(u0))
+
+
+NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE = 0, 1, 2
+PENDULUM_TF = 4.0   # seconds (the time spans are not printed)
+CARTPOLE_TF = 3.0
+
+# Sec. V: pendulum g = 9.81, l = 1, m = 1, b = 1e-3, |tau| < 5;
+# cart-pole g = 9.81, l = 0.5, m_c = 10, m_p = 1, |F| < 60.
+PENDULUM_PARAM = (9.81, 1.0, 1.0, 1e-3)
+PENDULUM_UMAX = 5.0
+CARTPOLE_PARAM = (9.81, 0.5, 10.0, 1.0)
+CARTPOLE_UMAX = 60.0
+# Interior-point schedule of Sec. V: mu from 0.1, times 0.2 while above 1e-4.
+IP_MU0, IP_ZETA, IP_MU_MIN = 0.1, 0.2, 1e-4
+# Inner Newton loop: converged after the iteration that starts from a nominal
+# with |dJ_mu/du|_inf <= IP_TOL (the threshold itself is not printed), at
+# most IP_MAX_ITER iterations per barrier level.
+IP_TOL, IP_MAX_ITER = 1e-6, 100
+# Horizon lengths of the runtime figures of Sec. V.
+PAPER_HORIZONS = (20, 40, 80, 100, 200, 400, 800, 1000)
+
+
+def pendulum_problem(N: int, seed: int = 0, t_final: float = PENDULUM_TF) -> NMPCProblem:
+    """Torque-limited pendulum swing-up over a fixed time t_final in N Euler steps.
+
+    x = (theta, omega), theta = 0 hanging down; from rest at the bottom to the
+    upright x_ref = (pi, 0) at the end: control effort h * 1.0 * tau^2 / 2 per
+    step (a Riemann sum, so that the problem is the same for every N), no
+    running state cost, Q_T = diag(100, 10), |tau| < 5.  Initial controls:
+    u0 ~ N(0, 0.1^2) (strictly feasible).
+    """
+    rng = np.random.default_rng(seed)
+    u0 = 0.1 * rng.standard_normal((N, 1))
+    h = t_final / N
+    xref = np.tile(np.array([math.pi, 0.0]), (N + 1, 1))
+    return NMPCProblem(2, 1, N, h, None, None, np.zeros((2, 2)), np.array([[h * 1.0]]),
+                       np.diag([100.0, 10.0]), xref, np.zeros(2), u0, -PENDULUM_UMAX, PENDULUM_UMAX,
+                       NMPC_PENDULUM, np.array(PENDULUM_PARAM))
+
+
+def cartpole_problem(N: int, seed: int = 0, t_final: float = CARTPOLE_TF) -> NMPCProblem:
+    """Force-limited cart-pole swing-up over a fixed time t_final in N Euler steps.
+
+    x = (p, theta, v, omega), theta = 0 hanging down; from rest to the upright
+    x_ref = (0, pi, 0, 0) at the end: control effort h * 0.01 * F^2 / 2 per
+    step, no running state cost, Q_T = diag(100, 100, 10, 10), |F| < 60.
+    Initial controls: u0 ~ N(0, 1).
+    """
+    rng = np.random.default_rng(seed)
+    u0 = rng.standard_normal((N, 1))
+    h = t_final / N
+    xref = np.tile(np.array([0.0, math.pi, 0.0, 0.0]), (N + 1, 1))
+    return NMPCProblem(4, 1, N, h, None, None, np.zeros((4, 4)), np.array([[h * 0.01]]),
+                       np.diag([100.0, 100.0, 10.0, 10.0]), xref, np.zeros(4), u0, -CARTPOLE_UMAX, CARTPOLE_UMAX,
+                       NMPC_CARTPOLE, np.array(CARTPOLE_PARAM))
 
 
 NMPC_MU_LEVELS = (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
