@@ -230,19 +230,31 @@ lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value
 /*
  * ---------------------------------------------------------------------------
  * Newton / interior-point step (Alg. 4 inside the log-barrier method of
- * Sec. II-B) for the dynamics x_{k+1} = x_k + h (tanh(W x_k) + B u_k),
+ * Sec. II-B) for x_{k+1} = x_k + h f(x_k, u_k) (one explicit Euler step) with
  * l_k = 1/2 (x - ref_k)'Q(x - ref_k) + 1/2 u'R u, l_T = 1/2 (x - ref_T)'Q_T(x - ref_T),
  * and the control box umin < u < umax as 2 nu inequalities with the barrier
- * -mu sum [log(umax - u) + log(u - umin)].
+ * -mu sum [log(umax - u) + log(u - umin)].  Models f:
+ *   NMPC_TANH      f = tanh(W x) + B u (any nx <= 15, nu <= 4);
+ *   NMPC_PENDULUM  the torque-limited pendulum of Sec. V, nx = 2, nu = 1,
+ *                  x = (theta, omega), param = (g, l, m, b);
+ *   NMPC_CARTPOLE  the force-limited cart-pole of Sec. V, nx = 4, nu = 1,
+ *                  x = (p, theta, v, omega), param = (g, l, m_c, m_p), with
+ *                  omega^2 in the cart acceleration (textbook cart-pole).
+ * For the pendulum and cart-pole the second derivatives of f enter P, the
+ * cross term M and R of the expansion (eq:linearized-ocp-param).
  * ---------------------------------------------------------------------------
  */
+typedef enum { NMPC_TANH = 0, NMPC_PENDULUM = 1, NMPC_CARTPOLE = 2 } nmpc_model;
+
 typedef struct {
     int32_t nx, nu, T;
     double h;
-    const double *W, *Bm;          /* nx*nx, nx*nu                    (device) */
+    const double *W, *Bm;          /* nx*nx, nx*nu (device; NMPC_TANH only, else ignored) */
     const double *Q, *R, *QT;      /* nx*nx, nu*nu, nx*nx             (device) */
     const double *xref, *x0;       /* (T+1)*nx, nx                    (device) */
     double umin, umax;
+    int32_t model;                 /* nmpc_model                                */
+    double param[4];               /* model constants (host values)             */
 } nmpc_problem;
 
 /* Indices of the device scalar array nmpc_state.scal (NMPC_NSCAL doubles). */
@@ -255,7 +267,8 @@ enum {
     NMPC_RHO = 5,         /* gain ratio (-inf if rejected before it could be formed)  */
     NMPC_ACCEPTED = 6,    /* 1.0 if the step was accepted                             */
     NMPC_COST_NEW = 7,    /* J_mu of the candidate                                    */
-    NMPC_NSCAL = 8
+    NMPC_GRAD = 8,        /* |dJ_mu/du|_inf at the nominal the step started from      */
+    NMPC_NSCAL = 9
 };
 
 typedef struct {
@@ -282,7 +295,7 @@ lq_status nmpc_init(const lq_plan *plan, const nmpc_problem *prob, const nmpc_st
  * definite) leaves the nominal unchanged and increases alpha.  Everything is
  * enqueued on `stream`; decisions are taken on the device.  `status` is not
  * written (rejections are part of the method).  Errors: LQ_ERR_ARG if the
- * plan does not match the problem.
+ * plan does not match the problem or the model its sizes.
  */
 lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
                       int32_t *status, void *stream);

@@ -74,7 +74,7 @@ def lib():
                                             + [_P, _P, _P, _I, _P])
             L.oracle_nmpc_solve.restype = i
             L.oracle_nmpc_ip_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, d, d, d, i, d, d]
-                                               + [_P, _P, i, _P, _P, _P, _I, _I])
+                                               + [_P, _P, i, _P, _P, _P, _P, _I, _I])
             L.oracle_nmpc_ip_solve.restype = i
             _lib = L
     return _lib
@@ -298,7 +298,7 @@ def nmpc_solve(p, mu_levels, iters, alpha0, nu0):
 def nmpc_ip_solve(p, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, cap=4096):
     """Interior-point method with converged inner Newton loops (Sec. II-B, Alg. 4).
 
-    Returns dict(u, x, iters, level_iters, mu, cost, grad, accept) with
+    Returns dict(u, x, iters, level_iters, mu, cost, grad, pred, accept) with
     per-iteration traces (grad: |dJ_mu/du|_inf at the nominal each iteration starts from).
     """
     model, prm = _model(p)
@@ -306,13 +306,13 @@ def nmpc_ip_solve(p, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, cap=4096)
     Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
     u = _f(p.u0).copy()
     x = np.zeros((p.T + 1, p.nx))
-    mu_t, cost_t, grad_t = np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    mu_t, cost_t, grad_t, pred_t = np.zeros(cap), np.zeros(cap), np.zeros(cap), np.zeros(cap)
     acc_t = np.zeros(cap, np.int32)
     lv = np.zeros(64, np.int32)
     it = lib().oracle_nmpc_ip_solve(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
                                     _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu0),
                                     float(zeta), float(mu_min), float(tol), int(max_iter), float(alpha0),
-                                    float(nu0), _p(u), _p(x), cap, _p(mu_t), _p(cost_t), _p(grad_t),
+                                    float(nu0), _p(u), _p(x), cap, _p(mu_t), _p(cost_t), _p(grad_t), _p(pred_t),
                                     acc_t.ctypes.data_as(_I), lv.ctypes.data_as(_I))
     if it < 0:
         raise OracleError(it, -1)
@@ -322,4 +322,5 @@ def nmpc_ip_solve(p, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, cap=4096)
         n_lv += 1
         mu *= zeta
     return {"u": u, "x": x, "iters": it, "level_iters": lv[:n_lv].copy(), "mu": mu_t[:it].copy(),
-            "cost": cost_t[:it].copy(), "grad": grad_t[:it].copy(), "accept": acc_t[:it].astype(bool)}
+            "cost": cost_t[:it].copy(), "grad": grad_t[:it].copy(), "pred": pred_t[:it].copy(),
+            "accept": acc_t[:it].astype(bool)}

@@ -1051,8 +1051,9 @@ int oracle_nmpc_solve(int nx, int nu, int T, double h, int model, const double *
  * one that starts from a nominal with |dJ_mu/du|_inf <= tol (that
  * iteration's step is still taken), or max_iter iterations.  The nominal,
  * alpha and nu_lm carry over from level to level.  Traces of capacity cap
- * (any NULL): barrier weight, cost after, gradient norm before and accept
- * flag of every iteration; level_iters gets the iteration count of each
+ * (any NULL): barrier weight, cost after, gradient norm before, predicted
+ * decrease and accept flag of every iteration; level_iters gets the
+ * iteration count of each
  * level.  Returns the total number of iterations, -1 if u starts infeasible
  * or the model is unknown, -2 if cap is too small.
  */
@@ -1061,7 +1062,7 @@ int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const doubl
                          const double *xref, const double *x0, double umin, double umax, double mu0,
                          double zeta, double mu_min, double tol, int max_iter, double alpha0, double nu0,
                          double *u, double *x, int cap, double *mu_trace, double *cost_trace,
-                         double *grad_trace, int *accept_trace, int *level_iters)
+                         double *grad_trace, double *pred_trace, int *accept_trace, int *level_iters)
 {
     if (model_ok(model, nx, nu, prm) != 0 || !(zeta > 0.0 && zeta < 1.0) || !(mu0 > 0.0)) return -1;
     nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
@@ -1071,13 +1072,14 @@ int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const doubl
     for (double mu = mu0; mu > mu_min; mu *= zeta, ++lv) {
         int li = 0;
         for (; li < max_iter; ++li) {
-            double cst, grad;
+            double cst, grad, pred;
             if (it >= cap) return -2;
             int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, mu,
-                                              &alpha, &nu_lm, x, u, &cst, NULL, NULL, &grad);
+                                              &alpha, &nu_lm, x, u, &cst, &pred, NULL, &grad);
             if (mu_trace) mu_trace[it] = mu;
             if (cost_trace) cost_trace[it] = cst;
             if (grad_trace) grad_trace[it] = grad;
+            if (pred_trace) pred_trace[it] = pred;
             if (accept_trace) accept_trace[it] = acc;
             ++it;
             if (grad <= tol) {

@@ -406,7 +406,7 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
 
 // Layout of the Newton workspace after the plan's LQ workspace.
 struct NmpcLayout {
-    size_t A, B, P, Rt, Rh, d, th, g, lam, lamT, S, s, G, gm, dx, du, xc, uc, zero, status, total;
+    size_t A, B, P, M, Rt, Rh, d, th, g, lam, lamT, S, s, G, gm, dx, du, xc, uc, zero, status, total;
 };
 
 static NmpcLayout nmpc_layout(const lq_plan *p)
@@ -420,7 +420,7 @@ static NmpcLayout nmpc_layout(const lq_plan *p)
         off = align_up(off + bytes);
         return o;
     };
-    L.A = take(T * n * n * D); L.B = take(T * n * m * D); L.P = take(T * n * n * D);
+    L.A = take(T * n * n * D); L.B = take(T * n * m * D); L.P = take(T * n * n * D); L.M = take(T * n * m * D);
     L.Rt = take(T * m * m * D); L.Rh = take(T * m * m * D); L.d = take(T * m * D);
     L.th = take(T * n * D); L.g = take(T * n * D); L.lam = take((T + 1) * n * D); L.lamT = take(n * D);
     L.S = take((T + 1) * n * n * D); L.s = take((T + 1) * n * D); L.G = take(T * m * n * D);
@@ -434,8 +434,15 @@ static bool nmpc_matches(const lq_plan *p, const nmpc_problem *q)
 {
     if (!p || !q || p->batch != 1) return false;
     const InstDesc &d = p->h_inst[0];
-    return d.n == q->nx && d.m == q->nu && d.T == q->T && q->W && q->Bm && q->Q && q->R && q->QT && q->xref &&
-           q->x0 && q->umin < q->umax;
+    bool model_ok = false;
+    switch (q->model) {
+    case NMPC_TANH: model_ok = q->W && q->Bm; break;
+    case NMPC_PENDULUM: model_ok = q->nx == 2 && q->nu == 1; break;
+    case NMPC_CARTPOLE: model_ok = q->nx == 4 && q->nu == 1; break;
+    default: break;
+    }
+    return model_ok && d.n == q->nx && d.m == q->nu && d.T == q->T && q->Q && q->R && q->QT && q->xref && q->x0 &&
+           q->umin < q->umax;
 }
 
 static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
@@ -444,6 +451,8 @@ static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
     N.nx = q->nx; N.nu = q->nu; N.T = q->T; N.h = q->h;
     N.W = q->W; N.Bm = q->Bm; N.Q = q->Q; N.R = q->R; N.QT = q->QT; N.xref = q->xref; N.x0 = q->x0;
     N.umin = q->umin; N.umax = q->umax;
+    N.model = q->model;
+    for (int i = 0; i < 4; ++i) N.prm[i] = q->param[i];
     return N;
 }
 
@@ -453,7 +462,7 @@ static lqk::NmpcWork nmpc_work(const lq_plan *p, void *workspace)
     char *w = (char *)workspace;
     auto D = [&](size_t o) { return (double *)(w + o); };
     lqk::NmpcWork Wk;
-    Wk.A = D(L.A); Wk.B = D(L.B); Wk.P = D(L.P); Wk.Rt = D(L.Rt); Wk.Rh = D(L.Rh); Wk.d = D(L.d);
+    Wk.A = D(L.A); Wk.B = D(L.B); Wk.P = D(L.P); Wk.M = D(L.M); Wk.Rt = D(L.Rt); Wk.Rh = D(L.Rh); Wk.d = D(L.d);
     Wk.th = D(L.th); Wk.g = D(L.g); Wk.lam = D(L.lam); Wk.lamT = D(L.lamT); Wk.S = D(L.S); Wk.s = D(L.s);
     Wk.G = D(L.G); Wk.gm = D(L.gm); Wk.dx = D(L.dx); Wk.du = D(L.du); Wk.xc = D(L.xc); Wk.uc = D(L.uc);
     Wk.zero = D(L.zero);
@@ -490,14 +499,15 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     lqk::launch_nmpc_clear(st, Wk.status, Wk.zero, prob->nx);
     // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
-    lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x);
+    lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x, state->u);
     lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
     double *in = affine_scan(p, st, 1, Ya, Yb);
     lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
-    lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->u, state->scal);
+    lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->x, state->u, state->scal);
     // the LQ step
     lq_problem lp{};
-    lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt; lp.M = nullptr;
+    lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt;
+    lp.M = (prob->model == NMPC_TANH) ? nullptr : Wk.M;   // the tanh model has no mixed second derivative
     lp.q = nullptr; lp.r = Wk.d; lp.QT = prob->QT; lp.qT = nullptr; lp.x0 = Wk.zero;
     lq_value val{Wk.S, Wk.s, Wk.G, Wk.gm};
     const lq_status r = lq_solve(p, &lp, nullptr, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);

@@ -46,18 +46,21 @@ struct GradPtrs {
 
 // Newton / interior-point: device scalars (indices match include/lqscan.h).
 enum { NMPC_MU = 0, NMPC_ALPHA = 1, NMPC_NU = 2, NMPC_COST = 3, NMPC_PRED = 4, NMPC_RHO = 5,
-       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_NSCAL = 8 };
+       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_NSCAL = 9 };
+enum { MODEL_TANH = 0, MODEL_PENDULUM = 1, MODEL_CARTPOLE = 2 };
 
 struct NmpcPtrs {
     int nx, nu, T;
     double h;
     const double *W, *Bm, *Q, *R, *QT, *xref, *x0;
     double umin, umax;
+    int model;
+    double prm[4];
 };
 
 // Newton workspace arrays (stage-major like the LQ problem arrays).
 struct NmpcWork {
-    double *A, *B, *P, *Rt, *Rh, *d, *th, *g, *lam, *lamT;
+    double *A, *B, *P, *M, *Rt, *Rh, *d, *th, *g, *lam, *lamT;
     double *S, *s, *G, *gm, *dx, *du, *xc, *uc, *zero;
     int32_t *status;
 };

@@ -34,11 +34,12 @@ void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtr
 
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u);
 void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n);
-void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x);
+void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u);
 void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y);
 void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
                           const double *Yfin);
-void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal);
+void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
+                              const double *scal);
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal);
 void launch_nmpc_accept(hipStream_t st, double *scal);
 void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal);

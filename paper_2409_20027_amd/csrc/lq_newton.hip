@@ -1,23 +1,28 @@
 // lq_newton.hip -- one iteration of the parallel-in-time Newton method (Alg. 4)
 // inside the primal log-barrier method (Sec. II-B), for the dynamics
-//   x_{k+1} = x_k + h (tanh(W x_k) + B u_k),
+//   x_{k+1} = x_k + h f(x_k, u_k),
+// f = tanh(W x) + B u (synthetic network) or the pendulum / cart-pole of
+// Sec. V (lq_models.hpp; their derivatives by forward-mode jets),
 // tracking costs l_k = 1/2 (x - ref_k)'Q(x - ref_k) + 1/2 u'R u,
 // l_T = 1/2 (x - ref_T)'Q_T(x - ref_T), and the box |u| bounds written as
 // 2 nu inequalities u - umax <= 0, umin - u <= 0 with the barrier
 //   c(u) = -mu sum_i [log(umax - u_i) + log(u_i - umin)].
 //
 // Steps (all enqueued on the caller's stream, decisions taken on the device):
-//   1. k_nmpc_linearise      A_k = I + h diag(1 - tanh^2 z) W, B_k = h B, z = W x_k,
-//                            g_k = Q (x_k - ref_k)
+//   1. k_nmpc_linearise      A_k = I + h df/dx, B_k = h df/du (tanh model:
+//                            df/dx = diag(1 - tanh^2 z) W, z = W x_k), g_k = Q (x_k - ref_k)
 //   2. co-state suffix scan  lambda_T = Q_T(x_T - ref_T),
 //                            lambda_k = g_k + A_k' lambda_{k+1}   (eq:co-state-eq;
 //                            homogeneous maps [[A_k', g_k], [0, 1]], Alg. 1)
-//   3. k_nmpc_quadraticise   P_k = Q + sum_i lambda_{k+1,i} h tanh''(z_i) w_i w_i',
-//                            R~_k = R + d2c/du2 + alpha I, d_k = R u + dc/du + B_k' lambda_{k+1}
+//   3. k_nmpc_quadraticise   P_k = Q + h lambda_{k+1}' d2f/dx2, M_k = h lambda_{k+1}' d2f/dxdu,
+//                            R~_k = R + d2c/du2 + h lambda_{k+1}' d2f/du2 + alpha I,
+//                            d_k = R u + dc/du + B_k' lambda_{k+1}
+//                            (tanh model: lambda' d2f/dx2 = sum_i lambda_i tanh''(z_i) w_i w_i',
+//                            no mixed or control second derivatives)
 //   4. the LQ step           eq:linearized-ocp with psi_t of eq:linearized-ocp-param
 //                            (delta x_0 = 0) by lq_scan_solve + lq_rollout
 //   5. k_nmpc_candidate      predicted decrease of the expansion (without alpha),
-//                            candidate u + du, its nonlinear rollout and J_mu
+//                            |d|_inf, candidate u + du, its nonlinear rollout and J_mu
 //   6. k_nmpc_accept         gain ratio rho = (J_mu(u) - J_mu(u + du)) / pred;
 //                            accept if pred > 0 and rho > 0: alpha *= max(1/3,
 //                            1 - (2 rho - 1)^3), nu = 2; else alpha *= nu, nu *= 2
@@ -25,6 +30,7 @@
 #include <algorithm>
 
 #include "lq_kernels.hpp"
+#include "lq_models.hpp"
 
 namespace lqk {
 
@@ -32,15 +38,79 @@ namespace lqk {
 constexpr int NXMAX = 15;
 constexpr int NUMAX = MMAX;
 
-// Nonlinear step x' = x + h (tanh(W x) + B u).
+// Nonlinear step x' = x + h f(x, u).
 LQK_DEV void f_step(const NmpcPtrs &N, int n, int m, const double *x, const double *u, double *xn)
 {
-    for (int i = 0; i < n; ++i) {
-        double z = 0.0, bu = 0.0;
-        for (int j = 0; j < n; ++j) z += N.W[i * n + j] * x[j];
-        for (int j = 0; j < m; ++j) bu += N.Bm[i * m + j] * u[j];
-        xn[i] = x[i] + N.h * (tanh(z) + bu);
+    if (N.model == MODEL_TANH) {
+        for (int i = 0; i < n; ++i) {
+            double z = 0.0, bu = 0.0;
+            for (int j = 0; j < n; ++j) z += N.W[i * n + j] * x[j];
+            for (int j = 0; j < m; ++j) bu += N.Bm[i * m + j] * u[j];
+            xn[i] = x[i] + N.h * (tanh(z) + bu);
+        }
+    } else if (N.model == MODEL_PENDULUM) {
+        const double z[3] = {x[0], x[1], u[0]};
+        double f[2];
+        pendulum_f<double, double>(N.prm, z, f);
+        for (int i = 0; i < 2; ++i) xn[i] = x[i] + N.h * f[i];
+    } else {
+        const double z[5] = {x[0], x[1], x[2], x[3], u[0]};
+        double f[4];
+        cartpole_f<double, double>(N.prm, z, f);
+        for (int i = 0; i < 4; ++i) xn[i] = x[i] + N.h * f[i];
     }
+}
+
+// Jets of f at z = (x_k, u_k) for the pendulum (NZ = 3) or cart-pole (NZ = 5).
+template <int NZ, typename RT>
+LQK_DEV void model_jets(const NmpcPtrs &N, const double *xk, const double *uk, Jet<NZ, RT> *f)
+{
+    constexpr int n = NZ - 1;
+    Jet<NZ, RT> z[NZ];
+#pragma unroll
+    for (int i = 0; i < n; ++i) z[i] = jvar<NZ, RT>((RT)xk[i], i);
+    z[n] = jvar<NZ, RT>((RT)uk[0], n);
+    RT prm[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) prm[i] = (RT)N.prm[i];
+    if constexpr (NZ == 3)
+        pendulum_f<Jet<NZ, RT>, RT>(prm, z, f);
+    else
+        cartpole_f<Jet<NZ, RT>, RT>(prm, z, f);
+}
+
+// A_k = I + h df/dx, B_k = h df/du from the jets (pendulum / cart-pole).
+template <int NZ>
+LQK_DEV void linearise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, const double *xk, const double *uk)
+{
+    constexpr int n = NZ - 1;
+    Jet<NZ, double> f[n];
+    model_jets<NZ, double>(N, xk, uk, f);
+    double *A = Wk.A + (int64_t)k * n * n, *B = Wk.B + (int64_t)k * n;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) A[i * n + j] = (i == j ? 1.0 : 0.0) + N.h * f[i].g[j];
+        B[i] = N.h * f[i].g[n];
+    }
+}
+
+// P_k = Q + h S_xx, M_k = h S_xu and h S_uu (added to R~ and Rh) of
+// S = lambda_{k+1}' f, in arithmetic type RT.
+template <int NZ, typename RT>
+LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, const double *xk, const double *uk,
+                              const double *l1)
+{
+    constexpr int n = NZ - 1;
+    Jet<NZ, RT> f[n];
+    model_jets<NZ, RT>(N, xk, uk, f);
+    Jet<NZ, RT> S = (RT)l1[0] * f[0];
+    for (int i = 1; i < n; ++i) S = S + (RT)l1[i] * f[i];
+    const RT h = (RT)N.h;
+    double *P = Wk.P + (int64_t)k * n * n, *M = Wk.M + (int64_t)k * n;
+    for (int a = 0; a < n; ++a) {
+        for (int b = 0; b < n; ++b) P[a * n + b] = (double)((RT)N.Q[a * n + b] + h * S.H[a][b]);
+        M[a] = (double)(h * S.H[a][n]);
+    }
+    return h * S.H[n][n];
 }
 
 // Stage cost plus barrier at stage k (returns +inf if u is infeasible).
@@ -91,7 +161,7 @@ __global__ void k_nmpc_clear(int32_t *st, double *zero, int n)
 
 // Step 1 (one lane per stage), arithmetic type RT, results stored in FP64.
 template <typename RT>
-__global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x)
+__global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = N.nx, m = N.nu;
@@ -106,20 +176,26 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
         }
         return;
     }
-    RT th[NXMAX];
-    const RT h = (RT)N.h;
-    for (int i = 0; i < n; ++i) {
-        RT z = 0;
-        for (int j = 0; j < n; ++j) z += (RT)N.W[i * n + j] * (RT)xk[j];
-        th[i] = tanh(z);
-        Wk.th[(int64_t)k * n + i] = (double)th[i];
+    if (N.model == MODEL_PENDULUM) {
+        linearise_model<3>(N, Wk, k, xk, u + (int64_t)k * m);
+    } else if (N.model == MODEL_CARTPOLE) {
+        linearise_model<5>(N, Wk, k, xk, u + (int64_t)k * m);
+    } else {
+        RT th[NXMAX];
+        const RT h = (RT)N.h;
+        for (int i = 0; i < n; ++i) {
+            RT z = 0;
+            for (int j = 0; j < n; ++j) z += (RT)N.W[i * n + j] * (RT)xk[j];
+            th[i] = tanh(z);
+            Wk.th[(int64_t)k * n + i] = (double)th[i];
+        }
+        double *A = Wk.A + (int64_t)k * n * n;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j)
+                A[i * n + j] = (double)((i == j ? (RT)1 : (RT)0) + h * ((RT)1 - th[i] * th[i]) * (RT)N.W[i * n + j]);
+        double *B = Wk.B + (int64_t)k * n * m;
+        for (int i = 0; i < n * m; ++i) B[i] = (double)(h * (RT)N.Bm[i]);
     }
-    double *A = Wk.A + (int64_t)k * n * n;
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j)
-            A[i * n + j] = (double)((i == j ? (RT)1 : (RT)0) + h * ((RT)1 - th[i] * th[i]) * (RT)N.W[i * n + j]);
-    double *B = Wk.B + (int64_t)k * n * m;
-    for (int i = 0; i < n * m; ++i) B[i] = (double)(h * (RT)N.Bm[i]);
     for (int i = 0; i < n; ++i) {
         RT v = 0;
         for (int j = 0; j < n; ++j) v += (RT)N.Q[i * n + j] * ((RT)xk[j] - (RT)rk[j]);
@@ -204,29 +280,36 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
 }
 
 // Step 3 (one lane per stage): second-order terms of the Hamiltonian.  In
-// mixed precision the lambda' d2f contraction of P is formed in RT = float;
-// the gradient d, the barrier terms and alpha stay FP64.
+// mixed precision the lambda' d2f contractions (P, M and their R part) are
+// formed in RT = float; the gradient d, the barrier terms and alpha stay FP64.
 template <typename RT>
-__global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *u,
+__global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                                                            const double *scal)
 {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     const int n = N.nx, m = N.nu;
     if (k >= N.T) return;
     const double mu = scal[NMPC_MU], alpha = scal[NMPC_ALPHA];
-    const double *th = Wk.th + (int64_t)k * n;
     const double *l1 = Wk.lam + (int64_t)(k + 1) * n;
-    double *P = Wk.P + (int64_t)k * n * n;
-    RT Pl[NXMAX * NXMAX];
-    for (int i = 0; i < n * n; ++i) Pl[i] = (RT)N.Q[i];
-    for (int i = 0; i < n; ++i) {
-        const RT t = (RT)th[i];
-        const RT w = (RT)l1[i] * (RT)N.h * ((RT)-2 * t * ((RT)1 - t * t));
-        for (int a = 0; a < n; ++a)
-            for (int b = 0; b < n; ++b) Pl[a * n + b] += w * (RT)N.W[i * n + a] * (RT)N.W[i * n + b];
-    }
-    for (int i = 0; i < n * n; ++i) P[i] = (double)Pl[i];
     const double *uk = u + (int64_t)k * m;
+    double huu = 0.0;   // h lambda' d2f/du2 (m = 1 for the pendulum and cart-pole)
+    if (N.model == MODEL_PENDULUM) {
+        huu = (double)quadraticise_model<3, RT>(N, Wk, k, x + (int64_t)k * n, uk, l1);
+    } else if (N.model == MODEL_CARTPOLE) {
+        huu = (double)quadraticise_model<5, RT>(N, Wk, k, x + (int64_t)k * n, uk, l1);
+    } else {
+        const double *th = Wk.th + (int64_t)k * n;
+        double *P = Wk.P + (int64_t)k * n * n;
+        RT Pl[NXMAX * NXMAX];
+        for (int i = 0; i < n * n; ++i) Pl[i] = (RT)N.Q[i];
+        for (int i = 0; i < n; ++i) {
+            const RT t = (RT)th[i];
+            const RT w = (RT)l1[i] * (RT)N.h * ((RT)-2 * t * ((RT)1 - t * t));
+            for (int a = 0; a < n; ++a)
+                for (int b = 0; b < n; ++b) Pl[a * n + b] += w * (RT)N.W[i * n + a] * (RT)N.W[i * n + b];
+        }
+        for (int i = 0; i < n * n; ++i) P[i] = (double)Pl[i];
+    }
     double *Rt = Wk.Rt + (int64_t)k * m * m;
     double *Rh = Wk.Rh + (int64_t)k * m * m;
     for (int i = 0; i < m * m; ++i) Rh[i] = N.R[i];
@@ -234,6 +317,7 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
         const double a = N.umax - uk[i], b = uk[i] - N.umin;
         Rh[i * m + i] += mu * (1.0 / (a * a) + 1.0 / (b * b));
     }
+    if (N.model != MODEL_TANH) Rh[0] += huu;
     for (int i = 0; i < m * m; ++i) Rt[i] = Rh[i];
     for (int i = 0; i < m; ++i) Rt[i * m + i] += alpha;
     // the gradient d_k stays FP64 (mixed precision only approximates the Hessian)
@@ -257,15 +341,23 @@ __global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, 
     const int n = N.nx, m = N.nu, T = N.T;
     const double mu = scal[NMPC_MU];
     const bool lq_ok = (Wk.status[0] == 0);
-    // predicted decrease (alpha excluded)
-    double pred = 0.0;
+    // predicted decrease (alpha excluded) and |d|_inf
+    double pred = 0.0, gmax = 0.0;
     for (int k = 0; k < T; ++k) {
         const double *dxk = Wk.dx + (int64_t)k * n, *duk = Wk.du + (int64_t)k * m;
-        for (int i = 0; i < m; ++i) pred += Wk.d[(int64_t)k * m + i] * duk[i];
+        for (int i = 0; i < m; ++i) {
+            pred += Wk.d[(int64_t)k * m + i] * duk[i];
+            gmax = fmax(gmax, fabs(Wk.d[(int64_t)k * m + i]));
+        }
         double qf = 0.0;
         const double *P = Wk.P + (int64_t)k * n * n, *Rh = Wk.Rh + (int64_t)k * m * m;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) qf += dxk[i] * P[i * n + j] * dxk[j];
+        if (N.model != MODEL_TANH) {
+            const double *Mk = Wk.M + (int64_t)k * n * m;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < m; ++j) qf += 2.0 * dxk[i] * Mk[i * m + j] * duk[j];
+        }
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) qf += duk[i] * Rh[i * m + j] * duk[j];
         pred += 0.5 * qf;
@@ -303,6 +395,7 @@ __global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, 
     J1 += terminal_cost(N, n, T, xc);
     if (!feas) J1 = INFINITY;
     scal[NMPC_PRED] = lq_ok ? pred : 0.0;
+    scal[NMPC_GRAD] = gmax;
     scal[NMPC_COST] = J0;
     scal[NMPC_COST_NEW] = lq_ok ? J1 : INFINITY;
 }
@@ -355,12 +448,12 @@ void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
 {
     hipLaunchKernelGGL(k_nmpc_clear, dim3(1), dim3(64), 0, st, status, zero, n);
 }
-void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x)
+void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u)
 {
     // The Jacobians define the co-states and hence the gradient, which sets
     // the point Newton converges to: FP64 in every precision mode.
     (void)pr;
-    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x);
+    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x, u);
 }
 void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
 {
@@ -375,12 +468,13 @@ void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWor
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
-void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *u, const double *scal)
+void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
+                              const double *scal)
 {
     if (pr)
-        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
+        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, x, u, scal);
     else
-        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, u, scal);
+        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, x, u, scal);
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {

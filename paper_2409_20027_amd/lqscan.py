@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -359,13 +360,16 @@ def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=Non
 # Newton / interior point (newton_step)
 # ---------------------------------------------------------------------------
 
-NMPC_MU, NMPC_ALPHA, NMPC_NU, NMPC_COST, NMPC_PRED, NMPC_RHO, NMPC_ACCEPTED, NMPC_COST_NEW, NMPC_NSCAL = range(9)
+(NMPC_MU, NMPC_ALPHA, NMPC_NU, NMPC_COST, NMPC_PRED, NMPC_RHO, NMPC_ACCEPTED, NMPC_COST_NEW, NMPC_GRAD,
+ NMPC_NSCAL) = range(10)
+NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE = 0, 1, 2
 
 
 class NMPCProblemC(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("T", ctypes.c_int32), ("h", ctypes.c_double),
                 ("W", _P), ("Bm", _P), ("Q", _P), ("R", _P), ("QT", _P), ("xref", _P), ("x0", _P),
-                ("umin", ctypes.c_double), ("umax", ctypes.c_double)]
+                ("umin", ctypes.c_double), ("umax", ctypes.c_double), ("model", ctypes.c_int32),
+                ("param", ctypes.c_double * 4)]
 
 
 class NMPCStateC(ctypes.Structure):
@@ -396,26 +400,33 @@ def newton_step(plan, prob_c, state_c, workspace, status=None, stream=None):
 
 
 class NewtonMPC:
-    """Interior-point Newton solver for x' = x + h (tanh(W x) + B u), |u| bounded.
+    """Interior-point Newton solver for x' = x + h f(x, u) with |u| bounded.
 
-    `p` has numpy fields nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, u0, umin, umax.
-    All iterations run on the GPU through newton_step; the host only sets the
-    barrier weight between levels and reads the traces at the end.
+    `p` has numpy fields nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, u0, umin,
+    umax and optionally model (NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE) and
+    param (the model constants); W and Bm are read by the tanh model only.
+    All iterations run on the GPU through newton_step; the host sets the
+    barrier weight and, in ip_solve, reads the gradient norm after each
+    iteration to end a barrier level.
     """
 
-    def __init__(self, p, device="cuda", seg_len=0, precision="fp64"):
+    def __init__(self, p, device="cuda", seg_len=0, precision="fp64", mode="scan"):
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
         self.p = p
-        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len, precision=precision)
-        self.dev = {k: t(getattr(p, k)) for k in ("W", "Bm", "Q", "R", "QT", "xref", "x0")}
+        model = int(getattr(p, "model", NMPC_TANH) or 0)
+        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len, precision=precision, mode=mode)
+        names = ("Q", "R", "QT", "xref", "x0") + (("W", "Bm") if model == NMPC_TANH else ())
+        self.dev = {k: t(getattr(p, k)) for k in names}
         self.x = torch.zeros((p.T + 1) * p.nx, dtype=torch.float64, device=device)
         self.u = t(p.u0).reshape(-1).clone()
         self.scal = torch.zeros(NMPC_NSCAL, dtype=torch.float64, device=device)
         self.ws = torch.empty(nmpc_workspace_bytes(self.plan), dtype=torch.uint8, device=device)
         d = self.dev
-        self.prob_c = NMPCProblemC(p.nx, p.nu, p.T, float(p.h), _f64(d["W"]), _f64(d["Bm"]), _f64(d["Q"]),
+        prm = getattr(p, "param", None)
+        prm = (ctypes.c_double * 4)(*([float(v) for v in prm] if prm is not None else [0.0] * 4))
+        self.prob_c = NMPCProblemC(p.nx, p.nu, p.T, float(p.h), _f64(d.get("W")), _f64(d.get("Bm")), _f64(d["Q"]),
                                    _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(d["x0"]),
-                                   float(p.umin), float(p.umax))
+                                   float(p.umin), float(p.umax), model, prm)
         self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
 
     def init(self, alpha0, nu0):
@@ -447,3 +458,39 @@ class NewtonMPC:
                 "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
                 "cost": a[:, NMPC_COST], "accept": a[:, NMPC_ACCEPTED] > 0.5,
                 "alpha": before.cpu().numpy()[:, NMPC_ALPHA], "pred": a[:, NMPC_PRED], "rho": a[:, NMPC_RHO]}
+
+    def ip_solve(self, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, trace=True):
+        """The interior-point method of Sec. II-B with converged inner Newton loops:
+        mu = mu0, mu0 zeta, ... while mu > mu_min; a level ends after the iteration
+        that starts from |dJ_mu/du|_inf <= tol, or after max_iter iterations.
+
+        The gradient norm of each iteration is read back (one small device-to-host
+        copy per iteration, into pinned memory).  Returns dict(u, x, iters,
+        level_iters, and with trace the per-iteration mu, cost, grad, accept, pred).
+        """
+        self.init(alpha0, nu0)
+        host = torch.empty(NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
+        rows, level_iters = [], []
+        mu = float(mu0)
+        while mu > mu_min:
+            li = 0
+            while li < max_iter:
+                self.scal[NMPC_MU] = mu
+                newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+                host.copy_(self.scal, non_blocking=True)
+                torch.cuda.current_stream().synchronize()
+                li += 1
+                if trace:
+                    rows.append((mu, float(host[NMPC_COST]), float(host[NMPC_GRAD]), float(host[NMPC_ACCEPTED]),
+                                 float(host[NMPC_PRED])))
+                if float(host[NMPC_GRAD]) <= tol:
+                    break
+            level_iters.append(li)
+            mu *= zeta
+        out = {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
+               "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
+               "iters": int(sum(level_iters)), "level_iters": np.array(level_iters)}
+        if trace:
+            r = np.array(rows).reshape(-1, 5)
+            out.update(mu=r[:, 0], cost=r[:, 1], grad=r[:, 2], accept=r[:, 3] > 0.5, pred=r[:, 4])
+        return out

@@ -1,0 +1,113 @@
+"""GPU parity of the Newton / interior-point step for the pendulum and cart-pole
+models of Sec. V (newton_step with model selector) against the FP64 oracle.
+
+Single steps: accept decision identical, predicted decrease, costs, alpha,
+gradient norm and the new trajectory within 1e-10 (normwise relative).
+
+Whole interior-point solves (mu from 0.1 times 0.2 while above 1e-4, inner
+loops to |dJ_mu/du|_inf <= 1e-6): an accept decision taken where the
+predicted decrease is below 1e-9 |J_mu| compares rounding errors and is not
+determined by the arithmetic; it can change the damping and from there on
+the two runs may follow different (equally valid) paths.  Up to the first such
+iteration the traces take the same decisions (a step whose LQ solve fails has
+pred = 0 on both sides and is rejected by both) and their costs agree to 2e-7:
+the oracle's own loop with u perturbed by 1e-15 (relative) after every step
+moves its cost trace by up to 3.8e-8 there (pendulum, N = 400: up to a
+hundred iterations of a nonconvex descent amplify round-off).  At the end
+both runs are stationary to the tolerance in the last barrier level (or at
+its iteration cap) and reach the same local minimum: final J_mu within 1e-7,
+controls and states within 1e-5 (the perturbed oracle runs end up to 4e-7
+apart).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_20027_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MODELS = {"pendulum": W.pendulum_problem, "cartpole": W.cartpole_problem}
+
+
+@pytest.fixture(scope="module")
+def lq():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2409_20027_amd import lqscan
+    return lqscan
+
+
+def rel(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+@pytest.mark.parametrize("seg_len,mode", [(0, "scan"), (5, "scan"), (1, "scan"), (0, "sequential")])
+def test_single_newton_step(lq, name, seg_len, mode):
+    p = MODELS[name](97)
+    u0 = p.u0 * 5.0   # away from zero so that every term is exercised
+    import dataclasses
+    p = dataclasses.replace(p, u0=u0, Q=np.eye(p.nx) * 0.2)
+    mu, alpha, nu = 0.1, 0.05, 2.0
+    x0 = oracle.nmpc_rollout(p, p.u0)
+    acc, x1, u1, a1, nu1, cost, pred, rho, grad = oracle.nmpc_newton_step(p, x0, p.u0, mu, alpha, nu,
+                                                                          with_grad=True)
+    s = lq.NewtonMPC(p, seg_len=seg_len, mode=mode)
+    s.init(alpha, nu)
+    s.step(mu)
+    torch.cuda.synchronize()
+    sc = s.scal.cpu().numpy()
+    assert bool(sc[lq.NMPC_ACCEPTED] > 0.5) == acc
+    assert abs(sc[lq.NMPC_PRED] - pred) <= 1e-10 * abs(pred)
+    assert abs(sc[lq.NMPC_COST] - cost) <= 1e-10 * abs(cost)
+    assert abs(sc[lq.NMPC_GRAD] - grad) <= 1e-10 * abs(grad)
+    assert abs(sc[lq.NMPC_ALPHA] - a1) <= 1e-10 * abs(a1) and sc[lq.NMPC_NU] == nu1
+    assert rel(s.u.cpu().numpy().reshape(p.T, p.nu), u1) < 1e-10
+    assert rel(s.x.cpu().numpy().reshape(p.T + 1, p.nx), x1) < 1e-10
+
+
+def ip(lq, p, **kw):
+    args = dict(mu0=W.IP_MU0, zeta=W.IP_ZETA, mu_min=W.IP_MU_MIN, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    ref = oracle.nmpc_ip_solve(p, **args)
+    got = lq.NewtonMPC(p, **kw).ip_solve(**args)
+    return got, ref
+
+
+@pytest.mark.parametrize("name,N", [("pendulum", 40), ("cartpole", 40), ("pendulum", 400), ("cartpole", 1000)])
+def test_interior_point_solve_matches_oracle(lq, name, N):
+    p = MODELS[name](N)
+    got, ref = ip(lq, p)
+    check_ip(p, got, ref)
+
+
+def check_ip(p, got, ref):
+    n = min(len(got["cost"]), len(ref["cost"]))
+    # pred = 0 exactly: the LQ step failed (R + B'S'B not positive definite) and
+    # both runs reject; a positive pred below 1e-9 |J| is a round-off decision
+    soft = (ref["pred"][:n] != 0.0) & (np.abs(ref["pred"][:n]) <= 1e-9 * np.abs(ref["cost"][:n]))
+    first = int(np.argmax(soft)) if soft.any() else n
+    assert first >= 5
+    assert np.array_equal(got["accept"][:first], ref["accept"][:first])
+    assert rel(got["cost"][:first], ref["cost"][:first]) < 2e-7
+    last_level = np.sum(got["level_iters"]) - got["level_iters"][-1]
+    assert got["grad"][-1] <= W.IP_TOL or got["level_iters"][-1] == W.IP_MAX_ITER
+    eJ = abs(got["cost"][-1] - ref["cost"][-1]) / max(1.0, abs(ref["cost"][-1]))
+    eu, ex = rel(got["u"], ref["u"]), rel(got["x"], ref["x"])
+    print(f"first round-off decision at {first} of {len(ref['cost'])}; levels {got['level_iters']} vs "
+          f"{ref['level_iters']}; final J rel {eJ:.1e}, u {eu:.1e}, x {ex:.1e}")
+    assert last_level >= 0
+    assert eJ < 1e-7
+    assert eu < 1e-5 and ex < 1e-5
+    assert np.all(got["u"] < p.umax) and np.all(got["u"] > p.umin)
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_interior_point_sequential_mode_matches_oracle(lq, name):
+    """The sequential-in-time path (one segment per instance) on the same solve."""
+    p = MODELS[name](100)
+    got, ref = ip(lq, p, mode="sequential")
+    check_ip(p, got, ref)
