@@ -254,6 +254,48 @@ def batched(lqscan, workloads, dev, steps: int, warmup: int) -> dict:
     return res
 
 
+def paper_ip_solves(lqscan, workloads, reps: int, with_cpu: bool) -> dict:
+    """The paper's own experiments (Sec. V): interior-point solves of the
+    torque-limited pendulum and force-limited cart-pole swing-ups at horizons
+    N = 20 .. 1000, wall time of the whole solve (host loop over Newton steps
+    with one gradient-norm readback per step), parallel-in-time path against
+    the sequential-in-time path on the same GPU (one segment per solve), and
+    the FP64 oracle on one host core.  Costs and time spans are proposed (the
+    paper does not print them)."""
+    import torch
+    args = dict(mu0=workloads.IP_MU0, zeta=workloads.IP_ZETA, mu_min=workloads.IP_MU_MIN, tol=workloads.IP_TOL,
+                max_iter=workloads.IP_MAX_ITER, alpha0=workloads.NMPC_ALPHA0, nu0=workloads.NMPC_NU0)
+    out = {"unit": "ms per interior-point solve", "seg_len_parallel": workloads.IP_SEG_LEN}
+    if with_cpu:
+        import oracle
+    for name, mk in (("pendulum", workloads.pendulum_problem), ("cartpole", workloads.cartpole_problem)):
+        rows = {}
+        for N in workloads.PAPER_HORIZONS:
+            p = mk(N)
+            row = {}
+            for label, kw, r in (("parallel_ms", dict(seg_len=workloads.IP_SEG_LEN), reps),
+                                 ("sequential_ms", dict(mode="sequential"), 1)):
+                s = lqscan.NewtonMPC(p, **kw)
+                o = s.ip_solve(**args, trace=False)   # warm-up (first launches, allocations)
+                torch.cuda.synchronize()
+                ts = []
+                for _ in range(r):
+                    t0 = time.perf_counter()
+                    o = s.ip_solve(**args, trace=False)
+                    torch.cuda.synchronize()
+                    ts.append((time.perf_counter() - t0) * 1e3)
+                row[label] = min(ts)
+                row["newton_iters" if label == "parallel_ms" else "newton_iters_sequential"] = o["iters"]
+            if with_cpu:
+                t0 = time.perf_counter()
+                ro = oracle.nmpc_ip_solve(p, **args)
+                row["oracle_ms"] = (time.perf_counter() - t0) * 1e3
+                row["oracle_newton_iters"] = ro["iters"]
+            rows[str(N)] = row
+        out[name] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +307,7 @@ def main():
     ap.add_argument("--no-seq", action="store_true")
     ap.add_argument("--replays", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
+    ap.add_argument("--no-paper", action="store_true", help="skip the pendulum / cart-pole interior-point solves")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -438,6 +481,8 @@ def main():
            "roofline": roof}
     if not args.no_batch:
         out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), 1)
+    if not args.no_paper:
+        out["paper_ip_solves"] = paper_ip_solves(lqscan, workloads, 3, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out))

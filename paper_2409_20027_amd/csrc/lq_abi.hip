@@ -514,7 +514,6 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     if (r != LQ_OK) return r;
     // candidate, decision, commit
     lqk::launch_nmpc_candidate(st, N, Wk, state->x, state->u, state->scal);
-    lqk::launch_nmpc_accept(st, state->scal);
     lqk::launch_nmpc_commit(st, N, Wk, state->x, state->u, state->scal);
     return launched();
 }

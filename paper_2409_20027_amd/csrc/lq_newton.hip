@@ -21,11 +21,14 @@
 //                            no mixed or control second derivatives)
 //   4. the LQ step           eq:linearized-ocp with psi_t of eq:linearized-ocp-param
 //                            (delta x_0 = 0) by lq_scan_solve + lq_rollout
-//   5. k_nmpc_candidate      predicted decrease of the expansion (without alpha),
-//                            |d|_inf, candidate u + du, its nonlinear rollout and J_mu
-//   6. k_nmpc_accept         gain ratio rho = (J_mu(u) - J_mu(u + du)) / pred;
-//                            accept if pred > 0 and rho > 0: alpha *= max(1/3,
-//                            1 - (2 rho - 1)^3), nu = 2; else alpha *= nu, nu *= 2
+//   5. k_nmpc_rollout        candidate u + du and its nonlinear rollout (one lane,
+//                            sequential in k)
+//   6. k_nmpc_reduce         predicted decrease of the expansion (without alpha),
+//                            |d|_inf, J_mu of the nominal and of the candidate
+//                            (block reductions), gain ratio rho = (J_mu(u) -
+//                            J_mu(u + du)) / pred; accept if pred > 0 and rho > 0:
+//                            alpha *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; else
+//                            alpha *= nu, nu *= 2
 //   7. k_nmpc_commit         on acceptance the candidate replaces the nominal.
 #include <algorithm>
 
@@ -138,17 +141,94 @@ LQK_DEV double terminal_cost(const NmpcPtrs &N, int n, int T, const double *xT)
     return J;
 }
 
-// Initial nonlinear rollout of the nominal controls (one lane).
-__global__ __launch_bounds__(64) void k_nmpc_init(NmpcPtrs N, double *x, const double *u)
+// Nonlinear rollout x_{k+1} = x_k + h f(x_k, u_k + du_k) from x0 (du may be
+// null), one lane: the recursion is sequential in k.  Writes x (T+1 rows)
+// and, if uout is set, the controls used.
+//
+// Pendulum and cart-pole (nu = 1): the raw u_{k+1} and du_{k+1} are loaded
+// (index clamped, no branch) while step k is computed and summed one step
+// later, so the loads' latency hides behind a step of the recursion.
+template <int MODEL, bool DU>
+__global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *__restrict__ u,
+                                                     const double *__restrict__ du, double *__restrict__ xout,
+                                                     double *__restrict__ uout)
 {
+    constexpr int n = (MODEL == MODEL_PENDULUM) ? 2 : 4;
     if (threadIdx.x != 0) return;
-    const int n = N.nx, m = N.nu;
-    double xc[NXMAX];
-    for (int i = 0; i < n; ++i) xc[i] = x[i] = N.x0[i];
-    for (int k = 0; k < N.T; ++k) {
+    const int T = N.T;
+    double x[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        x[i] = N.x0[i];
+        xout[i] = x[i];
+    }
+    if (T <= 0) return;
+    double ua = u[0], da = DU ? du[0] : 0.0;
+    for (int k = 0; k < T; ++k) {
+        const double uk = DU ? ua + da : ua;
+        const int kn = min(k + 1, T - 1);
+        ua = u[kn];
+        if constexpr (DU) da = du[kn];
+        if (uout) uout[k] = uk;
+        double f[n];
+        if constexpr (MODEL == MODEL_PENDULUM) {
+            const double z[3] = {x[0], x[1], uk};
+            pendulum_f<double, double>(N.prm, z, f);
+        } else {
+            const double z[5] = {x[0], x[1], x[2], x[3], uk};
+            cartpole_f<double, double>(N.prm, z, f);
+        }
+#pragma unroll
+        for (int i = 0; i < n; ++i) {
+            x[i] = x[i] + N.h * f[i];
+            xout[(int64_t)(k + 1) * n + i] = x[i];
+        }
+    }
+}
+
+// The tanh model (any nx <= 15, nu <= 4): W and B in LDS, loops unrolled to
+// the maximum sizes with guards so that the state stays in registers.
+__global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
+                                                          const double *__restrict__ du, double *__restrict__ xout,
+                                                          double *__restrict__ uout)
+{
+    __shared__ double sW[NXMAX * NXMAX], sB[NXMAX * NUMAX];
+    const int n = N.nx, m = N.nu, T = N.T;
+    for (int i = threadIdx.x; i < n * n; i += 64) sW[i] = N.W[i];
+    for (int i = threadIdx.x; i < n * m; i += 64) sB[i] = N.Bm[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double x[NXMAX];
+#pragma unroll
+    for (int i = 0; i < NXMAX; ++i) {
+        x[i] = (i < n) ? N.x0[i] : 0.0;
+        if (i < n) xout[i] = x[i];
+    }
+    for (int k = 0; k < T; ++k) {
+        double uk[NUMAX];
+#pragma unroll
+        for (int i = 0; i < NUMAX; ++i) {
+            const int64_t o = (int64_t)k * m + (i < m ? i : 0);
+            uk[i] = (i < m) ? u[o] + (du ? du[o] : 0.0) : 0.0;
+            if (uout && i < m) uout[o] = uk[i];
+        }
         double xn[NXMAX];
-        f_step(N, n, m, xc, u + (int64_t)k * m, xn);
-        for (int i = 0; i < n; ++i) x[(int64_t)(k + 1) * n + i] = xc[i] = xn[i];
+#pragma unroll
+        for (int i = 0; i < NXMAX; ++i) {
+            double z = 0.0, bu = 0.0;
+#pragma unroll
+            for (int j = 0; j < NXMAX; ++j)
+                if (i < n && j < n) z += sW[i * n + j] * x[j];
+#pragma unroll
+            for (int j = 0; j < NUMAX; ++j)
+                if (i < n && j < m) bu += sB[i * m + j] * uk[j];
+            xn[i] = (i < n) ? x[i] + N.h * (tanh(z) + bu) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NXMAX; ++i) {
+            x[i] = xn[i];
+            if (i < n) xout[(int64_t)(k + 1) * n + i] = xn[i];
+        }
     }
 }
 
@@ -332,24 +412,28 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     }
 }
 
-// Step 5 (one lane): predicted decrease, candidate controls, their nonlinear
-// rollout, J_mu of the nominal and of the candidate.
-__global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
-                                                       double *scal)
+// Step 5b (one block): data-parallel sums over the stages with a fixed
+// reduction tree -- the predicted decrease of the expansion (alpha excluded),
+// |d|_inf, J_mu of the nominal and of the candidate -- then the decision
+// (step 6): gain ratio rho = (J_mu(u) - J_mu(u + du)) / pred, accept if
+// pred > 0 and rho > 0: alpha *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; else
+// alpha *= nu, nu *= 2.  An LQ step that failed counts as pred = 0.
+constexpr int RED = 256;
+__global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
+                                                     double *scal)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ double sp[RED], s0[RED], s1[RED], sg[RED];
+    const int t = threadIdx.x;
     const int n = N.nx, m = N.nu, T = N.T;
     const double mu = scal[NMPC_MU];
-    const bool lq_ok = (Wk.status[0] == 0);
-    // predicted decrease (alpha excluded) and |d|_inf
-    double pred = 0.0, gmax = 0.0;
-    for (int k = 0; k < T; ++k) {
+    double pred = 0.0, J0 = 0.0, J1 = 0.0, gmax = 0.0;
+    for (int k = t; k < T; k += RED) {
         const double *dxk = Wk.dx + (int64_t)k * n, *duk = Wk.du + (int64_t)k * m;
+        double lin = 0.0, qf = 0.0;
         for (int i = 0; i < m; ++i) {
-            pred += Wk.d[(int64_t)k * m + i] * duk[i];
+            lin += Wk.d[(int64_t)k * m + i] * duk[i];
             gmax = fmax(gmax, fabs(Wk.d[(int64_t)k * m + i]));
         }
-        double qf = 0.0;
         const double *P = Wk.P + (int64_t)k * n * n, *Rh = Wk.Rh + (int64_t)k * m * m;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) qf += dxk[i] * P[i * n + j] * dxk[j];
@@ -360,8 +444,25 @@ __global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, 
         }
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) qf += duk[i] * Rh[i * m + j] * duk[j];
-        pred += 0.5 * qf;
+        pred += lin + 0.5 * qf;
+        J0 += stage_cost(N, n, m, k, x + (int64_t)k * n, u + (int64_t)k * m, mu);
+        J1 += stage_cost(N, n, m, k, Wk.xc + (int64_t)k * n, Wk.uc + (int64_t)k * m, mu);
     }
+    sp[t] = pred;
+    s0[t] = J0;
+    s1[t] = J1;
+    sg[t] = gmax;
+    for (int h = RED / 2; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) {
+            sp[t] += sp[t + h];
+            s0[t] += s0[t + h];
+            s1[t] += s1[t + h];
+            sg[t] = fmax(sg[t], sg[t + h]);
+        }
+    }
+    if (t != 0) return;
+    pred = sp[0];
     {
         const double *dxT = Wk.dx + (int64_t)T * n;
         double qf = 0.0;
@@ -370,41 +471,13 @@ __global__ __launch_bounds__(64) void k_nmpc_candidate(NmpcPtrs N, NmpcWork Wk, 
         pred += 0.5 * qf;
     }
     pred = -pred;
-    // J_mu of the nominal
-    double J0 = 0.0;
-    for (int k = 0; k < T; ++k) J0 += stage_cost(N, n, m, k, x + (int64_t)k * n, u + (int64_t)k * m, mu);
-    J0 += terminal_cost(N, n, T, x + (int64_t)T * n);
-    // candidate
-    double xc[NXMAX];
-    for (int i = 0; i < n; ++i) xc[i] = Wk.xc[i] = N.x0[i];
-    double J1 = 0.0;
-    bool feas = true;
-    for (int k = 0; k < T; ++k) {
-        double uk[NUMAX];
-        for (int i = 0; i < m; ++i) {
-            uk[i] = u[(int64_t)k * m + i] + Wk.du[(int64_t)k * m + i];
-            Wk.uc[(int64_t)k * m + i] = uk[i];
-            feas = feas && (uk[i] < N.umax) && (uk[i] > N.umin);
-        }
-        const double c = stage_cost(N, n, m, k, xc, uk, mu);
-        J1 += c;
-        double xn[NXMAX];
-        f_step(N, n, m, xc, uk, xn);
-        for (int i = 0; i < n; ++i) Wk.xc[(int64_t)(k + 1) * n + i] = xc[i] = xn[i];
+    J0 = s0[0] + terminal_cost(N, n, T, x + (int64_t)T * n);
+    J1 = s1[0] + terminal_cost(N, n, T, Wk.xc + (int64_t)T * n);
+    const bool lq_ok = (Wk.status[0] == 0);
+    if (!lq_ok) {
+        pred = 0.0;
+        J1 = INFINITY;
     }
-    J1 += terminal_cost(N, n, T, xc);
-    if (!feas) J1 = INFINITY;
-    scal[NMPC_PRED] = lq_ok ? pred : 0.0;
-    scal[NMPC_GRAD] = gmax;
-    scal[NMPC_COST] = J0;
-    scal[NMPC_COST_NEW] = lq_ok ? J1 : INFINITY;
-}
-
-// Step 6 (one lane): accept / reject and the damping update.
-__global__ void k_nmpc_accept(double *scal)
-{
-    if (threadIdx.x != 0) return;
-    const double pred = scal[NMPC_PRED], J0 = scal[NMPC_COST], J1 = scal[NMPC_COST_NEW];
     double alpha = scal[NMPC_ALPHA], nu = scal[NMPC_NU];
     double rho = -INFINITY;
     bool acc = false;
@@ -413,15 +486,18 @@ __global__ void k_nmpc_accept(double *scal)
         acc = rho > 0.0;
     }
     if (acc) {
-        const double t = 2.0 * rho - 1.0;
-        const double f = 1.0 - t * t * t;
+        const double tt = 2.0 * rho - 1.0;
+        const double f = 1.0 - tt * tt * tt;
         alpha *= (f > 1.0 / 3.0 ? f : 1.0 / 3.0);
         nu = 2.0;
-        scal[NMPC_COST] = J1;
     } else {
         alpha *= nu;
         nu *= 2.0;
     }
+    scal[NMPC_PRED] = pred;
+    scal[NMPC_GRAD] = sg[0];
+    scal[NMPC_COST] = acc ? J1 : J0;
+    scal[NMPC_COST_NEW] = J1;
     scal[NMPC_ALPHA] = alpha;
     scal[NMPC_NU] = nu;
     scal[NMPC_RHO] = rho;
@@ -440,9 +516,22 @@ __global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork 
 }
 
 
+static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, const double *du, double *xout,
+                           double *uout)
+{
+#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(1), dim3(64), 0, st, N, u, du, xout, uout)
+    if (N.model == MODEL_PENDULUM) {
+        if (du) RL(MODEL_PENDULUM, true); else RL(MODEL_PENDULUM, false);
+    } else if (N.model == MODEL_CARTPOLE) {
+        if (du) RL(MODEL_CARTPOLE, true); else RL(MODEL_CARTPOLE, false);
+    } else {
+        hipLaunchKernelGGL(k_nmpc_rollout_tanh, dim3(1), dim3(64), 0, st, N, u, du, xout, uout);
+    }
+#undef RL
+}
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
 {
-    hipLaunchKernelGGL(k_nmpc_init, dim3(1), dim3(64), 0, st, N, x, u);
+    launch_rollout(st, N, u, nullptr, x, nullptr);
 }
 void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
 {
@@ -478,11 +567,8 @@ void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, c
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
-    hipLaunchKernelGGL(k_nmpc_candidate, dim3(1), dim3(64), 0, st, N, Wk, x, u, scal);
-}
-void launch_nmpc_accept(hipStream_t st, double *scal)
-{
-    hipLaunchKernelGGL(k_nmpc_accept, dim3(1), dim3(64), 0, st, scal);
+    launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc);
+    hipLaunchKernelGGL(k_nmpc_reduce, dim3(1), dim3(RED), 0, st, N, Wk, x, u, scal);
 }
 void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal)
 {

@@ -418,7 +418,8 @@ class NewtonMPC:
         names = ("Q", "R", "QT", "xref", "x0") + (("W", "Bm") if model == NMPC_TANH else ())
         self.dev = {k: t(getattr(p, k)) for k in names}
         self.x = torch.zeros((p.T + 1) * p.nx, dtype=torch.float64, device=device)
-        self.u = t(p.u0).reshape(-1).clone()
+        self.u0 = t(p.u0).reshape(-1).clone()
+        self.u = self.u0.clone()
         self.scal = torch.zeros(NMPC_NSCAL, dtype=torch.float64, device=device)
         self.ws = torch.empty(nmpc_workspace_bytes(self.plan), dtype=torch.uint8, device=device)
         d = self.dev
@@ -430,6 +431,8 @@ class NewtonMPC:
         self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
 
     def init(self, alpha0, nu0):
+        """Nominal controls back to u0 (and x to their rollout), damping to (alpha0, nu0)."""
+        self.u.copy_(self.u0)
         self.scal.zero_()
         self.scal[NMPC_ALPHA] = alpha0
         self.scal[NMPC_NU] = nu0

@@ -272,6 +272,10 @@ IP_MU0, IP_ZETA, IP_MU_MIN = 0.1, 0.2, 1e-4
 # with |dJ_mu/du|_inf <= IP_TOL (the threshold itself is not printed), at
 # most IP_MAX_ITER iterations per barrier level.
 IP_TOL, IP_MAX_ITER = 1e-6, 100
+# Segment length of the parallel path for these small systems (n <= 4):
+# shorter segments than the default (fewer stages in the per-segment kernels,
+# which dominate at n <= 4) measured fastest for N >= 100.
+IP_SEG_LEN = 4
 # Horizon lengths of the runtime figures of Sec. V.
 PAPER_HORIZONS = (20, 40, 80, 100, 200, 400, 800, 1000)
 
