@@ -59,15 +59,15 @@ def lib():
             L.oracle_stateprop_combine.restype = None
             L.oracle_lq_adjoint.argtypes = [i, i, i] + [_P] * 11 + [_P] * 2 + [_P] * 11 + [_I]
             L.oracle_lq_adjoint.restype = i
-            L.oracle_nmpc_cost.argtypes = [i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, _P]
+            L.oracle_nmpc_cost.argtypes = [i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, _P, _P, d, _P]
             L.oracle_nmpc_cost.restype = d
             L.oracle_nmpc_rollout.argtypes = [i, i, i, d, i, _P, _P, _P, _P, _P, _P]
             L.oracle_nmpc_rollout.restype = i
             L.oracle_nmpc_f.argtypes = [i, _P, i, i, _P, _P, _P]
             L.oracle_nmpc_f.restype = i
-            L.oracle_nmpc_expand.argtypes = [i, i, i, d, i, _P] + [_P] * 6 + [d, d, d, _P, _P] + [_P] * 7
+            L.oracle_nmpc_expand.argtypes = [i, i, i, d, i, _P] + [_P] * 6 + [d, d, d, _P, _P, d, _P, _P] + [_P] * 7
             L.oracle_nmpc_expand.restype = None
-            L.oracle_nmpc_newton_step.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d]
+            L.oracle_nmpc_newton_step.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, _P, _P, d]
                                                   + [_P, _P, _P, _P, _P, _P, _P, _P])
             L.oracle_nmpc_newton_step.restype = i
             L.oracle_nmpc_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, _P, i, i, d, d]
@@ -76,6 +76,11 @@ def lib():
             L.oracle_nmpc_ip_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, d, d, d, i, d, d]
                                                + [_P, _P, i, _P, _P, _P, _P, _I, _I])
             L.oracle_nmpc_ip_solve.restype = i
+            L.oracle_nmpc_admm_solve.argtypes = ([i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, d, d, i, i, d, d]
+                                                 + [_P, _P, _P, _P, i, _I, _P, _P, _I])
+            L.oracle_nmpc_admm_solve.restype = i
+            L.oracle_nmpc_admm_update.argtypes = [i, i, d, d, d, _P, _P, _P, i, _P, _P]
+            L.oracle_nmpc_admm_update.restype = None
             _lib = L
     return _lib
 
@@ -219,25 +224,36 @@ def nmpc_f(p, x, u):
     return f
 
 
-def nmpc_cost(p, u, mu):
+def _admm(admm):
+    """(rho, z, v) of an ADMM augmentation dict, or the barrier's (0, None, None)."""
+    if admm is None:
+        return 0.0, None, None
+    return float(admm["rho"]), _f(admm["z"]), _f(admm["v"])
+
+
+def nmpc_cost(p, u, mu, admm=None):
+    """J_mu(u) (barrier), or J_AD(u) with admm = dict(rho, z, v) ([T, 2 nu] arrays)."""
     model, prm = _model(p)
     u = _f(u)
     W, Bm = _wb(p)
+    rho, z, v = _admm(admm)
     Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
     return lib().oracle_nmpc_cost(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
-                                  _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), float(mu), _p(u))
+                                  _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), rho, _p(z), _p(v),
+                                  float(mu), _p(u))
 
 
-def nmpc_expand(p, x, u, mu):
+def nmpc_expand(p, x, u, mu, admm=None):
     model, prm = _model(p)
     x, u = _f(x), _f(u)
     W, Bm = _wb(p)
+    rho, z, v = _admm(admm)
     Q, R, QT, xref = map(_f, (p.Q, p.R, p.QT, p.xref))
     T, n, m = p.T, p.nx, p.nu
     o = {"A": np.zeros((T, n, n)), "B": np.zeros((T, n, m)), "lam": np.zeros((T + 1, n)),
          "P": np.zeros((T, n, n)), "Rh": np.zeros((T, m, m)), "d": np.zeros((T, m)), "M": np.zeros((T, n, m))}
     lib().oracle_nmpc_expand(n, m, T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R), _p(QT), _p(xref),
-                             float(p.umin), float(p.umax), float(mu), _p(x), _p(u),
+                             float(p.umin), float(p.umax), rho, _p(z), _p(v), float(mu), _p(x), _p(u),
                              _p(o["A"]), _p(o["B"]), _p(o["lam"]), _p(o["P"]), _p(o["Rh"]), _p(o["d"]),
                              _p(o["M"]))
     return o
@@ -255,18 +271,19 @@ def nmpc_rollout(p, u):
     return x
 
 
-def nmpc_newton_step(p, x, u, mu, alpha, nu_lm, *, with_grad=False):
+def nmpc_newton_step(p, x, u, mu, alpha, nu_lm, *, with_grad=False, admm=None):
     """One Alg. 4 iteration; returns (accepted, x, u, alpha, nu_lm, cost, pred, rho)
     (plus |dJ_mu/du|_inf at the starting nominal when with_grad)."""
     model, prm = _model(p)
     x, u = _f(x).copy(), _f(u).copy()
     W, Bm = _wb(p)
+    rho_a, z, v = _admm(admm)
     Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
     a, nl = ctypes.c_double(alpha), ctypes.c_double(nu_lm)
     cost, pred, rho, grad = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     acc = lib().oracle_nmpc_newton_step(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q),
-                                        _p(R), _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax),
-                                        float(mu), ctypes.byref(a), ctypes.byref(nl), _p(x), _p(u),
+                                        _p(R), _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), rho_a,
+                                        _p(z), _p(v), float(mu), ctypes.byref(a), ctypes.byref(nl), _p(x), _p(u),
                                         ctypes.byref(cost), ctypes.byref(pred), ctypes.byref(rho),
                                         ctypes.byref(grad))
     if acc < 0:
@@ -324,3 +341,41 @@ def nmpc_ip_solve(p, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, cap=4096)
     return {"u": u, "x": x, "iters": it, "level_iters": lv[:n_lv].copy(), "mu": mu_t[:it].copy(),
             "cost": cost_t[:it].copy(), "grad": grad_t[:it].copy(), "pred": pred_t[:it].copy(),
             "accept": acc_t[:it].astype(bool)}
+
+
+def nmpc_admm_solve(p, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0):
+    """ADMM of Sec. II-C for the control box with Alg. 4 as inner solver.
+
+    Returns dict(u, x, z, v, admm_iters, newton_iters, inner [per ADMM iteration],
+    rp, rd [residual norms per ADMM iteration]).
+    """
+    model, prm = _model(p)
+    W, Bm = _wb(p)
+    Q, R, QT, xref, x0 = map(_f, (p.Q, p.R, p.QT, p.xref, p.x0))
+    u = _f(p.u0).copy()
+    x = np.zeros((p.T + 1, p.nx))
+    z = np.zeros((p.T, 2 * p.nu))
+    v = np.zeros((p.T, 2 * p.nu))
+    cap = int(max_admm)
+    inner = np.zeros(cap, np.int32)
+    rp, rd = np.zeros(cap), np.zeros(cap)
+    tot = ctypes.c_int(0)
+    it = lib().oracle_nmpc_admm_solve(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
+                                      _p(QT), _p(xref), _p(x0), float(p.umin), float(p.umax), float(rho),
+                                      float(eps), float(tol), int(max_iter), int(max_admm), float(alpha0),
+                                      float(nu0), _p(u), _p(x), _p(z), _p(v), cap, inner.ctypes.data_as(_I),
+                                      _p(rp), _p(rd), ctypes.byref(tot))
+    if it < 0:
+        raise OracleError(it, -1)
+    return {"u": u, "x": x, "z": z, "v": v, "admm_iters": it, "newton_iters": tot.value,
+            "inner": inner[:it].copy(), "rp": rp[:it].copy(), "rd": rd[:it].copy()}
+
+
+def nmpc_admm_update(p, u, z, v, rho, init):
+    """One consensus / multiplier step (eq:admm-step-4, -5); returns (z, v, rp, rd) (new arrays)."""
+    u = _f(np.asarray(u).reshape(p.T, p.nu))
+    z, v = _f(z).copy(), _f(v).copy()
+    rp, rd = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    lib().oracle_nmpc_admm_update(p.T, p.nu, float(p.umin), float(p.umax), float(rho), _p(u), _p(z), _p(v),
+                                  int(bool(init)), ctypes.byref(rp), ctypes.byref(rd))
+    return z, v, rp.value, rd.value

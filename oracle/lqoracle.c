@@ -575,6 +575,10 @@ typedef struct {
     const double *prm;
     const double *W, *Bm, *Q, *R, *QT, *xref, *x0;
     double umin, umax;
+    /* rho > 0: the ADMM augmentation rho/2 |h(u) - z + v/rho|^2 of Sec. II-C
+     * (z, v: [T][2 nu], rows u - umax then umin - u) replaces the barrier */
+    double rho;
+    const double *z, *v;
 } nmpc_prob;
 
 /* Value and derivatives over (theta, omega, F) of a cart-pole quantity. */
@@ -738,23 +742,36 @@ static int model_ok(int model, int n, int m, const double *prm)
 int oracle_nmpc_f(int model, const double *prm, int nx, int nu, const double *x, const double *u, double *f)
 {
     if (model == NMPC_TANH || model_ok(model, nx, nu, prm) != 0) return -1;
-    nmpc_prob P = {nx, nu, 0, 0.0, model, prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0.0, 0.0};
+    nmpc_prob P = {nx, nu, 0, 0.0, model, prm, NULL, NULL, NULL, NULL, NULL, NULL, NULL, 0.0, 0.0, 0.0, NULL, NULL};
     model_f(&P, x, u, f);
     return 0;
 }
 
-/* Nonlinear rollout from x0 under u; returns 0, or -1 if u is infeasible. */
+/* Nonlinear rollout from x0 under u; returns 0, or -1 if u is infeasible for
+ * the barrier (ADMM iterates may leave the box). */
 static int rollout(const nmpc_prob *P, const double *u, double *x)
 {
     const int n = P->nx, m = P->nu;
     memcpy(x, P->x0, sizeof(double) * n);
     for (int k = 0; k < P->T; ++k) f_step(P, x + (size_t)k * n, u + (size_t)k * m, x + (size_t)(k + 1) * n);
+    if (P->rho > 0.0) return 0;
     for (long i = 0; i < (long)P->T * m; ++i)
         if (!(u[i] < P->umax && u[i] > P->umin)) return -1;
     return 0;
 }
 
-/* J_mu(u): cost of the nonlinear rollout plus the barrier; +inf if infeasible. */
+/* ADMM residual of stage k, input i: (a, b) = h(u) - z + v / rho for the rows
+ * u_i - umax <= 0 and umin - u_i <= 0. */
+static void admm_ab(const nmpc_prob *P, int k, int i, double ui, double *a, double *b)
+{
+    const int m = P->nu;
+    const double *zk = P->z + (size_t)k * 2 * m, *vk = P->v + (size_t)k * 2 * m;
+    *a = (ui - P->umax) - zk[i] + vk[i] / P->rho;
+    *b = (P->umin - ui) - zk[m + i] + vk[m + i] / P->rho;
+}
+
+/* J_mu(u): cost of the nonlinear rollout plus the barrier, +inf if infeasible;
+ * with rho > 0 the ADMM augmentation instead of the barrier (J_AD of Sec. II-C). */
 static double cost_mu(const nmpc_prob *P, const double *u, const double *x, double mu)
 {
     const int n = P->nx, m = P->nu;
@@ -765,6 +782,12 @@ static double cost_mu(const nmpc_prob *P, const double *u, const double *x, doub
             for (int j = 0; j < n; ++j) J += 0.5 * (xk[i] - rk[i]) * P->Q[i * n + j] * (xk[j] - rk[j]);
         for (int i = 0; i < m; ++i) {
             for (int j = 0; j < m; ++j) J += 0.5 * uk[i] * P->R[i * m + j] * uk[j];
+            if (P->rho > 0.0) {
+                double a, b;
+                admm_ab(P, k, i, uk[i], &a, &b);
+                J += 0.5 * P->rho * (a * a + b * b);
+                continue;
+            }
             double a = P->umax - uk[i], b = uk[i] - P->umin;
             if (!(a > 0 && b > 0)) return INFINITY;
             J += -mu * (log(a) + log(b));
@@ -778,10 +801,11 @@ static double cost_mu(const nmpc_prob *P, const double *u, const double *x, doub
 
 double oracle_nmpc_cost(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
                         const double *Bm, const double *Q, const double *R, const double *QT, const double *xref,
-                        const double *x0, double umin, double umax, double mu, const double *u)
+                        const double *x0, double umin, double umax, double rho, const double *z, const double *v,
+                        double mu, const double *u)
 {
     if (model_ok(model, nx, nu, prm) != 0) return NAN;
-    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, rho, z, v};
     double *x = malloc(sizeof(double) * (size_t)(T + 1) * nx);
     double J = rollout(&P, u, x) == 0 ? cost_mu(&P, u, x, mu) : INFINITY;
     free(x);
@@ -793,7 +817,7 @@ int oracle_nmpc_rollout(int nx, int nu, int T, double h, int model, const double
                         const double *Bm, const double *x0, const double *u, double *x)
 {
     if (model_ok(model, nx, nu, prm) != 0) return -1;
-    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, NULL, NULL, NULL, NULL, x0, 0.0, 0.0};
+    nmpc_prob P = {nx, nu, T, h, model, prm, W, Bm, NULL, NULL, NULL, NULL, x0, 0.0, 0.0, 1.0, NULL, NULL};
     memcpy(x, x0, sizeof(double) * nx);
     for (int k = 0; k < T; ++k) f_step(&P, x + (size_t)k * nx, u + (size_t)k * nu, x + (size_t)(k + 1) * nx);
     return 0;
@@ -818,13 +842,13 @@ int oracle_nmpc_rollout(int nx, int nu, int T, double h, int model, const double
  */
 void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
                         const double *Bm, const double *Q, const double *R, const double *QT,
-                        const double *xref, double umin, double umax, double mu, const double *x,
-                        const double *u, double *A, double *Bl, double *lam, double *P, double *Rh, double *d,
-                        double *M)
+                        const double *xref, double umin, double umax, double rho, const double *z,
+                        const double *v, double mu, const double *x, const double *u, double *A, double *Bl,
+                        double *lam, double *P, double *Rh, double *d, double *M)
 {
     const int n = nx, m = nu;
     if (model_ok(model, nx, nu, prm) != 0) return;
-    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, NULL, umin, umax};
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, NULL, umin, umax, rho, z, v};
     double *th = malloc(sizeof(double) * (size_t)T * n);
     if (model == NMPC_TANH) {
         for (int k = 0; k < T; ++k)
@@ -891,7 +915,7 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double
             memcpy(Rk, R, sizeof(double) * m * m);
             for (int i = 0; i < m; ++i) {
                 double uu = u[(size_t)k * m + i], a = umax - uu, b = uu - umin;
-                Rk[i * m + i] += mu * (1.0 / (a * a) + 1.0 / (b * b));
+                Rk[i * m + i] += (rho > 0.0) ? 2.0 * rho : mu * (1.0 / (a * a) + 1.0 / (b * b));
             }
             if (model != NMPC_TANH)
                 for (int i = 0; i < m * m; ++i) Rk[i] += h * Huu[i];
@@ -901,7 +925,13 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double
                 double v = 0;
                 for (int j = 0; j < m; ++j) v += R[i * m + j] * u[(size_t)k * m + j];
                 double uu = u[(size_t)k * m + i];
-                v += mu * (1.0 / (umax - uu) - 1.0 / (uu - umin));
+                if (rho > 0.0) {
+                    double a, b;
+                    admm_ab(&Pb, k, i, uu, &a, &b);
+                    v += rho * (a - b);
+                } else {
+                    v += mu * (1.0 / (umax - uu) - 1.0 / (uu - umin));
+                }
                 for (int j = 0; j < n; ++j) v += Bl[(size_t)k * n * m + j * m + i] * lam[(size_t)(k + 1) * n + j];
                 d[(size_t)k * m + i] = v;
             }
@@ -929,13 +959,13 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double
  */
 int oracle_nmpc_newton_step(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
                             const double *Bm, const double *Q, const double *R, const double *QT,
-                            const double *xref, const double *x0, double umin, double umax,
-                            double mu, double *alpha, double *nu_lm, double *x, double *u,
-                            double *cost, double *pred_out, double *rho_out, double *grad_out)
+                            const double *xref, const double *x0, double umin, double umax, double admm_rho,
+                            const double *z, const double *v, double mu, double *alpha, double *nu_lm, double *x,
+                            double *u, double *cost, double *pred_out, double *rho_out, double *grad_out)
 {
     const int n = nx, m = nu;
     if (model_ok(model, nx, nu, prm) != 0) return -1;
-    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, admm_rho, z, v};
     size_t Tn = (size_t)T * n, Tnn = Tn * n, Tm = (size_t)T * m;
     double *A = malloc(sizeof(double) * Tnn), *Bl = malloc(sizeof(double) * Tn * m);
     double *lam = malloc(sizeof(double) * (Tn + n)), *P = malloc(sizeof(double) * Tnn);
@@ -947,8 +977,8 @@ int oracle_nmpc_newton_step(int nx, int nu, int T, double h, int model, const do
     double *zero = calloc((size_t)n, sizeof(double));
     int accepted = 0;
     double J0 = cost_mu(&Pb, u, x, mu), pred = 0, rho = -INFINITY;
-    oracle_nmpc_expand(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, umin, umax, mu, x, u, A, Bl, lam, P, Rh, d,
-                       Mx);
+    oracle_nmpc_expand(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, umin, umax, admm_rho, z, v, mu, x, u, A, Bl,
+                       lam, P, Rh, d, Mx);
     for (size_t k = 0; k < (size_t)T; ++k)
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j)
@@ -1028,15 +1058,15 @@ int oracle_nmpc_solve(int nx, int nu, int T, double h, int model, const double *
                       double *cost_trace, int *accept_trace, double *alpha_trace)
 {
     if (model_ok(model, nx, nu, prm) != 0) return -1;
-    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0, NULL, NULL};
     if (rollout(&Pb, u, x) != 0) return -1;
     double alpha = alpha0, nu_lm = nu0;
     int it = 0;
     for (int lv = 0; lv < n_levels; ++lv)
         for (int i = 0; i < iters; ++i, ++it) {
             double a_used = alpha, cst;
-            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax,
-                                              mu_levels[lv], &alpha, &nu_lm, x, u, &cst, NULL, NULL, NULL);
+            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0,
+                                              NULL, NULL, mu_levels[lv], &alpha, &nu_lm, x, u, &cst, NULL, NULL, NULL);
             if (cost_trace) cost_trace[it] = cst;
             if (accept_trace) accept_trace[it] = acc;
             if (alpha_trace) alpha_trace[it] = a_used;
@@ -1065,7 +1095,7 @@ int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const doubl
                          double *grad_trace, double *pred_trace, int *accept_trace, int *level_iters)
 {
     if (model_ok(model, nx, nu, prm) != 0 || !(zeta > 0.0 && zeta < 1.0) || !(mu0 > 0.0)) return -1;
-    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax};
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0, NULL, NULL};
     if (rollout(&Pb, u, x) != 0) return -1;
     double alpha = alpha0, nu_lm = nu0;
     int it = 0, lv = 0;
@@ -1074,8 +1104,8 @@ int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const doubl
         for (; li < max_iter; ++li) {
             double cst, grad, pred;
             if (it >= cap) return -2;
-            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, mu,
-                                              &alpha, &nu_lm, x, u, &cst, &pred, NULL, &grad);
+            int acc = oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0,
+                                              NULL, NULL, mu, &alpha, &nu_lm, x, u, &cst, &pred, NULL, &grad);
             if (mu_trace) mu_trace[it] = mu;
             if (cost_trace) cost_trace[it] = cst;
             if (grad_trace) grad_trace[it] = grad;
@@ -1089,5 +1119,95 @@ int oracle_nmpc_ip_solve(int nx, int nu, int T, double h, int model, const doubl
         }
         if (level_iters) level_iters[lv] = li;
     }
+    return it;
+}
+
+/*
+ * ADMM consensus and multiplier steps (eq:admm-step-4, eq:admm-step-5) for the
+ * control box: w = h(u) = [u - umax; umin - u] per stage ([T][2 nu] rows),
+ * C = {w <= 0}, Pi_C(y) = min(0, y):
+ *   init:  z = Pi_C(w), v = 0;
+ *   else:  z <- Pi_C(w + v / rho), v <- v + rho (w - z),
+ *          *rp = |w - z|_inf, *rd = |z - z_prev|_inf.
+ */
+void oracle_nmpc_admm_update(int T, int nu, double umin, double umax, double rho, const double *u, double *z,
+                             double *v, int init, double *rp_out, double *rd_out)
+{
+    const int m = nu;
+    double rp = 0.0, rd = 0.0;
+    for (int k = 0; k < T; ++k)
+        for (int i = 0; i < 2 * m; ++i) {
+            const double ui = u[(size_t)k * m + (i < m ? i : i - m)];
+            const double w = (i < m) ? ui - umax : umin - ui;
+            const size_t o = (size_t)k * 2 * m + i;
+            if (init) {
+                z[o] = fmin(0.0, w);
+                v[o] = 0.0;
+                continue;
+            }
+            const double zn = fmin(0.0, w + v[o] / rho);
+            rd = fmax(rd, fabs(zn - z[o]));
+            rp = fmax(rp, fabs(w - zn));
+            z[o] = zn;
+            v[o] += rho * (w - zn);
+        }
+    if (rp_out) *rp_out = rp;
+    if (rd_out) *rd_out = rd;
+}
+
+/*
+ * ADMM of Sec. II-C for the control box, with Alg. 4 as the inner solver of
+ * eq:admm-min: w(u) = h(u) = [u - umax; umin - u] per stage, C = {w <= 0}.
+ *   z0 = Pi_C(h(u0)) = min(0, h(u0)), v0 = 0;
+ *   repeat: Newton iterations on J_AD(u) = J(u) + rho/2 sum |h(u) - z + v/rho|^2
+ *           until the iteration that starts from |dJ_AD/du|_inf <= tol (or
+ *           max_iter); x the nonlinear rollout (eq:admm-step-2);
+ *           z <- min(0, h(u) + v/rho) (eq:admm-step-4, the projection on C);
+ *           v <- v + rho (h(u) - z) (eq:admm-step-5);
+ *           r_p = h(u) - z, r_d = z - z_prev;
+ *   until |r_p|_inf <= eps and |r_d|_inf <= eps, or max_admm iterations.
+ * alpha and nu_lm carry over from one ADMM iteration to the next.  z, v
+ * ([T][2 nu]) are outputs.  Traces of capacity cap (any NULL): Newton
+ * iterations, r_p and r_d of every ADMM iteration.  Returns the number of
+ * ADMM iterations, -1 for an unknown model or rho <= 0, -2 if cap is too
+ * small; *newton_total gets the Newton iterations over all of them.
+ */
+int oracle_nmpc_admm_solve(int nx, int nu, int T, double h, int model, const double *prm, const double *W,
+                           const double *Bm, const double *Q, const double *R, const double *QT,
+                           const double *xref, const double *x0, double umin, double umax, double rho, double eps,
+                           double tol, int max_iter, int max_admm, double alpha0, double nu0, double *u, double *x,
+                           double *z, double *v, int cap, int *inner_trace, double *rp_trace, double *rd_trace,
+                           int *newton_total)
+{
+    if (model_ok(model, nx, nu, prm) != 0 || !(rho > 0.0)) return -1;
+    nmpc_prob Pb = {nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, rho, z, v};
+    oracle_nmpc_admm_update(T, nu, umin, umax, rho, u, z, v, 1, NULL, NULL);
+    rollout(&Pb, u, x);
+    double alpha = alpha0, nu_lm = nu0;
+    int total = 0, it = 0;
+    for (; it < max_admm; ++it) {
+        if (it >= cap) return -2;
+        int li = 0;
+        for (; li < max_iter; ++li) {
+            double cst, grad;
+            oracle_nmpc_newton_step(nx, nu, T, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, rho, z, v, 0.0,
+                                    &alpha, &nu_lm, x, u, &cst, NULL, NULL, &grad);
+            if (grad <= tol) {
+                ++li;
+                break;
+            }
+        }
+        total += li;
+        double rp, rd;
+        oracle_nmpc_admm_update(T, nu, umin, umax, rho, u, z, v, 0, &rp, &rd);
+        if (inner_trace) inner_trace[it] = li;
+        if (rp_trace) rp_trace[it] = rp;
+        if (rd_trace) rd_trace[it] = rd;
+        if (rp <= eps && rd <= eps) {
+            ++it;
+            break;
+        }
+    }
+    if (newton_total) *newton_total = total;
     return it;
 }

@@ -276,6 +276,13 @@ IP_TOL, IP_MAX_ITER = 1e-6, 100
 # shorter segments than the default (fewer stages in the per-segment kernels,
 # which dominate at n <= 4) measured fastest for N >= 100.
 IP_SEG_LEN = 4
+# ADMM of Sec. V: rho = 1 (pendulum), 0.5 (cart-pole) per unit time (each
+# stage's augmentation term is weighted h rho, like the stage cost), stop at
+# |r_p|_inf, |r_d|_inf <= 1e-2; the inner Newton loops share IP_TOL and
+# IP_MAX_ITER; at most ADMM_MAX_ITER ADMM iterations.
+ADMM_RHO = {"pendulum": 1.0, "cartpole": 0.5}
+ADMM_EPS = 1e-2
+ADMM_MAX_ITER = 5000
 # Horizon lengths of the runtime figures of Sec. V.
 PAPER_HORIZONS = (20, 40, 80, 100, 200, 400, 800, 1000)
 

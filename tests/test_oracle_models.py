@@ -200,3 +200,74 @@ def test_tanh_model_unchanged_by_default():
     assert np.all(e["M"] == 0.0)
     xn = x[0] + p.h * (np.tanh(p.W @ x[0]) + p.Bm @ p.u0[0])
     assert rel(x[1], xn) < 1e-15
+
+
+# --------------------------------------------------------------------------
+# ADMM (Sec. II-C) on the control box
+# --------------------------------------------------------------------------
+
+def random_admm(p, rng, rho=0.7):
+    z = -np.abs(rng.standard_normal((p.T, 2 * p.nu)))
+    v = np.abs(rng.standard_normal((p.T, 2 * p.nu)))
+    return {"rho": rho, "z": z, "v": v}
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_admm_gradient_is_fd_gradient(name):
+    """With the augmentation rho/2 |h(u) - z + v/rho|^2 in place of the barrier, d_k is the
+    gradient of J_AD(u) of the nonlinear rollout (u may leave the box)."""
+    p = MODELS[name](25)
+    rng = np.random.default_rng(5)
+    admm = random_admm(p, rng)
+    u = p.u0 * 5.0
+    u[3, 0] = 1.2 * p.umax   # outside the box: allowed for ADMM
+    e = oracle.nmpc_expand(p, oracle.nmpc_rollout(p, u), u, 0.0, admm=admm)
+    g = np.zeros_like(u)
+    eps = 1e-6
+    for k in range(p.T):
+        up, um = u.copy(), u.copy()
+        up[k, 0] += eps
+        um[k, 0] -= eps
+        g[k, 0] = (oracle.nmpc_cost(p, up, 0.0, admm=admm) - oracle.nmpc_cost(p, um, 0.0, admm=admm)) / (2 * eps)
+    assert np.isfinite(oracle.nmpc_cost(p, u, 0.0, admm=admm))
+    assert rel(e["d"], g) < 1e-6
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_admm_newton_step_solves_regularised_newton_system(name):
+    """The Newton step of J_AD (R + 2 rho I in the expansion) solves (Hess J_AD + alpha I) du = -grad J_AD."""
+    p = MODELS[name](20)
+    rng = np.random.default_rng(6)
+    admm = random_admm(p, rng)
+    alpha = 0.5
+    u = p.u0 * 5.0
+    e = oracle.nmpc_expand(p, oracle.nmpc_rollout(p, u), u, 0.0, admm=admm)
+    Ra = e["Rh"] + alpha * np.eye(p.nu)[None]
+    du = oracle.lq_solve(e["A"], e["B"], None, e["P"], Ra, p.QT, np.zeros(p.nx), M=e["M"], r=e["d"])["u"]
+
+    def grad(uu):
+        return oracle.nmpc_expand(p, oracle.nmpc_rollout(p, uu), uu, 0.0, admm=admm)["d"]
+
+    eps = 1e-5
+    Hv = (grad(u + eps * du) - grad(u - eps * du)) / (2 * eps)
+    assert np.max(np.abs(Hv + alpha * du + e["d"])) < 1e-5 * np.max(np.abs(e["d"]))
+
+
+@pytest.mark.parametrize("name,N", [("pendulum", 40), ("cartpole", 20)])
+def test_admm_solve_invariants_and_convergence(name, N):
+    """z stays in C = {z <= 0}, the multipliers stay non-negative and complementary to z
+    (v_i > 0 only where z_i = 0), the loop stops at |r_p|, |r_d| <= eps, the final controls
+    violate the box by at most eps, and the swing-up still reaches the top."""
+    p = MODELS[name](N)
+    rho = W.ADMM_RHO[name] * p.h
+    o = oracle.nmpc_admm_solve(p, rho=rho, eps=W.ADMM_EPS, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                               max_admm=W.ADMM_MAX_ITER, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    assert o["admm_iters"] < W.ADMM_MAX_ITER
+    assert o["rp"][-1] <= W.ADMM_EPS and o["rd"][-1] <= W.ADMM_EPS
+    assert np.all(o["z"] <= 0.0) and np.all(o["v"] >= 0.0)
+    assert np.all((o["v"] == 0.0) | (o["z"] == 0.0))
+    viol = max(np.max(o["u"] - p.umax), np.max(p.umin - o["u"]))
+    assert viol <= W.ADMM_EPS
+    theta = o["x"][-1][0 if name == "pendulum" else 1]
+    assert abs(theta - np.pi) < 0.15
+    assert rel(oracle.nmpc_rollout(p, o["u"]), o["x"]) < 1e-14
