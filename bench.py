@@ -296,6 +296,45 @@ def paper_ip_solves(lqscan, workloads, reps: int, with_cpu: bool) -> dict:
     return out
 
 
+def paper_admm_solves(lqscan, workloads, with_cpu: bool, seq_max_n: int = 200) -> dict:
+    """ADMM solves of the same swing-ups (Sec. II-C, Sec. V: rho = 1 pendulum,
+    0.5 cart-pole, per unit time; stop at |r_p|, |r_d| <= 1e-2): wall time of
+    the whole solve, parallel path (segments of 4) for every N, the sequential
+    path up to seq_max_n (it grows linearly and the cart-pole needs thousands
+    of Newton iterations), and the oracle on one host core."""
+    import torch
+    out = {"unit": "ms per ADMM solve", "seg_len_parallel": workloads.IP_SEG_LEN}
+    if with_cpu:
+        import oracle
+    for name, mk in (("pendulum", workloads.pendulum_problem), ("cartpole", workloads.cartpole_problem)):
+        rows = {}
+        for N in workloads.PAPER_HORIZONS:
+            p = mk(N)
+            args = dict(rho=workloads.ADMM_RHO[name] * p.h, eps=workloads.ADMM_EPS, tol=workloads.IP_TOL,
+                        max_iter=workloads.IP_MAX_ITER, max_admm=workloads.ADMM_MAX_ITER,
+                        alpha0=workloads.NMPC_ALPHA0, nu0=workloads.NMPC_NU0)
+            row = {}
+            for label, kw in (("parallel_ms", dict(seg_len=workloads.IP_SEG_LEN)), ("sequential_ms", dict(mode="sequential"))):
+                if label == "sequential_ms" and N > seq_max_n:
+                    continue
+                s = lqscan.NewtonMPC(p, **kw)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                o = s.admm_solve(**args)
+                torch.cuda.synchronize()
+                row[label] = (time.perf_counter() - t0) * 1e3
+                if label == "parallel_ms":
+                    row["admm_iters"], row["newton_iters"] = o["admm_iters"], o["newton_iters"]
+            if with_cpu:
+                t0 = time.perf_counter()
+                ro = oracle.nmpc_admm_solve(p, **args)
+                row["oracle_ms"] = (time.perf_counter() - t0) * 1e3
+                row["oracle_admm_iters"] = ro["admm_iters"]
+            rows[str(N)] = row
+        out[name] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -483,6 +522,7 @@ def main():
         out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), 1)
     if not args.no_paper:
         out["paper_ip_solves"] = paper_ip_solves(lqscan, workloads, 3, not args.no_cpu)
+        out["paper_admm_solves"] = paper_admm_solves(lqscan, workloads, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out))

@@ -255,6 +255,14 @@ typedef struct {
     double umin, umax;
     int32_t model;                 /* nmpc_model                                */
     double param[4];               /* model constants (host values)             */
+    /* ADMM (Sec. II-C): with admm_rho > 0 the augmentation
+     * admm_rho/2 |h(u_k) - z_k + v_k/admm_rho|^2, h(u) = [u - umax; umin - u],
+     * replaces the barrier (mu is then unused and u may leave the box).
+     * admm_z, admm_v: T*2*nu device arrays, rows u - umax then umin - u per
+     * stage, written by nmpc_admm_update.  admm_rho is the weight of each
+     * stage's term (fold any time step into it). */
+    double admm_rho;
+    double *admm_z, *admm_v;
 } nmpc_problem;
 
 /* Indices of the device scalar array nmpc_state.scal (NMPC_NSCAL doubles). */
@@ -268,7 +276,9 @@ enum {
     NMPC_ACCEPTED = 6,    /* 1.0 if the step was accepted                             */
     NMPC_COST_NEW = 7,    /* J_mu of the candidate                                    */
     NMPC_GRAD = 8,        /* |dJ_mu/du|_inf at the nominal the step started from      */
-    NMPC_NSCAL = 9
+    NMPC_RP = 9,          /* ADMM primal residual |h(u) - z|_inf (nmpc_admm_update)   */
+    NMPC_RD = 10,         /* ADMM dual residual |z - z_prev|_inf (nmpc_admm_update)   */
+    NMPC_NSCAL = 11
 };
 
 typedef struct {
@@ -299,6 +309,19 @@ lq_status nmpc_init(const lq_plan *plan, const nmpc_problem *prob, const nmpc_st
  */
 lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, void *workspace,
                       int32_t *status, void *stream);
+
+/*
+ * ADMM consensus and multiplier steps (eq:admm-step-4 and eq:admm-step-5 of
+ * Sec. II-C) for the control box, from the nominal controls state->u, with
+ * w = h(u) = [u - umax; umin - u] per stage and C = {w <= 0}:
+ *   init != 0:  z = min(0, w), v = 0 (the start of the ADMM loop);
+ *   init == 0:  z <- min(0, w + v/rho), v <- v + rho (w - z), and
+ *               scal[NMPC_RP] = |w - z|_inf, scal[NMPC_RD] = |z - z_prev|_inf.
+ * One block on `stream`.  Errors: LQ_ERR_ARG if the plan does not match the
+ * problem or prob->admm_rho <= 0 or admm_z / admm_v is null.
+ */
+lq_status nmpc_admm_update(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, int32_t init,
+                           void *stream);
 
 /*
  * Diagnostic: one 16 x 16 tile product D = op(X) op(Y) (+ Z) through the

@@ -441,8 +441,9 @@ static bool nmpc_matches(const lq_plan *p, const nmpc_problem *q)
     case NMPC_CARTPOLE: model_ok = q->nx == 4 && q->nu == 1; break;
     default: break;
     }
-    return model_ok && d.n == q->nx && d.m == q->nu && d.T == q->T && q->Q && q->R && q->QT && q->xref && q->x0 &&
-           q->umin < q->umax;
+    const bool aug_ok = !(q->admm_rho > 0.0) || (q->admm_z && q->admm_v);
+    return model_ok && aug_ok && d.n == q->nx && d.m == q->nu && d.T == q->T && q->Q && q->R && q->QT && q->xref &&
+           q->x0 && q->umin < q->umax;
 }
 
 static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
@@ -453,6 +454,9 @@ static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
     N.umin = q->umin; N.umax = q->umax;
     N.model = q->model;
     for (int i = 0; i < 4; ++i) N.prm[i] = q->param[i];
+    N.rho = (q->admm_rho > 0.0) ? q->admm_rho : 0.0;
+    N.z = q->admm_z;
+    N.v = q->admm_v;
     return N;
 }
 
@@ -515,6 +519,14 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     // candidate, decision, commit
     lqk::launch_nmpc_candidate(st, N, Wk, state->x, state->u, state->scal);
     lqk::launch_nmpc_commit(st, N, Wk, state->x, state->u, state->scal);
+    return launched();
+}
+
+lq_status nmpc_admm_update(const lq_plan *p, const nmpc_problem *prob, const nmpc_state *state, int32_t init,
+                           void *stream)
+{
+    if (!nmpc_matches(p, prob) || !state || !state->u || !state->scal || !(prob->admm_rho > 0.0)) return LQ_ERR_ARG;
+    lqk::launch_admm_update((hipStream_t)stream, nmpc_ptrs(prob), state->u, state->scal, init);
     return launched();
 }
 

@@ -46,7 +46,7 @@ struct GradPtrs {
 
 // Newton / interior-point: device scalars (indices match include/lqscan.h).
 enum { NMPC_MU = 0, NMPC_ALPHA = 1, NMPC_NU = 2, NMPC_COST = 3, NMPC_PRED = 4, NMPC_RHO = 5,
-       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_NSCAL = 9 };
+       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_RP = 9, NMPC_RD = 10, NMPC_NSCAL = 11 };
 enum { MODEL_TANH = 0, MODEL_PENDULUM = 1, MODEL_CARTPOLE = 2 };
 
 struct NmpcPtrs {
@@ -56,6 +56,10 @@ struct NmpcPtrs {
     double umin, umax;
     int model;
     double prm[4];
+    // rho > 0: the ADMM augmentation rho/2 |h(u) - z + v/rho|^2 (z, v: [T][2 nu],
+    // rows u - umax then umin - u) replaces the barrier
+    double rho;
+    double *z, *v;
 };
 
 // Newton workspace arrays (stage-major like the LQ problem arrays).

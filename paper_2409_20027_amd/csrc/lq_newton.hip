@@ -117,6 +117,18 @@ LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, cons
 }
 
 // Stage cost plus barrier at stage k (returns +inf if u is infeasible).
+// ADMM residual of stage k, input i: (a, b) = h(u) - z + v / rho for the rows
+// u_i - umax <= 0 and umin - u_i <= 0.
+LQK_DEV void admm_ab(const NmpcPtrs &N, int k, int i, double ui, double &a, double &b)
+{
+    const int m = N.nu;
+    const double *zk = N.z + (int64_t)k * 2 * m, *vk = N.v + (int64_t)k * 2 * m;
+    a = (ui - N.umax) - zk[i] + vk[i] / N.rho;
+    b = (N.umin - ui) - zk[m + i] + vk[m + i] / N.rho;
+}
+
+// Stage cost plus the barrier (+inf if u is infeasible), or plus the ADMM
+// augmentation when N.rho > 0.
 LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, const double *xk, const double *uk, double mu)
 {
     const double *rk = N.xref + (int64_t)k * n;
@@ -125,6 +137,12 @@ LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, const double *
         for (int j = 0; j < n; ++j) J += 0.5 * (xk[i] - rk[i]) * N.Q[i * n + j] * (xk[j] - rk[j]);
     for (int i = 0; i < m; ++i) {
         for (int j = 0; j < m; ++j) J += 0.5 * uk[i] * N.R[i * m + j] * uk[j];
+        if (N.rho > 0.0) {
+            double a, b;
+            admm_ab(N, k, i, uk[i], a, b);
+            J += 0.5 * N.rho * (a * a + b * b);
+            continue;
+        }
         const double a = N.umax - uk[i], b = uk[i] - N.umin;
         if (!(a > 0.0 && b > 0.0)) return INFINITY;
         J += -mu * (log(a) + log(b));
@@ -395,7 +413,7 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     for (int i = 0; i < m * m; ++i) Rh[i] = N.R[i];
     for (int i = 0; i < m; ++i) {
         const double a = N.umax - uk[i], b = uk[i] - N.umin;
-        Rh[i * m + i] += mu * (1.0 / (a * a) + 1.0 / (b * b));
+        Rh[i * m + i] += (N.rho > 0.0) ? 2.0 * N.rho : mu * (1.0 / (a * a) + 1.0 / (b * b));
     }
     if (N.model != MODEL_TANH) Rh[0] += huu;
     for (int i = 0; i < m * m; ++i) Rt[i] = Rh[i];
@@ -406,7 +424,13 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
         double v = 0.0;
         for (int j = 0; j < m; ++j) v += N.R[i * m + j] * uk[j];
         const double uu = uk[i];
-        v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
+        if (N.rho > 0.0) {
+            double a, b;
+            admm_ab(N, k, i, uu, a, b);
+            v += N.rho * (a - b);
+        } else {
+            v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
+        }
         for (int j = 0; j < n; ++j) v += B[j * m + i] * l1[j];
         Wk.d[(int64_t)k * m + i] = v;
     }
@@ -504,6 +528,48 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
     scal[NMPC_ACCEPTED] = acc ? 1.0 : 0.0;
 }
 
+// ADMM consensus and multiplier steps of Sec. II-C (eq:admm-step-4, -5) for
+// the control box, w = h(u) = [u - umax; umin - u] per stage, C = {w <= 0}:
+// z <- min(0, w + v / rho), v <- v + rho (w - z), with |r_p|_inf = |w - z|_inf
+// and |r_d|_inf = |z - z_prev|_inf reduced over the block (init: z = min(0, w),
+// v = 0, residuals not formed).
+__global__ __launch_bounds__(RED) void k_admm_update(NmpcPtrs N, const double *u, double *scal, int init)
+{
+    __shared__ double sp[RED], sd[RED];
+    const int t = threadIdx.x, m = N.nu;
+    const int64_t cnt = (int64_t)N.T * 2 * m;
+    double rp = 0.0, rd = 0.0;
+    for (int64_t o = t; o < cnt; o += RED) {
+        const int64_t k = o / (2 * m);
+        const int i = (int)(o - k * 2 * m);
+        const double ui = u[k * m + (i < m ? i : i - m)];
+        const double w = (i < m) ? ui - N.umax : N.umin - ui;
+        if (init) {
+            N.z[o] = fmin(0.0, w);
+            N.v[o] = 0.0;
+            continue;
+        }
+        const double zn = fmin(0.0, w + N.v[o] / N.rho);
+        rd = fmax(rd, fabs(zn - N.z[o]));
+        rp = fmax(rp, fabs(w - zn));
+        N.z[o] = zn;
+        N.v[o] += N.rho * (w - zn);
+    }
+    sp[t] = rp;
+    sd[t] = rd;
+    for (int h = RED / 2; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) {
+            sp[t] = fmax(sp[t], sp[t + h]);
+            sd[t] = fmax(sd[t], sd[t + h]);
+        }
+    }
+    if (t == 0 && !init) {
+        scal[NMPC_RP] = sp[0];
+        scal[NMPC_RD] = sd[0];
+    }
+}
+
 // Step 7: on acceptance the candidate becomes the nominal.
 __global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork Wk, double *x, double *u,
                                                      const double *scal)
@@ -569,6 +635,10 @@ void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double
 {
     launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc);
     hipLaunchKernelGGL(k_nmpc_reduce, dim3(1), dim3(RED), 0, st, N, Wk, x, u, scal);
+}
+void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init)
+{
+    hipLaunchKernelGGL(k_admm_update, dim3(1), dim3(RED), 0, st, N, u, scal, init);
 }
 void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal)
 {

@@ -361,7 +361,7 @@ def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=Non
 # ---------------------------------------------------------------------------
 
 (NMPC_MU, NMPC_ALPHA, NMPC_NU, NMPC_COST, NMPC_PRED, NMPC_RHO, NMPC_ACCEPTED, NMPC_COST_NEW, NMPC_GRAD,
- NMPC_NSCAL) = range(10)
+ NMPC_RP, NMPC_RD, NMPC_NSCAL) = range(12)
 NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE = 0, 1, 2
 
 
@@ -369,7 +369,7 @@ class NMPCProblemC(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("nu", ctypes.c_int32), ("T", ctypes.c_int32), ("h", ctypes.c_double),
                 ("W", _P), ("Bm", _P), ("Q", _P), ("R", _P), ("QT", _P), ("xref", _P), ("x0", _P),
                 ("umin", ctypes.c_double), ("umax", ctypes.c_double), ("model", ctypes.c_int32),
-                ("param", ctypes.c_double * 4)]
+                ("param", ctypes.c_double * 4), ("admm_rho", ctypes.c_double), ("admm_z", _P), ("admm_v", _P)]
 
 
 class NMPCStateC(ctypes.Structure):
@@ -382,7 +382,10 @@ _lib.nmpc_init.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER
 _lib.nmpc_init.restype = ctypes.c_int
 _lib.newton_step.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), _P, _P, _P]
 _lib.newton_step.restype = ctypes.c_int
-EXPORTED = EXPORTED + ("nmpc_workspace_bytes", "nmpc_init", "newton_step")
+_lib.nmpc_admm_update.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), ctypes.c_int32,
+                                  _P]
+_lib.nmpc_admm_update.restype = ctypes.c_int
+EXPORTED = EXPORTED + ("nmpc_workspace_bytes", "nmpc_init", "newton_step", "nmpc_admm_update")
 
 
 def nmpc_workspace_bytes(plan: Plan) -> int:
@@ -397,6 +400,11 @@ def nmpc_init(plan, prob_c, state_c, workspace, stream=None):
 def newton_step(plan, prob_c, state_c, workspace, status=None, stream=None):
     _check("newton_step", _lib.newton_step(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c),
                                            _ptr(workspace), _ptr(status), _stream(stream)))
+
+
+def nmpc_admm_update(plan, prob_c, state_c, init, stream=None):
+    _check("nmpc_admm_update", _lib.nmpc_admm_update(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c),
+                                                     int(init), _stream(stream)))
 
 
 class NewtonMPC:
@@ -462,6 +470,59 @@ class NewtonMPC:
                 "cost": a[:, NMPC_COST], "accept": a[:, NMPC_ACCEPTED] > 0.5,
                 "alpha": before.cpu().numpy()[:, NMPC_ALPHA], "pred": a[:, NMPC_PRED], "rho": a[:, NMPC_RHO]}
 
+    def _newton_level(self, mu, tol, max_iter, host, rows):
+        """Newton iterations until the one that starts from |dJ/du|_inf <= tol (or max_iter)."""
+        li = 0
+        while li < max_iter:
+            self.scal[NMPC_MU] = mu
+            newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+            host.copy_(self.scal, non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            li += 1
+            if rows is not None:
+                rows.append((mu, float(host[NMPC_COST]), float(host[NMPC_GRAD]), float(host[NMPC_ACCEPTED]),
+                             float(host[NMPC_PRED])))
+            if float(host[NMPC_GRAD]) <= tol:
+                break
+        return li
+
+    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0):
+        """ADMM of Sec. II-C for the control box with newton_step as the inner solver:
+        z = min(0, h(u0)), v = 0; repeat Newton iterations on J_AD to |dJ_AD/du|_inf <= tol
+        (or max_iter), then nmpc_admm_update, until |r_p|_inf, |r_d|_inf <= eps or max_admm.
+        rho is the weight of each stage's augmentation term.  Returns dict(u, x, z, v,
+        admm_iters, newton_iters, inner, rp, rd)."""
+        dev = self.x.device
+        z = torch.zeros(self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
+        v = torch.zeros_like(z)
+        self.prob_c.admm_rho = float(rho)
+        self.prob_c.admm_z = _f64(z)
+        self.prob_c.admm_v = _f64(v)
+        try:
+            self.init(alpha0, nu0)
+            nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
+            host = torch.empty(NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
+            inner, rps, rds = [], [], []
+            for _ in range(max_admm):
+                inner.append(self._newton_level(0.0, tol, max_iter, host, None))
+                nmpc_admm_update(self.plan, self.prob_c, self.state_c, 0)
+                host.copy_(self.scal, non_blocking=True)
+                torch.cuda.current_stream().synchronize()
+                rps.append(float(host[NMPC_RP]))
+                rds.append(float(host[NMPC_RD]))
+                if rps[-1] <= eps and rds[-1] <= eps:
+                    break
+        finally:
+            self.prob_c.admm_rho = 0.0
+            self.prob_c.admm_z = None
+            self.prob_c.admm_v = None
+        return {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
+                "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
+                "z": z.cpu().numpy().reshape(self.p.T, 2 * self.p.nu),
+                "v": v.cpu().numpy().reshape(self.p.T, 2 * self.p.nu),
+                "admm_iters": len(inner), "newton_iters": int(sum(inner)), "inner": np.array(inner),
+                "rp": np.array(rps), "rd": np.array(rds)}
+
     def ip_solve(self, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, trace=True):
         """The interior-point method of Sec. II-B with converged inner Newton loops:
         mu = mu0, mu0 zeta, ... while mu > mu_min; a level ends after the iteration
@@ -473,22 +534,10 @@ class NewtonMPC:
         """
         self.init(alpha0, nu0)
         host = torch.empty(NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
-        rows, level_iters = [], []
+        rows, level_iters = ([] if trace else None), []
         mu = float(mu0)
         while mu > mu_min:
-            li = 0
-            while li < max_iter:
-                self.scal[NMPC_MU] = mu
-                newton_step(self.plan, self.prob_c, self.state_c, self.ws)
-                host.copy_(self.scal, non_blocking=True)
-                torch.cuda.current_stream().synchronize()
-                li += 1
-                if trace:
-                    rows.append((mu, float(host[NMPC_COST]), float(host[NMPC_GRAD]), float(host[NMPC_ACCEPTED]),
-                                 float(host[NMPC_PRED])))
-                if float(host[NMPC_GRAD]) <= tol:
-                    break
-            level_iters.append(li)
+            level_iters.append(self._newton_level(mu, tol, max_iter, host, rows))
             mu *= zeta
         out = {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
                "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),

@@ -111,3 +111,96 @@ def test_interior_point_sequential_mode_matches_oracle(lq, name):
     p = MODELS[name](100)
     got, ref = ip(lq, p, mode="sequential")
     check_ip(p, got, ref)
+
+
+# --------------------------------------------------------------------------
+# ADMM (Sec. II-C)
+# --------------------------------------------------------------------------
+
+def admm_state(p, seed, rho=0.7):
+    rng = np.random.default_rng(seed)
+    z = -np.abs(rng.standard_normal((p.T, 2 * p.nu)))
+    v = np.abs(rng.standard_normal((p.T, 2 * p.nu)))
+    return {"rho": rho, "z": z, "v": v}
+
+
+def gpu_with_admm(lq, p, admm, **kw):
+    s = lq.NewtonMPC(p, **kw)
+    z = torch.as_tensor(admm["z"].reshape(-1), dtype=torch.float64, device="cuda").contiguous()
+    v = torch.as_tensor(admm["v"].reshape(-1), dtype=torch.float64, device="cuda").contiguous()
+    s.prob_c.admm_rho = admm["rho"]
+    s.prob_c.admm_z = z.data_ptr()
+    s.prob_c.admm_v = v.data_ptr()
+    return s, z, v
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+@pytest.mark.parametrize("seg_len", [0, 3])
+def test_admm_newton_step(lq, name, seg_len):
+    """One Newton step on J_AD (augmentation instead of barrier; a control outside the box)."""
+    import dataclasses
+    p = MODELS[name](61)
+    u0 = p.u0 * 5.0
+    u0[7, 0] = 1.1 * p.umax
+    p = dataclasses.replace(p, u0=u0, Q=np.eye(p.nx) * 0.2)
+    admm = admm_state(p, 3)
+    alpha, nu = 0.05, 2.0
+    x0 = oracle.nmpc_rollout(p, p.u0)
+    acc, x1, u1, a1, nu1, cost, pred, rho, grad = oracle.nmpc_newton_step(p, x0, p.u0, 0.0, alpha, nu,
+                                                                          with_grad=True, admm=admm)
+    s, z, v = gpu_with_admm(lq, p, admm, seg_len=seg_len)
+    s.init(alpha, nu)
+    s.step(0.0)
+    torch.cuda.synchronize()
+    sc = s.scal.cpu().numpy()
+    assert bool(sc[lq.NMPC_ACCEPTED] > 0.5) == acc
+    assert abs(sc[lq.NMPC_PRED] - pred) <= 1e-10 * abs(pred)
+    assert abs(sc[lq.NMPC_COST] - cost) <= 1e-10 * abs(cost)
+    assert abs(sc[lq.NMPC_GRAD] - grad) <= 1e-10 * abs(grad)
+    assert rel(s.u.cpu().numpy().reshape(p.T, p.nu), u1) < 1e-10
+    assert rel(s.x.cpu().numpy().reshape(p.T + 1, p.nx), x1) < 1e-10
+
+
+@pytest.mark.parametrize("init", [1, 0])
+def test_admm_update_matches_oracle(lq, init):
+    """The consensus / multiplier step: z bit for bit (a projection of the same sums), v and
+    both residual norms to round-off (the GPU contracts v + rho (w - z) into one fused
+    multiply-add, the oracle rounds twice; for inactive rows v is the cancellation
+    v + rho (w - (w + v / rho)) of a few ulp of rho |w|), with controls inside, on and
+    outside the box."""
+    p = W.cartpole_problem(300)
+    rng = np.random.default_rng(9)
+    u = rng.uniform(-1.3 * p.umax, 1.3 * p.umax, (p.T, p.nu))
+    u[5, 0] = p.umax
+    admm = admm_state(p, 10, rho=0.37)
+    zr, vr, rp, rd = oracle.nmpc_admm_update(p, u, admm["z"], admm["v"], admm["rho"], init)
+    s, z, v = gpu_with_admm(lq, p, admm)
+    s.u.copy_(torch.as_tensor(u.reshape(-1), dtype=torch.float64))
+    lq.nmpc_admm_update(s.plan, s.prob_c, s.state_c, init)
+    torch.cuda.synchronize()
+    assert np.array_equal(z.cpu().numpy().reshape(p.T, -1), zr)
+    vg = v.cpu().numpy().reshape(p.T, -1)
+    w = np.concatenate([u - p.umax, p.umin - u], axis=1)
+    scale = admm["rho"] * np.abs(w) + np.abs(admm["v"])
+    assert np.all(np.abs(vg - vr) <= 8 * np.finfo(float).eps * scale)
+    if not init:
+        sc = s.scal.cpu().numpy()
+        assert abs(sc[lq.NMPC_RP] - rp) <= 1e-14 * max(rp, 1.0) and abs(sc[lq.NMPC_RD] - rd) <= 1e-14 * max(rd, 1.0)
+
+
+@pytest.mark.parametrize("name,N", [("pendulum", 40), ("pendulum", 400), ("cartpole", 20)])
+def test_admm_solve_matches_oracle(lq, name, N):
+    """Whole ADMM solves: the same number of ADMM iterations and the same final
+    trajectory (ADMM's inner loops end far above round-off, see the IP tests), the
+    invariants z <= 0, v >= 0, v z = 0, and residuals within eps."""
+    p = MODELS[name](N)
+    args = dict(rho=W.ADMM_RHO[name] * p.h, eps=W.ADMM_EPS, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                max_admm=W.ADMM_MAX_ITER, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    ref = oracle.nmpc_admm_solve(p, **args)
+    got = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN).admm_solve(**args)
+    print(f"{name} N={N}: ADMM {got['admm_iters']} vs {ref['admm_iters']}, Newton {got['newton_iters']} vs "
+          f"{ref['newton_iters']}, u {rel(got['u'], ref['u']):.1e}")
+    assert got["admm_iters"] == ref["admm_iters"]
+    assert rel(got["u"], ref["u"]) < 1e-5 and rel(got["x"], ref["x"]) < 1e-5
+    assert np.all(got["z"] <= 0.0) and np.all(got["v"] >= 0.0) and np.all((got["v"] == 0) | (got["z"] == 0))
+    assert got["rp"][-1] <= W.ADMM_EPS and got["rd"][-1] <= W.ADMM_EPS
