@@ -246,12 +246,17 @@ lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value
  */
 typedef enum { NMPC_TANH = 0, NMPC_PENDULUM = 1, NMPC_CARTPOLE = 2 } nmpc_model;
 
+/* A plan with batch B >= 1 instances, all of sizes (nx, nu, T), solves B
+ * problems at once that share the model, costs, bounds and reference and
+ * differ in x0 ([B][nx]) and their trajectories: nmpc_state.x is
+ * [B][(T+1) nx], u [B][T nu], scal [B][NMPC_NSCAL], admm_z / admm_v
+ * [B][T][2 nu]; every decision is taken per instance. */
 typedef struct {
     int32_t nx, nu, T;
     double h;
     const double *W, *Bm;          /* nx*nx, nx*nu (device; NMPC_TANH only, else ignored) */
     const double *Q, *R, *QT;      /* nx*nx, nu*nu, nx*nx             (device) */
-    const double *xref, *x0;       /* (T+1)*nx, nx                    (device) */
+    const double *xref, *x0;       /* (T+1)*nx, batch*nx              (device) */
     double umin, umax;
     int32_t model;                 /* nmpc_model                                */
     double param[4];               /* model constants (host values)             */
@@ -286,8 +291,8 @@ typedef struct {
     double *scal;    /* NMPC_NSCAL device scalars                                             */
 } nmpc_state;
 
-/* Workspace of newton_step / nmpc_init for a plan with batch 1 and the same
- * (nx, nu, T) (the plan's segment length is used by every scan). */
+/* Workspace of newton_step / nmpc_init for a plan whose instances all have
+ * the problem's (nx, nu, T) (the plan's segment length is used by every scan). */
 size_t nmpc_workspace_bytes(const lq_plan *plan);
 
 /* x <- nonlinear rollout of u from x0 (call once before the first step). */
@@ -322,6 +327,19 @@ lq_status newton_step(const lq_plan *plan, const nmpc_problem *prob, const nmpc_
  */
 lq_status nmpc_admm_update(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, int32_t init,
                            void *stream);
+
+/*
+ * Receding horizon (Sec. V, model predictive control): for every instance the
+ * plant takes one step with the first control, x0 <- x0 + h f(x0, u_0) (x0 is
+ * the device array prob->x0 points to, updated in place; u_0 is written to
+ * u_applied [batch][nu]), and state->u shifts by one stage for the next
+ * solve's warm start (the last control is kept).  Call nmpc_init before the
+ * next solve's first newton_step (it re-rolls the nominal from the new x0).
+ * Errors: LQ_ERR_ARG if the plan does not match the problem or a pointer is
+ * null.
+ */
+lq_status nmpc_shift(const lq_plan *plan, const nmpc_problem *prob, const nmpc_state *state, double *x0,
+                     double *u_applied, void *stream);
 
 /*
  * Diagnostic: one 16 x 16 tile product D = op(X) op(Y) (+ Z) through the

@@ -81,6 +81,9 @@ def lib():
             L.oracle_nmpc_admm_solve.restype = i
             L.oracle_nmpc_admm_update.argtypes = [i, i, d, d, d, _P, _P, _P, i, _P, _P]
             L.oracle_nmpc_admm_update.restype = None
+            L.oracle_nmpc_mpc_simulate.argtypes = ([i, i, i, d, i, _P] + [_P] * 8 + [d, d, _P, i, i, d, d, i]
+                                                   + [_P, _P])
+            L.oracle_nmpc_mpc_simulate.restype = i
             _lib = L
     return _lib
 
@@ -379,3 +382,23 @@ def nmpc_admm_update(p, u, z, v, rho, init):
     lib().oracle_nmpc_admm_update(p.T, p.nu, float(p.umin), float(p.umax), float(rho), _p(u), _p(z), _p(v),
                                   int(bool(init)), ctypes.byref(rp), ctypes.byref(rd))
     return z, v, rp.value, rd.value
+
+
+def nmpc_mpc_simulate(p, x_init, *, steps, mu_levels, iters, alpha0, nu0):
+    """Receding-horizon simulation of `steps` plant steps (fixed IP budget per solve,
+    warm start by shifting); returns dict(x [steps+1, nx], u [steps, nu])."""
+    model, prm = _model(p)
+    W, Bm = _wb(p)
+    Q, R, QT, xref = map(_f, (p.Q, p.R, p.QT, p.xref))
+    xi = _f(np.asarray(x_init, np.float64))
+    ui = _f(np.asarray(p.u0, np.float64).reshape(p.T, p.nu))
+    mus = np.asarray(mu_levels, np.float64)
+    x_cl = np.zeros((steps + 1, p.nx))
+    u_cl = np.zeros((steps, p.nu))
+    st = lib().oracle_nmpc_mpc_simulate(p.nx, p.nu, p.T, float(p.h), model, _p(prm), _p(W), _p(Bm), _p(Q), _p(R),
+                                        _p(QT), _p(xref), _p(xi), _p(ui), float(p.umin), float(p.umax), _p(mus),
+                                        len(mus), int(iters), float(alpha0), float(nu0), int(steps), _p(x_cl),
+                                        _p(u_cl))
+    if st != 0:
+        raise OracleError(st, -1)
+    return {"x": x_cl, "u": u_cl}

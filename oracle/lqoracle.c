@@ -1211,3 +1211,52 @@ int oracle_nmpc_admm_solve(int nx, int nu, int T, double h, int model, const dou
     if (newton_total) *newton_total = total;
     return it;
 }
+
+/*
+ * Receding-horizon simulation (Sec. V, model predictive control): at every
+ * step t the interior-point method with a fixed budget (iters Newton
+ * iterations at each barrier weight of mu_levels) solves the N-stage problem
+ * from the current state, warm-started with the previous solution shifted by
+ * one stage (the last control repeated; the first solve starts from u_init);
+ * alpha and nu_lm restart from (alpha0, nu0) at every step.  The first
+ * control is applied to the plant, one Euler step of the same model.
+ * Outputs: x_cl [steps+1][nx] (x_cl[0] = x_init), u_cl [steps][nu].
+ * Returns 0, or -1 for an unknown model or an infeasible u_init.
+ */
+int oracle_nmpc_mpc_simulate(int nx, int nu, int N, double h, int model, const double *prm, const double *W,
+                             const double *Bm, const double *Q, const double *R, const double *QT,
+                             const double *xref, const double *x_init, const double *u_init, double umin,
+                             double umax, const double *mu_levels, int n_levels, int iters, double alpha0,
+                             double nu0, int steps, double *x_cl, double *u_cl)
+{
+    const int n = nx, m = nu;
+    if (model_ok(model, nx, nu, prm) != 0) return -1;
+    double *u = malloc(sizeof(double) * (size_t)N * m), *x = malloc(sizeof(double) * (size_t)(N + 1) * n);
+    double x0[16];
+    memcpy(u, u_init, sizeof(double) * (size_t)N * m);
+    memcpy(x0, x_init, sizeof(double) * n);
+    memcpy(x_cl, x_init, sizeof(double) * n);
+    int st = 0;
+    for (int t = 0; t < steps && st == 0; ++t) {
+        nmpc_prob Pb = {nx, nu, N, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0, NULL, NULL};
+        if (rollout(&Pb, u, x) != 0) {
+            st = -1;
+            break;
+        }
+        double alpha = alpha0, nu_lm = nu0;
+        for (int lv = 0; lv < n_levels; ++lv)
+            for (int i = 0; i < iters; ++i)
+                oracle_nmpc_newton_step(nx, nu, N, h, model, prm, W, Bm, Q, R, QT, xref, x0, umin, umax, 0.0, NULL,
+                                        NULL, mu_levels[lv], &alpha, &nu_lm, x, u, NULL, NULL, NULL, NULL);
+        double xn[16];
+        f_step(&Pb, x0, u, xn);
+        for (int i = 0; i < m; ++i) u_cl[(size_t)t * m + i] = u[i];
+        memcpy(x0, xn, sizeof(double) * n);
+        memcpy(x_cl + (size_t)(t + 1) * n, xn, sizeof(double) * n);
+        for (int k = 0; k + 1 < N; ++k)
+            for (int i = 0; i < m; ++i) u[(size_t)k * m + i] = u[(size_t)(k + 1) * m + i];
+    }
+    free(u);
+    free(x);
+    return st;
+}

@@ -406,34 +406,38 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
 
 // Layout of the Newton workspace after the plan's LQ workspace.
 struct NmpcLayout {
-    size_t A, B, P, M, Rt, Rh, d, th, g, lam, lamT, S, s, G, gm, dx, du, xc, uc, zero, status, total;
+    size_t QTb, A, B, P, M, Rt, Rh, d, th, g, lam, lamT, S, s, G, gm, dx, du, xc, uc, zero, status, total;
 };
 
+// Newton workspace after the LQ workspace: every array holds the plan's
+// `batch` instances packed like the LQ arrays (all instances of equal sizes).
 static NmpcLayout nmpc_layout(const lq_plan *p)
 {
     const InstDesc &d = p->h_inst[0];
-    const size_t n = d.n, m = d.m, T = d.T, D = sizeof(double);
+    const size_t n = d.n, m = d.m, T = d.T, D = sizeof(double), Bn = (size_t)p->batch;
     NmpcLayout L{};
     size_t off = align_up(p->ws_bytes);
     auto take = [&](size_t bytes) {
         const size_t o = off;
-        off = align_up(off + bytes);
+        off = align_up(off + Bn * bytes);
         return o;
     };
+    L.QTb = take(n * n * D);
     L.A = take(T * n * n * D); L.B = take(T * n * m * D); L.P = take(T * n * n * D); L.M = take(T * n * m * D);
     L.Rt = take(T * m * m * D); L.Rh = take(T * m * m * D); L.d = take(T * m * D);
     L.th = take(T * n * D); L.g = take(T * n * D); L.lam = take((T + 1) * n * D); L.lamT = take(n * D);
     L.S = take((T + 1) * n * n * D); L.s = take((T + 1) * n * D); L.G = take(T * m * n * D);
     L.gm = take(T * m * D); L.dx = take((T + 1) * n * D); L.du = take(T * m * D);
-    L.xc = take((T + 1) * n * D); L.uc = take(T * m * D); L.zero = take(n * D); L.status = take(64);
+    L.xc = take((T + 1) * n * D); L.uc = take(T * m * D); L.zero = take(n * D); L.status = take(sizeof(int32_t));
     L.total = off;
     return L;
 }
 
 static bool nmpc_matches(const lq_plan *p, const nmpc_problem *q)
 {
-    if (!p || !q || p->batch != 1) return false;
-    const InstDesc &d = p->h_inst[0];
+    if (!p || !q || p->batch < 1) return false;
+    for (const InstDesc &d : p->h_inst)
+        if (d.n != q->nx || d.m != q->nu || d.T != q->T) return false;
     bool model_ok = false;
     switch (q->model) {
     case NMPC_TANH: model_ok = q->W && q->Bm; break;
@@ -442,14 +446,13 @@ static bool nmpc_matches(const lq_plan *p, const nmpc_problem *q)
     default: break;
     }
     const bool aug_ok = !(q->admm_rho > 0.0) || (q->admm_z && q->admm_v);
-    return model_ok && aug_ok && d.n == q->nx && d.m == q->nu && d.T == q->T && q->Q && q->R && q->QT && q->xref &&
-           q->x0 && q->umin < q->umax;
+    return model_ok && aug_ok && q->Q && q->R && q->QT && q->xref && q->x0 && q->umin < q->umax;
 }
 
-static lqk::NmpcPtrs nmpc_ptrs(const nmpc_problem *q)
+static lqk::NmpcPtrs nmpc_ptrs(const lq_plan *p, const nmpc_problem *q)
 {
     lqk::NmpcPtrs N;
-    N.nx = q->nx; N.nu = q->nu; N.T = q->T; N.h = q->h;
+    N.nx = q->nx; N.nu = q->nu; N.T = q->T; N.batch = p->batch; N.h = q->h;
     N.W = q->W; N.Bm = q->Bm; N.Q = q->Q; N.R = q->R; N.QT = q->QT; N.xref = q->xref; N.x0 = q->x0;
     N.umin = q->umin; N.umax = q->umax;
     N.model = q->model;
@@ -466,6 +469,7 @@ static lqk::NmpcWork nmpc_work(const lq_plan *p, void *workspace)
     char *w = (char *)workspace;
     auto D = [&](size_t o) { return (double *)(w + o); };
     lqk::NmpcWork Wk;
+    Wk.QTb = D(L.QTb);
     Wk.A = D(L.A); Wk.B = D(L.B); Wk.P = D(L.P); Wk.M = D(L.M); Wk.Rt = D(L.Rt); Wk.Rh = D(L.Rh); Wk.d = D(L.d);
     Wk.th = D(L.th); Wk.g = D(L.g); Wk.lam = D(L.lam); Wk.lamT = D(L.lamT); Wk.S = D(L.S); Wk.s = D(L.s);
     Wk.G = D(L.G); Wk.gm = D(L.gm); Wk.dx = D(L.dx); Wk.du = D(L.du); Wk.xc = D(L.xc); Wk.uc = D(L.uc);
@@ -476,7 +480,7 @@ static lqk::NmpcWork nmpc_work(const lq_plan *p, void *workspace)
 
 size_t nmpc_workspace_bytes(const lq_plan *p)
 {
-    if (!p || p->batch != 1) return 0;
+    if (!p || p->batch < 1) return 0;
     return nmpc_layout(p).total;
 }
 
@@ -486,7 +490,7 @@ lq_status nmpc_init(const lq_plan *p, const nmpc_problem *prob, const nmpc_state
     if (!nmpc_matches(p, prob) || !state || !state->x || !state->u || !state->scal) return LQ_ERR_ARG;
     if (prob->nx > 15 || prob->nu > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
     (void)workspace;
-    lqk::launch_nmpc_init((hipStream_t)stream, nmpc_ptrs(prob), state->x, state->u);
+    lqk::launch_nmpc_init((hipStream_t)stream, nmpc_ptrs(p, prob), state->x, state->u);
     return launched();
 }
 
@@ -497,22 +501,23 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     if (!nmpc_matches(p, prob) || !state || !state->x || !state->u || !state->scal) return LQ_ERR_ARG;
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    const lqk::NmpcPtrs N = nmpc_ptrs(prob);
+    const lqk::NmpcPtrs N = nmpc_ptrs(p, prob);
     const lqk::NmpcWork Wk = nmpc_work(p, workspace);
     char *ws = (char *)workspace;
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
-    lqk::launch_nmpc_clear(st, Wk.status, Wk.zero, prob->nx);
+    lqk::launch_nmpc_clear(st, N, Wk);
     // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
     lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x, state->u);
-    lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, Ya);
+    lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch, Ya);
     double *in = affine_scan(p, st, 1, Ya, Yb);
-    lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, in);
+    lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch,
+                              in);
     lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->x, state->u, state->scal);
-    // the LQ step
+    // the LQ step (all instances in one batched solve)
     lq_problem lp{};
     lp.A = Wk.A; lp.B = Wk.B; lp.c = nullptr; lp.Q = Wk.P; lp.R = Wk.Rt;
     lp.M = (prob->model == NMPC_TANH) ? nullptr : Wk.M;   // the tanh model has no mixed second derivative
-    lp.q = nullptr; lp.r = Wk.d; lp.QT = prob->QT; lp.qT = nullptr; lp.x0 = Wk.zero;
+    lp.q = nullptr; lp.r = Wk.d; lp.QT = Wk.QTb; lp.qT = nullptr; lp.x0 = Wk.zero;
     lq_value val{Wk.S, Wk.s, Wk.G, Wk.gm};
     const lq_status r = lq_solve(p, &lp, nullptr, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);
     if (r != LQ_OK) return r;
@@ -526,7 +531,16 @@ lq_status nmpc_admm_update(const lq_plan *p, const nmpc_problem *prob, const nmp
                            void *stream)
 {
     if (!nmpc_matches(p, prob) || !state || !state->u || !state->scal || !(prob->admm_rho > 0.0)) return LQ_ERR_ARG;
-    lqk::launch_admm_update((hipStream_t)stream, nmpc_ptrs(prob), state->u, state->scal, init);
+    lqk::launch_admm_update((hipStream_t)stream, nmpc_ptrs(p, prob), state->u, state->scal, init);
+    return launched();
+}
+
+lq_status nmpc_shift(const lq_plan *p, const nmpc_problem *prob, const nmpc_state *state, double *x0,
+                     double *u_applied, void *stream)
+{
+    if (!nmpc_matches(p, prob) || !state || !state->u || !x0 || !u_applied) return LQ_ERR_ARG;
+    if (prob->nx > 15 || prob->nu > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
+    lqk::launch_nmpc_shift((hipStream_t)stream, nmpc_ptrs(p, prob), x0, state->u, u_applied);
     return launched();
 }
 

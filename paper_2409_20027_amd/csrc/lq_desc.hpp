@@ -49,8 +49,11 @@ enum { NMPC_MU = 0, NMPC_ALPHA = 1, NMPC_NU = 2, NMPC_COST = 3, NMPC_PRED = 4, N
        NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_RP = 9, NMPC_RD = 10, NMPC_NSCAL = 11 };
 enum { MODEL_TANH = 0, MODEL_PENDULUM = 1, MODEL_CARTPOLE = 2 };
 
+// A batch of `batch` instances of equal sizes (nx, nu, T): per-instance arrays
+// are packed instance by instance (x0 [batch][nx], trajectories, workspace,
+// scalars [batch][NMPC_NSCAL]); model, costs, bounds and reference are shared.
 struct NmpcPtrs {
-    int nx, nu, T;
+    int nx, nu, T, batch;
     double h;
     const double *W, *Bm, *Q, *R, *QT, *xref, *x0;
     double umin, umax;
@@ -64,6 +67,7 @@ struct NmpcPtrs {
 
 // Newton workspace arrays (stage-major like the LQ problem arrays).
 struct NmpcWork {
+    double *QTb;   // Q_T replicated per instance (the LQ step takes one per instance)
     double *A, *B, *P, *M, *Rt, *Rh, *d, *th, *g, *lam, *lamT;
     double *S, *s, *G, *gm, *dx, *du, *xc, *uc, *zero;
     int32_t *status;

@@ -33,11 +33,13 @@ void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtr
                           const InstDesc *inst, const int32_t *seg_start, int batch, const double *Yfin);
 
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u);
-void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n);
+void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk);
+void launch_nmpc_shift(hipStream_t st, NmpcPtrs N, double *x0, double *u, double *uapp);
 void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u);
-void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y);
+void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                         const int32_t *seg_start, int batch, double *Y);
 void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
-                          const double *Yfin);
+                          const int32_t *seg_start, int batch, const double *Yfin);
 void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                               const double *scal);
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init);

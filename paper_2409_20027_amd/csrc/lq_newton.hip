@@ -82,14 +82,15 @@ LQK_DEV void model_jets(const NmpcPtrs &N, const double *xk, const double *uk, J
         cartpole_f<Jet<NZ, RT>, RT>(prm, z, f);
 }
 
-// A_k = I + h df/dx, B_k = h df/du from the jets (pendulum / cart-pole).
+// A_k = I + h df/dx, B_k = h df/du from the jets (pendulum / cart-pole);
+// gk = instance * T + stage indexes the packed workspace.
 template <int NZ>
-LQK_DEV void linearise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, const double *xk, const double *uk)
+LQK_DEV void linearise_model(const NmpcPtrs &N, const NmpcWork &Wk, int64_t gk, const double *xk, const double *uk)
 {
     constexpr int n = NZ - 1;
     Jet<NZ, double> f[n];
     model_jets<NZ, double>(N, xk, uk, f);
-    double *A = Wk.A + (int64_t)k * n * n, *B = Wk.B + (int64_t)k * n;
+    double *A = Wk.A + gk * n * n, *B = Wk.B + gk * n;
     for (int i = 0; i < n; ++i) {
         for (int j = 0; j < n; ++j) A[i * n + j] = (i == j ? 1.0 : 0.0) + N.h * f[i].g[j];
         B[i] = N.h * f[i].g[n];
@@ -99,7 +100,7 @@ LQK_DEV void linearise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, const
 // P_k = Q + h S_xx, M_k = h S_xu and h S_uu (added to R~ and Rh) of
 // S = lambda_{k+1}' f, in arithmetic type RT.
 template <int NZ, typename RT>
-LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, const double *xk, const double *uk,
+LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int64_t gk, const double *xk, const double *uk,
                               const double *l1)
 {
     constexpr int n = NZ - 1;
@@ -108,7 +109,7 @@ LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, cons
     Jet<NZ, RT> S = (RT)l1[0] * f[0];
     for (int i = 1; i < n; ++i) S = S + (RT)l1[i] * f[i];
     const RT h = (RT)N.h;
-    double *P = Wk.P + (int64_t)k * n * n, *M = Wk.M + (int64_t)k * n;
+    double *P = Wk.P + gk * n * n, *M = Wk.M + gk * n;
     for (int a = 0; a < n; ++a) {
         for (int b = 0; b < n; ++b) P[a * n + b] = (double)((RT)N.Q[a * n + b] + h * S.H[a][b]);
         M[a] = (double)(h * S.H[a][n]);
@@ -116,20 +117,21 @@ LQK_DEV RT quadraticise_model(const NmpcPtrs &N, const NmpcWork &Wk, int k, cons
     return h * S.H[n][n];
 }
 
-// Stage cost plus barrier at stage k (returns +inf if u is infeasible).
-// ADMM residual of stage k, input i: (a, b) = h(u) - z + v / rho for the rows
-// u_i - umax <= 0 and umin - u_i <= 0.
-LQK_DEV void admm_ab(const NmpcPtrs &N, int k, int i, double ui, double &a, double &b)
+// ADMM residual of global stage gk (instance * T + stage), input i:
+// (a, b) = h(u) - z + v / rho for the rows u_i - umax <= 0 and umin - u_i <= 0.
+LQK_DEV void admm_ab(const NmpcPtrs &N, int64_t gk, int i, double ui, double &a, double &b)
 {
     const int m = N.nu;
-    const double *zk = N.z + (int64_t)k * 2 * m, *vk = N.v + (int64_t)k * 2 * m;
+    const double *zk = N.z + gk * 2 * m, *vk = N.v + gk * 2 * m;
     a = (ui - N.umax) - zk[i] + vk[i] / N.rho;
     b = (N.umin - ui) - zk[m + i] + vk[m + i] / N.rho;
 }
 
 // Stage cost plus the barrier (+inf if u is infeasible), or plus the ADMM
-// augmentation when N.rho > 0.
-LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, const double *xk, const double *uk, double mu)
+// augmentation when N.rho > 0; k is the stage (reference row), gk the global
+// stage of the instance.
+LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, int64_t gk, const double *xk, const double *uk,
+                          double mu)
 {
     const double *rk = N.xref + (int64_t)k * n;
     double J = 0.0;
@@ -139,7 +141,7 @@ LQK_DEV double stage_cost(const NmpcPtrs &N, int n, int m, int k, const double *
         for (int j = 0; j < m; ++j) J += 0.5 * uk[i] * N.R[i * m + j] * uk[j];
         if (N.rho > 0.0) {
             double a, b;
-            admm_ab(N, k, i, uk[i], a, b);
+            admm_ab(N, gk, i, uk[i], a, b);
             J += 0.5 * N.rho * (a * a + b * b);
             continue;
         }
@@ -160,8 +162,8 @@ LQK_DEV double terminal_cost(const NmpcPtrs &N, int n, int T, const double *xT)
 }
 
 // Nonlinear rollout x_{k+1} = x_k + h f(x_k, u_k + du_k) from x0 (du may be
-// null), one lane: the recursion is sequential in k.  Writes x (T+1 rows)
-// and, if uout is set, the controls used.
+// null): the recursion is sequential in k, so one lane per instance.  Writes
+// x (T+1 rows) and, if uout is set, the controls used.
 //
 // Pendulum and cart-pole (nu = 1): the raw u_{k+1} and du_{k+1} are loaded
 // (index clamped, no branch) while step k is computed and summed one step
@@ -172,12 +174,17 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *_
                                                      double *__restrict__ uout)
 {
     constexpr int n = (MODEL == MODEL_PENDULUM) ? 2 : 4;
-    if (threadIdx.x != 0) return;
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= N.batch) return;
     const int T = N.T;
+    u += (int64_t)b * T;
+    if (DU) du += (int64_t)b * T;
+    xout += (int64_t)b * (T + 1) * n;
+    if (uout) uout += (int64_t)b * T;
     double x[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        x[i] = N.x0[i];
+        x[i] = N.x0[(int64_t)b * n + i];
         xout[i] = x[i];
     }
     if (T <= 0) return;
@@ -212,14 +219,19 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const doub
 {
     __shared__ double sW[NXMAX * NXMAX], sB[NXMAX * NUMAX];
     const int n = N.nx, m = N.nu, T = N.T;
+    const int b = blockIdx.x;   // one instance per block
     for (int i = threadIdx.x; i < n * n; i += 64) sW[i] = N.W[i];
     for (int i = threadIdx.x; i < n * m; i += 64) sB[i] = N.Bm[i];
     __syncthreads();
     if (threadIdx.x != 0) return;
+    u += (int64_t)b * T * m;
+    if (du) du += (int64_t)b * T * m;
+    xout += (int64_t)b * (T + 1) * n;
+    if (uout) uout += (int64_t)b * T * m;
     double x[NXMAX];
 #pragma unroll
     for (int i = 0; i < NXMAX; ++i) {
-        x[i] = (i < n) ? N.x0[i] : 0.0;
+        x[i] = (i < n) ? N.x0[(int64_t)b * n + i] : 0.0;
         if (i < n) xout[i] = x[i];
     }
     for (int k = 0; k < T; ++k) {
@@ -250,34 +262,41 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const doub
     }
 }
 
-// Step 0: clear the internal LQ status and the LQ's zero initial state.
-__global__ void k_nmpc_clear(int32_t *st, double *zero, int n)
+// Step 0 (one block per instance): clear the internal LQ status, the LQ's
+// zero initial state and replicate Q_T.
+__global__ __launch_bounds__(64) void k_nmpc_clear(NmpcPtrs N, NmpcWork Wk)
 {
-    if (threadIdx.x == 0) st[0] = 0;
-    if (threadIdx.x < n) zero[threadIdx.x] = 0.0;
+    const int b = blockIdx.x, n = N.nx;
+    if (threadIdx.x == 0) Wk.status[b] = 0;
+    for (int i = threadIdx.x; i < n; i += 64) Wk.zero[(int64_t)b * n + i] = 0.0;
+    for (int i = threadIdx.x; i < n * n; i += 64) Wk.QTb[(int64_t)b * n * n + i] = N.QT[i];
 }
 
-// Step 1 (one lane per stage), arithmetic type RT, results stored in FP64.
+// Step 1 (one lane per stage of every instance), arithmetic type RT, results
+// stored in FP64.
 template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = N.nx, m = N.nu;
-    if (k > N.T) return;
-    const double *xk = x + (int64_t)k * n;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = N.nx, m = N.nu, T = N.T;
+    if (idx >= (int64_t)N.batch * (T + 1)) return;
+    const int b = (int)(idx / (T + 1)), k = (int)(idx - (int64_t)b * (T + 1));
+    const int64_t gk = (int64_t)b * T + k;   // packed stage index (k < T)
+    const double *xk = x + ((int64_t)b * (T + 1) + k) * n;
     const double *rk = N.xref + (int64_t)k * n;
-    if (k == N.T) {   // terminal co-state lambda_T = Q_T (x_T - ref_T)
+    if (k == T) {   // terminal co-state lambda_T = Q_T (x_T - ref_T)
         for (int i = 0; i < n; ++i) {
             RT v = 0;
             for (int j = 0; j < n; ++j) v += (RT)N.QT[i * n + j] * ((RT)xk[j] - (RT)rk[j]);
-            Wk.lamT[i] = (double)v;
+            Wk.lamT[(int64_t)b * n + i] = (double)v;
         }
         return;
     }
+    const double *uk = u + gk * m;
     if (N.model == MODEL_PENDULUM) {
-        linearise_model<3>(N, Wk, k, xk, u + (int64_t)k * m);
+        linearise_model<3>(N, Wk, gk, xk, uk);
     } else if (N.model == MODEL_CARTPOLE) {
-        linearise_model<5>(N, Wk, k, xk, u + (int64_t)k * m);
+        linearise_model<5>(N, Wk, gk, xk, uk);
     } else {
         RT th[NXMAX];
         const RT h = (RT)N.h;
@@ -285,27 +304,28 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
             RT z = 0;
             for (int j = 0; j < n; ++j) z += (RT)N.W[i * n + j] * (RT)xk[j];
             th[i] = tanh(z);
-            Wk.th[(int64_t)k * n + i] = (double)th[i];
+            Wk.th[gk * n + i] = (double)th[i];
         }
-        double *A = Wk.A + (int64_t)k * n * n;
+        double *A = Wk.A + gk * n * n;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j)
                 A[i * n + j] = (double)((i == j ? (RT)1 : (RT)0) + h * ((RT)1 - th[i] * th[i]) * (RT)N.W[i * n + j]);
-        double *B = Wk.B + (int64_t)k * n * m;
+        double *B = Wk.B + gk * n * m;
         for (int i = 0; i < n * m; ++i) B[i] = (double)(h * (RT)N.Bm[i]);
     }
     for (int i = 0; i < n; ++i) {
         RT v = 0;
         for (int j = 0; j < n; ++j) v += (RT)N.Q[i * n + j] * ((RT)xk[j] - (RT)rk[j]);
-        Wk.g[(int64_t)k * n + i] = (double)v;
+        Wk.g[gk * n + i] = (double)v;
     }
 }
 
-// Co-state map M_k = [[A_k', g_k], [0, 1]] from the linearisation: R(M_k).
+// Co-state map M_k = [[A_k', g_k], [0, 1]] from the linearisation: R(M_k)
+// (the workspace is packed like the LQ arrays: instance offsets d.oA, d.oc).
 LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k)
 {
     const int n = d.n, c = tcol();
-    const double *A = Wk.A + (int64_t)k * n * n, *g = Wk.g + (int64_t)k * n;
+    const double *A = Wk.A + d.oA + (int64_t)k * n * n, *g = Wk.g + d.oc + (int64_t)k * n;
     Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -326,7 +346,7 @@ LQK_DEV Tile costate_map(const NmpcWork &Wk, const InstDesc &d, int k)
 LQK_DEV Tile costate_map_t(const NmpcWork &Wk, const InstDesc &d, int k)
 {
     const int n = d.n, c = tcol();
-    const double *A = Wk.A + (int64_t)k * n * n, *g = Wk.g + (int64_t)k * n;
+    const double *A = Wk.A + d.oA + (int64_t)k * n * n, *g = Wk.g + d.oc + (int64_t)k * n;
     Tile t;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -347,13 +367,15 @@ LQK_DEV Tile costate_map_t(const NmpcWork &Wk, const InstDesc &d, int k)
 // M_{k1-1} kept as Psi'; the block of the last segment writes the terminal
 // element [[0, lambda_T], [0, 1]].
 template <int NK, int PR>
-__global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst, double *Y)
+__global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst,
+                                                     const int32_t *__restrict__ seg_start, int batch, double *Y)
 {
     __shared__ double lds[SLOT];
-    const InstDesc d = inst[0];
-    const int s = blockIdx.x;
+    const int gs = blockIdx.x;
+    const InstDesc d = inst[find_inst(seg_start, batch, gs)];
+    const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT, d.n, d.n, d.n));
+    if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT + d.on, d.n, d.n, d.n));
     if (s == 0) return;
     Tile PsiT = tident(d.n + 1);
     for (int k = k0; k < k1; ++k) PsiT = tnz<NK, PR>(costate_map(Wk, d, k), PsiT);   // (Psi M_k)'
@@ -363,17 +385,20 @@ __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc
 // Step 2c: co-states inside each segment from lambda at its right end.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDesc *__restrict__ inst,
+                                                      const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Yfin)
 {
-    const InstDesc d = inst[0];
-    const int s = blockIdx.x;
+    const int gs = blockIdx.x;
+    const InstDesc d = inst[find_inst(seg_start, batch, gs)];
+    const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n;
+    double *lam = Wk.lam + d.os;
     Tile L = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);
-    if (s == d.nseg - 1) store_vec(Wk.lam + (int64_t)d.T * n, L, n, n);
+    if (s == d.nseg - 1) store_vec(lam + (int64_t)d.T * n, L, n, n);
     for (int k = k1 - 1; k >= k0; --k) {
         L = tnz<NK, PR>(costate_map_t(Wk, d, k), L);   // M_k L
-        store_vec(Wk.lam + (int64_t)k * n, L, n, n);
+        store_vec(lam + (int64_t)k * n, L, n, n);
     }
 }
 
@@ -384,20 +409,23 @@ template <typename RT>
 __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                                                            const double *scal)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = N.nx, m = N.nu;
-    if (k >= N.T) return;
+    const int64_t gk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // instance * T + stage
+    const int n = N.nx, m = N.nu, T = N.T;
+    if (gk >= (int64_t)N.batch * T) return;
+    const int b = (int)(gk / T);
+    scal += (int64_t)b * NMPC_NSCAL;
     const double mu = scal[NMPC_MU], alpha = scal[NMPC_ALPHA];
-    const double *l1 = Wk.lam + (int64_t)(k + 1) * n;
-    const double *uk = u + (int64_t)k * m;
+    const double *l1 = Wk.lam + (gk + b + 1) * n;   // lambda_{k+1}; T + 1 rows per instance
+    const double *uk = u + gk * m;
+    const double *xk = x + (gk + b) * n;
     double huu = 0.0;   // h lambda' d2f/du2 (m = 1 for the pendulum and cart-pole)
     if (N.model == MODEL_PENDULUM) {
-        huu = (double)quadraticise_model<3, RT>(N, Wk, k, x + (int64_t)k * n, uk, l1);
+        huu = (double)quadraticise_model<3, RT>(N, Wk, gk, xk, uk, l1);
     } else if (N.model == MODEL_CARTPOLE) {
-        huu = (double)quadraticise_model<5, RT>(N, Wk, k, x + (int64_t)k * n, uk, l1);
+        huu = (double)quadraticise_model<5, RT>(N, Wk, gk, xk, uk, l1);
     } else {
-        const double *th = Wk.th + (int64_t)k * n;
-        double *P = Wk.P + (int64_t)k * n * n;
+        const double *th = Wk.th + gk * n;
+        double *P = Wk.P + gk * n * n;
         RT Pl[NXMAX * NXMAX];
         for (int i = 0; i < n * n; ++i) Pl[i] = (RT)N.Q[i];
         for (int i = 0; i < n; ++i) {
@@ -408,8 +436,8 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
         }
         for (int i = 0; i < n * n; ++i) P[i] = (double)Pl[i];
     }
-    double *Rt = Wk.Rt + (int64_t)k * m * m;
-    double *Rh = Wk.Rh + (int64_t)k * m * m;
+    double *Rt = Wk.Rt + gk * m * m;
+    double *Rh = Wk.Rh + gk * m * m;
     for (int i = 0; i < m * m; ++i) Rh[i] = N.R[i];
     for (int i = 0; i < m; ++i) {
         const double a = N.umax - uk[i], b = uk[i] - N.umin;
@@ -419,24 +447,24 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     for (int i = 0; i < m * m; ++i) Rt[i] = Rh[i];
     for (int i = 0; i < m; ++i) Rt[i * m + i] += alpha;
     // the gradient d_k stays FP64 (mixed precision only approximates the Hessian)
-    const double *B = Wk.B + (int64_t)k * n * m;
+    const double *B = Wk.B + gk * n * m;
     for (int i = 0; i < m; ++i) {
         double v = 0.0;
         for (int j = 0; j < m; ++j) v += N.R[i * m + j] * uk[j];
         const double uu = uk[i];
         if (N.rho > 0.0) {
-            double a, b;
-            admm_ab(N, k, i, uu, a, b);
-            v += N.rho * (a - b);
+            double ra, rb;
+            admm_ab(N, gk, i, uu, ra, rb);
+            v += N.rho * (ra - rb);
         } else {
             v += mu * (1.0 / (N.umax - uu) - 1.0 / (uu - N.umin));
         }
         for (int j = 0; j < n; ++j) v += B[j * m + i] * l1[j];
-        Wk.d[(int64_t)k * m + i] = v;
+        Wk.d[gk * m + i] = v;
     }
 }
 
-// Step 5b (one block): data-parallel sums over the stages with a fixed
+// Step 5b (one block per instance): data-parallel sums over the stages with a fixed
 // reduction tree -- the predicted decrease of the expansion (alpha excluded),
 // |d|_inf, J_mu of the nominal and of the candidate -- then the decision
 // (step 6): gain ratio rho = (J_mu(u) - J_mu(u + du)) / pred, accept if
@@ -447,30 +475,37 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
                                                      double *scal)
 {
     __shared__ double sp[RED], s0[RED], s1[RED], sg[RED];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, b = blockIdx.x;
     const int n = N.nx, m = N.nu, T = N.T;
+    scal += (int64_t)b * NMPC_NSCAL;
+    const int64_t s0k = (int64_t)b * T;              // first packed stage of the instance
+    const int64_t xo = (int64_t)b * (T + 1) * n;    // its trajectory rows
+    x += xo;
+    u += s0k * m;
+    const double *xc = Wk.xc + xo, *uc = Wk.uc + s0k * m, *dx = Wk.dx + xo;
     const double mu = scal[NMPC_MU];
     double pred = 0.0, J0 = 0.0, J1 = 0.0, gmax = 0.0;
     for (int k = t; k < T; k += RED) {
-        const double *dxk = Wk.dx + (int64_t)k * n, *duk = Wk.du + (int64_t)k * m;
+        const int64_t gk = s0k + k;
+        const double *dxk = dx + (int64_t)k * n, *duk = Wk.du + gk * m;
         double lin = 0.0, qf = 0.0;
         for (int i = 0; i < m; ++i) {
-            lin += Wk.d[(int64_t)k * m + i] * duk[i];
-            gmax = fmax(gmax, fabs(Wk.d[(int64_t)k * m + i]));
+            lin += Wk.d[gk * m + i] * duk[i];
+            gmax = fmax(gmax, fabs(Wk.d[gk * m + i]));
         }
-        const double *P = Wk.P + (int64_t)k * n * n, *Rh = Wk.Rh + (int64_t)k * m * m;
+        const double *P = Wk.P + gk * n * n, *Rh = Wk.Rh + gk * m * m;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) qf += dxk[i] * P[i * n + j] * dxk[j];
         if (N.model != MODEL_TANH) {
-            const double *Mk = Wk.M + (int64_t)k * n * m;
+            const double *Mk = Wk.M + gk * n * m;
             for (int i = 0; i < n; ++i)
                 for (int j = 0; j < m; ++j) qf += 2.0 * dxk[i] * Mk[i * m + j] * duk[j];
         }
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j) qf += duk[i] * Rh[i * m + j] * duk[j];
         pred += lin + 0.5 * qf;
-        J0 += stage_cost(N, n, m, k, x + (int64_t)k * n, u + (int64_t)k * m, mu);
-        J1 += stage_cost(N, n, m, k, Wk.xc + (int64_t)k * n, Wk.uc + (int64_t)k * m, mu);
+        J0 += stage_cost(N, n, m, k, gk, x + (int64_t)k * n, u + (int64_t)k * m, mu);
+        J1 += stage_cost(N, n, m, k, gk, xc + (int64_t)k * n, uc + (int64_t)k * m, mu);
     }
     sp[t] = pred;
     s0[t] = J0;
@@ -488,7 +523,7 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
     if (t != 0) return;
     pred = sp[0];
     {
-        const double *dxT = Wk.dx + (int64_t)T * n;
+        const double *dxT = dx + (int64_t)T * n;
         double qf = 0.0;
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) qf += dxT[i] * N.QT[i * n + j] * dxT[j];
@@ -496,8 +531,8 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
     }
     pred = -pred;
     J0 = s0[0] + terminal_cost(N, n, T, x + (int64_t)T * n);
-    J1 = s1[0] + terminal_cost(N, n, T, Wk.xc + (int64_t)T * n);
-    const bool lq_ok = (Wk.status[0] == 0);
+    J1 = s1[0] + terminal_cost(N, n, T, xc + (int64_t)T * n);
+    const bool lq_ok = (Wk.status[b] == 0);
     if (!lq_ok) {
         pred = 0.0;
         J1 = INFINITY;
@@ -536,8 +571,11 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
 __global__ __launch_bounds__(RED) void k_admm_update(NmpcPtrs N, const double *u, double *scal, int init)
 {
     __shared__ double sp[RED], sd[RED];
-    const int t = threadIdx.x, m = N.nu;
+    const int t = threadIdx.x, m = N.nu, b = blockIdx.x;   // one block per instance
     const int64_t cnt = (int64_t)N.T * 2 * m;
+    u += (int64_t)b * N.T * m;
+    double *z = N.z + (int64_t)b * cnt, *v = N.v + (int64_t)b * cnt;
+    scal += (int64_t)b * NMPC_NSCAL;
     double rp = 0.0, rd = 0.0;
     for (int64_t o = t; o < cnt; o += RED) {
         const int64_t k = o / (2 * m);
@@ -545,15 +583,15 @@ __global__ __launch_bounds__(RED) void k_admm_update(NmpcPtrs N, const double *u
         const double ui = u[k * m + (i < m ? i : i - m)];
         const double w = (i < m) ? ui - N.umax : N.umin - ui;
         if (init) {
-            N.z[o] = fmin(0.0, w);
-            N.v[o] = 0.0;
+            z[o] = fmin(0.0, w);
+            v[o] = 0.0;
             continue;
         }
-        const double zn = fmin(0.0, w + N.v[o] / N.rho);
-        rd = fmax(rd, fabs(zn - N.z[o]));
+        const double zn = fmin(0.0, w + v[o] / N.rho);
+        rd = fmax(rd, fabs(zn - z[o]));
         rp = fmax(rp, fabs(w - zn));
-        N.z[o] = zn;
-        N.v[o] += N.rho * (w - zn);
+        z[o] = zn;
+        v[o] += N.rho * (w - zn);
     }
     sp[t] = rp;
     sd[t] = rd;
@@ -570,28 +608,52 @@ __global__ __launch_bounds__(RED) void k_admm_update(NmpcPtrs N, const double *u
     }
 }
 
-// Step 7: on acceptance the candidate becomes the nominal.
+// Step 7: on acceptance the candidate becomes the nominal (grid y: instance).
 __global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork Wk, double *x, double *u,
                                                      const double *scal)
 {
-    if (scal[NMPC_ACCEPTED] == 0.0) return;
+    const int b = blockIdx.y;
+    if (scal[(int64_t)b * NMPC_NSCAL + NMPC_ACCEPTED] == 0.0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)(N.T + 1) * N.nx, nu = (int64_t)N.T * N.nu;
-    if (i < nx) x[i] = Wk.xc[i];
-    if (i < nu) u[i] = Wk.uc[i];
+    if (i < nx) x[b * nx + i] = Wk.xc[b * nx + i];
+    if (i < nu) u[b * nu + i] = Wk.uc[b * nu + i];
+}
+
+// Receding horizon (one lane per instance): the plant takes one step with the
+// first control, x0 <- x0 + h f(x0, u_0) (u_0 is also written to uapp), and
+// the controls shift by one stage for the next solve's warm start (the last
+// one is kept).
+__global__ __launch_bounds__(64) void k_nmpc_shift(NmpcPtrs N, double *x0, double *u, double *uapp)
+{
+    const int b = blockIdx.x * 64 + threadIdx.x;
+    if (b >= N.batch) return;
+    const int n = N.nx, m = N.nu, T = N.T;
+    double *xb = x0 + (int64_t)b * n, *ub = u + (int64_t)b * T * m;
+    double xc[NXMAX], u0[NUMAX], xn[NXMAX];
+    for (int i = 0; i < n; ++i) xc[i] = xb[i];
+    for (int i = 0; i < m; ++i) {
+        u0[i] = ub[i];
+        uapp[(int64_t)b * m + i] = u0[i];
+    }
+    f_step(N, n, m, xc, u0, xn);
+    for (int i = 0; i < n; ++i) xb[i] = xn[i];
+    for (int k = 0; k + 1 < T; ++k)
+        for (int i = 0; i < m; ++i) ub[(int64_t)k * m + i] = ub[(int64_t)(k + 1) * m + i];
 }
 
 
 static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, const double *du, double *xout,
                            double *uout)
 {
-#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(1), dim3(64), 0, st, N, u, du, xout, uout)
+    const unsigned lanes = (unsigned)((N.batch + 63) / 64);
+#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(lanes), dim3(64), 0, st, N, u, du, xout, uout)
     if (N.model == MODEL_PENDULUM) {
         if (du) RL(MODEL_PENDULUM, true); else RL(MODEL_PENDULUM, false);
     } else if (N.model == MODEL_CARTPOLE) {
         if (du) RL(MODEL_CARTPOLE, true); else RL(MODEL_CARTPOLE, false);
     } else {
-        hipLaunchKernelGGL(k_nmpc_rollout_tanh, dim3(1), dim3(64), 0, st, N, u, du, xout, uout);
+        hipLaunchKernelGGL(k_nmpc_rollout_tanh, dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout);
     }
 #undef RL
 }
@@ -599,51 +661,59 @@ void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
 {
     launch_rollout(st, N, u, nullptr, x, nullptr);
 }
-void launch_nmpc_clear(hipStream_t st, int32_t *status, double *zero, int n)
+void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk)
 {
-    hipLaunchKernelGGL(k_nmpc_clear, dim3(1), dim3(64), 0, st, status, zero, n);
+    hipLaunchKernelGGL(k_nmpc_clear, dim3(N.batch), dim3(64), 0, st, N, Wk);
+}
+void launch_nmpc_shift(hipStream_t st, NmpcPtrs N, double *x0, double *u, double *uapp)
+{
+    hipLaunchKernelGGL(k_nmpc_shift, dim3((N.batch + 63) / 64), dim3(64), 0, st, N, x0, u, uapp);
 }
 void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u)
 {
     // The Jacobians define the co-states and hence the gradient, which sets
     // the point Newton converges to: FP64 in every precision mode.
     (void)pr;
-    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((N.T + 1 + 255) / 256), dim3(256), 0, st, N, Wk, x, u);
+    const int64_t cnt = (int64_t)N.batch * (N.T + 1);
+    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, Wk, x, u);
 }
-void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst, double *Y)
+void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                         const int32_t *seg_start, int batch, double *Y)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_costate_fold<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, Y)
+#define CALL(K, R) hipLaunchKernelGGL((k_costate_fold<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, seg_start, batch, Y)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
-                          const double *Yfin)
+                          const int32_t *seg_start, int batch, const double *Yfin)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_costate_apply<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, Yfin)
+#define CALL(K, R) \
+    hipLaunchKernelGGL((k_costate_apply<K, R>), dim3(grid), dim3(64), 0, st, Wk, inst, seg_start, batch, Yfin)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                               const double *scal)
 {
+    const unsigned g = (unsigned)(((int64_t)N.batch * N.T + 255) / 256);
     if (pr)
-        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, x, u, scal);
+        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3(g), dim3(256), 0, st, N, Wk, x, u, scal);
     else
-        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3((N.T + 255) / 256), dim3(256), 0, st, N, Wk, x, u, scal);
+        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3(g), dim3(256), 0, st, N, Wk, x, u, scal);
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
     launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc);
-    hipLaunchKernelGGL(k_nmpc_reduce, dim3(1), dim3(RED), 0, st, N, Wk, x, u, scal);
+    hipLaunchKernelGGL(k_nmpc_reduce, dim3(N.batch), dim3(RED), 0, st, N, Wk, x, u, scal);
 }
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init)
 {
-    hipLaunchKernelGGL(k_admm_update, dim3(1), dim3(RED), 0, st, N, u, scal, init);
+    hipLaunchKernelGGL(k_admm_update, dim3(N.batch), dim3(RED), 0, st, N, u, scal, init);
 }
 void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal)
 {
     const int64_t cnt = std::max((int64_t)(N.T + 1) * N.nx, (int64_t)N.T * N.nu);
-    hipLaunchKernelGGL(k_nmpc_commit, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, Wk, x, u, scal);
+    hipLaunchKernelGGL(k_nmpc_commit, dim3((unsigned)((cnt + 255) / 256), N.batch), dim3(256), 0, st, N, Wk, x, u, scal);
 }
 
 }  // namespace lqk

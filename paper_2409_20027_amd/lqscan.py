@@ -385,7 +385,9 @@ _lib.newton_step.restype = ctypes.c_int
 _lib.nmpc_admm_update.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), ctypes.c_int32,
                                   _P]
 _lib.nmpc_admm_update.restype = ctypes.c_int
-EXPORTED = EXPORTED + ("nmpc_workspace_bytes", "nmpc_init", "newton_step", "nmpc_admm_update")
+_lib.nmpc_shift.argtypes = [_plan_p, ctypes.POINTER(NMPCProblemC), ctypes.POINTER(NMPCStateC), _P, _P, _P]
+_lib.nmpc_shift.restype = ctypes.c_int
+EXPORTED = EXPORTED + ("nmpc_workspace_bytes", "nmpc_init", "newton_step", "nmpc_admm_update", "nmpc_shift")
 
 
 def nmpc_workspace_bytes(plan: Plan) -> int:
@@ -402,55 +404,77 @@ def newton_step(plan, prob_c, state_c, workspace, status=None, stream=None):
                                            _ptr(workspace), _ptr(status), _stream(stream)))
 
 
+def nmpc_shift(plan, prob_c, state_c, x0, u_applied, stream=None):
+    _check("nmpc_shift", _lib.nmpc_shift(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c), _ptr(x0),
+                                         _ptr(u_applied), _stream(stream)))
+
+
 def nmpc_admm_update(plan, prob_c, state_c, init, stream=None):
     _check("nmpc_admm_update", _lib.nmpc_admm_update(plan.handle, ctypes.byref(prob_c), ctypes.byref(state_c),
                                                      int(init), _stream(stream)))
 
 
 class NewtonMPC:
-    """Interior-point Newton solver for x' = x + h f(x, u) with |u| bounded.
+    """Interior-point / ADMM Newton solver for x' = x + h f(x, u) with |u| bounded.
 
     `p` has numpy fields nx, nu, T, h, W, Bm, Q, R, QT, xref, x0, u0, umin,
     umax and optionally model (NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE) and
     param (the model constants); W and Bm are read by the tanh model only.
-    All iterations run on the GPU through newton_step; the host sets the
-    barrier weight and, in ip_solve, reads the gradient norm after each
-    iteration to end a barrier level.
+    A batch of problems that differ only in x0 ([B, nx]) and u0 ([B, T, nu])
+    is solved at once (every decision per instance).  All iterations run on
+    the GPU through newton_step; the host sets the barrier weight and, in
+    ip_solve / admm_solve, reads the gradient norms after each iteration to end
+    a barrier level (when every instance has converged).
     """
 
     def __init__(self, p, device="cuda", seg_len=0, precision="fp64", mode="scan"):
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
         self.p = p
         model = int(getattr(p, "model", NMPC_TANH) or 0)
-        self.plan = Plan([p.nx], [p.nu], [p.T], seg_len=seg_len, precision=precision, mode=mode)
-        names = ("Q", "R", "QT", "xref", "x0") + (("W", "Bm") if model == NMPC_TANH else ())
+        self.B = 1 if np.ndim(p.x0) == 1 else int(np.shape(p.x0)[0])
+        B = self.B
+        self.plan = Plan([p.nx] * B, [p.nu] * B, [p.T] * B, seg_len=seg_len, precision=precision, mode=mode)
+        names = ("Q", "R", "QT", "xref") + (("W", "Bm") if model == NMPC_TANH else ())
         self.dev = {k: t(getattr(p, k)) for k in names}
-        self.x = torch.zeros((p.T + 1) * p.nx, dtype=torch.float64, device=device)
-        self.u0 = t(p.u0).reshape(-1).clone()
+        self.x0 = t(p.x0).reshape(-1).clone()
+        self.dev["x0"] = self.x0
+        self.x = torch.zeros(B * (p.T + 1) * p.nx, dtype=torch.float64, device=device)
+        u0 = np.asarray(p.u0, np.float64)
+        if B > 1 and u0.ndim == 2:
+            u0 = np.broadcast_to(u0, (B,) + u0.shape)
+        self.u0 = t(np.ascontiguousarray(u0)).reshape(-1).clone()
         self.u = self.u0.clone()
-        self.scal = torch.zeros(NMPC_NSCAL, dtype=torch.float64, device=device)
+        self.scal = torch.zeros(B * NMPC_NSCAL, dtype=torch.float64, device=device)
+        self._sc = self.scal.view(B, NMPC_NSCAL)
         self.ws = torch.empty(nmpc_workspace_bytes(self.plan), dtype=torch.uint8, device=device)
         d = self.dev
         prm = getattr(p, "param", None)
         prm = (ctypes.c_double * 4)(*([float(v) for v in prm] if prm is not None else [0.0] * 4))
         self.prob_c = NMPCProblemC(p.nx, p.nu, p.T, float(p.h), _f64(d.get("W")), _f64(d.get("Bm")), _f64(d["Q"]),
-                                   _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(d["x0"]),
+                                   _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(self.x0),
                                    float(p.umin), float(p.umax), model, prm)
         self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
 
-    def init(self, alpha0, nu0):
-        """Nominal controls back to u0 (and x to their rollout), damping to (alpha0, nu0)."""
-        self.u.copy_(self.u0)
+    def _shape(self, a, rows, cols):
+        a = a.cpu().numpy()
+        return a.reshape(rows, cols) if self.B == 1 else a.reshape(self.B, rows, cols)
+
+    def init(self, alpha0, nu0, reset_u=True):
+        """Nominal controls back to u0 (unless reset_u is False), x to their rollout,
+        damping to (alpha0, nu0)."""
+        if reset_u:
+            self.u.copy_(self.u0)
         self.scal.zero_()
-        self.scal[NMPC_ALPHA] = alpha0
-        self.scal[NMPC_NU] = nu0
+        self._sc[:, NMPC_ALPHA] = alpha0
+        self._sc[:, NMPC_NU] = nu0
         nmpc_init(self.plan, self.prob_c, self.state_c, self.ws)
 
     def step(self, mu):
-        self.scal[NMPC_MU] = mu
+        self._sc[:, NMPC_MU] = mu
         newton_step(self.plan, self.prob_c, self.state_c, self.ws)
 
     def run(self, mu_levels, iters, alpha0, nu0):
+        """Fixed iterations per barrier level; traces of instance 0."""
         self.init(alpha0, nu0)
         n_it = len(mu_levels) * iters
         before = torch.zeros(n_it, NMPC_NSCAL, dtype=torch.float64, device=self.x.device)
@@ -458,89 +482,141 @@ class NewtonMPC:
         it = 0
         for mu in mu_levels:
             for _ in range(iters):
-                self.scal[NMPC_MU] = mu
-                before[it].copy_(self.scal)
+                self._sc[:, NMPC_MU] = mu
+                before[it].copy_(self._sc[0])
                 newton_step(self.plan, self.prob_c, self.state_c, self.ws)
-                after[it].copy_(self.scal)
+                after[it].copy_(self._sc[0])
                 it += 1
         torch.cuda.synchronize()
         a = after.cpu().numpy()
-        return {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
-                "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
+        return {"u": self._shape(self.u, self.p.T, self.p.nu), "x": self._shape(self.x, self.p.T + 1, self.p.nx),
                 "cost": a[:, NMPC_COST], "accept": a[:, NMPC_ACCEPTED] > 0.5,
                 "alpha": before.cpu().numpy()[:, NMPC_ALPHA], "pred": a[:, NMPC_PRED], "rho": a[:, NMPC_RHO]}
 
-    def _newton_level(self, mu, tol, max_iter, host, rows):
+    def _capture_step(self):
+        """newton_step captured once into a HIP graph (its kernel sequence, replayed per
+        iteration; the barrier weight and every decision live in device memory).  One eager
+        step first (the state is reset afterwards by init)."""
+        newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+        torch.cuda.current_stream().wait_stream(side)
+        return g
+
+    def _newton_level(self, mu, tol, max_iter, host, rows, graph=None):
         """Newton iterations until the one that starts from |dJ/du|_inf <= tol (or max_iter)."""
         li = 0
+        hv = host.view(self.B, NMPC_NSCAL)
         while li < max_iter:
-            self.scal[NMPC_MU] = mu
-            newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+            self._sc[:, NMPC_MU] = mu
+            if graph is not None:
+                graph.replay()
+            else:
+                newton_step(self.plan, self.prob_c, self.state_c, self.ws)
             host.copy_(self.scal, non_blocking=True)
             torch.cuda.current_stream().synchronize()
             li += 1
             if rows is not None:
-                rows.append((mu, float(host[NMPC_COST]), float(host[NMPC_GRAD]), float(host[NMPC_ACCEPTED]),
-                             float(host[NMPC_PRED])))
-            if float(host[NMPC_GRAD]) <= tol:
+                rows.append((mu, float(hv[0, NMPC_COST]), float(hv[0, NMPC_GRAD]), float(hv[0, NMPC_ACCEPTED]),
+                             float(hv[0, NMPC_PRED])))
+            if float(hv[:, NMPC_GRAD].max()) <= tol:
                 break
         return li
 
-    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0):
+    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True):
         """ADMM of Sec. II-C for the control box with newton_step as the inner solver:
         z = min(0, h(u0)), v = 0; repeat Newton iterations on J_AD to |dJ_AD/du|_inf <= tol
         (or max_iter), then nmpc_admm_update, until |r_p|_inf, |r_d|_inf <= eps or max_admm.
-        rho is the weight of each stage's augmentation term.  Returns dict(u, x, z, v,
-        admm_iters, newton_iters, inner, rp, rd)."""
+        rho is the weight of each stage's augmentation term.  graph: replay newton_step from a
+        HIP graph captured once per solve.  Returns dict(u, x, z, v, admm_iters, newton_iters,
+        inner, rp, rd)."""
         dev = self.x.device
-        z = torch.zeros(self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
+        z = torch.zeros(self.B * self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
         v = torch.zeros_like(z)
         self.prob_c.admm_rho = float(rho)
         self.prob_c.admm_z = _f64(z)
         self.prob_c.admm_v = _f64(v)
         try:
+            g = self._capture_step() if graph else None
             self.init(alpha0, nu0)
             nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
-            host = torch.empty(NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
+            host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
+            hv = host.view(self.B, NMPC_NSCAL)
             inner, rps, rds = [], [], []
             for _ in range(max_admm):
-                inner.append(self._newton_level(0.0, tol, max_iter, host, None))
+                inner.append(self._newton_level(0.0, tol, max_iter, host, None, g))
                 nmpc_admm_update(self.plan, self.prob_c, self.state_c, 0)
                 host.copy_(self.scal, non_blocking=True)
                 torch.cuda.current_stream().synchronize()
-                rps.append(float(host[NMPC_RP]))
-                rds.append(float(host[NMPC_RD]))
+                rps.append(float(hv[:, NMPC_RP].max()))
+                rds.append(float(hv[:, NMPC_RD].max()))
                 if rps[-1] <= eps and rds[-1] <= eps:
                     break
         finally:
             self.prob_c.admm_rho = 0.0
             self.prob_c.admm_z = None
             self.prob_c.admm_v = None
-        return {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
-                "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
-                "z": z.cpu().numpy().reshape(self.p.T, 2 * self.p.nu),
-                "v": v.cpu().numpy().reshape(self.p.T, 2 * self.p.nu),
+        return {"u": self._shape(self.u, self.p.T, self.p.nu), "x": self._shape(self.x, self.p.T + 1, self.p.nx),
+                "z": self._shape(z, self.p.T, 2 * self.p.nu), "v": self._shape(v, self.p.T, 2 * self.p.nu),
                 "admm_iters": len(inner), "newton_iters": int(sum(inner)), "inner": np.array(inner),
                 "rp": np.array(rps), "rd": np.array(rds)}
 
-    def ip_solve(self, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, trace=True):
+    def mpc_simulate(self, steps, *, mu_levels, iters, alpha0, nu0, graph=True):
+        """Receding-horizon simulation of every instance (Sec. V): per plant step a
+        fixed IP budget (iters Newton iterations at each barrier weight), warm start
+        from the previous solution shifted by one stage (nmpc_shift), the first control
+        applied to the plant (one Euler step).  No host synchronisation inside the
+        simulation.  Returns dict(x [B, steps+1, nx], u [B, steps, nu]) (no batch axis
+        for B = 1)."""
+        B, n, m = self.B, self.p.nx, self.p.nu
+        dev = self.x.device
+        g = self._capture_step() if graph else None
+        x_init = self.x0.clone()
+        x_cl = torch.empty(steps + 1, B * n, dtype=torch.float64, device=dev)
+        u_cl = torch.empty(steps, B * m, dtype=torch.float64, device=dev)
+        try:
+            self.u.copy_(self.u0)
+            x_cl[0].copy_(self.x0)
+            for t in range(steps):
+                self.init(alpha0, nu0, reset_u=False)
+                for mu in mu_levels:
+                    for _ in range(iters):
+                        self._sc[:, NMPC_MU] = mu
+                        if g is not None:
+                            g.replay()
+                        else:
+                            newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+                nmpc_shift(self.plan, self.prob_c, self.state_c, self.x0, u_cl[t])
+                x_cl[t + 1].copy_(self.x0)
+            torch.cuda.synchronize()
+        finally:
+            self.x0.copy_(x_init)
+        xs = x_cl.cpu().numpy().reshape(steps + 1, B, n).transpose(1, 0, 2)
+        us = u_cl.cpu().numpy().reshape(steps, B, m).transpose(1, 0, 2)
+        return {"x": xs[0] if B == 1 else xs, "u": us[0] if B == 1 else us}
+
+    def ip_solve(self, *, mu0, zeta, mu_min, tol, max_iter, alpha0, nu0, trace=True, graph=True):
         """The interior-point method of Sec. II-B with converged inner Newton loops:
         mu = mu0, mu0 zeta, ... while mu > mu_min; a level ends after the iteration
         that starts from |dJ_mu/du|_inf <= tol, or after max_iter iterations.
 
         The gradient norm of each iteration is read back (one small device-to-host
-        copy per iteration, into pinned memory).  Returns dict(u, x, iters,
-        level_iters, and with trace the per-iteration mu, cost, grad, accept, pred).
+        copy per iteration, into pinned memory).  graph: replay newton_step from a HIP
+        graph captured once per solve.  Returns dict(u, x, iters, level_iters, and with
+        trace the per-iteration mu, cost, grad, accept, pred).
         """
+        g = self._capture_step() if graph else None
         self.init(alpha0, nu0)
-        host = torch.empty(NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
+        host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
         rows, level_iters = ([] if trace else None), []
         mu = float(mu0)
         while mu > mu_min:
-            level_iters.append(self._newton_level(mu, tol, max_iter, host, rows))
+            level_iters.append(self._newton_level(mu, tol, max_iter, host, rows, g))
             mu *= zeta
-        out = {"u": self.u.cpu().numpy().reshape(self.p.T, self.p.nu),
-               "x": self.x.cpu().numpy().reshape(self.p.T + 1, self.p.nx),
+        out = {"u": self._shape(self.u, self.p.T, self.p.nu), "x": self._shape(self.x, self.p.T + 1, self.p.nx),
                "iters": int(sum(level_iters)), "level_iters": np.array(level_iters)}
         if trace:
             r = np.array(rows).reshape(-1, 5)

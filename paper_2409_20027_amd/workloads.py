@@ -322,6 +322,48 @@ def cartpole_problem(N: int, seed: int = 0, t_final: float = CARTPOLE_TF) -> NMP
                        NMPC_CARTPOLE, np.array(CARTPOLE_PARAM))
 
 
+# Receding-horizon MPC of Sec. V: N = 60 stages at 100 Hz, 4 s of plant time.
+MPC_N, MPC_H, MPC_STEPS = 60, 0.01, 400
+# Per MPC step (proposed; the paper gives no budget): the IP schedule's five
+# barrier levels with MPC_ITERS Newton iterations each, warm start from the
+# previous solution shifted by one stage, damping restarted.
+MPC_ITERS = 2
+MPC_MU_LEVELS = tuple(IP_MU0 * IP_ZETA ** k for k in range(5))
+
+
+def mpc_problem(name: str, x_init: np.ndarray) -> NMPCProblem:
+    """Stabilisation MPC (Sec. V): the pendulum upright, the cart-pole upright
+    with the cart at 0, from the states x_init ([B, nx]); stage cost
+    h (x - x_ref)'Q(x - x_ref)/2 + h R u^2/2 (pendulum Q = diag(100, 10),
+    R = 0.1; cart-pole Q = diag(10, 50, 1, 1), R = 1e-3), Q_T = diag(100, 10)
+    / diag(100, 100, 10, 10), bounds |tau| < 5, |F| < 60, zero initial
+    controls.  Costs and initial states are proposed (not printed)."""
+    N, h = MPC_N, MPC_H
+    x_init = np.ascontiguousarray(np.asarray(x_init, np.float64))
+    B = 1 if x_init.ndim == 1 else x_init.shape[0]
+    if name == "pendulum":
+        p = pendulum_problem(N, t_final=N * h)
+        Qc, Rc, QT = np.diag([100.0, 10.0]), 0.1, np.diag([100.0, 10.0])
+    else:
+        p = cartpole_problem(N, t_final=N * h)
+        Qc, Rc, QT = np.diag([10.0, 50.0, 1.0, 1.0]), 1e-3, np.diag([100.0, 100.0, 10.0, 10.0])
+    u0 = np.zeros((N, 1)) if B == 1 else np.zeros((B, N, 1))
+    return dataclasses.replace(p, Q=h * Qc, R=np.array([[h * Rc]]), QT=QT, x0=x_init, u0=u0)
+
+
+def mpc_initial_states(name: str, count: int, seed: int = 7) -> np.ndarray:
+    """Initial states around the upright equilibrium, inside the region this
+    short-horizon, input-bounded controller recovers (the torque limit 5 is
+    half of m g l): pendulum theta ~ pi + U(-0.3, 0.3), omega ~ U(-0.3, 0.3);
+    cart-pole p ~ U(-0.3, 0.3), theta ~ pi + U(-0.4, 0.4), v, omega ~
+    U(-0.3, 0.3)."""
+    rng = np.random.default_rng(seed)
+    if name == "pendulum":
+        return np.stack([math.pi + rng.uniform(-0.3, 0.3, count), rng.uniform(-0.3, 0.3, count)], axis=1)
+    return np.stack([rng.uniform(-0.3, 0.3, count), math.pi + rng.uniform(-0.4, 0.4, count),
+                     rng.uniform(-0.3, 0.3, count), rng.uniform(-0.3, 0.3, count)], axis=1)
+
+
 NMPC_MU_LEVELS = (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6)
 NMPC_ITERS_PER_LEVEL = 10
 NMPC_ALPHA0 = 1e-3

@@ -204,3 +204,69 @@ def test_admm_solve_matches_oracle(lq, name, N):
     assert rel(got["u"], ref["u"]) < 1e-5 and rel(got["x"], ref["x"]) < 1e-5
     assert np.all(got["z"] <= 0.0) and np.all(got["v"] >= 0.0) and np.all((got["v"] == 0) | (got["z"] == 0))
     assert got["rp"][-1] <= W.ADMM_EPS and got["rd"][-1] <= W.ADMM_EPS
+
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_graph_replayed_solves_equal_eager(lq, name):
+    """ip_solve and admm_solve replaying a captured newton_step graph (with the host's
+    eager writes and readbacks between replays) give the eager results bit for bit."""
+    p = MODELS[name](60)
+    args = dict(mu0=W.IP_MU0, zeta=W.IP_ZETA, mu_min=W.IP_MU_MIN, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    s = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN)
+    e = s.ip_solve(**args, graph=False)
+    g = s.ip_solve(**args, graph=True)
+    assert np.array_equal(e["level_iters"], g["level_iters"])
+    assert np.array_equal(e["cost"], g["cost"]) and np.array_equal(e["grad"], g["grad"])
+    assert np.array_equal(e["u"], g["u"]) and np.array_equal(e["x"], g["x"])
+    aargs = dict(rho=W.ADMM_RHO[name] * p.h, eps=W.ADMM_EPS, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                 max_admm=40, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    ea = s.admm_solve(**aargs, graph=False)
+    ga = s.admm_solve(**aargs, graph=True)
+    assert ea["admm_iters"] == ga["admm_iters"] and np.array_equal(ea["inner"], ga["inner"])
+    assert np.array_equal(ea["rp"], ga["rp"]) and np.array_equal(ea["u"], ga["u"])
+
+
+# --------------------------------------------------------------------------
+# Batches and receding-horizon MPC (Sec. V)
+# --------------------------------------------------------------------------
+
+def test_batched_newton_matches_single_instances(lq):
+    """A batch of pendulum problems that differ in x0 and u0, fixed Newton iterations per
+    barrier level: every instance ends where the oracle's single-instance loop does."""
+    import dataclasses
+    B = 4
+    base = W.pendulum_problem(80)
+    rng = np.random.default_rng(12)
+    x0 = np.stack([rng.uniform(-0.5, 0.5, B), rng.uniform(-0.5, 0.5, B)], axis=1)
+    u0 = 0.1 * rng.standard_normal((B, base.T, 1))
+    p = dataclasses.replace(base, x0=x0, u0=u0)
+    levels, iters = W.MPC_MU_LEVELS[:3], 3
+    got = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN).run(levels, iters, W.NMPC_ALPHA0, W.NMPC_NU0)
+    for b in range(B):
+        pb = dataclasses.replace(base, x0=x0[b], u0=u0[b])
+        ref = oracle.nmpc_solve(pb, levels, iters, W.NMPC_ALPHA0, W.NMPC_NU0)
+        assert rel(got["u"][b], ref["u"]) < 1e-10
+        assert rel(got["x"][b], ref["x"]) < 1e-10
+
+
+@pytest.mark.parametrize("name,B,steps", [("pendulum", 5, 40), ("cartpole", 3, 30)])
+def test_mpc_simulation_matches_oracle(lq, name, B, steps):
+    """Batched receding-horizon simulation (one launch sequence for all instances, warm
+    start by nmpc_shift): each instance's closed-loop states and applied controls against
+    the oracle's sequential simulation, to 1e-6.  Near the upright equilibrium the last
+    Newton steps of a barrier level predict decreases at round-off of the cost, where the
+    accept decision compares rounding errors; the oracle's own loop with u perturbed by
+    1e-15 (relative) after every Newton step spreads the pendulum's closed loop by up to
+    4.7e-8 (cart-pole 2e-13) over these cases."""
+    xs = W.mpc_initial_states(name, B, seed=21)
+    p = W.mpc_problem(name, xs)
+    got = lq.NewtonMPC(p).mpc_simulate(steps, mu_levels=W.MPC_MU_LEVELS, iters=W.MPC_ITERS,
+                                       alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    worst = 0.0
+    for b in range(B):
+        ref = oracle.nmpc_mpc_simulate(W.mpc_problem(name, xs[b]), xs[b], steps=steps, mu_levels=W.MPC_MU_LEVELS,
+                                       iters=W.MPC_ITERS, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+        worst = max(worst, rel(got["x"][b], ref["x"]), rel(got["u"][b], ref["u"]))
+    print(f"{name}: closed-loop rel diff {worst:.1e}")
+    assert worst < 1e-6

@@ -271,3 +271,25 @@ def test_admm_solve_invariants_and_convergence(name, N):
     theta = o["x"][-1][0 if name == "pendulum" else 1]
     assert abs(theta - np.pi) < 0.15
     assert rel(oracle.nmpc_rollout(p, o["u"]), o["x"]) < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Receding-horizon MPC (Sec. V)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("name", sorted(MODELS))
+def test_mpc_closed_loop_stabilises(name):
+    """The closed loop follows the plant model step by step, keeps every applied control
+    inside the bounds and ends at the upright equilibrium (cart at 0) after 4 s."""
+    xs = W.mpc_initial_states(name, 6)
+    for xi in xs:
+        p = W.mpc_problem(name, xi)
+        o = oracle.nmpc_mpc_simulate(p, xi, steps=W.MPC_STEPS, mu_levels=W.MPC_MU_LEVELS, iters=W.MPC_ITERS,
+                                     alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+        x, u = o["x"], o["u"]
+        assert np.all(np.abs(u) < p.umax)
+        for t in (0, 7, 150, W.MPC_STEPS - 1):
+            f = oracle.nmpc_f(p, x[t], u[t])
+            assert rel(x[t + 1], x[t] + p.h * f) < 1e-15
+        target = p.xref[0]
+        assert np.max(np.abs(x[-1] - target)) < 0.05, x[-1]
