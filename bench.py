@@ -335,6 +335,43 @@ def paper_admm_solves(lqscan, workloads, with_cpu: bool, seq_max_n: int = 200) -
     return out
 
 
+def paper_mpc(lqscan, workloads, with_cpu: bool, batches=(1, 64, 1024, 4096)) -> dict:
+    """Receding-horizon MPC of Sec. V (N = 60 at 100 Hz, 4 s = 400 plant steps,
+    fixed IP budget per step, warm start): wall time of whole closed-loop
+    simulations, a batch of simulations from different initial states in one
+    launch sequence, against the oracle's sequential simulation on one host
+    core."""
+    import torch
+    kw = dict(mu_levels=workloads.MPC_MU_LEVELS, iters=workloads.MPC_ITERS, alpha0=workloads.NMPC_ALPHA0,
+              nu0=workloads.NMPC_NU0)
+    out = {"unit": "closed-loop simulations per second", "plant_steps": workloads.MPC_STEPS,
+           "horizon": workloads.MPC_N}
+    if with_cpu:
+        import oracle
+    for name in ("pendulum", "cartpole"):
+        rows = {}
+        for B in batches:
+            xs = workloads.mpc_initial_states(name, B, seed=5)
+            p = workloads.mpc_problem(name, xs if B > 1 else xs[0])
+            s = lqscan.NewtonMPC(p)
+            s.mpc_simulate(2, **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            o = s.mpc_simulate(workloads.MPC_STEPS, **kw)
+            dt = time.perf_counter() - t0
+            x = o["x"] if B > 1 else o["x"][None]
+            settled = float(np.mean(np.max(np.abs(x[:, -1] - p.xref[0]), axis=1) < 0.05))
+            rows[str(B)] = {"s": dt, "sims_per_s": B / dt, "seg_len": s.plan.seg_len(), "settled_fraction": settled}
+        if with_cpu:
+            xs = workloads.mpc_initial_states(name, 1, seed=5)
+            t0 = time.perf_counter()
+            oracle.nmpc_mpc_simulate(workloads.mpc_problem(name, xs[0]), xs[0], steps=workloads.MPC_STEPS, **kw)
+            rows["oracle_one_core"] = {"s": time.perf_counter() - t0}
+            rows["oracle_one_core"]["sims_per_s"] = 1.0 / rows["oracle_one_core"]["s"]
+        out[name] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -523,6 +560,7 @@ def main():
     if not args.no_paper:
         out["paper_ip_solves"] = paper_ip_solves(lqscan, workloads, 3, not args.no_cpu)
         out["paper_admm_solves"] = paper_admm_solves(lqscan, workloads, not args.no_cpu)
+        out["paper_mpc"] = paper_mpc(lqscan, workloads, not args.no_cpu)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(inst)
     print(json.dumps(out))

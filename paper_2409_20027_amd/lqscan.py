@@ -433,6 +433,12 @@ class NewtonMPC:
         model = int(getattr(p, "model", NMPC_TANH) or 0)
         self.B = 1 if np.ndim(p.x0) == 1 else int(np.shape(p.x0)[0])
         B = self.B
+        if seg_len == 0 and mode == "scan" and B > 1:
+            # a batch fills the GPU by itself: about 1536 segment waves in all, so that
+            # large batches run the plain recursion per instance (measured for N = 60:
+            # B = 256 best at 6 segments, B >= 1024 at one)
+            nseg = max(1, -(-1536 // B))
+            seg_len = max(1, -(-p.T // nseg))
         self.plan = Plan([p.nx] * B, [p.nu] * B, [p.T] * B, seg_len=seg_len, precision=precision, mode=mode)
         names = ("Q", "R", "QT", "xref") + (("W", "Bm") if model == NMPC_TANH else ())
         self.dev = {k: t(getattr(p, k)) for k in names}
