@@ -39,15 +39,23 @@ PROFILES = os.path.join(ROOT, "profiles")
 CALIB_BYTES = 256 << 20   # the plain copy launched by --calib (read and written once)
 
 
-def source_hash() -> str:
-    """SHA-256 over the HIP sources, so that a stored counter reading is only
-    used while the kernels it was taken from are unchanged."""
+PHASE_SOURCE = {"value": "lq_value.hip", "roll": "lq_rollout.hip", "adj": "lq_adjoint.hip"}
+
+
+def source_hash(phase: str | None = None) -> str:
+    """SHA-256 over the HIP sources a phase's kernel is built from (its .hip
+    file and the tile and descriptor headers; all sources when phase is None),
+    so that a stored counter reading is only used while that kernel's code is
+    unchanged."""
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(os.listdir(CSRC)):
-        if f.endswith((".hip", ".hpp")):
-            with open(os.path.join(CSRC, f), "rb") as fh:
-                h.update(f.encode() + b"\0" + fh.read())
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp")))
+    if phase is not None:
+        src = PHASE_SOURCE[phase.split("_")[0]]
+        files = [f for f in files if f in (src, "lq_tile.hpp", "lq_desc.hpp")]
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 
@@ -64,7 +72,7 @@ def stored_traffic(kernel: str):
             if ":" in line and not line.startswith(("|", "#")):
                 k, v = line.split(":", 1)
                 rec[k.strip().strip("`*")] = v.strip().strip("`")
-    if rec.get("source_sha256") != source_hash():
+    if rec.get("source_sha256") != source_hash(kernel):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])
