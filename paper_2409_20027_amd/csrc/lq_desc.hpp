@@ -329,4 +329,218 @@ LQK_DEV void store_vec(double *v, const Tile &t, int len, int col)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Stage data staged through LDS.
+//
+// One stage's problem arrays are copied into a wave-private LDS buffer with
+// coalesced loads (lane l reads elements l, l + 64, ... of each array) and
+// the homogeneous tiles are then gathered from the buffer with per-lane LDS
+// addresses that depend only on (n, m) and the lane; padding entries read two
+// constant slots (0.0 and 1.0).  The loads of the next stage are issued into
+// registers before the current stage's compute and written to the other of
+// two buffers after it, so their latency hides behind a stage.  This replaces
+// per-entry address selection (a chain of per-lane conditions for every
+// register of every tile) by one LDS read per register.
+// ---------------------------------------------------------------------------
+
+// Buffer layout in doubles: [0] = 0.0, [1] = 1.0, then A, c, Q, q, B, R, M, r
+// of one stage, then 64 doubles of write-off space for lanes past an array.
+struct StageLayout {
+    int oA, oc, oQ, oq, oB, oR, oM, orr, trash;
+};
+LQK_DEV StageLayout stage_layout(int n, int m)
+{
+    StageLayout L;
+    L.oA = 2;
+    L.oc = L.oA + n * n;
+    L.oQ = L.oc + n;
+    L.oq = L.oQ + n * n;
+    L.oB = L.oq + n;
+    L.oR = L.oB + n * m;
+    L.oM = L.oR + m * m;
+    L.orr = L.oM + n * m;
+    L.trash = L.orr + m;
+    return L;
+}
+
+// Buffer size in doubles for n <= 4 NK - 1, m <= MMAX.
+template <int NK>
+constexpr int stage_buf_size()
+{
+    constexpr int nm = 4 * NK - 1;
+    return 2 + 2 * nm * nm + 2 * nm + 2 * nm * MMAX + MMAX * MMAX + MMAX + 64;
+}
+
+// Register slots of one stage's copy: ceil(len / 64) per array at the
+// largest sizes.
+template <int NK, bool MR>
+struct StageFetch {
+    static constexpr int NM = 4 * NK - 1;
+    static constexpr int SA = (NM * NM + 63) / 64, SV = 1, SB = (NM * MMAX + 63) / 64, SR = 1;
+    static constexpr int N = 2 * SA + 2 * SV + SB + SR + (MR ? SB + SV : 0);
+    double v[N];
+};
+
+template <int S>
+LQK_DEV void fetch_array(const double *src, int len, double *v)
+{
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int idx = lane() + 64 * j;
+        v[j] = ldz(src, idx, src != nullptr && idx < len);
+    }
+}
+template <int S>
+LQK_DEV void put_array(double *buf, int off, int len, int trash, const double *v)
+{
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const int idx = lane() + 64 * j;
+        buf[idx < len ? off + idx : trash + lane()] = v[j];
+    }
+}
+
+// Loads of stage k into registers (arrays that are null read as zeros).
+template <int NK, bool MR>
+LQK_DEV void stage_fetch(const ProbPtrs &P, const InstDesc &d, int k, StageFetch<NK, MR> &f)
+{
+    using F = StageFetch<NK, MR>;
+    const int n = d.n, m = d.m;
+    double *v = f.v;
+    fetch_array<F::SA>(P.A + d.oA + (int64_t)k * n * n, n * n, v);
+    v += F::SA;
+    fetch_array<F::SV>(P.c ? P.c + d.oc + (int64_t)k * n : nullptr, n, v);
+    v += F::SV;
+    fetch_array<F::SA>(P.Q + d.oA + (int64_t)k * n * n, n * n, v);
+    v += F::SA;
+    fetch_array<F::SV>(P.q ? P.q + d.oc + (int64_t)k * n : nullptr, n, v);
+    v += F::SV;
+    fetch_array<F::SB>(P.B + d.oB + (int64_t)k * n * m, n * m, v);
+    v += F::SB;
+    fetch_array<F::SR>(P.R + d.oR + (int64_t)k * m * m, m * m, v);
+    v += F::SR;
+    if constexpr (MR) {
+        fetch_array<F::SB>(P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr, n * m, v);
+        v += F::SB;
+        fetch_array<F::SV>(P.r ? P.r + d.og + (int64_t)k * m : nullptr, m, v);
+    }
+}
+
+// The fetched registers into a buffer (after the constant slots).
+template <int NK, bool MR>
+LQK_DEV void stage_put(double *buf, const StageLayout &L, const InstDesc &d, const StageFetch<NK, MR> &f)
+{
+    using F = StageFetch<NK, MR>;
+    const int n = d.n, m = d.m;
+    const double *v = f.v;
+    put_array<F::SA>(buf, L.oA, n * n, L.trash, v);
+    v += F::SA;
+    put_array<F::SV>(buf, L.oc, n, L.trash, v);
+    v += F::SV;
+    put_array<F::SA>(buf, L.oQ, n * n, L.trash, v);
+    v += F::SA;
+    put_array<F::SV>(buf, L.oq, n, L.trash, v);
+    v += F::SV;
+    put_array<F::SB>(buf, L.oB, n * m, L.trash, v);
+    v += F::SB;
+    put_array<F::SR>(buf, L.oR, m * m, L.trash, v);
+    v += F::SR;
+    if constexpr (MR) {
+        put_array<F::SB>(buf, L.oM, n * m, L.trash, v);
+        v += F::SB;
+        put_array<F::SV>(buf, L.orr, m, L.trash, v);
+    }
+}
+
+LQK_DEV void stage_consts(double *buf)
+{
+    if (lane() < 2) buf[lane()] = (double)lane();
+}
+
+// Per-lane LDS addresses of a tile's four registers (0 = the 0.0 slot).
+struct GMap {
+    uint32_t a[4];
+};
+
+// A~ = [[A, c], [0, 1]]
+LQK_DEV GMap gmap_Ah(const StageLayout &L, int n)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        g.a[r] = (i < n && c < n) ? L.oA + i * n + c : (c == n && i < n) ? L.oc + i : (c == n && i == n) ? 1 : 0;
+    }
+    return g;
+}
+// Q~ = [[Q, q], [q', 0]]
+LQK_DEV GMap gmap_Qh(const StageLayout &L, int n)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        g.a[r] = (i < n && c < n) ? L.oQ + i * n + c : (c == n && i < n) ? L.oq + i : (i == n && c < n) ? L.oq + c : 0;
+    }
+    return g;
+}
+// B~ = [[B], [0]]
+LQK_DEV GMap gmap_Bh(const StageLayout &L, int n, int m)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        g.a[r] = (i < n && c < m) ? L.oB + i * m + c : 0;
+    }
+    return g;
+}
+// B~' = [B', 0]
+LQK_DEV GMap gmap_BhT(const StageLayout &L, int n, int m)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int a = trow(r);
+        g.a[r] = (a < m && c < n) ? L.oB + c * m + a : 0;
+    }
+    return g;
+}
+// R
+LQK_DEV GMap gmap_R(const StageLayout &L, int m)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        g.a[r] = (i < m && c < m) ? L.oR + i * m + c : 0;
+    }
+    return g;
+}
+// M~' = [M', r]
+LQK_DEV GMap gmap_MhT(const StageLayout &L, int n, int m)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int a = trow(r);
+        g.a[r] = (a < m && c < n) ? L.oM + c * m + a : (a < m && c == n) ? L.orr + a : 0;
+    }
+    return g;
+}
+
+LQK_DEV Tile gather(const double *buf, const GMap &g)
+{
+    Tile t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) t.v[r] = buf[g.a[r]];
+    return t;
+}
+
 }  // namespace lqk

@@ -54,19 +54,6 @@ struct StageRaw {
     Tile MT, BT;       // M~' = [M', r] and B~' (MR only)
 };
 
-template <bool MR>
-LQK_DEV void load_stage_raw(const ProbPtrs &P, const InstDesc &d, int k, StageRaw<MR> &w)
-{
-    w.A = load_Ah(P, d, k);
-    w.Q = load_Qh(P, d, k);
-    w.B = load_Bh(P, d, k);
-    w.R = load_R(P, d, k);
-    if constexpr (MR) {
-        w.MT = load_MhT(P, d, k);
-        w.BT = load_BhT(P, d, k);
-    }
-}
-
 // The stage element from its data.  With cross terms the Schur complement
 // needs R^{-1}: false if R is not positive definite.
 template <int PR, bool MR>
@@ -125,30 +112,41 @@ LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
     fk = first ? k : fk;
 }
 
-// Fused element build + fold over stages k1-1 .. k0 (right to left).  Stage
-// k-1's loads are issued at the top of step k, a whole step before they are
-// used; the first stage's data is settled before the loop so that the waits in
-// the loop count only the loads the loop issues.
+// Fused element build + fold over stages k1-1 .. k0 (right to left).  The
+// stage data comes through LDS (stage_fetch / stage_put / gather): stage
+// k-1's loads are issued at the top of step k and written to the other buffer
+// after its compute.
 template <int NK, int NB, int PR, bool MR>
 LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
-                        int &code, int &fk)
+                        int &code, int &fk, double *stg)
 {
-    StageRaw<MR> nxt;
-    load_stage_raw<MR>(P, d, k1 - 1, nxt);
-    settle(nxt.A);
-    settle(nxt.Q);
-    settle(nxt.B);
-    settle(nxt.R);
-    if constexpr (MR) {
-        settle(nxt.MT);
-        settle(nxt.BT);
-    }
-    for (int k = k1 - 1; k >= k0; --k) {
-        const StageRaw<MR> b = nxt;
-        load_stage_raw<MR>(P, d, max(k - 1, k0), nxt);
+    constexpr int SZ = stage_buf_size<NK>();
+    const int n = d.n, m = d.m;
+    const StageLayout L = stage_layout(n, m);
+    StageFetch<NK, MR> f;
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    stage_fetch<NK, MR>(P, d, k1 - 1, f);
+    stage_put<NK, MR>(stg, L, d, f);
+    wsync();
+    int b = 0;
+    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        stage_fetch<NK, MR>(P, d, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+        StageRaw<MR> w;
+        w.A = gather(cur, gmap_Ah(L, n));
+        w.Q = gather(cur, gmap_Qh(L, n));
+        w.B = gather(cur, gmap_Bh(L, n, m));
+        w.R = gather(cur, gmap_R(L, m));
+        if constexpr (MR) {
+            w.MT = gather(cur, gmap_MhT(L, n, m));
+            w.BT = gather(cur, gmap_BhT(L, n, m));
+        }
         StageElem e;
-        note(build_from_raw<PR, MR>(b, d, e), ERR_NOT_PD, k, code, fk);
+        note(build_from_raw<PR, MR>(w, d, e), ERR_NOT_PD, k, code, fk);
         note(fold_left<NK, NB, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
+        stage_put<NK, MR>(stg + (b ^ 1) * SZ, L, d, f);
+        wsync();
     }
 }
 
@@ -156,12 +154,12 @@ LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Ti
 // of 4 (then B~'s rows fit one slice fewer than n + 1), NK otherwise.
 template <int NK, int PR, bool MR>
 LQK_DEV void fold_fused_nb(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Tile &U, Tile &Ch, Tile &Jh,
-                           int &code, int &fk)
+                           int &code, int &fk, double *stg)
 {
     if (NK > 1 && (d.n & 3) == 0)
-        fold_fused<NK, (NK > 1 ? NK - 1 : 1), PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk);
+        fold_fused<NK, (NK > 1 ? NK - 1 : 1), PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
     else
-        fold_fused<NK, NK, PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk);
+        fold_fused<NK, NK, PR, MR>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,10 +246,11 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
         }
     } else {
         // fused element build
+        __shared__ double stg[2 * stage_buf_size<NK>()];
         if ((P.M != nullptr) || (P.r != nullptr))
-            fold_fused_nb<NK, PR, true>(P, d, k0, k1, U, Ch, Jh, code, fk);
+            fold_fused_nb<NK, PR, true>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
         else
-            fold_fused_nb<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk);
+            fold_fused_nb<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
     gstore(o, ttrans(U, lds));
