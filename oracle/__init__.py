@@ -57,6 +57,8 @@ def lib():
             L.oracle_costate_combine.restype = None
             L.oracle_stateprop_combine.argtypes = [i, _P, _P, _P]
             L.oracle_stateprop_combine.restype = None
+            L.oracle_lq_states_cv.argtypes = [i, i, i] + [_P] * 12 + [_I]
+            L.oracle_lq_states_cv.restype = i
             L.oracle_lq_adjoint.argtypes = [i, i, i] + [_P] * 11 + [_P] * 2 + [_P] * 11 + [_I]
             L.oracle_lq_adjoint.restype = i
             L.oracle_nmpc_cost.argtypes = [i, i, i, d, i, _P] + [_P] * 7 + [d, d, d, _P, _P, d, _P]
@@ -125,6 +127,20 @@ def lq_solve(A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None, *, check=Tr
     if check and st != 0:
         raise OracleError(st, fk.value)
     return out
+
+
+def lq_states_cv(A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None, *, check=True):
+    """Optimal states from the prefix conditional value functions and the
+    suffix value functions (eq:value-fun-prefix-sum); x [T+1, n]."""
+    A, B, c, Q, R, QT, x0, M, q, r, qT = map(_f, (A, B, c, Q, R, QT, x0, M, q, r, qT))
+    T, n, m = A.shape[0], A.shape[1], B.shape[2]
+    x = np.zeros((T + 1, n))
+    fk = ctypes.c_int(-1)
+    st = lib().oracle_lq_states_cv(n, m, T, _p(A), _p(B), _p(c), _p(Q), _p(R), _p(M), _p(q), _p(r),
+                                   _p(QT), _p(qT), _p(x0), _p(x), ctypes.byref(fk))
+    if check and st != 0:
+        raise OracleError(st, fk.value)
+    return x
 
 
 def elem_size(n):

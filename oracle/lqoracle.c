@@ -25,6 +25,9 @@
  *                          with the last b-term read as the later element's b.
  *   oracle_costate_combine eq:co-states-comb-rule (l and c gradients summed).
  *   oracle_stateprop_combine eq:state-prop-comb-rule.
+ *   oracle_lq_states_cv    the optimal states from the prefix conditional
+ *                          value functions and the suffix value functions
+ *                          of eq:value-fun-prefix-sum.
  *   oracle_lq_adjoint      gradients of a loss of (x, u) through the LQ
  *                          solution by implicit differentiation of its KKT
  *                          system (not in the paper): a second LQ solve with
@@ -469,6 +472,87 @@ void oracle_stateprop_combine(int n, const double *e1, const double *e2, double 
     for (int i = 0; i < n; ++i) o[nn + i] += e2[nn + i];
     memcpy(out, o, sizeof(double) * (n + nn));
     free(o);
+}
+
+/* ------------------------------------------------------------------ */
+/* States from conditional value functions (eq:value-fun-prefix-sum)   */
+/* ------------------------------------------------------------------ */
+/*
+ * The forward variant that Alg. 2's scans make possible: with the prefix
+ * element P_k = nu_0 (x) ... (x) nu_{k-1} (the conditional value function
+ * V(x_0, x_k) of eq:value-fun-def; P_0 the unit) and the value function
+ * V_k(x) = 1/2 x'S_k x + s_k'x of the suffix nu_k (x) ... (x) nu_T, the
+ * optimal x_k minimises V(x_0, x_k) + V_k(x_k).  In the dual form
+ * eq:value-fun-elements the stationarity conditions are
+ *   p = S_k x_k + s_k,   x_k = A_P x_0 + b_P - C_P p,
+ * so (I + C_P S_k) x_k = A_P x_0 + b_P - C_P s_k.
+ * Both scans are done sequentially with oracle_value_combine.
+ * x: (T+1) x n.  Returns 0, -2 (an R_k not PD; stage in *fail_k) or -3.
+ */
+int oracle_lq_states_cv(int n, int m, int T,
+                        const double *A, const double *B, const double *c,
+                        const double *Q, const double *R, const double *M,
+                        const double *q, const double *r,
+                        const double *QT, const double *qT, const double *x0,
+                        double *x, int *fail_k)
+{
+    const int nn = n * n, nm = n * m, mm = m * m, es = 3 * nn + 2 * n;
+    double *suf = malloc(sizeof(double) * (size_t)(T + 1) * es);   /* V_k */
+    double *pre = malloc(sizeof(double) * es), *el = malloc(sizeof(double) * es);
+    double *Mx = malloc(sizeof(double) * nn), *lu = malloc(sizeof(double) * nn);
+    double *rhs = malloc(sizeof(double) * n);
+    int *piv = malloc(sizeof(int) * n);
+    int status = OK;
+    if (fail_k) *fail_k = -1;
+    /* suffix: V_T = nu_T, V_k = nu_k (x) V_{k+1} */
+    oracle_value_terminal(n, QT, qT, suf + (size_t)T * es);
+    for (int k = T - 1; k >= 0; --k) {
+        status = oracle_value_element(n, m, A + (size_t)k * nn, B + (size_t)k * nm, c ? c + (size_t)k * n : NULL,
+                                      Q + (size_t)k * nn, R + (size_t)k * mm, M ? M + (size_t)k * nm : NULL,
+                                      q ? q + (size_t)k * n : NULL, r ? r + (size_t)k * m : NULL, el);
+        if (status != OK) {
+            if (fail_k) *fail_k = k;
+            goto done;
+        }
+        status = oracle_value_combine(n, el, suf + (size_t)(k + 1) * es, suf + (size_t)k * es);
+        if (status != OK) {
+            if (fail_k) *fail_k = k;
+            goto done;
+        }
+    }
+    /* prefix: P_0 = (I, 0, 0, 0, 0), P_{k+1} = P_k (x) nu_k */
+    memset(pre, 0, sizeof(double) * es);
+    for (int i = 0; i < n; ++i) pre[i * n + i] = 1.0;
+    for (int k = 0; k <= T; ++k) {
+        const double *PA = pre, *Pb = pre + nn, *PC = pre + nn + n;
+        const double *Sk = suf + (size_t)k * es + 2 * nn + 2 * n;   /* S_k = J(V_k)     */
+        const double *etak = suf + (size_t)k * es + 2 * nn + n;     /* s_k = -eta(V_k)  */
+        gemm(n, n, n, PC, 0, Sk, 0, Mx, 0);
+        for (int i = 0; i < n; ++i) Mx[i * n + i] += 1.0;           /* I + C_P S_k      */
+        gemv(n, n, PA, 0, x0, rhs, 0);
+        for (int i = 0; i < n; ++i) rhs[i] += Pb[i];
+        gemv(n, n, PC, 0, etak, rhs, 1);                            /* - C_P s_k = + C_P eta_k */
+        if (lu_factor(n, Mx, lu, piv) != 0) {
+            if (fail_k) *fail_k = k;
+            status = ERR_SINGULAR;
+            goto done;
+        }
+        lu_solve(n, lu, piv, rhs, 1);
+        memcpy(x + (size_t)k * n, rhs, sizeof(double) * n);
+        if (k == T) break;
+        oracle_value_element(n, m, A + (size_t)k * nn, B + (size_t)k * nm, c ? c + (size_t)k * n : NULL,
+                             Q + (size_t)k * nn, R + (size_t)k * mm, M ? M + (size_t)k * nm : NULL,
+                             q ? q + (size_t)k * n : NULL, r ? r + (size_t)k * m : NULL, el);
+        status = oracle_value_combine(n, pre, el, pre);
+        if (status != OK) {
+            if (fail_k) *fail_k = k;
+            goto done;
+        }
+    }
+    if (!all_finite(x, (long)(T + 1) * n)) status = ERR_NONFINITE;
+done:
+    free(suf); free(pre); free(el); free(Mx); free(lu); free(rhs); free(piv);
+    return status;
 }
 
 /* ------------------------------------------------------------------ */

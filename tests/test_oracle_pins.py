@@ -346,6 +346,33 @@ def test_stateprop_scan_equals_rollout():
 
 
 # --------------------------------------------------------------------------
+# P9: states from the prefix conditional value functions
+# (eq:value-fun-prefix-sum): minimiser of V(x_0, x_k) + V_k(x_k)
+# --------------------------------------------------------------------------
+
+def states_cv(inst):
+    return oracle.lq_states_cv(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                               M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+
+
+@pytest.mark.parametrize("T", [1, 2, 5, 8])
+@pytest.mark.parametrize("n,m", [(1, 1), (3, 2), (4, 4)])
+def test_cv_states_match_dense_kkt(T, n, m):
+    inst = W.lq_instance_general(np.random.default_rng(300 + 100 * T + 10 * n + m), n, m, T)
+    x, _, _, _ = dense_kkt(inst)
+    assert rel(states_cv(inst), x) < 1e-11
+
+
+@pytest.mark.parametrize("general", [False, True])
+def test_cv_states_match_riccati_rollout_long(general):
+    rng = np.random.default_rng(31)
+    inst = W.lq_instance_general(rng, 5, 2, 200) if general else W.lq_instance(rng, 6, 3, 200)
+    xc = states_cv(inst)
+    assert np.array_equal(xc[0], inst.x0)   # the unit prefix returns x_0 itself
+    assert rel(xc, solve(inst)["x"]) < 1e-10
+
+
+# --------------------------------------------------------------------------
 # P8: adjoint
 # --------------------------------------------------------------------------
 
