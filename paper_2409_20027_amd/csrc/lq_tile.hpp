@@ -372,7 +372,10 @@ LQK_DEV void gj_step(d4 &v, int n1, bool &ok, int &piv_out)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = 4 * r + g;
-        const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, v[r]) >> 32);
+        // through a scalar: a bit cast of the vector element itself has been
+        // compiled as a cast of element 0 whatever r is
+        const double x = v[r];
+        const uint32_t hi = (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
         const uint32_t k = (hi & 0x7ffffff0u) | (uint32_t)(15 - i);
         key = (c == P && i >= P && i < n1) ? max(key, k) : key;
     }
