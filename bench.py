@@ -380,6 +380,44 @@ def paper_mpc(lqscan, workloads, with_cpu: bool, batches=(1, 64, 1024, 4096)) ->
     return out
 
 
+def cv_rollout(lqscan, plan, prob, val, ws, status, inst, with_cpu: bool, reps: int = 20) -> dict:
+    """lq_rollout (closed-loop maps) and lq_rollout_cv (conditional value
+    functions, eq:value-fun-prefix-sum) from the same value pass: time per
+    call, the CV phases, and the CV states' error against the oracle's."""
+    import oracle
+    import torch
+    dev = prob["A"].device
+    out = {}
+    for name, fn in (("affine", lqscan.lq_rollout), ("cv", lqscan.lq_rollout_cv)):
+        st = lqscan.state_buffers(plan, dev)
+        fn(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+        b.record()
+        torch.cuda.synchronize()
+        out[f"{name}_us"] = a.elapsed_time(b) / reps * 1e3
+        if name == "cv":
+            plan.set_timing(["cv_fold", "cv_scan", "cv_start", "roll_apply"], capacity=4 * reps + 8)
+            for _ in range(reps):
+                fn(plan, prob, val, st["x"], st["u"], st["lam"], ws, status)
+            out["cv_phase_us"] = {k: v[0] / reps * 1e3 for k, v in plan.phase_times().items()}
+            plan.set_timing([], 0)
+            t0 = time.perf_counter()
+            xc = oracle.lq_states_cv(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
+            cpu_s = time.perf_counter() - t0
+            x = st["x"].cpu().numpy().reshape(inst.T + 1, inst.n)
+            out["err_x_vs_oracle_cv"] = float(np.max(np.abs(x - xc)) / np.max(np.abs(xc)))
+            if with_cpu:
+                out["oracle_cv_states_s"] = cpu_s
+    assert int(status.abs().sum()) == 0, "numerical failure reported"
+    out["what"] = ("rollout of the value pass's result at n=12, m=4, T=16384: closed-loop affine scan vs "
+                   "prefix conditional value functions (fold + prefix scan + segment-start solve + sweep)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,6 +430,7 @@ def main():
     ap.add_argument("--replays", type=int, default=100)
     ap.add_argument("--no-batch", action="store_true", help="skip the batched workloads")
     ap.add_argument("--no-paper", action="store_true", help="skip the pendulum / cart-pole interior-point solves")
+    ap.add_argument("--no-cv", action="store_true", help="skip the conditional-value rollout comparison")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -528,6 +567,12 @@ def main():
         seq = {"ms_per_step": seq_ms, "value": T / (seq_ms * 1e-3), "unit": "stage-steps/s",
                "what": "same step (forward + adjoint) with one segment: sequential recursions on the GPU"}
 
+    # the two rollouts of the same value pass: closed-loop maps (lq_rollout)
+    # and conditional value functions (lq_rollout_cv)
+    cv = None
+    if not args.no_cv:
+        cv = cv_rollout(lqscan, plan, prob, val, ws, status, inst, not args.no_cpu)
+
     mdl = models[dominant]
     # average duration of one kernel launch of the dominant phase (a scan phase
     # is timed as a whole: its time divided by its number of levels)
@@ -562,6 +607,7 @@ def main():
            "err_vs_oracle": err,
            "sequential_gpu": seq,
            "kernel_ms_per_step": breakdown,
+           "cv_rollout": cv,
            "roofline": roof}
     if not args.no_batch:
         out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), 1)

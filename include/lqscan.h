@@ -188,6 +188,29 @@ lq_status lq_rollout(const lq_plan *plan, const lq_problem *prob, const lq_value
                      double *x, double *u, double *lambda, void *workspace, int32_t *status,
                      void *stream);
 
+/*
+ * lq_rollout_cv -- the same outputs as lq_rollout from the conditional value
+ * functions instead of the closed-loop maps (eq:value-fun-prefix-sum): with
+ * the prefix element V(x_0, x_k) = nu_0 (x) ... (x) nu_{k-1} of eq:value-fun-def
+ * (dual form eq:value-fun-elements, parameters A, b, C) and the value function
+ * (S_k, s_k) of val, the optimal state minimises V(x_0, x_k) + V_k(x_k):
+ *   (I + C S_k) x_k = A x_0 + b - C s_k.
+ * Segmented: the prefix elements are formed at the segment starts (fold of
+ * each segment with the fused element build, then a log-depth prefix scan
+ * under eq:value-fun-param), the formula gives the segment-start states, and
+ * inside each segment the states follow the closed-loop recursion
+ * x_{k+1} = (A + B Gamma) x_k + B gamma + c (the formula with the one-stage
+ * prefix), u_k = Gamma x_k + gamma, lambda_k = S_k x_k + s_k.
+ * Arguments, layouts and ownership are those of lq_rollout; val must hold the
+ * lq_scan_solve (or lq_solve) output for the same problem.  The workspace's
+ * scan buffers are overwritten.  Numerical failures: LQ_ERR_NOT_PD (R_k not
+ * positive definite where cross terms need its inverse), LQ_ERR_SINGULAR (a
+ * singular I + C S_k or fold matrix).
+ */
+lq_status lq_rollout_cv(const lq_plan *plan, const lq_problem *prob, const lq_value *val,
+                        double *x, double *u, double *lambda, void *workspace, int32_t *status,
+                        void *stream);
+
 /* Gradients (device pointers, same packing as lq_problem; NULL = not wanted). */
 typedef struct {
     double *A, *B, *c, *Q, *R, *M, *q, *r, *QT, *qT, *x0;
@@ -371,7 +394,10 @@ enum {
     LQ_PH_ADJ_FWD_FOLD = 10,  /* adjoint: composition of each segment's forward maps  */
     LQ_PH_ADJ_FWD_SCAN = 11,  /* adjoint: log-depth prefix scan                      */
     LQ_PH_ADJ_FWD_APPLY = 12, /* adjoint: dx, du, dlambda and the gradients          */
-    LQ_NPHASE = 13
+    LQ_PH_CV_FOLD = 13,       /* conditional-value rollout: fold of each segment    */
+    LQ_PH_CV_SCAN = 14,       /* conditional-value rollout: log-depth prefix scan   */
+    LQ_PH_CV_START = 15,      /* conditional-value rollout: segment-start states    */
+    LQ_NPHASE = 16
 };
 /*
  * lq_plan_set_timing enables event recording around the phases whose bit is

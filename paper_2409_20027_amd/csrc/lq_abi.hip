@@ -287,14 +287,14 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
     double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
     timed(p, LQ_PH_VALUE_FOLD, st, [&] {
         lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
-                               Xa, status);
+                               Xa, 0, status);
     });
     double *in = Xa, *o = Xb;
     if (p->max_nseg > 1)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,
-                                     status);
+                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
+                                     o, status);
                 std::swap(in, o);
             }
         });
@@ -345,6 +345,44 @@ lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *v
         lqk::launch_roll_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
     });
     rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
+    return launched();
+}
+
+// Conditional-value states: fold of every segment but the last (the unit at
+// entry 0), prefix scan, the segment-start states from the prefix elements and
+// S~_k0, then the closed-loop sweep inside each segment.
+lq_status lq_rollout_cv(const lq_plan *p, const lq_problem *prob, const lq_value *val, double *x, double *u,
+                        double *lambda, void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(val) || !x || !u) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
+    double *Ya = (double *)(ws + p->off_Ya);
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
+    timed(p, LQ_PH_CV_FOLD, st, [&] {
+        lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, nullptr,
+                               Xa, 1, status);
+    });
+    double *in = Xa, *o = Xb;
+    if (p->max_nseg > 1)
+        timed(p, LQ_PH_CV_SCAN, st, [&] {
+            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in,
+                                     o, status);
+                std::swap(in, o);
+            }
+        });
+    timed(p, LQ_PH_CV_START, st, [&] {
+        lqk::launch_cv_start(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, in, Ya,
+                             status);
+    });
+    timed(p, LQ_PH_ROLL_APPLY, st, [&] {
+        lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya, x,
+                               u, lambda);
+    });
     return launched();
 }
 

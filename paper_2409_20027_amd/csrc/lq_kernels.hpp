@@ -12,9 +12,12 @@ void launch_selftest_mm(int pr, hipStream_t st, const double *X, const double *Y
                         int ty);
 
 void launch_value_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
-                       const int32_t *seg_start, int batch, const double *elems, double *X, int32_t *status);
+                       const int32_t *seg_start, int batch, const double *elems, double *X, int prefix,
+                       int32_t *status);
 void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
-                     int batch, int dd, const double *Xin, double *Xout, int32_t *status);
+                     int batch, int dd, int prefix, const double *Xin, double *Xout, int32_t *status);
+void launch_cv_start(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                     const int32_t *seg_start, int batch, const double *Xfin, double *Y, int32_t *status);
 void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                           const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
                           int32_t *status);

@@ -210,11 +210,15 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
 // element after the last segment of each instance.
 // Scan buffer entry = 3 tiles (A~, C~, J~).
 // ---------------------------------------------------------------------------
+//
+// prefix = 1 lays the entries out for the prefix scan of the conditional-value
+// states instead: the unit element at entry 0, segment s's element at entry
+// s + 1 (the last segment's element is never read), no terminal element.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
                                                    const double *__restrict__ elems, double *__restrict__ X,
-                                                   int32_t *status)
+                                                   int prefix, int32_t *status)
 {
     __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
@@ -225,15 +229,25 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     const int n1 = d.n + 1, m = d.m;
     Tile U = tident(n1), Ch = tzero(), Jh = tzero();
     int code = 0, fk = 0;
-    if (s == d.nseg - 1) {  // terminal element after the last segment
-        double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
-        gstore(t, corner(d.n));
-        gstore(t + TILE, tzero());
-        gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
+    if (prefix) {
+        if (s == 0) {
+            double *t = X + (int64_t)d.xbase * 3 * TILE;
+            gstore(t, tident(n1));
+            gstore(t + TILE, tzero());
+            gstore(t + 2 * TILE, tzero());
+        }
+        if (s == d.nseg - 1) return;
+    } else {
+        if (s == d.nseg - 1) {  // terminal element after the last segment
+            double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
+            gstore(t, corner(d.n));
+            gstore(t + TILE, tzero());
+            gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
+        }
+        // The element of segment 0 is never read: the Bellman steps of
+        // segment s start from the scanned element s + 1.
+        if (s == 0) return;
     }
-    // The element of segment 0 is never read: the Bellman steps of segment s
-    // start from the scanned element s + 1.
-    if (s == 0) return;
     if (elems) {
         for (int k = k1 - 1; k >= k0; --k) {
             StageElem e;
@@ -252,7 +266,7 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
         else
             fold_fused_nb<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
     }
-    double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
+    double *o = X + (int64_t)(d.xbase + s + prefix) * 3 * TILE;
     gstore(o, ttrans(U, lds));
     gstore(o + TILE, tsym(Ch, lds));
     gstore(o + 2 * TILE, tsym(Jh, lds));
@@ -269,11 +283,15 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
 // all P'Q of register tiles given R(Y') (the inverse of X' = I + J~2 C~1) and
 // R(A~2') (one LDS transpose).
 // ---------------------------------------------------------------------------
+//
+// prefix = 1: the inclusive prefix scan X_s <- X_{s-dd} (x) X_s over entries
+// 0 .. nseg-1 (laid out by k_value_fold with prefix = 1), general elements
+// throughout; an entry with s < dd is final and copied.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ inst,
                                                  const int32_t *__restrict__ x_start, int batch, int dd,
-                                                 const double *__restrict__ Xin, double *__restrict__ Xout,
-                                                 int32_t *status)
+                                                 int prefix, const double *__restrict__ Xin,
+                                                 double *__restrict__ Xout, int32_t *status)
 {
     __shared__ double lds[SLOT];
     const int gx = blockIdx.x;
@@ -281,15 +299,31 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const InstDesc d = inst[i];
     const int s = gx - d.xbase;
     const int nseg = d.nseg;
-    const double *a = Xin + (int64_t)gx * 3 * TILE;
     double *o = Xout + (int64_t)gx * 3 * TILE;
-    if (s == 0) return;   // never read (see k_value_fold)
-    if (s + dd > nseg) {  // already final (terminal-type): carry J~ over
-        gstore(o + 2 * TILE, gload(a + 2 * TILE));
-        return;
+    const double *a, *b;
+    bool b_term;
+    if (prefix) {
+        if (s >= nseg) return;
+        const double *e = Xin + (int64_t)gx * 3 * TILE;
+        if (s < dd) {
+            gstore(o, gload(e));
+            gstore(o + TILE, gload(e + TILE));
+            gstore(o + 2 * TILE, gload(e + 2 * TILE));
+            return;
+        }
+        a = Xin + (int64_t)(gx - dd) * 3 * TILE;
+        b = e;
+        b_term = false;
+    } else {
+        a = Xin + (int64_t)gx * 3 * TILE;
+        if (s == 0) return;   // never read (see k_value_fold)
+        if (s + dd > nseg) {  // already final (terminal-type): carry J~ over
+            gstore(o + 2 * TILE, gload(a + 2 * TILE));
+            return;
+        }
+        b = Xin + (int64_t)(gx + dd) * 3 * TILE;
+        b_term = (s + 2 * dd - 1 >= nseg);
     }
-    const double *b = Xin + (int64_t)(gx + dd) * 3 * TILE;
-    const bool b_term = (s + 2 * dd - 1 >= nseg);
     const int n1 = d.n + 1;
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
     const Tile A2 = gload(b), C2 = gload(b + TILE), J2 = gload(b + 2 * TILE);
@@ -377,22 +411,67 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
 }
 
 // ---------------------------------------------------------------------------
+// Conditional-value states at the segment starts (eq:value-fun-prefix-sum).
+// With the prefix element (A~, C~) of stages 0 .. k0-1 and the value function
+// S~ = [[S, s], [s', 0]] of stage k0, the optimal state minimises
+// V(x0, x) + V_k0(x), which in the dual form eq:value-fun-elements gives
+//   x~ = (I + C~ S~)^{-1} A~ x~0
+// (the last column of a tile whose other columns are zero, the form the
+// rollout's scan entries have).  (I + C~ S~)' = I + S~ C~ has last column
+// e_n, so the homogeneous Gauss-Jordan applies.
+// ---------------------------------------------------------------------------
+template <int NK, int PR>
+__global__ __launch_bounds__(64) void k_cv_start(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
+                                                 const int32_t *__restrict__ seg_start, int batch,
+                                                 const double *__restrict__ Xfin, double *__restrict__ Y,
+                                                 int32_t *status)
+{
+    __shared__ double lds[SLOT];
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int n1 = d.n + 1;
+    const double *e = Xfin + (int64_t)(d.xbase + s) * 3 * TILE;
+    const Tile Ah = gload(e), Ch = gload(e + TILE);
+    const Tile Sh = load_Sh(V.S, V.s, d, s * d.L);
+    const Tile X0 = load_vec(P.x0 + d.on, d.n, d.n, d.n);
+    Tile YT = tna<NK, PR>(Sh, Ch, tident(n1));          // (I + C~ S~)'
+    const bool ok = gj_inverse<NK>(YT, n1, true);      // (I + C~ S~)^{-T}
+    const Tile AX = tnz<NK, PR>(ttrans(Ah, lds), X0);   // A~ x~0
+    gstore(Y + (int64_t)(d.xbase + s) * TILE, tnz<NK, PR>(YT, AX));
+    if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers (the contraction slice count NK = ceil((n_max + 1) / 4) is a
 // template parameter so that every product is fully unrolled).
 // ---------------------------------------------------------------------------
 
 void launch_value_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
-                       const int32_t *seg_start, int batch, const double *elems, double *X, int32_t *status)
+                       const int32_t *seg_start, int batch, const double *elems, double *X, int prefix,
+                       int32_t *status)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_value_fold<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, elems, X, status)
+#define CALL(K, R) \
+    hipLaunchKernelGGL((k_value_fold<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, elems, X, prefix, status)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }
 
 void launch_value_ks(int nk, int pr, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
-                     int batch, int dd, const double *Xin, double *Xout, int32_t *status)
+                     int batch, int dd, int prefix, const double *Xin, double *Xout, int32_t *status)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_value_ks<K, R>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, Xin, Xout, status)
+#define CALL(K, R) \
+    hipLaunchKernelGGL((k_value_ks<K, R>), dim3(grid), dim3(64), 0, st, inst, x_start, batch, dd, prefix, Xin, Xout, status)
+    LQK_DISPATCH(nk, pr, CALL)
+#undef CALL
+}
+
+void launch_cv_start(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                     const int32_t *seg_start, int batch, const double *Xfin, double *Y, int32_t *status)
+{
+#define CALL(K, R) \
+    hipLaunchKernelGGL((k_cv_start<K, R>), dim3(grid), dim3(64), 0, st, P, V, inst, seg_start, batch, Xfin, Y, status)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }

@@ -65,6 +65,8 @@ _lib.lq_scan_solve.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.P
 _lib.lq_scan_solve.restype = ctypes.c_int
 _lib.lq_rollout.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P, _P]
 _lib.lq_rollout.restype = ctypes.c_int
+_lib.lq_rollout_cv.argtypes = _lib.lq_rollout.argtypes
+_lib.lq_rollout_cv.restype = ctypes.c_int
 _lib.lq_solve.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P, _P]
 _lib.lq_solve.restype = ctypes.c_int
 _lib.lq_adjoint.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P,
@@ -78,11 +80,12 @@ _lib.lq_selftest_tile_mm.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_in
 _lib.lq_selftest_tile_mm.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
-            "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout",
+            "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout", "lq_rollout_cv",
             "lq_solve", "lq_adjoint", "lq_selftest_tile_mm", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
-          "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply")
+          "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply",
+          "cv_fold", "cv_scan", "cv_start")
 
 
 class LQError(RuntimeError):
@@ -230,6 +233,12 @@ def lq_rollout(plan: Plan, prob: dict, value: dict, x, u, lam, workspace, status
                                          _ptr(workspace), _ptr(status), _stream(stream)))
 
 
+def lq_rollout_cv(plan: Plan, prob: dict, value: dict, x, u, lam, workspace, status=None, stream=None):
+    _check("lq_rollout_cv", _lib.lq_rollout_cv(plan.handle, ctypes.byref(_problem_struct(prob)),
+                                               ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
+                                               _ptr(workspace), _ptr(status), _stream(stream)))
+
+
 def lq_solve(plan: Plan, prob: dict, elements, value: dict, x, u, lam, workspace, status=None, stream=None):
     _check("lq_solve", _lib.lq_solve(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(elements),
                                      ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
@@ -282,9 +291,12 @@ def state_buffers(plan: Plan, device="cuda") -> dict:
 
 
 def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, fused: bool = True, workspace=None,
-          stream=None) -> dict:
-    """lq_solve (fused = False: lq_scan_solve then lq_rollout); returns flat
-    packed device tensors and the status array."""
+          stream=None, rollout: str = "affine") -> dict:
+    """lq_solve (fused = False: lq_scan_solve then lq_rollout; rollout = "cv":
+    lq_scan_solve then lq_rollout_cv); returns flat packed device tensors and
+    the status array."""
+    if rollout not in ("affine", "cv"):
+        raise ValueError(f"rollout must be 'affine' or 'cv', not {rollout!r}")
     dev = prob["A"].device
     ws = workspace if workspace is not None else plan.new_workspace(dev)
     status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
@@ -294,7 +306,10 @@ def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, fused: 
     if materialise_elements:
         el = plan.new_elements(dev)
         lq_build_elements(plan, prob, el, status, stream)
-    if fused:
+    if rollout == "cv":
+        lq_scan_solve(plan, prob, el, val, ws, status, stream)
+        lq_rollout_cv(plan, prob, val, st["x"], st["u"], st["lam"], ws, status, stream)
+    elif fused:
         lq_solve(plan, prob, el, val, st["x"], st["u"], st["lam"], ws, status, stream)
     else:
         lq_scan_solve(plan, prob, el, val, ws, status, stream)
