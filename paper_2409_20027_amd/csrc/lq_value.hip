@@ -355,32 +355,30 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
 // for the rollout, Phi_s = F~_{k1-1} ... F~_{k0} with F~_k = A~_k + B~_k Gamma~_k
 // (kept as Phi' across the sweep), and writes the rollout scan's entries:
 // Phi_s at s + 1 (s < nseg - 1) and the constant map of x0 at 0.
-template <int NK, int PR>
-__global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
-                                                      const int32_t *__restrict__ seg_start, int batch,
-                                                      const double *__restrict__ Xfin, ValPtrs V,
-                                                      double *__restrict__ Yroll, int32_t *status)
+// The sweep over stages k1-1 .. k0 from the carry St.  The stage data comes
+// through LDS as in the fused fold (the loads of stage k-1 are in flight
+// during stage k).  MR: cross terms present; ROLL: fold the rollout maps.
+template <int NK, int PR, bool MR, bool ROLL>
+LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &V, int k0, int k1, Tile &St,
+                           Tile &PhiT, int &code, int &fk, double *lds, double *stg)
 {
-    __shared__ double lds[SLOT];
-    const int gs = blockIdx.x;
-    const int i = find_inst(seg_start, batch, gs);
-    const InstDesc d = inst[i];
-    const int s = gs - d.seg0;
-    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    constexpr int SZ = stage_buf_size<NK>();
     const int n = d.n, m = d.m;
-    const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
-    Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
-    if (s == d.nseg - 1) {
-        gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
-        store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
-    }
-    int code = 0, fk = 0;
-    const bool roll = (Yroll != nullptr);
-    Tile PhiT = tident(n + 1);
-    for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Ah = load_Ah(P, d, k), Bh = load_Bh(P, d, k), Qh = load_Qh(P, d, k), Rk = load_R(P, d, k);
-        const Tile MhT = has_mr ? load_MhT(P, d, k) : tzero();
-        const Tile BhT = roll ? load_BhT(P, d, k) : tzero();
+    const StageLayout L = stage_layout(n, m);
+    StageFetch<NK, MR> f;
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    stage_fetch<NK, MR>(P, d, k1 - 1, f);
+    stage_put<NK, MR>(stg, L, d, f);
+    wsync();
+    int b = 0;
+    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        stage_fetch<NK, MR>(P, d, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+        const Tile Ah = gather(cur, gmap_Ah(L, n)), Bh = gather(cur, gmap_Bh(L, n, m));
+        const Tile Qh = gather(cur, gmap_Qh(L, n)), Rk = gather(cur, gmap_R(L, m));
+        const Tile MhT = MR ? gather(cur, gmap_MhT(L, n, m)) : tzero();
+        const Tile BhT = ROLL ? gather(cur, gmap_BhT(L, n, m)) : tzero();
         const Tile SB = tnz<NK, PR>(St, Bh);          // S~'B~
         const Tile SA = tnz<NK, PR>(St, Ah);          // S~'A~
         const Tile Quu = tna<NK, PR>(Bh, SB, Rk);     // R + B~'S~'B~
@@ -391,12 +389,50 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         Tile Gh = tnz<1, PR>(QiT, Qux);
         Gh.v = -Gh.v;                                 // -Q_uu^{-1} Q_ux~
         Sn = tna<1, PR>(Qux, Gh, Sn);                 // + Q_ux~' Gamma~
-        if (roll) PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gh, Ah), PhiT);   // (Phi F~_k)' = F~_k' Phi'
+        if (ROLL) PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gh, Ah), PhiT);   // (Phi F~_k)' = F~_k' Phi'
         St = tsym(Sn, lds);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
         store_vec(V.g + d.og + (int64_t)k * m, Gh, m, n);
+        stage_put<NK, MR>(stg + (b ^ 1) * SZ, L, d, f);
+        wsync();
+    }
+}
+
+template <int NK, int PR>
+__global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                      const int32_t *__restrict__ seg_start, int batch,
+                                                      const double *__restrict__ Xfin, ValPtrs V,
+                                                      double *__restrict__ Yroll, int32_t *status)
+{
+    __shared__ double lds[SLOT];
+    __shared__ double stg[2 * stage_buf_size<NK>()];
+    const int gs = blockIdx.x;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const int n = d.n;
+    const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
+    Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
+    if (s == d.nseg - 1) {
+        gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
+        store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
+    }
+    int code = 0, fk = 0;
+    const bool roll = (Yroll != nullptr);
+    Tile PhiT = tident(n + 1);
+    if (has_mr) {
+        if (roll)
+            riccati_sweep<NK, PR, true, true>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
+        else
+            riccati_sweep<NK, PR, true, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
+    } else {
+        if (roll)
+            riccati_sweep<NK, PR, false, true>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
+        else
+            riccati_sweep<NK, PR, false, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
     }
     if (roll) {
         if (s == 0) gstore(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n));
