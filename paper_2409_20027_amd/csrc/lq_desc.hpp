@@ -320,12 +320,14 @@ LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
 }
 LQK_DEV void store_vec(double *v, const Tile &t, int len, int col)
 {
-    if (tcol() == col) {
+    if (!v || len <= 0) return;
+    const __amdgpu_buffer_rsrc_t rs = brsrc(v, len);
+    const bool mine = (tcol() == col);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = trow(r);
-            if (i < len) v[i] = t.v[r];
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double x = t.v[r];
+        bstore(rs, (mine && i < len) ? 8 * i : BOOB, x);
     }
 }
 
@@ -371,85 +373,97 @@ constexpr int stage_buf_size()
     return 2 + 2 * nm * nm + 2 * nm + 2 * nm * MMAX + MMAX * MMAX + MMAX + 64;
 }
 
-// Register slots of one stage's copy: ceil(len / 64) per array at the
-// largest sizes.
-template <int NK, bool MR>
-struct StageFetch {
-    static constexpr int NM = 4 * NK - 1;
-    static constexpr int SA = (NM * NM + 63) / 64, SV = 1, SB = (NM * MMAX + 63) / 64, SR = 1;
-    static constexpr int N = 2 * SA + 2 * SV + SB + SR + (MR ? SB + SV : 0);
-    double v[N];
+// One array of a stage's data: stage k's elements are
+// base[k * stride .. k * stride + len), copied to buffer offset off.  A null
+// array reads as zeros: an empty range over a valid address.
+struct StageArr {
+    const double *base;
+    int64_t stride;
+    int bytes, len, off;
+};
+LQK_DEV StageArr stage_arr(const double *p, int64_t stride, int len, int off)
+{
+    StageArr a;
+    a.base = p ? p : zptr();
+    a.stride = p ? stride : 0;
+    a.bytes = p ? 8 * len : 0;
+    a.len = len;
+    a.off = off;
+    return a;
+}
+
+// Register slots of the arrays in flight: S_j = ceil(max len_j / 64).
+template <int... S>
+struct StageRegs {
+    double v[(S + ... + 0)];
 };
 
+// Lane l loads elements l, l + 64, ... of stage k's array (0 past its end).
 template <int S>
-LQK_DEV void fetch_array(const double *src, int len, double *v)
+LQK_DEV void fetch_arr(const StageArr &a, int k, double *v)
+{
+    // stage offsets inside one instance's array fit 32 bits
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(a.base + (uint32_t)(k * (int)a.stride)), (short)0, a.bytes, 0x00020000);
+#pragma unroll
+    for (int j = 0; j < S; ++j) v[j] = bload(r, lane() + 64 * j);
+}
+// ... and writes them to the buffer (lanes past the array to the write-off area).
+template <int S>
+LQK_DEV void put_arr(double *buf, const StageArr &a, int trash, const double *v)
 {
 #pragma unroll
     for (int j = 0; j < S; ++j) {
         const int idx = lane() + 64 * j;
-        v[j] = ldz(src, idx, src != nullptr && idx < len);
-    }
-}
-template <int S>
-LQK_DEV void put_array(double *buf, int off, int len, int trash, const double *v)
-{
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        const int idx = lane() + 64 * j;
-        buf[idx < len ? off + idx : trash + lane()] = v[j];
+        buf[idx < a.len ? a.off + idx : trash + lane()] = v[j];
     }
 }
 
-// Loads of stage k into registers (arrays that are null read as zeros).
-template <int NK, bool MR>
-LQK_DEV void stage_fetch(const ProbPtrs &P, const InstDesc &d, int k, StageFetch<NK, MR> &f)
+template <int... S>
+LQK_DEV void arr_fetch(const StageArr *a, int k, StageRegs<S...> &f)
 {
-    using F = StageFetch<NK, MR>;
-    const int n = d.n, m = d.m;
-    double *v = f.v;
-    fetch_array<F::SA>(P.A + d.oA + (int64_t)k * n * n, n * n, v);
-    v += F::SA;
-    fetch_array<F::SV>(P.c ? P.c + d.oc + (int64_t)k * n : nullptr, n, v);
-    v += F::SV;
-    fetch_array<F::SA>(P.Q + d.oA + (int64_t)k * n * n, n * n, v);
-    v += F::SA;
-    fetch_array<F::SV>(P.q ? P.q + d.oc + (int64_t)k * n : nullptr, n, v);
-    v += F::SV;
-    fetch_array<F::SB>(P.B + d.oB + (int64_t)k * n * m, n * m, v);
-    v += F::SB;
-    fetch_array<F::SR>(P.R + d.oR + (int64_t)k * m * m, m * m, v);
-    v += F::SR;
-    if constexpr (MR) {
-        fetch_array<F::SB>(P.M ? P.M + d.oB + (int64_t)k * n * m : nullptr, n * m, v);
-        v += F::SB;
-        fetch_array<F::SV>(P.r ? P.r + d.og + (int64_t)k * m : nullptr, m, v);
-    }
+    int j = 0, o = 0;
+    ((fetch_arr<S>(a[j], k, f.v + o), o += S, ++j), ...);
+}
+template <int... S>
+LQK_DEV void arr_put(double *buf, const StageArr *a, int trash, const StageRegs<S...> &f)
+{
+    int j = 0, o = 0;
+    ((put_arr<S>(buf, a[j], trash, f.v + o), o += S, ++j), ...);
 }
 
-// The fetched registers into a buffer (after the constant slots).
+// The problem arrays of a value-pass stage: A, c, Q, q, B, R, and with cross
+// terms (MR) M, r.
 template <int NK, bool MR>
-LQK_DEV void stage_put(double *buf, const StageLayout &L, const InstDesc &d, const StageFetch<NK, MR> &f)
+struct ValueStage;
+template <int NK>
+struct ValueStage<NK, false> {
+    static constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
+    using Regs = StageRegs<SA, 1, SA, 1, SB, 1>;
+    StageArr a[6];
+};
+template <int NK>
+struct ValueStage<NK, true> {
+    static constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
+    using Regs = StageRegs<SA, 1, SA, 1, SB, 1, SB, 1>;
+    StageArr a[8];
+};
+template <int NK, bool MR>
+LQK_DEV ValueStage<NK, MR> value_stage(const ProbPtrs &P, const InstDesc &d, const StageLayout &L)
 {
-    using F = StageFetch<NK, MR>;
+    ValueStage<NK, MR> v;
     const int n = d.n, m = d.m;
-    const double *v = f.v;
-    put_array<F::SA>(buf, L.oA, n * n, L.trash, v);
-    v += F::SA;
-    put_array<F::SV>(buf, L.oc, n, L.trash, v);
-    v += F::SV;
-    put_array<F::SA>(buf, L.oQ, n * n, L.trash, v);
-    v += F::SA;
-    put_array<F::SV>(buf, L.oq, n, L.trash, v);
-    v += F::SV;
-    put_array<F::SB>(buf, L.oB, n * m, L.trash, v);
-    v += F::SB;
-    put_array<F::SR>(buf, L.oR, m * m, L.trash, v);
-    v += F::SR;
+    v.a[0] = stage_arr(P.A + d.oA, n * n, n * n, L.oA);
+    v.a[1] = stage_arr(P.c ? P.c + d.oc : nullptr, n, n, L.oc);
+    v.a[2] = stage_arr(P.Q + d.oA, n * n, n * n, L.oQ);
+    v.a[3] = stage_arr(P.q ? P.q + d.oc : nullptr, n, n, L.oq);
+    v.a[4] = stage_arr(P.B + d.oB, n * m, n * m, L.oB);
+    v.a[5] = stage_arr(P.R + d.oR, m * m, m * m, L.oR);
     if constexpr (MR) {
-        put_array<F::SB>(buf, L.oM, n * m, L.trash, v);
-        v += F::SB;
-        put_array<F::SV>(buf, L.orr, m, L.trash, v);
+        v.a[6] = stage_arr(P.M ? P.M + d.oB : nullptr, n * m, n * m, L.oM);
+        v.a[7] = stage_arr(P.r ? P.r + d.og : nullptr, m, m, L.orr);
     }
+    return v;
 }
 
 LQK_DEV void stage_consts(double *buf)
@@ -541,6 +555,18 @@ LQK_DEV Tile gather(const double *buf, const GMap &g)
 #pragma unroll
     for (int r = 0; r < 4; ++r) t.v[r] = buf[g.a[r]];
     return t;
+}
+
+// Tile maps from a function (row, col) -> buffer index (0: the 0.0 slot,
+// 1: the 1.0 slot).
+template <class F>
+LQK_DEV GMap gmap_of(F idx)
+{
+    GMap g;
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) g.a[r] = idx(trow(r), c);
+    return g;
 }
 
 }  // namespace lqk

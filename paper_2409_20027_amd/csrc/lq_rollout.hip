@@ -96,21 +96,54 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
                                                    const double *__restrict__ Yfin, double *__restrict__ x,
                                                    double *__restrict__ u, double *__restrict__ lam)
 {
+    // stage data through LDS, the next stage's loads in flight during this one
+    constexpr int NM = 4 * NK - 1;
+    constexpr int SZ = 2 + 2 * NM * NM + 2 * NM + 2 * NM * MMAX + MMAX + 64;
+    __shared__ double stg[2 * SZ];
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
+    const int oA = 2, oc = oA + n * n, oB = oc + n, oG = oB + n * m, og = oG + m * n, oS = og + m, os = oS + n * n,
+              trash = os + n;
+    const StageArr arr[7] = {stage_arr(P.A + d.oA, n * n, n * n, oA),
+                             stage_arr(P.c ? P.c + d.oc : nullptr, n, n, oc),
+                             stage_arr(P.B + d.oB, n * m, n * m, oB),
+                             stage_arr(V.G + d.oG, m * n, m * n, oG),
+                             stage_arr(V.g ? V.g + d.og : nullptr, m, m, og),
+                             stage_arr(lam ? V.S + d.oS : nullptr, n * n, n * n, oS),
+                             stage_arr(lam ? V.s + d.os : nullptr, n, n, os)};
+    constexpr int SA = (NM * NM + 63) / 64;
+    StageRegs<SA, 1, 1, 1, 1, SA, 1> f;
+    // Gamma~' = [[Gamma'], [gamma']], A~' = [[A', 0], [c', 1]], B~' = [B', 0], S~ = [[S, s], [s', 0]]
+    const GMap gG = gmap_of([&](int r, int c) { return (c < m && r < n) ? oG + c * n + r : (c < m && r == n) ? og + c : 0; });
+    const GMap gA = gmap_of([&](int r, int c) {
+        return (r < n && c < n) ? oA + c * n + r : (r == n && c < n) ? oc + c : (r == n && c == n) ? 1 : 0;
+    });
+    const GMap gB = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
+    const GMap gS = gmap_of([&](int r, int c) {
+        return (r < n && c < n) ? oS + r * n + c : (c == n && r < n) ? os + r : (r == n && c < n) ? os + c : 0;
+    });
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    arr_fetch(arr, k0, f);
+    arr_put(stg, arr, trash, f);
+    wsync();
     Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
-    for (int k = k0; k < k1; ++k) {
-        const Tile GhT = load_GhT(V.G, V.g, d, k), AhT = load_AhT(P, d, k), BhT = load_BhT(P, d, k);
-        const Tile Sh = lam ? load_Sh(V.S, V.s, d, k) : tzero();
+    int b = 0;
+    for (int k = k0; k < k1; ++k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        arr_fetch(arr, min(k + 1, k1 - 1), f);
+        const Tile GhT = gather(cur, gG), AhT = gather(cur, gA), BhT = gather(cur, gB);
         store_vec(x + d.os + (int64_t)k * n, X, n, n);
         const Tile Uk = tnz<NK, PR>(GhT, X);                       // Gamma~ x~
         store_vec(u + d.og + (int64_t)k * m, Uk, m, n);
-        if (lam) store_vec(lam + d.os + (int64_t)k * n, tnz<NK, PR>(Sh, X), n, n);
+        if (lam) store_vec(lam + d.os + (int64_t)k * n, tnz<NK, PR>(gather(cur, gS), X), n, n);
         X = tna<1, PR>(BhT, Uk, tnz<NK, PR>(AhT, X));              // A~ x~ + B~ u
+        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
+        wsync();
     }
     if (k1 == d.T) {
         store_vec(x + d.os + (int64_t)d.T * n, X, n, n);

@@ -115,6 +115,30 @@ LQK_DEV double ldg(const double *p)
     asm("" : "+v"(a));
     return *(const __attribute__((address_space(1))) double *)a;
 }
+// A raw buffer resource over the first len doubles at p (p null: an empty
+// range).  The hardware's range check returns 0 for a load past the end, so a
+// masked load needs no per-lane address selection.
+LQK_DEV __amdgpu_buffer_rsrc_t brsrc(const double *p, int len)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(p ? p : zptr()), (short)0, p ? len * 8 : 0, 0x00020000);
+}
+// Element idx of the range (0 past its end).
+LQK_DEV double bload(__amdgpu_buffer_rsrc_t r, int idx)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    const u2 v = __builtin_amdgcn_raw_buffer_load_b64(r, idx * 8, 0, 0);
+    return __builtin_bit_cast(double, v);
+}
+
+// Store to byte offset off of the range; a store at or past its end is
+// dropped by the same check, so a masked store needs no branch.
+constexpr int BOOB = (int)0x80000000u;   // an offset past any range
+LQK_DEV void bstore(__amdgpu_buffer_rsrc_t r, int off, double x)
+{
+    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
+}
+
 // p[idx] if ok, else 0 (from a constant in memory).
 LQK_DEV const double *at(const double *p, int64_t idx, bool ok) { return ok ? p + idx : zptr(); }
 LQK_DEV double ldz(const double *p, int64_t idx, bool ok) { return ldg(at(p, idx, ok)); }
@@ -149,11 +173,14 @@ LQK_DEV Tile gload_rm_t(const double *src, int rows, int cols, int ld, int i0 = 
 // Store the rows x cols block at tile offset (i0, j0) to row-major dst.
 LQK_DEV void gstore_rm(double *dst, const Tile &t, int rows, int cols, int ld, int i0 = 0, int j0 = 0)
 {
+    if (!dst || rows <= 0 || cols <= 0) return;
+    const __amdgpu_buffer_rsrc_t rs = brsrc(dst, (rows - 1) * ld + cols);
     const int c = tcol() - j0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = trow(r) - i0;
-        if (i >= 0 && i < rows && c >= 0 && c < cols) dst[i * ld + c] = t.v[r];
+        const double x = t.v[r];
+        bstore(rs, (i >= 0 && i < rows && c >= 0 && c < cols) ? 8 * (i * ld + c) : BOOB, x);
     }
 }
 

@@ -113,7 +113,7 @@ LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
 }
 
 // Fused element build + fold over stages k1-1 .. k0 (right to left).  The
-// stage data comes through LDS (stage_fetch / stage_put / gather): stage
+// stage data comes through LDS (arr_fetch / arr_put / gather): stage
 // k-1's loads are issued at the top of step k and written to the other buffer
 // after its compute.
 template <int NK, int NB, int PR, bool MR>
@@ -123,16 +123,17 @@ LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Ti
     constexpr int SZ = stage_buf_size<NK>();
     const int n = d.n, m = d.m;
     const StageLayout L = stage_layout(n, m);
-    StageFetch<NK, MR> f;
+    const ValueStage<NK, MR> VS = value_stage<NK, MR>(P, d, L);
+    typename ValueStage<NK, MR>::Regs f;
     stage_consts(stg);
     stage_consts(stg + SZ);
-    stage_fetch<NK, MR>(P, d, k1 - 1, f);
-    stage_put<NK, MR>(stg, L, d, f);
+    arr_fetch(VS.a, k1 - 1, f);
+    arr_put(stg, VS.a, L.trash, f);
     wsync();
     int b = 0;
     for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
         const double *cur = stg + b * SZ;
-        stage_fetch<NK, MR>(P, d, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+        arr_fetch(VS.a, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
         StageRaw<MR> w;
         w.A = gather(cur, gmap_Ah(L, n));
         w.Q = gather(cur, gmap_Qh(L, n));
@@ -145,7 +146,7 @@ LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Ti
         StageElem e;
         note(build_from_raw<PR, MR>(w, d, e), ERR_NOT_PD, k, code, fk);
         note(fold_left<NK, NB, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
-        stage_put<NK, MR>(stg + (b ^ 1) * SZ, L, d, f);
+        arr_put(stg + (b ^ 1) * SZ, VS.a, L.trash, f);
         wsync();
     }
 }
@@ -365,16 +366,17 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
     constexpr int SZ = stage_buf_size<NK>();
     const int n = d.n, m = d.m;
     const StageLayout L = stage_layout(n, m);
-    StageFetch<NK, MR> f;
+    const ValueStage<NK, MR> VS = value_stage<NK, MR>(P, d, L);
+    typename ValueStage<NK, MR>::Regs f;
     stage_consts(stg);
     stage_consts(stg + SZ);
-    stage_fetch<NK, MR>(P, d, k1 - 1, f);
-    stage_put<NK, MR>(stg, L, d, f);
+    arr_fetch(VS.a, k1 - 1, f);
+    arr_put(stg, VS.a, L.trash, f);
     wsync();
     int b = 0;
     for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
         const double *cur = stg + b * SZ;
-        stage_fetch<NK, MR>(P, d, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+        arr_fetch(VS.a, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
         const Tile Ah = gather(cur, gmap_Ah(L, n)), Bh = gather(cur, gmap_Bh(L, n, m));
         const Tile Qh = gather(cur, gmap_Qh(L, n)), Rk = gather(cur, gmap_R(L, m));
         const Tile MhT = MR ? gather(cur, gmap_MhT(L, n, m)) : tzero();
@@ -395,7 +397,7 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
         store_vec(V.g + d.og + (int64_t)k * m, Gh, m, n);
-        stage_put<NK, MR>(stg + (b ^ 1) * SZ, L, d, f);
+        arr_put(stg + (b ^ 1) * SZ, VS.a, L.trash, f);
         wsync();
     }
 }
