@@ -37,16 +37,38 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
     if (s == d.nseg - 1)
         gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * n, n, n, n));
     if (s == 0) return;   // never read: segment s starts from entry s + 1
+    // stage data through LDS, the next stage's loads in flight during this one
+    constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
+    constexpr int SZ = 2 + NM * NM + 2 * NM * MMAX + MMAX + NM + 64;
+    __shared__ double stg[2 * SZ];
+    const int oA = 2, oG = oA + n * n, oB = oG + m * n, ou = oB + n * m, ox = ou + m, trash = ox + n;
+    const StageArr arr[5] = {stage_arr(P.A + d.oA, n * n, n * n, oA), stage_arr(J.G + d.oG, m * n, m * n, oG),
+                             stage_arr(P.B + d.oB, n * m, n * m, oB), stage_arr(J.gu + d.og, m, m, ou),
+                             stage_arr(J.gx + d.os, n, n, ox)};
+    StageRegs<SA, SB, SB, 1, 1> f;
+    // A_noc~' = [[A', 0], [0, 1]], Gamma_0~ = [Gamma, 0], B~' = [B', 0], gu and gx in column n
+    const GMap gA = gmap_of([&](int r, int c) { return (r < n && c < n) ? oA + c * n + r : (r == n && c == n) ? 1 : 0; });
+    const GMap gG = gmap_of([&](int r, int c) { return (r < m && c < n) ? oG + r * n + c : 0; });
+    const GMap gB = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
+    const GMap gU = gmap_of([&](int r, int c) { return (c == n && r < m) ? ou + r : 0; });
+    const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    arr_fetch(arr, k0, f);
+    arr_put(stg, arr, trash, f);
+    wsync();
     Tile PsiT = tident(n + 1);
-    for (int k = k0; k < k1; ++k) {
+    int b = 0;
+    for (int k = k0; k < k1; ++k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        arr_fetch(arr, min(k + 1, k1 - 1), f);
         // R(Y~_k) = A_noc~' + Gamma_0~'(B~' + [gu in column n]) + [gx in column n]
-        const Tile AnT = load_AhT(P, d, k, false);
-        const Tile G0 = load_Gh(J.G, nullptr, d, k);
-        const Tile BhT = load_BhT(P, d, k);
-        const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
-        const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
+        const Tile AnT = gather(cur, gA), G0 = gather(cur, gG), BhT = gather(cur, gB);
+        const Tile GU = gather(cur, gU), GX = gather(cur, gX);
         const Tile Yk = tna<1, PR>(G0, tadd(BhT, GU), tadd(AnT, GX));
         PsiT = tnz<NK, PR>(Yk, PsiT);   // (Psi Y~_k)' = Y~_k' Psi'
+        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
+        wsync();
     }
     gstore(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds));
 }
@@ -75,12 +97,42 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     Tile SV = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);   // [[0, s~_{k1}], [0, 1]]
     if (s == d.nseg - 1) store_vec(J.st + d.os + (int64_t)d.T * n, SV, n, n);
     int code = 0, fk = 0;
+    // stage data through LDS, the next stage's loads in flight during this one
+    constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
+    constexpr int SZ = 2 + 2 * NM * NM + 2 * NM * MMAX + MMAX * MMAX + 2 * NM + MMAX + 64;
+    __shared__ double stg[2 * SZ];
+    const int oA = 2, oB = oA + n * n, oR = oB + n * m, oG = oR + m * m, oS = oG + m * n, os = oS + n * n,
+              ou = os + n, ox = ou + m, trash = ox + n;
+    // S~ and s~ of stage k + 1 with stage k's data
+    const StageArr arr[8] = {stage_arr(P.A + d.oA, n * n, n * n, oA),   stage_arr(P.B + d.oB, n * m, n * m, oB),
+                             stage_arr(P.R + d.oR, m * m, m * m, oR),   stage_arr(J.G + d.oG, m * n, m * n, oG),
+                             stage_arr(J.S + d.oS + n * n, n * n, n * n, oS), stage_arr(J.s + d.os + n, n, n, os),
+                             stage_arr(J.gu + d.og, m, m, ou),          stage_arr(J.gx + d.os, n, n, ox)};
+    StageRegs<SA, SB, 1, SB, SA, 1, 1, 1> f;
+    // B~, B~', S~ = [[S, s], [s', 0]], R, A_noc~ = [[A, 0], [0, 1]], Gamma_0~ = [Gamma, 0], gu and gx in column n
+    const GMap gBh = gmap_of([&](int r, int c) { return (r < n && c < m) ? oB + r * m + c : 0; });
+    const GMap gBt = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
+    const GMap gS = gmap_of([&](int r, int c) {
+        return (r < n && c < n) ? oS + r * n + c : (c == n && r < n) ? os + r : (r == n && c < n) ? os + c : 0;
+    });
+    const GMap gR = gmap_of([&](int r, int c) { return (r < m && c < m) ? oR + r * m + c : 0; });
+    const GMap gA = gmap_of([&](int r, int c) { return (r < n && c < n) ? oA + r * n + c : (r == n && c == n) ? 1 : 0; });
+    const GMap gG = gmap_of([&](int r, int c) { return (r < m && c < n) ? oG + r * n + c : 0; });
+    const GMap gU = gmap_of([&](int r, int c) { return (c == n && r < m) ? ou + r : 0; });
+    const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    arr_fetch(arr, k1 - 1, f);
+    arr_put(stg, arr, trash, f);
+    wsync();
     Tile PhiT = tident(n + 1);
-    for (int k = k1 - 1; k >= k0; --k) {
-        const Tile Bh = load_Bh(P, d, k), BhT = load_BhT(P, d, k), Sh = load_Sh(J.S, J.s, d, k + 1);
-        const Tile Rk = load_R(P, d, k), An = load_Ah(P, d, k, false), G0 = load_Gh(J.G, nullptr, d, k);
-        const Tile GU = load_vec(J.gu + d.og + (int64_t)k * m, m, n, -1);
-        const Tile GX = load_vec(J.gx + d.os + (int64_t)k * n, n, n, -1);
+    int b = 0;
+    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        arr_fetch(arr, max(k - 1, k0), f);
+        const Tile Bh = gather(cur, gBh), BhT = gather(cur, gBt), Sh = gather(cur, gS);
+        const Tile Rk = gather(cur, gR), An = gather(cur, gA), G0 = gather(cur, gG);
+        const Tile GU = gather(cur, gU), GX = gather(cur, gX);
         const Tile SB = tnz<NK, PR>(Sh, Bh);                 // S~_{k+1} B~
         const Tile Quu = tna<NK, PR>(Bh, SB, Rk);            // R + B~'S~B~
         Tile QiT;
@@ -97,6 +149,8 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
         PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gt, F), PhiT);   // (Phi F'_k)' = F'_k' Phi'
         SV = tna<NK, PR>(F, SV, tna<1, PR>(G0, GU, GX));
         store_vec(J.st + d.os + (int64_t)k * n, SV, n, n);
+        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
+        wsync();
     }
     if (s == 0) gstore(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n));   // dx_0 = 0
     if (s < d.nseg - 1) gstore(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds));
@@ -117,11 +171,42 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int n = d.n, m = d.m;
     Tile DX = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, dx_k0], [0, 1]]
     if (s == 0 && Gr.x0) store_vec(Gr.x0 + d.on, tnz<NK, PR>(load_Sh(J.S, J.st, d, 0), DX), n, n);
-    for (int k = k0; k < k1; ++k) {
-        const Tile GhT = load_GhT(J.G, J.gt, d, k), BhT = load_BhT(P, d, k), AnT = load_AhT(P, d, k, false);
-        const Tile S1 = load_Sh(J.S, J.st, d, k + 1);
-        const Tile X = load_vec(J.x + d.os + (int64_t)k * n, n, n, -1), U = load_vec(J.u + d.og + (int64_t)k * m, m, n, -1);
-        const Tile L1 = load_vec(J.lam + d.os + (int64_t)(k + 1) * n, n, n, -1);
+    // stage data through LDS, the next stage's loads in flight during this one
+    constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
+    constexpr int SZ = 2 + 2 * NM * NM + 2 * NM * MMAX + 4 * NM + 2 * MMAX + 64;
+    __shared__ double stg[2 * SZ];
+    const int oG = 2, og = oG + m * n, oB = og + m, oA = oB + n * m, oS = oA + n * n, os = oS + n * n, ox = os + n,
+              ou = ox + n, ol = ou + m, trash = ol + n;
+    // S~, s~ and lambda of stage k + 1 with stage k's data
+    const StageArr arr[9] = {stage_arr(J.G + d.oG, m * n, m * n, oG),   stage_arr(J.gt + d.og, m, m, og),
+                             stage_arr(P.B + d.oB, n * m, n * m, oB),   stage_arr(P.A + d.oA, n * n, n * n, oA),
+                             stage_arr(J.S + d.oS + n * n, n * n, n * n, oS), stage_arr(J.st + d.os + n, n, n, os),
+                             stage_arr(J.x + d.os, n, n, ox),           stage_arr(J.u + d.og, m, m, ou),
+                             stage_arr(J.lam + d.os + n, n, n, ol)};
+    StageRegs<SB, 1, SB, SA, SA, 1, 1, 1, 1> f;
+    // Gamma~' = [[Gamma'], [gamma~']], B~', A_noc~', S~, x, u, lambda in column n
+    const GMap gG = gmap_of([&](int r, int c) { return (c < m && r < n) ? oG + c * n + r : (c < m && r == n) ? og + c : 0; });
+    const GMap gB = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
+    const GMap gA = gmap_of([&](int r, int c) { return (r < n && c < n) ? oA + c * n + r : (r == n && c == n) ? 1 : 0; });
+    const GMap gS = gmap_of([&](int r, int c) {
+        return (r < n && c < n) ? oS + r * n + c : (c == n && r < n) ? os + r : (r == n && c < n) ? os + c : 0;
+    });
+    const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
+    const GMap gU = gmap_of([&](int r, int c) { return (c == n && r < m) ? ou + r : 0; });
+    const GMap gL = gmap_of([&](int r, int c) { return (c == n && r < n) ? ol + r : 0; });
+    stage_consts(stg);
+    stage_consts(stg + SZ);
+    arr_fetch(arr, k0, f);
+    arr_put(stg, arr, trash, f);
+    wsync();
+    int b = 0;
+    for (int k = k0; k < k1; ++k, b ^= 1) {
+        const double *cur = stg + b * SZ;
+        arr_fetch(arr, min(k + 1, k1 - 1), f);
+        const Tile GhT = gather(cur, gG), BhT = gather(cur, gB), AnT = gather(cur, gA);
+        const Tile S1 = gather(cur, gS);
+        const Tile X = gather(cur, gX), U = gather(cur, gU);
+        const Tile L1 = gather(cur, gL);
         const Tile DU = tnz<NK, PR>(GhT, DX);                          // Gamma dx + gamma~
         const Tile DXn = tna<1, PR>(BhT, DU, tnz<NK, PR>(AnT, DX));    // A dx + B du
         const Tile DL1 = tnz<NK, PR>(S1, DXn);                         // S dx' + s~'
@@ -157,6 +242,8 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
         if (Gr.q) store_vec(Gr.q + d.oc + (int64_t)k * n, DX, n, n);
         if (Gr.r) store_vec(Gr.r + d.og + (int64_t)k * m, DU, m, n);
         DX = DXn;
+        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
+        wsync();
     }
     if (k1 == d.T) {
         const Tile X = load_vec(J.x + d.os + (int64_t)d.T * n, n, n, -1);
