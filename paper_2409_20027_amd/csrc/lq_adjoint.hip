@@ -191,9 +191,12 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const GMap gS = gmap_of([&](int r, int c) {
         return (r < n && c < n) ? oS + r * n + c : (c == n && r < n) ? os + r : (r == n && c < n) ? os + c : 0;
     });
-    const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
-    const GMap gU = gmap_of([&](int r, int c) { return (c == n && r < m) ? ou + r : 0; });
-    const GMap gL = gmap_of([&](int r, int c) { return (c == n && r < n) ? ol + r : 0; });
+    // x, u, lambda at each lane's rows, and x, u at its column (the outer
+    // products' operands, read straight from the buffer)
+    const GMap gXr = gmap_of([&](int r, int c) { return r < n ? ox + r : 0; });
+    const GMap gUr = gmap_of([&](int r, int c) { return r < m ? ou + r : 0; });
+    const GMap gLr = gmap_of([&](int r, int c) { return r < n ? ol + r : 0; });
+    const int iXc = tcol() < n ? ox + tcol() : 0, iUc = tcol() < m ? ou + tcol() : 0;
     stage_consts(stg);
     stage_consts(stg + SZ);
     arr_fetch(arr, k0, f);
@@ -205,14 +208,13 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
         arr_fetch(arr, min(k + 1, k1 - 1), f);
         const Tile GhT = gather(cur, gG), BhT = gather(cur, gB), AnT = gather(cur, gA);
         const Tile S1 = gather(cur, gS);
-        const Tile X = gather(cur, gX), U = gather(cur, gU);
-        const Tile L1 = gather(cur, gL);
+        const d4 x_r = gather(cur, gXr).v, u_r = gather(cur, gUr).v, l1_r = gather(cur, gLr).v;
+        const double x_c = cur[iXc], u_c = cur[iUc];
         const Tile DU = tnz<NK, PR>(GhT, DX);                          // Gamma dx + gamma~
         const Tile DXn = tna<1, PR>(BhT, DU, tnz<NK, PR>(AnT, DX));    // A dx + B du
         const Tile DL1 = tnz<NK, PR>(S1, DXn);                         // S dx' + s~'
-        const d4 dx_r = vrows(DX, n), x_r = vrows(X, n), du_r = vrows(DU, n), u_r = vrows(U, n);
-        const d4 l1_r = vrows(L1, n), dl1_r = vrows(DL1, n);
-        const double dx_c = vcol(DX, n), x_c = vcol(X, n), du_c = vcol(DU, n), u_c = vcol(U, n);
+        const d4 dx_r = vrows(DX, n), du_r = vrows(DU, n), dl1_r = vrows(DL1, n);
+        const double dx_c = vcol(DX, n), du_c = vcol(DU, n);
         if (Gr.A) {
             Tile o;
             o.v = l1_r * dx_c + dl1_r * x_c;

@@ -378,10 +378,9 @@ constexpr int stage_buf_size()
 // array reads as zeros: an empty range over a valid address.
 struct StageArr {
     const double *base;
-    int64_t stride;
-    int bytes, len, off;
+    int stride, bytes, len, off;   // stage offsets inside one instance's array fit 32 bits
 };
-LQK_DEV StageArr stage_arr(const double *p, int64_t stride, int len, int off)
+LQK_DEV StageArr stage_arr(const double *p, int stride, int len, int off)
 {
     StageArr a;
     a.base = p ? p : zptr();
@@ -402,9 +401,8 @@ struct StageRegs {
 template <int S>
 LQK_DEV void fetch_arr(const StageArr &a, int k, double *v)
 {
-    // stage offsets inside one instance's array fit 32 bits
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(a.base + (uint32_t)(k * (int)a.stride)), (short)0, a.bytes, 0x00020000);
+        (void *)(a.base + (uint32_t)(k * a.stride)), (short)0, a.bytes, 0x00020000);
 #pragma unroll
     for (int j = 0; j < S; ++j) v[j] = bload(r, lane() + 64 * j);
 }
