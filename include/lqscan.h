@@ -377,6 +377,19 @@ lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z,
                               int32_t transpose_x, int32_t transpose_y, int32_t precision, void *stream);
 
 /*
+ * Diagnostic: the solver's register Gauss-Jordan inverse (partial pivoting)
+ * of the leading n1 x n1 block of X (1 <= n1 <= 16).  homog != 0 declares X
+ * of the form [[M, 0], [r, 1]] (last column e_{n1-1}; n1 >= 2), as the value
+ * operator's I + J~C~; pivots are then taken among the first n1 - 1 rows.  X
+ * and Xinv are device pointers to row-major 16 x 16 FP64 arrays (entries
+ * outside the block are ignored; on success Xinv is zero there); *ok (device
+ * int32) receives 1, or 0 for a zero or non-finite pivot.  Used by the test
+ * suite to pin the pivot search.
+ */
+lq_status lq_selftest_tile_inverse(const double *X, double *Xinv, int32_t n1, int32_t homog, int32_t *ok,
+                                   void *stream);
+
+/*
  * Diagnostic phase timing.  Phases of the solve calls, in enqueue order (a
  * phase is one kernel launch, except the scans: one launch per level):
  */

@@ -627,4 +627,12 @@ lq_status lq_selftest_tile_mm(const double *X, const double *Y, const double *Z,
     return launched();
 }
 
+lq_status lq_selftest_tile_inverse(const double *X, double *Xinv, int32_t n1, int32_t homog, int32_t *ok,
+                                   void *stream)
+{
+    if (!X || !Xinv || !ok || n1 < 1 || n1 > 16 || (homog && n1 < 2)) return LQ_ERR_ARG;
+    lqk::launch_selftest_inv((hipStream_t)stream, X, Xinv, n1, homog, ok);
+    return launched();
+}
+
 }  // extern "C"

@@ -8,6 +8,7 @@ namespace lqk {
 
 void launch_build_elements(int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                            const int64_t *elem_start, int batch, double *elems, int32_t *status);
+void launch_selftest_inv(hipStream_t st, const double *X, double *Xi, int n1, int homog, int32_t *ok);
 void launch_selftest_mm(int pr, hipStream_t st, const double *X, const double *Y, const double *Z, double *D, int tx,
                         int ty);
 

@@ -537,6 +537,21 @@ __global__ __launch_bounds__(64) void k_selftest_mm(const double *X, const doubl
     gstore_rm(D, tna<4, PR>(xf, yf, zt), 16, 16, 16);
 }
 
+// Diagnostic: the register Gauss-Jordan inverse of the leading n1 x n1 block
+// of a row-major 16 x 16 input; *ok = success.
+__global__ __launch_bounds__(64) void k_selftest_inv(const double *X, double *Xi, int n1, int homog, int32_t *ok)
+{
+    Tile x = gload_rm(X, n1, n1, 16);
+    const bool good = gj_inverse<4>(x, n1, homog != 0);
+    gstore_rm(Xi, x, 16, 16, 16);
+    if (lane() == 0) *ok = good ? 1 : 0;
+}
+
+void launch_selftest_inv(hipStream_t st, const double *X, double *Xi, int n1, int homog, int32_t *ok)
+{
+    hipLaunchKernelGGL(k_selftest_inv, dim3(1), dim3(64), 0, st, X, Xi, n1, homog, ok);
+}
+
 void launch_build_elements(int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                            const int64_t *elem_start, int batch, double *elems, int32_t *status)
 {

@@ -78,10 +78,12 @@ _lib.lq_plan_phase_times.argtypes = [_plan_p, ctypes.POINTER(ctypes.c_double), c
 _lib.lq_plan_phase_times.restype = ctypes.c_int
 _lib.lq_selftest_tile_mm.argtypes = [_P, _P, _P, _P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P]
 _lib.lq_selftest_tile_mm.restype = ctypes.c_int
+_lib.lq_selftest_tile_inverse.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
+_lib.lq_selftest_tile_inverse.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout", "lq_rollout_cv",
-            "lq_solve", "lq_adjoint", "lq_selftest_tile_mm", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
+            "lq_solve", "lq_adjoint", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
           "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply",
@@ -252,6 +254,11 @@ def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: di
                                          ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
                                          _f64(gx), _f64(gu), ctypes.byref(g), _ptr(workspace), _ptr(status),
                                          _stream(stream)))
+
+
+def lq_selftest_tile_inverse(X, Xinv, n1, homog, ok, stream=None):
+    _check("lq_selftest_tile_inverse", _lib.lq_selftest_tile_inverse(_f64(X), _f64(Xinv), int(n1), int(homog),
+                                                                     _ptr(ok), _stream(stream)))
 
 
 def lq_selftest_tile_mm(X, Y, Z, D, tx=False, ty=False, precision="fp64", stream=None):

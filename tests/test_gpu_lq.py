@@ -87,6 +87,65 @@ def test_tile_mm_selftest(lq, tx, ty, prec, tol):
     assert rel(D.cpu().numpy(), ref) < tol
 
 
+def tile_inverse(lq, A, n1, homog=False):
+    X = np.zeros((16, 16))
+    X[:n1, :n1] = A
+    Xi = torch.zeros(16, 16, dtype=torch.float64, device="cuda")
+    ok = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lq.lq_selftest_tile_inverse(torch.tensor(X, dtype=torch.float64, device="cuda"), Xi, n1, homog, ok)
+    torch.cuda.synchronize()
+    Xi, ok = Xi.cpu().numpy(), bool(ok.item())
+    if ok:
+        assert not np.any(Xi[n1:, :]) and not np.any(Xi[:, n1:])
+    return Xi[:n1, :n1], ok
+
+
+@pytest.mark.parametrize("n1", [1, 2, 5, 6, 13, 16])
+def test_tile_inverse_pivoting(lq, n1):
+    """The register Gauss-Jordan inverse: a matrix whose pivots all lie on the
+    diagonal, one whose pivot for column j lies in row j + n1/2 (so the pivot
+    rows come from every register of the tile), the exact identity, and a
+    singular matrix."""
+    rng = np.random.default_rng(40 + n1)
+    A = rng.standard_normal((n1, n1))
+    np.fill_diagonal(A, 0.0)
+    A[np.diag_indices(n1)] = np.abs(A).sum(axis=0) + 0.5
+    Xi, ok = tile_inverse(lq, A, n1)
+    assert ok and rel(Xi, np.linalg.inv(A)) < 1e-13
+    if n1 > 1:
+        perm = np.roll(np.arange(n1), n1 // 2)
+        B = 0.05 * rng.standard_normal((n1, n1))
+        B[perm, np.arange(n1)] += 4.0 + rng.random(n1)   # dominant entry of column j in row perm[j]
+        Xi, ok = tile_inverse(lq, B, n1)
+        assert ok and rel(Xi, np.linalg.inv(B)) < 1e-12
+        S = rng.standard_normal((n1, n1))
+        S[:, n1 - 1] = 0.0
+        _, ok = tile_inverse(lq, S, n1)
+        assert not ok
+    Xi, ok = tile_inverse(lq, np.eye(n1), n1)
+    assert ok and np.array_equal(Xi, np.eye(n1))
+
+
+@pytest.mark.parametrize("n1", [2, 6, 13])
+def test_tile_inverse_homogeneous(lq, n1):
+    """[[M, 0], [r, 1]] with pivots taken among the first n1 - 1 rows, with and
+    without row exchanges."""
+    rng = np.random.default_rng(60 + n1)
+    for dominant in (True, False):
+        M = 0.1 * rng.standard_normal((n1 - 1, n1 - 1))
+        if dominant:
+            np.fill_diagonal(M, 0.0)
+            M[np.diag_indices(n1 - 1)] = np.abs(M).sum(axis=0) + 0.5
+        else:
+            M[np.roll(np.arange(n1 - 1), 1), np.arange(n1 - 1)] += 3.0
+        X = np.zeros((n1, n1))
+        X[:n1 - 1, :n1 - 1] = M
+        X[n1 - 1, :n1 - 1] = rng.standard_normal(n1 - 1)
+        X[n1 - 1, n1 - 1] = 1.0
+        Xi, ok = tile_inverse(lq, X, n1, homog=True)
+        assert ok and rel(Xi, np.linalg.inv(X)) < 1e-12
+
+
 def test_cfg0_small_scan(lq):
     inst = W.cfg0_small()
     per, status, plan = run(lq, [inst])
