@@ -113,10 +113,10 @@ def kernel_models(n, m, T=16384, L=16):
     }
     out = {k: {"flops": v["flops"] * T, "bytes": v["bytes"] * T, "launches": 1, "units": T,
                "unit_name": "stages"} for k, v in per_stage.items()}
-    # value scan: radix-2 Kogge-Stone over the nseg segment elements plus the
-    # terminal; per level each entry s >= 1 either combines with s + dd (a full
-    # combine, or a J-only one when the right operand already covers the
-    # terminal) or carries its J over.  A combine reads 6 (n1 x n1) matrices
+    # value scan: radix-2 Kogge-Stone over the segment elements 1 .. nseg-1
+    # (the last one folded onto the terminal element); per level each entry
+    # either combines with s + dd (a full combine, or a J-only one when the
+    # right operand already covers the terminal) or carries its J over.  A combine reads 6 (n1 x n1) matrices
     # and writes 3; its flops: X' (2 n1^2 n), the n x n Gauss-Jordan inverse
     # (2 n^3), Z, J2 A1, the J rule (3 x 2 n1^3), A2 Z, X^{-1} C1, two C
     # products (2 n1^3 + 2 n1^2 n + 2 x 2 n1^3).
@@ -127,12 +127,13 @@ def kernel_models(n, m, T=16384, L=16):
     fl = by = 0.0
     lev = combines = 0
     dd = 1
-    while dd < nseg:
+    last = nseg - 1
+    while dd < last:
         lev += 1
-        for s_ in range(1, nseg + 1):
-            if s_ + dd > nseg:
+        for s_ in range(1, last + 1):
+            if s_ + dd > last:
                 by += 2 * mat
-            elif s_ + 2 * dd - 1 >= nseg:
+            elif s_ + 2 * dd - 1 >= last:
                 fl += jonly_f
                 by += 5 * mat
                 combines += 1

@@ -290,9 +290,10 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
                                Xa, 0, status);
     });
     double *in = Xa, *o = Xb;
-    if (p->max_nseg > 1)
+    // entries 1 .. nseg-1 of each instance (the last holds the terminal)
+    if (p->max_nseg > 2)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
+            for (int dd = 1; dd < p->max_nseg - 1; dd *= 2) {
                 lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
                                      o, status);
                 std::swap(in, o);

@@ -14,12 +14,14 @@
 //
 // Segmented scan, three phases per instance:
 //   1. k_value_fold: each wave folds one segment of L stages right to left
-//      into one element.  A stage element has C~ = B~ R^{-1} B~' of rank m, so
+//      into one element (the last segment onto the terminal element, so its
+//      element is already a whole suffix).  A stage element has
+//      C~ = B~ R^{-1} B~' of rank m, so
 //      the operator with a stage element on the left needs only an m x m
 //      inverse (Woodbury):  X^{-1} = I - B~ W^{-1} B~'J^,  W = R + B~'J^ B~,
 //      and no factorisation of R itself (R enters only through W).
-//   2. k_value_ks: Kogge-Stone suffix scan over the segment elements plus the
-//      terminal element, one launch per level, general operator with an
+//   2. k_value_ks: Kogge-Stone suffix scan over the segment elements 1 ..
+//      nseg-1, one launch per level, general operator with an
 //      (n+1) x (n+1) Gauss-Jordan inverse (of X', which is what the products
 //      need).
 //   3. k_value_riccati: inside each segment the suffix is completed from the
@@ -207,8 +209,8 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
 }
 
 // ---------------------------------------------------------------------------
-// Phase 1: fold each segment into one element; also write the terminal
-// element after the last segment of each instance.
+// Phase 1: fold each segment s >= 1 into one element at entry s, the last
+// segment onto the terminal element.
 // Scan buffer entry = 3 tiles (A~, C~, J~).
 // ---------------------------------------------------------------------------
 //
@@ -239,15 +241,17 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
         }
         if (s == d.nseg - 1) return;
     } else {
-        if (s == d.nseg - 1) {  // terminal element after the last segment
-            double *t = X + (int64_t)(d.xbase + d.nseg) * 3 * TILE;
-            gstore(t, corner(d.n));
-            gstore(t + TILE, tzero());
-            gstore(t + 2 * TILE, load_terminal_J(P, d, lds));
-        }
         // The element of segment 0 is never read: the Bellman steps of
-        // segment s start from the scanned element s + 1.
+        // segment s start from the scanned element s + 1 (the last segment's
+        // from the terminal element itself).
         if (s == 0) return;
+        // The last segment folds onto the terminal element, so its entry is
+        // already the whole suffix (terminal-type) and the scan has one entry
+        // less.
+        if (s == d.nseg - 1) {
+            U = corner(d.n);
+            Jh = load_terminal_J(P, d, lds);
+        }
     }
     if (elems) {
         for (int k = k1 - 1; k >= k0; --k) {
@@ -276,9 +280,10 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
 
 // ---------------------------------------------------------------------------
 // Phase 2: one Kogge-Stone level of the suffix scan, X_s <- X_s (x) X_{s+dd}.
-// Before the level, X_s covers segments [s, s+dd-1] (clipped at the terminal
-// index nseg); it is terminal-type (A~ = corner, C~ = 0, only J~ meaningful)
-// once it covers nseg.  Terminal-type entries are only ever right operands.
+// Before the level, X_s covers segments [s, s+dd-1] (clipped at the last
+// segment nseg-1, whose element includes the terminal); it is terminal-type
+// (A~ = corner, C~ = 0, only J~ meaningful) once it covers nseg-1.
+// Terminal-type entries are only ever right operands.
 // With Y = X^{-1}, the products are
 //   Z = Y A~1,  J~ = Z'(J~2 A~1) + J~1,  A~ = A~2 Z,  C~ = A~2 (Y C~1) A~2' + C~2,
 // all P'Q of register tiles given R(Y') (the inverse of X' = I + J~2 C~1) and
@@ -316,14 +321,16 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
         b = e;
         b_term = false;
     } else {
+        // entries 1 .. nseg-1; the last already covers the terminal element
         a = Xin + (int64_t)gx * 3 * TILE;
-        if (s == 0) return;   // never read (see k_value_fold)
-        if (s + dd > nseg) {  // already final (terminal-type): carry J~ over
+        const int last = nseg - 1;
+        if (s == 0 || s > last) return;   // never read (see k_value_fold)
+        if (s + dd > last) {              // already final (terminal-type): carry J~ over
             gstore(o + 2 * TILE, gload(a + 2 * TILE));
             return;
         }
         b = Xin + (int64_t)(gx + dd) * 3 * TILE;
-        b_term = (s + 2 * dd - 1 >= nseg);
+        b_term = (s + 2 * dd - 1 >= last);
     }
     const int n1 = d.n + 1;
     const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
@@ -417,7 +424,10 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n;
     const bool has_mr = (P.M != nullptr) || (P.r != nullptr);
-    Tile St = gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
+    // the carry: the scanned suffix from segment s + 1, or for the last
+    // segment the terminal element
+    Tile St = (s == d.nseg - 1) ? load_terminal_J(P, d, lds)
+                                : gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
     if (s == d.nseg - 1) {
         gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
