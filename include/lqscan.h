@@ -88,7 +88,9 @@ typedef struct lq_plan lq_plan;   /* opaque */
  * (host arrays).  `seg_len` is the number of stages folded per segment of the
  * scan (0 = choose automatically, ignored in LQ_SEQUENTIAL mode).  Allocates
  * small device descriptor tables on the current device.
- * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED, LQ_ERR_HIP.
+ * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED (nx > 15, nu > 4, or an instance
+ * with (T + 1) nx^2 >= 2^31: stage offsets inside one instance's arrays are
+ * 32-bit), LQ_ERR_HIP.
  */
 lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
                          int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out);

@@ -44,6 +44,7 @@ def test_plan_create_rejects_bad_arguments(lib):
     assert f(1, arr(4), arr(5), arr(4), 0, 0, 0, ctypes.byref(plan)) == -7          # m too large
     assert f(1, arr(4), arr(1), arr(4), 7, 0, 0, ctypes.byref(plan)) == -1          # precision
     assert f(1, arr(4), arr(1), arr(4), 0, 0, -3, ctypes.byref(plan)) == -1         # seg_len
+    assert f(1, arr(15), arr(1), arr(10_000_000), 0, 0, 0, ctypes.byref(plan)) == -7  # (T + 1) n^2 >= 2^31
 
 
 def test_version(lib):
