@@ -139,6 +139,33 @@ LQK_DEV void bstore(__amdgpu_buffer_rsrc_t r, int off, double x)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, x), r, off, 0, 0);
 }
 
+// A tile's leading n1 x n1 block stored row-major with row stride n1 at p
+// (the start of a TILE slot): only n1^2 doubles move; the rest of the tile
+// is zero.
+LQK_DEV Tile gload_c(const double *p, int n1)
+{
+    const __amdgpu_buffer_rsrc_t rs = brsrc(p, n1 * n1);
+    const int c = tcol();
+    Tile t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        t.v[r] = bload(rs, (i < n1 && c < n1) ? i * n1 + c : n1 * n1);   // past the end: 0
+    }
+    return t;
+}
+LQK_DEV void gstore_c(double *p, const Tile &t, int n1)
+{
+    const __amdgpu_buffer_rsrc_t rs = brsrc(p, n1 * n1);
+    const int c = tcol();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        const double x = t.v[r];
+        bstore(rs, (i < n1 && c < n1) ? 8 * (i * n1 + c) : BOOB, x);
+    }
+}
+
 // p[idx] if ok, else 0 (from a constant in memory).
 LQK_DEV const double *at(const double *p, int64_t idx, bool ok) { return ok ? p + idx : zptr(); }
 LQK_DEV double ldz(const double *p, int64_t idx, bool ok) { return ldg(at(p, idx, ok)); }

@@ -211,7 +211,8 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
 // ---------------------------------------------------------------------------
 // Phase 1: fold each segment s >= 1 into one element at entry s, the last
 // segment onto the terminal element.
-// Scan buffer entry = 3 tiles (A~, C~, J~).
+// Scan buffer entry = 3 tiles (A~, C~, J~), each stored compactly: its n1 x n1
+// block row-major at the start of a TILE slot (gload_c / gstore_c).
 // ---------------------------------------------------------------------------
 //
 // prefix = 1 lays the entries out for the prefix scan of the conditional-value
@@ -235,9 +236,9 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     if (prefix) {
         if (s == 0) {
             double *t = X + (int64_t)d.xbase * 3 * TILE;
-            gstore(t, tident(n1));
-            gstore(t + TILE, tzero());
-            gstore(t + 2 * TILE, tzero());
+            gstore_c(t, tident(n1), n1);
+            gstore_c(t + TILE, tzero(), n1);
+            gstore_c(t + 2 * TILE, tzero(), n1);
         }
         if (s == d.nseg - 1) return;
     } else {
@@ -272,9 +273,9 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
             fold_fused_nb<NK, PR, false>(P, d, k0, k1, U, Ch, Jh, code, fk, stg);
     }
     double *o = X + (int64_t)(d.xbase + s + prefix) * 3 * TILE;
-    gstore(o, ttrans(U, lds));
-    gstore(o + TILE, tsym(Ch, lds));
-    gstore(o + 2 * TILE, tsym(Jh, lds));
+    gstore_c(o, ttrans(U, lds), n1);
+    gstore_c(o + TILE, tsym(Ch, lds), n1);
+    gstore_c(o + 2 * TILE, tsym(Jh, lds), n1);
     if (code) report(status, i, code, fk);
 }
 
@@ -305,6 +306,7 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
     const InstDesc d = inst[i];
     const int s = gx - d.xbase;
     const int nseg = d.nseg;
+    const int n1 = d.n + 1;
     double *o = Xout + (int64_t)gx * 3 * TILE;
     const double *a, *b;
     bool b_term;
@@ -312,9 +314,9 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
         if (s >= nseg) return;
         const double *e = Xin + (int64_t)gx * 3 * TILE;
         if (s < dd) {
-            gstore(o, gload(e));
-            gstore(o + TILE, gload(e + TILE));
-            gstore(o + 2 * TILE, gload(e + 2 * TILE));
+            gstore_c(o, gload_c(e, n1), n1);
+            gstore_c(o + TILE, gload_c(e + TILE, n1), n1);
+            gstore_c(o + 2 * TILE, gload_c(e + 2 * TILE, n1), n1);
             return;
         }
         a = Xin + (int64_t)(gx - dd) * 3 * TILE;
@@ -326,27 +328,26 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
         const int last = nseg - 1;
         if (s == 0 || s > last) return;   // never read (see k_value_fold)
         if (s + dd > last) {              // already final (terminal-type): carry J~ over
-            gstore(o + 2 * TILE, gload(a + 2 * TILE));
+            gstore_c(o + 2 * TILE, gload_c(a + 2 * TILE, n1), n1);
             return;
         }
         b = Xin + (int64_t)(gx + dd) * 3 * TILE;
         b_term = (s + 2 * dd - 1 >= last);
     }
-    const int n1 = d.n + 1;
-    const Tile A1 = gload(a), C1 = gload(a + TILE), J1 = gload(a + 2 * TILE);
-    const Tile A2 = gload(b), C2 = gload(b + TILE), J2 = gload(b + 2 * TILE);
+    const Tile A1 = gload_c(a, n1), C1 = gload_c(a + TILE, n1), J1 = gload_c(a + 2 * TILE, n1);
+    const Tile A2 = gload_c(b, n1), C2 = gload_c(b + TILE, n1), J2 = gload_c(b + 2 * TILE, n1);
     Tile YT = tna<NK, PR>(J2, C1, tident(n1));   // X' = I + J~2 C~1 = [[I + J C, 0], [-eta' C, 1]]
     const bool ok = gj_inverse<NK>(YT, n1, true);   // X^{-T}
     const Tile Z = tnz<NK, PR>(YT, A1);          // X^{-1} A~1
     const Tile JA = tnz<NK, PR>(J2, A1);         // J~2 A~1
     const Tile Jn = tna<NK, PR>(Z, JA, J1);      // A~1'X^{-T}J~2 A~1 + J~1
-    gstore(o + 2 * TILE, tsym(Jn, lds));
+    gstore_c(o + 2 * TILE, tsym(Jn, lds), n1);
     if (!b_term) {
         const Tile A2T = ttrans(A2, lds);
         const Tile Y = tnz<NK, PR>(YT, C1);      // X^{-1} C~1
         const Tile Vt = tnz<NK, PR>(Y, A2T);     // (A~2 X^{-1} C~1)'
-        gstore(o, tnz<NK, PR>(A2T, Z));          // A~2 X^{-1} A~1
-        gstore(o + TILE, tsym(tna<NK, PR>(Vt, A2T, C2), lds));
+        gstore_c(o, tnz<NK, PR>(A2T, Z), n1);          // A~2 X^{-1} A~1
+        gstore_c(o + TILE, tsym(tna<NK, PR>(Vt, A2T, C2), lds), n1);
     }
     if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
 }
@@ -427,7 +428,7 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     // the carry: the scanned suffix from segment s + 1, or for the last
     // segment the terminal element
     Tile St = (s == d.nseg - 1) ? load_terminal_J(P, d, lds)
-                                : gload(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE);
+                                : gload_c(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE, n + 1);
     if (s == d.nseg - 1) {
         gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(64) void k_cv_start(ProbPtrs P, ValPtrs V, const In
     const int s = gs - d.seg0;
     const int n1 = d.n + 1;
     const double *e = Xfin + (int64_t)(d.xbase + s) * 3 * TILE;
-    const Tile Ah = gload(e), Ch = gload(e + TILE);
+    const Tile Ah = gload_c(e, n1), Ch = gload_c(e + TILE, n1);
     const Tile Sh = load_Sh(V.S, V.s, d, s * d.L);
     const Tile X0 = load_vec(P.x0 + d.on, d.n, d.n, d.n);
     Tile YT = tna<NK, PR>(Sh, Ch, tident(n1));          // (I + C~ S~)'
