@@ -35,7 +35,7 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
     if (s == d.nseg - 1)
-        gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * n, n, n, n));
+        gstore_c(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * n, n, n, n), d.n + 1);
     if (s == 0) return;   // never read: segment s starts from entry s + 1
     // stage data through LDS, the next stage's loads in flight during this one
     constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
         arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
         wsync();
     }
-    gstore(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds));
+    gstore_c(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds), d.n + 1);
 }
 
 // Inside each segment, from s~ at its right end: s~_k and gamma~_k.
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
-    Tile SV = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);   // [[0, s~_{k1}], [0, 1]]
+    Tile SV = gload_c(Yfin + (int64_t)(d.xbase + s + 1) * TILE, d.n + 1);   // [[0, s~_{k1}], [0, 1]]
     if (s == d.nseg - 1) store_vec(J.st + d.os + (int64_t)d.T * n, SV, n, n);
     int code = 0, fk = 0;
     // stage data through LDS, the next stage's loads in flight during this one
@@ -152,8 +152,8 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
         arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
         wsync();
     }
-    if (s == 0) gstore(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n));   // dx_0 = 0
-    if (s < d.nseg - 1) gstore(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds));
+    if (s == 0) gstore_c(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n), d.n + 1);   // dx_0 = 0
+    if (s < d.nseg - 1) gstore_c(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
     if (code) report(status, i, code, fk);
 }
 
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n, m = d.m;
-    Tile DX = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, dx_k0], [0, 1]]
+    Tile DX = gload_c(Yfin + (int64_t)(d.xbase + s) * TILE, d.n + 1);   // [[0, dx_k0], [0, 1]]
     if (s == 0 && Gr.x0) store_vec(Gr.x0 + d.on, tnz<NK, PR>(load_Sh(J.S, J.st, d, 0), DX), n, n);
     // stage data through LDS, the next stage's loads in flight during this one
     constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;

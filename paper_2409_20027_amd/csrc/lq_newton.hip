@@ -375,11 +375,11 @@ __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc
     const InstDesc d = inst[find_inst(seg_start, batch, gs)];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    if (s == d.nseg - 1) gstore(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT + d.on, d.n, d.n, d.n));
+    if (s == d.nseg - 1) gstore_c(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT + d.on, d.n, d.n, d.n), d.n + 1);
     if (s == 0) return;
     Tile PsiT = tident(d.n + 1);
     for (int k = k0; k < k1; ++k) PsiT = tnz<NK, PR>(costate_map(Wk, d, k), PsiT);   // (Psi M_k)'
-    gstore(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds));
+    gstore_c(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds), d.n + 1);
 }
 
 // Step 2c: co-states inside each segment from lambda at its right end.
@@ -394,7 +394,7 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n;
     double *lam = Wk.lam + d.os;
-    Tile L = gload(Yfin + (int64_t)(d.xbase + s + 1) * TILE);
+    Tile L = gload_c(Yfin + (int64_t)(d.xbase + s + 1) * TILE, d.n + 1);
     if (s == d.nseg - 1) store_vec(lam + (int64_t)d.T * n, L, n, n);
     for (int k = k1 - 1; k >= k0; --k) {
         L = tnz<NK, PR>(costate_map_t(Wk, d, k), L);   // M_k L

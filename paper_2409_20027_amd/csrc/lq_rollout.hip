@@ -36,14 +36,14 @@ __global__ __launch_bounds__(64) void k_roll_fold(ProbPtrs P, ValPtrs V, const I
     const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
-    if (s == 0) gstore(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n));
+    if (s == 0) gstore_c(Y + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, d.n, d.n, d.n), d.n + 1);
     // The map of the last segment is never read: segment s starts from the
     // scanned entry s.
     if (s == d.nseg - 1) return;
     Tile Phi = tident(d.n + 1);
     for (int k = k0; k < k1; ++k)
         Phi = tnz<NK, PR>(closed_loop_t<PR>(load_AhT(P, d, k), load_Gh(V.G, V.g, d, k), load_BhT(P, d, k)), Phi);   // F~ Phi
-    gstore(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi);
+    gstore_c(Y + (int64_t)(d.xbase + s + 1) * TILE, Phi, d.n + 1);
 }
 
 // One radix-RAD Kogge-Stone level over entries [xbase, xbase + nseg] of each
@@ -70,22 +70,22 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     const InstDesc d = inst[i];
     const int s = gx - d.xbase;
     if (suffix ? (s == 0) : (s == d.nseg)) return;   // entries that are never read
-    const Tile a = gload(Yin + (int64_t)gx * TILE);
+    const Tile a = gload_c(Yin + (int64_t)gx * TILE, d.n + 1);
     const int avail = suffix ? (d.nseg - s) / dd : s / dd;   // terms that exist on that side
     const int terms = min(RAD - 1, avail);
     if (terms == 0) {
-        gstore(Yout + (int64_t)gx * TILE, a);
+        gstore_c(Yout + (int64_t)gx * TILE, a, d.n + 1);
         return;
     }
     const int64_t step = suffix ? dd : -dd;
     Tile b[RAD - 1];
 #pragma unroll
-    for (int j = 0; j < RAD - 1; ++j) b[j] = gload(Yin + (gx + (j < terms ? (j + 1) * step : 0)) * TILE);
+    for (int j = 0; j < RAD - 1; ++j) b[j] = gload_c(Yin + (gx + (j < terms ? (j + 1) * step : 0)) * TILE, d.n + 1);
     Tile PT = tnz<NK, PR>(b[0], ttrans(a, lds));   // (a b1)'
 #pragma unroll
     for (int j = 1; j < RAD - 1; ++j)
         if (j < terms) PT = tnz<NK, PR>(b[j], PT);  // (a b1 ... b_{j+1})'
-    gstore(Yout + (int64_t)gx * TILE, ttrans(PT, lds));
+    gstore_c(Yout + (int64_t)gx * TILE, ttrans(PT, lds), d.n + 1);
 }
 
 // From the state at the segment start: u_k = Gamma~ x~, lambda_k = S~_k x~,
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     arr_fetch(arr, k0, f);
     arr_put(stg, arr, trash, f);
     wsync();
-    Tile X = gload(Yfin + (int64_t)(d.xbase + s) * TILE);   // [[0, x_k0], [0, 1]]
+    Tile X = gload_c(Yfin + (int64_t)(d.xbase + s) * TILE, d.n + 1);   // [[0, x_k0], [0, 1]]
     int b = 0;
     for (int k = k0; k < k1; ++k, b ^= 1) {
         const double *cur = stg + b * SZ;

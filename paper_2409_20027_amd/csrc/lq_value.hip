@@ -448,8 +448,8 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
             riccati_sweep<NK, PR, false, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
     }
     if (roll) {
-        if (s == 0) gstore(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n));
-        if (s < d.nseg - 1) gstore(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds));
+        if (s == 0) gstore_c(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n), d.n + 1);
+        if (s < d.nseg - 1) gstore_c(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
     }
     const bool bad = !(isfinite(St.v[0]) && isfinite(St.v[1]) && isfinite(St.v[2]) && isfinite(St.v[3]));
     if (__ballot(bad) && !code) {
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(64) void k_cv_start(ProbPtrs P, ValPtrs V, const In
     Tile YT = tna<NK, PR>(Sh, Ch, tident(n1));          // (I + C~ S~)'
     const bool ok = gj_inverse<NK>(YT, n1, true);      // (I + C~ S~)^{-T}
     const Tile AX = tnz<NK, PR>(ttrans(Ah, lds), X0);   // A~ x~0
-    gstore(Y + (int64_t)(d.xbase + s) * TILE, tnz<NK, PR>(YT, AX));
+    gstore_c(Y + (int64_t)(d.xbase + s) * TILE, tnz<NK, PR>(YT, AX), d.n + 1);
     if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
 }
 
