@@ -471,10 +471,13 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
 // pred > 0 and rho > 0: alpha *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; else
 // alpha *= nu, nu *= 2.  An LQ step that failed counts as pred = 0.
 constexpr int RED = 256;
-__global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
-                                                     double *scal)
+// RB threads per instance, chosen from the horizon (about one to four stages
+// per thread).
+template <int RB>
+__global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
+                                                    double *scal)
 {
-    __shared__ double sp[RED], s0[RED], s1[RED], sg[RED];
+    __shared__ double sp[RB], s0[RB], s1[RB], sg[RB];
     const int t = threadIdx.x, b = blockIdx.x;
     const int n = N.nx, m = N.nu, T = N.T;
     scal += (int64_t)b * NMPC_NSCAL;
@@ -485,7 +488,7 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
     const double *xc = Wk.xc + xo, *uc = Wk.uc + s0k * m, *dx = Wk.dx + xo;
     const double mu = scal[NMPC_MU];
     double pred = 0.0, J0 = 0.0, J1 = 0.0, gmax = 0.0;
-    for (int k = t; k < T; k += RED) {
+    for (int k = t; k < T; k += RB) {
         const int64_t gk = s0k + k;
         const double *dxk = dx + (int64_t)k * n, *duk = Wk.du + gk * m;
         double lin = 0.0, qf = 0.0;
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(RED) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, co
     s0[t] = J0;
     s1[t] = J1;
     sg[t] = gmax;
-    for (int h = RED / 2; h > 0; h >>= 1) {
+    for (int h = RB / 2; h > 0; h >>= 1) {
         __syncthreads();
         if (t < h) {
             sp[t] += sp[t + h];
@@ -704,7 +707,12 @@ void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, c
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
     launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc);
-    hipLaunchKernelGGL(k_nmpc_reduce, dim3(N.batch), dim3(RED), 0, st, N, Wk, x, u, scal);
+    if (N.T <= 96)
+        hipLaunchKernelGGL(k_nmpc_reduce<64>, dim3(N.batch), dim3(64), 0, st, N, Wk, x, u, scal);
+    else if (N.T <= 384)
+        hipLaunchKernelGGL(k_nmpc_reduce<256>, dim3(N.batch), dim3(256), 0, st, N, Wk, x, u, scal);
+    else
+        hipLaunchKernelGGL(k_nmpc_reduce<1024>, dim3(N.batch), dim3(1024), 0, st, N, Wk, x, u, scal);
 }
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init)
 {
