@@ -154,12 +154,6 @@ LQK_DEV Tile load_BhT(const ProbPtrs &P, const InstDesc &d, int k)
     return gload_rm_t(P.B + d.oB + (int64_t)k * d.n * d.m, d.m, d.n, d.m);
 }
 
-// B~ = [[B], [0]]   ((n+1) x m)
-LQK_DEV Tile load_Bh(const ProbPtrs &P, const InstDesc &d, int k)
-{
-    return gload_rm(P.B + d.oB + (int64_t)k * d.n * d.m, d.n, d.m, d.m);
-}
-
 // Q~ = [[Q, q], [q', 0]]
 LQK_DEV Tile load_Qh(const ProbPtrs &P, const InstDesc &d, int k)
 {
@@ -253,26 +247,6 @@ LQK_DEV Tile load_Gh(const double *Gam, const double *gam, const InstDesc &d, in
             p = G + a * n + c;
         else if (a < m && c == n && gg)
             p = gg + a;
-        t.v[r] = ldg(p);
-    }
-    return t;
-}
-
-// Gamma~' = [[Gamma'], [gamma']]   ((n+1) x m)
-LQK_DEV Tile load_GhT(const double *Gam, const double *gam, const InstDesc &d, int k)
-{
-    const int n = d.n, m = d.m, c = tcol();
-    const double *G = Gam + d.oG + (int64_t)k * m * n;
-    const double *gg = gam ? gam + d.og + (int64_t)k * m : nullptr;
-    Tile t;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int i = trow(r);
-        const double *p = zptr();
-        if (c < m && i < n)
-            p = G + c * n + i;
-        else if (c < m && i == n && gg)
-            p = gg + c;
         t.v[r] = ldg(p);
     }
     return t;
