@@ -181,6 +181,18 @@ def test_general_lq_all_terms(lq, n, m, T, L, fused):
     check(per, [inst])
 
 
+@pytest.mark.parametrize("nseg", [2, 3, 5, 9, 17, 33])
+def test_segment_counts_around_scan_levels(lq, nseg):
+    """Segment counts whose scan entries (nseg - 1 of them: the last segment is
+    folded onto the terminal element) are a power of two, with a ragged last
+    segment."""
+    L = 3
+    inst = W.lq_instance_general(np.random.default_rng(700 + nseg), 4, 2, L * (nseg - 1) + 2)
+    per, status, plan = run(lq, [inst], seg_len=L)
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+
+
 def test_ragged_batch_mixed_sizes(lq):
     rng = np.random.default_rng(5)
     insts = []
