@@ -193,6 +193,46 @@ def test_segment_counts_around_scan_levels(lq, nseg):
     check(per, [inst])
 
 
+def random_config(rng):
+    """A seeded random LQ configuration: sizes up to the limits, a segment
+    length from one stage to past the horizon (or automatic), and each optional
+    term present or absent."""
+    n, m = int(rng.integers(1, 16)), int(rng.integers(1, 5))
+    T = int(rng.choice([1, 2, int(rng.integers(3, 40)), int(rng.integers(40, 300))]))
+    inst = W.lq_instance_general(rng, n, m, T)
+    for f in ("c", "M", "q", "r", "qT"):
+        if rng.random() < 0.4:
+            setattr(inst, f, None)
+    L = int(rng.choice([0, 1, int(rng.integers(1, T + 3))]))
+    return inst, L
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configurations(lq, seed):
+    """Seeded random sizes, segment lengths and optional terms, one instance
+    and a ragged batch of three with their own segment lengths, against the
+    oracle at every stage."""
+    rng = np.random.default_rng(9000 + seed)
+    inst, L = random_config(rng)
+    per, status, _ = run(lq, [inst], seg_len=L)
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst])
+    batch = [random_config(rng) for _ in range(3)]
+    insts = [b[0] for b in batch]
+    packed = W.pack(insts)
+    prob = lq.to_device(packed)
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], seg_lens=[b[1] for b in batch])
+    out = lq.solve(plan, prob)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    xs = split(out["x"].cpu().numpy(), [(i.T + 1, i.n) for i in insts])
+    us = split(out["u"].cpu().numpy(), [(i.T, i.m) for i in insts])
+    Ss = split(out["S"].cpu().numpy(), [(i.T + 1, i.n, i.n) for i in insts])
+    for inst_, x_, u_, S_ in zip(insts, xs, us, Ss):
+        ref = oracle_ref(inst_)
+        assert rel(x_, ref["x"]) < TOL and rel(u_, ref["u"]) < TOL and rel(S_, ref["S"]) < TOL
+
+
 def test_ragged_batch_mixed_sizes(lq):
     rng = np.random.default_rng(5)
     insts = []
