@@ -434,6 +434,8 @@ def main():
     ap.add_argument("--no-cv", action="store_true", help="skip the conditional-value rollout comparison")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
+    ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc"), default=None,
+                    help="run only this section of the paper's workloads (GPU paths only) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: sharding the horizon or the batch over several GPUs is a "
@@ -443,6 +445,13 @@ def main():
     import torch
 
     from paper_2409_20027_amd import lqscan, workloads
+
+    if args.section:
+        fn = {"paper_ip": lambda: paper_ip_solves(lqscan, workloads, 3, False),
+              "paper_admm": lambda: paper_admm_solves(lqscan, workloads, False),
+              "paper_mpc": lambda: paper_mpc(lqscan, workloads, False)}[args.section]
+        print(json.dumps({args.section: fn()}))
+        return
 
     dev = torch.device("cuda:0")
     inst = workloads.cfg2_long(T=args.T)
