@@ -376,7 +376,7 @@ template <int S>
 LQK_DEV void fetch_arr(const StageArr &a, int k, double *v)
 {
     const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(a.base + (uint32_t)(k * a.stride)), (short)0, a.bytes, 0x00020000);
+        (void *)(a.base + (uint32_t)(k * a.stride)), (short)0, a.bytes, kRawBufferWord3);
 #pragma unroll
     for (int j = 0; j < S; ++j) v[j] = bload(r, lane() + 64 * j);
 }

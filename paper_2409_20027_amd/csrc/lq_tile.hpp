@@ -115,12 +115,16 @@ LQK_DEV double ldg(const double *p)
     asm("" : "+v"(a));
     return *(const __attribute__((address_space(1))) double *)a;
 }
+// Last word of a raw (unswizzled, stride 0) buffer resource on gfx9-class
+// GPUs: 32-bit data format, the value the ROCm libraries use for raw buffers.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // A raw buffer resource over the first len doubles at p (p null: an empty
 // range).  The hardware's range check returns 0 for a load past the end, so a
 // masked load needs no per-lane address selection.
 LQK_DEV __amdgpu_buffer_rsrc_t brsrc(const double *p, int len)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((void *)(p ? p : zptr()), (short)0, p ? len * 8 : 0, 0x00020000);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)(p ? p : zptr()), (short)0, p ? len * 8 : 0, kRawBufferWord3);
 }
 // Element idx of the range (0 past its end).
 LQK_DEV double bload(__amdgpu_buffer_rsrc_t r, int idx)
