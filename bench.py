@@ -497,6 +497,16 @@ def main():
     plan.set_timing([], 0)
     breakdown = {k: v[0] / prof_steps for k, v in phases.items()}
     models = kernel_models(n, m, T, plan.seg_len())
+    # every modelled phase against both peaks: algorithmic bytes and flops per
+    # step over the phase's time per step
+    phase_roofline = {}
+    for ph, mdl_ in models.items():
+        if ph not in breakdown or breakdown[ph] <= 0:
+            continue
+        sec = breakdown[ph] * 1e-3
+        gbs_, tf_ = mdl_["bytes"] / sec / 1e9, mdl_["flops"] / sec / 1e12
+        phase_roofline[ph] = {"us_per_step": breakdown[ph] * 1e3, "GB/s": gbs_, "hbm_frac": gbs_ / HBM_PEAK_GBS,
+                              "TFLOP/s": tf_, "fp64_frac": tf_ / FP64_PEAK_TFLOPS}
     dominant = max((k for k in breakdown if k in models), key=lambda k: breakdown[k])
 
     # timed pass: events only around the dominant kernel
@@ -617,6 +627,7 @@ def main():
            "err_vs_oracle": err,
            "sequential_gpu": seq,
            "kernel_ms_per_step": breakdown,
+           "phase_roofline": phase_roofline,
            "cv_rollout": cv,
            "roofline": roof}
     if not args.no_batch:
