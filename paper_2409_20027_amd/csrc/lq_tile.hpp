@@ -82,13 +82,6 @@ LQK_DEV Tile tsub(const Tile &a, const Tile &b)
     t.v = a.v - b.v;
     return t;
 }
-LQK_DEV Tile tneg(const Tile &a)
-{
-    Tile t;
-    t.v = -a.v;
-    return t;
-}
-
 // Global memory, tile-native layout: 64 lanes x 4 doubles, 2 KiB, coalesced.
 LQK_DEV Tile gload(const double *p)
 {
@@ -237,15 +230,6 @@ LQK_DEV Tile sget_t(const double *s)
 #pragma unroll
     for (int r = 0; r < 4; ++r) t.v[r] = s[c * LD + trow(r)];
     return t;
-}
-
-// Marks a tile's registers as used here (no instruction): a load into them has
-// to complete first.  Placed before a loop that carries prefetched tiles, it
-// makes the loop's entry state "loaded", so the waits inside the loop count
-// only the loads the loop itself issues.
-LQK_DEV void settle(const Tile &t)
-{
-    asm volatile("" ::"v"(t.v[0]), "v"(t.v[1]), "v"(t.v[2]), "v"(t.v[3]));
 }
 
 // Row permutation that makes the FP32 16x16x4 instruction's accumulator (row
