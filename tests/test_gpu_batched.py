@@ -106,6 +106,52 @@ def test_ragged_batch_graph_replay(lq, batch):
     assert int(status.abs().sum()) == 0
 
 
+def test_full_step_graph_replay(lq):
+    """The whole benchmark step -- lq_solve, lq_adjoint -- and the
+    conditional-value rollout captured once in a HIP graph; every replay (with
+    eager work between replays) reproduces the eager results bit for bit."""
+    inst = W.lq_instance_general(np.random.default_rng(77), 12, 4, 1500)
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([12], [4], [1500], seg_len=16)
+    ws, ws2 = plan.new_workspace(), plan.new_workspace()
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    val = lq.value_buffers(plan)
+    st = lq.state_buffers(plan)
+    cv = lq.state_buffers(plan)
+    names = ("A", "B", "c", "Q", "R", "M", "q", "r", "QT", "qT", "x0")
+    grads = lq.grad_buffers(plan, names)
+    gx = torch.randn_like(st["x"])
+    gu = torch.randn_like(st["u"])
+
+    def step():
+        lq.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+        lq.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, ws, status)
+        lq.lq_rollout_cv(plan, prob, val, cv["x"], cv["u"], cv["lam"], ws2, status)
+
+    step()
+    torch.cuda.synchronize()
+    outs = {"x": st["x"], "S": val["S"], "cv_x": cv["x"], **{"g" + k: v for k, v in grads.items()}}
+    ref = {k: v.clone() for k, v in outs.items()}
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            step()
+    torch.cuda.synchronize()
+    for r in range(3):
+        for v in outs.values():
+            v.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in outs.items():
+            assert torch.equal(v, ref[k]), (r, k)
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    assert int(status.abs().sum()) == 0
+
+
 def test_ragged_batch_autotuned(lq, batch, tmp_path):
     from paper_2409_20027_amd import autotune
     insts, prob = batch
