@@ -233,6 +233,18 @@ def test_random_configurations(lq, seed):
         assert rel(x_, ref["x"]) < TOL and rel(u_, ref["u"]) < TOL and rel(S_, ref["S"]) < TOL
 
 
+def test_long_segment_fold_stays_accurate(lq):
+    """A 137-stage fold (n = 13, m = 1, seg_len 140 of T = 277; found by a
+    random sweep): without the fold's per-stage symmetrisation of J the error
+    reached 3e-11, which the 1e-10 bar let through, so this case is held to
+    1e-13."""
+    inst, _ = random_config(np.random.default_rng(50204))
+    assert (inst.n, inst.m, inst.T) == (13, 1, 277)
+    per, status, _ = run(lq, [inst], seg_len=140)
+    assert int(np.abs(status).sum()) == 0
+    check(per, [inst], tol=1e-13)
+
+
 def test_ragged_batch_mixed_sizes(lq):
     rng = np.random.default_rng(5)
     insts = []
