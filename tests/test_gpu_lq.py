@@ -207,16 +207,17 @@ def random_config(rng):
     return inst, L
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(24))
 def test_random_configurations(lq, seed):
     """Seeded random sizes, segment lengths and optional terms, one instance
     and a ragged batch of three with their own segment lengths, against the
-    oracle at every stage."""
+    oracle at every stage, to 1e-12 (a sweep of 300 such configurations peaks
+    at 6e-15)."""
     rng = np.random.default_rng(9000 + seed)
     inst, L = random_config(rng)
     per, status, _ = run(lq, [inst], seg_len=L)
     assert int(np.abs(status).sum()) == 0
-    check(per, [inst])
+    check(per, [inst], tol=1e-12)
     batch = [random_config(rng) for _ in range(3)]
     insts = [b[0] for b in batch]
     packed = W.pack(insts)
@@ -230,7 +231,7 @@ def test_random_configurations(lq, seed):
     Ss = split(out["S"].cpu().numpy(), [(i.T + 1, i.n, i.n) for i in insts])
     for inst_, x_, u_, S_ in zip(insts, xs, us, Ss):
         ref = oracle_ref(inst_)
-        assert rel(x_, ref["x"]) < TOL and rel(u_, ref["u"]) < TOL and rel(S_, ref["S"]) < TOL
+        assert rel(x_, ref["x"]) < 1e-12 and rel(u_, ref["u"]) < 1e-12 and rel(S_, ref["S"]) < 1e-12
 
 
 def test_long_segment_fold_stays_accurate(lq):
