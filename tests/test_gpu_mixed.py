@@ -101,3 +101,27 @@ def test_mixed_newton_converges_to_fp64_optimum(lq):
     print(f"mixed newton (converging instance): |dJ/du| {g_got:.2e} (u0: {g0:.2e}), final u rel err {eu:.2e}")
     assert g_got <= 1e-4 * g0
     assert eu <= 1e-3
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mixed_random_configurations(lq, seed):
+    """The mixed-precision plan on seeded random sizes, segment lengths and
+    optional terms, to the mixed bound 1e-4 (a sweep of 100 such
+    configurations peaks at 9e-7)."""
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location("_lqtests", os.path.join(os.path.dirname(__file__), "test_gpu_lq.py"))
+    t = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(t)
+    inst, L = t.random_config(np.random.default_rng(90000 + seed))
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([inst.n], [inst.m], [inst.T], seg_lens=[L], precision="mixed")
+    out = lq.solve(plan, prob)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    ref = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                          M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+    n, m, T = inst.n, inst.m, inst.T
+    assert rel(out["x"].cpu().numpy().reshape(T + 1, n), ref["x"]) <= 1e-4
+    assert rel(out["u"].cpu().numpy().reshape(T, m), ref["u"]) <= 1e-4
+    assert rel(out["S"].cpu().numpy().reshape(T + 1, n, n), ref["S"]) <= 1e-4
