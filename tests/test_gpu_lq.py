@@ -181,11 +181,11 @@ def test_general_lq_all_terms(lq, n, m, T, L, fused):
     check(per, [inst])
 
 
-@pytest.mark.parametrize("nseg", [2, 3, 5, 9, 17, 33])
+@pytest.mark.parametrize("nseg", [2, 3, 4, 5, 6, 9, 17, 18, 33, 65, 66, 67, 257])
 def test_segment_counts_around_scan_levels(lq, nseg):
     """Segment counts whose scan entries (nseg - 1 of them: the last segment is
-    folded onto the terminal element) are a power of two, with a ragged last
-    segment."""
+    folded onto the terminal element) are a power of two, or one or two past
+    it, with a ragged last segment."""
     L = 3
     inst = W.lq_instance_general(np.random.default_rng(700 + nseg), 4, 2, L * (nseg - 1) + 2)
     per, status, plan = run(lq, [inst], seg_len=L)
@@ -232,6 +232,18 @@ def test_random_configurations(lq, seed):
     for inst_, x_, u_, S_ in zip(insts, xs, us, Ss):
         ref = oracle_ref(inst_)
         assert rel(x_, ref["x"]) < 1e-12 and rel(u_, ref["u"]) < 1e-12 and rel(S_, ref["S"]) < 1e-12
+
+
+def test_value_scan_ragged_batch(lq):
+    """The value scan on a ragged batch whose instances finish at different
+    levels (1 to 300 entries, one stage per segment), against the oracle to
+    1e-12."""
+    rng = np.random.default_rng(7100)
+    insts = [W.lq_instance_general(rng, 5, 2, 301), W.lq_instance(rng, 2, 1, 4), W.lq_instance(rng, 12, 4, 70),
+             W.lq_instance(rng, 3, 1, 2), W.lq_instance_general(rng, 13, 3, 17)]
+    per, status, _ = run(lq, insts, seg_len=1)
+    assert int(np.abs(status).sum()) == 0
+    check(per, insts, tol=1e-12)
 
 
 def test_long_segment_fold_stays_accurate(lq):
