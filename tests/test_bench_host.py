@@ -1,0 +1,67 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU contract, the
+algorithmic cost model of the value scan against a closed form, and the
+stored HBM-traffic records."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
+
+
+@pytest.mark.parametrize("T,L", [(16384, 16), (4096, 16), (1000, 7), (64, 4), (48, 16)])
+def test_value_scan_model_closed_form(T, L):
+    """Radix-2 Kogge-Stone over the entries 1 .. last (last = nseg - 1): the
+    level with distance d has last - d combines, one per entry s with
+    s + d <= last, and the levels are d = 1, 2, 4, ... while d < last."""
+    nseg = -(-T // L)
+    last = nseg - 1
+    levels = [1 << k for k in range(64) if (1 << k) < last]
+    mdl = bench.kernel_models(12, 4, T=T, L=L)["value_scan"]
+    assert mdl["launches"] == max(len(levels), 1)
+    assert mdl["units"] == sum(last - d for d in levels)
+    # every entry of every level moves at least its own J (read and write)
+    n1 = 13
+    assert mdl["bytes"] >= 2 * 8 * n1 * n1 * last * len(levels)
+
+
+def test_value_scan_model_headline_figures():
+    """The figures the roofline line is quoted with: 10 levels and 9207
+    combines at n = 12, m = 4, T = 16384, L = 16."""
+    mdl = bench.kernel_models(12, 4, T=16384, L=16)["value_scan"]
+    assert mdl["launches"] == 10 and mdl["units"] == 10 * 1023 - 1023
+
+
+@pytest.mark.parametrize("kernel", ["value_scan", "value_fold", "value_bellman", "roll_apply", "adj_back_fold",
+                                    "adj_back_apply", "adj_fwd_apply"])
+def test_traffic_records_parse(kernel):
+    """Each committed traffic record names its command, its calibration and
+    the source hash it was taken on, and gives a positive byte count."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}.md")
+    assert os.path.exists(path)
+    text = open(path).read()
+    assert "rocprofv3 --pmc FETCH_SIZE" in text and "rocprofv3 --pmc WRITE_SIZE" in text
+    rec = {}
+    for line in text.splitlines():
+        if ":" in line and not line.startswith(("|", "#")):
+            k, v = line.split(":", 1)
+            rec[k.strip().strip("`*")] = v.strip().strip("`")
+    assert len(rec.get("source_sha256", "")) == 64
+    assert float(rec["traffic_bytes_per_launch"]) > 0
+
+
+def test_stale_traffic_record_is_not_reported(monkeypatch):
+    """A record taken on other kernel sources is reported as null."""
+    monkeypatch.setattr(bench, "source_hash", lambda kernel: "0" * 64)
+    assert bench.stored_traffic("value_scan") is None
