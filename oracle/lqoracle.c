@@ -1036,6 +1036,11 @@ void oracle_nmpc_expand(int nx, int nu, int T, double h, int model, const double
  *        rho = (J_mu(u) - J_mu(u + du)) / pred;
  *   7.   accept if pred > 0 and rho > 0 (finite): alpha *= max(1/3, 1-(2 rho-1)^3),
  *        nu_lm = 2; else alpha *= nu_lm, nu_lm *= 2.
+ *        The paper names this update only by reference (a gain-ratio rule of
+ *        Madsen et al.), so it is a reading.  Its ends are pinned by the
+ *        tests (an exact quadratic model gives rho = 1 and alpha / 3; a step
+ *        out of the box is rejected); its shape for 0 < rho < 1 is parity
+ *        unpinned.
  * x, u hold the nominal and are replaced on acceptance.  Returns 1 if
  * accepted, 0 if rejected, -1 for an unknown model; *cost gets J_mu of the
  * (possibly new) nominal, *grad_out max_k,i |d_k,i| = |dJ_mu/du|_inf at the

@@ -560,3 +560,34 @@ def test_newton_converges_quadratically_near_solution():
     assert len(small) >= 3
     ratios = [small[i + 1] / small[i] ** 1.5 for i in range(len(small) - 1)]
     assert max(ratios) < 50.0, norms
+
+
+@pytest.mark.parametrize("seed,nx,nu,T", [(3, 3, 2, 12), (5, 2, 1, 30), (8, 4, 1, 7)])
+def test_damping_rule_on_an_exact_quadratic_model(seed, nx, nu, T):
+    """The damping update of Sec. III-F is a reading (the rule is named by
+    reference only); this pins its two ends.  With W = 0 the tanh dynamics are
+    linear (x+ = x + h B u) and at mu = 0 the cost is quadratic inside the box,
+    so the quadratic model is exact: an accepted step has gain ratio 1 up to
+    rounding, whatever alpha is, and the rule then divides alpha by 3 and
+    resets nu to 2.  A step that leaves the box (cost +inf) is rejected with
+    alpha <- alpha nu, nu <- 2 nu.  A predicted decrease that kept the alpha
+    term, a ratio taken the wrong way up or a missing 1/2 moves the ratio
+    away from 1."""
+    import dataclasses
+    p = W.nmpc_problem(seed=seed, nx=nx, nu=nu, T=T)
+    p = dataclasses.replace(p, W=np.zeros_like(p.W))
+    u = p.u0.copy()
+    x = oracle.nmpc_rollout(p, u)
+    alpha, nu_lm = 1e-3, 2.0
+    seen = {True: 0, False: 0}
+    for _ in range(9):
+        acc, x, u, a2, n2, cost, pred, rho = oracle.nmpc_newton_step(p, x, u, 0.0, alpha, nu_lm)
+        seen[acc] += 1
+        if acc:
+            assert pred > 0 and abs(rho - 1.0) < 1e-9
+            assert a2 == pytest.approx(alpha / 3.0, rel=1e-14) and n2 == 2.0
+        else:
+            assert rho == -np.inf
+            assert a2 == alpha * nu_lm and n2 == 2.0 * nu_lm
+        alpha, nu_lm = a2, n2
+    assert seen[True] >= 1 and seen[False] >= 1
