@@ -50,3 +50,51 @@ def test_plan_create_rejects_bad_arguments(lib):
 def test_version(lib):
     lib.lq_version.restype = ctypes.c_char_p
     assert b"gfx950" in lib.lq_version()
+
+
+# entry point -> number of arguments (all pointers or int32 here); each is
+# called with a null plan (or null buffers) and must return LQ_ERR_ARG (-1)
+# before any device work
+NULL_PLAN_CALLS = {"lq_build_elements": 5, "lq_scan_solve": 7, "lq_rollout": 9, "lq_rollout_cv": 9, "lq_solve": 10,
+                   "lq_adjoint": 12, "nmpc_init": 5, "newton_step": 6, "nmpc_admm_update": 5, "nmpc_shift": 6,
+                   "lq_plan_phase_times": 3}
+
+
+@pytest.mark.parametrize("name", sorted(NULL_PLAN_CALLS))
+def test_null_plan_is_an_argument_error(lib, name):
+    f = getattr(lib, name)
+    f.restype = ctypes.c_int
+    assert f(*([None] * NULL_PLAN_CALLS[name])) == -1
+
+
+def test_size_queries_of_a_null_plan(lib):
+    for name in ("lq_plan_workspace_bytes", "lq_plan_elements_bytes", "nmpc_workspace_bytes"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_size_t
+        f.argtypes = [ctypes.c_void_p]
+        assert f(None) == 0
+    lib.lq_plan_seg_len.restype = ctypes.c_int32
+    assert lib.lq_plan_seg_len(None) == 0
+    lib.lq_plan_set_timing.restype = ctypes.c_int
+    lib.lq_plan_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32]
+    assert lib.lq_plan_set_timing(None, 1, 4) == -1
+
+
+def test_selftests_reject_bad_arguments(lib):
+    """Sizes outside a tile, a homogeneous block without room for its last
+    row, missing buffers and an unknown precision are refused before launch."""
+    inv = lib.lq_selftest_tile_inverse
+    inv.restype = ctypes.c_int
+    inv.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                    ctypes.c_void_p]
+    fake = ctypes.c_void_p(256)   # never dereferenced: every call below fails its checks first
+    assert inv(fake, fake, 0, 0, fake, None) == -1
+    assert inv(fake, fake, 17, 0, fake, None) == -1
+    assert inv(fake, fake, 1, 1, fake, None) == -1
+    assert inv(fake, fake, 4, 0, None, None) == -1
+    assert inv(None, fake, 4, 0, fake, None) == -1
+    mm = lib.lq_selftest_tile_mm
+    mm.restype = ctypes.c_int
+    mm.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int32] * 3 + [ctypes.c_void_p]
+    assert mm(fake, fake, fake, fake, 0, 0, 7, None) == -1
+    assert mm(None, fake, fake, fake, 0, 0, 0, None) == -1
