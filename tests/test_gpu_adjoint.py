@@ -181,3 +181,22 @@ def test_random_adjoint_configurations(lq, seed):
     for k in have:
         a = grads[k].cpu().numpy().reshape(g[k].shape)
         assert rel(a, g[k]) < 1e-12, (k, n, m, T, L)
+
+
+def test_maximum_sizes_full_horizon(lq):
+    """The largest supported sizes (n = 15, m = 4) with every LQ term at
+    T = 16384 and the default segment length: solution and gradients against
+    the oracle at every stage, to 1e-10."""
+    inst = W.lq_instance_general(np.random.default_rng(15004), 15, 4, 16384)
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([15], [4], [16384])
+    out = lq.solve(plan, prob)
+    torch.cuda.synchronize()
+    assert int(out["status"].abs().sum()) == 0
+    ref = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0,
+                          M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+    T, n, m = 16384, 15, 4
+    assert rel(out["x"].cpu().numpy().reshape(T + 1, n), ref["x"]) < 1e-10
+    assert rel(out["u"].cpu().numpy().reshape(T, m), ref["u"]) < 1e-10
+    assert rel(out["S"].cpu().numpy().reshape(T + 1, n, n), ref["S"]) < 1e-10
+    check(gpu_grads(lq, [inst]), [inst])
