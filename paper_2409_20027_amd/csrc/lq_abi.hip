@@ -83,11 +83,13 @@ static lq_status launched()
 // Radix of the affine-map scan levels.  A level costs a fixed launch-and-load
 // latency plus, per entry, up to r - 1 dependent tile products.  When the
 // entries fit one wave per SIMD the level is latency-bound and radix 8 saves
-// levels (T = 16384, L = 16, n = 12: 19.3 us per scan against 19.8 at radix 4,
-// 30.4 at radix 2, 23 at radix 32); with more entries than SIMDs the products
-// and the tile traffic dominate and radix 4 does least work per level that
-// still halves the levels of radix 2 (256 x 4096 stages: 10.42 ms per
-// differentiated solve against 10.55 at radix 8 and 10.91 at radix 2).
+// levels; with more entries than SIMDs the products and the tile traffic
+// dominate and radix 4 does least work per level that still halves the levels
+// of radix 2.  With entries stored as n1 x n1 blocks the two radices measure
+// within noise of each other on both kinds of workload (T = 16384, L = 16,
+// n = 12, 1025 entries: 18.4 us per rollout scan at radix 4, 18.7 at radix 8;
+// 256 x 4096 stages: 9.23 ms per differentiated solve at radix 4, 9.42 at
+// radix 8), and radix 2 is slower on both.
 // LQSCAN_AFFINE_RADIX (2, 4, 8, 16 or 32) overrides the choice.
 static int choose_affine_radix(int64_t entries, int device)
 {
