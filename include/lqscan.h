@@ -184,7 +184,9 @@ lq_status lq_scan_solve(const lq_plan *plan, const lq_problem *prob, const doubl
  * composed by a prefix scan (eq:state-prop-comb-rule; the first element
  * carries x0 as in eq:state-prop-init-elem-init), then u_k = Gamma x_k + gamma
  * and the co-states lambda_k = S_k x_k + s_k.
- * Outputs x ((T+1) n), u (T m), lambda ((T+1) n, nullable).
+ * Outputs x ((T+1) n), u (T m), lambda ((T+1) n, nullable).  The pass is
+ * products and sums only, so it has no numerical failure: status is not
+ * written (it is kept for a signature uniform with the other solve calls).
  */
 lq_status lq_rollout(const lq_plan *plan, const lq_problem *prob, const lq_value *val,
                      double *x, double *u, double *lambda, void *workspace, int32_t *status,
