@@ -45,7 +45,7 @@
  *   order in which the device work finishes; status must be zeroed by the
  *   caller before the first call that should report into it.  Results of a
  *   failed instance are unspecified; other instances are unaffected.
- * - Supported sizes: 1 <= n <= 15, 1 <= m <= 4, T >= 1.
+ * - Supported sizes: 1 <= n <= 15, 1 <= m <= 4, 1 <= T < 2^23.
  * - Calls that share a workspace must not run concurrently.
  */
 #ifndef LQSCAN_H
@@ -88,9 +88,10 @@ typedef struct lq_plan lq_plan;   /* opaque */
  * (host arrays).  `seg_len` is the number of stages folded per segment of the
  * scan (0 = choose automatically, ignored in LQ_SEQUENTIAL mode).  Allocates
  * small device descriptor tables on the current device.
- * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED (nx > 15, nu > 4, or an instance
- * with (T + 1) nx^2 >= 2^31: stage offsets inside one instance's arrays are
- * 32-bit), LQ_ERR_HIP.
+ * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED (nx > 15, nu > 4, or T >= 2^23:
+ * the status word (-code) | (k << 8) must stay a positive int32 for every
+ * stage k <= T; with nx <= 15 this also keeps (T + 1) nx^2 below 2^31, the
+ * 32-bit stage offsets inside one instance's arrays), LQ_ERR_HIP.
  */
 lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
                          int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out);

@@ -134,9 +134,11 @@ static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu
     for (int i = 0; i < batch; ++i) {
         if (T[i] < 1 || nx[i] < 1 || nu[i] < 1) return LQ_ERR_ARG;
         if (nx[i] > 15 || nu[i] > lqk::MMAX) return LQ_ERR_UNSUPPORTED;
+        // the status word (-code) | (k << 8) holds stages k <= T below 2^23
+        if (T[i] >= lqk::TMAX_STATUS) return LQ_ERR_UNSUPPORTED;
         // the kernels address stage k of an instance's array with a 32-bit
         // element offset
-        if ((int64_t)(T[i] + 1) * nx[i] * nx[i] >= ((int64_t)1 << 31)) return LQ_ERR_UNSUPPORTED;
+        if (((int64_t)T[i] + 1) * nx[i] * nx[i] >= ((int64_t)1 << 31)) return LQ_ERR_UNSUPPORTED;
     }
     lq_plan *p = new (std::nothrow) lq_plan();
     if (!p) return LQ_ERR_ARG;

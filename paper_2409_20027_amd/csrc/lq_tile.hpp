@@ -300,6 +300,13 @@ LQK_DEV double vcol(const Tile &V, int col)
     return rr == 0 ? x0 : (rr == 1 ? x1 : (rr == 2 ? x2 : x3));
 }
 
+// True on every lane if no entry of the tile is NaN or infinite.
+LQK_DEV bool tfinite(const Tile &X)
+{
+    const bool bad = !(isfinite(X.v[0]) && isfinite(X.v[1]) && isfinite(X.v[2]) && isfinite(X.v[3]));
+    return __ballot(bad) == 0;
+}
+
 // Symmetric part 1/2 (X + X').
 LQK_DEV Tile tsym(const Tile &X, double *s)
 {
@@ -634,6 +641,10 @@ LQK_DEV bool small_chol_inv(double a[MMAX][MMAX])
         default: CALL(4, 0); break;  \
         }                            \
     }
+
+// Horizons the status encoding can report: stages k <= T < 2^23 keep
+// (-code) | (k << 8) a positive int32.
+constexpr int TMAX_STATUS = 1 << 23;
 
 // Report a failure of an instance: status = (-code) | (k << 8).  Of several
 // failures the one at the largest stage index is kept (the first one a

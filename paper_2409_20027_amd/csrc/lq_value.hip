@@ -403,12 +403,17 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
         const Tile Qux = tna<NK, PR>(Bh, SA, MhT);    // M~' + B~'S~'A~
         Tile Sn = tna<NK, PR>(Ah, SA, Qh);            // Q~ + A~'S~'A~
         Tile QiT;
-        note(spd_inverse_t(Quu, m, QiT), ERR_NOT_PD, k, code, fk);
+        const bool pd = spd_inverse_t(Quu, m, QiT);
         Tile Gh = tnz<1, PR>(QiT, Qux);
         Gh.v = -Gh.v;                                 // -Q_uu^{-1} Q_ux~
         Sn = tna<1, PR>(Qux, Gh, Sn);                 // + Q_ux~' Gamma~
         if (ROLL) PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gh, Ah), PhiT);   // (Phi F~_k)' = F~_k' Phi'
         St = tsym(Sn, lds);
+        // Every entry of the stage's data (A, B, c, Q, R, M, q, r) reaches
+        // S~_k, so a NaN or Inf among them is reported at this stage, ahead of
+        // the positive-definiteness test that a non-finite Q_uu also fails.
+        note(tfinite(St), ERR_NONFINITE, k, code, fk);
+        note(pd, ERR_NOT_PD, k, code, fk);
         gstore_rm(V.S + d.oS + (int64_t)k * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
@@ -437,11 +442,12 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     // segment the terminal element
     Tile St = (s == d.nseg - 1) ? load_terminal_J(P, d, lds)
                                 : gload_c(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE, n + 1);
+    int code = 0, fk = 0;
     if (s == d.nseg - 1) {
         gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
         store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
+        note(tfinite(St), ERR_NONFINITE, d.T, code, fk);   // Q_T, q_T
     }
-    int code = 0, fk = 0;
     const bool roll = (Yroll != nullptr);
     Tile PhiT = tident(n + 1);
     if (has_mr) {
@@ -458,11 +464,6 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     if (roll) {
         if (s == 0) gstore_c(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n), d.n + 1);
         if (s < d.nseg - 1) gstore_c(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
-    }
-    const bool bad = !(isfinite(St.v[0]) && isfinite(St.v[1]) && isfinite(St.v[2]) && isfinite(St.v[3]));
-    if (__ballot(bad) && !code) {
-        code = ERR_NONFINITE;
-        fk = k0;
     }
     if (code) report(status, i, code, fk);
 }

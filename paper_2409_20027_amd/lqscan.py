@@ -344,8 +344,14 @@ class LQSolveFunction(torch.autograd.Function):
 
     Inputs are flat packed float64 device tensors (lq_problem layout); c, M, q,
     r, qT may be None.  The forward pass is one lq_solve call, the backward
-    pass one lq_adjoint call; both run in the HIP library.
+    pass one lq_adjoint call; both run in the HIP library.  The problem
+    tensors and the outputs x, u are saved with save_for_backward (so an
+    in-place change of an input between forward and backward is detected and
+    no output is referenced from its own grad_fn); the value functions, gains,
+    co-states and the workspace are intermediates kept on ctx.
     """
+
+    NAMES = ("A", "B", "c", "Q", "R", "QT", "x0", "M", "q", "r", "qT")
 
     @staticmethod
     def forward(ctx, plan, A, B, c, Q, R, QT, x0, M, q, r, qT):
@@ -356,20 +362,25 @@ class LQSolveFunction(torch.autograd.Function):
         val = value_buffers(plan, dev)
         st = state_buffers(plan, dev)
         lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
-        ctx.plan, ctx.prob, ctx.val, ctx.st, ctx.ws, ctx.status = plan, prob, val, st, ws, status
+        ctx.save_for_backward(A, B, c, Q, R, QT, x0, M, q, r, qT, st["x"], st["u"])
+        ctx.plan, ctx.val, ctx.lam, ctx.ws = plan, val, st["lam"], ws
         ctx.mark_non_differentiable(status)
         return st["x"], st["u"], status
 
     @staticmethod
     def backward(ctx, gx, gu, _gstatus):
-        plan, prob = ctx.plan, ctx.prob
-        names = ("A", "B", "c", "Q", "R", "QT", "x0", "M", "q", "r", "qT")
+        saved = ctx.saved_tensors
+        names = LQSolveFunction.NAMES
+        prob = dict(zip(names, saved[:len(names)]))
+        x, u = saved[len(names):]
+        plan = ctx.plan
         want = [f for i, f in enumerate(names) if ctx.needs_input_grad[i + 1]]
-        dev = prob["A"].device
-        gx = torch.zeros_like(ctx.st["x"]) if gx is None else gx.contiguous()
-        gu = torch.zeros_like(ctx.st["u"]) if gu is None else gu.contiguous()
+        dev = x.device
+        gx = torch.zeros_like(x) if gx is None else gx.contiguous()
+        gu = torch.zeros_like(u) if gu is None else gu.contiguous()
         g = grad_buffers(plan, want, dev)
-        lq_adjoint(plan, prob, ctx.val, ctx.st["x"], ctx.st["u"], ctx.st["lam"], gx, gu, g, ctx.ws, ctx.status)
+        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
+        lq_adjoint(plan, prob, ctx.val, x, u, ctx.lam, gx, gu, g, ctx.ws, status)
         return (None,) + tuple(g.get(f) for f in names)
 
 

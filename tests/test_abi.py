@@ -44,7 +44,12 @@ def test_plan_create_rejects_bad_arguments(lib):
     assert f(1, arr(4), arr(5), arr(4), 0, 0, 0, ctypes.byref(plan)) == -7          # m too large
     assert f(1, arr(4), arr(1), arr(4), 7, 0, 0, ctypes.byref(plan)) == -1          # precision
     assert f(1, arr(4), arr(1), arr(4), 0, 0, -3, ctypes.byref(plan)) == -1         # seg_len
-    assert f(1, arr(15), arr(1), arr(10_000_000), 0, 0, 0, ctypes.byref(plan)) == -7  # (T + 1) n^2 >= 2^31
+    # the status word (-code) | (k << 8) holds stages below 2^23: longer horizons are refused
+    # (for n <= 15 this also keeps the (T + 1) n^2 stage offsets within 32 bits), and
+    # T = INT32_MAX does not wrap
+    assert f(1, arr(15), arr(1), arr(10_000_000), 0, 0, 0, ctypes.byref(plan)) == -7
+    assert f(1, arr(1), arr(1), arr(1 << 23), 0, 0, 0, ctypes.byref(plan)) == -7
+    assert f(1, arr(1), arr(1), arr(2**31 - 1), 0, 0, 0, ctypes.byref(plan)) == -7
 
 
 def test_version(lib):

@@ -200,3 +200,93 @@ def test_maximum_sizes_full_horizon(lq):
     assert rel(out["u"].cpu().numpy().reshape(T, m), ref["u"]) < 1e-10
     assert rel(out["S"].cpu().numpy().reshape(T + 1, n, n), ref["S"]) < 1e-10
     check(gpu_grads(lq, [inst]), [inst])
+
+
+def test_adjoint_mixed_batch_sample(lq):
+    """Sample of the differentiated-solve workload in mixed precision (FP32
+    products; FP64 inverses, Cholesky factors and symmetrisation): 3 instances
+    of n=12, m=4, T=4096, every gradient against the FP64 oracle at the mixed
+    bound 1e-3 (normwise relative)."""
+    insts = W.cfg4_batch(batch=3, T=4096)
+    worst = check(gpu_grads(lq, insts, precision="mixed"), insts, tol=1e-3)
+    print(f"mixed adjoint, 3 x T=4096: worst rel err {worst:.2e}")
+
+
+def test_finite_differences_long_horizon(lq):
+    """Central finite differences (h = 1e-6) of L = sum ||x||^2 + ||u||^2 along
+    16 random unit directions over (A, B, c, Q, R, Q_T, x0) -- N(0,1) entries,
+    symmetrised for Q, R, Q_T, normalised to unit norm -- on one instance of
+    the differentiated workload (n=12, m=4, T=4096, FP64): the GPU forward's
+    difference quotient against the GPU adjoint's directional derivative, to
+    1e-6 relative (the oracle's own quotient at this size is within 3e-8)."""
+    inst = W.cfg4_batch(batch=1, T=4096)[0]
+    names = ("A", "B", "c", "Q", "R", "QT", "x0")
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([12], [4], [4096])
+    ws = plan.new_workspace()
+
+    def loss(p):
+        out = lq.solve(plan, p, workspace=ws)
+        torch.cuda.synchronize()
+        assert int(out["status"].abs().sum()) == 0
+        return float((out["x"] * out["x"]).sum() + (out["u"] * out["u"]).sum()), out
+
+    _, out = loss(prob)
+    g = lq.grad_buffers(plan, names)
+    lq.lq_adjoint(plan, prob, {k: out[k] for k in ("S", "s", "Gamma", "gamma")}, out["x"], out["u"], out["lam"],
+                  2 * out["x"], 2 * out["u"], g, ws, out["status"])
+    torch.cuda.synchronize()
+    check([{f: g[f].cpu().numpy().reshape(SHAPES[f](inst)) for f in names}], [inst])   # oracle, 1e-10
+    rng = np.random.default_rng(36)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(16):
+        d = {f: rng.standard_normal(SHAPES[f](inst)) for f in names}
+        for f in ("Q", "R", "QT"):
+            d[f] = 0.5 * (d[f] + np.swapaxes(d[f], -1, -2))
+        nrm = np.sqrt(sum(float((v * v).sum()) for v in d.values()))
+        dd = {f: torch.tensor((v / nrm).reshape(-1), device="cuda") for f, v in d.items()}
+        plus, _ = loss({**prob, **{f: prob[f] + h * dd[f] for f in names}})
+        minus, _ = loss({**prob, **{f: prob[f] - h * dd[f] for f in names}})
+        fd = (plus - minus) / (2 * h)
+        an = float(sum((g[f] * dd[f]).sum() for f in names))
+        e = abs(fd - an) / max(1.0, abs(an))
+        worst = max(worst, e)
+        assert e <= 1e-6, (fd, an)
+    print(f"finite differences, n=12 T=4096: worst rel err {worst:.2e}")
+
+
+def test_autograd_saved_tensors(lq):
+    """The wrapper saves its inputs and outputs with save_for_backward: an
+    in-place change of an input between forward and backward is refused, and
+    with the cyclic garbage collector off, device memory returns to its level
+    before the solve once the outputs are dropped (no output is held by its
+    own grad_fn)."""
+    import gc
+    inst = W.lq_instance_general(np.random.default_rng(37), 4, 2, 200)
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([4], [2], [200], seg_len=8)
+    names = lq.LQSolveFunction.NAMES
+    leaves = {f: prob[f].clone().requires_grad_(True) for f in names}
+    A = leaves["A"] * 1.0
+    x, u, _ = lq.solve_diff(plan, A, *[leaves[f] for f in names[1:]])
+    L = (x * x).sum() + (u * u).sum()
+    with torch.no_grad():
+        A.add_(1e-3)
+    with pytest.raises(RuntimeError, match="modified by an inplace operation"):
+        L.backward()
+    del x, u, L, A
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        base = torch.cuda.memory_allocated()
+        for _ in range(3):
+            x, u, _ = lq.solve_diff(plan, *[leaves[f] for f in names])
+            L = (x * x).sum() + (u * u).sum()
+            grads = torch.autograd.grad(L, [leaves[f] for f in names])
+            del x, u, L, grads
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() == base
+    finally:
+        gc.enable()
