@@ -166,100 +166,247 @@ def cpu_baseline(inst, budget_s: float = 10.0) -> dict:
                       f"in {dt:.1f} s on one host core"}
 
 
-def batched(lqscan, workloads, dev, steps: int, warmup: int) -> dict:
-    """Throughput of the batched workloads (inputs generated on the device):
-    the differentiated batch (256 instances, n=12, m=4, T=4096, forward +
-    adjoint) and the ragged batch (4096 instances, T ~ U{32..2048},
-    n in {2, 4, 12}, m = max(1, n/3), forward), each with the plain sequential
-    path (one segment per instance) beside it."""
+# ---------------------------------------------------------------------------
+# Whole-solve cost per stage (the scan method's product count of section 8(d)
+# of the design and the bytes a perfect kernel would move), for the batched
+# and small-case lines.  Forward: read A, B, c, Q, R, write x, u.  Forward +
+# adjoint adds re-reading A, B, Q, R, x, u and the loss gradients, and writing
+# the gradients of A, B, c, Q, R.
+# ---------------------------------------------------------------------------
+
+
+def stage_model(n: int, m: int, adjoint: bool = False) -> dict:
+    words = 2 * n * n + n * m + 2 * n + m * m + m
+    flops = 24.7 * n ** 3 + 8 * n * n * m
+    if adjoint:
+        words += 4 * n * n + 2 * n * m + 2 * m * m + 3 * n + 2 * m
+        flops += 4 * n ** 3 + 8 * n * n * m
+    return {"bytes": 8.0 * words, "flops": flops}
+
+
+def fractions(sizes, ms: float, adjoint: bool = False) -> dict:
+    """Achieved HBM and FP64 rates of a batch of (n, m, T) solved in ms, and
+    their fractions of the MI355X peaks."""
+    by = sum(T * stage_model(n, m, adjoint)["bytes"] for n, m, T in sizes)
+    fl = sum(T * stage_model(n, m, adjoint)["flops"] for n, m, T in sizes)
+    s = ms * 1e-3
+    return {"GB/s": by / s / 1e9, "hbm_frac": by / s / 1e9 / HBM_PEAK_GBS, "TFLOP/s": fl / s / 1e12,
+            "fp64_frac": fl / s / 1e12 / FP64_PEAK_TFLOPS}
+
+
+def time_graph(fn, reps: int, warm: int = 3) -> float:
+    """ms per call of fn captured once in a HIP graph: the median over `reps`
+    replays, each bracketed by its own events (one eager call first)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for _ in range(warm):
+        g.replay()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        g.replay()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def time_eager(fn, reps: int, warm: int = 1) -> float:
+    """ms per call of fn launched eagerly (events around `reps` calls)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def host_info() -> dict:
+    threads = min(16, len(os.sched_getaffinity(0)))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"threads": threads, "nproc": os.cpu_count(), "cpu_model": model}
+
+
+def oracle_batch(insts, adjoint: bool) -> dict:
+    """The oracle over a sample of a batch on the host cores: a thread pool
+    (the oracle's C calls release the interpreter lock) over the instances,
+    largest T n^3 first so that the pool balances; stage-steps per second."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    info = host_info()
+
+    def one(i):
+        o = oracle.lq_solve(i.A, i.B, i.c, i.Q, i.R, i.QT, i.x0)
+        if adjoint:
+            oracle.lq_adjoint(i.A, i.B, i.c, i.Q, i.R, i.QT, i.x0, 2 * o["x"], 2 * o["u"])
+        return i.T
+
+    order = sorted(insts, key=lambda i: -i.T * i.n ** 3)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(info["threads"]) as ex:
+        stages = sum(ex.map(one, order))
+    dt = time.perf_counter() - t0
+    return {"value": stages / dt, "unit": "stage-steps/s", "cores": info["threads"], "kind": "oracle",
+            "seconds": dt, "stages": stages, "nproc": info["nproc"], "cpu_model": info["cpu_model"]}
+
+
+def solve_buffers(lqscan, plan, dev, grads=False):
+    import torch
+    b = {"ws": plan.new_workspace(dev), "status": torch.zeros(plan.batch, dtype=torch.int32, device=dev),
+         "val": lqscan.value_buffers(plan, dev), "st": lqscan.state_buffers(plan, dev)}
+    if grads:
+        b["grads"] = lqscan.grad_buffers(plan, ("A", "B", "c", "Q", "R", "QT", "x0"), dev)
+    return b
+
+
+def batched(lqscan, workloads, dev, reps: int, with_cpu: bool) -> dict:
+    """Throughput of the batched workloads (inputs generated on the device),
+    each timed as graph replays of the captured solve (eager launches beside
+    it), in FP64 and mixed precision, with the plain sequential path (one
+    segment per instance) beside the scan, and HBM / FP64 fractions from the
+    per-stage model of stage_model:
+      differentiated batch  256 instances, n=12, m=4, T=4096, forward + adjoint;
+      ragged batch          4096 instances, T ~ U{32..2048}, n in {2, 4, 12},
+                            m = max(1, n/3), forward; also per size class and
+                            with per-class segment lengths from the autotuner
+                            (tuned twice to show the choice is stable)."""
     import torch
 
-    def timeit(fn, reps):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(reps):
-            fn()
-        b.record()
-        torch.cuda.synchronize()
-        return a.elapsed_time(b) / reps
+    from paper_2409_20027_amd import autotune
 
-    res = {}
+    res = {"timing": "ms_per_step: median of graph replays; eager_ms: eager launches"}
+
+    def line(sizes, ms, eager, adjoint, **extra):
+        stages = sum(t for _, _, t in sizes)
+        d = {"ms_per_step": ms, "value": stages / (ms * 1e-3), "unit": "stage-steps/s", "eager_ms": eager,
+             **fractions(sizes, ms, adjoint)}
+        d.update(extra)
+        return d
+
     # differentiated batch
     sizes = [(12, 4, 4096)] * 256
     prob = workloads.device_batch(sizes, seed=4, a_scale=0.02, r_fixed=0.1, device=dev)
-    stages = 256 * 4096
-    for mode in ("scan", "sequential"):
-        plan = lqscan.Plan([12] * 256, [4] * 256, [4096] * 256, mode=mode)
-        ws = plan.new_workspace(dev)
-        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
-        val = lqscan.value_buffers(plan, dev)
-        st = lqscan.state_buffers(plan, dev)
-        grads = lqscan.grad_buffers(plan, ("A", "B", "c", "Q", "R", "QT", "x0"), dev)
-        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
-        torch.cuda.synchronize()
-        gx, gu = 2 * st["x"], 2 * st["u"]
+    for prec in ("fp64", "mixed"):
+        for mode in ("scan", "sequential"):
+            plan = lqscan.Plan([12] * 256, [4] * 256, [4096] * 256, mode=mode, precision=prec)
+            b = solve_buffers(lqscan, plan, dev, grads=True)
+            st, val = b["st"], b["val"]
+            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+            gx, gu = 2 * st["x"], 2 * st["u"]
 
-        def step():
-            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
-            lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, grads, ws, status)
+            def step():
+                lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+                lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, b["grads"], b["ws"],
+                                  b["status"])
 
-        ms = timeit(step, steps if mode == "scan" else 2)
-        assert int(status.abs().sum()) == 0
-        res[f"batch256_T4096_fwd_adj_{mode}"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3),
-                                                 "unit": "stage-steps/s", "seg_len": plan.seg_len()}
-        del ws, val, st, grads, gx, gu
+            r = reps if mode == "scan" else 2
+            ms = time_graph(step, r, warm=1)
+            eager = time_eager(step, r)
+            assert int(b["status"].abs().sum()) == 0
+            res[f"batch256_T4096_fwd_adj_{prec}_{mode}"] = line(sizes, ms, eager, True, seg_len=plan.seg_len())
+            del b, gx, gu, plan
     del prob
     torch.cuda.empty_cache()
+    if with_cpu:
+        insts = workloads.cfg4_batch(batch=48, T=4096)
+        res["batch256_T4096_fwd_adj_oracle"] = dict(oracle_batch(insts, True),
+                                                    sample="48 of the 256 instances (seed 4), forward + adjoint")
+        del insts
+
     # ragged batch, ordered by size class
     _, ns, ms_, Ts = workloads.cfg3_ragged_sizes()
     order = np.lexsort((Ts, ns))
     sizes = [(int(ns[i]), int(ms_[i]), int(Ts[i])) for i in order]
     prob = workloads.device_batch(sizes, seed=3, a_scale=0.05, device=dev)
-    stages = int(sum(t for _, _, t in sizes))
-    for mode in ("scan", "sequential"):
-        plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], mode=mode)
-        ws = plan.new_workspace(dev)
-        status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
-        val = lqscan.value_buffers(plan, dev)
-        st = lqscan.state_buffers(plan, dev)
-
-        def fwd():
-            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
-
-        ms = timeit(fwd, steps if mode == "scan" else 2)
-        assert int(status.abs().sum()) == 0
-        res[f"ragged4096_fwd_{mode}"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3), "unit": "stage-steps/s",
-                                         "stages": stages}
-        del ws, val, st
-    # the same batch with per-class segment lengths from the autotuner
-    from paper_2409_20027_amd import autotune
 
     def make_prob(sel):
-        sub = [sizes[j] for j in sel]
-        return workloads.device_batch(sub, seed=5, a_scale=0.05, device=dev)
+        return workloads.device_batch([sizes[j] for j in sel], seed=5, a_scale=0.05, device=dev)
 
+    tuned = {}
     t0 = time.perf_counter()
-    seg, _ = autotune.tune_sizes(sizes, make_prob, reps=2)
+    tuned["fp64"], _ = autotune.tune_sizes(sizes, make_prob, precision="fp64")
     tune_s = time.perf_counter() - t0
-    plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], seg_lens=seg)
-    ws = plan.new_workspace(dev)
-    status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
-    val = lqscan.value_buffers(plan, dev)
-    st = lqscan.state_buffers(plan, dev)
+    again, _ = autotune.tune_sizes(sizes, make_prob, precision="fp64")
+    tuned["mixed"], _ = autotune.tune_sizes(sizes, make_prob, precision="mixed")
+    res["ragged4096_autotune"] = {"seconds": tune_s, "choice_fp64": autotune.seg_lens_summary(sizes, tuned["fp64"]),
+                                  "choice_mixed": autotune.seg_lens_summary(sizes, tuned["mixed"]),
+                                  "fp64_second_tune_same_choice": again == tuned["fp64"],
+                                  "fp64_second_tune_differs_for": sum(a != b for a, b in zip(again, tuned["fp64"])),
+                                  "reps": autotune.DEFAULT_REPS, "margin": autotune.MARGIN}
+    for prec in ("fp64", "mixed"):
+        for mode in ("scan", "sequential", "autotuned"):
+            kw = {"seg_lens": tuned[prec]} if mode == "autotuned" else {"mode": mode}
+            plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], precision=prec,
+                               **kw)
+            b = solve_buffers(lqscan, plan, dev)
 
-    def fwd_t():
-        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+            def fwd():
+                lqscan.lq_solve(plan, prob, None, b["val"], b["st"]["x"], b["st"]["u"], b["st"]["lam"], b["ws"],
+                                b["status"])
 
-    ms = timeit(fwd_t, steps)
-    assert int(status.abs().sum()) == 0
-    res["ragged4096_fwd_autotuned"] = {"ms_per_step": ms, "value": stages / (ms * 1e-3), "unit": "stage-steps/s",
-                                       "tuning_s": tune_s, "choice": autotune.seg_lens_summary(sizes, seg)}
-    del ws, val, st
+            r = reps if mode != "sequential" else 3
+            ms = time_graph(fwd, r, warm=1)
+            eager = time_eager(fwd, r)
+            assert int(b["status"].abs().sum()) == 0
+            res[f"ragged4096_fwd_{prec}_{mode}"] = line(sizes, ms, eager, False)
+            del b, plan
     del prob
     torch.cuda.empty_cache()
+    # per size class (autotuned FP64 segment lengths): stage-steps/s and the
+    # fraction of the class's own HBM ceiling
+    for n in (2, 4, 12):
+        sel = [j for j, z in enumerate(sizes) if z[0] == n]
+        sub = [sizes[j] for j in sel]
+        cprob = workloads.device_batch(sub, seed=6, a_scale=0.05, device=dev)
+        for mode, kw in (("autotuned", {"seg_lens": [tuned["fp64"][j] for j in sel]}), ("sequential", {"mode": "sequential"})):
+            plan = lqscan.Plan([z[0] for z in sub], [z[1] for z in sub], [z[2] for z in sub], **kw)
+            b = solve_buffers(lqscan, plan, dev)
+
+            def fwd():
+                lqscan.lq_solve(plan, cprob, None, b["val"], b["st"]["x"], b["st"]["u"], b["st"]["lam"], b["ws"],
+                                b["status"])
+
+            ms = time_graph(fwd, reps, warm=1)
+            assert int(b["status"].abs().sum()) == 0
+            m_ = max(1, n // 3)
+            ceil = HBM_PEAK_GBS * 1e9 / stage_model(n, m_)["bytes"]
+            d = line(sub, ms, None, False, instances=len(sub), hbm_ceiling_stage_per_s=ceil)
+            d["frac_of_hbm_ceiling"] = d["value"] / ceil
+            res[f"ragged4096_class_n{n}_{mode}"] = d
+            del b, plan
+        del cprob
+        torch.cuda.empty_cache()
+    if with_cpu:
+        rng, ns_, ms2, Ts_ = workloads.cfg3_ragged_sizes()
+        pick = np.arange(0, len(Ts_), 8)
+        insts = [workloads.lq_instance(np.random.default_rng(1000 + int(j)), int(ns_[j]), int(ms2[j]), int(Ts_[j]))
+                 for j in pick]
+        res["ragged4096_fwd_oracle"] = dict(oracle_batch(insts, False),
+                                            sample=f"every 8th instance of the ragged batch ({len(insts)} "
+                                                   f"instances), forward")
+        del insts
     return res
 
 
@@ -419,6 +566,135 @@ def cv_rollout(lqscan, plan, prob, val, ws, status, inst, with_cpu: bool, reps: 
     return out
 
 
+def cfg0_small(lqscan, workloads, dev, replays: int, with_cpu: bool) -> dict:
+    """The small case (n=2, m=1, T=64, FP64): latency of the forward solve and
+    of forward + adjoint as graph replays, scan and sequential, the error
+    against the oracle, and the oracle's time per solve on one host core."""
+    import oracle
+    inst = workloads.cfg0_small()
+    prob = lqscan.to_device(workloads.pack([inst]), dev)
+    ref = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
+    gref = oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, 2 * ref["x"], 2 * ref["u"])
+    out = {"workload": "time-varying LQ, n=2, m=1, T=64, one instance, FP64"}
+    for mode in ("scan", "sequential"):
+        plan = lqscan.Plan([2], [1], [64], mode=mode)
+        b = solve_buffers(lqscan, plan, dev, grads=True)
+        st, val = b["st"], b["val"]
+
+        def fwd():
+            lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+
+        fwd()
+        gx, gu = 2 * st["x"], 2 * st["u"]
+
+        def step():
+            fwd()
+            lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, b["grads"], b["ws"], b["status"])
+
+        lat_f = time_graph(fwd, replays) * 1e3
+        lat_s = time_graph(step, replays) * 1e3
+        assert int(b["status"].abs().sum()) == 0
+        err = max(float(np.max(np.abs(st["x"].cpu().numpy().reshape(65, 2) - ref["x"])) / np.max(np.abs(ref["x"]))),
+                  max(float(np.max(np.abs(b["grads"][k].cpu().numpy().reshape(gref[k].shape) - gref[k]))
+                            / np.max(np.abs(gref[k]))) for k in ("A", "Q", "x0")))
+        out[mode] = {"forward_latency_us": lat_f, "forward_adjoint_latency_us": lat_s,
+                     "stage_steps_per_s_fwd_adj": 64 / (lat_s * 1e-6), "seg_len": plan.seg_len(),
+                     "err_vs_oracle": err}
+    if with_cpu:
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < 1.0:
+            r = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0)
+            oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, 2 * r["x"], 2 * r["u"])
+            reps += 1
+        us = (time.perf_counter() - t0) / reps * 1e6
+        out["oracle_one_core"] = {"forward_adjoint_us": us, "stage_steps_per_s_fwd_adj": 64 / (us * 1e-6)}
+    return out
+
+
+def cfg1_newton(lqscan, workloads, reps: int, with_cpu: bool) -> dict:
+    """The interior-point Newton loop on the tanh model (n=4, m=1, T=1024, six
+    barrier levels of ten Newton steps), FP64 and mixed: wall time of the
+    60-step solve with every step replayed from one captured HIP graph (no
+    host synchronisation inside), ms per Newton step and stage-steps/s
+    (T stages per Newton step); final cost against the FP64 oracle's and the
+    number of decisions that differ; the oracle's loop on one host core."""
+    import torch
+
+    import oracle
+    p = workloads.nmpc_problem(seed=1, T=1024)
+    levels, iters = workloads.NMPC_MU_LEVELS, workloads.NMPC_ITERS_PER_LEVEL
+    a0, nu0 = workloads.NMPC_ALPHA0, workloads.NMPC_NU0
+    steps = len(levels) * iters
+    t0 = time.perf_counter()
+    ref = oracle.nmpc_solve(p, levels, iters, a0, nu0)
+    cpu_s = time.perf_counter() - t0
+    out = {"workload": "tanh-network dynamics, n=4, m=1, T=1024, 6 barrier levels x 10 Newton steps",
+           "newton_steps": steps}
+    for prec in ("fp64", "mixed"):
+        s = lqscan.NewtonMPC(p, precision=prec)
+        trace = s.run(levels, iters, a0, nu0)
+        g = s._capture_step()
+
+        def solve():
+            s.init(a0, nu0)
+            for mu in levels:
+                for _ in range(iters):
+                    s._sc[:, lqscan.NMPC_MU] = mu
+                    g.replay()
+
+        solve()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            solve()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ms = float(np.median(ts)) * 1e3
+        out[prec] = {"ms_per_solve": ms, "ms_per_newton_step": ms / steps,
+                     "stage_steps_per_s": p.T * steps / (ms * 1e-3),
+                     "final_cost_rel_err": abs(trace["cost"][-1] - ref["cost"][-1]) / abs(ref["cost"][-1]),
+                     "decision_mismatches": int(np.sum(trace["accept"] != ref["accept"]))}
+    if with_cpu:
+        out["oracle_one_core"] = {"ms_per_solve": cpu_s * 1e3, "ms_per_newton_step": cpu_s * 1e3 / steps,
+                                  "stage_steps_per_s": p.T * steps / cpu_s}
+    return out
+
+
+def cfg2_mixed(lqscan, dev, prob, inst, ref, gref, steps: int, replays: int) -> dict:
+    """The headline workload (n=12, m=4, T=16384, forward + adjoint) in mixed
+    precision: FP32 products, FP64 inverses, Cholesky factors and
+    symmetrisation; errors against the FP64 oracle."""
+    n, m, T = inst.n, inst.m, inst.T
+    plan = lqscan.Plan([n], [m], [T], precision="mixed")
+    b = solve_buffers(lqscan, plan, dev, grads=True)
+    st, val = b["st"], b["val"]
+
+    def fwd():
+        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+
+    fwd()
+    gx, gu = 2 * st["x"], 2 * st["u"]
+
+    def step():
+        fwd()
+        lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, b["grads"], b["ws"], b["status"])
+
+    ms = time_eager(step, steps, warm=3)
+    lat = time_graph(fwd, replays) * 1e3
+    assert int(b["status"].abs().sum()) == 0
+
+    def rel(a, r):
+        return float(np.max(np.abs(a - r)) / np.max(np.abs(r)))
+
+    err = {"x": rel(st["x"].cpu().numpy().reshape(T + 1, n), ref["x"]),
+           "u": rel(st["u"].cpu().numpy().reshape(T, m), ref["u"]),
+           "S": rel(val["S"].cpu().numpy().reshape(T + 1, n, n), ref["S"]),
+           **{f"grad_{k}": rel(b["grads"][k].cpu().numpy().reshape(gref[k].shape), gref[k]) for k in ("A", "Q", "x0")}}
+    return {"ms_per_step": ms, "value": T / (ms * 1e-3), "unit": "stage-steps/s", "dtype": "f32 products, f64 inverses",
+            "latency_us_T16384_forward": lat, "err_vs_oracle": err, **fractions([(n, m, T)], ms, True)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -434,8 +710,8 @@ def main():
     ap.add_argument("--no-cv", action="store_true", help="skip the conditional-value rollout comparison")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
-    ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc"), default=None,
-                    help="run only this section of the paper's workloads (GPU paths only) and print its JSON")
+    ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc", "batched", "cfg0", "cfg1"),
+                    default=None, help="run only this section (GPU paths only) and print its JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: sharding the horizon or the batch over several GPUs is a "
@@ -446,14 +722,17 @@ def main():
 
     from paper_2409_20027_amd import lqscan, workloads
 
+    dev = torch.device("cuda:0")
     if args.section:
         fn = {"paper_ip": lambda: paper_ip_solves(lqscan, workloads, 3, False),
               "paper_admm": lambda: paper_admm_solves(lqscan, workloads, False),
-              "paper_mpc": lambda: paper_mpc(lqscan, workloads, False)}[args.section]
+              "paper_mpc": lambda: paper_mpc(lqscan, workloads, False),
+              "batched": lambda: batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), False),
+              "cfg0": lambda: cfg0_small(lqscan, workloads, dev, args.replays, False),
+              "cfg1": lambda: cfg1_newton(lqscan, workloads, 3, False)}[args.section]
         print(json.dumps({args.section: fn()}))
         return
 
-    dev = torch.device("cuda:0")
     inst = workloads.cfg2_long(T=args.T)
     packed = workloads.pack([inst])
     prob = lqscan.to_device(packed, dev)
@@ -630,8 +909,11 @@ def main():
            "phase_roofline": phase_roofline,
            "cv_rollout": cv,
            "roofline": roof}
+    out["mixed_precision"] = cfg2_mixed(lqscan, dev, prob, inst, ref, gref, args.steps, args.replays)
+    out["small_case"] = cfg0_small(lqscan, workloads, dev, args.replays, not args.no_cpu)
+    out["newton_ip"] = cfg1_newton(lqscan, workloads, 3, not args.no_cpu)
     if not args.no_batch:
-        out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), 1)
+        out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), not args.no_cpu)
     if not args.no_paper:
         out["paper_ip_solves"] = paper_ip_solves(lqscan, workloads, 3, not args.no_cpu)
         out["paper_admm_solves"] = paper_admm_solves(lqscan, workloads, not args.no_cpu)

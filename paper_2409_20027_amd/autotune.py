@@ -7,12 +7,16 @@ depth T).  The best L depends on the state size, the horizon and on how many
 instances share the GPU, so it is measured instead of assumed.
 
 Instances are grouped into classes (n, m, T bucket).  For each class the tuner
-times the forward solve (lq_solve) of the class's instances
-for every candidate L with HIP events and keeps the fastest.  A class timed
+times the forward solve (lq_solve) of the class's instances for every
+candidate L with HIP events (the median of `reps` timed calls, each bracketed
+by its own events) and keeps the fastest only if it beats the library
+default (L = 0) by more than MARGIN; otherwise the default stays.  Choices
+within timing noise of each other therefore do not flip from one tuning to
+the next.  A class timed
 alone can prefer the scan where, inside the whole batch, the GPU is already
 full and the sequential recursion (least work) is faster; so the per-class
 choice is then refined on the whole batch, switching classes to L = T while
-that makes the batch faster.  Results are cached in a JSON file keyed by
+that makes the batch faster by more than MARGIN.  Results are cached in a JSON file keyed by
 class, batch-size bucket and precision, and returned as one segment length per
 instance for lq_plan_create_seg.
 """
@@ -25,6 +29,10 @@ import os
 import numpy as np
 
 DEFAULT_CANDIDATES = (0, 4, 8, 16, 32, 64, -1)   # 0 = library default, -1 = sequential (L = T)
+DEFAULT_REPS = 5
+# A candidate replaces the current choice only if it is faster by more than
+# this fraction (repeated timings of one configuration vary by a few percent).
+MARGIN = 0.05
 
 
 def _bucket(v: int) -> int:
@@ -52,16 +60,22 @@ def _time_forward_lens(lq, prob, sizes, seg_lens, precision, reps, torch):
 
     fwd()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in ev:
+        a.record()
         fwd()
-    b.record()
+        b.record()
     torch.cuda.synchronize()
-    return a.elapsed_time(b) / reps
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
-def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cache_path=None,
+def _pick(times: dict, default):
+    """The fastest candidate if it beats `default` by more than MARGIN, else `default`."""
+    best = min(times, key=times.get)
+    return best if times[best] < (1.0 - MARGIN) * times[default] else default
+
+
+def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=DEFAULT_REPS, cache_path=None,
                sample_per_class=None, refine=True):
     """Per-instance segment lengths for a batch given as (n, m, T) sizes.
 
@@ -95,7 +109,7 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
         sub = [sizes[j] for j in sel]
         times = {L: _time_forward(lq, prob, sub, L, precision, reps, torch) for L in candidates}
         del prob
-        best = min(times, key=times.get)
+        best = _pick(times, candidates[0])
         choice[(n, m, tb)] = best
         report[key] = {str(k): v for k, v in times.items()}
         cache[key] = {"L": best, "ms": report[key]}
@@ -120,14 +134,14 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
             trial = dict(choice)
             trial[key3] = -1
             t = run(trial)
-            if t < best_t:
+            if t < (1.0 - MARGIN) * best_t:
                 best_t, choice = t, trial
                 ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
                 cache[ck] = {"L": -1, "ms": cache.get(ck, {}).get("ms", {}), "refined_on_batch": True}
         # and the plain sequential recursion for every class
         allseq = {k: -1 for k in choice}
         t = run(allseq)
-        if t < best_t:
+        if t < (1.0 - MARGIN) * best_t:
             best_t, choice = t, allseq
             for key3 in classes:
                 ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
@@ -144,7 +158,7 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
     return seg_lens, report
 
 
-def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=3, cache_path=None,
+def tune(insts, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=DEFAULT_REPS, cache_path=None,
          sample_per_class=None, refine=True):
     """tune_sizes for a list of LQInstance (host arrays, packed and uploaded per class)."""
     from . import lqscan as lq
@@ -168,4 +182,4 @@ def seg_lens_summary(insts, seg_lens):
     return {f"n={n},T<={tb}": sorted(map(str, v)) for (n, tb), v in sorted(rows.items())}
 
 
-__all__ = ["tune", "tune_sizes", "class_key", "seg_lens_summary", "DEFAULT_CANDIDATES", "np"]
+__all__ = ["tune", "tune_sizes", "class_key", "seg_lens_summary", "DEFAULT_CANDIDATES", "DEFAULT_REPS", "MARGIN"]

@@ -65,3 +65,18 @@ def test_stale_traffic_record_is_not_reported(monkeypatch):
     """A record taken on other kernel sources is reported as null."""
     monkeypatch.setattr(bench, "source_hash", lambda kernel: "0" * 64)
     assert bench.stored_traffic("value_scan") is None
+
+
+def test_stage_model_matches_the_stated_per_stage_costs():
+    """Per-stage algorithmic bytes of the batched lines: inputs A, B, c, Q, R
+    and outputs x, u, 16 / 46 / 380 words for n = 2, 4, 12 (m = 1, 1, 4), so
+    HBM ceilings of 62.5, 21.7 and 2.63 G stage/s at 8 TB/s; the scan method's
+    flops 24.7 n^3 + 8 n^2 m (about 48 k at n = 12)."""
+    import bench
+    for (n, m), words in {(2, 1): 16, (4, 1): 46, (12, 4): 380}.items():
+        assert bench.stage_model(n, m)["bytes"] == 8 * words
+    assert abs(bench.stage_model(12, 4)["flops"] - 47290) < 1
+    ceil = {n: bench.HBM_PEAK_GBS * 1e9 / bench.stage_model(n, max(1, n // 3))["bytes"] for n in (2, 4, 12)}
+    assert abs(ceil[2] - 62.5e9) < 1e6 and abs(ceil[4] - 21.74e9) < 1e7 and abs(ceil[12] - 2.63e9) < 1e7
+    # forward + adjoint: about 9.1 KB per stage at n = 12
+    assert bench.stage_model(12, 4, True)["bytes"] == 9024
