@@ -235,6 +235,30 @@ lq_status lq_solve(const lq_plan *plan, const lq_problem *prob, const double *el
                    double *x, double *u, double *lambda, void *workspace, int32_t *status, void *stream);
 
 /*
+ * lq_solve_static -- lq_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture that must not see an allocation, tight
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with the scan buffers in a scratch array that the library holds
+ * in device memory (LQ_STATIC_SCRATCH_BYTES per GPU, for the life of the
+ * process) instead of a caller workspace.  The call allocates nothing and
+ * makes no allocating library call; its first call on a device looks up that
+ * device's copy of the array (once per device).
+ * Arguments, layouts, ownership and numerical failures are those of lq_solve
+ * without `workspace`.  Errors: those of lq_solve, and LQ_ERR_WORKSPACE
+ * (synchronously, nothing enqueued) if the plan's scan buffers exceed
+ * LQ_STATIC_SCRATCH_BYTES (lq_plan_static_bytes tells what a plan needs), or
+ * LQ_ERR_HIP if the array's address cannot be found.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind: calls that overlap in time on one GPU (concurrent streams, host
+ * threads) race and must be serialised by the caller.  The solve reads no
+ * scratch entry before writing it, so nothing needs clearing between calls.
+ */
+#define LQ_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+size_t lq_plan_static_bytes(const lq_plan *plan);
+lq_status lq_solve_static(const lq_plan *plan, const lq_problem *prob, const double *elements, const lq_value *out,
+                          double *x, double *u, double *lambda, int32_t *status, void *stream);
+
+/*
  * lq_adjoint -- reverse-mode derivative of the LQ solution (not in the
  * paper; implicit differentiation of the KKT system).  Given the loss
  * gradients gx = dL/dx_k (k = 0..T, (T+1) n) and gu = dL/du_k (T m), the

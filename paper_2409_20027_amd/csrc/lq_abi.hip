@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -30,6 +31,35 @@ int auto_seg_len(int T)
     if (L < 1) L = 1;
     if (L > 16) L = 16;
     return L;
+}
+
+}  // namespace
+
+// Scratch of lq_solve_static: the scan buffers of an allocation-free solve.
+// In host code `scratch` names a host-side stand-in, not device memory: only
+// the address hipGetSymbolAddress returns for the current device is passed
+// to kernels.
+static __device__ __align__(256) unsigned char scratch[LQ_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The current device's copy of `scratch`, looked up once per device.
+bool static_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return false;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return false;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return true;
 }
 
 }  // namespace
@@ -394,20 +424,39 @@ lq_status lq_rollout_cv(const lq_plan *p, const lq_problem *prob, const lq_value
     return launched();
 }
 
-lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out, double *x,
-                   double *u, double *lambda, void *workspace, int32_t *status, void *stream)
+// Value pass and rollout with the scan buffers at ws (only the plan's scan
+// regions [0, off_st) are used).
+static lq_status solve_with(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                            double *x, double *u, double *lambda, char *ws, int32_t *status, hipStream_t st)
 {
-    if (!p || !prob_ok(prob) || !value_ok(out) || !x || !u) return LQ_ERR_ARG;
-    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
-    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
     value_pass(p, P, elements, V, ws, Ya, status, st);
     rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
     return launched();
+}
+
+lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out, double *x,
+                   double *u, double *lambda, void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(out) || !x || !u) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    return solve_with(p, prob, elements, out, x, u, lambda, (char *)workspace, status, (hipStream_t)stream);
+}
+
+size_t lq_plan_static_bytes(const lq_plan *p) { return p ? p->off_st : 0; }
+
+lq_status lq_solve_static(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                          double *x, double *u, double *lambda, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(out) || !x || !u) return LQ_ERR_ARG;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    if (p->off_st > LQ_STATIC_SCRATCH_BYTES) return LQ_ERR_WORKSPACE;
+    void *ws = nullptr;
+    if (!static_scratch(&ws)) return LQ_ERR_HIP;
+    return solve_with(p, prob, elements, out, x, u, lambda, (char *)ws, status, (hipStream_t)stream);
 }
 
 lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *val, const double *x,

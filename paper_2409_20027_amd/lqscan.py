@@ -69,6 +69,11 @@ _lib.lq_rollout_cv.argtypes = _lib.lq_rollout.argtypes
 _lib.lq_rollout_cv.restype = ctypes.c_int
 _lib.lq_solve.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P, _P]
 _lib.lq_solve.restype = ctypes.c_int
+_lib.lq_solve_static.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.POINTER(LQValueC), _P, _P, _P, _P,
+                                 _P]
+_lib.lq_solve_static.restype = ctypes.c_int
+_lib.lq_plan_static_bytes.argtypes = [_plan_p]
+_lib.lq_plan_static_bytes.restype = ctypes.c_size_t
 _lib.lq_adjoint.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P,
                             ctypes.POINTER(LQGradsC), _P, _P, _P]
 _lib.lq_adjoint.restype = ctypes.c_int
@@ -83,7 +88,7 @@ _lib.lq_selftest_tile_inverse.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout", "lq_rollout_cv",
-            "lq_solve", "lq_adjoint", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
+            "lq_solve", "lq_solve_static", "lq_plan_static_bytes", "lq_adjoint", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
           "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply",
@@ -245,6 +250,19 @@ def lq_solve(plan: Plan, prob: dict, elements, value: dict, x, u, lam, workspace
     _check("lq_solve", _lib.lq_solve(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(elements),
                                      ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
                                      _ptr(workspace), _ptr(status), _stream(stream)))
+
+
+def lq_solve_static(plan: Plan, prob: dict, elements, value: dict, x, u, lam, status=None, stream=None):
+    _check("lq_solve_static", _lib.lq_solve_static(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(elements),
+                                                   ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
+                                                   _ptr(status), _stream(stream)))
+
+
+def lq_plan_static_bytes(plan: Plan) -> int:
+    return int(_lib.lq_plan_static_bytes(plan.handle))
+
+
+LQ_STATIC_SCRATCH_BYTES = 32 << 20
 
 
 def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: dict, workspace, status=None,

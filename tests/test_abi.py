@@ -61,7 +61,7 @@ def test_version(lib):
 # called with a null plan (or null buffers) and must return LQ_ERR_ARG (-1)
 # before any device work
 NULL_PLAN_CALLS = {"lq_build_elements": 5, "lq_scan_solve": 7, "lq_rollout": 9, "lq_rollout_cv": 9, "lq_solve": 10,
-                   "lq_adjoint": 12, "nmpc_init": 5, "newton_step": 6, "nmpc_admm_update": 5, "nmpc_shift": 6,
+                   "lq_solve_static": 9, "lq_adjoint": 12, "nmpc_init": 5, "newton_step": 6, "nmpc_admm_update": 5, "nmpc_shift": 6,
                    "lq_plan_phase_times": 3}
 
 
@@ -73,7 +73,7 @@ def test_null_plan_is_an_argument_error(lib, name):
 
 
 def test_size_queries_of_a_null_plan(lib):
-    for name in ("lq_plan_workspace_bytes", "lq_plan_elements_bytes", "nmpc_workspace_bytes"):
+    for name in ("lq_plan_workspace_bytes", "lq_plan_elements_bytes", "nmpc_workspace_bytes", "lq_plan_static_bytes"):
         f = getattr(lib, name)
         f.restype = ctypes.c_size_t
         f.argtypes = [ctypes.c_void_p]
