@@ -327,6 +327,38 @@ def batched(lqscan, workloads, dev, reps: int, with_cpu: bool) -> dict:
             assert int(b["status"].abs().sum()) == 0
             res[f"batch256_T4096_fwd_adj_{prec}_{mode}"] = line(sizes, ms, eager, True, seg_len=plan.seg_len())
             del b, gx, gu, plan
+    # level checkpointing: the forward keeps one carry per `stride` segments
+    # (or nothing: "recompute"), the adjoint recomputes S, Gamma from it; the
+    # bytes kept between forward and backward against the stored value arrays
+    plan = lqscan.Plan([12] * 256, [4] * 256, [4096] * 256)
+    b = solve_buffers(lqscan, plan, dev, grads=True)
+    st, val = b["st"], b["val"]
+    gx, gu = 2 * st["x"], 2 * st["u"]
+    aws = plan.new_adjoint_ckpt_workspace(dev)
+    value_bytes = sum(int(t.numel()) * 8 for t in val.values())
+    stored_ms = res["batch256_T4096_fwd_adj_fp64_scan"]["ms_per_step"]
+    ck = {"stored_value_bytes": value_bytes, "stored_ms_per_step": stored_ms}
+    for stride in (1, 4, 16, "recompute"):
+        ckpt = None if stride == "recompute" else plan.new_checkpoint(stride, dev)
+        s_ = 1 if ckpt is None else stride
+
+        def step():
+            if ckpt is None:
+                lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+            else:
+                lqscan.lq_solve_ckpt(plan, prob, None, val, st["x"], st["u"], st["lam"], ckpt, s_, b["ws"],
+                                     b["status"])
+            lqscan.lq_adjoint_ckpt(plan, prob, ckpt, s_, st["x"], st["u"], st["lam"], gx, gu, b["grads"], aws,
+                                   b["status"])
+
+        ms = time_graph(step, reps, warm=1)
+        assert int(b["status"].abs().sum()) == 0
+        kept = 0 if ckpt is None else plan.checkpoint_bytes(stride)
+        ck[f"stride_{stride}"] = dict(line(sizes, ms, None, True), checkpoint_bytes=kept,
+                                      bytes_saved=value_bytes - kept, time_added_ms=ms - stored_ms)
+        del ckpt
+    res["batch256_T4096_fwd_adj_fp64_checkpointed"] = ck
+    del b, gx, gu, aws, plan, val, st
     del prob
     torch.cuda.empty_cache()
     if with_cpu:
@@ -408,6 +440,72 @@ def batched(lqscan, workloads, dev, reps: int, with_cpu: bool) -> dict:
                                                    f"instances), forward")
         del insts
     return res
+
+
+def ragged_replay(lqscan, workloads, dev, replays: int) -> dict:
+    """Graph replays of the captured ragged-batch forward solve (4096
+    instances, default segments, FP64), for a kernel trace: under
+    rocprofv3 --kernel-trace the dispatches of each replay show whether the
+    gaps between the per-phase and per-level launches matter against the
+    batch solve (--gap-summary reads that trace)."""
+    import torch
+
+    _, ns, ms_, Ts = workloads.cfg3_ragged_sizes()
+    order = np.lexsort((Ts, ns))
+    sizes = [(int(ns[i]), int(ms_[i]), int(Ts[i])) for i in order]
+    prob = workloads.device_batch(sizes, seed=3, a_scale=0.05, device=dev)
+    res = {}
+    for mode in ("scan", "sequential"):
+        plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], mode=mode)
+        b = solve_buffers(lqscan, plan, dev)
+
+        def fwd():
+            lqscan.lq_solve(plan, prob, None, b["val"], b["st"]["x"], b["st"]["u"], b["st"]["lam"], b["ws"],
+                            b["status"])
+
+        res[mode] = {"ms_per_replay": time_graph(fwd, replays, warm=1), "replays": replays}
+        assert int(b["status"].abs().sum()) == 0
+        del b, plan
+    return res
+
+
+def gap_summary(path: str, split_us: float = 5.0) -> dict:
+    """Launch gaps inside graph replays, from a rocprofv3 kernel trace (CSV
+    with Kernel_Name, Start_Timestamp, End_Timestamp): the library's
+    dispatches (kernel names in namespace lqk) ordered by start; a replay is a
+    run of them whose start-to-previous-end gaps stay below split_us
+    (consecutive replays are separated by event records and a host wait).  Per
+    replay: dispatches, span, busy time (union of kernel intervals), idle time
+    between kernels and its share of the span."""
+    import csv
+
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"]))
+    rows.sort()
+    groups, cur = [], []
+    for a, b, k in rows:
+        ours = "lqk::" in k
+        if cur and (not ours or a - cur[-1][1] > split_us * 1e3):
+            groups.append(cur)
+            cur = []
+        if ours:
+            cur.append((a, b, k))
+    if cur:
+        groups.append(cur)
+    out = []
+    for g in groups:
+        if len(g) < 3:
+            continue
+        span = g[-1][1] - g[0][0]
+        busy, end = 0, g[0][0]
+        for a, b, _ in g:
+            busy += max(0, b - max(a, end))
+            end = max(end, b)
+        out.append({"dispatches": len(g), "span_us": span / 1e3, "busy_us": busy / 1e3,
+                    "idle_us": (span - busy) / 1e3, "idle_frac": (span - busy) / span if span else 0.0})
+    return {"replays": out, "max_idle_frac": max((o["idle_frac"] for o in out), default=None)}
 
 
 def paper_ip_solves(lqscan, workloads, reps: int, with_cpu: bool) -> dict:
@@ -710,9 +808,15 @@ def main():
     ap.add_argument("--no-cv", action="store_true", help="skip the conditional-value rollout comparison")
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
-    ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc", "batched", "cfg0", "cfg1"),
+    ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc", "batched", "cfg0", "cfg1",
+                                          "ragged_replay"),
                     default=None, help="run only this section (GPU paths only) and print its JSON")
+    ap.add_argument("--gap-summary", metavar="KERNEL_TRACE_CSV", default=None,
+                    help="summarise launch gaps inside graph replays from a rocprofv3 kernel trace (no GPU)")
     args = ap.parse_args()
+    if args.gap_summary:
+        print(json.dumps(gap_summary(args.gap_summary)))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: sharding the horizon or the batch over several GPUs is a "
               "design in this repository, not a built path (run with --gpus 1)", file=sys.stderr)
@@ -729,7 +833,8 @@ def main():
               "paper_mpc": lambda: paper_mpc(lqscan, workloads, False),
               "batched": lambda: batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), False),
               "cfg0": lambda: cfg0_small(lqscan, workloads, dev, args.replays, False),
-              "cfg1": lambda: cfg1_newton(lqscan, workloads, 3, False)}[args.section]
+              "cfg1": lambda: cfg1_newton(lqscan, workloads, 3, False),
+              "ragged_replay": lambda: ragged_replay(lqscan, workloads, dev, max(3, min(args.steps, 10)))}[args.section]
         print(json.dumps({args.section: fn()}))
         return
 

@@ -280,6 +280,53 @@ lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value
                      void *workspace, int32_t *status, void *stream);
 
 /*
+ * Level checkpointing of the differentiated solve (not in the paper): the
+ * forward keeps only the scan's segment carries, and the adjoint recomputes
+ * S_k, s_k, Gamma_k, gamma_k from them instead of reading them back, so that
+ * between forward and backward a caller holds one (n+1) x (n+1) carry per
+ * `stride` segments instead of the (T+1) n^2 + T m n + ... value arrays.
+ *
+ * The checkpoint of a plan for a stride (>= 1) is lq_plan_checkpoint_bytes
+ * of device memory (caller-owned, 256-byte aligned): one 16 x 16-double slot
+ * per group of `stride` consecutive segments of an instance, holding the
+ * value function S~ = [[S, s], [s', const]] at the group's right end (the
+ * terminal element for the instance's last group) as an (n+1) x (n+1)
+ * row-major block at the start of the slot; instance i's first slot is
+ * seg0_i / stride + i (seg0_i: the instance's first segment in the plan).
+ *
+ * lq_solve_ckpt -- lq_solve that also writes the checkpoint for `stride`.
+ * Arguments, layouts, ownership and errors are those of lq_solve, plus
+ * LQ_ERR_ARG for stride < 1 and LQ_ERR_WORKSPACE for a NULL or misaligned
+ * ckpt.  The value outputs `out` are still written (the rollout's co-states
+ * need S_k and s_k); a caller that differentiates later may release them once
+ * the call has completed and keep only ckpt, x, u and lambda.
+ *
+ * lq_adjoint_ckpt -- lq_adjoint without the value functions: with ckpt
+ * (written by lq_solve_ckpt for the same problem, plan and stride) one wave
+ * per group reruns the Bellman steps of eq:value-fun-param (with the gain of
+ * eq:value-fun-feedback) from the group's carry, right to left over its
+ * stride * seg_len stages; with ckpt == NULL the whole value pass (Alg. 2)
+ * is rerun from the problem data (nothing kept from the forward but x, u,
+ * lambda).  The recomputed S, s, Gamma, gamma go to the workspace, which
+ * must hold lq_plan_adjoint_ckpt_workspace_bytes (more than
+ * lq_plan_workspace_bytes); the rest is lq_adjoint.  With stride 1 the
+ * recomputed arrays equal the forward's bit for bit; larger strides trade
+ * checkpoint memory (about 1/stride) for a longer sequential sweep per wave,
+ * and agree with the forward up to rounding order.  Numerical failures are
+ * those of the forward's Bellman steps (LQ_ERR_NOT_PD, LQ_ERR_NONFINITE), then
+ * of lq_adjoint.
+ */
+size_t lq_plan_checkpoint_bytes(const lq_plan *plan, int32_t stride);
+size_t lq_plan_adjoint_ckpt_workspace_bytes(const lq_plan *plan);
+lq_status lq_solve_ckpt(const lq_plan *plan, const lq_problem *prob, const double *elements, const lq_value *out,
+                        double *x, double *u, double *lambda, double *ckpt, int32_t stride, void *workspace,
+                        int32_t *status, void *stream);
+lq_status lq_adjoint_ckpt(const lq_plan *plan, const lq_problem *prob, const double *ckpt, int32_t stride,
+                          const double *x, const double *u, const double *lambda,
+                          const double *gx, const double *gu, const lq_grads *grads,
+                          void *workspace, int32_t *status, void *stream);
+
+/*
  * ---------------------------------------------------------------------------
  * Newton / interior-point step (Alg. 4 inside the log-barrier method of
  * Sec. II-B) for x_{k+1} = x_k + h f(x_k, u_k) (one explicit Euler step) with
@@ -439,7 +486,8 @@ enum {
     LQ_PH_CV_FOLD = 13,       /* conditional-value rollout: fold of each segment    */
     LQ_PH_CV_SCAN = 14,       /* conditional-value rollout: log-depth prefix scan   */
     LQ_PH_CV_START = 15,      /* conditional-value rollout: segment-start states    */
-    LQ_NPHASE = 16
+    LQ_PH_ADJ_RECOMPUTE = 16, /* checkpointed adjoint: S, Gamma from the checkpoint  */
+    LQ_NPHASE = 17
 };
 /*
  * lq_plan_set_timing enables event recording around the phases whose bit is

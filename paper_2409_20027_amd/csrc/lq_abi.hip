@@ -319,7 +319,8 @@ lq_status lq_build_elements(const lq_plan *p, const lq_problem *prob, double *el
 // Value pass: fold, log-depth scan, Bellman sweep.  With Yroll the sweep also
 // writes the rollout scan's entries (its segment fold fused in).
 static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *elements, const lqk::ValPtrs &V,
-                       char *ws, double *Yroll, int32_t *status, hipStream_t st)
+                       char *ws, double *Yroll, int32_t *status, hipStream_t st, double *ckpt = nullptr,
+                       int stride = 1)
 {
     double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
     timed(p, LQ_PH_VALUE_FOLD, st, [&] {
@@ -339,7 +340,7 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
     double *fin = in;
     timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
         lqk::launch_value_riccati(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
-                                  V, Yroll, status);
+                                  V, Yroll, ckpt, stride, status);
     });
 }
 
@@ -425,14 +426,16 @@ lq_status lq_rollout_cv(const lq_plan *p, const lq_problem *prob, const lq_value
 }
 
 // Value pass and rollout with the scan buffers at ws (only the plan's scan
-// regions [0, off_st) are used).
+// regions [0, off_st) are used); with ckpt the Bellman sweep also writes the
+// checkpoint of the differentiated solve.
 static lq_status solve_with(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
-                            double *x, double *u, double *lambda, char *ws, int32_t *status, hipStream_t st)
+                            double *x, double *u, double *lambda, char *ws, int32_t *status, hipStream_t st,
+                            double *ckpt = nullptr, int stride = 1)
 {
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
-    value_pass(p, P, elements, V, ws, Ya, status, st);
+    value_pass(p, P, elements, V, ws, Ya, status, st, ckpt, stride);
     rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
     return launched();
 }
@@ -448,6 +451,53 @@ lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *eleme
 
 size_t lq_plan_static_bytes(const lq_plan *p) { return p ? p->off_st : 0; }
 
+// Checkpoint slots for a stride: total_seg / stride + batch tiles (ckpt_slot).
+static int64_t ckpt_slots(const lq_plan *p, int stride) { return p->total_seg / stride + p->batch; }
+
+size_t lq_plan_checkpoint_bytes(const lq_plan *p, int32_t stride)
+{
+    if (!p || stride < 1) return 0;
+    return align_up((size_t)ckpt_slots(p, stride) * TILE * sizeof(double));
+}
+
+// The checkpointed adjoint's workspace: the plan's workspace, then room for
+// the recomputed S, s, Gamma, gamma.
+struct RecomputeLayout {
+    size_t S, s, G, g, total;
+};
+static RecomputeLayout recompute_layout(const lq_plan *p)
+{
+    RecomputeLayout L{};
+    int64_t nS = 0, ns = 0, nG = 0, ng = 0;
+    for (const InstDesc &d : p->h_inst) {
+        nS += (int64_t)(d.T + 1) * d.n * d.n;
+        ns += (int64_t)(d.T + 1) * d.n;
+        nG += (int64_t)d.T * d.m * d.n;
+        ng += (int64_t)d.T * d.m;
+    }
+    size_t off = align_up(p->ws_bytes);
+    L.S = off; off = align_up(off + (size_t)nS * sizeof(double));
+    L.s = off; off = align_up(off + (size_t)ns * sizeof(double));
+    L.G = off; off = align_up(off + (size_t)nG * sizeof(double));
+    L.g = off; off = align_up(off + (size_t)ng * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+size_t lq_plan_adjoint_ckpt_workspace_bytes(const lq_plan *p) { return p ? recompute_layout(p).total : 0; }
+
+lq_status lq_solve_ckpt(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                        double *x, double *u, double *lambda, double *ckpt, int32_t stride, void *workspace,
+                        int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(out) || !x || !u || stride < 1) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
+    if (!ckpt || !aligned(ckpt)) return LQ_ERR_WORKSPACE;
+    return solve_with(p, prob, elements, out, x, u, lambda, (char *)workspace, status, (hipStream_t)stream, ckpt,
+                      stride);
+}
+
 lq_status lq_solve_static(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
                           double *x, double *u, double *lambda, int32_t *status, void *stream)
 {
@@ -459,18 +509,14 @@ lq_status lq_solve_static(const lq_plan *p, const lq_problem *prob, const double
     return solve_with(p, prob, elements, out, x, u, lambda, (char *)ws, status, (hipStream_t)stream);
 }
 
-lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *val, const double *x,
-                     const double *u, const double *lambda, const double *gx, const double *gu,
-                     const lq_grads *grads, void *workspace, int32_t *status, void *stream)
+// The adjoint's scans and sweeps from the value functions and gains in val.
+static lq_status adjoint_with(const lq_plan *p, const lq_problem *prob, const lqk::ValPtrs &val, const double *x,
+                              const double *u, const double *lambda, const double *gx, const double *gu,
+                              const lq_grads *grads, char *ws, int32_t *status, hipStream_t st)
 {
-    if (!p || !prob_ok(prob) || !val || !val->S || !val->s || !val->Gamma || !val->gamma) return LQ_ERR_ARG;
-    if (!x || !u || !lambda || !gx || !gu || !grads) return LQ_ERR_ARG;
-    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
-    hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
-    lqk::AdjPtrs J{val->S, val->s, val->Gamma, val->gamma, x, u, lambda, gx, gu,
+    lqk::AdjPtrs J{val.S, val.s, val.G, val.g, x, u, lambda, gx, gu,
                    (double *)(ws + p->off_st), (double *)(ws + p->off_gt)};
     lqk::GradPtrs G{grads->A, grads->B, grads->c, grads->Q, grads->R, grads->M,
                     grads->q, grads->r, grads->QT, grads->qT, grads->x0};
@@ -493,6 +539,40 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
         lqk::launch_adj_fwd_apply(p->nk, p->prec, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
     });
     return launched();
+}
+
+lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *val, const double *x,
+                     const double *u, const double *lambda, const double *gx, const double *gu,
+                     const lq_grads *grads, void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || !value_ok(val)) return LQ_ERR_ARG;
+    if (!x || !u || !lambda || !gx || !gu || !grads) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    const lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
+    return adjoint_with(p, prob, V, x, u, lambda, gx, gu, grads, (char *)workspace, status, (hipStream_t)stream);
+}
+
+lq_status lq_adjoint_ckpt(const lq_plan *p, const lq_problem *prob, const double *ckpt, int32_t stride,
+                          const double *x, const double *u, const double *lambda, const double *gx, const double *gu,
+                          const lq_grads *grads, void *workspace, int32_t *status, void *stream)
+{
+    if (!p || !prob_ok(prob) || (ckpt && stride < 1)) return LQ_ERR_ARG;
+    if (!x || !u || !lambda || !gx || !gu || !grads) return LQ_ERR_ARG;
+    if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
+    if (ckpt && !aligned(ckpt)) return LQ_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    const RecomputeLayout L = recompute_layout(p);
+    const lqk::ValPtrs V{(double *)(ws + L.S), (double *)(ws + L.s), (double *)(ws + L.G), (double *)(ws + L.g)};
+    const lqk::ProbPtrs P = probptrs(prob);
+    if (ckpt)
+        timed(p, LQ_PH_ADJ_RECOMPUTE, st, [&] {
+            lqk::launch_value_recompute(p->nk, p->prec, (unsigned)ckpt_slots(p, stride), st, P, p->d_inst,
+                                        p->d_seg_start, p->batch, stride, ckpt, V, status);
+        });
+    else
+        value_pass(p, P, nullptr, V, ws, nullptr, status, st);
+    return adjoint_with(p, prob, V, x, u, lambda, gx, gu, grads, ws, status, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -73,6 +73,14 @@ struct NmpcWork {
     int32_t *status;
 };
 
+// First checkpoint slot of instance i when one carry is kept per group of
+// `stride` segments: seg0 / stride + i.  The instance needs
+// ceil(nseg / stride) slots, and floor((seg0 + nseg) / stride) + i + 1 >=
+// floor(seg0 / stride) + i + ceil(nseg / stride), so the slots of
+// consecutive instances never overlap and total_seg / stride + batch slots
+// hold them all, without a table that depends on the stride.
+LQK_DEV int ckpt_slot(const InstDesc &d, int i, int stride) { return d.seg0 / stride + i; }
+
 // Index of the instance owning global item g, by binary search over the
 // prefix array start[0..batch] (start[0] = 0, start[batch] = total).
 LQK_DEV int find_inst(const int32_t *start, int batch, int64_t g)

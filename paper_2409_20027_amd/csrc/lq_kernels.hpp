@@ -21,7 +21,10 @@ void launch_cv_start(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, 
                      const int32_t *seg_start, int batch, const double *Xfin, double *Y, int32_t *status);
 void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                           const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
-                          int32_t *status);
+                          double *ckpt, int stride, int32_t *status);
+void launch_value_recompute(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                            const int32_t *seg_start, int batch, int stride, const double *ckpt, ValPtrs V,
+                            int32_t *status);
 void launch_roll_fold(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                       const int32_t *seg_start, int batch, double *Y);
 void launch_affine_ks(int nk, int pr, int radix, unsigned grid, hipStream_t st, const InstDesc *inst, const int32_t *x_start, int batch,

@@ -423,11 +423,17 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
     }
 }
 
+// With ckpt != nullptr the last segment of each group of `stride` segments
+// also stores its carry (the value function at the group's right end; the
+// terminal element for the instance's last group) in checkpoint slot
+// ckpt_slot(...) + s / stride, from which k_value_recompute restarts the
+// sweep of the whole group.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
                                                       const int32_t *__restrict__ seg_start, int batch,
                                                       const double *__restrict__ Xfin, ValPtrs V,
-                                                      double *__restrict__ Yroll, int32_t *status)
+                                                      double *__restrict__ Yroll, double *__restrict__ ckpt,
+                                                      int stride, int32_t *status)
 {
     __shared__ double lds[SLOT];
     __shared__ double stg[2 * stage_buf_size<NK>()];
@@ -442,6 +448,8 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
     // segment the terminal element
     Tile St = (s == d.nseg - 1) ? load_terminal_J(P, d, lds)
                                 : gload_c(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE, n + 1);
+    if (ckpt && ((s + 1) % stride == 0 || s == d.nseg - 1))
+        gstore_c(ckpt + (int64_t)(ckpt_slot(d, i, stride) + s / stride) * TILE, St, n + 1);
     int code = 0, fk = 0;
     if (s == d.nseg - 1) {
         gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
@@ -465,6 +473,56 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         if (s == 0) gstore_c(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n), d.n + 1);
         if (s < d.nseg - 1) gstore_c(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
     }
+    if (code) report(status, i, code, fk);
+}
+
+// ---------------------------------------------------------------------------
+// Recompute of the value functions and the control law from a checkpoint
+// (level checkpointing of the differentiated solve): one wave per group of
+// `stride` consecutive segments, restarting from the group's stored carry and
+// running the Bellman steps of eq:value-fun-param (in the Riccati form of
+// k_value_riccati) over all its stages right to left.  The results equal the
+// forward's up to the association order inside the group (bit for bit when
+// stride = 1: the same carry and the same sweep).  Block g serves slot g;
+// slots between one instance's last group and the next instance's first are
+// idle.
+// ---------------------------------------------------------------------------
+template <int NK, int PR>
+__global__ __launch_bounds__(64) void k_value_recompute(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                        const int32_t *__restrict__ seg_start, int batch, int stride,
+                                                        const double *__restrict__ ckpt, ValPtrs V, int32_t *status)
+{
+    __shared__ double lds[SLOT];
+    __shared__ double stg[2 * stage_buf_size<NK>()];
+    const int g = blockIdx.x;
+    // instance owning slot g: the largest i with seg_start[i] / stride + i <= g
+    int lo = 0, hi = batch - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (seg_start[mid] / stride + mid <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int i = lo;
+    const InstDesc d = inst[i];
+    const int j = g - ckpt_slot(d, i, stride);
+    const int groups = (d.nseg + stride - 1) / stride;
+    if (j >= groups) return;
+    const int n = d.n;
+    const int k0 = j * stride * d.L, k1 = min(k0 + stride * d.L, d.T);
+    Tile St = gload_c(ckpt + (int64_t)g * TILE, n + 1);
+    int code = 0, fk = 0;
+    if (j == groups - 1) {
+        gstore_rm(V.S + d.oS + (int64_t)d.T * n * n, St, n, n, n);
+        store_vec(V.s + d.os + (int64_t)d.T * n, St, n, n);
+        note(tfinite(St), ERR_NONFINITE, d.T, code, fk);
+    }
+    Tile PhiT = tzero();
+    if ((P.M != nullptr) || (P.r != nullptr))
+        riccati_sweep<NK, PR, true, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
+    else
+        riccati_sweep<NK, PR, false, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
     if (code) report(status, i, code, fk);
 }
 
@@ -536,9 +594,18 @@ void launch_cv_start(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, 
 
 void launch_value_riccati(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
                           const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
-                          int32_t *status)
+                          double *ckpt, int stride, int32_t *status)
 {
-#define CALL(K, R) hipLaunchKernelGGL((k_value_riccati<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, Yroll, status)
+#define CALL(K, R) hipLaunchKernelGGL((k_value_riccati<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, Xfin, V, Yroll, ckpt, stride, status)
+    LQK_DISPATCH(nk, pr, CALL)
+#undef CALL
+}
+
+void launch_value_recompute(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                            const int32_t *seg_start, int batch, int stride, const double *ckpt, ValPtrs V,
+                            int32_t *status)
+{
+#define CALL(K, R) hipLaunchKernelGGL((k_value_recompute<K, R>), dim3(grid), dim3(64), 0, st, P, inst, seg_start, batch, stride, ckpt, V, status)
     LQK_DISPATCH(nk, pr, CALL)
 #undef CALL
 }

@@ -77,6 +77,16 @@ _lib.lq_plan_static_bytes.restype = ctypes.c_size_t
 _lib.lq_adjoint.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), ctypes.POINTER(LQValueC), _P, _P, _P, _P, _P,
                             ctypes.POINTER(LQGradsC), _P, _P, _P]
 _lib.lq_adjoint.restype = ctypes.c_int
+_lib.lq_plan_checkpoint_bytes.argtypes = [_plan_p, ctypes.c_int32]
+_lib.lq_plan_checkpoint_bytes.restype = ctypes.c_size_t
+_lib.lq_plan_adjoint_ckpt_workspace_bytes.argtypes = [_plan_p]
+_lib.lq_plan_adjoint_ckpt_workspace_bytes.restype = ctypes.c_size_t
+_lib.lq_solve_ckpt.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.POINTER(LQValueC), _P, _P, _P, _P,
+                               ctypes.c_int32, _P, _P, _P]
+_lib.lq_solve_ckpt.restype = ctypes.c_int
+_lib.lq_adjoint_ckpt.argtypes = [_plan_p, ctypes.POINTER(LQProblemC), _P, ctypes.c_int32, _P, _P, _P, _P, _P,
+                                 ctypes.POINTER(LQGradsC), _P, _P, _P]
+_lib.lq_adjoint_ckpt.restype = ctypes.c_int
 _lib.lq_plan_set_timing.argtypes = [_plan_p, ctypes.c_uint32, ctypes.c_int32]
 _lib.lq_plan_set_timing.restype = ctypes.c_int
 _lib.lq_plan_phase_times.argtypes = [_plan_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -88,11 +98,12 @@ _lib.lq_selftest_tile_inverse.restype = ctypes.c_int
 
 EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout", "lq_rollout_cv",
-            "lq_solve", "lq_solve_static", "lq_plan_static_bytes", "lq_adjoint", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
+            "lq_solve", "lq_solve_static", "lq_plan_static_bytes", "lq_adjoint",
+            "lq_plan_checkpoint_bytes", "lq_plan_adjoint_ckpt_workspace_bytes", "lq_solve_ckpt", "lq_adjoint_ckpt", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
 
 PHASES = ("build", "value_fold", "value_scan", "value_bellman", "roll_fold", "roll_scan", "roll_apply",
           "adj_back_fold", "adj_back_scan", "adj_back_apply", "adj_fwd_fold", "adj_fwd_scan", "adj_fwd_apply",
-          "cv_fold", "cv_scan", "cv_start")
+          "cv_fold", "cv_scan", "cv_start", "adj_recompute")
 
 
 class LQError(RuntimeError):
@@ -181,6 +192,18 @@ class Plan:
 
     def new_workspace(self, device="cuda"):
         return torch.empty(max(self.workspace_bytes(), 256), dtype=torch.uint8, device=device)
+
+    def checkpoint_bytes(self, stride: int) -> int:
+        return int(_lib.lq_plan_checkpoint_bytes(self._h, int(stride)))
+
+    def adjoint_ckpt_workspace_bytes(self) -> int:
+        return int(_lib.lq_plan_adjoint_ckpt_workspace_bytes(self._h))
+
+    def new_checkpoint(self, stride: int, device="cuda"):
+        return torch.empty(max(self.checkpoint_bytes(stride) // 8, 32), dtype=torch.float64, device=device)
+
+    def new_adjoint_ckpt_workspace(self, device="cuda"):
+        return torch.empty(max(self.adjoint_ckpt_workspace_bytes(), 256), dtype=torch.uint8, device=device)
 
     def new_elements(self, device="cuda"):
         return torch.empty(max(self.elements_bytes() // 8, 32), dtype=torch.float64, device=device)
@@ -274,6 +297,23 @@ def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: di
                                          _stream(stream)))
 
 
+def lq_solve_ckpt(plan: Plan, prob: dict, elements, value: dict, x, u, lam, ckpt, stride: int, workspace,
+                  status=None, stream=None):
+    _check("lq_solve_ckpt", _lib.lq_solve_ckpt(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(elements),
+                                               ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
+                                               _f64(ckpt), int(stride), _ptr(workspace), _ptr(status),
+                                               _stream(stream)))
+
+
+def lq_adjoint_ckpt(plan: Plan, prob: dict, ckpt, stride: int, x, u, lam, gx, gu, grads: dict, workspace,
+                    status=None, stream=None):
+    g = LQGradsC(*[_f64(grads.get(f)) for f in _PROBLEM_FIELDS])
+    _check("lq_adjoint_ckpt", _lib.lq_adjoint_ckpt(plan.handle, ctypes.byref(_problem_struct(prob)), _f64(ckpt),
+                                                   int(stride), _f64(x), _f64(u), _f64(lam), _f64(gx), _f64(gu),
+                                                   ctypes.byref(g), _ptr(workspace), _ptr(status),
+                                                   _stream(stream)))
+
+
 def lq_selftest_tile_inverse(X, Xinv, n1, homog, ok, stream=None):
     _check("lq_selftest_tile_inverse", _lib.lq_selftest_tile_inverse(_f64(X), _f64(Xinv), int(n1), int(homog),
                                                                      _ptr(ok), _stream(stream)))
@@ -358,30 +398,46 @@ def grad_buffers(plan: Plan, which, device="cuda") -> dict:
 
 
 class LQSolveFunction(torch.autograd.Function):
-    """(x, u) = LQ solution of the packed problem; gradients by lq_adjoint.
+    """(x, u) = LQ solution of the packed problem; gradients by the adjoint.
 
     Inputs are flat packed float64 device tensors (lq_problem layout); c, M, q,
-    r, qT may be None.  The forward pass is one lq_solve call, the backward
-    pass one lq_adjoint call; both run in the HIP library.  The problem
-    tensors and the outputs x, u are saved with save_for_backward (so an
-    in-place change of an input between forward and backward is detected and
-    no output is referenced from its own grad_fn); the value functions, gains,
-    co-states and the workspace are intermediates kept on ctx.
+    r, qT may be None.  `checkpoint` picks what the forward keeps for the
+    backward pass:
+      k >= 1       level checkpointing: lq_solve_ckpt keeps one value-function
+                   carry per k segments (lq_plan_checkpoint_bytes) and the
+                   backward's lq_adjoint_ckpt recomputes S, Gamma from it;
+      "recompute"  nothing but x, u and the co-states: lq_adjoint_ckpt reruns
+                   the whole value pass;
+      0            S, s, Gamma, gamma themselves (lq_solve, then lq_adjoint).
+    The problem tensors and the outputs x, u are saved with save_for_backward
+    (so an in-place change of an input between forward and backward is
+    detected and no output is referenced from its own grad_fn); the co-states,
+    checkpoint or value arrays are intermediates kept on ctx.
     """
 
     NAMES = ("A", "B", "c", "Q", "R", "QT", "x0", "M", "q", "r", "qT")
 
     @staticmethod
-    def forward(ctx, plan, A, B, c, Q, R, QT, x0, M, q, r, qT):
+    def forward(ctx, plan, checkpoint, A, B, c, Q, R, QT, x0, M, q, r, qT):
         prob = {"A": A, "B": B, "c": c, "Q": Q, "R": R, "QT": QT, "x0": x0, "M": M, "q": q, "r": r, "qT": qT}
         dev = A.device
         ws = plan.new_workspace(dev)
         status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
         val = value_buffers(plan, dev)
         st = state_buffers(plan, dev)
-        lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+        ctx.plan, ctx.lam, ctx.checkpoint = plan, st["lam"], checkpoint
+        ctx.val = ctx.ckpt = None
+        if checkpoint == 0:
+            lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+            ctx.val = val
+        elif checkpoint == "recompute":
+            lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+        else:
+            if not (isinstance(checkpoint, int) and checkpoint >= 1):
+                raise ValueError(f"checkpoint must be 0, a stride >= 1 or 'recompute', not {checkpoint!r}")
+            ctx.ckpt = plan.new_checkpoint(checkpoint, dev)
+            lq_solve_ckpt(plan, prob, None, val, st["x"], st["u"], st["lam"], ctx.ckpt, checkpoint, ws, status)
         ctx.save_for_backward(A, B, c, Q, R, QT, x0, M, q, r, qT, st["x"], st["u"])
-        ctx.plan, ctx.val, ctx.lam, ctx.ws = plan, val, st["lam"], ws
         ctx.mark_non_differentiable(status)
         return st["x"], st["u"], status
 
@@ -392,19 +448,28 @@ class LQSolveFunction(torch.autograd.Function):
         prob = dict(zip(names, saved[:len(names)]))
         x, u = saved[len(names):]
         plan = ctx.plan
-        want = [f for i, f in enumerate(names) if ctx.needs_input_grad[i + 1]]
+        want = [f for i, f in enumerate(names) if ctx.needs_input_grad[i + 2]]
         dev = x.device
         gx = torch.zeros_like(x) if gx is None else gx.contiguous()
         gu = torch.zeros_like(u) if gu is None else gu.contiguous()
         g = grad_buffers(plan, want, dev)
         status = torch.zeros(plan.batch, dtype=torch.int32, device=dev)
-        lq_adjoint(plan, prob, ctx.val, x, u, ctx.lam, gx, gu, g, ctx.ws, status)
-        return (None,) + tuple(g.get(f) for f in names)
+        if ctx.val is not None:
+            lq_adjoint(plan, prob, ctx.val, x, u, ctx.lam, gx, gu, g, plan.new_workspace(dev), status)
+        else:
+            stride = 1 if ctx.ckpt is None else ctx.checkpoint
+            lq_adjoint_ckpt(plan, prob, ctx.ckpt, stride, x, u, ctx.lam, gx, gu, g,
+                            plan.new_adjoint_ckpt_workspace(dev), status)
+        return (None, None) + tuple(g.get(f) for f in names)
 
 
-def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None):
-    """Differentiable LQ solve on packed device tensors; returns (x, u, status)."""
-    return LQSolveFunction.apply(plan, A, B, c, Q, R, QT, x0, M, q, r, qT)
+def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=None, *, checkpoint=1):
+    """Differentiable LQ solve on packed device tensors; returns (x, u, status).
+
+    checkpoint: stride of the level checkpoint kept for the backward pass
+    (default 1: one carry per segment), "recompute" (keep nothing), or 0 (keep
+    the value functions and gains)."""
+    return LQSolveFunction.apply(plan, checkpoint, A, B, c, Q, R, QT, x0, M, q, r, qT)
 
 
 # ---------------------------------------------------------------------------

@@ -61,7 +61,8 @@ def test_version(lib):
 # called with a null plan (or null buffers) and must return LQ_ERR_ARG (-1)
 # before any device work
 NULL_PLAN_CALLS = {"lq_build_elements": 5, "lq_scan_solve": 7, "lq_rollout": 9, "lq_rollout_cv": 9, "lq_solve": 10,
-                   "lq_solve_static": 9, "lq_adjoint": 12, "nmpc_init": 5, "newton_step": 6, "nmpc_admm_update": 5, "nmpc_shift": 6,
+                   "lq_solve_static": 9, "lq_adjoint": 12,
+                   "lq_solve_ckpt": 12, "lq_adjoint_ckpt": 13, "nmpc_init": 5, "newton_step": 6, "nmpc_admm_update": 5, "nmpc_shift": 6,
                    "lq_plan_phase_times": 3}
 
 
@@ -78,6 +79,12 @@ def test_size_queries_of_a_null_plan(lib):
         f.restype = ctypes.c_size_t
         f.argtypes = [ctypes.c_void_p]
         assert f(None) == 0
+    lib.lq_plan_checkpoint_bytes.restype = ctypes.c_size_t
+    lib.lq_plan_checkpoint_bytes.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    assert lib.lq_plan_checkpoint_bytes(None, 1) == 0
+    lib.lq_plan_adjoint_ckpt_workspace_bytes.restype = ctypes.c_size_t
+    lib.lq_plan_adjoint_ckpt_workspace_bytes.argtypes = [ctypes.c_void_p]
+    assert lib.lq_plan_adjoint_ckpt_workspace_bytes(None) == 0
     lib.lq_plan_seg_len.restype = ctypes.c_int32
     assert lib.lq_plan_seg_len(None) == 0
     lib.lq_plan_set_timing.restype = ctypes.c_int

@@ -290,3 +290,106 @@ def test_autograd_saved_tensors(lq):
         assert torch.cuda.memory_allocated() == base
     finally:
         gc.enable()
+
+
+# ---------------------------------------------------------------------------
+# Level checkpointing: lq_solve_ckpt keeps one value-function carry per
+# `stride` segments, lq_adjoint_ckpt recomputes S, s, Gamma, gamma from it
+# (or, with no checkpoint, reruns the whole value pass).
+# ---------------------------------------------------------------------------
+
+def gpu_grads_ckpt(lq, insts, stride, **plan_kw):
+    """Gradients through lq_solve_ckpt + lq_adjoint_ckpt (stride "recompute":
+    lq_solve, then lq_adjoint_ckpt without a checkpoint).  The backward
+    workspace is filled with NaN bytes first, so a value array the recompute
+    failed to write shows in the gradients."""
+    prob = lq.to_device(W.pack(insts))
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], **plan_kw)
+    status = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+    val = lq.value_buffers(plan)
+    st = lq.state_buffers(plan)
+    ws = plan.new_workspace()
+    if stride == "recompute":
+        ckpt, s = None, 1
+        lq.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+    else:
+        ckpt, s = plan.new_checkpoint(stride), stride
+        lq.lq_solve_ckpt(plan, prob, None, val, st["x"], st["u"], st["lam"], ckpt, s, ws, status)
+    torch.cuda.synchronize()
+    del val
+    want = [f for f in FIELDS if prob.get(f) is not None or f in ("M", "q", "r", "qT", "c")]
+    g = lq.grad_buffers(plan, want)
+    aws = plan.new_adjoint_ckpt_workspace()
+    aws.fill_(255)
+    lq.lq_adjoint_ckpt(plan, prob, ckpt, s, st["x"], st["u"], st["lam"], 2 * st["x"], 2 * st["u"], g, aws, status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    per = [dict() for _ in insts]
+    for f, t in g.items():
+        for j, a in enumerate(split(t.cpu().numpy(), [SHAPES[f](i) for i in insts])):
+            per[j][f] = a
+    return per
+
+
+@pytest.mark.parametrize("stride", [1, 2, 3, 16, "recompute"])
+def test_checkpointed_adjoint_ragged_batch(lq, stride):
+    """Ragged batch with every optional term in some instances, segment
+    lengths that leave ragged last segments and groups, T = 1 and a single
+    segment: every gradient against the oracle to 1e-10."""
+    rng = np.random.default_rng(90)
+    insts = [W.lq_instance(rng, n, m, T) for n, m, T in [(2, 1, 5), (12, 4, 70), (4, 1, 1), (7, 3, 33)]]
+    insts += [W.lq_instance_general(rng, 5, 2, 21), W.lq_instance_general(rng, 15, 4, 131)]
+    print(f"checkpoint stride {stride}", flush=True)
+    check(gpu_grads_ckpt(lq, insts, stride, seg_len=4), insts)
+
+
+@pytest.mark.parametrize("stride", [1, 4, "recompute"])
+def test_checkpointed_adjoint_long_horizon_sample(lq, stride):
+    """Sample of the differentiated-solve workload (3 x n=12, m=4, T=4096,
+    default segments) through the checkpointed adjoint: 1e-10 to the oracle."""
+    insts = W.cfg4_batch(batch=3, T=4096)
+    print(f"checkpoint stride {stride}, 3 x T=4096", flush=True)
+    check(gpu_grads_ckpt(lq, insts, stride), insts)
+
+
+def test_checkpoint_stride_one_equals_stored_path(lq):
+    """With stride 1 the recompute reruns the forward's own Bellman sweeps from
+    the same carries, so the gradients equal the stored-value path bit for
+    bit."""
+    rng = np.random.default_rng(91)
+    insts = [W.lq_instance_general(rng, 6, 2, 300), W.lq_instance(rng, 12, 4, 1000)]
+    a = gpu_grads(lq, insts)
+    b = gpu_grads_ckpt(lq, insts, 1)
+    for ga, gb in zip(a, b):
+        for f in ga:
+            assert np.array_equal(ga[f], gb[f]), f
+
+
+@pytest.mark.parametrize("checkpoint", [0, 1, 5, "recompute"])
+def test_autograd_checkpoint_modes(lq, checkpoint):
+    """The autograd wrapper in each mode (0: keep S and Gamma; k: stride-k
+    checkpoint; "recompute": keep nothing) gives the oracle's gradients, and
+    what it keeps between forward and backward shrinks accordingly."""
+    inst = W.lq_instance_general(np.random.default_rng(92), 12, 4, 2000)
+    prob = lq.to_device(W.pack([inst]))
+    plan = lq.Plan([12], [4], [2000], seg_len=8)
+    names = lq.LQSolveFunction.NAMES
+    leaves = {f: prob[f].clone().requires_grad_(True) for f in names}
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    x, u, _ = lq.solve_diff(plan, *[leaves[f] for f in names], checkpoint=checkpoint)
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - base
+    L = (x * x).sum() + (u * u).sum()
+    grads = torch.autograd.grad(L, [leaves[f] for f in names])
+    ref = oracle_grads(inst)
+    for f, g in zip(names, grads):
+        assert rel(g.detach().cpu().numpy().reshape(ref[f].shape), ref[f]) < 1e-10, f
+    T, n, m = 2000, 12, 4
+    value_bytes = 8 * ((T + 1) * n * n + (T + 1) * n + T * m * n + T * m)
+    if checkpoint == 0:
+        assert held >= value_bytes
+    else:
+        assert held < value_bytes / 2, (held, value_bytes)
+    print(f"checkpoint={checkpoint}: {held / 2**20:.2f} MiB held after forward "
+          f"(value arrays {value_bytes / 2**20:.2f} MiB)")
