@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "liblqscan.so")
-SOURCES = ["lq_value.hip", "lq_rollout.hip", "lq_adjoint.hip", "lq_newton.hip", "lq_abi.hip"]
+SOURCES = ["lq_value.hip", "lq_rollout.hip", "lq_adjoint.hip", "lq_newton.hip", "lq_small.hip", "lq_abi.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

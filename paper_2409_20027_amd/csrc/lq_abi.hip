@@ -79,6 +79,15 @@ struct lq_plan {
     int aff_radix = 4;   // radix of the affine-map scan levels
     // workspace layout (bytes)
     size_t off_Xa = 0, off_Xb = 0, off_Ya = 0, off_Yb = 0, off_st = 0, off_gt = 0, ws_bytes = 0, el_bytes = 0;
+    // per-lane path: every instance has n = sn <= SMALL_NMAX and m = sm
+    bool small = false;
+    int sn = 0, sm = 0;
+    // a plan over several size classes delegates to one sub-plan per class
+    // (descriptors with this plan's array offsets and instance indices); each
+    // sub-plan's scan buffers start at sub_off[c] in the workspace
+    std::vector<lq_plan *> subs;
+    std::vector<size_t> sub_off;
+    const lq_plan *owner = nullptr;   // plan holding the timing events (subs: the parent)
     // diagnostic phase timing (events created by lq_plan_set_timing)
     mutable uint32_t tmask = 0;
     mutable std::vector<hipEvent_t> ev;
@@ -88,8 +97,9 @@ struct lq_plan {
 
 // Records events around one phase if its bit is enabled; `fn` enqueues it.
 template <class F>
-static void timed(const lq_plan *p, int phase, hipStream_t st, F fn)
+static void timed(const lq_plan *q, int phase, hipStream_t st, F fn)
 {
+    const lq_plan *p = q->owner ? q->owner : q;
     const bool on = (p->tmask >> phase) & 1u;
     size_t slot = p->ev_used;
     if (on && 2 * (slot + 1) <= p->ev.size()) {
@@ -138,20 +148,33 @@ static int choose_affine_radix(int64_t entries, int device)
 static double *affine_scan(const lq_plan *p, hipStream_t st, int suffix, double *in, double *o)
 {
     for (int64_t dd = 1; dd < p->max_nseg; dd *= p->aff_radix) {
-        lqk::launch_affine_ks(p->nk, p->prec, p->aff_radix, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch,
-                              (int)dd, suffix, in, o);
+        if (p->small)
+            lqk::launch_small_affine_ks(p->sn, p->aff_radix, p->total_x, st, p->d_inst, p->d_x_start, p->batch, (int)dd,
+                                        suffix, in, o);
+        else
+            lqk::launch_affine_ks(p->nk, p->prec, p->aff_radix, (unsigned)p->total_x, st, p->d_inst, p->d_x_start,
+                                  p->batch, (int)dd, suffix, in, o);
         std::swap(in, o);
     }
     return in;
+}
+
+// Largest state dimension served by the per-lane kernels (lq_small.hip).
+// LQSCAN_SMALL=0 sends every instance through the matrix-core tile kernels.
+constexpr int SMALL_NMAX = 4;
+static bool small_path_enabled()
+{
+    const char *e = getenv("LQSCAN_SMALL");
+    return !(e && e[0] == '0' && e[1] == 0);
 }
 
 extern "C" {
 
 const char *lq_version(void) { return "lqscan 0.1 (gfx950, fp64 tiles)"; }
 
-static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
-                             int32_t precision, int32_t mode, int32_t seg_len, const int32_t *seg_lens,
-                             lq_plan **out)
+static lq_status plan_build(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                            int32_t precision, int32_t mode, int32_t seg_len, const int32_t *seg_lens,
+                            lq_plan **out)
 {
     if (!out || batch <= 0 || !nx || !nu || !T) return LQ_ERR_ARG;
     if (precision != LQ_FP64 && precision != LQ_MIXED) return LQ_ERR_ARG;
@@ -194,7 +217,7 @@ static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu
         d.nseg = (int)((t + d.L - 1) / d.L);
         d.seg0 = (int)seg;
         d.xbase = (int)(seg + i);
-        d.pad = 0;
+        d.orig = i;
         d.elem0 = el;
         d.oA = oA; d.oB = oB; d.oR = oR; d.oc = oc; d.oQT = oQT; d.on = on;
         d.oS = oS; d.os = os; d.oG = oG; d.og = og;
@@ -259,6 +282,94 @@ static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu
     return LQ_OK;
 }
 
+// A plan over the given instances; when they fall into several size classes
+// (each (n, m) with n <= SMALL_NMAX served by the per-lane kernels, every
+// larger n by the tile kernels) it delegates to one sub-plan per class, whose
+// descriptors keep this plan's array offsets and instance indices, so the
+// packed arrays, outputs and status words are shared.  Workspace of such a
+// plan: each sub-plan's scan buffers in turn, then the adjoint's s~ and
+// gamma~ vectors in this plan's packing.
+static lq_status plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                             int32_t precision, int32_t mode, int32_t seg_len, const int32_t *seg_lens,
+                             lq_plan **out)
+{
+    lq_plan *p = nullptr;
+    lq_status st = plan_build(batch, nx, nu, T, precision, mode, seg_len, seg_lens, &p);
+    if (st != LQ_OK) return st;
+    const bool sm = small_path_enabled();
+    auto key = [&](int i) { return (sm && nx[i] <= SMALL_NMAX) ? nx[i] * 8 + nu[i] : 0; };
+    std::vector<int> keys;
+    for (int i = 0; i < batch; ++i)
+        if (std::find(keys.begin(), keys.end(), key(i)) == keys.end()) keys.push_back(key(i));
+    if (keys.size() == 1) {
+        if (keys[0]) {
+            p->small = true;
+            p->sn = nx[0];
+            p->sm = nu[0];
+        }
+        *out = p;
+        return LQ_OK;
+    }
+    size_t off = 0;
+    for (int kc : keys) {
+        std::vector<int32_t> idx, cn, cm, cT, cL;
+        for (int i = 0; i < batch; ++i)
+            if (key(i) == kc) {
+                idx.push_back(i);
+                cn.push_back(nx[i]);
+                cm.push_back(nu[i]);
+                cT.push_back(T[i]);
+                cL.push_back(seg_lens ? seg_lens[i] : 0);
+            }
+        lq_plan *q = nullptr;
+        st = plan_build((int32_t)idx.size(), cn.data(), cm.data(), cT.data(), precision, mode, seg_len,
+                        seg_lens ? cL.data() : nullptr, &q);
+        if (st != LQ_OK) {
+            lq_plan_destroy(p);
+            return st;
+        }
+        p->subs.push_back(q);
+        q->owner = p;
+        if (kc) {
+            q->small = true;
+            q->sn = cn[0];
+            q->sm = cm[0];
+        }
+        for (size_t j = 0; j < idx.size(); ++j) {
+            InstDesc &dq = q->h_inst[j];
+            const InstDesc &dp = p->h_inst[idx[j]];
+            dq.orig = dp.orig;
+            dq.elem0 = dp.elem0;
+            dq.oA = dp.oA; dq.oB = dp.oB; dq.oR = dp.oR; dq.oc = dp.oc; dq.oQT = dp.oQT; dq.on = dp.on;
+            dq.oS = dp.oS; dq.os = dp.os; dq.oG = dp.oG; dq.og = dp.og;
+        }
+        if (hipMemcpy(q->d_inst, q->h_inst.data(), sizeof(InstDesc) * q->h_inst.size(), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+            lq_plan_destroy(p);
+            return LQ_ERR_HIP;
+        }
+        p->sub_off.push_back(off);
+        off = align_up(off + q->off_st);
+    }
+    int64_t ns = 0, ng = 0;
+    for (const InstDesc &d : p->h_inst) {
+        ns += (int64_t)(d.T + 1) * d.n;
+        ng += (int64_t)d.T * d.m;
+    }
+    p->off_Xa = p->off_Xb = p->off_Ya = p->off_Yb = 0;   // unused: the sub-plans hold the scan buffers
+    p->off_st = off; off = align_up(off + (size_t)ns * sizeof(double));
+    p->off_gt = off; off = align_up(off + (size_t)ng * sizeof(double));
+    p->ws_bytes = off;
+    *out = p;
+    return LQ_OK;
+}
+
+// The plans that run a call's work: a mixed plan's size-class sub-plans, or
+// the plan itself; class c's scan buffers start at class_ws(p, c).
+static int nclass(const lq_plan *p) { return p->subs.empty() ? 1 : (int)p->subs.size(); }
+static const lq_plan *class_plan(const lq_plan *p, int c) { return p->subs.empty() ? p : p->subs[c]; }
+static size_t class_ws(const lq_plan *p, int c) { return p->subs.empty() ? 0 : p->sub_off[c]; }
+
 lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
                          int32_t precision, int32_t mode, int32_t seg_len, lq_plan **out)
 {
@@ -275,6 +386,7 @@ lq_status lq_plan_create_seg(int32_t batch, const int32_t *nx, const int32_t *nu
 void lq_plan_destroy(lq_plan *p)
 {
     if (!p) return;
+    for (lq_plan *q : p->subs) lq_plan_destroy(q);
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
     if (p->d_inst) (void)hipFree(p->d_inst);
     if (p->d_seg_start) (void)hipFree(p->d_seg_start);
@@ -324,23 +436,49 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
 {
     double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
     timed(p, LQ_PH_VALUE_FOLD, st, [&] {
-        lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, elements,
-                               Xa, 0, status);
+        if (p->small && !elements)
+            lqk::launch_small_value_fold(p->sn, p->sm, p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, Xa,
+                                         status);
+        else
+            lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch,
+                                   elements, Xa, 0, status);
     });
     double *in = Xa, *o = Xb;
     // entries 1 .. nseg-1 of each instance (the last holds the terminal)
     if (p->max_nseg > 2)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
             for (int dd = 1; dd < p->max_nseg - 1; dd *= 2) {
-                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 0, in,
-                                     o, status);
+                if (p->small)
+                    lqk::launch_small_value_ks(p->sn, p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,
+                                               status);
+                else
+                    lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch,
+                                         dd, 0, in, o, status);
                 std::swap(in, o);
             }
         });
     double *fin = in;
     timed(p, LQ_PH_VALUE_BELLMAN, st, [&] {
-        lqk::launch_value_riccati(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, fin,
-                                  V, Yroll, ckpt, stride, status);
+        if (p->small)
+            lqk::launch_small_value_riccati(p->sn, p->sm, p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch,
+                                            fin, V, Yroll, ckpt, stride, status);
+        else
+            lqk::launch_value_riccati(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start,
+                                      p->batch, fin, V, Yroll, ckpt, stride, status);
+    });
+}
+
+// States, controls and co-states from the scanned segment-start states.
+static void roll_apply(const lq_plan *p, const lqk::ProbPtrs &P, const lqk::ValPtrs &V, const double *fin, double *x,
+                       double *u, double *lambda, hipStream_t st)
+{
+    timed(p, LQ_PH_ROLL_APPLY, st, [&] {
+        if (p->small)
+            lqk::launch_small_roll_apply(p->sn, p->sm, p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch,
+                                         fin, x, u, lambda);
+        else
+            lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start,
+                                   p->batch, fin, x, u, lambda);
     });
 }
 
@@ -350,10 +488,7 @@ static void rollout_scan_apply(const lq_plan *p, const lqk::ProbPtrs &P, const l
 {
     double *fin = Ya;
     if (p->max_nseg > 1) timed(p, LQ_PH_ROLL_SCAN, st, [&] { fin = affine_scan(p, st, 0, Ya, Yb); });
-    timed(p, LQ_PH_ROLL_APPLY, st, [&] {
-        lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, fin, x,
-                               u, lambda);
-    });
+    roll_apply(p, P, V, fin, x, u, lambda, st);
 }
 
 static bool value_ok(const lq_value *v) { return v && v->S && v->s && v->Gamma && v->gamma; }
@@ -365,7 +500,9 @@ lq_status lq_scan_solve(const lq_plan *p, const lq_problem *prob, const double *
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
     if (elements && !aligned(elements)) return LQ_ERR_WORKSPACE;
     lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
-    value_pass(p, probptrs(prob), elements, V, (char *)workspace, nullptr, status, (hipStream_t)stream);
+    for (int c = 0; c < nclass(p); ++c)
+        value_pass(class_plan(p, c), probptrs(prob), elements, V, (char *)workspace + class_ws(p, c), nullptr, status,
+                   (hipStream_t)stream);
     return launched();
 }
 
@@ -376,14 +513,18 @@ lq_status lq_rollout(const lq_plan *p, const lq_problem *prob, const lq_value *v
     if (!p || !prob_ok(prob) || !value_ok(val) || !x || !u) return LQ_ERR_ARG;
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
-    timed(p, LQ_PH_ROLL_FOLD, st, [&] {
-        lqk::launch_roll_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya);
-    });
-    rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
+    for (int c = 0; c < nclass(p); ++c) {
+        const lq_plan *q = class_plan(p, c);
+        char *ws = (char *)workspace + class_ws(p, c);
+        double *Ya = (double *)(ws + q->off_Ya), *Yb = (double *)(ws + q->off_Yb);
+        timed(q, LQ_PH_ROLL_FOLD, st, [&] {
+            lqk::launch_roll_fold(q->nk, q->prec, (unsigned)q->total_seg, st, P, V, q->d_inst, q->d_seg_start, q->batch,
+                                  Ya);
+        });
+        rollout_scan_apply(q, P, V, Ya, Yb, x, u, lambda, st);
+    }
     return launched();
 }
 
@@ -396,49 +537,42 @@ lq_status lq_rollout_cv(const lq_plan *p, const lq_problem *prob, const lq_value
     if (!p || !prob_ok(prob) || !value_ok(val) || !x || !u) return LQ_ERR_ARG;
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
-    char *ws = (char *)workspace;
-    double *Xa = (double *)(ws + p->off_Xa), *Xb = (double *)(ws + p->off_Xb);
-    double *Ya = (double *)(ws + p->off_Ya);
     const lqk::ProbPtrs P = probptrs(prob);
     lqk::ValPtrs V{val->S, val->s, val->Gamma, val->gamma};
-    timed(p, LQ_PH_CV_FOLD, st, [&] {
-        lqk::launch_value_fold(p->nk, p->prec, (unsigned)p->total_seg, st, P, p->d_inst, p->d_seg_start, p->batch, nullptr,
-                               Xa, 1, status);
-    });
-    double *in = Xa, *o = Xb;
-    if (p->max_nseg > 1)
-        timed(p, LQ_PH_CV_SCAN, st, [&] {
-            for (int dd = 1; dd < p->max_nseg; dd *= 2) {
-                lqk::launch_value_ks(p->nk, p->prec, (unsigned)p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, 1, in,
-                                     o, status);
-                std::swap(in, o);
-            }
+    for (int c = 0; c < nclass(p); ++c) {
+        const lq_plan *q = class_plan(p, c);
+        char *ws = (char *)workspace + class_ws(p, c);
+        double *Xa = (double *)(ws + q->off_Xa), *Xb = (double *)(ws + q->off_Xb);
+        double *Ya = (double *)(ws + q->off_Ya);
+        timed(q, LQ_PH_CV_FOLD, st, [&] {
+            lqk::launch_value_fold(q->nk, q->prec, (unsigned)q->total_seg, st, P, q->d_inst, q->d_seg_start, q->batch,
+                                   nullptr, Xa, 1, status);
         });
-    timed(p, LQ_PH_CV_START, st, [&] {
-        lqk::launch_cv_start(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, in, Ya,
-                             status);
-    });
-    timed(p, LQ_PH_ROLL_APPLY, st, [&] {
-        lqk::launch_roll_apply(p->nk, p->prec, (unsigned)p->total_seg, st, P, V, p->d_inst, p->d_seg_start, p->batch, Ya, x,
-                               u, lambda);
-    });
+        double *in = Xa, *o = Xb;
+        if (q->max_nseg > 1)
+            timed(q, LQ_PH_CV_SCAN, st, [&] {
+                for (int dd = 1; dd < q->max_nseg; dd *= 2) {
+                    lqk::launch_value_ks(q->nk, q->prec, (unsigned)q->total_x, st, q->d_inst, q->d_x_start, q->batch,
+                                         dd, 1, in, o, status);
+                    std::swap(in, o);
+                }
+            });
+        timed(q, LQ_PH_CV_START, st, [&] {
+            lqk::launch_cv_start(q->nk, q->prec, (unsigned)q->total_seg, st, P, V, q->d_inst, q->d_seg_start, q->batch,
+                                 in, Ya, status);
+        });
+        roll_apply(q, P, V, Ya, x, u, lambda, st);
+    }
     return launched();
 }
 
-// Value pass and rollout with the scan buffers at ws (only the plan's scan
-// regions [0, off_st) are used); with ckpt the Bellman sweep also writes the
-// checkpoint of the differentiated solve.
+// Value pass and rollout of every size class, class c's scan buffers at
+// ws + class_ws(p, c) (only each class plan's scan regions [0, off_st) are
+// used); with ckpt the Bellman sweep also writes the checkpoint of the
+// differentiated solve (class c's slots after those of the classes before it).
 static lq_status solve_with(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
-                            double *x, double *u, double *lambda, char *ws, int32_t *status, hipStream_t st,
-                            double *ckpt = nullptr, int stride = 1)
-{
-    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
-    const lqk::ProbPtrs P = probptrs(prob);
-    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
-    value_pass(p, P, elements, V, ws, Ya, status, st, ckpt, stride);
-    rollout_scan_apply(p, P, V, Ya, Yb, x, u, lambda, st);
-    return launched();
-}
+                            double *x, double *u, double *lambda, char *ws0, int32_t *status, hipStream_t st,
+                            double *ckpt = nullptr, int stride = 1);
 
 lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out, double *x,
                    double *u, double *lambda, void *workspace, int32_t *status, void *stream)
@@ -451,13 +585,37 @@ lq_status lq_solve(const lq_plan *p, const lq_problem *prob, const double *eleme
 
 size_t lq_plan_static_bytes(const lq_plan *p) { return p ? p->off_st : 0; }
 
-// Checkpoint slots for a stride: total_seg / stride + batch tiles (ckpt_slot).
-static int64_t ckpt_slots(const lq_plan *p, int stride) { return p->total_seg / stride + p->batch; }
+// Checkpoint slots of one class plan for a stride: total_seg / stride + batch
+// tiles (ckpt_slot); a mixed plan keeps its classes' slots one after another.
+static int64_t ckpt_slots(const lq_plan *q, int stride) { return q->total_seg / stride + q->batch; }
+static size_t class_ckpt_bytes(const lq_plan *q, int stride)
+{
+    return align_up((size_t)ckpt_slots(q, stride) * TILE * sizeof(double));
+}
 
 size_t lq_plan_checkpoint_bytes(const lq_plan *p, int32_t stride)
 {
     if (!p || stride < 1) return 0;
-    return align_up((size_t)ckpt_slots(p, stride) * TILE * sizeof(double));
+    size_t b = 0;
+    for (int c = 0; c < nclass(p); ++c) b += class_ckpt_bytes(class_plan(p, c), stride);
+    return b;
+}
+
+static lq_status solve_with(const lq_plan *p, const lq_problem *prob, const double *elements, const lq_value *out,
+                            double *x, double *u, double *lambda, char *ws0, int32_t *status, hipStream_t st,
+                            double *ckpt, int stride)
+{
+    const lqk::ProbPtrs P = probptrs(prob);
+    lqk::ValPtrs V{out->S, out->s, out->Gamma, out->gamma};
+    for (int c = 0; c < nclass(p); ++c) {
+        const lq_plan *q = class_plan(p, c);
+        char *ws = ws0 + class_ws(p, c);
+        double *Ya = (double *)(ws + q->off_Ya), *Yb = (double *)(ws + q->off_Yb);
+        value_pass(q, P, elements, V, ws, Ya, status, st, ckpt, stride);
+        rollout_scan_apply(q, P, V, Ya, Yb, x, u, lambda, st);
+        if (ckpt) ckpt += class_ckpt_bytes(q, stride) / sizeof(double);
+    }
+    return launched();
 }
 
 // The checkpointed adjoint's workspace: the plan's workspace, then room for
@@ -509,35 +667,47 @@ lq_status lq_solve_static(const lq_plan *p, const lq_problem *prob, const double
     return solve_with(p, prob, elements, out, x, u, lambda, (char *)ws, status, (hipStream_t)stream);
 }
 
-// The adjoint's scans and sweeps from the value functions and gains in val.
+// The adjoint's scans and sweeps of one class plan q from the value functions
+// and gains in val; its scan buffers at ws, the s~ and gamma~ vectors (in the
+// caller's packing) at st_v and gt_v.
+static void adjoint_class(const lq_plan *q, const lqk::ProbPtrs &P, const lqk::ValPtrs &val, const double *x,
+                          const double *u, const double *lambda, const double *gx, const double *gu,
+                          const lqk::GradPtrs &G, char *ws, double *st_v, double *gt_v, int32_t *status,
+                          hipStream_t st)
+{
+    double *Ya = (double *)(ws + q->off_Ya), *Yb = (double *)(ws + q->off_Yb);
+    lqk::AdjPtrs J{val.S, val.s, val.G, val.g, x, u, lambda, gx, gu, st_v, gt_v};
+    const unsigned nseg = (unsigned)q->total_seg;
+    // backward linear-term scan
+    timed(q, LQ_PH_ADJ_BACK_FOLD, st, [&] {
+        lqk::launch_adj_back_fold(q->nk, q->prec, nseg, st, P, J, q->d_inst, q->d_seg_start, q->batch, Ya);
+    });
+    double *fin = Ya;
+    if (q->max_nseg > 1) timed(q, LQ_PH_ADJ_BACK_SCAN, st, [&] { fin = affine_scan(q, st, 1, Ya, Yb); });
+    // the backward sweep also writes the forward scan's entries (its segment fold fused in)
+    double *fwd = (fin == Ya) ? Yb : Ya, *fwd2 = fin;
+    timed(q, LQ_PH_ADJ_BACK_APPLY, st, [&] {
+        lqk::launch_adj_back_apply(q->nk, q->prec, nseg, st, P, J, q->d_inst, q->d_seg_start, q->batch, fin, fwd,
+                                   status);
+    });
+    // forward derivative scan + gradients
+    double *ffin = fwd;
+    if (q->max_nseg > 1) timed(q, LQ_PH_ADJ_FWD_SCAN, st, [&] { ffin = affine_scan(q, st, 0, fwd, fwd2); });
+    timed(q, LQ_PH_ADJ_FWD_APPLY, st, [&] {
+        lqk::launch_adj_fwd_apply(q->nk, q->prec, nseg, st, P, J, G, q->d_inst, q->d_seg_start, q->batch, ffin);
+    });
+}
+
 static lq_status adjoint_with(const lq_plan *p, const lq_problem *prob, const lqk::ValPtrs &val, const double *x,
                               const double *u, const double *lambda, const double *gx, const double *gu,
                               const lq_grads *grads, char *ws, int32_t *status, hipStream_t st)
 {
-    double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     const lqk::ProbPtrs P = probptrs(prob);
-    lqk::AdjPtrs J{val.S, val.s, val.G, val.g, x, u, lambda, gx, gu,
-                   (double *)(ws + p->off_st), (double *)(ws + p->off_gt)};
     lqk::GradPtrs G{grads->A, grads->B, grads->c, grads->Q, grads->R, grads->M,
                     grads->q, grads->r, grads->QT, grads->qT, grads->x0};
-    const unsigned nseg = (unsigned)p->total_seg;
-    // backward linear-term scan
-    timed(p, LQ_PH_ADJ_BACK_FOLD, st, [&] {
-        lqk::launch_adj_back_fold(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, Ya);
-    });
-    double *fin = Ya;
-    if (p->max_nseg > 1) timed(p, LQ_PH_ADJ_BACK_SCAN, st, [&] { fin = affine_scan(p, st, 1, Ya, Yb); });
-    // the backward sweep also writes the forward scan's entries (its segment fold fused in)
-    double *fwd = (fin == Ya) ? Yb : Ya, *fwd2 = fin;
-    timed(p, LQ_PH_ADJ_BACK_APPLY, st, [&] {
-        lqk::launch_adj_back_apply(p->nk, p->prec, nseg, st, P, J, p->d_inst, p->d_seg_start, p->batch, fin, fwd, status);
-    });
-    // forward derivative scan + gradients
-    double *ffin = fwd;
-    if (p->max_nseg > 1) timed(p, LQ_PH_ADJ_FWD_SCAN, st, [&] { ffin = affine_scan(p, st, 0, fwd, fwd2); });
-    timed(p, LQ_PH_ADJ_FWD_APPLY, st, [&] {
-        lqk::launch_adj_fwd_apply(p->nk, p->prec, nseg, st, P, J, G, p->d_inst, p->d_seg_start, p->batch, ffin);
-    });
+    double *st_v = (double *)(ws + p->off_st), *gt_v = (double *)(ws + p->off_gt);
+    for (int c = 0; c < nclass(p); ++c)
+        adjoint_class(class_plan(p, c), P, val, x, u, lambda, gx, gu, G, ws + class_ws(p, c), st_v, gt_v, status, st);
     return launched();
 }
 
@@ -565,13 +735,19 @@ lq_status lq_adjoint_ckpt(const lq_plan *p, const lq_problem *prob, const double
     const RecomputeLayout L = recompute_layout(p);
     const lqk::ValPtrs V{(double *)(ws + L.S), (double *)(ws + L.s), (double *)(ws + L.G), (double *)(ws + L.g)};
     const lqk::ProbPtrs P = probptrs(prob);
-    if (ckpt)
-        timed(p, LQ_PH_ADJ_RECOMPUTE, st, [&] {
-            lqk::launch_value_recompute(p->nk, p->prec, (unsigned)ckpt_slots(p, stride), st, P, p->d_inst,
-                                        p->d_seg_start, p->batch, stride, ckpt, V, status);
-        });
-    else
-        value_pass(p, P, nullptr, V, ws, nullptr, status, st);
+    const double *ck = ckpt;
+    for (int c = 0; c < nclass(p); ++c) {
+        const lq_plan *q = class_plan(p, c);
+        if (ck) {
+            timed(q, LQ_PH_ADJ_RECOMPUTE, st, [&] {
+                lqk::launch_value_recompute(q->nk, q->prec, (unsigned)ckpt_slots(q, stride), st, P, q->d_inst,
+                                            q->d_seg_start, q->batch, stride, ck, V, status);
+            });
+            ck += class_ckpt_bytes(q, stride) / sizeof(double);
+        } else {
+            value_pass(q, P, nullptr, V, ws + class_ws(p, c), nullptr, status, st);
+        }
+    }
     return adjoint_with(p, prob, V, x, u, lambda, gx, gu, grads, ws, status, st);
 }
 

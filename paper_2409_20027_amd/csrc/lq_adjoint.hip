@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     }
     if (s == 0) gstore_c(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n), d.n + 1);   // dx_0 = 0
     if (s < d.nseg - 1) gstore_c(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
-    if (code) report(status, i, code, fk);
+    if (code) report(status, d.orig, code, fk);
 }
 
 template <int NK, int PR>

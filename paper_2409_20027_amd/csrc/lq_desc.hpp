@@ -15,7 +15,7 @@ struct InstDesc {
     int32_t L;          // stages per segment (last one may be shorter)
     int32_t seg0;       // first global segment index
     int32_t xbase;      // first index in the scan buffers (seg0 + instance index)
-    int32_t pad;
+    int32_t orig;       // index of the instance in the caller's batch (its status word)
     int64_t elem0;      // first element index (T + 1 elements per instance)
     int64_t oA, oB, oR, oc, oQT, on;   // offsets: A/Q (T n n), B/M (T n m), R (T m m),
                                        // c/q (T n), QT (n n), qT/x0 (n)

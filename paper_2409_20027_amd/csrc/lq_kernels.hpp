@@ -39,6 +39,20 @@ void launch_adj_back_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPt
 void launch_adj_fwd_apply(int nk, int pr, unsigned grid, hipStream_t st, ProbPtrs P, AdjPtrs J, GradPtrs Gr,
                           const InstDesc *inst, const int32_t *seg_start, int batch, const double *Yfin);
 
+// Per-lane path for n <= 4 (lq_small.hip): one lane per segment or scan entry.
+void launch_small_value_fold(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                             const int32_t *seg_start, int batch, double *X, int32_t *status);
+void launch_small_value_ks(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+                           int batch, int dd, const double *Xin, double *Xout, int32_t *status);
+void launch_small_value_riccati(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                                const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
+                                double *ckpt, int stride, int32_t *status);
+void launch_small_affine_ks(int n, int radix, int64_t total, hipStream_t st, const InstDesc *inst,
+                            const int32_t *x_start, int batch, int dd, int suffix, const double *Yin, double *Yout);
+void launch_small_roll_apply(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                             const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u,
+                             double *lam);
+
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u);
 void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk);
 void launch_nmpc_shift(hipStream_t st, NmpcPtrs N, double *x0, double *u, double *uapp);

@@ -1,0 +1,1135 @@
+// lq_small.hip -- the LQ solve for small state dimensions (n <= 4) on gfx950:
+// one lane per segment (the sweeps) or per scan entry (the scan levels), every
+// matrix of an element in registers, sizes N = n and M = m fixed at compile
+// time.
+//
+// At n <= 4 a value element (A, b, C, eta, J) of eq:value-fun-elements is at
+// most 4 x 4, and the 16 x 16 matrix-core tiles of the general path would be
+// mostly padding, with one wave's dependent instruction chain per stage.  Here a
+// wave carries 64 segments (or scan entries) side by side, each lane running the
+// same recursions in plain FP64 vector arithmetic:
+//   k_small_value_fold     fold of a segment right to left (fused element build
+//                          of eq:value-fun-elem-init, rank-m Woodbury form of
+//                          eq:value-fun-param with the stage element on the left)
+//   k_small_value_ks       one Kogge-Stone level of the suffix scan (the general
+//                          operator eq:value-fun-param, n x n Gauss-Jordan)
+//   k_small_value_riccati  Bellman steps from the segment's carry with the
+//                          control law of eq:value-fun-feedback, and the
+//                          composition of the segment's closed-loop maps (the
+//                          elements of Alg. 3)
+//   k_small_affine_ks      one level of an affine-map scan (eq:state-prop-comb-rule)
+//   k_small_roll_apply     states, controls and co-states inside a segment
+// Scan entries are stored in the general path's layout (an (n+1) x (n+1)
+// homogeneous block, row-major, at the start of a 256-double slot: A~ =
+// [[A, b], [0, 1]], C~ = [[C, 0], [0, 0]], J~ = [[J, -eta], [-eta', c0]], affine
+// maps [[F, e], [0, 1]]), so kernels of either path can follow one another on
+// the same buffers.  The constant c0 of J~ never feeds S or s and is stored as 0.
+// Every lane reports its own instance's failures (status word as in the general
+// path: the failure at the largest stage is kept).
+#include <math.h>
+
+#include "lq_kernels.hpp"
+
+namespace lqk {
+namespace {
+
+constexpr int SERR_NOT_PD = -2;
+constexpr int SERR_SINGULAR = -3;
+constexpr int SERR_NONFINITE = -4;
+
+LQK_DEV void note1(bool ok, int err, int k, int &code, int &fk)
+{
+    const bool first = !ok && code == 0;
+    code = first ? err : code;
+    fk = first ? k : fk;
+}
+
+LQK_DEV void report1(int32_t *status, int inst, int code, int k)
+{
+    if (status) atomicMax(&status[inst], (int32_t)((-code) | (k << 8)));
+}
+
+LQK_DEV int gid() { return (int)blockIdx.x * 64 + (int)threadIdx.x; }
+
+// ---- loads and stores of row-major blocks (nullable sources read as 0) ----
+
+template <int R, int C>
+LQK_DEV void ldm(const double *p, double (&X)[R][C])
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j) X[i][j] = p ? p[i * C + j] : 0.0;
+}
+template <int R>
+LQK_DEV void ldv(const double *p, double (&x)[R])
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i) x[i] = p ? p[i] : 0.0;
+}
+template <int R, int C>
+LQK_DEV void stm(double *p, const double (&X)[R][C])
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < C; ++j) p[i * C + j] = X[i][j];
+}
+template <int R>
+LQK_DEV void stv(double *p, const double (&x)[R])
+{
+#pragma unroll
+    for (int i = 0; i < R; ++i) p[i] = x[i];
+}
+
+// ---- homogeneous entries (compact (N+1) x (N+1) blocks) ----
+
+// A~ = [[A, b], [0, 1]]
+template <int N>
+LQK_DEV void load_map(const double *p, double (&F)[N][N], double (&e)[N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) F[i][j] = p[i * N1 + j];
+        e[i] = p[i * N1 + N];
+    }
+}
+template <int N>
+LQK_DEV void store_map(double *p, const double (&F)[N][N], const double (&e)[N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) p[i * N1 + j] = F[i][j];
+        p[i * N1 + N] = e[i];
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) p[N * N1 + j] = 0.0;
+    p[N * N1 + N] = 1.0;
+}
+// C~ = [[C, 0], [0, 0]]
+template <int N>
+LQK_DEV void load_c(const double *p, double (&C)[N][N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) C[i][j] = p[i * N1 + j];
+}
+template <int N>
+LQK_DEV void store_c(double *p, const double (&C)[N][N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N1; ++i)
+#pragma unroll
+        for (int j = 0; j < N1; ++j) p[i * N1 + j] = (i < N && j < N) ? C[i][j] : 0.0;
+}
+// J~ = [[J, v], [v', 0]] with v = -eta (value functions: S~ = [[S, s], [s', 0]])
+template <int N>
+LQK_DEV void load_jv(const double *p, double (&J)[N][N], double (&v)[N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) J[i][j] = p[i * N1 + j];
+        v[i] = p[i * N1 + N];
+    }
+}
+template <int N>
+LQK_DEV void store_jv(double *p, const double (&J)[N][N], const double (&v)[N])
+{
+    constexpr int N1 = N + 1;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) p[i * N1 + j] = J[i][j];
+        p[i * N1 + N] = v[i];
+        p[N * N1 + i] = v[i];
+    }
+    p[N * N1 + N] = 0.0;
+}
+
+template <int N>
+LQK_DEV void sym(double (&S)[N][N])
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) {
+            const double a = 0.5 * (S[i][j] + S[j][i]);
+            S[i][j] = a;
+            S[j][i] = a;
+        }
+}
+
+// ---- small inverses ----
+
+// Inverse of an R x R matrix by Gauss-Jordan elimination on [X | I] with
+// partial pivoting (rows exchanged by selects); false for a zero or
+// non-finite pivot.
+template <int R>
+LQK_DEV bool inv_gj(const double (&X)[R][R], double (&Y)[R][R])
+{
+    double a[R][2 * R];
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            a[i][j] = X[i][j];
+            a[i][R + j] = (i == j) ? 1.0 : 0.0;
+        }
+    bool ok = true;
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+#pragma unroll
+        for (int i = p + 1; i < R; ++i) {
+            const bool sw = fabs(a[i][p]) > fabs(a[p][p]);
+#pragma unroll
+            for (int j = p; j < 2 * R; ++j) {
+                const double t = a[p][j];
+                a[p][j] = sw ? a[i][j] : t;
+                a[i][j] = sw ? t : a[i][j];
+            }
+        }
+        const double piv = a[p][p];
+        ok = ok && (piv != 0.0) && isfinite(piv);
+        const double r = 1.0 / piv;
+#pragma unroll
+        for (int j = p; j < 2 * R; ++j) a[p][j] *= r;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i == p) continue;
+            const double f = a[i][p];
+#pragma unroll
+            for (int j = p; j < 2 * R; ++j) a[i][j] -= f * a[p][j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) Y[i][j] = a[i][R + j];
+    return ok;
+}
+
+// Inverse of a symmetric R x R matrix through its Cholesky factor X = L L';
+// false unless X is positive definite (a non-positive or NaN pivot).  A
+// non-positive pivot is replaced by 1 so that the result stays finite; a NaN
+// one is kept, so that a NaN in X reaches the inverse (and the value function
+// downstream, where it is reported as non-finite at its stage).
+template <int R>
+LQK_DEV bool inv_spd(const double (&X)[R][R], double (&Y)[R][R])
+{
+    double L[R][R], id[R];
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        double sj = X[j][j];
+#pragma unroll
+        for (int k = 0; k < j; ++k) sj -= L[j][k] * L[j][k];
+        ok = ok && (sj > 0.0);
+        const double dj = sqrt((sj > 0.0 || isnan(sj)) ? sj : 1.0);
+        id[j] = 1.0 / dj;
+        L[j][j] = dj;
+#pragma unroll
+        for (int i = j + 1; i < R; ++i) {
+            double t = X[i][j];
+#pragma unroll
+            for (int k = 0; k < j; ++k) t -= L[i][k] * L[j][k];
+            L[i][j] = t * id[j];
+        }
+    }
+    // W = L^{-1} (lower triangular), then Y = W'W
+    double W[R][R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            if (i < j) {
+                W[i][j] = 0.0;
+                continue;
+            }
+            double t = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = j; k < i; ++k) t -= L[i][k] * W[k][j];
+            W[i][j] = t * id[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k) t += W[k][i] * W[k][j];
+            Y[i][j] = t;
+        }
+    return ok;
+}
+
+// ---- stage data ----
+
+template <int N, int M>
+struct Stage {
+    double A[N][N], B[N][M], c[N], Q[N][N], R[M][M], q[N];
+};
+
+template <int N, int M>
+LQK_DEV void load_stage(const ProbPtrs &P, const InstDesc &d, int k, Stage<N, M> &w)
+{
+    ldm(P.A + d.oA + (int64_t)k * N * N, w.A);
+    ldm(P.B + d.oB + (int64_t)k * N * M, w.B);
+    ldv(P.c ? P.c + d.oc + (int64_t)k * N : nullptr, w.c);
+    ldm(P.Q + d.oA + (int64_t)k * N * N, w.Q);
+    ldm(P.R + d.oR + (int64_t)k * M * M, w.R);
+    ldv(P.q ? P.q + d.oc + (int64_t)k * N : nullptr, w.q);
+}
+
+// The stage element of eq:value-fun-elem-init in place, for cross terms M, r:
+// A - B K_M, c - B K_r, Q - M K_M, q - M K_r with [K_M, K_r] = R^{-1}[M', r]
+// (C = B R^{-1} B' stays implicit: the fold uses B and R).  False if R is not
+// positive definite.
+template <int N, int M>
+LQK_DEV bool schur_cross(const ProbPtrs &P, const InstDesc &d, int k, Stage<N, M> &w)
+{
+    double Mk[N][M], rk[M], Ri[M][M];
+    ldm(P.M ? P.M + d.oB + (int64_t)k * N * M : nullptr, Mk);
+    ldv(P.r ? P.r + d.og + (int64_t)k * M : nullptr, rk);
+    const bool ok = inv_spd<M>(w.R, Ri);
+    double KM[M][N], Kr[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int b = 0; b < M; ++b) t += Ri[a][b] * Mk[j][b];
+            KM[a][j] = t;
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int b = 0; b < M; ++b) t += Ri[a][b] * rk[b];
+        Kr[a] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double ta = w.A[i][j], tq = w.Q[i][j];
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                ta -= w.B[i][a] * KM[a][j];
+                tq -= Mk[i][a] * KM[a][j];
+            }
+            w.A[i][j] = ta;
+            w.Q[i][j] = tq;
+        }
+        double tc = w.c[i], tqv = w.q[i];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            tc -= w.B[i][a] * Kr[a];
+            tqv -= Mk[i][a] * Kr[a];
+        }
+        w.c[i] = tc;
+        w.q[i] = tqv;
+    }
+    return ok;
+}
+
+// ---- the element of an aggregate suffix ----
+
+template <int N>
+struct Elem {
+    double A[N][N], b[N], C[N][N], e[N], J[N][N];   // e = eta
+};
+
+// E <- e_k (x) E for the stage element e_k = (A, c, B R^{-1} B', -q, Q) of w
+// (eq:value-fun-param with the stage on the left, in the rank-m form):
+//   W = R + B'J B,  P = B'J A,  v = eta - J c,  p = B'v,  H = A^ B,
+//   A^ <- A^ A - H W^{-1} P,        b^ <- A^ c + b^ + H W^{-1} p,
+//   C^ <- C^ + H W^{-1} H',         eta^ <- A'v - P'W^{-1} p - q,
+//   J^ <- Q + A'J A - P'W^{-1} P    (then symmetrised).
+// False if W is singular.
+template <int N, int M>
+LQK_DEV bool fold_stage(const Stage<N, M> &w, Elem<N> &E)
+{
+    double JB[N][M], JA[N][N], v[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += E.J[i][k] * w.B[k][a];
+            JB[i][a] = t;
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += E.J[i][k] * w.A[k][j];
+            JA[i][j] = t;
+        }
+        double t = E.e[i];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t -= E.J[i][k] * w.c[k];
+        v[i] = t;
+    }
+    double W[M][M], Pm[M][N], pb[M], H[N][M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int b2 = 0; b2 < M; ++b2) {
+            double t = w.R[a][b2];
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += w.B[k][a] * JB[k][b2];
+            W[a][b2] = t;
+        }
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += JB[k][a] * w.A[k][j];
+            Pm[a][j] = t;
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) t += w.B[k][a] * v[k];
+        pb[a] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += E.A[i][k] * w.B[k][a];
+            H[i][a] = t;
+        }
+    double Wi[M][M];
+    const bool ok = inv_gj<M>(W, Wi);
+    double WP[M][N], Wp[M], WH[M][N];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double t = 0.0, u = 0.0;
+#pragma unroll
+            for (int b2 = 0; b2 < M; ++b2) {
+                t += Wi[a][b2] * Pm[b2][j];
+                u += Wi[a][b2] * H[j][b2];
+            }
+            WP[a][j] = t;
+            WH[a][j] = u;
+        }
+        double t = 0.0;
+#pragma unroll
+        for (int b2 = 0; b2 < M; ++b2) t += Wi[a][b2] * pb[b2];
+        Wp[a] = t;
+    }
+    // b^, eta^ read the old A^, J^ only through H, v and P (formed above), so
+    // every field but A^ is updated in place; J^ on its upper triangle.
+    double nA[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        double tb = E.b[i], te = -w.q[i];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            tb += E.A[i][k] * w.c[k];
+            te += w.A[k][i] * v[k];
+        }
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            tb += H[i][a] * Wp[a];
+            te -= Pm[a][i] * Wp[a];
+        }
+        E.b[i] = tb;
+        E.e[i] = te;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            double ta = 0.0, tc = E.C[i][j];
+#pragma unroll
+            for (int k = 0; k < N; ++k) ta += E.A[i][k] * w.A[k][j];
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                ta -= H[i][a] * WP[a][j];
+                tc += H[i][a] * WH[a][j];
+            }
+            nA[i][j] = ta;
+            E.C[i][j] = tc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = i; j < N; ++j) {
+            double tj = 0.5 * (w.Q[i][j] + w.Q[j][i]);
+#pragma unroll
+            for (int k = 0; k < N; ++k) tj += 0.5 * (w.A[k][i] * JA[k][j] + w.A[k][j] * JA[k][i]);
+#pragma unroll
+            for (int a = 0; a < M; ++a) tj -= 0.5 * (Pm[a][i] * WP[a][j] + Pm[a][j] * WP[a][i]);
+            E.J[i][j] = tj;
+            E.J[j][i] = tj;
+            E.A[i][j] = nA[i][j];
+            E.A[j][i] = nA[j][i];
+        }
+    return ok;
+}
+
+// ---------------------------------------------------------------------------
+// Phase 1: fold of segment s >= 1 into one element at scan entry s (the last
+// segment folded onto the terminal element (0, 0, 0, -q_T, Q_T)); segment 0's
+// element is never read.
+// ---------------------------------------------------------------------------
+template <int N, int M>
+__global__ __launch_bounds__(64) void k_small_value_fold(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                         const int32_t *__restrict__ seg_start, int batch, int total,
+                                                         double *__restrict__ X, int32_t *status)
+{
+    const int gs = gid();
+    if (gs >= total) return;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    if (s == 0) return;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    Elem<N> E;
+    const bool last = (s == d.nseg - 1);
+    double qT[N];
+    ldv(P.qT ? P.qT + d.on : nullptr, qT);
+    if (last) ldm(P.QT + d.oQT, E.J);
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            E.A[r][c] = (!last && r == c) ? 1.0 : 0.0;
+            E.C[r][c] = 0.0;
+            if (!last) E.J[r][c] = 0.0;
+        }
+        E.b[r] = 0.0;
+        E.e[r] = last ? -qT[r] : 0.0;
+    }
+    const bool mr = (P.M != nullptr) || (P.r != nullptr);
+    int code = 0, fk = 0;
+    for (int k = k1 - 1; k >= k0; --k) {
+        Stage<N, M> w;
+        load_stage(P, d, k, w);
+        if (mr) note1(schur_cross(P, d, k, w), SERR_NOT_PD, k, code, fk);
+        note1(fold_stage(w, E), SERR_SINGULAR, k, code, fk);
+    }
+    double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
+    store_map(o, E.A, E.b);
+    store_c(o + TILE, E.C);
+    double v[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) v[r] = -E.e[r];
+    store_jv(o + 2 * TILE, E.J, v);
+    if (code) report1(status, d.orig, code, fk);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 2: one Kogge-Stone level of the suffix scan, X_s <- X_s (x) X_{s+dd}
+// over entries 1 .. nseg-1 (the same schedule as k_value_ks): with
+// Y = (I + C1 J2)^{-1},
+//   A = A2 Y A1,  b = A2 Y (b1 + C1 eta2) + b2,  C = A2 Y C1 A2' + C2,
+//   eta = A1'Y'(eta2 - J2 b1) + eta1,  J = A1'Y'J2 A1 + J1;
+// only (eta, J) once the right operand covers the terminal element.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restrict__ inst,
+                                                       const int32_t *__restrict__ x_start, int batch, int total,
+                                                       int dd, const double *__restrict__ Xin,
+                                                       double *__restrict__ Xout, int32_t *status)
+{
+    constexpr int N1 = N + 1;
+    const int gx = gid();
+    if (gx >= total) return;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    const int last = d.nseg - 1;
+    if (s == 0 || s > last) return;
+    const double *a = Xin + (int64_t)gx * 3 * TILE;
+    double *o = Xout + (int64_t)gx * 3 * TILE;
+    if (s + dd > last) {   // final already: carry J~ over
+#pragma unroll
+        for (int r = 0; r < N1 * N1; ++r) o[2 * TILE + r] = a[2 * TILE + r];
+        return;
+    }
+    const double *bp = Xin + (int64_t)(gx + dd) * 3 * TILE;
+    const bool b_term = (s + 2 * dd - 1 >= last);
+    double A1[N][N], b1[N], C1[N][N], J1[N][N], v1[N], J2[N][N], v2[N];
+    load_map(a, A1, b1);
+    load_c(a + TILE, C1);
+    load_jv(a + 2 * TILE, J1, v1);   // v = -eta
+    load_jv(bp + 2 * TILE, J2, v2);
+    double X[N][N], Y[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double t = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += C1[r][k] * J2[k][c];
+            X[r][c] = t;
+        }
+    const bool ok = inv_gj<N>(X, Y);
+    // w = eta2 - J2 b1 = -(v2 + J2 b1);  Y'w;  G = J2 A1;  Y'G
+    double w[N], G[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = -v2[r];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t -= J2[r][k] * b1[k];
+        w[r] = t;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) u += J2[r][k] * A1[k][c];
+            G[r][c] = u;
+        }
+    }
+    double Yw[N], YG[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) t += Y[k][r] * w[k];
+        Yw[r] = t;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) u += Y[k][r] * G[k][c];
+            YG[r][c] = u;
+        }
+    }
+    double Jn[N][N], vn[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = v1[r];   // -eta = -(A1'Y'w + eta1)
+#pragma unroll
+        for (int k = 0; k < N; ++k) t -= A1[k][r] * Yw[k];
+        vn[r] = t;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = J1[r][c];
+#pragma unroll
+            for (int k = 0; k < N; ++k) u += A1[k][r] * YG[k][c];
+            Jn[r][c] = u;
+        }
+    }
+    sym(Jn);
+    store_jv(o + 2 * TILE, Jn, vn);
+    if (!b_term) {
+        double A2[N][N], b2[N], C2[N][N];
+        load_map(bp, A2, b2);
+        load_c(bp + TILE, C2);
+        // YA = Y A1, y = Y (b1 + C1 eta2), YC = Y C1
+        double z[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = b1[r];
+#pragma unroll
+            for (int k = 0; k < N; ++k) t -= C1[r][k] * v2[k];   // eta2 = -v2
+            z[r] = t;
+        }
+        double YA[N][N], yz[N], YC[N][N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += Y[r][k] * z[k];
+            yz[r] = t;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = 0.0, x = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    u += Y[r][k] * A1[k][c];
+                    x += Y[r][k] * C1[k][c];
+                }
+                YA[r][c] = u;
+                YC[r][c] = x;
+            }
+        }
+        double An[N][N], bn[N], T2[N][N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = b2[r];
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += A2[r][k] * yz[k];
+            bn[r] = t;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = 0.0, x = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    u += A2[r][k] * YA[k][c];
+                    x += A2[r][k] * YC[k][c];
+                }
+                An[r][c] = u;
+                T2[r][c] = x;
+            }
+        }
+        double Cn[N][N];
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = C2[r][c];
+#pragma unroll
+                for (int k = 0; k < N; ++k) u += T2[r][k] * A2[c][k];
+                Cn[r][c] = u;
+            }
+        sym(Cn);
+        store_map(o, An, bn);
+        store_c(o + TILE, Cn);
+    }
+    if (!ok) report1(status, d.orig, SERR_SINGULAR, s * d.L);
+}
+
+// ---------------------------------------------------------------------------
+// Phase 3: Bellman steps over stages k1-1 .. k0 from the carry (the scanned
+// value function of entry s + 1, or the terminal cost for the last segment):
+//   Q_uu = R + B'S'B,  Q_ux = M' + B'S'A,  q_u = r + B'(S'c + s'),
+//   Gamma = -Q_uu^{-1} Q_ux,  gamma = -Q_uu^{-1} q_u,
+//   S = sym(Q + A'S'A + Q_ux'Gamma),  s = q + A'(S'c + s') + Q_ux'gamma.
+// With Yroll the sweep also composes the segment's closed-loop maps
+// Phi = F~_{k1-1} ... F~_{k0}, F~ = [[A + B Gamma, c + B gamma], [0, 1]], and
+// writes the rollout scan's entries (Phi at s + 1 for s < nseg - 1, the
+// constant map of x0 at 0).  With ckpt the last segment of each group of
+// `stride` segments stores its carry in the checkpoint (as k_value_riccati).
+// ---------------------------------------------------------------------------
+template <int N, int M>
+__global__ __launch_bounds__(64) void k_small_value_riccati(ProbPtrs P, const InstDesc *__restrict__ inst,
+                                                            const int32_t *__restrict__ seg_start, int batch,
+                                                            int total, const double *__restrict__ Xfin, ValPtrs V,
+                                                            double *__restrict__ Yroll, double *__restrict__ ckpt,
+                                                            int stride, int32_t *status)
+{
+    const int gs = gid();
+    if (gs >= total) return;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const bool last = (s == d.nseg - 1);
+    double S[N][N], sv[N];
+    if (last) {
+        ldm(P.QT + d.oQT, S);
+        ldv(P.qT ? P.qT + d.on : nullptr, sv);
+    } else {
+        load_jv(Xfin + (int64_t)(d.xbase + s + 1) * 3 * TILE + 2 * TILE, S, sv);
+    }
+    if (ckpt && ((s + 1) % stride == 0 || last))
+        store_jv(ckpt + (int64_t)(ckpt_slot(d, i, stride) + s / stride) * TILE, S, sv);
+    int code = 0, fk = 0;
+    if (last) {
+        stm(V.S + d.oS + (int64_t)d.T * N * N, S);
+        stv(V.s + d.os + (int64_t)d.T * N, sv);
+        bool fin = true;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            fin = fin && isfinite(sv[r]);
+#pragma unroll
+            for (int c = 0; c < N; ++c) fin = fin && isfinite(S[r][c]);
+        }
+        note1(fin, SERR_NONFINITE, d.T, code, fk);
+    }
+    const bool mr = (P.M != nullptr) || (P.r != nullptr);
+    const bool roll = (Yroll != nullptr);
+    double FA[N][N], Fb[N];   // Phi = [[FA, Fb], [0, 1]]
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+        for (int c = 0; c < N; ++c) FA[r][c] = (r == c) ? 1.0 : 0.0;
+        Fb[r] = 0.0;
+    }
+    for (int k = k1 - 1; k >= k0; --k) {
+        Stage<N, M> w;
+        load_stage(P, d, k, w);
+        double Mk[N][M], rk[M];
+        ldm(mr && P.M ? P.M + d.oB + (int64_t)k * N * M : nullptr, Mk);
+        ldv(mr && P.r ? P.r + d.og + (int64_t)k * M : nullptr, rk);
+        // Sc = S'c + s',  SA = S'A,  SB = S'B
+        double Sc[N], SA[N][N], SB[N][M];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = sv[r];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) t += S[r][k2] * w.c[k2];
+            Sc[r] = t;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.A[k2][c];
+                SA[r][c] = u;
+            }
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                double u = 0.0;
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.B[k2][a];
+                SB[r][a] = u;
+            }
+        }
+        double Quu[M][M], Qux[M][N], qu[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+#pragma unroll
+            for (int b2 = 0; b2 < M; ++b2) {
+                double t = w.R[a][b2];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SB[k2][b2];
+                Quu[a][b2] = t;
+            }
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double t = Mk[c][a];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SA[k2][c];
+                Qux[a][c] = t;
+            }
+            double t = rk[a];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * Sc[k2];
+            qu[a] = t;
+        }
+        double Qi[M][M];
+        const bool pd = inv_spd<M>(Quu, Qi);
+        double G[M][N], g[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * Qux[b2][c];
+                G[a][c] = t;
+            }
+            double t = 0.0;
+#pragma unroll
+            for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * qu[b2];
+            g[a] = t;
+        }
+        double Sn[N][N], sn[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double t = w.Q[r][c];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * SA[k2][c];
+#pragma unroll
+                for (int a = 0; a < M; ++a) t += Qux[a][r] * G[a][c];
+                Sn[r][c] = t;
+            }
+            double t = w.q[r];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * Sc[k2];
+#pragma unroll
+            for (int a = 0; a < M; ++a) t += Qux[a][r] * g[a];
+            sn[r] = t;
+        }
+        sym(Sn);
+        bool fin = true;
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            fin = fin && isfinite(sn[r]);
+#pragma unroll
+            for (int c = 0; c < N; ++c) fin = fin && isfinite(Sn[r][c]);
+        }
+        note1(fin, SERR_NONFINITE, k, code, fk);
+        note1(pd, SERR_NOT_PD, k, code, fk);
+        stm(V.S + d.oS + (int64_t)k * N * N, Sn);
+        stv(V.s + d.os + (int64_t)k * N, sn);
+        stm(V.G + d.oG + (int64_t)k * M * N, G);
+        stv(V.g + d.og + (int64_t)k * M, g);
+        if (roll) {
+            // Phi <- Phi F~_k:  FA <- FA (A + B Gamma),  Fb <- FA (c + B gamma) + Fb
+            double F[N][N], f[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double t = w.c[r];
+#pragma unroll
+                for (int a = 0; a < M; ++a) t += w.B[r][a] * g[a];
+                f[r] = t;
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double u = w.A[r][c];
+#pragma unroll
+                    for (int a = 0; a < M; ++a) u += w.B[r][a] * G[a][c];
+                    F[r][c] = u;
+                }
+            }
+            double nA[N][N], nb[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double t = Fb[r];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += FA[r][k2] * f[k2];
+                nb[r] = t;
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double u = 0.0;
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) u += FA[r][k2] * F[k2][c];
+                    nA[r][c] = u;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                Fb[r] = nb[r];
+#pragma unroll
+                for (int c = 0; c < N; ++c) FA[r][c] = nA[r][c];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            sv[r] = sn[r];
+#pragma unroll
+            for (int c = 0; c < N; ++c) S[r][c] = Sn[r][c];
+        }
+    }
+    if (roll) {
+        if (s == 0) {
+            double Z[N][N], x0[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+#pragma unroll
+                for (int c = 0; c < N; ++c) Z[r][c] = 0.0;
+            ldv(P.x0 + d.on, x0);
+            store_map(Yroll + (int64_t)d.xbase * TILE, Z, x0);
+        }
+        if (!last) store_map(Yroll + (int64_t)(d.xbase + s + 1) * TILE, FA, Fb);
+    }
+    if (code) report1(status, d.orig, code, fk);
+}
+
+// ---------------------------------------------------------------------------
+// One radix-RAD level of an affine-map scan (the schedule of k_affine_ks):
+//   prefix: Y_s <- Y_s Y_{s-dd} ... Y_{s-(RAD-1)dd},
+//   suffix: Y_s <- Y_s Y_{s+dd} ... Y_{s+(RAD-1)dd},
+// terms outside [0, nseg] left out; the entry no segment reads is skipped.
+// [[F1, e1], [0, 1]] [[F2, e2], [0, 1]] = [[F1 F2, F1 e2 + e1], [0, 1]].
+// ---------------------------------------------------------------------------
+template <int N, int RAD>
+__global__ __launch_bounds__(64) void k_small_affine_ks(const InstDesc *__restrict__ inst,
+                                                        const int32_t *__restrict__ x_start, int batch, int total,
+                                                        int dd, int suffix, const double *__restrict__ Yin,
+                                                        double *__restrict__ Yout)
+{
+    const int gx = gid();
+    if (gx >= total) return;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    if (suffix ? (s == 0) : (s == d.nseg)) return;
+    double F[N][N], e[N];
+    load_map(Yin + (int64_t)gx * TILE, F, e);
+    const int avail = suffix ? (d.nseg - s) / dd : s / dd;
+    const int terms = min(RAD - 1, avail);
+    const int64_t step = suffix ? dd : -dd;
+    for (int j = 1; j <= terms; ++j) {
+        double F2[N][N], e2[N];
+        load_map(Yin + (gx + j * step) * TILE, F2, e2);
+        double nF[N][N], ne[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = e[r];
+#pragma unroll
+            for (int k = 0; k < N; ++k) t += F[r][k] * e2[k];
+            ne[r] = t;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = 0.0;
+#pragma unroll
+                for (int k = 0; k < N; ++k) u += F[r][k] * F2[k][c];
+                nF[r][c] = u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            e[r] = ne[r];
+#pragma unroll
+            for (int c = 0; c < N; ++c) F[r][c] = nF[r][c];
+        }
+    }
+    store_map(Yout + (int64_t)gx * TILE, F, e);
+}
+
+// ---------------------------------------------------------------------------
+// States from the segment start (the last column of scanned entry s):
+// x_k stored, u_k = Gamma_k x_k + gamma_k, lambda_k = S_k x_k + s_k,
+// x_{k+1} = A x_k + B u_k + c; the last segment also writes x_T, lambda_T.
+// ---------------------------------------------------------------------------
+template <int N, int M>
+__global__ __launch_bounds__(64) void k_small_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
+                                                         const int32_t *__restrict__ seg_start, int batch, int total,
+                                                         const double *__restrict__ Yfin, double *__restrict__ x,
+                                                         double *__restrict__ u, double *__restrict__ lam)
+{
+    constexpr int N1 = N + 1;
+    const int gs = gid();
+    if (gs >= total) return;
+    const int i = find_inst(seg_start, batch, gs);
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    const double *ye = Yfin + (int64_t)(d.xbase + s) * TILE;
+    double xv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) xv[r] = ye[r * N1 + N];
+    for (int k = k0; k < k1; ++k) {
+        stv(x + d.os + (int64_t)k * N, xv);
+        double A[N][N], B[N][M], c[N], Gm[M][N], g[M];
+        ldm(P.A + d.oA + (int64_t)k * N * N, A);
+        ldm(P.B + d.oB + (int64_t)k * N * M, B);
+        ldv(P.c ? P.c + d.oc + (int64_t)k * N : nullptr, c);
+        ldm(V.G + d.oG + (int64_t)k * M * N, Gm);
+        ldv(V.g + d.og + (int64_t)k * M, g);
+        double uk[M];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            double t = g[a];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) t += Gm[a][k2] * xv[k2];
+            uk[a] = t;
+        }
+        stv(u + d.og + (int64_t)k * M, uk);
+        if (lam) {
+            double Sk[N][N], sk[N], l[N];
+            ldm(V.S + d.oS + (int64_t)k * N * N, Sk);
+            ldv(V.s + d.os + (int64_t)k * N, sk);
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double t = sk[r];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += Sk[r][k2] * xv[k2];
+                l[r] = t;
+            }
+            stv(lam + d.os + (int64_t)k * N, l);
+        }
+        double xn[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = c[r];
+#pragma unroll
+            for (int k2 = 0; k2 < N; ++k2) t += A[r][k2] * xv[k2];
+#pragma unroll
+            for (int a = 0; a < M; ++a) t += B[r][a] * uk[a];
+            xn[r] = t;
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) xv[r] = xn[r];
+    }
+    if (k1 == d.T) {
+        stv(x + d.os + (int64_t)d.T * N, xv);
+        if (lam) {
+            double Sk[N][N], sk[N], l[N];
+            ldm(V.S + d.oS + (int64_t)d.T * N * N, Sk);
+            ldv(V.s + d.os + (int64_t)d.T * N, sk);
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double t = sk[r];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += Sk[r][k2] * xv[k2];
+                l[r] = t;
+            }
+            stv(lam + d.os + (int64_t)d.T * N, l);
+        }
+    }
+}
+
+unsigned lanes_grid(int64_t total) { return (unsigned)((total + 63) / 64); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host launchers: (n, m) in 1..4 x 1..4, one lane per segment or entry.
+// ---------------------------------------------------------------------------
+
+#define LQK_SMALL_NM(n, m, CALL)                                                     \
+    switch ((n) * 8 + (m)) {                                                         \
+    case 9: CALL(1, 1); break;  case 10: CALL(1, 2); break;                          \
+    case 11: CALL(1, 3); break; case 12: CALL(1, 4); break;                          \
+    case 17: CALL(2, 1); break; case 18: CALL(2, 2); break;                          \
+    case 19: CALL(2, 3); break; case 20: CALL(2, 4); break;                          \
+    case 25: CALL(3, 1); break; case 26: CALL(3, 2); break;                          \
+    case 27: CALL(3, 3); break; case 28: CALL(3, 4); break;                          \
+    case 33: CALL(4, 1); break; case 34: CALL(4, 2); break;                          \
+    case 35: CALL(4, 3); break; default: CALL(4, 4); break;                          \
+    }
+#define LQK_SMALL_N(n, CALL)                                                         \
+    switch (n) {                                                                     \
+    case 1: CALL(1); break; case 2: CALL(2); break;                                  \
+    case 3: CALL(3); break; default: CALL(4); break;                                 \
+    }
+
+void launch_small_value_fold(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                             const int32_t *seg_start, int batch, double *X, int32_t *status)
+{
+#define CALL(N, M) hipLaunchKernelGGL((k_small_value_fold<N, M>), dim3(lanes_grid(total)), dim3(64), 0, st, P, inst, seg_start, batch, (int)total, X, status)
+    LQK_SMALL_NM(n, m, CALL)
+#undef CALL
+}
+
+void launch_small_value_ks(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+                           int batch, int dd, const double *Xin, double *Xout, int32_t *status)
+{
+#define CALL(N) hipLaunchKernelGGL((k_small_value_ks<N>), dim3(lanes_grid(total)), dim3(64), 0, st, inst, x_start, batch, (int)total, dd, Xin, Xout, status)
+    LQK_SMALL_N(n, CALL)
+#undef CALL
+}
+
+void launch_small_value_riccati(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, const InstDesc *inst,
+                                const int32_t *seg_start, int batch, const double *Xfin, ValPtrs V, double *Yroll,
+                                double *ckpt, int stride, int32_t *status)
+{
+#define CALL(N, M) hipLaunchKernelGGL((k_small_value_riccati<N, M>), dim3(lanes_grid(total)), dim3(64), 0, st, P, inst, seg_start, batch, (int)total, Xfin, V, Yroll, ckpt, stride, status)
+    LQK_SMALL_NM(n, m, CALL)
+#undef CALL
+}
+
+void launch_small_affine_ks(int n, int radix, int64_t total, hipStream_t st, const InstDesc *inst,
+                            const int32_t *x_start, int batch, int dd, int suffix, const double *Yin, double *Yout)
+{
+#define CALLR(N, RAD) hipLaunchKernelGGL((k_small_affine_ks<N, RAD>), dim3(lanes_grid(total)), dim3(64), 0, st, inst, x_start, batch, (int)total, dd, suffix, Yin, Yout)
+#define CALL2(N) CALLR(N, 2)
+#define CALL4(N) CALLR(N, 4)
+#define CALL8(N) CALLR(N, 8)
+#define CALL16(N) CALLR(N, 16)
+#define CALL32(N) CALLR(N, 32)
+    switch (radix) {
+    case 2: LQK_SMALL_N(n, CALL2) break;
+    case 8: LQK_SMALL_N(n, CALL8) break;
+    case 16: LQK_SMALL_N(n, CALL16) break;
+    case 32: LQK_SMALL_N(n, CALL32) break;
+    default: LQK_SMALL_N(n, CALL4) break;
+    }
+#undef CALL2
+#undef CALL4
+#undef CALL8
+#undef CALL16
+#undef CALL32
+#undef CALLR
+}
+
+void launch_small_roll_apply(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
+                             const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u,
+                             double *lam)
+{
+#define CALL(N, M) hipLaunchKernelGGL((k_small_roll_apply<N, M>), dim3(lanes_grid(total)), dim3(64), 0, st, P, V, inst, seg_start, batch, (int)total, Yfin, x, u, lam)
+    LQK_SMALL_NM(n, m, CALL)
+#undef CALL
+}
+
+}  // namespace lqk

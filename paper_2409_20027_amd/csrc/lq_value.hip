@@ -212,7 +212,7 @@ __global__ __launch_bounds__(64) void k_build_elements(ProbPtrs P, const InstDes
     gstore(out + TILE, tnz<1, PR>(GT, GT));
     gstore(out + 2 * TILE, J);
     gstore(out + 3 * TILE, G);
-    if (!ok) report(status, i, ERR_NOT_PD, k);
+    if (!ok) report(status, d.orig, ERR_NOT_PD, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(64) void k_value_fold(ProbPtrs P, const InstDesc *_
     gstore_c(o, ttrans(U, lds), n1);
     gstore_c(o + TILE, tsym(Ch, lds), n1);
     gstore_c(o + 2 * TILE, tsym(Jh, lds), n1);
-    if (code) report(status, i, code, fk);
+    if (code) report(status, d.orig, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
         gstore_c(o, tnz<NK, PR>(A2T, Z), n1);          // A~2 X^{-1} A~1
         gstore_c(o + TILE, tsym(tna<NK, PR>(Vt, A2T, C2), lds), n1);
     }
-    if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
+    if (!ok) report(status, d.orig, ERR_SINGULAR, s * d.L);
 }
 
 // ---------------------------------------------------------------------------
@@ -473,7 +473,7 @@ __global__ __launch_bounds__(64) void k_value_riccati(ProbPtrs P, const InstDesc
         if (s == 0) gstore_c(Yroll + (int64_t)d.xbase * TILE, load_vec(P.x0 + d.on, n, n, n), d.n + 1);
         if (s < d.nseg - 1) gstore_c(Yroll + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
     }
-    if (code) report(status, i, code, fk);
+    if (code) report(status, d.orig, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -523,7 +523,7 @@ __global__ __launch_bounds__(64) void k_value_recompute(ProbPtrs P, const InstDe
         riccati_sweep<NK, PR, true, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
     else
         riccati_sweep<NK, PR, false, false>(P, d, V, k0, k1, St, PhiT, code, fk, lds, stg);
-    if (code) report(status, i, code, fk);
+    if (code) report(status, d.orig, code, fk);
 }
 
 // ---------------------------------------------------------------------------
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(64) void k_cv_start(ProbPtrs P, ValPtrs V, const In
     const bool ok = gj_inverse<NK>(YT, n1, true);      // (I + C~ S~)^{-T}
     const Tile AX = tnz<NK, PR>(ttrans(Ah, lds), X0);   // A~ x~0
     gstore_c(Y + (int64_t)(d.xbase + s) * TILE, tnz<NK, PR>(YT, AX), d.n + 1);
-    if (!ok) report(status, i, ERR_SINGULAR, s * d.L);
+    if (!ok) report(status, d.orig, ERR_SINGULAR, s * d.L);
 }
 
 // ---------------------------------------------------------------------------
