@@ -211,53 +211,80 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *_
     }
 }
 
-// The tanh model (any nx <= 15, nu <= 4): W and B in LDS, loops unrolled to
-// the maximum sizes with guards so that the state stays in registers.
+// The tanh model: one block per instance.  The controls u + du are staged
+// through LDS in chunks of CH stages by the whole block (coalesced loads, the
+// used controls written back from there), and one lane runs the recursion
+// over the chunk reading LDS, so no step waits for a load from HBM.  NX > 0:
+// the sizes are compile-time (nx = NX <= 4, nu = NU), W and B sit in
+// registers; NX = 0: any nx <= 15, nu <= 4, loops unrolled to the maximum
+// sizes with guards (tanh evaluated for the nx rows only).
+template <int NX, int NU>
 __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
                                                           const double *__restrict__ du, double *__restrict__ xout,
                                                           double *__restrict__ uout)
 {
-    __shared__ double sW[NXMAX * NXMAX], sB[NXMAX * NUMAX];
-    const int n = N.nx, m = N.nu, T = N.T;
+    constexpr bool FIXED = NX > 0;
+    constexpr int XM = FIXED ? NX : NXMAX, UM = FIXED ? NU : NUMAX;
+    constexpr int CH = 512;
+    __shared__ double su[CH * UM];
+    __shared__ double sW[XM * XM], sB[XM * UM];
+    const int n = FIXED ? NX : N.nx, m = FIXED ? NU : N.nu, T = N.T;
     const int b = blockIdx.x;   // one instance per block
-    for (int i = threadIdx.x; i < n * n; i += 64) sW[i] = N.W[i];
-    for (int i = threadIdx.x; i < n * m; i += 64) sB[i] = N.Bm[i];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
+    const int t = threadIdx.x;
+    for (int i = t; i < n * n; i += 64) sW[i] = N.W[i];
+    for (int i = t; i < n * m; i += 64) sB[i] = N.Bm[i];
     u += (int64_t)b * T * m;
     if (du) du += (int64_t)b * T * m;
     xout += (int64_t)b * (T + 1) * n;
     if (uout) uout += (int64_t)b * T * m;
-    double x[NXMAX];
+    __syncthreads();
+    double W[XM][XM], Bm[XM][UM], x[XM];
 #pragma unroll
-    for (int i = 0; i < NXMAX; ++i) {
-        x[i] = (i < n) ? N.x0[(int64_t)b * n + i] : 0.0;
-        if (i < n) xout[i] = x[i];
+    for (int i = 0; i < XM; ++i) {
+#pragma unroll
+        for (int j = 0; j < XM; ++j) W[i][j] = (i < n && j < n) ? sW[i * n + j] : 0.0;
+#pragma unroll
+        for (int j = 0; j < UM; ++j) Bm[i][j] = (i < n && j < m) ? sB[i * m + j] : 0.0;
+        x[i] = (i < n) ? N.x0[(int64_t)b * n + (i < n ? i : 0)] : 0.0;
+        if (t == 0 && i < n) xout[i] = x[i];
     }
-    for (int k = 0; k < T; ++k) {
-        double uk[NUMAX];
-#pragma unroll
-        for (int i = 0; i < NUMAX; ++i) {
-            const int64_t o = (int64_t)k * m + (i < m ? i : 0);
-            uk[i] = (i < m) ? u[o] + (du ? du[o] : 0.0) : 0.0;
-            if (uout && i < m) uout[o] = uk[i];
+    for (int c0 = 0; c0 < T; c0 += CH) {
+        const int len = min(CH, T - c0);
+        __syncthreads();   // the previous chunk has been consumed
+        for (int i = t; i < len * m; i += 64) {
+            const int64_t o = (int64_t)c0 * m + i;
+            const double v = u[o] + (du ? du[o] : 0.0);
+            su[i] = v;
+            if (uout) uout[o] = v;
         }
-        double xn[NXMAX];
+        __syncthreads();
+        if (t != 0) continue;
+        for (int k = 0; k < len; ++k) {
+            double uk[UM];
 #pragma unroll
-        for (int i = 0; i < NXMAX; ++i) {
-            double z = 0.0, bu = 0.0;
+            for (int j = 0; j < UM; ++j) uk[j] = (j < m) ? su[k * m + (j < m ? j : 0)] : 0.0;
+            double xn[XM];
 #pragma unroll
-            for (int j = 0; j < NXMAX; ++j)
-                if (i < n && j < n) z += sW[i * n + j] * x[j];
+            for (int i = 0; i < XM; ++i) {
+                if (i < n) {
+                    double z = 0.0, bu = 0.0;
 #pragma unroll
-            for (int j = 0; j < NUMAX; ++j)
-                if (i < n && j < m) bu += sB[i * m + j] * uk[j];
-            xn[i] = (i < n) ? x[i] + N.h * (tanh(z) + bu) : 0.0;
-        }
+                    for (int j = 0; j < XM; ++j)
+                        if (j < n) z += W[i][j] * x[j];
 #pragma unroll
-        for (int i = 0; i < NXMAX; ++i) {
-            x[i] = xn[i];
-            if (i < n) xout[(int64_t)(k + 1) * n + i] = xn[i];
+                    for (int j = 0; j < UM; ++j)
+                        if (j < m) bu += Bm[i][j] * uk[j];
+                    xn[i] = x[i] + N.h * (tanh(z) + bu);
+                } else {
+                    xn[i] = 0.0;
+                }
+            }
+            double *xo = xout + (int64_t)(c0 + k + 1) * n;
+#pragma unroll
+            for (int i = 0; i < XM; ++i) {
+                x[i] = xn[i];
+                if (i < n) xo[i] = xn[i];
+            }
         }
     }
 }
@@ -656,7 +683,18 @@ static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, c
     } else if (N.model == MODEL_CARTPOLE) {
         if (du) RL(MODEL_CARTPOLE, true); else RL(MODEL_CARTPOLE, false);
     } else {
-        hipLaunchKernelGGL(k_nmpc_rollout_tanh, dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout);
+#define RT(X, U) hipLaunchKernelGGL((k_nmpc_rollout_tanh<X, U>), dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout)
+        if (N.nx <= 4) {
+            switch (N.nx * 8 + N.nu) {
+            case 9: RT(1, 1); break;  case 10: RT(1, 2); break; case 11: RT(1, 3); break; case 12: RT(1, 4); break;
+            case 17: RT(2, 1); break; case 18: RT(2, 2); break; case 19: RT(2, 3); break; case 20: RT(2, 4); break;
+            case 25: RT(3, 1); break; case 26: RT(3, 2); break; case 27: RT(3, 3); break; case 28: RT(3, 4); break;
+            case 33: RT(4, 1); break; case 34: RT(4, 2); break; case 35: RT(4, 3); break; default: RT(4, 4); break;
+            }
+        } else {
+            RT(0, 0);
+        }
+#undef RT
     }
 #undef RL
 }
