@@ -811,6 +811,8 @@ def main():
     ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc", "batched", "cfg0", "cfg1",
                                           "ragged_replay"),
                     default=None, help="run only this section (GPU paths only) and print its JSON")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="the headline workload only (no mixed-precision, small-case or Newton sections)")
     ap.add_argument("--gap-summary", metavar="KERNEL_TRACE_CSV", default=None,
                     help="summarise launch gaps inside graph replays from a rocprofv3 kernel trace (no GPU)")
     args = ap.parse_args()
@@ -1014,9 +1016,10 @@ def main():
            "phase_roofline": phase_roofline,
            "cv_rollout": cv,
            "roofline": roof}
-    out["mixed_precision"] = cfg2_mixed(lqscan, dev, prob, inst, ref, gref, args.steps, args.replays)
-    out["small_case"] = cfg0_small(lqscan, workloads, dev, args.replays, not args.no_cpu)
-    out["newton_ip"] = cfg1_newton(lqscan, workloads, 3, not args.no_cpu)
+    if not args.only_headline:
+        out["mixed_precision"] = cfg2_mixed(lqscan, dev, prob, inst, ref, gref, args.steps, args.replays)
+        out["small_case"] = cfg0_small(lqscan, workloads, dev, args.replays, not args.no_cpu)
+        out["newton_ip"] = cfg1_newton(lqscan, workloads, 3, not args.no_cpu)
     if not args.no_batch:
         out["batched"] = batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), not args.no_cpu)
     if not args.no_paper:

@@ -8,15 +8,17 @@ instances share the GPU, so it is measured instead of assumed.
 
 Instances are grouped into classes (n, m, T bucket).  For each class the tuner
 times the forward solve (lq_solve) of the class's instances for every
-candidate L with HIP events (the median of `reps` timed calls, each bracketed
-by its own events) and keeps the fastest only if it beats the library
-default (L = 0) by more than MARGIN; otherwise the default stays.  Choices
-within timing noise of each other therefore do not flip from one tuning to
-the next.  A class timed
+candidate L with HIP events (the median of `reps` timed samples, each
+bracketed by its own events and repeating the solve until it lasts at least
+MIN_SAMPLE_MS) and keeps the fastest only if it beats the library default
+(L = 0) by more than MARGIN on the medians and then wins CONFIRM_WINS of
+CONFIRM_PAIRS interleaved head-to-head samples against it; otherwise the
+default stays.  Choices within timing noise of each other therefore do not
+flip from one tuning to the next.  A class timed
 alone can prefer the scan where, inside the whole batch, the GPU is already
 full and the sequential recursion (least work) is faster; so the per-class
 choice is then refined on the whole batch, switching classes to L = T while
-that makes the batch faster by more than MARGIN.  Results are cached in a JSON file keyed by
+that makes the batch faster by more than MARGIN (with the same confirmation).  Results are cached in a JSON file keyed by
 class, batch-size bucket and precision, and returned as one segment length per
 instance for lq_plan_create_seg.
 """
@@ -43,36 +45,72 @@ def class_key(n, m, T, count, precision):
     return f"n{n}_m{m}_T{_bucket(T)}_B{_bucket(count)}_{precision}"
 
 
-def _time_forward(lq, prob, sizes, seg, precision, reps, torch):
-    return _time_forward_lens(lq, prob, sizes, [z[2] if seg < 0 else seg for z in sizes], precision, reps, torch)
+# A timed sample repeats the solve until it lasts at least this long, so that
+# classes whose solve takes a few microseconds are not timed at the
+# resolution of a single launch.
+MIN_SAMPLE_MS = 0.5
+# A candidate that beats the default on the medians must also win this many
+# of CONFIRM_PAIRS interleaved head-to-head samples against it.
+CONFIRM_PAIRS = 8
+CONFIRM_WINS = 6
+
+
+class _Timer:
+    """Forward solves (lq_solve) of one plan, timed in samples of `k` calls
+    bracketed by HIP events; ms per call."""
+
+    def __init__(self, lq, prob, sizes, seg_lens, precision, torch):
+        self.torch = torch
+        plan = lq.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], precision=precision,
+                       seg_lens=seg_lens)
+        ws = plan.new_workspace()
+        status = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+        val = lq.value_buffers(plan)
+        st = lq.state_buffers(plan)
+        self._keep = (plan, ws, status, val, st)
+
+        def fwd():
+            lq.lq_solve(plan, prob, None, val, st["x"], st["u"], None, ws, status)
+
+        self.fwd = fwd
+        fwd()
+        torch.cuda.synchronize()
+        one = self.sample(1)
+        self.k = max(1, int(np.ceil(MIN_SAMPLE_MS / max(one, 1e-3))))
+
+    def sample(self, k=None):
+        k = self.k if k is None else k
+        a, b = self.torch.cuda.Event(enable_timing=True), self.torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            self.fwd()
+        b.record()
+        self.torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    def median(self, reps):
+        return float(np.median([self.sample() for _ in range(reps)]))
 
 
 def _time_forward_lens(lq, prob, sizes, seg_lens, precision, reps, torch):
-    plan = lq.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], precision=precision,
-                   seg_lens=seg_lens)
-    ws = plan.new_workspace()
-    status = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
-    val = lq.value_buffers(plan)
-    st = lq.state_buffers(plan)
-
-    def fwd():
-        lq.lq_solve(plan, prob, None, val, st["x"], st["u"], None, ws, status)
-
-    fwd()
-    torch.cuda.synchronize()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    for a, b in ev:
-        a.record()
-        fwd()
-        b.record()
-    torch.cuda.synchronize()
-    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+    return _Timer(lq, prob, sizes, seg_lens, precision, torch).median(reps)
 
 
 def _pick(times: dict, default):
     """The fastest candidate if it beats `default` by more than MARGIN, else `default`."""
     best = min(times, key=times.get)
     return best if times[best] < (1.0 - MARGIN) * times[default] else default
+
+
+def _confirmed(ta: "_Timer", tb: "_Timer") -> bool:
+    """True if b is faster than a in at least CONFIRM_WINS of CONFIRM_PAIRS
+    interleaved samples and by more than MARGIN on their medians."""
+    pa, pb = [], []
+    for _ in range(CONFIRM_PAIRS):
+        pa.append(ta.sample())
+        pb.append(tb.sample())
+    wins = sum(b < a for a, b in zip(pa, pb))
+    return wins >= CONFIRM_WINS and float(np.median(pb)) < (1.0 - MARGIN) * float(np.median(pa))
 
 
 def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDATES, reps=DEFAULT_REPS, cache_path=None,
@@ -107,9 +145,13 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
         sel = members if sample_per_class is None else members[:sample_per_class]
         prob = make_prob(sel)
         sub = [sizes[j] for j in sel]
-        times = {L: _time_forward(lq, prob, sub, L, precision, reps, torch) for L in candidates}
-        del prob
+        timers = {L: _Timer(lq, prob, sub, [z[2] if L < 0 else L for z in sub], precision, torch)
+                  for L in candidates}
+        times = {L: t.median(reps) for L, t in timers.items()}
         best = _pick(times, candidates[0])
+        if best != candidates[0] and not _confirmed(timers[candidates[0]], timers[best]):
+            best = candidates[0]
+        del prob, timers
         choice[(n, m, tb)] = best
         report[key] = {str(k): v for k, v in times.items()}
         cache[key] = {"L": best, "ms": report[key]}
@@ -123,25 +165,28 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
         def seglens(ch):
             return [T if ch[(n, m, _bucket(T))] < 0 else ch[(n, m, _bucket(T))] for n, m, T in sizes]
 
-        def run(ch):
-            return _time_forward_lens(lq, prob, sizes, seglens(ch), precision, reps, torch)
+        def timer(ch):
+            return _Timer(lq, prob, sizes, seglens(ch), precision, torch)
 
-        best_t = run(choice)
+        cur = timer(choice)
+        best_t = cur.median(reps)
         order = sorted(classes, key=lambda k: -sum(sizes[j][2] for j in classes[k]))
         for key3 in order:
             if choice[key3] < 0:
                 continue
             trial = dict(choice)
             trial[key3] = -1
-            t = run(trial)
-            if t < (1.0 - MARGIN) * best_t:
-                best_t, choice = t, trial
+            tt = timer(trial)
+            t = tt.median(reps)
+            if t < (1.0 - MARGIN) * best_t and _confirmed(cur, tt):
+                best_t, choice, cur = t, trial, tt
                 ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
                 cache[ck] = {"L": -1, "ms": cache.get(ck, {}).get("ms", {}), "refined_on_batch": True}
         # and the plain sequential recursion for every class
         allseq = {k: -1 for k in choice}
-        t = run(allseq)
-        if t < (1.0 - MARGIN) * best_t:
+        ta = timer(allseq)
+        t = ta.median(reps)
+        if t < (1.0 - MARGIN) * best_t and _confirmed(cur, ta):
             best_t, choice = t, allseq
             for key3 in classes:
                 ck = class_key(key3[0], key3[1], key3[2], len(classes[key3]), precision)
