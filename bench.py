@@ -469,6 +469,43 @@ def ragged_replay(lqscan, workloads, dev, replays: int) -> dict:
     return res
 
 
+def batch_profile(lqscan, workloads, dev, reps: int) -> dict:
+    """The batched workloads' kernels for counter passes: `reps` eager steps of
+    the differentiated batch (256 x n=12, m=4, T=4096, forward + adjoint) and
+    of the ragged batch's forward solve (4096 instances, default segments),
+    with no tuning or graph capture around them."""
+    import torch
+
+    out = {}
+    sizes = [(12, 4, 4096)] * 256
+    prob = workloads.device_batch(sizes, seed=4, a_scale=0.02, r_fixed=0.1, device=dev)
+    plan = lqscan.Plan([12] * 256, [4] * 256, [4096] * 256)
+    b = solve_buffers(lqscan, plan, dev, grads=True)
+    st, val = b["st"], b["val"]
+    lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+    gx, gu = 2 * st["x"], 2 * st["u"]
+
+    def step():
+        lqscan.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], b["ws"], b["status"])
+        lqscan.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, b["grads"], b["ws"], b["status"])
+
+    out["batch256_T4096_fwd_adj_ms"] = time_eager(step, reps)
+    del b, gx, gu, plan, prob, st, val
+    torch.cuda.empty_cache()
+    _, ns, ms_, Ts = workloads.cfg3_ragged_sizes()
+    order = np.lexsort((Ts, ns))
+    rs = [(int(ns[i]), int(ms_[i]), int(Ts[i])) for i in order]
+    prob = workloads.device_batch(rs, seed=3, a_scale=0.05, device=dev)
+    plan = lqscan.Plan([z[0] for z in rs], [z[1] for z in rs], [z[2] for z in rs])
+    b = solve_buffers(lqscan, plan, dev)
+
+    def fwd():
+        lqscan.lq_solve(plan, prob, None, b["val"], b["st"]["x"], b["st"]["u"], b["st"]["lam"], b["ws"], b["status"])
+
+    out["ragged4096_fwd_ms"] = time_eager(fwd, reps)
+    return out
+
+
 def gap_summary(path: str, split_us: float = 5.0) -> dict:
     """Launch gaps inside graph replays, from a rocprofv3 kernel trace (CSV
     with Kernel_Name, Start_Timestamp, End_Timestamp): the library's
@@ -809,7 +846,7 @@ def main():
     ap.add_argument("--calib", action="store_true",
                     help="also launch one plain copy of 256 MiB (scale reference for HBM counters)")
     ap.add_argument("--section", choices=("paper_ip", "paper_admm", "paper_mpc", "batched", "cfg0", "cfg1",
-                                          "ragged_replay"),
+                                          "ragged_replay", "batch_profile"),
                     default=None, help="run only this section (GPU paths only) and print its JSON")
     ap.add_argument("--only-headline", action="store_true",
                     help="the headline workload only (no mixed-precision, small-case or Newton sections)")
@@ -836,7 +873,8 @@ def main():
               "batched": lambda: batched(lqscan, workloads, dev, max(3, min(args.steps, 10)), False),
               "cfg0": lambda: cfg0_small(lqscan, workloads, dev, args.replays, False),
               "cfg1": lambda: cfg1_newton(lqscan, workloads, 3, False),
-              "ragged_replay": lambda: ragged_replay(lqscan, workloads, dev, max(3, min(args.steps, 10)))}[args.section]
+              "ragged_replay": lambda: ragged_replay(lqscan, workloads, dev, max(3, min(args.steps, 10))),
+              "batch_profile": lambda: batch_profile(lqscan, workloads, dev, max(1, min(args.steps, 10)))}[args.section]
         print(json.dumps({args.section: fn()}))
         return
 
