@@ -382,7 +382,19 @@ enum {
     NMPC_GRAD = 8,        /* |dJ_mu/du|_inf at the nominal the step started from      */
     NMPC_RP = 9,          /* ADMM primal residual |h(u) - z|_inf (nmpc_admm_update)   */
     NMPC_RD = 10,         /* ADMM dual residual |z - z_prev|_inf (nmpc_admm_update)   */
-    NMPC_NSCAL = 11
+    /* Barrier levels ended on the device, so that a caller can enqueue several
+     * newton_step calls (or replay a graph of them) between read-backs: with
+     * LEVEL_TOL > 0 each step counts the level's iterations in LEVEL_ITERS and,
+     * after the iteration that starts from |dJ_mu/du|_inf <= LEVEL_TOL or that
+     * reaches LEVEL_MAX iterations, sets LEVEL_DONE to 0.5; the next step turns
+     * it to 1 and, while it is 1, newton_step leaves the instance unchanged.
+     * The caller sets LEVEL_TOL and LEVEL_MAX and zeroes LEVEL_ITERS and
+     * LEVEL_DONE when it starts a level.  LEVEL_TOL <= 0: no level control. */
+    NMPC_LEVEL_TOL = 11,
+    NMPC_LEVEL_MAX = 12,
+    NMPC_LEVEL_ITERS = 13,
+    NMPC_LEVEL_DONE = 14,
+    NMPC_NSCAL = 15
 };
 
 typedef struct {

@@ -826,6 +826,7 @@ static lqk::NmpcWork nmpc_work(const lq_plan *p, void *workspace)
     Wk.G = D(L.G); Wk.gm = D(L.gm); Wk.dx = D(L.dx); Wk.du = D(L.du); Wk.xc = D(L.xc); Wk.uc = D(L.uc);
     Wk.zero = D(L.zero);
     Wk.status = (int32_t *)(w + L.status);
+    Wk.scal = nullptr;
     return Wk;
 }
 
@@ -853,7 +854,8 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     const lqk::NmpcPtrs N = nmpc_ptrs(p, prob);
-    const lqk::NmpcWork Wk = nmpc_work(p, workspace);
+    lqk::NmpcWork Wk = nmpc_work(p, workspace);
+    Wk.scal = state->scal;
     char *ws = (char *)workspace;
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
     lqk::launch_nmpc_clear(st, N, Wk);

@@ -46,7 +46,8 @@ struct GradPtrs {
 
 // Newton / interior-point: device scalars (indices match include/lqscan.h).
 enum { NMPC_MU = 0, NMPC_ALPHA = 1, NMPC_NU = 2, NMPC_COST = 3, NMPC_PRED = 4, NMPC_RHO = 5,
-       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_RP = 9, NMPC_RD = 10, NMPC_NSCAL = 11 };
+       NMPC_ACCEPTED = 6, NMPC_COST_NEW = 7, NMPC_GRAD = 8, NMPC_RP = 9, NMPC_RD = 10, NMPC_LEVEL_TOL = 11,
+       NMPC_LEVEL_MAX = 12, NMPC_LEVEL_ITERS = 13, NMPC_LEVEL_DONE = 14, NMPC_NSCAL = 15 };
 enum { MODEL_TANH = 0, MODEL_PENDULUM = 1, MODEL_CARTPOLE = 2 };
 
 // A batch of `batch` instances of equal sizes (nx, nu, T): per-instance arrays
@@ -71,7 +72,19 @@ struct NmpcWork {
     double *A, *B, *P, *M, *Rt, *Rh, *d, *th, *g, *lam, *lamT;
     double *S, *s, *G, *gm, *dx, *du, *xc, *uc, *zero;
     int32_t *status;
+    double *scal;   // the state's device scalars (level control), NMPC_NSCAL per instance
 };
+
+// A barrier level of instance b ended on the device (scal[NMPC_LEVEL_DONE] is
+// 0 while it runs, 0.5 after its last iteration, 1 from the next step on):
+// the Newton kernels leave the instance unchanged.  `last_ok` lets the commit
+// of the last iteration itself (0.5) through.
+LQK_DEV bool level_done(const double *scal, int64_t b, bool last_ok = false)
+{
+    if (!scal) return false;
+    const double d = scal[b * NMPC_NSCAL + NMPC_LEVEL_DONE];
+    return last_ok ? (d >= 1.0) : (d >= 0.5);
+}
 
 // First checkpoint slot of instance i when one carry is kept per group of
 // `stride` segments: seg0 / stride + i.  The instance needs

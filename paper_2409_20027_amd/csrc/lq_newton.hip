@@ -171,11 +171,11 @@ LQK_DEV double terminal_cost(const NmpcPtrs &N, int n, int T, const double *xT)
 template <int MODEL, bool DU>
 __global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *__restrict__ u,
                                                      const double *__restrict__ du, double *__restrict__ xout,
-                                                     double *__restrict__ uout)
+                                                     double *__restrict__ uout, const double *lvl)
 {
     constexpr int n = (MODEL == MODEL_PENDULUM) ? 2 : 4;
     const int b = blockIdx.x * 64 + threadIdx.x;
-    if (b >= N.batch) return;
+    if (b >= N.batch || level_done(lvl, b)) return;
     const int T = N.T;
     u += (int64_t)b * T;
     if (DU) du += (int64_t)b * T;
@@ -221,8 +221,9 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *_
 template <int NX, int NU>
 __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
                                                           const double *__restrict__ du, double *__restrict__ xout,
-                                                          double *__restrict__ uout)
+                                                          double *__restrict__ uout, const double *lvl)
 {
+    if (level_done(lvl, blockIdx.x)) return;   // uniform over the block
     constexpr bool FIXED = NX > 0;
     constexpr int XM = FIXED ? NX : NXMAX, UM = FIXED ? NU : NUMAX;
     constexpr int CH = 512;
@@ -294,6 +295,16 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const doub
 __global__ __launch_bounds__(64) void k_nmpc_clear(NmpcPtrs N, NmpcWork Wk)
 {
     const int b = blockIdx.x, n = N.nx;
+    if (Wk.scal) {
+        // the step after a level's last iteration: the level is over (0.5 -> 1)
+        double *sc = Wk.scal + (int64_t)b * NMPC_NSCAL;
+        const double d = sc[NMPC_LEVEL_DONE];
+        __syncthreads();
+        if (d >= 0.5) {
+            if (threadIdx.x == 0) sc[NMPC_LEVEL_DONE] = 1.0;
+            return;
+        }
+    }
     if (threadIdx.x == 0) Wk.status[b] = 0;
     for (int i = threadIdx.x; i < n; i += 64) Wk.zero[(int64_t)b * n + i] = 0.0;
     for (int i = threadIdx.x; i < n * n; i += 64) Wk.QTb[(int64_t)b * n * n + i] = N.QT[i];
@@ -308,6 +319,7 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
     const int n = N.nx, m = N.nu, T = N.T;
     if (idx >= (int64_t)N.batch * (T + 1)) return;
     const int b = (int)(idx / (T + 1)), k = (int)(idx - (int64_t)b * (T + 1));
+    if (level_done(Wk.scal, b)) return;
     const int64_t gk = (int64_t)b * T + k;   // packed stage index (k < T)
     const double *xk = x + ((int64_t)b * (T + 1) + k) * n;
     const double *rk = N.xref + (int64_t)k * n;
@@ -399,7 +411,9 @@ __global__ __launch_bounds__(64) void k_costate_fold(NmpcWork Wk, const InstDesc
 {
     __shared__ double lds[SLOT];
     const int gs = blockIdx.x;
-    const InstDesc d = inst[find_inst(seg_start, batch, gs)];
+    const int i = find_inst(seg_start, batch, gs);
+    if (level_done(Wk.scal, i)) return;
+    const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     if (s == d.nseg - 1) gstore_c(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(Wk.lamT + d.on, d.n, d.n, d.n), d.n + 1);
@@ -416,7 +430,9 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
                                                       const double *__restrict__ Yfin)
 {
     const int gs = blockIdx.x;
-    const InstDesc d = inst[find_inst(seg_start, batch, gs)];
+    const int i = find_inst(seg_start, batch, gs);
+    if (level_done(Wk.scal, i)) return;
+    const InstDesc d = inst[i];
     const int s = gs - d.seg0;
     const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
     const int n = d.n;
@@ -440,6 +456,7 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     const int n = N.nx, m = N.nu, T = N.T;
     if (gk >= (int64_t)N.batch * T) return;
     const int b = (int)(gk / T);
+    if (level_done(Wk.scal, b)) return;
     scal += (int64_t)b * NMPC_NSCAL;
     const double mu = scal[NMPC_MU], alpha = scal[NMPC_ALPHA];
     const double *l1 = Wk.lam + (gk + b + 1) * n;   // lambda_{k+1}; T + 1 rows per instance
@@ -507,6 +524,7 @@ __global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, con
     __shared__ double sp[RB], s0[RB], s1[RB], sg[RB];
     const int t = threadIdx.x, b = blockIdx.x;
     const int n = N.nx, m = N.nu, T = N.T;
+    if (level_done(scal, b)) return;   // uniform over the block
     scal += (int64_t)b * NMPC_NSCAL;
     const int64_t s0k = (int64_t)b * T;              // first packed stage of the instance
     const int64_t xo = (int64_t)b * (T + 1) * n;    // its trajectory rows
@@ -591,6 +609,14 @@ __global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, con
     scal[NMPC_NU] = nu;
     scal[NMPC_RHO] = rho;
     scal[NMPC_ACCEPTED] = acc ? 1.0 : 0.0;
+    // level control: the level ends after the iteration that started from
+    // |d|_inf <= LEVEL_TOL or that used up LEVEL_MAX iterations
+    const double tol = scal[NMPC_LEVEL_TOL];
+    if (tol > 0.0) {
+        const double it = scal[NMPC_LEVEL_ITERS] + 1.0;
+        scal[NMPC_LEVEL_ITERS] = it;
+        if (sg[0] <= tol || it >= scal[NMPC_LEVEL_MAX]) scal[NMPC_LEVEL_DONE] = 0.5;
+    }
 }
 
 // ADMM consensus and multiplier steps of Sec. II-C (eq:admm-step-4, -5) for
@@ -643,6 +669,7 @@ __global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork 
                                                      const double *scal)
 {
     const int b = blockIdx.y;
+    if (level_done(scal, b, true)) return;   // the level's last iteration (0.5) still commits
     if (scal[(int64_t)b * NMPC_NSCAL + NMPC_ACCEPTED] == 0.0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nx = (int64_t)(N.T + 1) * N.nx, nu = (int64_t)N.T * N.nu;
@@ -674,16 +701,16 @@ __global__ __launch_bounds__(64) void k_nmpc_shift(NmpcPtrs N, double *x0, doubl
 
 
 static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, const double *du, double *xout,
-                           double *uout)
+                           double *uout, const double *lvl)
 {
     const unsigned lanes = (unsigned)((N.batch + 63) / 64);
-#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(lanes), dim3(64), 0, st, N, u, du, xout, uout)
+#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(lanes), dim3(64), 0, st, N, u, du, xout, uout, lvl)
     if (N.model == MODEL_PENDULUM) {
         if (du) RL(MODEL_PENDULUM, true); else RL(MODEL_PENDULUM, false);
     } else if (N.model == MODEL_CARTPOLE) {
         if (du) RL(MODEL_CARTPOLE, true); else RL(MODEL_CARTPOLE, false);
     } else {
-#define RT(X, U) hipLaunchKernelGGL((k_nmpc_rollout_tanh<X, U>), dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout)
+#define RT(X, U) hipLaunchKernelGGL((k_nmpc_rollout_tanh<X, U>), dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout, lvl)
         if (N.nx <= 4) {
             switch (N.nx * 8 + N.nu) {
             case 9: RT(1, 1); break;  case 10: RT(1, 2); break; case 11: RT(1, 3); break; case 12: RT(1, 4); break;
@@ -700,7 +727,7 @@ static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, c
 }
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
 {
-    launch_rollout(st, N, u, nullptr, x, nullptr);
+    launch_rollout(st, N, u, nullptr, x, nullptr, nullptr);
 }
 void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk)
 {
@@ -744,7 +771,7 @@ void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, c
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
-    launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc);
+    launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc, Wk.scal);
     if (N.T <= 96)
         hipLaunchKernelGGL(k_nmpc_reduce<64>, dim3(N.batch), dim3(64), 0, st, N, Wk, x, u, scal);
     else if (N.T <= 384)

@@ -477,7 +477,7 @@ def solve_diff(plan: Plan, A, B, c, Q, R, QT, x0, M=None, q=None, r=None, qT=Non
 # ---------------------------------------------------------------------------
 
 (NMPC_MU, NMPC_ALPHA, NMPC_NU, NMPC_COST, NMPC_PRED, NMPC_RHO, NMPC_ACCEPTED, NMPC_COST_NEW, NMPC_GRAD,
- NMPC_RP, NMPC_RD, NMPC_NSCAL) = range(12)
+ NMPC_RP, NMPC_RD, NMPC_LEVEL_TOL, NMPC_LEVEL_MAX, NMPC_LEVEL_ITERS, NMPC_LEVEL_DONE, NMPC_NSCAL) = range(16)
 NMPC_TANH, NMPC_PENDULUM, NMPC_CARTPOLE = 0, 1, 2
 
 
@@ -538,12 +538,14 @@ class NewtonMPC:
     param (the model constants); W and Bm are read by the tanh model only.
     A batch of problems that differ only in x0 ([B, nx]) and u0 ([B, T, nu])
     is solved at once (every decision per instance).  All iterations run on
-    the GPU through newton_step; the host sets the barrier weight and, in
-    ip_solve / admm_solve, reads the gradient norms after each iteration to end
-    a barrier level (when every instance has converged).
+    the GPU through newton_step; the host sets the barrier weight.  In
+    ip_solve / admm_solve a barrier level ends on the device (the NMPC_LEVEL_*
+    scalars of newton_step): a captured graph of `level_chunk` steps is
+    replayed and the scalars are read back once per replay (eager, graph=False:
+    one step and one read-back per iteration, the level ended by the host).
     """
 
-    def __init__(self, p, device="cuda", seg_len=0, precision="fp64", mode="scan"):
+    def __init__(self, p, device="cuda", seg_len=0, precision="fp64", mode="scan", level_chunk=4):
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
         self.p = p
         model = int(getattr(p, "model", NMPC_TANH) or 0)
@@ -568,6 +570,10 @@ class NewtonMPC:
         self.u = self.u0.clone()
         self.scal = torch.zeros(B * NMPC_NSCAL, dtype=torch.float64, device=device)
         self._sc = self.scal.view(B, NMPC_NSCAL)
+        self.level_chunk = max(1, int(level_chunk))
+        # per-step copies of the scalars inside a replayed chunk, and their host mirror
+        self._hist = torch.zeros(self.level_chunk, B * NMPC_NSCAL, dtype=torch.float64, device=device)
+        self._hist_host = torch.empty(self.level_chunk, B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
         self.ws = torch.empty(nmpc_workspace_bytes(self.plan), dtype=torch.uint8, device=device)
         d = self.dev
         prm = getattr(p, "param", None)
@@ -628,8 +634,29 @@ class NewtonMPC:
         torch.cuda.current_stream().wait_stream(side)
         return g
 
+    def _capture_chunk(self, k):
+        """k <= level_chunk newton_step calls captured into one HIP graph, each followed
+        by a copy of the device scalars into its slot of self._hist; returns (graph, k).
+        One eager step first (the state is reset afterwards by init)."""
+        k = max(1, min(int(k), self.level_chunk))
+        newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.graph(g, stream=side):
+            for j in range(k):
+                newton_step(self.plan, self.prob_c, self.state_c, self.ws)
+                self._hist[j].copy_(self.scal)
+        torch.cuda.current_stream().wait_stream(side)
+        return g, k
+
     def _newton_level(self, mu, tol, max_iter, host, rows, graph=None):
-        """Newton iterations until the one that starts from |dJ/du|_inf <= tol (or max_iter)."""
+        """Newton iterations until the one that starts from |dJ/du|_inf <= tol (or
+        max_iter).  With a chunk graph (_capture_chunk) the level ends on the
+        device and the host reads the scalars back once per replay of
+        level_chunk steps; eagerly, once per step."""
+        if isinstance(graph, tuple):
+            return self._newton_level_device(mu, tol, max_iter, rows, graph)
         li = 0
         hv = host.view(self.B, NMPC_NSCAL)
         while li < max_iter:
@@ -648,6 +675,29 @@ class NewtonMPC:
                 break
         return li
 
+    def _newton_level_device(self, mu, tol, max_iter, rows, graph):
+        graph, k = graph
+        cols = [NMPC_MU, NMPC_LEVEL_TOL, NMPC_LEVEL_MAX, NMPC_LEVEL_ITERS, NMPC_LEVEL_DONE]
+        self._sc[:, cols] = torch.tensor([mu, tol, float(max_iter), 0.0, 0.0], dtype=torch.float64,
+                                         device=self.scal.device)
+        hist = self._hist_host[:k].view(k, self.B, NMPC_NSCAL)
+        seen = 0
+        while True:
+            graph.replay()
+            self._hist_host[:k].copy_(self._hist[:k], non_blocking=True)
+            torch.cuda.current_stream().synchronize()
+            for j in range(k):
+                it = int(hist[j, 0, NMPC_LEVEL_ITERS])
+                if it > seen:
+                    seen = it
+                    if rows is not None:
+                        r = hist[j, 0]
+                        rows.append((mu, float(r[NMPC_COST]), float(r[NMPC_GRAD]), float(r[NMPC_ACCEPTED]),
+                                     float(r[NMPC_PRED])))
+            if bool((hist[-1, :, NMPC_LEVEL_DONE] >= 0.5).all()):
+                break
+        return int(hist[-1, :, NMPC_LEVEL_ITERS].max())
+
     def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True):
         """ADMM of Sec. II-C for the control box with newton_step as the inner solver:
         z = min(0, h(u0)), v = 0; repeat Newton iterations on J_AD to |dJ_AD/du|_inf <= tol
@@ -662,6 +712,9 @@ class NewtonMPC:
         self.prob_c.admm_z = _f64(z)
         self.prob_c.admm_v = _f64(v)
         try:
+            # ADMM's inner levels average two to three Newton iterations: one step per
+            # read-back with the level ended by the host (steps past a level's end
+            # would cost more than the read-backs they save)
             g = self._capture_step() if graph else None
             self.init(alpha0, nu0)
             nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
@@ -725,12 +778,13 @@ class NewtonMPC:
         mu = mu0, mu0 zeta, ... while mu > mu_min; a level ends after the iteration
         that starts from |dJ_mu/du|_inf <= tol, or after max_iter iterations.
 
-        The gradient norm of each iteration is read back (one small device-to-host
-        copy per iteration, into pinned memory).  graph: replay newton_step from a HIP
-        graph captured once per solve.  Returns dict(u, x, iters, level_iters, and with
-        trace the per-iteration mu, cost, grad, accept, pred).
+        graph: the level ends on the device and a HIP graph of level_chunk steps,
+        captured once per solve, is replayed with one device-to-host copy of the
+        scalars per replay (into pinned memory); eagerly (graph=False) the gradient
+        norm is read back after every step.  Returns dict(u, x, iters, level_iters,
+        and with trace the per-iteration mu, cost, grad, accept, pred).
         """
-        g = self._capture_step() if graph else None
+        g = self._capture_chunk(self.level_chunk) if graph else None
         self.init(alpha0, nu0)
         host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
         rows, level_iters = ([] if trace else None), []

@@ -270,3 +270,44 @@ def test_mpc_simulation_matches_oracle(lq, name, B, steps):
         worst = max(worst, rel(got["x"][b], ref["x"]), rel(got["u"][b], ref["u"]))
     print(f"{name}: closed-loop rel diff {worst:.1e}")
     assert worst < 1e-6
+
+
+@pytest.mark.parametrize("chunk", [2, 3, 7])
+def test_device_level_control_equals_host_levels(lq, chunk):
+    """ip_solve with the barrier levels ended on the device (graph chunks of 2, 3
+    and 7 newton_step calls per read-back, so that levels end inside, at the end
+    of and well before the end of a chunk) equals the eager solve, whose levels
+    the host ends after every step, bit for bit: the steps past a level's end
+    leave the instance unchanged."""
+    p = MODELS["pendulum"](60)
+    args = dict(mu0=W.IP_MU0, zeta=W.IP_ZETA, mu_min=W.IP_MU_MIN, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    e = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN).ip_solve(**args, graph=False)
+    g = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN, level_chunk=chunk).ip_solve(**args, graph=True)
+    assert np.array_equal(e["level_iters"], g["level_iters"])
+    assert np.array_equal(e["cost"], g["cost"]) and np.array_equal(e["accept"], g["accept"])
+    assert np.array_equal(e["u"], g["u"]) and np.array_equal(e["x"], g["x"])
+
+
+def test_step_after_a_finished_level_is_a_no_op(lq):
+    """newton_step with level control: a tolerance every nominal meets ends the
+    level after one iteration (LEVEL_DONE = 0.5, LEVEL_ITERS = 1); the next two
+    steps change neither the trajectory nor any scalar but LEVEL_DONE (0.5 -> 1)."""
+    p = MODELS["cartpole"](50)
+    s = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN)
+    s.init(W.NMPC_ALPHA0, W.NMPC_NU0)
+    s._sc[:, lq.NMPC_MU] = W.IP_MU0
+    s._sc[:, lq.NMPC_LEVEL_TOL] = 1e300
+    s._sc[:, lq.NMPC_LEVEL_MAX] = 100.0
+    lq.newton_step(s.plan, s.prob_c, s.state_c, s.ws)
+    torch.cuda.synchronize()
+    sc1, x1, u1 = s.scal.cpu().numpy().copy(), s.x.cpu().numpy().copy(), s.u.cpu().numpy().copy()
+    assert sc1[lq.NMPC_LEVEL_DONE] == 0.5 and sc1[lq.NMPC_LEVEL_ITERS] == 1.0
+    for _ in range(2):
+        lq.newton_step(s.plan, s.prob_c, s.state_c, s.ws)
+    torch.cuda.synchronize()
+    sc2 = s.scal.cpu().numpy()
+    assert sc2[lq.NMPC_LEVEL_DONE] == 1.0
+    keep = [i for i in range(lq.NMPC_NSCAL) if i != lq.NMPC_LEVEL_DONE]
+    assert np.array_equal(sc1[keep], sc2[keep])
+    assert np.array_equal(s.x.cpu().numpy(), x1) and np.array_equal(s.u.cpu().numpy(), u1)
