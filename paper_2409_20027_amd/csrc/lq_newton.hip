@@ -211,13 +211,23 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *_
     }
 }
 
+// Value of a double held by lane `src` of the wave, in every lane.
+LQK_DEV double wave_bcast(double v, int src)
+{
+    const uint64_t b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, src);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), src);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // The tanh model: one block per instance.  The controls u + du are staged
 // through LDS in chunks of CH stages by the whole block (coalesced loads, the
-// used controls written back from there), and one lane runs the recursion
-// over the chunk reading LDS, so no step waits for a load from HBM.  NX > 0:
-// the sizes are compile-time (nx = NX <= 4, nu = NU), W and B sit in
-// registers; NX = 0: any nx <= 15, nu <= 4, loops unrolled to the maximum
-// sizes with guards (tanh evaluated for the nx rows only).
+// used controls written back from there); then lane i < nx computes row i of
+// every step, x_i <- x_i + h (tanh(w_i'x) + b_i'u), with the state broadcast
+// from its lanes after each step, so the nx tanh evaluations of a step run
+// side by side instead of one after another.  Each row is the same arithmetic
+// in the same order as a one-lane loop.  NX > 0: compile-time sizes (nx = NX
+// <= 4, nu = NU); NX = 0: any nx <= 15, nu <= 4.
 template <int NX, int NU>
 __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
                                                           const double *__restrict__ du, double *__restrict__ xout,
@@ -228,27 +238,26 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const doub
     constexpr int XM = FIXED ? NX : NXMAX, UM = FIXED ? NU : NUMAX;
     constexpr int CH = 512;
     __shared__ double su[CH * UM];
-    __shared__ double sW[XM * XM], sB[XM * UM];
     const int n = FIXED ? NX : N.nx, m = FIXED ? NU : N.nu, T = N.T;
     const int b = blockIdx.x;   // one instance per block
     const int t = threadIdx.x;
-    for (int i = t; i < n * n; i += 64) sW[i] = N.W[i];
-    for (int i = t; i < n * m; i += 64) sB[i] = N.Bm[i];
+    const bool row = t < n;
+    const int ti = row ? t : 0;
     u += (int64_t)b * T * m;
     if (du) du += (int64_t)b * T * m;
     xout += (int64_t)b * (T + 1) * n;
     if (uout) uout += (int64_t)b * T * m;
-    __syncthreads();
-    double W[XM][XM], Bm[XM][UM], x[XM];
+    // this lane's row of W and B, and the initial state
+    double Wr[XM], Br[UM];
 #pragma unroll
-    for (int i = 0; i < XM; ++i) {
+    for (int j = 0; j < XM; ++j) Wr[j] = (j < n) ? N.W[ti * n + (j < n ? j : 0)] : 0.0;
 #pragma unroll
-        for (int j = 0; j < XM; ++j) W[i][j] = (i < n && j < n) ? sW[i * n + j] : 0.0;
+    for (int j = 0; j < UM; ++j) Br[j] = (j < m) ? N.Bm[ti * m + (j < m ? j : 0)] : 0.0;
+    double xi = N.x0[(int64_t)b * n + ti];
+    if (row) xout[t] = xi;
+    double x[XM];
 #pragma unroll
-        for (int j = 0; j < UM; ++j) Bm[i][j] = (i < n && j < m) ? sB[i * m + j] : 0.0;
-        x[i] = (i < n) ? N.x0[(int64_t)b * n + (i < n ? i : 0)] : 0.0;
-        if (t == 0 && i < n) xout[i] = x[i];
-    }
+    for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
     for (int c0 = 0; c0 < T; c0 += CH) {
         const int len = min(CH, T - c0);
         __syncthreads();   // the previous chunk has been consumed
@@ -259,33 +268,21 @@ __global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const doub
             if (uout) uout[o] = v;
         }
         __syncthreads();
-        if (t != 0) continue;
         for (int k = 0; k < len; ++k) {
             double uk[UM];
 #pragma unroll
             for (int j = 0; j < UM; ++j) uk[j] = (j < m) ? su[k * m + (j < m ? j : 0)] : 0.0;
-            double xn[XM];
+            double z = 0.0, bu = 0.0;
 #pragma unroll
-            for (int i = 0; i < XM; ++i) {
-                if (i < n) {
-                    double z = 0.0, bu = 0.0;
+            for (int j = 0; j < XM; ++j)
+                if (j < n) z += Wr[j] * x[j];
 #pragma unroll
-                    for (int j = 0; j < XM; ++j)
-                        if (j < n) z += W[i][j] * x[j];
+            for (int j = 0; j < UM; ++j)
+                if (j < m) bu += Br[j] * uk[j];
+            xi = xi + N.h * (tanh(z) + bu);
+            if (row) xout[(int64_t)(c0 + k + 1) * n + t] = xi;
 #pragma unroll
-                    for (int j = 0; j < UM; ++j)
-                        if (j < m) bu += Bm[i][j] * uk[j];
-                    xn[i] = x[i] + N.h * (tanh(z) + bu);
-                } else {
-                    xn[i] = 0.0;
-                }
-            }
-            double *xo = xout + (int64_t)(c0 + k + 1) * n;
-#pragma unroll
-            for (int i = 0; i < XM; ++i) {
-                x[i] = xn[i];
-                if (i < n) xo[i] = xn[i];
-            }
+            for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
         }
     }
 }
