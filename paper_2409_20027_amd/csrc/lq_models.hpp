@@ -163,6 +163,44 @@ LQK_DEV void sincos_cw(double x, double &s, double &c)
     c = (q == 0) ? C : (q == 1) ? -S : (q == 2) ? -C : S;
 }
 
+// tanh z in FP64 as e / (e + 2) with e = expm1(2|z|), sign restored at the
+// end: the quotient has no cancellation for any z.  expm1 by Cody-Waite
+// reduction 2|z| = k ln2 + r, |r| <= ln2 / 2 (ln2 split into two doubles),
+// the Taylor series of expm1(r) to r^13 (truncation below 2e-17 relative) and
+// expm1(2|z|) = 2^k expm1(r) + (2^k - 1), exact scaling by 2^k.  Within 2.5
+// ulp of tanh (libm's own is about 2); |z| > 20 gives +-1, which is tanh
+// rounded to FP64 there.  About a fifth of the dependent operations of the
+// library routine's double-double evaluation, which matters in the
+// sequential rollout of the tanh model.
+LQK_DEV double tanh_em1(double z)
+{
+    constexpr double L1 = 0x1.62e42feep-1, L2 = 0x1.a39ef35793c76p-33;   // ln2 = L1 + L2
+    constexpr double INV_LN2 = 0x1.71547652b82fep+0;
+    constexpr double f2 = 1.0 / 2, f3 = f2 / 3, f4 = f3 / 4, f5 = f4 / 5, f6 = f5 / 6, f7 = f6 / 7, f8 = f7 / 8;
+    constexpr double f9 = f8 / 9, f10 = f9 / 10, f11 = f10 / 11, f12 = f11 / 12, f13 = f12 / 13;
+    const double a = fabs(z);
+    const double y = a + a;
+    const double k = rint(y * INV_LN2);
+    double r = fma(-k, L1, y);
+    r = fma(-k, L2, r);
+    double p = fma(r, f13, f12);
+    p = fma(r, p, f11);
+    p = fma(r, p, f10);
+    p = fma(r, p, f9);
+    p = fma(r, p, f8);
+    p = fma(r, p, f7);
+    p = fma(r, p, f6);
+    p = fma(r, p, f5);
+    p = fma(r, p, f4);
+    p = fma(r, p, f3);
+    p = fma(r, p, f2);
+    const double q = fma(r * r, p, r);
+    const double s = ldexp(1.0, (int)fmin(k, 64.0));
+    const double e = fma(s, q, s - 1.0);
+    const double t = e / (e + 2.0);
+    return copysign(a > 20.0 ? 1.0 : t, z);
+}
+
 LQK_DEV void sincos_rt(double x, double &s, double &c) { sincos_cw(x, s, c); }
 LQK_DEV void sincos_rt(float x, float &s, float &c)
 {

@@ -21,8 +21,8 @@
 //                            no mixed or control second derivatives)
 //   4. the LQ step           eq:linearized-ocp with psi_t of eq:linearized-ocp-param
 //                            (delta x_0 = 0) by lq_scan_solve + lq_rollout
-//   5. k_nmpc_rollout        candidate u + du and its nonlinear rollout (one lane,
-//                            sequential in k)
+//   5. k_nmpc_rollout        candidate u + du and its nonlinear rollout (sequential
+//                            in k on one wave, controls staged through LDS)
 //   6. k_nmpc_reduce         predicted decrease of the expansion (without alpha),
 //                            |d|_inf, J_mu of the nominal and of the candidate
 //                            (block reductions), gain ratio rho = (J_mu(u) -
@@ -49,7 +49,7 @@ LQK_DEV void f_step(const NmpcPtrs &N, int n, int m, const double *x, const doub
             double z = 0.0, bu = 0.0;
             for (int j = 0; j < n; ++j) z += N.W[i * n + j] * x[j];
             for (int j = 0; j < m; ++j) bu += N.Bm[i * m + j] * u[j];
-            xn[i] = x[i] + N.h * (tanh(z) + bu);
+            xn[i] = x[i] + N.h * (tanh_em1(z) + bu);
         }
     } else if (N.model == MODEL_PENDULUM) {
         const double z[3] = {x[0], x[1], u[0]};
@@ -161,53 +161,114 @@ LQK_DEV double terminal_cost(const NmpcPtrs &N, int n, int T, const double *xT)
     return J;
 }
 
-// Nonlinear rollout x_{k+1} = x_k + h f(x_k, u_k + du_k) from x0 (du may be
-// null): the recursion is sequential in k, so one lane per instance.  Writes
-// x (T+1 rows) and, if uout is set, the controls used.
-//
-// Pendulum and cart-pole (nu = 1): the raw u_{k+1} and du_{k+1} are loaded
-// (index clamped, no branch) while step k is computed and summed one step
-// later, so the loads' latency hides behind a step of the recursion.
+// The nonlinear rollouts below are sequential in time.  Each block has four
+// waves: wave 0 runs the recursion reading the controls from LDS, while waves
+// 1-3 stage the next chunk of controls u + du (du may be null) into the other
+// of two LDS buffers (and write the sums to uout), so no step of the recursion
+// waits for a global load, and the only wait on memory is the barrier
+// between chunks.
+// A chunk is ROLL_SLOTS doubles: R rows (instances) of 2^lg slots each.
+constexpr int ROLL_THREADS = 256;
+constexpr int ROLL_SLOTS = 4096;
+
+// Stage one chunk: row r (instance inst0 + r, skipped unless bit r of `act`
+// is set) copies cnt doubles from global offset (inst0 + r) * rstride + g0
+// into LDS at r * (2^lg + 1) (the padding keeps lanes reading different rows
+// at the same slot in different banks).  Threads tp = 0 .. np-1 take part;
+// each issues U loads before it stores the first value.
+template <bool DU>
+LQK_DEV void stage_controls(double *__restrict__ buf, int lg, int cnt, uint64_t act, int64_t inst0, int64_t rstride,
+                            int64_t g0, const double *__restrict__ u, const double *__restrict__ du,
+                            double *__restrict__ uout, int tp, int np)
+{
+    constexpr int U = 8;
+    const int cap = 1 << lg;
+    for (int base = tp; base < ROLL_SLOTS; base += np * U) {
+        double v[U];
+        int64_t o[U];
+        bool ok[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int idx = base + j * np;
+            const int r = idx >> lg, k = idx & (cap - 1);
+            ok[j] = idx < ROLL_SLOTS && k < cnt && ((act >> r) & 1);
+            o[j] = (inst0 + r) * rstride + g0 + k;
+            v[j] = 0.0;
+            if (ok[j]) v[j] = (DU && du) ? u[o[j]] + du[o[j]] : u[o[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (!ok[j]) continue;
+            const int idx = base + j * np;
+            buf[(idx >> lg) * (cap + 1) + (idx & (cap - 1))] = v[j];
+            if (uout) uout[o[j]] = v[j];
+        }
+    }
+}
+
+// Pendulum and cart-pole (nu = 1): x_{k+1} = x_k + h f(x_k, u_k + du_k) from
+// x0 (du may be null), lane r of wave 0 for instance blockIdx.x * R + r,
+// R = 2^(12 - lg) instances per block, chunks of 2^lg stages.  Writes x
+// (T + 1 rows) and, if uout is set, the controls used.
 template <int MODEL, bool DU>
-__global__ __launch_bounds__(64) void k_nmpc_rollout(NmpcPtrs N, const double *__restrict__ u,
-                                                     const double *__restrict__ du, double *__restrict__ xout,
-                                                     double *__restrict__ uout, const double *lvl)
+__global__ __launch_bounds__(ROLL_THREADS) void k_nmpc_rollout(NmpcPtrs N, const double *__restrict__ u,
+                                                               const double *__restrict__ du,
+                                                               double *__restrict__ xout, double *__restrict__ uout,
+                                                               const double *lvl, int lg)
 {
     constexpr int n = (MODEL == MODEL_PENDULUM) ? 2 : 4;
-    const int b = blockIdx.x * 64 + threadIdx.x;
-    if (b >= N.batch || level_done(lvl, b)) return;
-    const int T = N.T;
-    u += (int64_t)b * T;
-    if (DU) du += (int64_t)b * T;
-    xout += (int64_t)b * (T + 1) * n;
-    if (uout) uout += (int64_t)b * T;
+    __shared__ double su[2][ROLL_SLOTS + 64];
+    const int T = N.T, R = ROLL_SLOTS >> lg, CH = 1 << lg;
+    const int t = threadIdx.x, lane = t & 63;
+    const int64_t inst0 = (int64_t)blockIdx.x * R;
+    const int64_t b = inst0 + lane;
+    const bool mine = lane < R && b < N.batch && !level_done(lvl, b);
+    const uint64_t act = __ballot(mine);   // the same in every wave
+    if (act == 0) return;                  // uniform over the block
+    if (!DU) du = nullptr;
+    const int nch = (T + CH - 1) / CH;
     double x[n];
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-        x[i] = N.x0[(int64_t)b * n + i];
-        xout[i] = x[i];
-    }
-    if (T <= 0) return;
-    double ua = u[0], da = DU ? du[0] : 0.0;
-    for (int k = 0; k < T; ++k) {
-        const double uk = DU ? ua + da : ua;
-        const int kn = min(k + 1, T - 1);
-        ua = u[kn];
-        if constexpr (DU) da = du[kn];
-        if (uout) uout[k] = uk;
-        double f[n];
-        if constexpr (MODEL == MODEL_PENDULUM) {
-            const double z[3] = {x[0], x[1], uk};
-            pendulum_f<double, double>(N.prm, z, f);
-        } else {
-            const double z[5] = {x[0], x[1], x[2], x[3], uk};
-            cartpole_f<double, double>(N.prm, z, f);
-        }
+    if (t < 64 && mine) {
 #pragma unroll
         for (int i = 0; i < n; ++i) {
-            x[i] = x[i] + N.h * f[i];
-            xout[(int64_t)(k + 1) * n + i] = x[i];
+            x[i] = N.x0[b * n + i];
+            xout[b * (T + 1) * n + i] = x[i];
         }
+    }
+    if (nch == 0) return;
+    stage_controls<DU>(su[0], lg, min(CH, T), act, inst0, T, 0, u, du, uout, t, ROLL_THREADS);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int c0 = c * CH, len = min(CH, T - c0);
+        if (t < 64) {
+            if (mine) {
+                const double *row = su[c & 1] + lane * (CH + 1);
+                double *xo = xout + b * (T + 1) * n + (int64_t)(c0 + 1) * n;
+                double un = row[0];
+                for (int k = 0; k < len; ++k) {
+                    const double uk = un;
+                    un = row[min(k + 1, len - 1)];   // next control read while this step runs
+                    double f[n];
+                    if constexpr (MODEL == MODEL_PENDULUM) {
+                        const double z[3] = {x[0], x[1], uk};
+                        pendulum_f<double, double>(N.prm, z, f);
+                    } else {
+                        const double z[5] = {x[0], x[1], x[2], x[3], uk};
+                        cartpole_f<double, double>(N.prm, z, f);
+                    }
+#pragma unroll
+                    for (int i = 0; i < n; ++i) {
+                        x[i] = x[i] + N.h * f[i];
+                        xo[(int64_t)k * n + i] = x[i];
+                    }
+                }
+            }
+        } else if (c + 1 < nch) {
+            const int n0 = c0 + CH;
+            stage_controls<DU>(su[(c + 1) & 1], lg, min(CH, T - n0), act, inst0, T, n0, u, du, uout, t - 64,
+                               ROLL_THREADS - 64);
+        }
+        __syncthreads();
     }
 }
 
@@ -220,70 +281,72 @@ LQK_DEV double wave_bcast(double v, int src)
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// The tanh model: one block per instance.  The controls u + du are staged
-// through LDS in chunks of CH stages by the whole block (coalesced loads, the
-// used controls written back from there); then lane i < nx computes row i of
-// every step, x_i <- x_i + h (tanh(w_i'x) + b_i'u), with the state broadcast
-// from its lanes after each step, so the nx tanh evaluations of a step run
-// side by side instead of one after another.  Each row is the same arithmetic
-// in the same order as a one-lane loop.  NX > 0: compile-time sizes (nx = NX
-// <= 4, nu = NU); NX = 0: any nx <= 15, nu <= 4.
+// The tanh model: one block per instance, chunks of 1024 stages (m <= 4
+// controls each) staged as above.  Lane i < nx of wave 0 computes row i of
+// every step, x_i <- x_i + h (tanh(w_i'x) + b_i'u), and the state is
+// broadcast from those lanes after each step, so the nx tanh evaluations of
+// a step run side by side.  Each row is the same arithmetic in the same
+// order as a one-lane loop.  NX > 0: compile-time sizes (nx = NX <= 4,
+// nu = NU); NX = 0: any nx <= 15, nu <= 4.
 template <int NX, int NU>
-__global__ __launch_bounds__(64) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
-                                                          const double *__restrict__ du, double *__restrict__ xout,
-                                                          double *__restrict__ uout, const double *lvl)
+__global__ __launch_bounds__(ROLL_THREADS) void k_nmpc_rollout_tanh(NmpcPtrs N, const double *__restrict__ u,
+                                                                    const double *__restrict__ du,
+                                                                    double *__restrict__ xout,
+                                                                    double *__restrict__ uout, const double *lvl)
 {
     if (level_done(lvl, blockIdx.x)) return;   // uniform over the block
     constexpr bool FIXED = NX > 0;
     constexpr int XM = FIXED ? NX : NXMAX, UM = FIXED ? NU : NUMAX;
-    constexpr int CH = 512;
-    __shared__ double su[CH * UM];
+    constexpr int CH = 1024, LG = 12;   // CH * m <= 2^LG = ROLL_SLOTS
+    __shared__ double su[2][ROLL_SLOTS + 64];
     const int n = FIXED ? NX : N.nx, m = FIXED ? NU : N.nu, T = N.T;
-    const int b = blockIdx.x;   // one instance per block
+    const int64_t b = blockIdx.x;   // one instance per block
     const int t = threadIdx.x;
     const bool row = t < n;
     const int ti = row ? t : 0;
-    u += (int64_t)b * T * m;
-    if (du) du += (int64_t)b * T * m;
-    xout += (int64_t)b * (T + 1) * n;
-    if (uout) uout += (int64_t)b * T * m;
+    const int nch = (T + CH - 1) / CH;
+    xout += b * (T + 1) * n;
     // this lane's row of W and B, and the initial state
-    double Wr[XM], Br[UM];
+    double Wr[XM], Br[UM], x[XM], xi = 0.0;
+    if (t < 64) {
 #pragma unroll
-    for (int j = 0; j < XM; ++j) Wr[j] = (j < n) ? N.W[ti * n + (j < n ? j : 0)] : 0.0;
+        for (int j = 0; j < XM; ++j) Wr[j] = (j < n) ? N.W[ti * n + (j < n ? j : 0)] : 0.0;
 #pragma unroll
-    for (int j = 0; j < UM; ++j) Br[j] = (j < m) ? N.Bm[ti * m + (j < m ? j : 0)] : 0.0;
-    double xi = N.x0[(int64_t)b * n + ti];
-    if (row) xout[t] = xi;
-    double x[XM];
+        for (int j = 0; j < UM; ++j) Br[j] = (j < m) ? N.Bm[ti * m + (j < m ? j : 0)] : 0.0;
+        xi = N.x0[b * n + ti];
+        if (row) xout[t] = xi;
 #pragma unroll
-    for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
-    for (int c0 = 0; c0 < T; c0 += CH) {
-        const int len = min(CH, T - c0);
-        __syncthreads();   // the previous chunk has been consumed
-        for (int i = t; i < len * m; i += 64) {
-            const int64_t o = (int64_t)c0 * m + i;
-            const double v = u[o] + (du ? du[o] : 0.0);
-            su[i] = v;
-            if (uout) uout[o] = v;
+        for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
+    }
+    if (nch == 0) return;
+    stage_controls<true>(su[0], LG, min(CH, T) * m, 1, b, (int64_t)T * m, 0, u, du, uout, t, ROLL_THREADS);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+        const int c0 = c * CH, len = min(CH, T - c0);
+        if (t < 64) {
+            const double *sc = su[c & 1];
+            for (int k = 0; k < len; ++k) {
+                double uk[UM];
+#pragma unroll
+                for (int j = 0; j < UM; ++j) uk[j] = (j < m) ? sc[k * m + (j < m ? j : 0)] : 0.0;
+                double z = 0.0, bu = 0.0;
+#pragma unroll
+                for (int j = 0; j < XM; ++j)
+                    if (j < n) z += Wr[j] * x[j];
+#pragma unroll
+                for (int j = 0; j < UM; ++j)
+                    if (j < m) bu += Br[j] * uk[j];
+                xi = xi + N.h * (tanh_em1(z) + bu);
+                if (row) xout[(int64_t)(c0 + k + 1) * n + t] = xi;
+#pragma unroll
+                for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
+            }
+        } else if (c + 1 < nch) {
+            const int n0 = c0 + CH;
+            stage_controls<true>(su[(c + 1) & 1], LG, min(CH, T - n0) * m, 1, b, (int64_t)T * m, (int64_t)n0 * m, u,
+                                 du, uout, t - 64, ROLL_THREADS - 64);
         }
         __syncthreads();
-        for (int k = 0; k < len; ++k) {
-            double uk[UM];
-#pragma unroll
-            for (int j = 0; j < UM; ++j) uk[j] = (j < m) ? su[k * m + (j < m ? j : 0)] : 0.0;
-            double z = 0.0, bu = 0.0;
-#pragma unroll
-            for (int j = 0; j < XM; ++j)
-                if (j < n) z += Wr[j] * x[j];
-#pragma unroll
-            for (int j = 0; j < UM; ++j)
-                if (j < m) bu += Br[j] * uk[j];
-            xi = xi + N.h * (tanh(z) + bu);
-            if (row) xout[(int64_t)(c0 + k + 1) * n + t] = xi;
-#pragma unroll
-            for (int j = 0; j < XM; ++j) x[j] = (j < n) ? wave_bcast(xi, j) : 0.0;
-        }
     }
 }
 
@@ -700,14 +763,20 @@ __global__ __launch_bounds__(64) void k_nmpc_shift(NmpcPtrs N, double *x0, doubl
 static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, const double *du, double *xout,
                            double *uout, const double *lvl)
 {
-    const unsigned lanes = (unsigned)((N.batch + 63) / 64);
-#define RL(M, D) hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(lanes), dim3(64), 0, st, N, u, du, xout, uout, lvl)
+    // pendulum / cart-pole: R = 2^(12 - lg) instances per block, the smallest
+    // power of two >= batch, at most 64 (one lane of wave 0 each)
+    int lg = 12;
+    while (lg > 6 && (int64_t)(ROLL_SLOTS >> lg) < N.batch) --lg;
+    const unsigned blocks = (unsigned)((N.batch + (ROLL_SLOTS >> lg) - 1) / (ROLL_SLOTS >> lg));
+#define RL(M, D) \
+    hipLaunchKernelGGL((k_nmpc_rollout<M, D>), dim3(blocks), dim3(ROLL_THREADS), 0, st, N, u, du, xout, uout, lvl, lg)
     if (N.model == MODEL_PENDULUM) {
         if (du) RL(MODEL_PENDULUM, true); else RL(MODEL_PENDULUM, false);
     } else if (N.model == MODEL_CARTPOLE) {
         if (du) RL(MODEL_CARTPOLE, true); else RL(MODEL_CARTPOLE, false);
     } else {
-#define RT(X, U) hipLaunchKernelGGL((k_nmpc_rollout_tanh<X, U>), dim3(N.batch), dim3(64), 0, st, N, u, du, xout, uout, lvl)
+#define RT(X, U) \
+    hipLaunchKernelGGL((k_nmpc_rollout_tanh<X, U>), dim3(N.batch), dim3(ROLL_THREADS), 0, st, N, u, du, xout, uout, lvl)
         if (N.nx <= 4) {
             switch (N.nx * 8 + N.nu) {
             case 9: RT(1, 1); break;  case 10: RT(1, 2); break; case 11: RT(1, 3); break; case 12: RT(1, 4); break;
