@@ -404,6 +404,16 @@ def batched(lqscan, workloads, dev, reps: int, with_cpu: bool) -> dict:
             assert int(b["status"].abs().sum()) == 0
             res[f"ragged4096_fwd_{prec}_{mode}"] = line(sizes, ms, eager, False)
             del b, plan
+    # the second tuning's choice on the same batch: what a flip costs
+    plan = lqscan.Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], seg_lens=again)
+    b = solve_buffers(lqscan, plan, dev)
+
+    def fwd2():
+        lqscan.lq_solve(plan, prob, None, b["val"], b["st"]["x"], b["st"]["u"], b["st"]["lam"], b["ws"], b["status"])
+
+    res["ragged4096_autotune"]["fp64_second_tune_ms_per_step"] = time_graph(fwd2, reps, warm=1)
+    res["ragged4096_autotune"]["fp64_first_tune_ms_per_step"] = res["ragged4096_fwd_fp64_autotuned"]["ms_per_step"]
+    del b, plan
     del prob
     torch.cuda.empty_cache()
     # per size class (autotuned FP64 segment lengths): stage-steps/s and the

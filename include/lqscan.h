@@ -86,8 +86,11 @@ typedef struct lq_plan lq_plan;   /* opaque */
 /*
  * Create a plan for a batch of `batch` instances with sizes nx[i], nu[i], T[i]
  * (host arrays).  `seg_len` is the number of stages folded per segment of the
- * scan (0 = choose automatically, ignored in LQ_SEQUENTIAL mode).  Allocates
- * small device descriptor tables on the current device.
+ * scan (0 = choose automatically, ignored in LQ_SEQUENTIAL mode: T/16
+ * clamped to 1..16, and at most 4 for the instances of a size class with
+ * n <= 4, served by the per-lane kernels, when the class has fewer than 16384
+ * stages in all).  Allocates small device descriptor tables on the current
+ * device.
  * Errors: LQ_ERR_ARG, LQ_ERR_UNSUPPORTED (nx > 15, nu > 4, or T >= 2^23:
  * the status word (-code) | (k << 8) must stay a positive int32 for every
  * stage k <= T; with nx <= 15 this also keeps (T + 1) nx^2 below 2^31, the

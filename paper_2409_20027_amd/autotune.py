@@ -10,11 +10,12 @@ Instances are grouped into classes (n, m, T bucket).  For each class the tuner
 times the forward solve (lq_solve) of the class's instances for every
 candidate L with HIP events (the median of `reps` timed samples, each
 bracketed by its own events and repeating the solve until it lasts at least
-MIN_SAMPLE_MS) and keeps the fastest only if it beats the library default
-(L = 0) by more than MARGIN on the medians and then wins CONFIRM_WINS of
-CONFIRM_PAIRS interleaved head-to-head samples against it; otherwise the
-default stays.  Choices within timing noise of each other therefore do not
-flip from one tuning to the next.  A class timed
+MIN_SAMPLE_MS).  Of the candidates within MARGIN of the fastest it takes the
+first in the candidate order (the library default L = 0 first), and keeps it
+only if it beats the default by more than MARGIN on the medians and then wins
+CONFIRM_WINS of CONFIRM_PAIRS interleaved head-to-head samples against it;
+otherwise the default stays.  Candidates that time within noise of each other
+therefore do not flip the choice from one tuning to the next.  A class timed
 alone can prefer the scan where, inside the whole batch, the GPU is already
 full and the sequential recursion (least work) is faster; so the per-class
 choice is then refined on the whole batch, switching classes to L = T while
@@ -96,10 +97,15 @@ def _time_forward_lens(lq, prob, sizes, seg_lens, precision, reps, torch):
     return _Timer(lq, prob, sizes, seg_lens, precision, torch).median(reps)
 
 
-def _pick(times: dict, default):
-    """The fastest candidate if it beats `default` by more than MARGIN, else `default`."""
-    best = min(times, key=times.get)
-    return best if times[best] < (1.0 - MARGIN) * times[default] else default
+def _pick(times: dict, default, order):
+    """Among the candidates within MARGIN of the fastest, the first in `order`
+    (so that candidates timing within noise of each other do not flip the
+    choice from one tuning to the next); it replaces `default` only if it beats
+    it by more than MARGIN."""
+    fastest = min(times.values())
+    near = [L for L in order if times[L] <= (1.0 + MARGIN) * fastest]
+    pick = default if default in near else near[0]
+    return pick if times[pick] < (1.0 - MARGIN) * times[default] else default
 
 
 def _confirmed(ta: "_Timer", tb: "_Timer") -> bool:
@@ -148,7 +154,7 @@ def tune_sizes(sizes, make_prob, *, precision="fp64", candidates=DEFAULT_CANDIDA
         timers = {L: _Timer(lq, prob, sub, [z[2] if L < 0 else L for z in sub], precision, torch)
                   for L in candidates}
         times = {L: t.median(reps) for L, t in timers.items()}
-        best = _pick(times, candidates[0])
+        best = _pick(times, candidates[0], candidates)
         if best != candidates[0] and not _confirmed(timers[candidates[0]], timers[best]):
             best = candidates[0]
         del prob, timers

@@ -80,3 +80,20 @@ def test_stage_model_matches_the_stated_per_stage_costs():
     assert abs(ceil[2] - 62.5e9) < 1e6 and abs(ceil[4] - 21.74e9) < 1e7 and abs(ceil[12] - 2.63e9) < 1e7
     # forward + adjoint: about 9.1 KB per stage at n = 12
     assert bench.stage_model(12, 4, True)["bytes"] == 9024
+
+
+def test_autotune_pick_is_order_stable():
+    """The segment-length choice among candidates within the margin of the
+    fastest is the first in the candidate order, so two tunings whose timings
+    differ only by noise pick the same L; the default stays unless the pick
+    beats it by more than the margin."""
+    from paper_2409_20027_amd import autotune
+    order = autotune.DEFAULT_CANDIDATES
+    pick = autotune._pick
+    # 4 and 8 within 5% of each other, both well ahead of the default
+    assert pick({0: 1.0, 4: 0.80, 8: 0.79, 16: 0.9, 32: 1.2, 64: 1.5, -1: 2.0}, 0, order) == 4
+    assert pick({0: 1.0, 4: 0.79, 8: 0.80, 16: 0.9, 32: 1.2, 64: 1.5, -1: 2.0}, 0, order) == 4
+    # the default within the margin of the fastest: the default
+    assert pick({0: 0.82, 4: 0.80, 8: 0.79, 16: 0.9, 32: 1.2, 64: 1.5, -1: 2.0}, 0, order) == 0
+    # a clear winner far ahead of everything else
+    assert pick({0: 1.0, 4: 0.9, 8: 0.9, 16: 0.9, 32: 0.9, 64: 0.9, -1: 0.3}, 0, order) == -1
