@@ -371,12 +371,13 @@ __global__ __launch_bounds__(64) void k_nmpc_clear(NmpcPtrs N, NmpcWork Wk)
 }
 
 // Step 1 (one lane per stage of every instance), arithmetic type RT, results
-// stored in FP64.
-template <typename RT>
+// stored in FP64.  NX > 0: compile-time sizes nx = NX, nu = NU (the tanh
+// model's per-stage arrays then stay in registers).
+template <typename RT, int NX, int NU>
 __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u)
 {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = N.nx, m = N.nu, T = N.T;
+    const int n = NX > 0 ? NX : N.nx, m = NX > 0 ? NU : N.nu, T = N.T;
     if (idx >= (int64_t)N.batch * (T + 1)) return;
     const int b = (int)(idx / (T + 1)), k = (int)(idx - (int64_t)b * (T + 1));
     if (level_done(Wk.scal, b)) return;
@@ -397,7 +398,7 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
     } else if (N.model == MODEL_CARTPOLE) {
         linearise_model<5>(N, Wk, gk, xk, uk);
     } else {
-        RT th[NXMAX];
+        RT th[NX > 0 ? NX : NXMAX];
         const RT h = (RT)N.h;
         for (int i = 0; i < n; ++i) {
             RT z = 0;
@@ -508,12 +509,13 @@ __global__ __launch_bounds__(64) void k_costate_apply(NmpcWork Wk, const InstDes
 // Step 3 (one lane per stage): second-order terms of the Hamiltonian.  In
 // mixed precision the lambda' d2f contractions (P, M and their R part) are
 // formed in RT = float; the gradient d, the barrier terms and alpha stay FP64.
-template <typename RT>
+// NX > 0: compile-time sizes as in k_nmpc_linearise.
+template <typename RT, int NX, int NU>
 __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                                                            const double *scal)
 {
     const int64_t gk = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // instance * T + stage
-    const int n = N.nx, m = N.nu, T = N.T;
+    const int n = NX > 0 ? NX : N.nx, m = NX > 0 ? NU : N.nu, T = N.T;
     if (gk >= (int64_t)N.batch * T) return;
     const int b = (int)(gk / T);
     if (level_done(Wk.scal, b)) return;
@@ -530,7 +532,7 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
     } else {
         const double *th = Wk.th + gk * n;
         double *P = Wk.P + gk * n * n;
-        RT Pl[NXMAX * NXMAX];
+        RT Pl[NX > 0 ? NX * NX : NXMAX * NXMAX];
         for (int i = 0; i < n * n; ++i) Pl[i] = (RT)N.Q[i];
         for (int i = 0; i < n; ++i) {
             const RT t = (RT)th[i];
@@ -576,14 +578,17 @@ __global__ __launch_bounds__(256) void k_nmpc_quadraticise(NmpcPtrs N, NmpcWork 
 // alpha *= nu, nu *= 2.  An LQ step that failed counts as pred = 0.
 constexpr int RED = 256;
 // RB threads per instance, chosen from the horizon (about one to four stages
-// per thread).
-template <int RB>
+// per thread).  NX > 0: the sizes nx = NX, nu = NU are compile-time (the
+// pendulum, and the cart-pole and tanh model at n = 4, m = 1), so each
+// thread's loads of a stage are issued together instead of one loop trip
+// at a time.
+template <int RB, int NX, int NU>
 __global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                                                     double *scal)
 {
     __shared__ double sp[RB], s0[RB], s1[RB], sg[RB];
     const int t = threadIdx.x, b = blockIdx.x;
-    const int n = N.nx, m = N.nu, T = N.T;
+    const int n = NX > 0 ? NX : N.nx, m = NX > 0 ? NU : N.nu, T = N.T;
     if (level_done(scal, b)) return;   // uniform over the block
     scal += (int64_t)b * NMPC_NSCAL;
     const int64_t s0k = (int64_t)b * T;              // first packed stage of the instance
@@ -809,7 +814,13 @@ void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, cons
     // the point Newton converges to: FP64 in every precision mode.
     (void)pr;
     const int64_t cnt = (int64_t)N.batch * (N.T + 1);
-    hipLaunchKernelGGL(k_nmpc_linearise<double>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st, N, Wk, x, u);
+    const dim3 g((unsigned)((cnt + 255) / 256));
+    if (N.nx == 2 && N.nu == 1)
+        hipLaunchKernelGGL((k_nmpc_linearise<double, 2, 1>), g, dim3(256), 0, st, N, Wk, x, u);
+    else if (N.nx == 4 && N.nu == 1)
+        hipLaunchKernelGGL((k_nmpc_linearise<double, 4, 1>), g, dim3(256), 0, st, N, Wk, x, u);
+    else
+        hipLaunchKernelGGL((k_nmpc_linearise<double, 0, 0>), g, dim3(256), 0, st, N, Wk, x, u);
 }
 void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
                          const int32_t *seg_start, int batch, double *Y)
@@ -830,20 +841,36 @@ void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, c
                               const double *scal)
 {
     const unsigned g = (unsigned)(((int64_t)N.batch * N.T + 255) / 256);
-    if (pr)
-        hipLaunchKernelGGL(k_nmpc_quadraticise<float>, dim3(g), dim3(256), 0, st, N, Wk, x, u, scal);
+#define QC(R, X, U) hipLaunchKernelGGL((k_nmpc_quadraticise<R, X, U>), dim3(g), dim3(256), 0, st, N, Wk, x, u, scal)
+    if (N.nx == 2 && N.nu == 1) {
+        if (pr) QC(float, 2, 1); else QC(double, 2, 1);
+    } else if (N.nx == 4 && N.nu == 1) {
+        if (pr) QC(float, 4, 1); else QC(double, 4, 1);
+    } else {
+        if (pr) QC(float, 0, 0); else QC(double, 0, 0);
+    }
+#undef QC
+}
+template <int RB>
+static void launch_reduce(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk, const double *x, const double *u,
+                          double *scal)
+{
+    if (N.nx == 2 && N.nu == 1)
+        hipLaunchKernelGGL((k_nmpc_reduce<RB, 2, 1>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
+    else if (N.nx == 4 && N.nu == 1)
+        hipLaunchKernelGGL((k_nmpc_reduce<RB, 4, 1>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
     else
-        hipLaunchKernelGGL(k_nmpc_quadraticise<double>, dim3(g), dim3(256), 0, st, N, Wk, x, u, scal);
+        hipLaunchKernelGGL((k_nmpc_reduce<RB, 0, 0>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
 }
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
     launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc, Wk.scal);
     if (N.T <= 96)
-        hipLaunchKernelGGL(k_nmpc_reduce<64>, dim3(N.batch), dim3(64), 0, st, N, Wk, x, u, scal);
+        launch_reduce<64>(st, N, Wk, x, u, scal);
     else if (N.T <= 384)
-        hipLaunchKernelGGL(k_nmpc_reduce<256>, dim3(N.batch), dim3(256), 0, st, N, Wk, x, u, scal);
+        launch_reduce<256>(st, N, Wk, x, u, scal);
     else
-        hipLaunchKernelGGL(k_nmpc_reduce<1024>, dim3(N.batch), dim3(1024), 0, st, N, Wk, x, u, scal);
+        launch_reduce<1024>(st, N, Wk, x, u, scal);
 }
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init)
 {
