@@ -783,8 +783,8 @@ def cfg1_newton(lqscan, workloads, reps: int, with_cpu: bool) -> dict:
         def solve():
             s.init(a0, nu0)
             for mu in levels:
+                s._sc[:, lqscan.NMPC_MU] = mu
                 for _ in range(iters):
-                    s._sc[:, lqscan.NMPC_MU] = mu
                     g.replay()
 
         solve()
