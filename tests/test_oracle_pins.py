@@ -591,3 +591,42 @@ def test_damping_rule_on_an_exact_quadratic_model(seed, nx, nu, T):
             assert a2 == alpha * nu_lm and n2 == 2.0 * nu_lm
         alpha, nu_lm = a2, n2
     assert seen[True] >= 1 and seen[False] >= 1
+
+
+def test_damping_rule_interior_shape():
+    """The damping update between the ends (0 < gain ratio < 1), pinned by the
+    shape the gain-ratio rule of the reference the paper names is built to
+    have, not by its formula: on accepted Newton steps of the pendulum and
+    cart-pole swing-ups from u = 0 (gain ratios 0.19 .. 1 over a sweep of
+    alpha and mu), the factor alpha_new / alpha is a function of the ratio
+    alone -- non-increasing, with at most slope 6 between any two samples --
+    above 1 exactly when the ratio is below 1/2 (poor agreement enlarges the
+    damping, good agreement shrinks it), between 1/3 and 2, and at its floor
+    1/3 once the ratio is near 1 (from about 0.937 on); nu (8 before the step)
+    is reset to 2.  A
+    square for the cube, the sign of (2 rho - 1) flipped, another floor or a
+    nu left unreset each fail."""
+    samples = []
+    for mk in (W.pendulum_problem, W.cartpole_problem):
+        p = mk(60)
+        u = np.zeros_like(p.u0)
+        x = oracle.nmpc_rollout(p, u)
+        for mu in (0.01, 0.1, 1.0):
+            for a in np.geomspace(1e-6, 1e2, 25):
+                acc, _, _, a2, n2, _, pred, rho = oracle.nmpc_newton_step(p, x, u, mu, a, 8.0)
+                if acc:
+                    assert pred > 0 and rho > 0 and n2 == 2.0
+                    samples.append((rho, a2 / a))
+    samples.sort()
+    rhos = np.array([s[0] for s in samples])
+    f = np.array([s[1] for s in samples])
+    assert rhos.min() < 0.3 and ((rhos > 0.4) & (rhos < 0.5)).any() and ((rhos > 0.5) & (rhos < 0.9)).any()
+    assert (f >= 1.0 / 3.0 - 1e-15).all() and (f < 2.0).all()
+    assert (np.diff(f) <= 1e-12).all()                       # non-increasing in rho
+    for i in range(len(f)):
+        for j in range(i + 1, len(f)):
+            assert abs(f[i] - f[j]) <= 6.0 * abs(rhos[i] - rhos[j]) + 1e-12
+    off = np.abs(rhos - 0.5) > 1e-3
+    assert ((f[off] > 1.0) == (rhos[off] < 0.5)).all()
+    assert np.allclose(f[rhos >= 0.94], 1.0 / 3.0, rtol=1e-14)
+    assert (f[rhos < 0.93] > 1.0 / 3.0 + 1e-3).all()
