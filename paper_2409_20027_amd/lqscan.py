@@ -552,10 +552,16 @@ class NewtonMPC:
         self.B = 1 if np.ndim(p.x0) == 1 else int(np.shape(p.x0)[0])
         B = self.B
         if seg_len == 0 and mode == "scan" and B > 1:
-            # a batch fills the GPU by itself: about 1536 segment waves in all, so that
-            # large batches run the plain recursion per instance (measured for N = 60:
-            # B = 256 best at 6 segments, B >= 1024 at one)
-            nseg = max(1, -(-1536 // B))
+            # a batch fills the GPU by itself.  Tile kernels (n > 4, one wave per
+            # segment): about 1536 segments in all, so that large batches run the
+            # plain recursion per instance (N = 60: B = 256 best at 6 segments,
+            # B >= 1024 at one).  Per-lane kernels (n <= 4, one lane per segment):
+            # about 16384 segments, at least 4 stages each (N = 60, receding-horizon
+            # simulations: B = 64 and 1024 best at 4 stages per segment, 4096 at 15)
+            if p.nx <= 4:
+                nseg = max(1, min(-(-16384 // B), p.T // 4))
+            else:
+                nseg = max(1, -(-1536 // B))
             seg_len = max(1, -(-p.T // nseg))
         self.plan = Plan([p.nx] * B, [p.nu] * B, [p.T] * B, seg_len=seg_len, precision=precision, mode=mode)
         names = ("Q", "R", "QT", "xref") + (("W", "Bm") if model == NMPC_TANH else ())
