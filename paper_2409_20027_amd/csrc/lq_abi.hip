@@ -891,10 +891,18 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     lqk::launch_nmpc_clear(st, N, Wk);
     // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
     lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x, state->u);
-    lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch, Ya);
+    // (n <= 4: the per-lane kernels, in FP64 whatever the plan's precision)
+    if (p->small)
+        lqk::launch_small_costate_fold(p->sn, p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch, Ya);
+    else
+        lqk::launch_costate_fold(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch,
+                                 Ya);
     double *in = affine_scan(p, st, 1, Ya, Yb);
-    lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch,
-                              in);
+    if (p->small)
+        lqk::launch_small_costate_apply(p->sn, p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch, in);
+    else
+        lqk::launch_costate_apply(p->nk, p->prec, (unsigned)p->total_seg, st, Wk, p->d_inst, p->d_seg_start, p->batch,
+                                  in);
     lqk::launch_nmpc_quadraticise(p->prec, st, N, Wk, state->x, state->u, state->scal);
     // the LQ step (all instances in one batched solve)
     lq_problem lp{};

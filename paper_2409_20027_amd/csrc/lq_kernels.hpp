@@ -49,6 +49,10 @@ void launch_small_value_riccati(int n, int m, int64_t total, hipStream_t st, Pro
                                 double *ckpt, int stride, int32_t *status);
 void launch_small_affine_ks(int n, int radix, int64_t total, hipStream_t st, const InstDesc *inst,
                             const int32_t *x_start, int batch, int dd, int suffix, const double *Yin, double *Yout);
+void launch_small_costate_fold(int n, int64_t total, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                               const int32_t *seg_start, int batch, double *Y);
+void launch_small_costate_apply(int n, int64_t total, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                                const int32_t *seg_start, int batch, const double *Yfin);
 void launch_small_roll_apply(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
                              const int32_t *seg_start, int batch, const double *Yfin, double *x, double *u,
                              double *lam);

@@ -19,6 +19,8 @@
 //                          elements of Alg. 3)
 //   k_small_affine_ks      one level of an affine-map scan (eq:state-prop-comb-rule)
 //   k_small_roll_apply     states, controls and co-states inside a segment
+//   k_small_costate_fold,  the Newton step's co-state pass (segment fold of the
+//   k_small_costate_apply  maps [[A', g], [0, 1]], then co-states from the scan)
 // Scan entries are stored in the general path's layout (an (n+1) x (n+1)
 // homogeneous block, row-major, at the start of a 256-double slot: A~ =
 // [[A, b], [0, 1]], C~ = [[C, 0], [0, 0]], J~ = [[J, -eta], [-eta', c0]], affine
@@ -1049,6 +1051,106 @@ __global__ __launch_bounds__(64) void k_small_roll_apply(ProbPtrs P, ValPtrs V, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// The Newton step's co-state pass (Alg. 1) for n <= 4, one lane per segment:
+// lambda_k = A_k' lambda_{k+1} + g_k, i.e. [lambda_k; 1] = M_k [lambda_{k+1}; 1]
+// with M_k = [[A_k', g_k], [0, 1]] (A_k, g_k from the linearisation).
+// Fold: Psi_s = M_{k0} M_{k0+1} ... M_{k1-1} as an affine map [[F, e], [0, 1]];
+// the last segment also writes the terminal element [[0, lambda_T], [0, 1]].
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64) void k_small_costate_fold(NmpcWork Wk, const InstDesc *__restrict__ inst,
+                                                           const int32_t *__restrict__ seg_start, int batch,
+                                                           int total, double *__restrict__ Y)
+{
+    const int gs = gid();
+    if (gs >= total) return;
+    const int i = find_inst(seg_start, batch, gs);
+    if (level_done(Wk.scal, i)) return;
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    if (s == d.nseg - 1) {
+        double Z[N][N], lT[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            lT[r] = Wk.lamT[d.on + r];
+#pragma unroll
+            for (int c = 0; c < N; ++c) Z[r][c] = 0.0;
+        }
+        store_map(Y + (int64_t)(d.xbase + d.nseg) * TILE, Z, lT);
+    }
+    if (s == 0) return;
+    double F[N][N], e[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        e[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) F[r][c] = (r == c) ? 1.0 : 0.0;
+    }
+    for (int k = k0; k < k1; ++k) {
+        double A[N][N], g[N];
+        ldm(Wk.A + d.oA + (int64_t)k * N * N, A);
+        ldv(Wk.g + d.oc + (int64_t)k * N, g);
+        double nF[N][N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = e[r];
+#pragma unroll
+            for (int j = 0; j < N; ++j) t += F[r][j] * g[j];
+            e[r] = t;
+#pragma unroll
+            for (int c = 0; c < N; ++c) {
+                double u = 0.0;
+#pragma unroll
+                for (int j = 0; j < N; ++j) u += F[r][j] * A[c][j];   // (F A_k')_{rc}
+                nF[r][c] = u;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r)
+#pragma unroll
+            for (int c = 0; c < N; ++c) F[r][c] = nF[r][c];
+    }
+    store_map(Y + (int64_t)(d.xbase + s) * TILE, F, e);
+}
+
+// Co-states inside each segment from lambda at its right end (the last column
+// of scanned entry s + 1; for the last segment the terminal element, whose
+// lambda_T it also stores).
+template <int N>
+__global__ __launch_bounds__(64) void k_small_costate_apply(NmpcWork Wk, const InstDesc *__restrict__ inst,
+                                                            const int32_t *__restrict__ seg_start, int batch,
+                                                            int total, const double *__restrict__ Yfin)
+{
+    const int gs = gid();
+    if (gs >= total) return;
+    const int i = find_inst(seg_start, batch, gs);
+    if (level_done(Wk.scal, i)) return;
+    const InstDesc d = inst[i];
+    const int s = gs - d.seg0;
+    const int k0 = s * d.L, k1 = min(k0 + d.L, d.T);
+    double *lam = Wk.lam + d.os;
+    double F[N][N], l[N];
+    load_map(Yfin + (int64_t)(d.xbase + s + 1) * TILE, F, l);
+    if (s == d.nseg - 1) stv(lam + (int64_t)d.T * N, l);
+    for (int k = k1 - 1; k >= k0; --k) {
+        double A[N][N], g[N], ln[N];
+        ldm(Wk.A + d.oA + (int64_t)k * N * N, A);
+        ldv(Wk.g + d.oc + (int64_t)k * N, g);
+#pragma unroll
+        for (int r = 0; r < N; ++r) {
+            double t = g[r];
+#pragma unroll
+            for (int j = 0; j < N; ++j) t += A[j][r] * l[j];   // (A_k' lambda)_r
+            ln[r] = t;
+        }
+#pragma unroll
+        for (int r = 0; r < N; ++r) l[r] = ln[r];
+        stv(lam + (int64_t)k * N, l);
+    }
+}
+
 unsigned lanes_grid(int64_t total) { return (unsigned)((total + 63) / 64); }
 
 }  // namespace
@@ -1121,6 +1223,22 @@ void launch_small_affine_ks(int n, int radix, int64_t total, hipStream_t st, con
 #undef CALL16
 #undef CALL32
 #undef CALLR
+}
+
+void launch_small_costate_fold(int n, int64_t total, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                               const int32_t *seg_start, int batch, double *Y)
+{
+#define CALL(N) hipLaunchKernelGGL((k_small_costate_fold<N>), dim3(lanes_grid(total)), dim3(64), 0, st, Wk, inst, seg_start, batch, (int)total, Y)
+    LQK_SMALL_N(n, CALL)
+#undef CALL
+}
+
+void launch_small_costate_apply(int n, int64_t total, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
+                                const int32_t *seg_start, int batch, const double *Yfin)
+{
+#define CALL(N) hipLaunchKernelGGL((k_small_costate_apply<N>), dim3(lanes_grid(total)), dim3(64), 0, st, Wk, inst, seg_start, batch, (int)total, Yfin)
+    LQK_SMALL_N(n, CALL)
+#undef CALL
 }
 
 void launch_small_roll_apply(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, ValPtrs V, const InstDesc *inst,
