@@ -105,6 +105,19 @@ lq_status lq_plan_create(int32_t batch, const int32_t *nx, const int32_t *nu, co
  */
 lq_status lq_plan_create_seg(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
                              int32_t precision, const int32_t *seg_len, lq_plan **out);
+/*
+ * Same with the segment lengths of an autotuner cache (the JSON file that
+ * paper_2409_20027_amd/autotune.py writes): each instance takes the length
+ * tuned for its class -- key "n<n>_m<m>_T<t>_B<b>_<fp64|mixed>" with t the
+ * power of two at or above T[i] and b the one at or above the number of
+ * instances of the batch in that (n, m, t) class -- where -1 means the
+ * sequential recursion (one segment) and a class absent from the cache
+ * gets the automatic length.  cache_path NULL: every length automatic.
+ * Errors: LQ_ERR_ARG also for a file that cannot be read or an entry
+ * without a readable "L"; otherwise those of lq_plan_create.
+ */
+lq_status lq_plan_create_tuned(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                               int32_t precision, const char *cache_path, lq_plan **out);
 void lq_plan_destroy(lq_plan *plan);
 
 /* Bytes of scratch device memory the solve calls need (256-byte aligned base). */
@@ -276,6 +289,11 @@ lq_status lq_solve_static(const lq_plan *plan, const lq_problem *prob, const dou
  *   dL/dQ_k = sym(dx_k x_k')   dL/dR_k = sym(du_k u_k')   dL/dM_k = dx_k u_k' + x_k du_k'
  *   dL/dq_k = dx_k   dL/dr_k = du_k   dL/dQ_T = sym(dx_T x_T')   dL/dq_T = dx_T.
  * Inputs: the forward solution val (S, s, Gamma, gamma), x, u, lambda.
+ * val may be NULL: the value functions are then recomputed by rerunning the
+ * value pass from the problem data, exactly as lq_adjoint_ckpt with
+ * ckpt == NULL, and the workspace must hold
+ * lq_plan_adjoint_ckpt_workspace_bytes (LQ_ERR_WORKSPACE if NULL or
+ * misaligned).
  */
 lq_status lq_adjoint(const lq_plan *plan, const lq_problem *prob, const lq_value *val,
                      const double *x, const double *u, const double *lambda,

@@ -7,9 +7,11 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "lq_kernels.hpp"
@@ -413,6 +415,51 @@ lq_status lq_plan_create_seg(int32_t batch, const int32_t *nx, const int32_t *nu
     return plan_create(batch, nx, nu, T, precision, LQ_SCAN, 0, seg_len, out);
 }
 
+lq_status lq_plan_create_tuned(int32_t batch, const int32_t *nx, const int32_t *nu, const int32_t *T,
+                               int32_t precision, const char *cache_path, lq_plan **out)
+{
+    if (!out || batch <= 0 || !nx || !nu || !T) return LQ_ERR_ARG;
+    if (precision != LQ_FP64 && precision != LQ_MIXED) return LQ_ERR_ARG;
+    std::string text;
+    if (cache_path) {
+        FILE *f = std::fopen(cache_path, "rb");
+        if (!f) return LQ_ERR_ARG;
+        char buf[4096];
+        size_t k;
+        while ((k = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, k);
+        std::fclose(f);
+    }
+    // the tuner's classes: (n, m, T rounded up to a power of two), sized by
+    // how many instances of the batch fall into them (rounded up likewise)
+    auto bucket = [](int64_t v) {
+        int64_t b = 1;
+        while (b < v) b <<= 1;
+        return b;
+    };
+    std::vector<int64_t> tb(batch);
+    for (int i = 0; i < batch; ++i) tb[i] = bucket(T[i] > 0 ? T[i] : 1);
+    std::vector<int32_t> lens(batch, 0);
+    for (int i = 0; i < batch && !text.empty(); ++i) {
+        int64_t count = 0;
+        for (int j = 0; j < batch; ++j) count += (nx[j] == nx[i] && nu[j] == nu[i] && tb[j] == tb[i]);
+        char key[128];
+        std::snprintf(key, sizeof key, "\"n%d_m%d_T%lld_B%lld_%s\"", nx[i], nu[i], (long long)tb[i],
+                      (long long)bucket(count), precision == LQ_MIXED ? "mixed" : "fp64");
+        const size_t at = text.find(key);
+        if (at == std::string::npos) continue;   // class not tuned: automatic
+        const size_t l = text.find("\"L\"", at);
+        const size_t close = text.find('}', at);
+        if (l == std::string::npos || l > close) return LQ_ERR_ARG;
+        const size_t colon = text.find(':', l);
+        if (colon == std::string::npos) return LQ_ERR_ARG;
+        char *end = nullptr;
+        const long L = std::strtol(text.c_str() + colon + 1, &end, 10);
+        if (end == text.c_str() + colon + 1 || L < -1 || L > INT32_MAX) return LQ_ERR_ARG;
+        lens[i] = (L < 0) ? T[i] : (int32_t)L;   // -1: the sequential recursion
+    }
+    return plan_create(batch, nx, nu, T, precision, LQ_SCAN, 0, lens.data(), out);
+}
+
 void lq_plan_destroy(lq_plan *p)
 {
     if (!p) return;
@@ -745,6 +792,9 @@ lq_status lq_adjoint(const lq_plan *p, const lq_problem *prob, const lq_value *v
                      const double *u, const double *lambda, const double *gx, const double *gu,
                      const lq_grads *grads, void *workspace, int32_t *status, void *stream)
 {
+    // without the value functions: rerun the value pass (lq_adjoint_ckpt without a checkpoint)
+    if (!val)
+        return lq_adjoint_ckpt(p, prob, nullptr, 1, x, u, lambda, gx, gu, grads, workspace, status, stream);
     if (!p || !prob_ok(prob) || !value_ok(val)) return LQ_ERR_ARG;
     if (!x || !u || !lambda || !gx || !gu || !grads) return LQ_ERR_ARG;
     if (!workspace || !aligned(workspace)) return LQ_ERR_WORKSPACE;

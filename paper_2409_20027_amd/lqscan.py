@@ -53,6 +53,9 @@ _lib.lq_plan_create.restype = ctypes.c_int
 _lib.lq_plan_create_seg.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p,
                                     ctypes.POINTER(_plan_p)]
 _lib.lq_plan_create_seg.restype = ctypes.c_int
+_lib.lq_plan_create_tuned.argtypes = [ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32, ctypes.c_char_p,
+                                      ctypes.POINTER(_plan_p)]
+_lib.lq_plan_create_tuned.restype = ctypes.c_int
 _lib.lq_plan_destroy.argtypes = [_plan_p]
 _lib.lq_plan_destroy.restype = None
 for _f, _rt in (("lq_plan_workspace_bytes", ctypes.c_size_t), ("lq_plan_elements_bytes", ctypes.c_size_t),
@@ -96,7 +99,7 @@ _lib.lq_selftest_tile_mm.restype = ctypes.c_int
 _lib.lq_selftest_tile_inverse.argtypes = [_P, _P, ctypes.c_int32, ctypes.c_int32, _P, _P]
 _lib.lq_selftest_tile_inverse.restype = ctypes.c_int
 
-EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
+EXPORTED = ("lq_plan_create", "lq_plan_create_seg", "lq_plan_create_tuned", "lq_plan_destroy", "lq_plan_workspace_bytes", "lq_plan_elements_bytes",
             "lq_plan_seg_len", "lq_plan_total_stages", "lq_build_elements", "lq_scan_solve", "lq_rollout", "lq_rollout_cv",
             "lq_solve", "lq_solve_static", "lq_plan_static_bytes", "lq_adjoint",
             "lq_plan_checkpoint_bytes", "lq_plan_adjoint_ckpt_workspace_bytes", "lq_solve_ckpt", "lq_adjoint_ckpt", "lq_selftest_tile_mm", "lq_selftest_tile_inverse", "lq_version", "lq_plan_set_timing", "lq_plan_phase_times")
@@ -155,7 +158,9 @@ class Plan:
     """Owns an lq_plan* (sizes, segment decomposition, device descriptor tables)."""
 
     def __init__(self, nx, nu, T, *, precision: str = "fp64", mode: str = "scan", seg_len: int = 0,
-                 seg_lens=None):
+                 seg_lens=None, autotune_cache: str | None = None):
+        """seg_lens: one segment length per instance; autotune_cache: the
+        autotuner's JSON cache, read by the library (lq_plan_create_tuned)."""
         nx, nu, T = (list(map(int, v)) if hasattr(v, "__len__") else [int(v)] for v in (nx, nu, T))
         self.batch = len(T)
         self.nx, self.nu, self.T = nx, nu, T
@@ -163,7 +168,11 @@ class Plan:
         arr = ctypes.c_int32 * self.batch
         prec = {"fp64": LQ_FP64, "mixed": LQ_MIXED}[precision]
         h = _plan_p()
-        if seg_lens is not None:
+        if autotune_cache is not None:
+            code = _lib.lq_plan_create_tuned(self.batch, arr(*nx), arr(*nu), arr(*T), prec,
+                                             os.fsencode(autotune_cache), ctypes.byref(h))
+            _check("lq_plan_create_tuned", code)
+        elif seg_lens is not None:
             code = _lib.lq_plan_create_seg(self.batch, arr(*nx), arr(*nu), arr(*T), prec,
                                            arr(*[int(v) for v in seg_lens]), ctypes.byref(h))
             _check("lq_plan_create_seg", code)
@@ -288,13 +297,15 @@ def lq_plan_static_bytes(plan: Plan) -> int:
 LQ_STATIC_SCRATCH_BYTES = 32 << 20
 
 
-def lq_adjoint(plan: Plan, prob: dict, value: dict, x, u, lam, gx, gu, grads: dict, workspace, status=None,
+def lq_adjoint(plan: Plan, prob: dict, value: dict | None, x, u, lam, gx, gu, grads: dict, workspace, status=None,
                stream=None):
+    """value None: the value functions are recomputed (the workspace must be
+    plan.new_adjoint_ckpt_workspace())."""
     g = LQGradsC(*[_f64(grads.get(f)) for f in _PROBLEM_FIELDS])
-    _check("lq_adjoint", _lib.lq_adjoint(plan.handle, ctypes.byref(_problem_struct(prob)),
-                                         ctypes.byref(_value_struct(value)), _f64(x), _f64(u), _f64(lam),
-                                         _f64(gx), _f64(gu), ctypes.byref(g), _ptr(workspace), _ptr(status),
-                                         _stream(stream)))
+    vs = None if value is None else ctypes.byref(_value_struct(value))
+    _check("lq_adjoint", _lib.lq_adjoint(plan.handle, ctypes.byref(_problem_struct(prob)), vs, _f64(x), _f64(u),
+                                         _f64(lam), _f64(gx), _f64(gu), ctypes.byref(g), _ptr(workspace),
+                                         _ptr(status), _stream(stream)))
 
 
 def lq_solve_ckpt(plan: Plan, prob: dict, elements, value: dict, x, u, lam, ckpt, stride: int, workspace,

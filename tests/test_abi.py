@@ -52,6 +52,26 @@ def test_plan_create_rejects_bad_arguments(lib):
     assert f(1, arr(1), arr(1), arr(2**31 - 1), 0, 0, 0, ctypes.byref(plan)) == -7
 
 
+def test_plan_create_tuned_rejects_bad_arguments(lib, tmp_path):
+    """lq_plan_create_tuned: argument errors, an unreadable cache file and a
+    cache entry without a segment length are refused before any device call."""
+    plan = ctypes.c_void_p()
+    arr = ctypes.c_int32 * 1
+    f = lib.lq_plan_create_tuned
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                  ctypes.c_char_p, ctypes.c_void_p]
+    assert f(0, arr(2), arr(1), arr(4), 0, None, ctypes.byref(plan)) == -1                 # batch 0
+    assert f(1, arr(2), arr(1), arr(4), 7, None, ctypes.byref(plan)) == -1                 # precision
+    missing = str(tmp_path / "missing.json").encode()
+    assert f(1, arr(2), arr(1), arr(4), 0, missing, ctypes.byref(plan)) == -1              # unreadable
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"n2_m1_T4_B1_fp64": {"ms": {"0": 1.0}}}')
+    assert f(1, arr(2), arr(1), arr(4), 0, str(bad).encode(), ctypes.byref(plan)) == -1    # no "L"
+    bad.write_text('{"n2_m1_T4_B1_fp64": {"L": "x"}}')
+    assert f(1, arr(2), arr(1), arr(4), 0, str(bad).encode(), ctypes.byref(plan)) == -1    # unreadable "L"
+
+
 def test_version(lib):
     lib.lq_version.restype = ctypes.c_char_p
     assert b"gfx950" in lib.lq_version()

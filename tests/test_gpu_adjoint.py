@@ -365,6 +365,32 @@ def test_checkpoint_stride_one_equals_stored_path(lq):
             assert np.array_equal(ga[f], gb[f]), f
 
 
+def test_adjoint_without_value_functions(lq):
+    """lq_adjoint with val = NULL reruns the value pass from the problem data
+    (the recompute of lq_adjoint_ckpt without a checkpoint): on a batch mixing
+    per-lane and tile classes the gradients equal those of the stored-value
+    path bit for bit, since the rerun repeats the forward's own arithmetic."""
+    rng = np.random.default_rng(93)
+    insts = [W.lq_instance_general(rng, 3, 1, 77), W.lq_instance(rng, 12, 4, 500), W.lq_instance_general(rng, 6, 2, 41)]
+    prob = lq.to_device(W.pack(insts))
+    plan = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], seg_len=8)
+    status = torch.zeros(plan.batch, dtype=torch.int32, device="cuda")
+    val, st = lq.value_buffers(plan), lq.state_buffers(plan)
+    ws = plan.new_workspace()
+    lq.lq_solve(plan, prob, None, val, st["x"], st["u"], st["lam"], ws, status)
+    gx, gu = 2 * st["x"], 2 * st["u"]
+    g_stored = lq.grad_buffers(plan, FIELDS)
+    lq.lq_adjoint(plan, prob, val, st["x"], st["u"], st["lam"], gx, gu, g_stored, ws, status)
+    g_none = lq.grad_buffers(plan, FIELDS)
+    aws = plan.new_adjoint_ckpt_workspace()
+    aws.fill_(255)
+    lq.lq_adjoint(plan, prob, None, st["x"], st["u"], st["lam"], gx, gu, g_none, aws, status)
+    torch.cuda.synchronize()
+    assert int(status.abs().sum()) == 0
+    for f in FIELDS:
+        assert torch.equal(g_stored[f], g_none[f]), f
+
+
 @pytest.mark.parametrize("checkpoint", [0, 1, 5, "recompute"])
 def test_autograd_checkpoint_modes(lq, checkpoint):
     """The autograd wrapper in each mode (0: keep S and Gamma; k: stride-k

@@ -180,3 +180,10 @@ def test_ragged_batch_autotuned(lq, batch, tmp_path):
     # a second call hits the cache and returns the same choice
     seg2, report2 = autotune.tune(insts, cache_path=cache, sample_per_class=48, reps=2)
     assert seg2 == seg and report2 == {}
+    # the library reads the same cache (lq_plan_create_tuned): the same segments, so the same bits
+    plan_c = lq.Plan([i.n for i in insts], [i.m for i in insts], [i.T for i in insts], autotune_cache=cache)
+    assert plan_c.seg_len() == plan.seg_len()
+    out_c = lq.solve(plan_c, prob)
+    torch.cuda.synchronize()
+    for k in ("x", "u", "S", "Gamma"):
+        assert torch.equal(out_c[k], out[k]), k
