@@ -366,8 +366,118 @@ def state_buffers(plan: Plan, device="cuda") -> dict:
     return {"x": z(((T + 1) * n).sum()), "u": z((T * m).sum()), "lam": z(((T + 1) * n).sum())}
 
 
-def solve(plan: Plan, prob: dict, *, materialise_elements: bool = False, fused: bool = True, workspace=None,
-          stream=None, rollout: str = "affine") -> dict:
+def solve(plan_or_A, *args, **kw):
+    """Two forms.
+
+    solve(plan, prob, ...): the packed batch on a plan (see _solve_plan),
+    returns the flat packed outputs and the status array.
+
+    solve(A, B, c, Q, R, QT, x0, *, M=None, q=None, r=None, qT=None,
+    precision="fp64", seg_len=0, checkpoint=1): one problem given as
+    stage-major float64 device tensors (A [T, n, n], B [T, n, m], c [T, n],
+    Q [T, n, n], R [T, m, m], QT [n, n], x0 [n], M [T, n, m], q [T, n],
+    r [T, m], qT [n]; c may be None); returns (x [T + 1, n], u [T, m]),
+    differentiable with respect to every tensor argument (the adjoint, with
+    the level checkpoint of `checkpoint`).  It waits for the solve to check
+    the status and raises LQError on a numerical failure."""
+    if isinstance(plan_or_A, Plan):
+        return _solve_plan(plan_or_A, *args, **kw)
+    return _solve_tensors(plan_or_A, *args, **kw)
+
+
+_PLAN_CACHE: dict = {}
+
+
+def _cached_plan(sizes, precision: str, seg_len: int) -> Plan:
+    """Plans of the tensor-form solves, kept for the last 32 size lists."""
+    key = (tuple(sizes), precision, int(seg_len))
+    p = _PLAN_CACHE.get(key)
+    if p is None:
+        if len(_PLAN_CACHE) >= 32:
+            _PLAN_CACHE.pop(next(iter(_PLAN_CACHE)))
+        p = Plan([z[0] for z in sizes], [z[1] for z in sizes], [z[2] for z in sizes], precision=precision,
+                 seg_len=seg_len)
+        _PLAN_CACHE[key] = p
+    return p
+
+
+_OPTIONAL = ("c", "M", "q", "r", "qT")
+
+
+def _sizes_of(A, B):
+    if A.dim() != 3 or B.dim() != 3 or A.shape[1] != A.shape[2] or B.shape[:2] != A.shape[:2]:
+        raise ValueError("A must be [T, n, n] and B [T, n, m]")
+    return int(A.shape[1]), int(B.shape[2]), int(A.shape[0])
+
+
+def _stage_shapes(n, m, T):
+    return {"A": (T, n, n), "B": (T, n, m), "c": (T, n), "Q": (T, n, n), "R": (T, m, m), "QT": (n, n), "x0": (n,),
+            "M": (T, n, m), "q": (T, n), "r": (T, m), "qT": (n,)}
+
+
+def _packed(problems, sizes):
+    """Flat packed fields of a list of problem dicts (autograd-preserving); an
+    optional field absent from every problem stays None, absent from some is
+    zero there."""
+    out = {}
+    for f in LQSolveFunction.NAMES:
+        have = [p.get(f) is not None for p in problems]
+        if f in _OPTIONAL and not any(have):
+            out[f] = None
+            continue
+        parts = []
+        for p, (n, m, T) in zip(problems, sizes):
+            shp = _stage_shapes(n, m, T)[f]
+            t = p.get(f)
+            if t is None:
+                if f not in _OPTIONAL:
+                    raise ValueError(f"missing {f}")
+                t = torch.zeros(shp, dtype=torch.float64, device=problems[0]["A"].device)
+            if tuple(t.shape) != shp:
+                raise ValueError(f"{f} has shape {tuple(t.shape)}, expected {shp}")
+            parts.append(t.to(torch.float64).contiguous().reshape(-1))
+        out[f] = torch.cat(parts) if len(parts) > 1 else parts[0]
+    return out
+
+
+def _check_status(status):
+    bad = torch.nonzero(status).flatten().tolist()
+    if bad:
+        w = int(status[bad[0]])
+        raise LQError(f"lq_solve (instance {bad[0]}, stage {w >> 8})", -(w & 0xFF))
+
+
+def _solve_tensors(A, B, c, Q, R, QT, x0, *, M=None, q=None, r=None, qT=None, precision="fp64", seg_len=0,
+                   checkpoint=1):
+    n, m, T = _sizes_of(A, B)
+    prob = {"A": A, "B": B, "c": c, "Q": Q, "R": R, "QT": QT, "x0": x0, "M": M, "q": q, "r": r, "qT": qT}
+    pk = _packed([prob], [(n, m, T)])
+    plan = _cached_plan([(n, m, T)], precision, seg_len)
+    x, u, status = solve_diff(plan, *[pk[f] for f in LQSolveFunction.NAMES], checkpoint=checkpoint)
+    _check_status(status)
+    return x.view(T + 1, n), u.view(T, m)
+
+
+def solve_batch(problems, *, precision="fp64", seg_len=0, checkpoint=1):
+    """A ragged batch given as a list of problem dicts (the tensors of the
+    tensor form of solve; sizes may differ, optional fields may be absent):
+    one batched, differentiable solve; returns a list of (x [T+1, n],
+    u [T, m]).  Waits to check the status, as solve does."""
+    sizes = [_sizes_of(p["A"], p["B"]) for p in problems]
+    pk = _packed(problems, sizes)
+    plan = _cached_plan(sizes, precision, seg_len)
+    x, u, status = solve_diff(plan, *[pk[f] for f in LQSolveFunction.NAMES], checkpoint=checkpoint)
+    _check_status(status)
+    out, ox, ou = [], 0, 0
+    for n, m, T in sizes:
+        out.append((x[ox:ox + (T + 1) * n].view(T + 1, n), u[ou:ou + T * m].view(T, m)))
+        ox += (T + 1) * n
+        ou += T * m
+    return out
+
+
+def _solve_plan(plan: Plan, prob: dict, *, materialise_elements: bool = False, fused: bool = True, workspace=None,
+                stream=None, rollout: str = "affine") -> dict:
     """lq_solve (fused = False: lq_scan_solve then lq_rollout; rollout = "cv":
     lq_scan_solve then lq_rollout_cv); returns flat packed device tensors and
     the status array."""

@@ -419,3 +419,57 @@ def test_autograd_checkpoint_modes(lq, checkpoint):
         assert held < value_bytes / 2, (held, value_bytes)
     print(f"checkpoint={checkpoint}: {held / 2**20:.2f} MiB held after forward "
           f"(value arrays {value_bytes / 2**20:.2f} MiB)")
+
+
+def test_tensor_form_solve_and_batch(lq):
+    """lqscan.solve on stage-major tensors and lqscan.solve_batch on a list of
+    problems of different sizes: x, u against the oracle (1e-10), gradients
+    through autograd against the oracle's adjoint (1e-9), and a numerical
+    failure raised as LQError with its stage."""
+    rng = np.random.default_rng(94)
+    insts = [W.lq_instance_general(rng, 5, 2, 40), W.lq_instance(rng, 2, 1, 17), W.lq_instance(rng, 12, 4, 64)]
+
+    def tensors(inst, grad=False):
+        d = {}
+        for f, shp in (("A", (inst.T, inst.n, inst.n)), ("B", (inst.T, inst.n, inst.m)), ("c", (inst.T, inst.n)),
+                       ("Q", (inst.T, inst.n, inst.n)), ("R", (inst.T, inst.m, inst.m)), ("QT", (inst.n, inst.n)),
+                       ("x0", (inst.n,)), ("M", (inst.T, inst.n, inst.m)), ("q", (inst.T, inst.n)),
+                       ("r", (inst.T, inst.m)), ("qT", (inst.n,))):
+            v = getattr(inst, f)
+            if v is None:
+                continue
+            d[f] = torch.tensor(np.asarray(v).reshape(shp), dtype=torch.float64, device="cuda", requires_grad=grad)
+        return d
+
+    def ref(inst):
+        o = oracle.lq_solve(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, M=inst.M, q=inst.q, r=inst.r,
+                            qT=inst.qT)
+        g = oracle.lq_adjoint(inst.A, inst.B, inst.c, inst.Q, inst.R, inst.QT, inst.x0, 2 * o["x"], 2 * o["u"],
+                              M=inst.M, q=inst.q, r=inst.r, qT=inst.qT)
+        return o, g
+
+    # one problem, tensor form
+    inst = insts[0]
+    d = tensors(inst, grad=True)
+    x, u = lq.solve(d["A"], d["B"], d.get("c"), d["Q"], d["R"], d["QT"], d["x0"], M=d.get("M"), q=d.get("q"),
+                    r=d.get("r"), qT=d.get("qT"))
+    o, g = ref(inst)
+    assert rel(x.detach().cpu().numpy(), o["x"]) < 1e-10 and rel(u.detach().cpu().numpy(), o["u"]) < 1e-10
+    ((x * x).sum() + (u * u).sum()).backward()
+    for f, t in d.items():
+        assert rel(t.grad.cpu().numpy().reshape(np.shape(g[f])), g[f]) < 1e-9, f
+    # the batch
+    ds = [tensors(i, grad=True) for i in insts]
+    outs = lq.solve_batch(ds)
+    loss = sum((x * x).sum() + (u * u).sum() for x, u in outs)
+    loss.backward()
+    for inst, dd, (x, u) in zip(insts, ds, outs):
+        o, g = ref(inst)
+        assert rel(x.detach().cpu().numpy(), o["x"]) < 1e-10 and rel(u.detach().cpu().numpy(), o["u"]) < 1e-10
+        for f, t in dd.items():
+            assert rel(t.grad.cpu().numpy().reshape(np.shape(g[f])), g[f]) < 1e-9, (inst.n, f)
+    # R indefinite at stage 9: LQError naming the stage
+    bad = tensors(insts[1])
+    bad["R"][9] = -50.0
+    with pytest.raises(lq.LQError, match="stage 9"):
+        lq.solve(bad["A"], bad["B"], bad.get("c"), bad["Q"], bad["R"], bad["QT"], bad["x0"])
