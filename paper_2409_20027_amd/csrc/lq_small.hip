@@ -279,6 +279,7 @@ LQK_DEV bool inv_spd(const double (&X)[R][R], double (&Y)[R][R])
 template <int N, int M>
 struct Stage {
     double A[N][N], B[N][M], c[N], Q[N][N], R[M][M], q[N];
+    double Mx[N][M], r[M];   // cross terms (zero when absent)
 };
 
 template <int N, int M>
@@ -290,18 +291,27 @@ LQK_DEV void load_stage(const ProbPtrs &P, const InstDesc &d, int k, Stage<N, M>
     ldm(P.Q + d.oA + (int64_t)k * N * N, w.Q);
     ldm(P.R + d.oR + (int64_t)k * M * M, w.R);
     ldv(P.q ? P.q + d.oc + (int64_t)k * N : nullptr, w.q);
+    ldm(P.M ? P.M + d.oB + (int64_t)k * N * M : nullptr, w.Mx);
+    ldv(P.r ? P.r + d.og + (int64_t)k * M : nullptr, w.r);
 }
+
+// Stages per chunk of the sweeps: a lane streams its own segment, and a
+// stage of an n <= 2 array fills a fraction of a cache line, so the sweeps
+// issue the loads of CH stages together, while the line is still cached,
+// instead of fetching it again for each stage.
+template <int N>
+constexpr int sweep_chunk() { return N <= 2 ? 4 : 1; }
 
 // The stage element of eq:value-fun-elem-init in place, for cross terms M, r:
 // A - B K_M, c - B K_r, Q - M K_M, q - M K_r with [K_M, K_r] = R^{-1}[M', r]
 // (C = B R^{-1} B' stays implicit: the fold uses B and R).  False if R is not
 // positive definite.
 template <int N, int M>
-LQK_DEV bool schur_cross(const ProbPtrs &P, const InstDesc &d, int k, Stage<N, M> &w)
+LQK_DEV bool schur_cross(Stage<N, M> &w)
 {
-    double Mk[N][M], rk[M], Ri[M][M];
-    ldm(P.M ? P.M + d.oB + (int64_t)k * N * M : nullptr, Mk);
-    ldv(P.r ? P.r + d.og + (int64_t)k * M : nullptr, rk);
+    const auto &Mk = w.Mx;
+    const auto &rk = w.r;
+    double Ri[M][M];
     const bool ok = inv_spd<M>(w.R, Ri);
     double KM[M][N], Kr[M];
 #pragma unroll
@@ -518,11 +528,18 @@ __global__ __launch_bounds__(64) void k_small_value_fold(ProbPtrs P, const InstD
     }
     const bool mr = (P.M != nullptr) || (P.r != nullptr);
     int code = 0, fk = 0;
-    for (int k = k1 - 1; k >= k0; --k) {
-        Stage<N, M> w;
-        load_stage(P, d, k, w);
-        if (mr) note1(schur_cross(P, d, k, w), SERR_NOT_PD, k, code, fk);
-        note1(fold_stage(w, E), SERR_SINGULAR, k, code, fk);
+    constexpr int CH = sweep_chunk<N>();
+    for (int kb = k1 - 1; kb >= k0; kb -= CH) {
+        Stage<N, M> w[CH];
+#pragma unroll
+        for (int j = 0; j < CH; ++j) load_stage(P, d, max(kb - j, k0), w[j]);   // past k0: stage k0 again, unused
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int k = kb - j;
+            if (k < k0) break;
+            if (mr) note1(schur_cross(w[j]), SERR_NOT_PD, k, code, fk);
+            note1(fold_stage(w[j], E), SERR_SINGULAR, k, code, fk);
+        }
     }
     double *o = X + (int64_t)(d.xbase + s) * 3 * TILE;
     store_map(o, E.A, E.b);
@@ -754,151 +771,158 @@ __global__ __launch_bounds__(64) void k_small_value_riccati(ProbPtrs P, const In
         for (int c = 0; c < N; ++c) FA[r][c] = (r == c) ? 1.0 : 0.0;
         Fb[r] = 0.0;
     }
-    for (int k = k1 - 1; k >= k0; --k) {
-        Stage<N, M> w;
-        load_stage(P, d, k, w);
-        double Mk[N][M], rk[M];
-        ldm(mr && P.M ? P.M + d.oB + (int64_t)k * N * M : nullptr, Mk);
-        ldv(mr && P.r ? P.r + d.og + (int64_t)k * M : nullptr, rk);
-        // Sc = S'c + s',  SA = S'A,  SB = S'B
-        double Sc[N], SA[N][N], SB[N][M];
+    constexpr int CH = sweep_chunk<N>();
+    for (int kb = k1 - 1; kb >= k0; kb -= CH) {
+        Stage<N, M> ws[CH];
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = sv[r];
+        for (int j = 0; j < CH; ++j) load_stage(P, d, max(kb - j, k0), ws[j]);   // past k0: stage k0 again, unused
 #pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) t += S[r][k2] * w.c[k2];
-            Sc[r] = t;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double u = 0.0;
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.A[k2][c];
-                SA[r][c] = u;
-            }
-#pragma unroll
-            for (int a = 0; a < M; ++a) {
-                double u = 0.0;
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.B[k2][a];
-                SB[r][a] = u;
-            }
-        }
-        double Quu[M][M], Qux[M][N], qu[M];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-#pragma unroll
-            for (int b2 = 0; b2 < M; ++b2) {
-                double t = w.R[a][b2];
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SB[k2][b2];
-                Quu[a][b2] = t;
-            }
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double t = Mk[c][a];
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SA[k2][c];
-                Qux[a][c] = t;
-            }
-            double t = rk[a];
-#pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * Sc[k2];
-            qu[a] = t;
-        }
-        double Qi[M][M];
-        const bool pd = inv_spd<M>(Quu, Qi);
-        double G[M][N], g[M];
-#pragma unroll
-        for (int a = 0; a < M; ++a) {
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double t = 0.0;
-#pragma unroll
-                for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * Qux[b2][c];
-                G[a][c] = t;
-            }
-            double t = 0.0;
-#pragma unroll
-            for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * qu[b2];
-            g[a] = t;
-        }
-        double Sn[N][N], sn[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double t = w.Q[r][c];
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * SA[k2][c];
-#pragma unroll
-                for (int a = 0; a < M; ++a) t += Qux[a][r] * G[a][c];
-                Sn[r][c] = t;
-            }
-            double t = w.q[r];
-#pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * Sc[k2];
-#pragma unroll
-            for (int a = 0; a < M; ++a) t += Qux[a][r] * g[a];
-            sn[r] = t;
-        }
-        sym(Sn);
-        bool fin = true;
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            fin = fin && isfinite(sn[r]);
-#pragma unroll
-            for (int c = 0; c < N; ++c) fin = fin && isfinite(Sn[r][c]);
-        }
-        note1(fin, SERR_NONFINITE, k, code, fk);
-        note1(pd, SERR_NOT_PD, k, code, fk);
-        stm(V.S + d.oS + (int64_t)k * N * N, Sn);
-        stv(V.s + d.os + (int64_t)k * N, sn);
-        stm(V.G + d.oG + (int64_t)k * M * N, G);
-        stv(V.g + d.og + (int64_t)k * M, g);
-        if (roll) {
-            // Phi <- Phi F~_k:  FA <- FA (A + B Gamma),  Fb <- FA (c + B gamma) + Fb
-            double F[N][N], f[N];
+        for (int j = 0; j < CH; ++j) {
+            const int k = kb - j;
+            if (k < k0) break;
+            const Stage<N, M> &w = ws[j];
+            const auto &Mk = w.Mx;
+            const auto &rk = w.r;
+            // Sc = S'c + s',  SA = S'A,  SB = S'B
+            double Sc[N], SA[N][N], SB[N][M];
 #pragma unroll
             for (int r = 0; r < N; ++r) {
-                double t = w.c[r];
+                double t = sv[r];
 #pragma unroll
-                for (int a = 0; a < M; ++a) t += w.B[r][a] * g[a];
-                f[r] = t;
-#pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    double u = w.A[r][c];
-#pragma unroll
-                    for (int a = 0; a < M; ++a) u += w.B[r][a] * G[a][c];
-                    F[r][c] = u;
-                }
-            }
-            double nA[N][N], nb[N];
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                double t = Fb[r];
-#pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) t += FA[r][k2] * f[k2];
-                nb[r] = t;
+                for (int k2 = 0; k2 < N; ++k2) t += S[r][k2] * w.c[k2];
+                Sc[r] = t;
 #pragma unroll
                 for (int c = 0; c < N; ++c) {
                     double u = 0.0;
 #pragma unroll
-                    for (int k2 = 0; k2 < N; ++k2) u += FA[r][k2] * F[k2][c];
-                    nA[r][c] = u;
+                    for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.A[k2][c];
+                    SA[r][c] = u;
+                }
+#pragma unroll
+                for (int a = 0; a < M; ++a) {
+                    double u = 0.0;
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) u += S[r][k2] * w.B[k2][a];
+                    SB[r][a] = u;
+                }
+            }
+            double Quu[M][M], Qux[M][N], qu[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+#pragma unroll
+                for (int b2 = 0; b2 < M; ++b2) {
+                    double t = w.R[a][b2];
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SB[k2][b2];
+                    Quu[a][b2] = t;
+                }
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double t = Mk[c][a];
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * SA[k2][c];
+                    Qux[a][c] = t;
+                }
+                double t = rk[a];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += w.B[k2][a] * Sc[k2];
+                qu[a] = t;
+            }
+            double Qi[M][M];
+            const bool pd = inv_spd<M>(Quu, Qi);
+            double G[M][N], g[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * Qux[b2][c];
+                    G[a][c] = t;
+                }
+                double t = 0.0;
+#pragma unroll
+                for (int b2 = 0; b2 < M; ++b2) t -= Qi[a][b2] * qu[b2];
+                g[a] = t;
+            }
+            double Sn[N][N], sn[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double t = w.Q[r][c];
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * SA[k2][c];
+#pragma unroll
+                    for (int a = 0; a < M; ++a) t += Qux[a][r] * G[a][c];
+                    Sn[r][c] = t;
+                }
+                double t = w.q[r];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += w.A[k2][r] * Sc[k2];
+#pragma unroll
+                for (int a = 0; a < M; ++a) t += Qux[a][r] * g[a];
+                sn[r] = t;
+            }
+            sym(Sn);
+            bool fin = true;
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                fin = fin && isfinite(sn[r]);
+#pragma unroll
+                for (int c = 0; c < N; ++c) fin = fin && isfinite(Sn[r][c]);
+            }
+            note1(fin, SERR_NONFINITE, k, code, fk);
+            note1(pd, SERR_NOT_PD, k, code, fk);
+            stm(V.S + d.oS + (int64_t)k * N * N, Sn);
+            stv(V.s + d.os + (int64_t)k * N, sn);
+            stm(V.G + d.oG + (int64_t)k * M * N, G);
+            stv(V.g + d.og + (int64_t)k * M, g);
+            if (roll) {
+                // Phi <- Phi F~_k:  FA <- FA (A + B Gamma),  Fb <- FA (c + B gamma) + Fb
+                double F[N][N], f[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    double t = w.c[r];
+#pragma unroll
+                    for (int a = 0; a < M; ++a) t += w.B[r][a] * g[a];
+                    f[r] = t;
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        double u = w.A[r][c];
+#pragma unroll
+                        for (int a = 0; a < M; ++a) u += w.B[r][a] * G[a][c];
+                        F[r][c] = u;
+                    }
+                }
+                double nA[N][N], nb[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    double t = Fb[r];
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) t += FA[r][k2] * f[k2];
+                    nb[r] = t;
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        double u = 0.0;
+#pragma unroll
+                        for (int k2 = 0; k2 < N; ++k2) u += FA[r][k2] * F[k2][c];
+                        nA[r][c] = u;
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    Fb[r] = nb[r];
+#pragma unroll
+                    for (int c = 0; c < N; ++c) FA[r][c] = nA[r][c];
                 }
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) {
-                Fb[r] = nb[r];
+                sv[r] = sn[r];
 #pragma unroll
-                for (int c = 0; c < N; ++c) FA[r][c] = nA[r][c];
+                for (int c = 0; c < N; ++c) S[r][c] = Sn[r][c];
             }
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            sv[r] = sn[r];
-#pragma unroll
-            for (int c = 0; c < N; ++c) S[r][c] = Sn[r][c];
         }
     }
     if (roll) {
@@ -990,48 +1014,65 @@ __global__ __launch_bounds__(64) void k_small_roll_apply(ProbPtrs P, ValPtrs V, 
     double xv[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) xv[r] = ye[r * N1 + N];
-    for (int k = k0; k < k1; ++k) {
-        stv(x + d.os + (int64_t)k * N, xv);
-        double A[N][N], B[N][M], c[N], Gm[M][N], g[M];
-        ldm(P.A + d.oA + (int64_t)k * N * N, A);
-        ldm(P.B + d.oB + (int64_t)k * N * M, B);
-        ldv(P.c ? P.c + d.oc + (int64_t)k * N : nullptr, c);
-        ldm(V.G + d.oG + (int64_t)k * M * N, Gm);
-        ldv(V.g + d.og + (int64_t)k * M, g);
-        double uk[M];
+    // Stages are loaded CH at a time, all loads of a chunk issued together:
+    // each lane streams its own segment, and a stage of an n <= 2 array fills
+    // a fraction of a cache line, so loading the next stages while the line
+    // is still cached saves fetching it again for each of them.  Past the
+    // segment's end the last stage is read again (in bounds) and not used.
+    constexpr int CH = (N <= 2) ? 4 : 2;
+    for (int kb = k0; kb < k1; kb += CH) {
+        double A[CH][N][N], B[CH][N][M], c[CH][N], Gm[CH][M][N], g[CH][M], Sk[CH][N][N], sk[CH][N];
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
-            double t = g[a];
-#pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) t += Gm[a][k2] * xv[k2];
-            uk[a] = t;
+        for (int j = 0; j < CH; ++j) {
+            const int k = min(kb + j, k1 - 1);
+            ldm(P.A + d.oA + (int64_t)k * N * N, A[j]);
+            ldm(P.B + d.oB + (int64_t)k * N * M, B[j]);
+            ldv(P.c ? P.c + d.oc + (int64_t)k * N : nullptr, c[j]);
+            ldm(V.G + d.oG + (int64_t)k * M * N, Gm[j]);
+            ldv(V.g + d.og + (int64_t)k * M, g[j]);
+            if (lam) {
+                ldm(V.S + d.oS + (int64_t)k * N * N, Sk[j]);
+                ldv(V.s + d.os + (int64_t)k * N, sk[j]);
+            }
         }
-        stv(u + d.og + (int64_t)k * M, uk);
-        if (lam) {
-            double Sk[N][N], sk[N], l[N];
-            ldm(V.S + d.oS + (int64_t)k * N * N, Sk);
-            ldv(V.s + d.os + (int64_t)k * N, sk);
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int k = kb + j;
+            if (k >= k1) break;
+            stv(x + d.os + (int64_t)k * N, xv);
+            double uk[M];
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                double t = g[j][a];
+#pragma unroll
+                for (int k2 = 0; k2 < N; ++k2) t += Gm[j][a][k2] * xv[k2];
+                uk[a] = t;
+            }
+            stv(u + d.og + (int64_t)k * M, uk);
+            if (lam) {
+                double l[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    double t = sk[j][r];
+#pragma unroll
+                    for (int k2 = 0; k2 < N; ++k2) t += Sk[j][r][k2] * xv[k2];
+                    l[r] = t;
+                }
+                stv(lam + d.os + (int64_t)k * N, l);
+            }
+            double xn[N];
 #pragma unroll
             for (int r = 0; r < N; ++r) {
-                double t = sk[r];
+                double t = c[j][r];
 #pragma unroll
-                for (int k2 = 0; k2 < N; ++k2) t += Sk[r][k2] * xv[k2];
-                l[r] = t;
+                for (int k2 = 0; k2 < N; ++k2) t += A[j][r][k2] * xv[k2];
+#pragma unroll
+                for (int a = 0; a < M; ++a) t += B[j][r][a] * uk[a];
+                xn[r] = t;
             }
-            stv(lam + d.os + (int64_t)k * N, l);
+#pragma unroll
+            for (int r = 0; r < N; ++r) xv[r] = xn[r];
         }
-        double xn[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = c[r];
-#pragma unroll
-            for (int k2 = 0; k2 < N; ++k2) t += A[r][k2] * xv[k2];
-#pragma unroll
-            for (int a = 0; a < M; ++a) t += B[r][a] * uk[a];
-            xn[r] = t;
-        }
-#pragma unroll
-        for (int r = 0; r < N; ++r) xv[r] = xn[r];
     }
     if (k1 == d.T) {
         stv(x + d.os + (int64_t)d.T * N, xv);
