@@ -1129,29 +1129,38 @@ __global__ __launch_bounds__(64) void k_small_costate_fold(NmpcWork Wk, const In
 #pragma unroll
         for (int c = 0; c < N; ++c) F[r][c] = (r == c) ? 1.0 : 0.0;
     }
-    for (int k = k0; k < k1; ++k) {
-        double A[N][N], g[N];
-        ldm(Wk.A + d.oA + (int64_t)k * N * N, A);
-        ldv(Wk.g + d.oc + (int64_t)k * N, g);
-        double nF[N][N];
+    constexpr int CH = (N <= 2) ? 4 : 2;   // stages loaded together, as in the sweeps
+    for (int kb = k0; kb < k1; kb += CH) {
+        double A[CH][N][N], g[CH][N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = e[r];
-#pragma unroll
-            for (int j = 0; j < N; ++j) t += F[r][j] * g[j];
-            e[r] = t;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double u = 0.0;
-#pragma unroll
-                for (int j = 0; j < N; ++j) u += F[r][j] * A[c][j];   // (F A_k')_{rc}
-                nF[r][c] = u;
-            }
+        for (int j = 0; j < CH; ++j) {
+            const int k = min(kb + j, k1 - 1);
+            ldm(Wk.A + d.oA + (int64_t)k * N * N, A[j]);
+            ldv(Wk.g + d.oc + (int64_t)k * N, g[j]);
         }
 #pragma unroll
-        for (int r = 0; r < N; ++r)
+        for (int j = 0; j < CH; ++j) {
+            if (kb + j >= k1) break;
+            double nF[N][N];
 #pragma unroll
-            for (int c = 0; c < N; ++c) F[r][c] = nF[r][c];
+            for (int r = 0; r < N; ++r) {
+                double t = e[r];
+#pragma unroll
+                for (int i2 = 0; i2 < N; ++i2) t += F[r][i2] * g[j][i2];
+                e[r] = t;
+#pragma unroll
+                for (int c = 0; c < N; ++c) {
+                    double u = 0.0;
+#pragma unroll
+                    for (int i2 = 0; i2 < N; ++i2) u += F[r][i2] * A[j][c][i2];   // (F A_k')_{rc}
+                    nF[r][c] = u;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+#pragma unroll
+                for (int c = 0; c < N; ++c) F[r][c] = nF[r][c];
+        }
     }
     store_map(Y + (int64_t)(d.xbase + s) * TILE, F, e);
 }
@@ -1175,20 +1184,31 @@ __global__ __launch_bounds__(64) void k_small_costate_apply(NmpcWork Wk, const I
     double F[N][N], l[N];
     load_map(Yfin + (int64_t)(d.xbase + s + 1) * TILE, F, l);
     if (s == d.nseg - 1) stv(lam + (int64_t)d.T * N, l);
-    for (int k = k1 - 1; k >= k0; --k) {
-        double A[N][N], g[N], ln[N];
-        ldm(Wk.A + d.oA + (int64_t)k * N * N, A);
-        ldv(Wk.g + d.oc + (int64_t)k * N, g);
+    constexpr int CH = (N <= 2) ? 4 : 2;
+    for (int kb = k1 - 1; kb >= k0; kb -= CH) {
+        double A[CH][N][N], g[CH][N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = g[r];
-#pragma unroll
-            for (int j = 0; j < N; ++j) t += A[j][r] * l[j];   // (A_k' lambda)_r
-            ln[r] = t;
+        for (int j = 0; j < CH; ++j) {
+            const int k = max(kb - j, k0);
+            ldm(Wk.A + d.oA + (int64_t)k * N * N, A[j]);
+            ldv(Wk.g + d.oc + (int64_t)k * N, g[j]);
         }
 #pragma unroll
-        for (int r = 0; r < N; ++r) l[r] = ln[r];
-        stv(lam + (int64_t)k * N, l);
+        for (int j = 0; j < CH; ++j) {
+            const int k = kb - j;
+            if (k < k0) break;
+            double ln[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                double t = g[j][r];
+#pragma unroll
+                for (int i2 = 0; i2 < N; ++i2) t += A[j][i2][r] * l[i2];   // (A_k' lambda)_r
+                ln[r] = t;
+            }
+#pragma unroll
+            for (int r = 0; r < N; ++r) l[r] = ln[r];
+            stv(lam + (int64_t)k * N, l);
+        }
     }
 }
 
