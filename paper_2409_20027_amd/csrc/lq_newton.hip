@@ -37,7 +37,7 @@
 
 namespace lqk {
 
-// Sequential pieces run on one lane; the state dimension is at most 15.
+// Largest state and control dimensions of the Newton kernels' per-lane arrays.
 constexpr int NXMAX = 15;
 constexpr int NUMAX = MMAX;
 
