@@ -247,6 +247,96 @@ LQK_DEV void jsincos(float a, float &s, float &c) { sincos_rt(a, s, c); }
 LQK_DEV double jrecip(double a) { return 1.0 / a; }
 LQK_DEV float jrecip(float a) { return 1.0f / a; }
 
+// First-order forward-mode number over NZ variables (value and gradient):
+// the Jacobians of the parallel rollout need no second derivatives.
+template <int NZ>
+struct Dual {
+    double v;
+    double g[NZ];
+};
+template <int NZ>
+LQK_DEV Dual<NZ> dvar(double v, int i)
+{
+    Dual<NZ> a;
+    a.v = v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) a.g[p] = (p == i) ? 1.0 : 0.0;
+    return a;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> operator+(const Dual<NZ> &a, const Dual<NZ> &b)
+{
+    Dual<NZ> r;
+    r.v = a.v + b.v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) r.g[p] = a.g[p] + b.g[p];
+    return r;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> operator-(const Dual<NZ> &a, const Dual<NZ> &b)
+{
+    Dual<NZ> r;
+    r.v = a.v - b.v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) r.g[p] = a.g[p] - b.g[p];
+    return r;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> operator*(double c, const Dual<NZ> &a)
+{
+    Dual<NZ> r;
+    r.v = c * a.v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) r.g[p] = c * a.g[p];
+    return r;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> operator+(double c, const Dual<NZ> &a)
+{
+    Dual<NZ> r = a;
+    r.v = c + a.v;
+    return r;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> operator*(const Dual<NZ> &a, const Dual<NZ> &b)
+{
+    Dual<NZ> r;
+    r.v = a.v * b.v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) r.g[p] = a.v * b.g[p] + b.v * a.g[p];
+    return r;
+}
+template <int NZ>
+LQK_DEV Dual<NZ> dchain(const Dual<NZ> &a, double v, double d1)
+{
+    Dual<NZ> r;
+    r.v = v;
+#pragma unroll
+    for (int p = 0; p < NZ; ++p) r.g[p] = d1 * a.g[p];
+    return r;
+}
+template <int NZ>
+LQK_DEV void jsincos(const Dual<NZ> &a, Dual<NZ> &js, Dual<NZ> &jc)
+{
+    double s, c;
+    sincos_cw(a.v, s, c);
+    js = dchain(a, s, c);
+    jc = dchain(a, c, -s);
+}
+template <int NZ>
+LQK_DEV Dual<NZ> jsin(const Dual<NZ> &a)
+{
+    double s, c;
+    sincos_cw(a.v, s, c);
+    return dchain(a, s, c);
+}
+template <int NZ>
+LQK_DEV Dual<NZ> jrecip(const Dual<NZ> &a)
+{
+    const double r = 1.0 / a.v;
+    return dchain(a, r, -r * r);
+}
+
 // Pendulum (Sec. V): z = (theta, omega, tau), prm = (g, l, m, b);
 // f = (omega, -(g/l) sin theta + (tau - b omega) / (m l^2)).
 template <typename S, typename RT>

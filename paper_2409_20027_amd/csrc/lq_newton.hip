@@ -31,6 +31,8 @@
 //                            alpha *= nu, nu *= 2
 //   7. k_nmpc_commit         on acceptance the candidate replaces the nominal.
 #include <algorithm>
+#include <cfloat>
+#include <cstdlib>
 
 #include "lq_kernels.hpp"
 #include "lq_models.hpp"
@@ -347,6 +349,274 @@ __global__ __launch_bounds__(ROLL_THREADS) void k_nmpc_rollout_tanh(NmpcPtrs N, 
                                  du, uout, t - 64, ROLL_THREADS - 64);
         }
         __syncthreads();
+    }
+}
+
+// One step of the discretised dynamics, x+ = x + h f(x, u), in the arithmetic
+// of the sequential rollouts above, and its Jacobian F = I + h df/dx (the
+// pendulum and cart-pole by first-order forward mode).
+template <int MODEL, int NX, int NU>
+LQK_DEV void step_jac(const NmpcPtrs &N, const double (&x)[NX], const double (&u)[NU], double (&xn)[NX],
+                      double (&F)[NX][NX])
+{
+    if constexpr (MODEL == MODEL_TANH) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            double z = 0.0, bu = 0.0;
+#pragma unroll
+            for (int j = 0; j < NX; ++j) z += N.W[i * NX + j] * x[j];
+#pragma unroll
+            for (int j = 0; j < NU; ++j) bu += N.Bm[i * NU + j] * u[j];
+            const double th = tanh_em1(z);
+            xn[i] = x[i] + N.h * (th + bu);
+            const double dth = 1.0 - th * th;
+#pragma unroll
+            for (int j = 0; j < NX; ++j) F[i][j] = ((i == j) ? 1.0 : 0.0) + N.h * (dth * N.W[i * NX + j]);
+        }
+    } else {
+        double z[NX + 1], f[NX];
+        Dual<NX> zd[NX + 1], fd[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            z[i] = x[i];
+            zd[i] = dvar<NX>(x[i], i);
+        }
+        z[NX] = u[0];
+        zd[NX] = dvar<NX>(u[0], -1);
+        if constexpr (MODEL == MODEL_PENDULUM) {
+            pendulum_f<double, double>(N.prm, z, f);
+            pendulum_f<Dual<NX>, double>(N.prm, zd, fd);
+        } else {
+            cartpole_f<double, double>(N.prm, z, f);
+            cartpole_f<Dual<NX>, double>(N.prm, zd, fd);
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            xn[i] = x[i] + N.h * f[i];
+#pragma unroll
+            for (int j = 0; j < NX; ++j) F[i][j] = ((i == j) ? 1.0 : 0.0) + N.h * fd[i].g[j];
+        }
+    }
+}
+
+// Maximum of v over the block (PAR_NT threads; NaN-free inputs).
+constexpr int PAR_NT = 256, PAR_SMAX = 4, PAR_ITMAX = 12;
+LQK_DEV double block_max(double v, double *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int t = threadIdx.x;
+    __syncthreads();   // red is free (its previous use has been read)
+    if ((t & 63) == 0) red[t >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+#pragma unroll
+    for (int w = 1; w < PAR_NT / 64; ++w) r = fmax(r, red[w]);
+    return r;
+}
+
+// The candidate's nonlinear rollout in parallel over time (not in the paper,
+// which takes the LQ step's states): Newton's method on the defects
+// d_k = x_k + h f(x_k, u_k) - x_{k+1} of a trajectory, started from the LQ
+// step's prediction x + dx.  An iteration solves the linearised recursion
+// delta_{k+1} = F_k delta_k + d_k, delta_0 = 0, with an affine-map scan over
+// the block's threads and sets x_{k+1} += delta_{k+1}.  It stops once every
+// defect is within 8 ulps of the trajectory's largest entry (the sequential
+// recursion's own rounding); without that after PAR_ITMAX iterations, or with
+// a defect that is not finite, thread 0 runs the sequential recursion
+// instead.  One block of PAR_NT threads per instance, each thread
+// S = ceil(T / PAR_NT) <= PAR_SMAX consecutive stages whose controls,
+// Jacobians and defects stay in its registers.
+template <int MODEL, int NX, int NU>
+__global__ __launch_bounds__(PAR_NT) void k_nmpc_rollout_par(NmpcPtrs N, const double *__restrict__ u,
+                                                             const double *__restrict__ du,
+                                                             const double *__restrict__ xnom,
+                                                             const double *__restrict__ dx, double *xout,
+                                                             double *uout, const double *lvl)
+{
+    constexpr int NM = NX * NX + NX;
+    __shared__ double sm[PAR_NT * NM];
+    __shared__ double red[PAR_NT / 64];
+    const int b = blockIdx.x;
+    if (level_done(lvl, b)) return;   // uniform over the block
+    const int T = N.T, t = threadIdx.x;
+    const int S = (T + PAR_NT - 1) / PAR_NT;
+    const int k0 = min(t * S, T), k1 = min(k0 + S, T);
+    u += (int64_t)b * T * NU;
+    du += (int64_t)b * T * NU;
+    uout += (int64_t)b * T * NU;
+    xout += (int64_t)b * (T + 1) * NX;
+    xnom += (int64_t)b * (T + 1) * NX;
+    dx += (int64_t)b * (T + 1) * NX;
+    double uk[PAR_SMAX][NU];
+#pragma unroll
+    for (int s = 0; s < PAR_SMAX; ++s) {
+        const int k = k0 + s;
+        if (k >= k1) break;
+#pragma unroll
+        for (int a = 0; a < NU; ++a) {
+            const double v = u[k * NU + a] + du[k * NU + a];
+            uk[s][a] = v;
+            uout[k * NU + a] = v;
+        }
+        // the start trajectory x + dx, rows k0 + 1 .. k1
+#pragma unroll
+        for (int i = 0; i < NX; ++i) xout[(k + 1) * NX + i] = xnom[(k + 1) * NX + i] + dx[(k + 1) * NX + i];
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int i = 0; i < NX; ++i) xout[i] = N.x0[(int64_t)b * NX + i];
+    }
+    __syncthreads();
+    bool done = false, bad = false;
+    for (int it = 0; it < PAR_ITMAX; ++it) {
+        double F[PAR_SMAX][NX][NX], dd[PAR_SMAX][NX], xo[PAR_SMAX][NX];
+        double dmax = 0.0, xmax = 0.0;
+        bool fin = true;
+#pragma unroll
+        for (int s = 0; s < PAR_SMAX; ++s) {
+            const int k = k0 + s;
+            if (k >= k1) break;
+            double xk[NX], xn[NX];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                xk[i] = xout[k * NX + i];
+                xo[s][i] = xout[(k + 1) * NX + i];
+            }
+            step_jac<MODEL, NX, NU>(N, xk, uk[s], xn, F[s]);
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                dd[s][i] = xn[i] - xo[s][i];
+                fin = fin && isfinite(dd[s][i]);
+                dmax = fmax(dmax, fabs(dd[s][i]));
+                xmax = fmax(xmax, fabs(xn[i]));
+            }
+        }
+        if (block_max(fin ? 0.0 : 1.0, red) > 0.0) {
+            bad = true;
+            break;
+        }
+        const double dall = block_max(dmax, red), xall = block_max(xmax, red);
+        if (dall <= 8.0 * DBL_EPSILON * xall) {
+            done = true;
+            break;
+        }
+        // this thread's stages composed: delta_{k1} = Ph delta_{k0} + ph
+        double Ph[NX][NX], ph[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            ph[i] = 0.0;
+#pragma unroll
+            for (int j = 0; j < NX; ++j) Ph[i][j] = (i == j) ? 1.0 : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < PAR_SMAX; ++s) {
+            if (k0 + s >= k1) break;
+            double nP[NX][NX], np[NX];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                double v = dd[s][i];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) v += F[s][i][j] * ph[j];
+                np[i] = v;
+#pragma unroll
+                for (int j = 0; j < NX; ++j) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NX; ++q) w += F[s][i][q] * Ph[q][j];
+                    nP[i][j] = w;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                ph[i] = np[i];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) Ph[i][j] = nP[i][j];
+            }
+        }
+        // inclusive prefix over threads (Kogge-Stone through LDS):
+        // (Ph, ph) <- (Ph, ph) o (prefix of the threads before)
+        for (int off = 1; off < PAR_NT; off <<= 1) {
+            double *me = sm + t * NM;
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                me[NX * NX + i] = ph[i];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) me[i * NX + j] = Ph[i][j];
+            }
+            __syncthreads();
+            if (t >= off) {
+                const double *o = sm + (t - off) * NM;
+                double nP[NX][NX], np[NX];
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+                    double v = ph[i];
+#pragma unroll
+                    for (int j = 0; j < NX; ++j) v += Ph[i][j] * o[NX * NX + j];
+                    np[i] = v;
+#pragma unroll
+                    for (int j = 0; j < NX; ++j) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int q = 0; q < NX; ++q) w += Ph[i][q] * o[q * NX + j];
+                        nP[i][j] = w;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < NX; ++i) {
+                    ph[i] = np[i];
+#pragma unroll
+                    for (int j = 0; j < NX; ++j) Ph[i][j] = nP[i][j];
+                }
+            }
+            __syncthreads();
+        }
+        // delta at this thread's first stage: the prefix of the threads before
+        // (delta_0 = 0, so only its translation part)
+#pragma unroll
+        for (int i = 0; i < NX; ++i) sm[t * NM + NX * NX + i] = ph[i];
+        __syncthreads();
+        double de[NX];
+#pragma unroll
+        for (int i = 0; i < NX; ++i) de[i] = (t > 0) ? sm[(t - 1) * NM + NX * NX + i] : 0.0;
+#pragma unroll
+        for (int s = 0; s < PAR_SMAX; ++s) {
+            const int k = k0 + s;
+            if (k >= k1) break;
+            double nd[NX];
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                double v = dd[s][i];
+#pragma unroll
+                for (int j = 0; j < NX; ++j) v += F[s][i][j] * de[j];
+                nd[i] = v;
+            }
+#pragma unroll
+            for (int i = 0; i < NX; ++i) {
+                de[i] = nd[i];
+                xout[(k + 1) * NX + i] = xo[s][i] + de[i];
+            }
+        }
+        __syncthreads();   // the updated trajectory is visible to every thread
+    }
+    if (done) return;
+    (void)bad;
+    // not converged (or not finite): the sequential recursion on thread 0
+    __syncthreads();
+    if (t != 0) return;
+    double x[NX];
+#pragma unroll
+    for (int i = 0; i < NX; ++i) x[i] = N.x0[(int64_t)b * NX + i];
+    for (int k = 0; k < T; ++k) {
+        double ukk[NU], xn[NX], Fd[NX][NX];
+#pragma unroll
+        for (int a = 0; a < NU; ++a) ukk[a] = uout[k * NU + a];
+        step_jac<MODEL, NX, NU>(N, x, ukk, xn, Fd);
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+            x[i] = xn[i];
+            xout[(k + 1) * NX + i] = x[i];
+        }
     }
 }
 
@@ -862,9 +1132,38 @@ static void launch_reduce(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk,
     else
         hipLaunchKernelGGL((k_nmpc_reduce<RB, 0, 0>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
 }
+// The parallel rollout where it applies: horizons of 256 .. PAR_NT * PAR_SMAX
+// stages for the pendulum, the cart-pole and the tanh model with nx <= 4,
+// nu = 1 (LQSCAN_PAR_ROLLOUT=0: always the sequential kernels).
+static bool launch_rollout_par(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk, const double *x,
+                               const double *u)
+{
+    const char *e = getenv("LQSCAN_PAR_ROLLOUT");
+    const bool on = !(e && e[0] == '0' && e[1] == 0);
+    if (!on || N.T < 256 || N.T > PAR_NT * PAR_SMAX || N.nu != 1) return false;
+#define RP(M, X) \
+    hipLaunchKernelGGL((k_nmpc_rollout_par<M, X, 1>), dim3(N.batch), dim3(PAR_NT), 0, st, N, u, Wk.du, x, Wk.dx, \
+                       Wk.xc, Wk.uc, Wk.scal)
+    if (N.model == MODEL_PENDULUM) {
+        RP(MODEL_PENDULUM, 2);
+    } else if (N.model == MODEL_CARTPOLE) {
+        RP(MODEL_CARTPOLE, 4);
+    } else {
+        switch (N.nx) {
+        case 1: RP(MODEL_TANH, 1); break;
+        case 2: RP(MODEL_TANH, 2); break;
+        case 3: RP(MODEL_TANH, 3); break;
+        case 4: RP(MODEL_TANH, 4); break;
+        default: return false;
+        }
+    }
+#undef RP
+    return true;
+}
+
 void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
 {
-    launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc, Wk.scal);
+    if (!launch_rollout_par(st, N, Wk, x, u)) launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc, Wk.scal);
     if (N.T <= 96)
         launch_reduce<64>(st, N, Wk, x, u, scal);
     else if (N.T <= 384)

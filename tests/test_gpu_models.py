@@ -311,3 +311,41 @@ def test_step_after_a_finished_level_is_a_no_op(lq):
     keep = [i for i in range(lq.NMPC_NSCAL) if i != lq.NMPC_LEVEL_DONE]
     assert np.array_equal(sc1[keep], sc2[keep])
     assert np.array_equal(s.x.cpu().numpy(), x1) and np.array_equal(s.u.cpu().numpy(), u1)
+
+
+@pytest.mark.parametrize("case,T", [("tanh", 512), ("tanh", 1024), ("pendulum", 400), ("pendulum", 1000),
+                                    ("cartpole", 1000)])
+def test_parallel_rollout_matches_sequential(lq, monkeypatch, case, T):
+    """One Newton step whose candidate rollout runs in parallel over time
+    (Newton on the defects from the LQ step's prediction, T >= 256) against the
+    same step with the sequential recursion (LQSCAN_PAR_ROLLOUT=0), from the
+    same state after three sequential steps: the same decision, the
+    candidate's cost within 1e-12 and the new trajectory within 1e-12
+    relative.  (The two differ at rounding level: each satisfies the recursion
+    to a few ulps per stage, which unstable dynamics amplify along the horizon,
+    and over many Newton steps the decisions of a barrier run may then part at
+    a round-off decision, as for any rounding change.)"""
+    if case == "tanh":
+        p = W.nmpc_problem(seed=3 if T == 512 else 1, T=T)
+        mu, seg = 0.1, 0
+    else:
+        p = MODELS[case](T)
+        mu, seg = W.IP_MU0, W.IP_SEG_LEN
+
+    def state(mode):
+        monkeypatch.setenv("LQSCAN_PAR_ROLLOUT", "0")
+        s = lq.NewtonMPC(p, seg_len=seg)
+        s.init(W.NMPC_ALPHA0, W.NMPC_NU0)
+        for _ in range(3):
+            s.step(mu)
+        monkeypatch.setenv("LQSCAN_PAR_ROLLOUT", mode)
+        s.step(mu)
+        torch.cuda.synchronize()
+        return s.scal.cpu().numpy(), s.x.cpu().numpy(), s.u.cpu().numpy()
+
+    sp, xp, up = state("1")
+    ss, xs, us = state("0")
+    assert sp[lq.NMPC_ACCEPTED] == ss[lq.NMPC_ACCEPTED]
+    cp, cs = sp[lq.NMPC_COST_NEW], ss[lq.NMPC_COST_NEW]   # +inf for a candidate outside the box
+    assert (cp == cs) if np.isinf(cs) else abs(cp - cs) <= 1e-12 * abs(cs)
+    assert rel(xp, xs) < 1e-12 and rel(up, us) < 1e-12
