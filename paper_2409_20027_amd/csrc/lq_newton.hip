@@ -1132,7 +1132,7 @@ static void launch_reduce(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk,
     else
         hipLaunchKernelGGL((k_nmpc_reduce<RB, 0, 0>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
 }
-// The parallel rollout where it applies: horizons of 256 .. PAR_NT * PAR_SMAX
+// The parallel rollout where it applies: horizons of 64 .. PAR_NT * PAR_SMAX
 // stages for the pendulum, the cart-pole and the tanh model with nx <= 4,
 // nu = 1 (LQSCAN_PAR_ROLLOUT=0: always the sequential kernels).
 static bool launch_rollout_par(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk, const double *x,
@@ -1140,7 +1140,7 @@ static bool launch_rollout_par(hipStream_t st, const NmpcPtrs &N, const NmpcWork
 {
     const char *e = getenv("LQSCAN_PAR_ROLLOUT");
     const bool on = !(e && e[0] == '0' && e[1] == 0);
-    if (!on || N.T < 256 || N.T > PAR_NT * PAR_SMAX || N.nu != 1) return false;
+    if (!on || N.T < 64 || N.T > PAR_NT * PAR_SMAX || N.nu != 1) return false;
 #define RP(M, X) \
     hipLaunchKernelGGL((k_nmpc_rollout_par<M, X, 1>), dim3(N.batch), dim3(PAR_NT), 0, st, N, u, Wk.du, x, Wk.dx, \
                        Wk.xc, Wk.uc, Wk.scal)
