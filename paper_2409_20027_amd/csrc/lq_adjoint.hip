@@ -19,6 +19,42 @@ namespace lqk {
 
 constexpr int ADJ_ERR_NOT_PD = -2;
 
+// body(k, cur) for the stages k = kfirst + dir j, j = 0 .. cnt - 1, each
+// stage's arrays staged through the two LDS buffers stg and stg + SZ.  Two
+// register sets hold stages in flight: stage j + 2's loads are issued before
+// body(j) and written to LDS after body(j + 1), so every load has two stages
+// of products to arrive in.  Both halves of the unrolled pair sit in the loop
+// body (no path back to the top leaves a load's wait to the next pass).
+// Loads issued before the call have arrived when the first stage's data is
+// written, so none of them is waited for inside the loop.
+template <class Regs, class Body>
+LQK_DEV void sweep_ahead2(double *stg, int SZ, const StageArr *arr, int trash, int kfirst, int cnt, int dir,
+                          Body &&body)
+{
+    auto kat = [&](int j) { return kfirst + dir * min(j, cnt - 1); };
+    Regs fa, fb;
+    arr_fetch(arr, kat(0), fa);
+    arr_put(stg, arr, trash, fa);
+    arr_fetch(arr, kat(1), fb);
+    wsync();
+    auto step = [&](int j, const double *cur, double *nxt, Regs &fnew, const Regs &fput)
+                    __attribute__((always_inline)) {
+        // keeps the scheduler from hoisting the next stage's loads above this
+        // stage's write to LDS, whose wait would then cover them too
+        __builtin_amdgcn_sched_barrier(0);
+        arr_fetch(arr, kat(j + 2), fnew);
+        body(kfirst + dir * j, cur);
+        arr_put(nxt, arr, trash, fput);
+        wsync();
+    };
+    int j = 0;
+    for (; j + 1 < cnt; j += 2) {
+        step(j, stg, stg + SZ, fa, fb);
+        step(j + 1, stg + SZ, stg, fb, fa);
+    }
+    if (j < cnt) step(j, stg, stg + SZ, fa, fb);
+}
+
 // Segment fold of the backward maps, Psi_s = Y~_{k0} ... Y~_{k1-1}, kept as
 // Psi' (Psi' <- Y~_k' Psi' is a register product); the block of the last
 // segment also writes the terminal vector map [[0, gx_T], [0, 1]].
@@ -45,7 +81,6 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
     const StageArr arr[5] = {stage_arr(P.A + d.oA, n * n, n * n, oA), stage_arr(J.G + d.oG, m * n, m * n, oG),
                              stage_arr(P.B + d.oB, n * m, n * m, oB), stage_arr(J.gu + d.og, m, m, ou),
                              stage_arr(J.gx + d.os, n, n, ox)};
-    StageRegs<SA, SB, SB, 1, 1> f;
     // A_noc~' = [[A', 0], [0, 1]], Gamma_0~ = [Gamma, 0], B~' = [B', 0], gu and gx in column n
     const GMap gA = gmap_of([&](int r, int c) { return (r < n && c < n) ? oA + c * n + r : (r == n && c == n) ? 1 : 0; });
     const GMap gG = gmap_of([&](int r, int c) { return (r < m && c < n) ? oG + r * n + c : 0; });
@@ -54,22 +89,16 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
     const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(arr, k0, f);
-    arr_put(stg, arr, trash, f);
-    wsync();
     Tile PsiT = tident(n + 1);
-    int b = 0;
-    for (int k = k0; k < k1; ++k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(arr, min(k + 1, k1 - 1), f);
+    // a stage's chain (five products) is shorter than a load's latency: the
+    // loads run two stages ahead
+    sweep_ahead2<StageRegs<SA, SB, SB, 1, 1>>(stg, SZ, arr, trash, k0, k1 - k0, 1, [&](int k, const double *cur) {
         // R(Y~_k) = A_noc~' + Gamma_0~'(B~' + [gu in column n]) + [gx in column n]
         const Tile AnT = gather(cur, gA), G0 = gather(cur, gG), BhT = gather(cur, gB);
         const Tile GU = gather(cur, gU), GX = gather(cur, gX);
         const Tile Yk = tna<1, PR>(G0, tadd(BhT, GU), tadd(AnT, GX));
         PsiT = tnz<NK, PR>(Yk, PsiT);   // (Psi Y~_k)' = Y~_k' Psi'
-        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
-        wsync();
-    }
+    });
     gstore_c(Y + (int64_t)(d.xbase + s) * TILE, ttrans(PsiT, lds), d.n + 1);
 }
 

@@ -88,8 +88,28 @@ __global__ __launch_bounds__(64) void k_affine_ks(const InstDesc *__restrict__ i
     gstore_c(Yout + (int64_t)gx * TILE, ttrans(PT, lds), d.n + 1);
 }
 
+// Rows [0, len) of column col of a tile to dst[0, len) in LDS; the other
+// lanes write to their own slot of trash (64 doubles), so there is no branch.
+LQK_DEV void lds_vec(double *dst, double *trash, const Tile &t, int len, int col)
+{
+    const bool mine = (tcol() == col);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = trow(r);
+        *((mine && i < len) ? dst + i : trash + lane()) = t.v[r];
+    }
+}
+
 // From the state at the segment start: u_k = Gamma~ x~, lambda_k = S~_k x~,
 // x~_{k+1} = A~ x~ + B~ u_k (x~ = [x; 1] in the last column of X).
+//
+// Memory order of a stage k: the stores of stage k - 1's x, u and lambda
+// (from a two-slot LDS ring), then the loads of stage k + 2, then stage k's
+// products, then stage k + 1's data (loaded during stage k - 1) to LDS.  The
+// vector memory counter completes in issue order, so a store issued after a
+// load could only be waited for together with that load; with the stores
+// first, the waits before the next stage's use of their registers leave the
+// later loads in flight, and two stages of products cover each load.
 template <int NK, int PR>
 __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const InstDesc *__restrict__ inst,
                                                    const int32_t *__restrict__ seg_start, int batch,
@@ -99,7 +119,10 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     // stage data through LDS, the next stage's loads in flight during this one
     constexpr int NM = 4 * NK - 1;
     constexpr int SZ = 2 + 2 * NM * NM + 2 * NM + 2 * NM * MMAX + MMAX + 64;
+    constexpr int RS = 2 * NM + MMAX;   // ring slot: x_k, u_k, lambda_k
     __shared__ double stg[2 * SZ];
+    __shared__ double ring[2 * RS + 64];
+    double *otr = ring + 2 * RS;
     const int gs = blockIdx.x;
     const int i = find_inst(seg_start, batch, gs);
     const InstDesc d = inst[i];
@@ -116,7 +139,6 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
                              stage_arr(lam ? V.S + d.oS : nullptr, n * n, n * n, oS),
                              stage_arr(lam ? V.s + d.os : nullptr, n, n, os)};
     constexpr int SA = (NM * NM + 63) / 64;
-    StageRegs<SA, 1, 1, 1, 1, SA, 1> f;
     // Gamma~' = [[Gamma'], [gamma']], A~' = [[A', 0], [c', 1]], B~' = [B', 0], S~ = [[S, s], [s', 0]]
     const GMap gG = gmap_of([&](int r, int c) { return (c < m && r < n) ? oG + c * n + r : (c < m && r == n) ? og + c : 0; });
     const GMap gA = gmap_of([&](int r, int c) {
@@ -128,23 +150,49 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
     });
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(arr, k0, f);
-    arr_put(stg, arr, trash, f);
-    wsync();
+    // The segment's start state is loaded ahead of the first stage's data, so
+    // it has arrived when that data is written to LDS and no wait for it is
+    // left inside the loop.
     Tile X = gload_c(Yfin + (int64_t)(d.xbase + s) * TILE, d.n + 1);   // [[0, x_k0], [0, 1]]
-    int b = 0;
-    for (int k = k0; k < k1; ++k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(arr, min(k + 1, k1 - 1), f);
+    // Two register sets: stage k + 2's loads are issued at the top of stage k
+    // and written to LDS at the end of stage k + 1.
+    StageRegs<SA, 1, 1, 1, 1, SA, 1> fa, fb;
+    arr_fetch(arr, k0, fa);
+    arr_put(stg, arr, trash, fa);
+    arr_fetch(arr, min(k0 + 1, k1 - 1), fb);
+    wsync();
+    double *const xo = x ? x + d.os : nullptr, *const uo = u ? u + d.og : nullptr,
+                 *const lo = lam ? lam + d.os : nullptr;
+    // stage kk's outputs from ring slot sl to memory (cnt = 0: nothing)
+    auto flush = [&](int kk, const double *sl, int cnt) __attribute__((always_inline)) {
+        const int l = lane();
+        bstore(brsrc(xo, (kk + 1) * n), (l < n && cnt) ? 8 * (kk * n + l) : BOOB, sl[l < n ? l : 0]);
+        bstore(brsrc(uo, (kk + 1) * m), (l < m && cnt) ? 8 * (kk * m + l) : BOOB, sl[l < m ? NM + l : 0]);
+        bstore(brsrc(lo, (kk + 1) * n), (l < n && cnt) ? 8 * (kk * n + l) : BOOB, sl[l < n ? NM + MMAX + l : 0]);
+    };
+    auto stage = [&](int k, const double *cur, double *nxt, StageRegs<SA, 1, 1, 1, 1, SA, 1> &fnew,
+                     const StageRegs<SA, 1, 1, 1, 1, SA, 1> &fput) __attribute__((always_inline)) {
+        double *sl = ring + (k & 1) * RS;
+        flush(k - 1, ring + ((k - 1) & 1) * RS, k > k0);
+        arr_fetch(arr, min(k + 2, k1 - 1), fnew);
         const Tile GhT = gather(cur, gG), AhT = gather(cur, gA), BhT = gather(cur, gB);
-        store_vec(x + d.os + (int64_t)k * n, X, n, n);
+        lds_vec(sl, otr, X, n, n);
         const Tile Uk = tnz<NK, PR>(GhT, X);                       // Gamma~ x~
-        store_vec(u + d.og + (int64_t)k * m, Uk, m, n);
-        if (lam) store_vec(lam + d.os + (int64_t)k * n, tnz<NK, PR>(gather(cur, gS), X), n, n);
+        lds_vec(sl + NM, otr, Uk, m, n);
+        lds_vec(sl + NM + MMAX, otr, tnz<NK, PR>(gather(cur, gS), X), n, n);   // zero without lam (S~ reads as 0)
         X = tna<1, PR>(BhT, Uk, tnz<NK, PR>(AhT, X));              // A~ x~ + B~ u
-        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
+        arr_put(nxt, arr, trash, fput);
         wsync();
+    };
+    // Both halves in the loop body (no path skips the second one back to the
+    // top with the first one's loads in flight); an odd last stage after it.
+    int k = k0;
+    for (; k + 1 < k1; k += 2) {
+        stage(k, stg, stg + SZ, fa, fb);
+        stage(k + 1, stg + SZ, stg, fb, fa);
     }
+    if (k < k1) stage(k, stg, stg + SZ, fa, fb);
+    flush(k1 - 1, ring + ((k1 - 1) & 1) * RS, 1);
     if (k1 == d.T) {
         store_vec(x + d.os + (int64_t)d.T * n, X, n, n);
         if (lam) store_vec(lam + d.os + (int64_t)d.T * n, tnz<NK, PR>(load_Sh(V.S, V.s, d, d.T), X), n, n);
