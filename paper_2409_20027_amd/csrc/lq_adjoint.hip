@@ -19,42 +19,6 @@ namespace lqk {
 
 constexpr int ADJ_ERR_NOT_PD = -2;
 
-// body(k, cur) for the stages k = kfirst + dir j, j = 0 .. cnt - 1, each
-// stage's arrays staged through the two LDS buffers stg and stg + SZ.  Two
-// register sets hold stages in flight: stage j + 2's loads are issued before
-// body(j) and written to LDS after body(j + 1), so every load has two stages
-// of products to arrive in.  Both halves of the unrolled pair sit in the loop
-// body (no path back to the top leaves a load's wait to the next pass).
-// Loads issued before the call have arrived when the first stage's data is
-// written, so none of them is waited for inside the loop.
-template <class Regs, class Body>
-LQK_DEV void sweep_ahead2(double *stg, int SZ, const StageArr *arr, int trash, int kfirst, int cnt, int dir,
-                          Body &&body)
-{
-    auto kat = [&](int j) { return kfirst + dir * min(j, cnt - 1); };
-    Regs fa, fb;
-    arr_fetch(arr, kat(0), fa);
-    arr_put(stg, arr, trash, fa);
-    arr_fetch(arr, kat(1), fb);
-    wsync();
-    auto step = [&](int j, const double *cur, double *nxt, Regs &fnew, const Regs &fput)
-                    __attribute__((always_inline)) {
-        // keeps the scheduler from hoisting the next stage's loads above this
-        // stage's write to LDS, whose wait would then cover them too
-        __builtin_amdgcn_sched_barrier(0);
-        arr_fetch(arr, kat(j + 2), fnew);
-        body(kfirst + dir * j, cur);
-        arr_put(nxt, arr, trash, fput);
-        wsync();
-    };
-    int j = 0;
-    for (; j + 1 < cnt; j += 2) {
-        step(j, stg, stg + SZ, fa, fb);
-        step(j + 1, stg + SZ, stg, fb, fa);
-    }
-    if (j < cnt) step(j, stg, stg + SZ, fa, fb);
-}
-
 // Segment fold of the backward maps, Psi_s = Y~_{k0} ... Y~_{k1-1}, kept as
 // Psi' (Psi' <- Y~_k' Psi' is a register product); the block of the last
 // segment also writes the terminal vector map [[0, gx_T], [0, 1]].
@@ -73,7 +37,7 @@ __global__ __launch_bounds__(64) void k_adj_back_fold(ProbPtrs P, AdjPtrs J, con
     if (s == d.nseg - 1)
         gstore_c(Y + (int64_t)(d.xbase + d.nseg) * TILE, load_vec(J.gx + d.os + (int64_t)d.T * n, n, n, n), d.n + 1);
     if (s == 0) return;   // never read: segment s starts from entry s + 1
-    // stage data through LDS, the next stage's loads in flight during this one
+    // stage data through LDS, loaded two stages ahead (sweep_ahead2)
     constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
     constexpr int SZ = 2 + NM * NM + 2 * NM * MMAX + MMAX + NM + 64;
     __shared__ double stg[2 * SZ];
@@ -126,7 +90,7 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     Tile SV = gload_c(Yfin + (int64_t)(d.xbase + s + 1) * TILE, d.n + 1);   // [[0, s~_{k1}], [0, 1]]
     if (s == d.nseg - 1) store_vec(J.st + d.os + (int64_t)d.T * n, SV, n, n);
     int code = 0, fk = 0;
-    // stage data through LDS, the next stage's loads in flight during this one
+    // stage data through LDS, loaded two stages ahead (sweep_ahead2)
     constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
     constexpr int SZ = 2 + 2 * NM * NM + 2 * NM * MMAX + MMAX * MMAX + 2 * NM + MMAX + 64;
     __shared__ double stg[2 * SZ];
@@ -137,7 +101,6 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
                              stage_arr(P.R + d.oR, m * m, m * m, oR),   stage_arr(J.G + d.oG, m * n, m * n, oG),
                              stage_arr(J.S + d.oS + n * n, n * n, n * n, oS), stage_arr(J.s + d.os + n, n, n, os),
                              stage_arr(J.gu + d.og, m, m, ou),          stage_arr(J.gx + d.os, n, n, ox)};
-    StageRegs<SA, SB, 1, SB, SA, 1, 1, 1> f;
     // B~, B~', S~ = [[S, s], [s', 0]], R, A_noc~ = [[A, 0], [0, 1]], Gamma_0~ = [Gamma, 0], gu and gx in column n
     const GMap gBh = gmap_of([&](int r, int c) { return (r < n && c < m) ? oB + r * m + c : 0; });
     const GMap gBt = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
@@ -151,14 +114,9 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
     const GMap gX = gmap_of([&](int r, int c) { return (c == n && r < n) ? ox + r : 0; });
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(arr, k1 - 1, f);
-    arr_put(stg, arr, trash, f);
-    wsync();
     Tile PhiT = tident(n + 1);
-    int b = 0;
-    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(arr, max(k - 1, k0), f);
+    sweep_ahead2<StageRegs<SA, SB, 1, SB, SA, 1, 1, 1>>(stg, SZ, arr, trash, k1 - 1, k1 - k0, -1,
+                                                        [&](int k, const double *cur) {
         const Tile Bh = gather(cur, gBh), BhT = gather(cur, gBt), Sh = gather(cur, gS);
         const Tile Rk = gather(cur, gR), An = gather(cur, gA), G0 = gather(cur, gG);
         const Tile GU = gather(cur, gU), GX = gather(cur, gX);
@@ -178,9 +136,7 @@ __global__ __launch_bounds__(64) void k_adj_back_apply(ProbPtrs P, AdjPtrs J, co
         PhiT = tnz<NK, PR>(tna<1, PR>(BhT, Gt, F), PhiT);   // (Phi F'_k)' = F'_k' Phi'
         SV = tna<NK, PR>(F, SV, tna<1, PR>(G0, GU, GX));
         store_vec(J.st + d.os + (int64_t)k * n, SV, n, n);
-        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
-        wsync();
-    }
+    });
     if (s == 0) gstore_c(Yfwd + (int64_t)d.xbase * TILE, load_vec(nullptr, n, n, n), d.n + 1);   // dx_0 = 0
     if (s < d.nseg - 1) gstore_c(Yfwd + (int64_t)(d.xbase + s + 1) * TILE, ttrans(PhiT, lds), d.n + 1);
     if (code) report(status, d.orig, code, fk);
@@ -200,7 +156,7 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int n = d.n, m = d.m;
     Tile DX = gload_c(Yfin + (int64_t)(d.xbase + s) * TILE, d.n + 1);   // [[0, dx_k0], [0, 1]]
     if (s == 0 && Gr.x0) store_vec(Gr.x0 + d.on, tnz<NK, PR>(load_Sh(J.S, J.st, d, 0), DX), n, n);
-    // stage data through LDS, the next stage's loads in flight during this one
+    // stage data through LDS, loaded two stages ahead (sweep_ahead2)
     constexpr int NM = 4 * NK - 1, SA = (NM * NM + 63) / 64, SB = (NM * MMAX + 63) / 64;
     constexpr int SZ = 2 + 2 * NM * NM + 2 * NM * MMAX + 4 * NM + 2 * MMAX + 64;
     __shared__ double stg[2 * SZ];
@@ -212,7 +168,6 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
                              stage_arr(J.S + d.oS + n * n, n * n, n * n, oS), stage_arr(J.st + d.os + n, n, n, os),
                              stage_arr(J.x + d.os, n, n, ox),           stage_arr(J.u + d.og, m, m, ou),
                              stage_arr(J.lam + d.os + n, n, n, ol)};
-    StageRegs<SB, 1, SB, SA, SA, 1, 1, 1, 1> f;
     // Gamma~' = [[Gamma'], [gamma~']], B~', A_noc~', S~, x, u, lambda in column n
     const GMap gG = gmap_of([&](int r, int c) { return (c < m && r < n) ? oG + c * n + r : (c < m && r == n) ? og + c : 0; });
     const GMap gB = gmap_of([&](int r, int c) { return (r < m && c < n) ? oB + c * m + r : 0; });
@@ -228,13 +183,8 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
     const int iXc = tcol() < n ? ox + tcol() : 0, iUc = tcol() < m ? ou + tcol() : 0;
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(arr, k0, f);
-    arr_put(stg, arr, trash, f);
-    wsync();
-    int b = 0;
-    for (int k = k0; k < k1; ++k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(arr, min(k + 1, k1 - 1), f);
+    sweep_ahead2<StageRegs<SB, 1, SB, SA, SA, 1, 1, 1, 1>>(stg, SZ, arr, trash, k0, k1 - k0, 1,
+                                                           [&](int k, const double *cur) {
         const Tile GhT = gather(cur, gG), BhT = gather(cur, gB), AnT = gather(cur, gA);
         const Tile S1 = gather(cur, gS);
         const d4 x_r = gather(cur, gXr).v, u_r = gather(cur, gUr).v, l1_r = gather(cur, gLr).v;
@@ -244,38 +194,26 @@ __global__ __launch_bounds__(64) void k_adj_fwd_apply(ProbPtrs P, AdjPtrs J, Gra
         const Tile DL1 = tnz<NK, PR>(S1, DXn);                         // S dx' + s~'
         const d4 dx_r = vrows(DX, n), du_r = vrows(DU, n), dl1_r = vrows(DL1, n);
         const double dx_c = vcol(DX, n), du_c = vcol(DU, n);
-        if (Gr.A) {
-            Tile o;
-            o.v = l1_r * dx_c + dl1_r * x_c;
-            gstore_rm(Gr.A + d.oA + (int64_t)k * n * n, o, n, n, n);
-        }
-        if (Gr.B) {
-            Tile o;
-            o.v = l1_r * du_c + dl1_r * u_c;
-            gstore_rm(Gr.B + d.oB + (int64_t)k * n * m, o, n, m, m);
-        }
-        if (Gr.c) store_vec(Gr.c + d.oc + (int64_t)k * n, DL1, n, n);
-        if (Gr.Q) {
-            Tile o;
-            o.v = 0.5 * (dx_r * x_c + x_r * dx_c);
-            gstore_rm(Gr.Q + d.oA + (int64_t)k * n * n, o, n, n, n);
-        }
-        if (Gr.R) {
-            Tile o;
-            o.v = 0.5 * (du_r * u_c + u_r * du_c);
-            gstore_rm(Gr.R + d.oR + (int64_t)k * m * m, o, m, m, m);
-        }
-        if (Gr.M) {
-            Tile o;
-            o.v = dx_r * u_c + x_r * du_c;
-            gstore_rm(Gr.M + d.oB + (int64_t)k * n * m, o, n, m, m);
-        }
-        if (Gr.q) store_vec(Gr.q + d.oc + (int64_t)k * n, DX, n, n);
-        if (Gr.r) store_vec(Gr.r + d.og + (int64_t)k * m, DU, m, n);
+        // Every gradient is formed and stored without a branch (an absent
+        // one goes to an empty range), so that the waits for the loads two
+        // stages ahead count the stores exactly.
+        const int64_t kn = (int64_t)k * n;
+        Tile o;
+        o.v = l1_r * dx_c + dl1_r * x_c;
+        gstore_rm(Gr.A ? Gr.A + d.oA + kn * n : nullptr, o, n, n, n);
+        o.v = l1_r * du_c + dl1_r * u_c;
+        gstore_rm(Gr.B ? Gr.B + d.oB + kn * m : nullptr, o, n, m, m);
+        store_vec(Gr.c ? Gr.c + d.oc + kn : nullptr, DL1, n, n);
+        o.v = 0.5 * (dx_r * x_c + x_r * dx_c);
+        gstore_rm(Gr.Q ? Gr.Q + d.oA + kn * n : nullptr, o, n, n, n);
+        o.v = 0.5 * (du_r * u_c + u_r * du_c);
+        gstore_rm(Gr.R ? Gr.R + d.oR + (int64_t)k * m * m : nullptr, o, m, m, m);
+        o.v = dx_r * u_c + x_r * du_c;
+        gstore_rm(Gr.M ? Gr.M + d.oB + kn * m : nullptr, o, n, m, m);
+        store_vec(Gr.q ? Gr.q + d.oc + kn : nullptr, DX, n, n);
+        store_vec(Gr.r ? Gr.r + d.og + (int64_t)k * m : nullptr, DU, m, n);
         DX = DXn;
-        arr_put(stg + (b ^ 1) * SZ, arr, trash, f);
-        wsync();
-    }
+    });
     if (k1 == d.T) {
         const Tile X = load_vec(J.x + d.os + (int64_t)d.T * n, n, n, -1);
         const d4 dx_r = vrows(DX, n), x_r = vrows(X, n);

@@ -315,8 +315,7 @@ LQK_DEV Tile load_vec(const double *v, int len, int col, int one_row)
 }
 LQK_DEV void store_vec(double *v, const Tile &t, int len, int col)
 {
-    if (!v || len <= 0) return;
-    const __amdgpu_buffer_rsrc_t rs = brsrc(v, len);
+    const __amdgpu_buffer_rsrc_t rs = brsrc(v, len > 0 ? len : 0);   // null or empty: every store dropped
     const bool mine = (tcol() == col);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -423,6 +422,42 @@ LQK_DEV void arr_put(double *buf, const StageArr *a, int trash, const StageRegs<
 {
     int j = 0, o = 0;
     ((put_arr<S>(buf, a[j], trash, f.v + o), o += S, ++j), ...);
+}
+
+// body(k, cur) for the stages k = kfirst + dir j, j = 0 .. cnt - 1, each
+// stage's arrays staged through the two LDS buffers stg and stg + SZ.  Two
+// register sets hold stages in flight: stage j + 2's loads are issued before
+// body(j) and written to LDS after body(j + 1), so every load has two stages
+// of products to arrive in.  Both halves of the unrolled pair sit in the loop
+// body (no path back to the top leaves a load's wait to the next pass).
+// Loads issued before the call have arrived when the first stage's data is
+// written, so none of them is waited for inside the loop.
+template <class Regs, class Body>
+LQK_DEV void sweep_ahead2(double *stg, int SZ, const StageArr *arr, int trash, int kfirst, int cnt, int dir,
+                          Body &&body)
+{
+    auto kat = [&](int j) { return kfirst + dir * min(j, cnt - 1); };
+    Regs fa, fb;
+    arr_fetch(arr, kat(0), fa);
+    arr_put(stg, arr, trash, fa);
+    arr_fetch(arr, kat(1), fb);
+    wsync();
+    auto step = [&](int j, const double *cur, double *nxt, Regs &fnew, const Regs &fput)
+                    __attribute__((always_inline)) {
+        // keeps the scheduler from hoisting the next stage's loads above this
+        // stage's write to LDS, whose wait would then cover them too
+        __builtin_amdgcn_sched_barrier(0);
+        arr_fetch(arr, kat(j + 2), fnew);
+        body(kfirst + dir * j, cur);
+        arr_put(nxt, arr, trash, fput);
+        wsync();
+    };
+    int j = 0;
+    for (; j + 1 < cnt; j += 2) {
+        step(j, stg, stg + SZ, fa, fb);
+        step(j + 1, stg + SZ, stg, fb, fa);
+    }
+    if (j < cnt) step(j, stg, stg + SZ, fa, fb);
 }
 
 // The problem arrays of a value-pass stage: A, c, Q, q, B, R, and with cross

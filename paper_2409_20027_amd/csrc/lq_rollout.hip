@@ -116,7 +116,7 @@ __global__ __launch_bounds__(64) void k_roll_apply(ProbPtrs P, ValPtrs V, const 
                                                    const double *__restrict__ Yfin, double *__restrict__ x,
                                                    double *__restrict__ u, double *__restrict__ lam)
 {
-    // stage data through LDS, the next stage's loads in flight during this one
+    // stage data through LDS, loaded two stages ahead
     constexpr int NM = 4 * NK - 1;
     constexpr int SZ = 2 + 2 * NM * NM + 2 * NM + 2 * NM * MMAX + MMAX + 64;
     constexpr int RS = 2 * NM + MMAX;   // ring slot: x_k, u_k, lambda_k

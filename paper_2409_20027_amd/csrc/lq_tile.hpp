@@ -197,8 +197,9 @@ LQK_DEV Tile gload_rm_t(const double *src, int rows, int cols, int ld, int i0 = 
 // Store the rows x cols block at tile offset (i0, j0) to row-major dst.
 LQK_DEV void gstore_rm(double *dst, const Tile &t, int rows, int cols, int ld, int i0 = 0, int j0 = 0)
 {
-    if (!dst || rows <= 0 || cols <= 0) return;
-    const __amdgpu_buffer_rsrc_t rs = brsrc(dst, (rows - 1) * ld + cols);
+    // No early return: an empty block is an empty range, so a sweep's stores
+    // stay branch-free and its waits for the loads count them exactly.
+    const __amdgpu_buffer_rsrc_t rs = brsrc(dst, (rows > 0 && cols > 0) ? (rows - 1) * ld + cols : 0);
     const int c = tcol() - j0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

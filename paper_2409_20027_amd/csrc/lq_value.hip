@@ -115,9 +115,8 @@ LQK_DEV void note(bool ok, int err, int k, int &code, int &fk)
 }
 
 // Fused element build + fold over stages k1-1 .. k0 (right to left).  The
-// stage data comes through LDS (arr_fetch / arr_put / gather): stage
-// k-1's loads are issued at the top of step k and written to the other buffer
-// after its compute.
+// stage data comes through LDS (sweep_ahead2 / gather), loaded two stages
+// ahead.
 //
 // J^ is symmetrised after every stage, as the Bellman sweep does with S: its
 // update carries a rounding error whose antisymmetric part the Riccati
@@ -132,16 +131,10 @@ LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Ti
     const int n = d.n, m = d.m;
     const StageLayout L = stage_layout(n, m);
     const ValueStage<NK, MR> VS = value_stage<NK, MR>(P, d, L);
-    typename ValueStage<NK, MR>::Regs f;
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(VS.a, k1 - 1, f);
-    arr_put(stg, VS.a, L.trash, f);
-    wsync();
-    int b = 0;
-    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(VS.a, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+    sweep_ahead2<typename ValueStage<NK, MR>::Regs>(stg, SZ, VS.a, L.trash, k1 - 1, k1 - k0, -1,
+                                                     [&](int k, const double *cur) {
         StageRaw<MR> w;
         w.A = gather(cur, gmap_Ah(L, n));
         w.Q = gather(cur, gmap_Qh(L, n));
@@ -155,9 +148,7 @@ LQK_DEV void fold_fused(const ProbPtrs &P, const InstDesc &d, int k0, int k1, Ti
         note(build_from_raw<PR, MR>(w, d, e), ERR_NOT_PD, k, code, fk);
         note(fold_left<NK, NB, PR>(e, U, Ch, Jh, d.m), ERR_SINGULAR, k, code, fk);
         Jh = tsym(Jh, lds);
-        arr_put(stg + (b ^ 1) * SZ, VS.a, L.trash, f);
-        wsync();
-    }
+    });
 }
 
 // The fused fold for the slice count of B~'s rows: NK - 1 when n is a multiple
@@ -373,8 +364,8 @@ __global__ __launch_bounds__(64) void k_value_ks(const InstDesc *__restrict__ in
 // (kept as Phi' across the sweep), and writes the rollout scan's entries:
 // Phi_s at s + 1 (s < nseg - 1) and the constant map of x0 at 0.
 // The sweep over stages k1-1 .. k0 from the carry St.  The stage data comes
-// through LDS as in the fused fold (the loads of stage k-1 are in flight
-// during stage k).  MR: cross terms present; ROLL: fold the rollout maps.
+// through LDS as in the fused fold (loaded two stages ahead).  MR: cross
+// terms present; ROLL: fold the rollout maps.
 template <int NK, int PR, bool MR, bool ROLL>
 LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &V, int k0, int k1, Tile &St,
                            Tile &PhiT, int &code, int &fk, double *lds, double *stg)
@@ -383,16 +374,10 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
     const int n = d.n, m = d.m;
     const StageLayout L = stage_layout(n, m);
     const ValueStage<NK, MR> VS = value_stage<NK, MR>(P, d, L);
-    typename ValueStage<NK, MR>::Regs f;
     stage_consts(stg);
     stage_consts(stg + SZ);
-    arr_fetch(VS.a, k1 - 1, f);
-    arr_put(stg, VS.a, L.trash, f);
-    wsync();
-    int b = 0;
-    for (int k = k1 - 1; k >= k0; --k, b ^= 1) {
-        const double *cur = stg + b * SZ;
-        arr_fetch(VS.a, max(k - 1, k0), f);   // the next stage's loads, in flight during this one
+    sweep_ahead2<typename ValueStage<NK, MR>::Regs>(stg, SZ, VS.a, L.trash, k1 - 1, k1 - k0, -1,
+                                                     [&](int k, const double *cur) {
         const Tile Ah = gather(cur, gmap_Ah(L, n)), Bh = gather(cur, gmap_Bh(L, n, m));
         const Tile Qh = gather(cur, gmap_Qh(L, n)), Rk = gather(cur, gmap_R(L, m));
         const Tile MhT = MR ? gather(cur, gmap_MhT(L, n, m)) : tzero();
@@ -418,9 +403,7 @@ LQK_DEV void riccati_sweep(const ProbPtrs &P, const InstDesc &d, const ValPtrs &
         store_vec(V.s + d.os + (int64_t)k * n, St, n, n);
         gstore_rm(V.G + d.oG + (int64_t)k * m * n, Gh, m, n, n);
         store_vec(V.g + d.og + (int64_t)k * m, Gh, m, n);
-        arr_put(stg + (b ^ 1) * SZ, VS.a, L.trash, f);
-        wsync();
-    }
+    });
 }
 
 // With ckpt != nullptr the last segment of each group of `stride` segments
