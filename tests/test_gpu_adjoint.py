@@ -473,3 +473,13 @@ def test_tensor_form_solve_and_batch(lq):
     bad["R"][9] = -50.0
     with pytest.raises(lq.LQError, match="stage 9"):
         lq.solve(bad["A"], bad["B"], bad.get("c"), bad["Q"], bad["R"], bad["QT"], bad["x0"])
+
+
+@pytest.mark.parametrize("seg_len", [1, 2, 3, 4, 5])
+def test_tile_sweeps_short_and_odd_segments(lq, seg_len):
+    """The tile-path sweeps stage their data two stages ahead in an unrolled
+    pair of stages with an odd last stage after the loop: segments of one to
+    five stages (T = 23, so the last segment is shorter except at L = 1) through
+    the value pass, the rollout and both adjoint sweeps, against the oracle."""
+    inst = W.lq_instance_general(np.random.default_rng(900 + seg_len), 6, 2, 23)
+    check(gpu_grads(lq, [inst], seg_len=seg_len), [inst])
