@@ -524,6 +524,10 @@ static void value_pass(const lq_plan *p, const lqk::ProbPtrs &P, const double *e
     // entries 1 .. nseg-1 of each instance (the last holds the terminal)
     if (p->max_nseg > 2)
         timed(p, LQ_PH_VALUE_SCAN, st, [&] {
+            // a small class with few entries: every level in one workgroup
+            if (p->small && lqk::launch_small_value_scan1(p->sn, p->total_x, st, p->d_inst, p->d_x_start, p->batch,
+                                                          p->max_nseg, Xa, status))
+                return;
             for (int dd = 1; dd < p->max_nseg - 1; dd *= 2) {
                 if (p->small)
                     lqk::launch_small_value_ks(p->sn, p->total_x, st, p->d_inst, p->d_x_start, p->batch, dd, in, o,

@@ -29,6 +29,7 @@
 // Every lane reports its own instance's failures (status word as in the general
 // path: the failure at the largest stage is kept).
 #include <math.h>
+#include <cstdlib>
 
 #include "lq_kernels.hpp"
 
@@ -559,34 +560,33 @@ __global__ __launch_bounds__(64) void k_small_value_fold(ProbPtrs P, const InstD
 //   eta = A1'Y'(eta2 - J2 b1) + eta1,  J = A1'Y'J2 A1 + J1;
 // only (eta, J) once the right operand covers the terminal element.
 // ---------------------------------------------------------------------------
+// The inputs of one combine: the entry's own A~, C~, J~ and its right
+// neighbour's J~ (and A~, C~ unless the neighbour covers the terminal).
 template <int N>
-__global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restrict__ inst,
-                                                       const int32_t *__restrict__ x_start, int batch, int total,
-                                                       int dd, const double *__restrict__ Xin,
-                                                       double *__restrict__ Xout, int32_t *status)
+struct KsIn {
+    double A1[N][N], b1[N], C1[N][N], J1[N][N], v1[N], J2[N][N], v2[N], A2[N][N], b2[N], C2[N][N];
+};
+// a, bp: the entry's and its neighbour's slots, with A~, C~, J~ KS doubles
+// apart (TILE in the scan buffers, (N + 1)^2 in the one-block scan's LDS).
+// LATE: the neighbour's A~ and C~ are loaded by the combine, where they are
+// first used (fewer live registers); otherwise here, with the rest.
+template <int N, int KS, bool LATE>
+LQK_DEV void ks_load(const double *a, const double *bp, bool b_term, KsIn<N> &in)
 {
-    constexpr int N1 = N + 1;
-    const int gx = gid();
-    if (gx >= total) return;
-    const int i = find_inst(x_start, batch, gx);
-    const InstDesc d = inst[i];
-    const int s = gx - d.xbase;
-    const int last = d.nseg - 1;
-    if (s == 0 || s > last) return;
-    const double *a = Xin + (int64_t)gx * 3 * TILE;
-    double *o = Xout + (int64_t)gx * 3 * TILE;
-    if (s + dd > last) {   // final already: carry J~ over
-#pragma unroll
-        for (int r = 0; r < N1 * N1; ++r) o[2 * TILE + r] = a[2 * TILE + r];
-        return;
+    load_map(a, in.A1, in.b1);
+    load_c(a + KS, in.C1);
+    load_jv(a + 2 * KS, in.J1, in.v1);   // v = -eta
+    load_jv(bp + 2 * KS, in.J2, in.v2);
+    if (!LATE && !b_term) {
+        load_map(bp, in.A2, in.b2);
+        load_c(bp + KS, in.C2);
     }
-    const double *bp = Xin + (int64_t)(gx + dd) * 3 * TILE;
-    const bool b_term = (s + 2 * dd - 1 >= last);
-    double A1[N][N], b1[N], C1[N][N], J1[N][N], v1[N], J2[N][N], v2[N];
-    load_map(a, A1, b1);
-    load_c(a + TILE, C1);
-    load_jv(a + 2 * TILE, J1, v1);   // v = -eta
-    load_jv(bp + 2 * TILE, J2, v2);
+}
+// The combine X_s (x) X_{s+dd} of the loaded inputs, stored to slot o; false
+// if I + C1 J2 is singular.
+template <int N, int KS, bool LATE>
+LQK_DEV bool ks_combine_store(KsIn<N> &in, bool b_term, double *o, const double *bp)
+{
     double X[N][N], Y[N][N];
 #pragma unroll
     for (int r = 0; r < N; ++r)
@@ -594,7 +594,7 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
         for (int c = 0; c < N; ++c) {
             double t = (r == c) ? 1.0 : 0.0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) t += C1[r][k] * J2[k][c];
+            for (int k = 0; k < N; ++k) t += in.C1[r][k] * in.J2[k][c];
             X[r][c] = t;
         }
     const bool ok = inv_gj<N>(X, Y);
@@ -602,15 +602,15 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
     double w[N], G[N][N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        double t = -v2[r];
+        double t = -in.v2[r];
 #pragma unroll
-        for (int k = 0; k < N; ++k) t -= J2[r][k] * b1[k];
+        for (int k = 0; k < N; ++k) t -= in.J2[r][k] * in.b1[k];
         w[r] = t;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
             double u = 0.0;
 #pragma unroll
-            for (int k = 0; k < N; ++k) u += J2[r][k] * A1[k][c];
+            for (int k = 0; k < N; ++k) u += in.J2[r][k] * in.A1[k][c];
             G[r][c] = u;
         }
     }
@@ -632,31 +632,32 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
     double Jn[N][N], vn[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        double t = v1[r];   // -eta = -(A1'Y'w + eta1)
+        double t = in.v1[r];   // -eta = -(A1'Y'w + eta1)
 #pragma unroll
-        for (int k = 0; k < N; ++k) t -= A1[k][r] * Yw[k];
+        for (int k = 0; k < N; ++k) t -= in.A1[k][r] * Yw[k];
         vn[r] = t;
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-            double u = J1[r][c];
+            double u = in.J1[r][c];
 #pragma unroll
-            for (int k = 0; k < N; ++k) u += A1[k][r] * YG[k][c];
+            for (int k = 0; k < N; ++k) u += in.A1[k][r] * YG[k][c];
             Jn[r][c] = u;
         }
     }
     sym(Jn);
-    store_jv(o + 2 * TILE, Jn, vn);
+    store_jv(o + 2 * KS, Jn, vn);
     if (!b_term) {
-        double A2[N][N], b2[N], C2[N][N];
-        load_map(bp, A2, b2);
-        load_c(bp + TILE, C2);
+        if constexpr (LATE) {
+            load_map(bp, in.A2, in.b2);
+            load_c(bp + KS, in.C2);
+        }
         // YA = Y A1, y = Y (b1 + C1 eta2), YC = Y C1
         double z[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
-            double t = b1[r];
+            double t = in.b1[r];
 #pragma unroll
-            for (int k = 0; k < N; ++k) t -= C1[r][k] * v2[k];   // eta2 = -v2
+            for (int k = 0; k < N; ++k) t -= in.C1[r][k] * in.v2[k];   // eta2 = -v2
             z[r] = t;
         }
         double YA[N][N], yz[N], YC[N][N];
@@ -671,8 +672,8 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
                 double u = 0.0, x = 0.0;
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    u += Y[r][k] * A1[k][c];
-                    x += Y[r][k] * C1[k][c];
+                    u += Y[r][k] * in.A1[k][c];
+                    x += Y[r][k] * in.C1[k][c];
                 }
                 YA[r][c] = u;
                 YC[r][c] = x;
@@ -681,17 +682,17 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
         double An[N][N], bn[N], T2[N][N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
-            double t = b2[r];
+            double t = in.b2[r];
 #pragma unroll
-            for (int k = 0; k < N; ++k) t += A2[r][k] * yz[k];
+            for (int k = 0; k < N; ++k) t += in.A2[r][k] * yz[k];
             bn[r] = t;
 #pragma unroll
             for (int c = 0; c < N; ++c) {
                 double u = 0.0, x = 0.0;
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    u += A2[r][k] * YA[k][c];
-                    x += A2[r][k] * YC[k][c];
+                    u += in.A2[r][k] * YA[k][c];
+                    x += in.A2[r][k] * YC[k][c];
                 }
                 An[r][c] = u;
                 T2[r][c] = x;
@@ -702,16 +703,93 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
         for (int r = 0; r < N; ++r)
 #pragma unroll
             for (int c = 0; c < N; ++c) {
-                double u = C2[r][c];
+                double u = in.C2[r][c];
 #pragma unroll
-                for (int k = 0; k < N; ++k) u += T2[r][k] * A2[c][k];
+                for (int k = 0; k < N; ++k) u += T2[r][k] * in.A2[c][k];
                 Cn[r][c] = u;
             }
         sym(Cn);
         store_map(o, An, bn);
-        store_c(o + TILE, Cn);
+        store_c(o + KS, Cn);
     }
+    return ok;
+}
+
+template <int N>
+__global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restrict__ inst,
+                                                       const int32_t *__restrict__ x_start, int batch, int total,
+                                                       int dd, const double *__restrict__ Xin,
+                                                       double *__restrict__ Xout, int32_t *status)
+{
+    constexpr int N1 = N + 1;
+    const int gx = gid();
+    if (gx >= total) return;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    const int last = d.nseg - 1;
+    if (s == 0 || s > last) return;
+    const double *a = Xin + (int64_t)gx * 3 * TILE;
+    double *o = Xout + (int64_t)gx * 3 * TILE;
+    if (s + dd > last) {   // final already: carry J~ over
+#pragma unroll
+        for (int r = 0; r < N1 * N1; ++r) o[2 * TILE + r] = a[2 * TILE + r];
+        return;
+    }
+    const bool b_term = (s + 2 * dd - 1 >= last);
+    const double *bp = Xin + (int64_t)(gx + dd) * 3 * TILE;
+    KsIn<N> in;
+    ks_load<N, TILE, true>(a, bp, b_term, in);
+    const bool ok = ks_combine_store<N, TILE, true>(in, b_term, o, bp);
     if (!ok) report1(status, d.orig, SERR_SINGULAR, s * d.L);
+}
+
+// Every level of the suffix scan in one workgroup, for a class (n <= 2) whose
+// scan has at most SCAN1_MAX entries: the entries are copied once into LDS (compact
+// (N+1)^2 blocks), each level reads its inputs into registers, waits for the
+// whole group, and writes its results in place; a barrier replaces the launch
+// between levels.  The final entries are copied back to the entries' slots of
+// X, in place.  Same schedule and arithmetic as the per-level kernel.
+constexpr int SCAN1_MAX = 256;
+template <int N>
+__global__ __launch_bounds__(SCAN1_MAX) void k_small_value_scan1(const InstDesc *__restrict__ inst,
+                                                                  const int32_t *__restrict__ x_start, int batch,
+                                                                  int total, int max_nseg, double *__restrict__ X,
+                                                                  int32_t *status)
+{
+    constexpr int N1 = N + 1, KS = N1 * N1, SL = 3 * KS;
+    __shared__ double sh[SCAN1_MAX * SL];
+    const int t = threadIdx.x;
+    for (int idx = t; idx < total * SL; idx += SCAN1_MAX) {
+        const int e = idx / SL, r = idx - e * SL, kind = r / KS;
+        sh[idx] = X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)];
+    }
+    bool live = t < total;
+    int s = 0, last = 0, orig = 0, L = 0;
+    if (live) {
+        const InstDesc d = inst[find_inst(x_start, batch, t)];
+        s = t - d.xbase;
+        last = d.nseg - 1;
+        orig = d.orig;
+        L = d.L;
+        live = (s != 0 && s <= last);
+    }
+    __syncthreads();
+    bool ok = true;
+    for (int dd = 1; dd < max_nseg - 1; dd *= 2) {
+        const bool act = live && (s + dd <= last);
+        const bool b_term = s + 2 * dd - 1 >= last;
+        KsIn<N> in;
+        if (act) ks_load<N, KS, false>(sh + t * SL, sh + (t + dd) * SL, b_term, in);
+        __syncthreads();
+        if (act && !ks_combine_store<N, KS, false>(in, b_term, sh + t * SL, nullptr)) ok = false;
+        __syncthreads();
+    }
+    if (!ok) report1(status, orig, SERR_SINGULAR, s * L);
+    for (int idx = t; idx < total * SL; idx += SCAN1_MAX) {
+        const int e = idx / SL, r = idx - e * SL, kind = r / KS;
+        X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)] = sh[idx];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1251,6 +1329,23 @@ void launch_small_value_ks(int n, int64_t total, hipStream_t st, const InstDesc 
 #define CALL(N) hipLaunchKernelGGL((k_small_value_ks<N>), dim3(lanes_grid(total)), dim3(64), 0, st, inst, x_start, batch, (int)total, dd, Xin, Xout, status)
     LQK_SMALL_N(n, CALL)
 #undef CALL
+}
+
+bool launch_small_value_scan1(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
+                              int batch, int max_nseg, double *X, int32_t *status)
+{
+    // n <= 2 only: at n = 4 the combine's inputs, all loaded before the
+    // in-place write, no longer fit the vector registers and the one-block
+    // scan was measured slower than the per-level launches
+    const char *e = getenv("LQSCAN_SCAN1");   // "0": the per-level kernels always
+    if (n > 2 || total > SCAN1_MAX || (e && e[0] == '0' && e[1] == 0)) return false;
+    if (n == 1)
+        hipLaunchKernelGGL((k_small_value_scan1<1>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total,
+                           max_nseg, X, status);
+    else
+        hipLaunchKernelGGL((k_small_value_scan1<2>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total,
+                           max_nseg, X, status);
+    return true;
 }
 
 void launch_small_value_riccati(int n, int m, int64_t total, hipStream_t st, ProbPtrs P, const InstDesc *inst,

@@ -126,6 +126,25 @@ def test_small_path_matches_tile_path(lq, monkeypatch):
             assert rel(ga[k], gb[k]) < 1e-12, k
 
 
+@pytest.mark.parametrize("n,m,Ts,L", [(2, 1, [1000], 4), (1, 1, [200, 37, 5], 3), (2, 2, [300, 64, 2, 129], 5),
+                                      (2, 1, [1], 1)])
+def test_one_block_value_scan_equals_per_level(lq, monkeypatch, n, m, Ts, L):
+    """Classes of n <= 2 with at most 256 scan entries run every value-scan
+    level in one workgroup (entries in LDS, a barrier between levels); the same
+    combines as the per-level launches (LQSCAN_SCAN1=0), so both agree to
+    rounding and both match the oracle.  Entry counts 251, 85, 104 and 2."""
+    rng = np.random.default_rng(40 + n + len(Ts))
+    insts = [W.lq_instance_general(rng, n, m, T) if j % 2 else W.lq_instance(rng, n, m, T) for j, T in enumerate(Ts)]
+    a, sa = solve(lq, insts, seg_len=L)
+    monkeypatch.setenv("LQSCAN_SCAN1", "0")
+    b, sb = solve(lq, insts, seg_len=L)
+    assert not sa.any() and not sb.any()
+    check(a, insts)
+    for ga, gb in zip(a, b):
+        for k in KEYS:
+            assert rel(ga[k], gb[k]) < 1e-14, k
+
+
 def test_mixed_precision_plan_on_small_sizes(lq):
     """A mixed-precision plan of small instances (the per-lane path computes in
     FP64): within the mixed bound, in fact within the FP64 bound."""
