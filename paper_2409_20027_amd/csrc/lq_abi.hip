@@ -149,6 +149,11 @@ static int choose_affine_radix(int64_t entries, int device)
 // holds the result.
 static double *affine_scan(const lq_plan *p, hipStream_t st, int suffix, double *in, double *o)
 {
+    // a small class with few entries: every level in one workgroup, in place
+    if (p->small && p->max_nseg > 1 &&
+        lqk::launch_small_affine_scan1(p->sn, p->aff_radix, p->total_x, st, p->d_inst, p->d_x_start, p->batch,
+                                       p->max_nseg, suffix, in))
+        return in;
     for (int64_t dd = 1; dd < p->max_nseg; dd *= p->aff_radix) {
         if (p->small)
             lqk::launch_small_affine_ks(p->sn, p->aff_radix, p->total_x, st, p->d_inst, p->d_x_start, p->batch, (int)dd,

@@ -750,7 +750,7 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
 // whole group, and writes its results in place; a barrier replaces the launch
 // between levels.  The final entries are copied back to the entries' slots of
 // X, in place.  Same schedule and arithmetic as the per-level kernel.
-constexpr int SCAN1_MAX = 256;
+constexpr int SCAN1_MAX = 512;
 template <int N>
 __global__ __launch_bounds__(SCAN1_MAX) void k_small_value_scan1(const InstDesc *__restrict__ inst,
                                                                   const int32_t *__restrict__ x_start, int batch,
@@ -1025,26 +1025,15 @@ __global__ __launch_bounds__(64) void k_small_value_riccati(ProbPtrs P, const In
 // terms outside [0, nseg] left out; the entry no segment reads is skipped.
 // [[F1, e1], [0, 1]] [[F2, e2], [0, 1]] = [[F1 F2, F1 e2 + e1], [0, 1]].
 // ---------------------------------------------------------------------------
-template <int N, int RAD>
-__global__ __launch_bounds__(64) void k_small_affine_ks(const InstDesc *__restrict__ inst,
-                                                        const int32_t *__restrict__ x_start, int batch, int total,
-                                                        int dd, int suffix, const double *__restrict__ Yin,
-                                                        double *__restrict__ Yout)
+// Entry gx's product Y_gx Y_{gx+step} ... over `terms` terms, entries KS
+// doubles apart from base y (TILE in the scan buffers, (N + 1)^2 in LDS).
+template <int N, int KS>
+LQK_DEV void affine_chain(const double *y, int64_t gx, int64_t step, int terms, double (&F)[N][N], double (&e)[N])
 {
-    const int gx = gid();
-    if (gx >= total) return;
-    const int i = find_inst(x_start, batch, gx);
-    const InstDesc d = inst[i];
-    const int s = gx - d.xbase;
-    if (suffix ? (s == 0) : (s == d.nseg)) return;
-    double F[N][N], e[N];
-    load_map(Yin + (int64_t)gx * TILE, F, e);
-    const int avail = suffix ? (d.nseg - s) / dd : s / dd;
-    const int terms = min(RAD - 1, avail);
-    const int64_t step = suffix ? dd : -dd;
+    load_map(y + gx * KS, F, e);
     for (int j = 1; j <= terms; ++j) {
         double F2[N][N], e2[N];
-        load_map(Yin + (gx + j * step) * TILE, F2, e2);
+        load_map(y + (gx + j * step) * KS, F2, e2);
         double nF[N][N], ne[N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
@@ -1067,7 +1056,67 @@ __global__ __launch_bounds__(64) void k_small_affine_ks(const InstDesc *__restri
             for (int c = 0; c < N; ++c) F[r][c] = nF[r][c];
         }
     }
+}
+
+template <int N, int RAD>
+__global__ __launch_bounds__(64) void k_small_affine_ks(const InstDesc *__restrict__ inst,
+                                                        const int32_t *__restrict__ x_start, int batch, int total,
+                                                        int dd, int suffix, const double *__restrict__ Yin,
+                                                        double *__restrict__ Yout)
+{
+    const int gx = gid();
+    if (gx >= total) return;
+    const int i = find_inst(x_start, batch, gx);
+    const InstDesc d = inst[i];
+    const int s = gx - d.xbase;
+    if (suffix ? (s == 0) : (s == d.nseg)) return;
+    const int avail = suffix ? (d.nseg - s) / dd : s / dd;
+    double F[N][N], e[N];
+    affine_chain<N, TILE>(Yin, gx, suffix ? dd : -dd, min(RAD - 1, avail), F, e);
     store_map(Yout + (int64_t)gx * TILE, F, e);
+}
+
+// Every level of an affine-map scan in one workgroup, for a class with at most
+// SCAN1_MAX entries: the entries copied once into LDS, each level's products
+// formed in registers, a barrier, then written in place; the results copied
+// back to the entries' slots of Y, in place.  Same schedule and arithmetic as
+// the per-level kernel.
+template <int N, int RAD>
+__global__ __launch_bounds__(SCAN1_MAX) void k_small_affine_scan1(const InstDesc *__restrict__ inst,
+                                                                   const int32_t *__restrict__ x_start, int batch,
+                                                                   int total, int max_nseg, int suffix,
+                                                                   double *__restrict__ Y)
+{
+    constexpr int N1 = N + 1, KS = N1 * N1;
+    __shared__ double sh[SCAN1_MAX * KS];
+    const int t = threadIdx.x;
+    for (int idx = t; idx < total * KS; idx += SCAN1_MAX) {
+        const int e = idx / KS;
+        sh[idx] = Y[(int64_t)e * TILE + (idx - e * KS)];
+    }
+    bool live = t < total;
+    int s = 0, nseg = 0;
+    if (live) {
+        const InstDesc d = inst[find_inst(x_start, batch, t)];
+        s = t - d.xbase;
+        nseg = d.nseg;
+        live = suffix ? (s != 0) : (s != nseg);
+    }
+    __syncthreads();
+    for (int dd = 1; dd < max_nseg; dd *= RAD) {
+        double F[N][N], e[N];
+        if (live) {
+            const int avail = suffix ? (nseg - s) / dd : s / dd;
+            affine_chain<N, KS>(sh, t, suffix ? dd : -dd, min(RAD - 1, avail), F, e);
+        }
+        __syncthreads();
+        if (live) store_map(sh + t * KS, F, e);
+        __syncthreads();
+    }
+    for (int idx = t; idx < total * KS; idx += SCAN1_MAX) {
+        const int e = idx / KS;
+        Y[(int64_t)e * TILE + (idx - e * KS)] = sh[idx];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1379,6 +1428,33 @@ void launch_small_affine_ks(int n, int radix, int64_t total, hipStream_t st, con
 #undef CALL16
 #undef CALL32
 #undef CALLR
+}
+
+bool launch_small_affine_scan1(int n, int radix, int64_t total, hipStream_t st, const InstDesc *inst,
+                               const int32_t *x_start, int batch, int max_nseg, int suffix, double *Y)
+{
+    const char *e = getenv("LQSCAN_SCAN1");   // "0": the per-level kernels always
+    if (total > SCAN1_MAX || (e && e[0] == '0' && e[1] == 0)) return false;
+#define CALLR(N, RAD) hipLaunchKernelGGL((k_small_affine_scan1<N, RAD>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total, max_nseg, suffix, Y)
+#define CALL2(N) CALLR(N, 2)
+#define CALL4(N) CALLR(N, 4)
+#define CALL8(N) CALLR(N, 8)
+#define CALL16(N) CALLR(N, 16)
+#define CALL32(N) CALLR(N, 32)
+    switch (radix) {
+    case 2: LQK_SMALL_N(n, CALL2) break;
+    case 8: LQK_SMALL_N(n, CALL8) break;
+    case 16: LQK_SMALL_N(n, CALL16) break;
+    case 32: LQK_SMALL_N(n, CALL32) break;
+    default: LQK_SMALL_N(n, CALL4) break;
+    }
+#undef CALL2
+#undef CALL4
+#undef CALL8
+#undef CALL16
+#undef CALL32
+#undef CALLR
+    return true;
 }
 
 void launch_small_costate_fold(int n, int64_t total, hipStream_t st, NmpcWork Wk, const InstDesc *inst,
