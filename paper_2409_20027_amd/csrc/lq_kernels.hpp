@@ -45,8 +45,8 @@ void launch_small_value_fold(int n, int m, int64_t total, hipStream_t st, ProbPt
 void launch_small_value_ks(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                            int batch, int dd, const double *Xin, double *Xout, int32_t *status);
 // Every level of the per-lane value scan in one workgroup (the entries held in
-// LDS); false, launching nothing, unless n <= 2 and the class has at most 512
-// scan entries (LQSCAN_SCAN1=0: never).
+// LDS); false, launching nothing, when the class has more scan entries than
+// 512 at n <= 2, 352 at n = 3, 200 at n = 4 (LQSCAN_SCAN1=0: never).
 bool launch_small_value_scan1(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                               int batch, int max_nseg, double *X, int32_t *status);
 // Every level of a per-lane affine-map scan in one workgroup, in place in Y;

@@ -567,27 +567,31 @@ struct KsIn {
     double A1[N][N], b1[N], C1[N][N], J1[N][N], v1[N], J2[N][N], v2[N], A2[N][N], b2[N], C2[N][N];
 };
 // a, bp: the entry's and its neighbour's slots, with A~, C~, J~ KS doubles
-// apart (TILE in the scan buffers, (N + 1)^2 in the one-block scan's LDS).
-// LATE: the neighbour's A~ and C~ are loaded by the combine, where they are
-// first used (fewer live registers); otherwise here, with the rest.
-template <int N, int KS, bool LATE>
-LQK_DEV void ks_load(const double *a, const double *bp, bool b_term, KsIn<N> &in)
+// apart (TILE in the scan buffers, (N + 1)^2 in the one-block scans' LDS).
+// ks_load reads what the first part of the combine uses (the entry's A~, C~,
+// J~ and the neighbour's J~); the neighbour's A~ and C~ are read by
+// ks_load_ac, where they are first used (fewer live registers).
+template <int N, int KS>
+LQK_DEV void ks_load(const double *a, const double *bp, KsIn<N> &in)
 {
     load_map(a, in.A1, in.b1);
     load_c(a + KS, in.C1);
     load_jv(a + 2 * KS, in.J1, in.v1);   // v = -eta
     load_jv(bp + 2 * KS, in.J2, in.v2);
-    if (!LATE && !b_term) {
-        load_map(bp, in.A2, in.b2);
-        load_c(bp + KS, in.C2);
-    }
 }
-// The combine X_s (x) X_{s+dd} of the loaded inputs, stored to slot o; false
-// if I + C1 J2 is singular.
-template <int N, int KS, bool LATE>
-LQK_DEV bool ks_combine_store(KsIn<N> &in, bool b_term, double *o, const double *bp)
+template <int N, int KS>
+LQK_DEV void ks_load_ac(const double *bp, KsIn<N> &in)
 {
-    double X[N][N], Y[N][N];
+    load_map(bp, in.A2, in.b2);
+    load_c(bp + KS, in.C2);
+}
+// First part of the combine X_s (x) X_{s+dd} (ks_part_j): Y = (I + C1 J2)^{-1}
+// (ks_inv_y, from C1 and J2; false if singular) and the new (eta, J) as (Jn,
+// vn = -eta) (ks_j_rest, from A1, b1, J1, v1, J2, v2).
+template <int N>
+LQK_DEV bool ks_inv_y(const KsIn<N> &in, double (&Y)[N][N])
+{
+    double X[N][N];
 #pragma unroll
     for (int r = 0; r < N; ++r)
 #pragma unroll
@@ -597,7 +601,11 @@ LQK_DEV bool ks_combine_store(KsIn<N> &in, bool b_term, double *o, const double 
             for (int k = 0; k < N; ++k) t += in.C1[r][k] * in.J2[k][c];
             X[r][c] = t;
         }
-    const bool ok = inv_gj<N>(X, Y);
+    return inv_gj<N>(X, Y);
+}
+template <int N>
+LQK_DEV void ks_j_rest(const KsIn<N> &in, const double (&Y)[N][N], double (&Jn)[N][N], double (&vn)[N])
+{
     // w = eta2 - J2 b1 = -(v2 + J2 b1);  Y'w;  G = J2 A1;  Y'G
     double w[N], G[N][N];
 #pragma unroll
@@ -629,7 +637,6 @@ LQK_DEV bool ks_combine_store(KsIn<N> &in, bool b_term, double *o, const double 
             YG[r][c] = u;
         }
     }
-    double Jn[N][N], vn[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         double t = in.v1[r];   // -eta = -(A1'Y'w + eta1)
@@ -645,74 +652,90 @@ LQK_DEV bool ks_combine_store(KsIn<N> &in, bool b_term, double *o, const double 
         }
     }
     sym(Jn);
-    store_jv(o + 2 * KS, Jn, vn);
-    if (!b_term) {
-        if constexpr (LATE) {
-            load_map(bp, in.A2, in.b2);
-            load_c(bp + KS, in.C2);
-        }
-        // YA = Y A1, y = Y (b1 + C1 eta2), YC = Y C1
-        double z[N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = in.b1[r];
-#pragma unroll
-            for (int k = 0; k < N; ++k) t -= in.C1[r][k] * in.v2[k];   // eta2 = -v2
-            z[r] = t;
-        }
-        double YA[N][N], yz[N], YC[N][N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = 0.0;
-#pragma unroll
-            for (int k = 0; k < N; ++k) t += Y[r][k] * z[k];
-            yz[r] = t;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double u = 0.0, x = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    u += Y[r][k] * in.A1[k][c];
-                    x += Y[r][k] * in.C1[k][c];
-                }
-                YA[r][c] = u;
-                YC[r][c] = x;
-            }
-        }
-        double An[N][N], bn[N], T2[N][N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            double t = in.b2[r];
-#pragma unroll
-            for (int k = 0; k < N; ++k) t += in.A2[r][k] * yz[k];
-            bn[r] = t;
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double u = 0.0, x = 0.0;
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    u += in.A2[r][k] * YA[k][c];
-                    x += in.A2[r][k] * YC[k][c];
-                }
-                An[r][c] = u;
-                T2[r][c] = x;
-            }
-        }
-        double Cn[N][N];
-#pragma unroll
-        for (int r = 0; r < N; ++r)
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                double u = in.C2[r][c];
-#pragma unroll
-                for (int k = 0; k < N; ++k) u += T2[r][k] * in.A2[c][k];
-                Cn[r][c] = u;
-            }
-        sym(Cn);
-        store_map(o, An, bn);
-        store_c(o + KS, Cn);
-    }
+}
+template <int N>
+LQK_DEV bool ks_part_j(const KsIn<N> &in, double (&Y)[N][N], double (&Jn)[N][N], double (&vn)[N])
+{
+    const bool ok = ks_inv_y<N>(in, Y);
+    ks_j_rest<N>(in, Y, Jn, vn);
     return ok;
+}
+// Second part (ks_part_ac), when the right operand does not cover the
+// terminal: YA, Y z, YC from Y and in.A1, b1, C1, v2 (ks_ac_y), then the new
+// A~ and C~ (An, bn, Cn) with the neighbour's A~, C~ in.A2, b2, C2 (ks_ac_out).
+template <int N>
+LQK_DEV void ks_ac_y(const KsIn<N> &in, const double (&Y)[N][N], double (&YA)[N][N], double (&yz)[N],
+                     double (&YC)[N][N])
+{
+    // YA = Y A1, y = Y (b1 + C1 eta2), YC = Y C1
+    double z[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = in.b1[r];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t -= in.C1[r][k] * in.v2[k];   // eta2 = -v2
+        z[r] = t;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) t += Y[r][k] * z[k];
+        yz[r] = t;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = 0.0, x = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                u += Y[r][k] * in.A1[k][c];
+                x += Y[r][k] * in.C1[k][c];
+            }
+            YA[r][c] = u;
+            YC[r][c] = x;
+        }
+    }
+}
+template <int N>
+LQK_DEV void ks_ac_out(const KsIn<N> &in, const double (&YA)[N][N], const double (&yz)[N], const double (&YC)[N][N],
+                       double (&An)[N][N], double (&bn)[N], double (&Cn)[N][N])
+{
+    double T2[N][N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        double t = in.b2[r];
+#pragma unroll
+        for (int k = 0; k < N; ++k) t += in.A2[r][k] * yz[k];
+        bn[r] = t;
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = 0.0, x = 0.0;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                u += in.A2[r][k] * YA[k][c];
+                x += in.A2[r][k] * YC[k][c];
+            }
+            An[r][c] = u;
+            T2[r][c] = x;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int c = 0; c < N; ++c) {
+            double u = in.C2[r][c];
+#pragma unroll
+            for (int k = 0; k < N; ++k) u += T2[r][k] * in.A2[c][k];
+            Cn[r][c] = u;
+        }
+    sym(Cn);
+}
+template <int N>
+LQK_DEV void ks_part_ac(const KsIn<N> &in, const double (&Y)[N][N], double (&An)[N][N], double (&bn)[N],
+                        double (&Cn)[N][N])
+{
+    double YA[N][N], yz[N], YC[N][N];
+    ks_ac_y<N>(in, Y, YA, yz, YC);
+    ks_ac_out<N>(in, YA, yz, YC, An, bn, Cn);
 }
 
 template <int N>
@@ -739,30 +762,54 @@ __global__ __launch_bounds__(64) void k_small_value_ks(const InstDesc *__restric
     const bool b_term = (s + 2 * dd - 1 >= last);
     const double *bp = Xin + (int64_t)(gx + dd) * 3 * TILE;
     KsIn<N> in;
-    ks_load<N, TILE, true>(a, bp, b_term, in);
-    const bool ok = ks_combine_store<N, TILE, true>(in, b_term, o, bp);
+    double Y[N][N], Jn[N][N], vn[N];
+    ks_load<N, TILE>(a, bp, in);
+    const bool ok = ks_part_j<N>(in, Y, Jn, vn);
+    store_jv(o + 2 * TILE, Jn, vn);
+    if (!b_term) {
+        ks_load_ac<N, TILE>(bp, in);
+        double An[N][N], bn[N], Cn[N][N];
+        ks_part_ac<N>(in, Y, An, bn, Cn);
+        store_map(o, An, bn);
+        store_c(o + TILE, Cn);
+    }
     if (!ok) report1(status, d.orig, SERR_SINGULAR, s * d.L);
 }
 
-// Every level of the suffix scan in one workgroup, for a class (n <= 2) whose
-// scan has at most SCAN1_MAX entries: the entries are copied once into LDS (compact
-// (N+1)^2 blocks), each level reads its inputs into registers, waits for the
-// whole group, and writes its results in place; a barrier replaces the launch
-// between levels.  The final entries are copied back to the entries' slots of
-// X, in place.  Same schedule and arithmetic as the per-level kernel.
+// Every level of the suffix scan in one workgroup, for a class whose scan has
+// at most value_scan1_cap(N) entries: the entries are copied once into LDS
+// (compact (N+1)^2 blocks); each level computes its two parts into registers
+// from LDS, each followed by a barrier and the in-place write of its results
+// (three barriers a level, in place of a launch).  The final entries are
+// copied back to the entries' slots of X, in place.  Same schedule and
+// arithmetic as the per-level kernel.
 constexpr int SCAN1_MAX = 512;
+// LDS doubles per entry of the one-block value scan: 3 (n+1)^2, made odd so
+// that the lanes' entries start in different banks
+constexpr int value_scan1_stride(int n) { return 3 * (n + 1) * (n + 1) | 1; }
+// Entries of the one-block value scan, one thread each: within the 160 KiB of
+// LDS of one workgroup (273 at n = 4) and, at n = 3, 4, below the measured
+// crossover where the one compute unit's FP64 issue rate makes the levels
+// slower than per-level launches spread over several (between 321 and 385
+// entries at n = 3, 193 and 209 at n = 4).
+constexpr int value_scan1_cap(int n)
+{
+    const int lds = 163840 / (8 * value_scan1_stride(n));
+    const int measured = n <= 2 ? SCAN1_MAX : (n == 3 ? 352 : 200);
+    return lds < measured ? lds : measured;
+}
 template <int N>
 __global__ __launch_bounds__(SCAN1_MAX) void k_small_value_scan1(const InstDesc *__restrict__ inst,
                                                                   const int32_t *__restrict__ x_start, int batch,
                                                                   int total, int max_nseg, double *__restrict__ X,
                                                                   int32_t *status)
 {
-    constexpr int N1 = N + 1, KS = N1 * N1, SL = 3 * KS;
-    __shared__ double sh[SCAN1_MAX * SL];
+    constexpr int N1 = N + 1, KS = N1 * N1, SL = value_scan1_stride(N);
+    __shared__ double sh[value_scan1_cap(N) * SL];
     const int t = threadIdx.x;
-    for (int idx = t; idx < total * SL; idx += SCAN1_MAX) {
-        const int e = idx / SL, r = idx - e * SL, kind = r / KS;
-        sh[idx] = X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)];
+    for (int idx = t; idx < total * 3 * KS; idx += SCAN1_MAX) {
+        const int e = idx / (3 * KS), r = idx - e * 3 * KS, kind = r / KS;
+        sh[e * SL + r] = X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)];
     }
     bool live = t < total;
     int s = 0, last = 0, orig = 0, L = 0;
@@ -778,17 +825,50 @@ __global__ __launch_bounds__(SCAN1_MAX) void k_small_value_scan1(const InstDesc 
     bool ok = true;
     for (int dd = 1; dd < max_nseg - 1; dd *= 2) {
         const bool act = live && (s + dd <= last);
-        const bool b_term = s + 2 * dd - 1 >= last;
-        KsIn<N> in;
-        if (act) ks_load<N, KS, false>(sh + t * SL, sh + (t + dd) * SL, b_term, in);
+        const bool ac = act && (s + 2 * dd - 1 < last);   // right operand short of the terminal
+        double *me = sh + t * SL;
+        const double *right = sh + (t + dd) * SL;
+        // Each part computes into registers from LDS, waits for the whole
+        // group's reads, then writes in place: the new J~ (read by no one in
+        // the second part) before the reads of A~, C~, the new A~, C~ after.
+        double Y[N][N], Jn[N][N], vn[N], v2[N];
+        if (act) {
+            // C~ and the neighbour's J~ first; the rest once Y is formed
+            KsIn<N> in;
+            load_c(me + KS, in.C1);
+            load_jv(right + 2 * KS, in.J2, in.v2);
+            if (!ks_inv_y<N>(in, Y)) ok = false;
+            load_map(me, in.A1, in.b1);
+            load_jv(me + 2 * KS, in.J1, in.v1);
+            ks_j_rest<N>(in, Y, Jn, vn);
+#pragma unroll
+            for (int r = 0; r < N; ++r) v2[r] = in.v2[r];
+        }
         __syncthreads();
-        if (act && !ks_combine_store<N, KS, false>(in, b_term, sh + t * SL, nullptr)) ok = false;
+        if (act) store_jv(me + 2 * KS, Jn, vn);
+        double An[N][N], bn[N], Cn[N][N];
+        if (ac) {
+            KsIn<N> in;   // own A~, C~ read again (unchanged), the neighbour's old eta kept
+            load_map(me, in.A1, in.b1);
+            load_c(me + KS, in.C1);
+#pragma unroll
+            for (int r = 0; r < N; ++r) in.v2[r] = v2[r];
+            double YA[N][N], yz[N], YC[N][N];
+            ks_ac_y<N>(in, Y, YA, yz, YC);
+            ks_load_ac<N, KS>(right, in);
+            ks_ac_out<N>(in, YA, yz, YC, An, bn, Cn);
+        }
+        __syncthreads();
+        if (ac) {
+            store_map(me, An, bn);
+            store_c(me + KS, Cn);
+        }
         __syncthreads();
     }
     if (!ok) report1(status, orig, SERR_SINGULAR, s * L);
-    for (int idx = t; idx < total * SL; idx += SCAN1_MAX) {
-        const int e = idx / SL, r = idx - e * SL, kind = r / KS;
-        X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)] = sh[idx];
+    for (int idx = t; idx < total * 3 * KS; idx += SCAN1_MAX) {
+        const int e = idx / (3 * KS), r = idx - e * 3 * KS, kind = r / KS;
+        X[(int64_t)e * 3 * TILE + kind * TILE + (r - kind * KS)] = sh[e * SL + r];
     }
 }
 
@@ -1087,12 +1167,12 @@ __global__ __launch_bounds__(SCAN1_MAX) void k_small_affine_scan1(const InstDesc
                                                                    int total, int max_nseg, int suffix,
                                                                    double *__restrict__ Y)
 {
-    constexpr int N1 = N + 1, KS = N1 * N1;
-    __shared__ double sh[SCAN1_MAX * KS];
+    constexpr int N1 = N + 1, KS = N1 * N1, AS = KS | 1;   // odd LDS stride: lanes' entries in different banks
+    __shared__ double sh[SCAN1_MAX * AS];
     const int t = threadIdx.x;
     for (int idx = t; idx < total * KS; idx += SCAN1_MAX) {
         const int e = idx / KS;
-        sh[idx] = Y[(int64_t)e * TILE + (idx - e * KS)];
+        sh[e * AS + (idx - e * KS)] = Y[(int64_t)e * TILE + (idx - e * KS)];
     }
     bool live = t < total;
     int s = 0, nseg = 0;
@@ -1107,15 +1187,15 @@ __global__ __launch_bounds__(SCAN1_MAX) void k_small_affine_scan1(const InstDesc
         double F[N][N], e[N];
         if (live) {
             const int avail = suffix ? (nseg - s) / dd : s / dd;
-            affine_chain<N, KS>(sh, t, suffix ? dd : -dd, min(RAD - 1, avail), F, e);
+            affine_chain<N, AS>(sh, t, suffix ? dd : -dd, min(RAD - 1, avail), F, e);
         }
         __syncthreads();
-        if (live) store_map(sh + t * KS, F, e);
+        if (live) store_map(sh + t * AS, F, e);
         __syncthreads();
     }
     for (int idx = t; idx < total * KS; idx += SCAN1_MAX) {
         const int e = idx / KS;
-        Y[(int64_t)e * TILE + (idx - e * KS)] = sh[idx];
+        Y[(int64_t)e * TILE + (idx - e * KS)] = sh[e * AS + (idx - e * KS)];
     }
 }
 
@@ -1383,17 +1463,11 @@ void launch_small_value_ks(int n, int64_t total, hipStream_t st, const InstDesc 
 bool launch_small_value_scan1(int n, int64_t total, hipStream_t st, const InstDesc *inst, const int32_t *x_start,
                               int batch, int max_nseg, double *X, int32_t *status)
 {
-    // n <= 2 only: at n = 4 the combine's inputs, all loaded before the
-    // in-place write, no longer fit the vector registers and the one-block
-    // scan was measured slower than the per-level launches
     const char *e = getenv("LQSCAN_SCAN1");   // "0": the per-level kernels always
-    if (n > 2 || total > SCAN1_MAX || (e && e[0] == '0' && e[1] == 0)) return false;
-    if (n == 1)
-        hipLaunchKernelGGL((k_small_value_scan1<1>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total,
-                           max_nseg, X, status);
-    else
-        hipLaunchKernelGGL((k_small_value_scan1<2>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total,
-                           max_nseg, X, status);
+    if (n < 1 || n > 4 || total > value_scan1_cap(n) || (e && e[0] == '0' && e[1] == 0)) return false;
+#define CALL(N) hipLaunchKernelGGL((k_small_value_scan1<N>), dim3(1), dim3(SCAN1_MAX), 0, st, inst, x_start, batch, (int)total, max_nseg, X, status)
+    LQK_SMALL_N(n, CALL)
+#undef CALL
     return true;
 }
 

@@ -127,13 +127,16 @@ def test_small_path_matches_tile_path(lq, monkeypatch):
 
 
 @pytest.mark.parametrize("n,m,Ts,L", [(2, 1, [1000], 4), (1, 1, [200, 37, 5], 3), (2, 2, [300, 64, 2, 129], 5),
-                                      (2, 1, [1], 1), (4, 1, [1000], 4), (3, 2, [77, 5], 3)])
+                                      (2, 1, [1], 1), (4, 1, [1000], 4), (3, 2, [77, 5], 3), (4, 1, [796], 4),
+                                      (3, 1, [1000, 47], 3), (4, 2, [9, 1, 40], 2), (1, 1, [2044], 4)])
 def test_one_block_scans_equal_per_level(lq, monkeypatch, n, m, Ts, L):
-    """Classes with at most 256 scan entries run every level of the rollout's
-    affine scan (any n <= 4) and of the value scan (n <= 2) in one workgroup
-    (entries in LDS, a barrier between levels); the same arithmetic as the
-    per-level launches (LQSCAN_SCAN1=0), so both agree to rounding and both
-    match the oracle.  Entry counts 251, 85, 104, 2, 251 and 30."""
+    """Classes with at most 512 scan entries run every level of the rollout's
+    affine scan in one workgroup, and so does the value scan up to its cap
+    (512 entries at n <= 2, 352 at n = 3, 200 at n = 4): entries in LDS, a
+    barrier between levels, the same arithmetic as the per-level launches
+    (LQSCAN_SCAN1=0), so both agree to rounding and both match the oracle.
+    Entry counts 251, 85, 104, 2, 251 (above the n = 4 cap: the affine scans
+    only), 30, 200 (the n = 4 cap), 352 (the n = 3 cap), 29 and 512."""
     rng = np.random.default_rng(40 + n + len(Ts))
     insts = [W.lq_instance_general(rng, n, m, T) if j % 2 else W.lq_instance(rng, n, m, T) for j, T in enumerate(Ts)]
     a, sa = solve(lq, insts, seg_len=L)
