@@ -971,9 +971,8 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     lq_value val{Wk.S, Wk.s, Wk.G, Wk.gm};
     const lq_status r = lq_solve(p, &lp, nullptr, &val, Wk.dx, Wk.du, nullptr, workspace, Wk.status, stream);
     if (r != LQ_OK) return r;
-    // candidate, decision, commit
+    // candidate, decision and commit
     lqk::launch_nmpc_candidate(st, N, Wk, state->x, state->u, state->scal);
-    lqk::launch_nmpc_commit(st, N, Wk, state->x, state->u, state->scal);
     return launched();
 }
 

@@ -78,7 +78,6 @@ void launch_costate_apply(int nk, int pr, unsigned grid, hipStream_t st, NmpcWor
 void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
                               const double *scal);
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init);
-void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal);
-void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal);
+void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, double *scal);
 
 }  // namespace lqk

@@ -28,8 +28,9 @@
 //                            (block reductions), gain ratio rho = (J_mu(u) -
 //                            J_mu(u + du)) / pred; accept if pred > 0 and rho > 0:
 //                            alpha *= max(1/3, 1 - (2 rho - 1)^3), nu = 2; else
-//                            alpha *= nu, nu *= 2
-//   7. k_nmpc_commit         on acceptance the candidate replaces the nominal.
+//                            alpha *= nu, nu *= 2; on acceptance the candidate
+//                            then replaces the nominal (the same block, after
+//                            the decision).
 #include <algorithm>
 #include <cfloat>
 #include <cstdlib>
@@ -853,10 +854,10 @@ constexpr int RED = 256;
 // thread's loads of a stage are issued together instead of one loop trip
 // at a time.
 template <int RB, int NX, int NU>
-__global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, const double *x, const double *u,
-                                                    double *scal)
+__global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, double *x, double *u, double *scal)
 {
     __shared__ double sp[RB], s0[RB], s1[RB], sg[RB];
+    __shared__ int s_acc;
     const int t = threadIdx.x, b = blockIdx.x;
     const int n = NX > 0 ? NX : N.nx, m = NX > 0 ? NU : N.nu, T = N.T;
     if (level_done(scal, b)) return;   // uniform over the block
@@ -903,55 +904,62 @@ __global__ __launch_bounds__(RB) void k_nmpc_reduce(NmpcPtrs N, NmpcWork Wk, con
             sg[t] = fmax(sg[t], sg[t + h]);
         }
     }
-    if (t != 0) return;
-    pred = sp[0];
-    {
-        const double *dxT = dx + (int64_t)T * n;
-        double qf = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) qf += dxT[i] * N.QT[i * n + j] * dxT[j];
-        pred += 0.5 * qf;
+    if (t == 0) {
+        pred = sp[0];
+        {
+            const double *dxT = dx + (int64_t)T * n;
+            double qf = 0.0;
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) qf += dxT[i] * N.QT[i * n + j] * dxT[j];
+            pred += 0.5 * qf;
+        }
+        pred = -pred;
+        J0 = s0[0] + terminal_cost(N, n, T, x + (int64_t)T * n);
+        J1 = s1[0] + terminal_cost(N, n, T, xc + (int64_t)T * n);
+        const bool lq_ok = (Wk.status[b] == 0);
+        if (!lq_ok) {
+            pred = 0.0;
+            J1 = INFINITY;
+        }
+        double alpha = scal[NMPC_ALPHA], nu = scal[NMPC_NU];
+        double rho = -INFINITY;
+        bool acc = false;
+        if (pred > 0.0 && isfinite(J1)) {
+            rho = (J0 - J1) / pred;
+            acc = rho > 0.0;
+        }
+        if (acc) {
+            const double tt = 2.0 * rho - 1.0;
+            const double f = 1.0 - tt * tt * tt;
+            alpha *= (f > 1.0 / 3.0 ? f : 1.0 / 3.0);
+            nu = 2.0;
+        } else {
+            alpha *= nu;
+            nu *= 2.0;
+        }
+        scal[NMPC_PRED] = pred;
+        scal[NMPC_GRAD] = sg[0];
+        scal[NMPC_COST] = acc ? J1 : J0;
+        scal[NMPC_COST_NEW] = J1;
+        scal[NMPC_ALPHA] = alpha;
+        scal[NMPC_NU] = nu;
+        scal[NMPC_RHO] = rho;
+        scal[NMPC_ACCEPTED] = acc ? 1.0 : 0.0;
+        s_acc = acc;
+        // level control: the level ends after the iteration that started from
+        // |d|_inf <= LEVEL_TOL or that used up LEVEL_MAX iterations
+        const double tol = scal[NMPC_LEVEL_TOL];
+        if (tol > 0.0) {
+            const double it = scal[NMPC_LEVEL_ITERS] + 1.0;
+            scal[NMPC_LEVEL_ITERS] = it;
+            if (sg[0] <= tol || it >= scal[NMPC_LEVEL_MAX]) scal[NMPC_LEVEL_DONE] = 0.5;
+        }
     }
-    pred = -pred;
-    J0 = s0[0] + terminal_cost(N, n, T, x + (int64_t)T * n);
-    J1 = s1[0] + terminal_cost(N, n, T, xc + (int64_t)T * n);
-    const bool lq_ok = (Wk.status[b] == 0);
-    if (!lq_ok) {
-        pred = 0.0;
-        J1 = INFINITY;
-    }
-    double alpha = scal[NMPC_ALPHA], nu = scal[NMPC_NU];
-    double rho = -INFINITY;
-    bool acc = false;
-    if (pred > 0.0 && isfinite(J1)) {
-        rho = (J0 - J1) / pred;
-        acc = rho > 0.0;
-    }
-    if (acc) {
-        const double tt = 2.0 * rho - 1.0;
-        const double f = 1.0 - tt * tt * tt;
-        alpha *= (f > 1.0 / 3.0 ? f : 1.0 / 3.0);
-        nu = 2.0;
-    } else {
-        alpha *= nu;
-        nu *= 2.0;
-    }
-    scal[NMPC_PRED] = pred;
-    scal[NMPC_GRAD] = sg[0];
-    scal[NMPC_COST] = acc ? J1 : J0;
-    scal[NMPC_COST_NEW] = J1;
-    scal[NMPC_ALPHA] = alpha;
-    scal[NMPC_NU] = nu;
-    scal[NMPC_RHO] = rho;
-    scal[NMPC_ACCEPTED] = acc ? 1.0 : 0.0;
-    // level control: the level ends after the iteration that started from
-    // |d|_inf <= LEVEL_TOL or that used up LEVEL_MAX iterations
-    const double tol = scal[NMPC_LEVEL_TOL];
-    if (tol > 0.0) {
-        const double it = scal[NMPC_LEVEL_ITERS] + 1.0;
-        scal[NMPC_LEVEL_ITERS] = it;
-        if (sg[0] <= tol || it >= scal[NMPC_LEVEL_MAX]) scal[NMPC_LEVEL_DONE] = 0.5;
-    }
+    // commit: every thread's reads of x, u are behind the reduction's barriers
+    __syncthreads();
+    if (!s_acc) return;
+    for (int i = t; i < (T + 1) * n; i += RB) x[i] = xc[i];
+    for (int i = t; i < T * m; i += RB) u[i] = uc[i];
 }
 
 // ADMM consensus and multiplier steps of Sec. II-C (eq:admm-step-4, -5) for
@@ -997,19 +1005,6 @@ __global__ __launch_bounds__(RED) void k_admm_update(NmpcPtrs N, const double *u
         scal[NMPC_RP] = sp[0];
         scal[NMPC_RD] = sd[0];
     }
-}
-
-// Step 7: on acceptance the candidate becomes the nominal (grid y: instance).
-__global__ __launch_bounds__(256) void k_nmpc_commit(NmpcPtrs N, const NmpcWork Wk, double *x, double *u,
-                                                     const double *scal)
-{
-    const int b = blockIdx.y;
-    if (level_done(scal, b, true)) return;   // the level's last iteration (0.5) still commits
-    if (scal[(int64_t)b * NMPC_NSCAL + NMPC_ACCEPTED] == 0.0) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nx = (int64_t)(N.T + 1) * N.nx, nu = (int64_t)N.T * N.nu;
-    if (i < nx) x[b * nx + i] = Wk.xc[b * nx + i];
-    if (i < nu) u[b * nu + i] = Wk.uc[b * nu + i];
 }
 
 // Receding horizon (one lane per instance): the plant takes one step with the
@@ -1122,8 +1117,7 @@ void launch_nmpc_quadraticise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, c
 #undef QC
 }
 template <int RB>
-static void launch_reduce(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk, const double *x, const double *u,
-                          double *scal)
+static void launch_reduce(hipStream_t st, const NmpcPtrs &N, const NmpcWork &Wk, double *x, double *u, double *scal)
 {
     if (N.nx == 2 && N.nu == 1)
         hipLaunchKernelGGL((k_nmpc_reduce<RB, 2, 1>), dim3(N.batch), dim3(RB), 0, st, N, Wk, x, u, scal);
@@ -1161,7 +1155,7 @@ static bool launch_rollout_par(hipStream_t st, const NmpcPtrs &N, const NmpcWork
     return true;
 }
 
-void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u, double *scal)
+void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, double *scal)
 {
     if (!launch_rollout_par(st, N, Wk, x, u)) launch_rollout(st, N, u, Wk.du, Wk.xc, Wk.uc, Wk.scal);
     if (N.T <= 96)
@@ -1174,11 +1168,6 @@ void launch_nmpc_candidate(hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double
 void launch_admm_update(hipStream_t st, NmpcPtrs N, const double *u, double *scal, int init)
 {
     hipLaunchKernelGGL(k_admm_update, dim3(N.batch), dim3(RED), 0, st, N, u, scal, init);
-}
-void launch_nmpc_commit(hipStream_t st, NmpcPtrs N, NmpcWork Wk, double *x, double *u, const double *scal)
-{
-    const int64_t cnt = std::max((int64_t)(N.T + 1) * N.nx, (int64_t)N.T * N.nu);
-    hipLaunchKernelGGL(k_nmpc_commit, dim3((unsigned)((cnt + 255) / 256), N.batch), dim3(256), 0, st, N, Wk, x, u, scal);
 }
 
 }  // namespace lqk
