@@ -947,8 +947,8 @@ lq_status newton_step(const lq_plan *p, const nmpc_problem *prob, const nmpc_sta
     Wk.scal = state->scal;
     char *ws = (char *)workspace;
     double *Ya = (double *)(ws + p->off_Ya), *Yb = (double *)(ws + p->off_Yb);
-    lqk::launch_nmpc_clear(st, N, Wk);
-    // linearisation and the co-state pass (suffix scan of [[A', g], [0, 1]])
+    // linearisation (with the step's clears) and the co-state pass (suffix
+    // scan of [[A', g], [0, 1]])
     lqk::launch_nmpc_linearise(p->prec, st, N, Wk, state->x, state->u);
     // (n <= 4: the per-lane kernels, in FP64 whatever the plan's precision)
     if (p->small)

@@ -68,7 +68,6 @@ void launch_small_roll_apply(int n, int m, int64_t total, hipStream_t st, ProbPt
                              double *lam);
 
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u);
-void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk);
 void launch_nmpc_shift(hipStream_t st, NmpcPtrs N, double *x0, double *u, double *uapp);
 void launch_nmpc_linearise(int pr, hipStream_t st, NmpcPtrs N, NmpcWork Wk, const double *x, const double *u);
 void launch_costate_fold(int nk, int pr, unsigned grid, hipStream_t st, NmpcWork Wk, const InstDesc *inst,

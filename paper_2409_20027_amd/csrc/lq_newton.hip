@@ -10,7 +10,9 @@
 //
 // Steps (all enqueued on the caller's stream, decisions taken on the device):
 //   1. k_nmpc_linearise      A_k = I + h df/dx, B_k = h df/du (tanh model:
-//                            df/dx = diag(1 - tanh^2 z) W, z = W x_k), g_k = Q (x_k - ref_k)
+//                            df/dx = diag(1 - tanh^2 z) W, z = W x_k), g_k = Q (x_k - ref_k);
+//                            its stage-0 lane also clears the step's LQ status
+//                            and zero initial state and copies Q_T
 //   2. co-state suffix scan  lambda_T = Q_T(x_T - ref_T),
 //                            lambda_k = g_k + A_k' lambda_{k+1}   (eq:co-state-eq;
 //                            homogeneous maps [[A_k', g_k], [0, 1]], Alg. 1)
@@ -621,26 +623,6 @@ __global__ __launch_bounds__(PAR_NT) void k_nmpc_rollout_par(NmpcPtrs N, const d
     }
 }
 
-// Step 0 (one block per instance): clear the internal LQ status, the LQ's
-// zero initial state and replicate Q_T.
-__global__ __launch_bounds__(64) void k_nmpc_clear(NmpcPtrs N, NmpcWork Wk)
-{
-    const int b = blockIdx.x, n = N.nx;
-    if (Wk.scal) {
-        // the step after a level's last iteration: the level is over (0.5 -> 1)
-        double *sc = Wk.scal + (int64_t)b * NMPC_NSCAL;
-        const double d = sc[NMPC_LEVEL_DONE];
-        __syncthreads();
-        if (d >= 0.5) {
-            if (threadIdx.x == 0) sc[NMPC_LEVEL_DONE] = 1.0;
-            return;
-        }
-    }
-    if (threadIdx.x == 0) Wk.status[b] = 0;
-    for (int i = threadIdx.x; i < n; i += 64) Wk.zero[(int64_t)b * n + i] = 0.0;
-    for (int i = threadIdx.x; i < n * n; i += 64) Wk.QTb[(int64_t)b * n * n + i] = N.QT[i];
-}
-
 // Step 1 (one lane per stage of every instance), arithmetic type RT, results
 // stored in FP64.  NX > 0: compile-time sizes nx = NX, nu = NU (the tanh
 // model's per-stage arrays then stay in registers).
@@ -651,7 +633,21 @@ __global__ __launch_bounds__(256) void k_nmpc_linearise(NmpcPtrs N, NmpcWork Wk,
     const int n = NX > 0 ? NX : N.nx, m = NX > 0 ? NU : N.nu, T = N.T;
     if (idx >= (int64_t)N.batch * (T + 1)) return;
     const int b = (int)(idx / (T + 1)), k = (int)(idx - (int64_t)b * (T + 1));
+    if (k == 0 && Wk.scal) {
+        // the step after a level's last iteration: the level is over (0.5 ->
+        // 1; the instance's other lanes read 0.5 or 1 and return too)
+        double *sc = Wk.scal + (int64_t)b * NMPC_NSCAL;
+        if (sc[NMPC_LEVEL_DONE] >= 0.5) {
+            sc[NMPC_LEVEL_DONE] = 1.0;
+            return;
+        }
+    }
     if (level_done(Wk.scal, b)) return;
+    if (k == 0) {   // the instance's internal LQ status, zero initial state and copy of Q_T, read later in the step
+        Wk.status[b] = 0;
+        for (int i = 0; i < n; ++i) Wk.zero[(int64_t)b * n + i] = 0.0;
+        for (int i = 0; i < n * n; ++i) Wk.QTb[(int64_t)b * n * n + i] = N.QT[i];
+    }
     const int64_t gk = (int64_t)b * T + k;   // packed stage index (k < T)
     const double *xk = x + ((int64_t)b * (T + 1) + k) * n;
     const double *rk = N.xref + (int64_t)k * n;
@@ -1064,10 +1060,6 @@ static void launch_rollout(hipStream_t st, const NmpcPtrs &N, const double *u, c
 void launch_nmpc_init(hipStream_t st, NmpcPtrs N, double *x, const double *u)
 {
     launch_rollout(st, N, u, nullptr, x, nullptr, nullptr);
-}
-void launch_nmpc_clear(hipStream_t st, NmpcPtrs N, NmpcWork Wk)
-{
-    hipLaunchKernelGGL(k_nmpc_clear, dim3(N.batch), dim3(64), 0, st, N, Wk);
 }
 void launch_nmpc_shift(hipStream_t st, NmpcPtrs N, double *x0, double *u, double *uapp)
 {
