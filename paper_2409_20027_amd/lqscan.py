@@ -709,6 +709,9 @@ class NewtonMPC:
                                    _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(self.x0),
                                    float(p.umin), float(p.umax), model, prm)
         self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
+        # ip_solve's chunk graph, kept across solves while the problem struct (sizes,
+        # parameters, pointers) is byte for byte the one it was captured with
+        self._chunk_graph, self._chunk_key = None, None
 
     def _shape(self, a, rows, cols):
         a = a.cpu().numpy()
@@ -906,12 +909,18 @@ class NewtonMPC:
         that starts from |dJ_mu/du|_inf <= tol, or after max_iter iterations.
 
         graph: the level ends on the device and a HIP graph of level_chunk steps,
-        captured once per solve, is replayed with one device-to-host copy of the
-        scalars per replay (into pinned memory); eagerly (graph=False) the gradient
-        norm is read back after every step.  Returns dict(u, x, iters, level_iters,
-        and with trace the per-iteration mu, cost, grad, accept, pred).
+        captured on the first solve (and again if prob_c has changed since), is
+        replayed with one device-to-host copy of the scalars per replay (into pinned
+        memory); eagerly (graph=False) the gradient norm is read back after every
+        step.  Returns dict(u, x, iters, level_iters, and with trace the
+        per-iteration mu, cost, grad, accept, pred).
         """
-        g = self._capture_chunk(self.level_chunk) if graph else None
+        g = None
+        if graph:
+            key = bytes(self.prob_c)
+            if self._chunk_key != key:
+                self._chunk_graph, self._chunk_key = self._capture_chunk(self.level_chunk), key
+            g = self._chunk_graph
         self.init(alpha0, nu0)
         host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
         rows, level_iters = ([] if trace else None), []

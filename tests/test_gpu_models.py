@@ -227,6 +227,39 @@ def test_graph_replayed_solves_equal_eager(lq, name):
     assert np.array_equal(ea["rp"], ga["rp"]) and np.array_equal(ea["u"], ga["u"])
 
 
+def test_ip_solve_keeps_its_graph_while_the_problem_is_unchanged(lq):
+    """ip_solve captures its chunk graph on the first solve and replays that graph
+    on later solves of the same problem, bit for bit equal, also after an
+    admm_solve that changes the problem struct and restores it; a changed problem
+    struct (a model parameter here) is captured again, and its solve equals that
+    of a fresh solver built with the new parameter."""
+    import dataclasses
+    p = MODELS["pendulum"](60)
+    args = dict(mu0=W.IP_MU0, zeta=W.IP_ZETA, mu_min=W.IP_MU_MIN, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+    aargs = dict(rho=W.ADMM_RHO["pendulum"] * p.h, eps=W.ADMM_EPS, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
+                 max_admm=40, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
+
+    def same(a, b):
+        assert np.array_equal(a["level_iters"], b["level_iters"]) and np.array_equal(a["cost"], b["cost"])
+        assert np.array_equal(a["u"], b["u"]) and np.array_equal(a["x"], b["x"])
+
+    s = lq.NewtonMPC(p, seg_len=W.IP_SEG_LEN)
+    a = s.ip_solve(**args)
+    g1 = s._chunk_graph
+    same(a, s.ip_solve(**args))
+    assert s._chunk_graph is g1
+    s.admm_solve(**aargs)
+    same(a, s.ip_solve(**args))
+    assert s._chunk_graph is g1
+    prm = np.array(p.param, dtype=np.float64)
+    prm[0] *= 1.05
+    s.prob_c.param[0] = float(prm[0])
+    d = s.ip_solve(**args)
+    assert s._chunk_graph is not g1
+    same(d, lq.NewtonMPC(dataclasses.replace(p, param=prm), seg_len=W.IP_SEG_LEN).ip_solve(**args))
+
+
 # --------------------------------------------------------------------------
 # Batches and receding-horizon MPC (Sec. V)
 # --------------------------------------------------------------------------
