@@ -709,9 +709,12 @@ class NewtonMPC:
                                    _f64(d["R"]), _f64(d["QT"]), _f64(d["xref"]), _f64(self.x0),
                                    float(p.umin), float(p.umax), model, prm)
         self.state_c = NMPCStateC(_f64(self.x), _f64(self.u), _f64(self.scal))
-        # ip_solve's chunk graph, kept across solves while the problem struct (sizes,
-        # parameters, pointers) is byte for byte the one it was captured with
+        # ip_solve's chunk graph and the single-step graphs of admm_solve and
+        # mpc_simulate, kept across calls while the problem struct (sizes, parameters,
+        # pointers) is byte for byte the one they were captured with
         self._chunk_graph, self._chunk_key = None, None
+        self._step_graphs = {}
+        self._admm_zv = None
 
     def _shape(self, a, rows, cols):
         a = a.cpu().numpy()
@@ -762,6 +765,17 @@ class NewtonMPC:
         with torch.cuda.graph(g, stream=side):
             newton_step(self.plan, self.prob_c, self.state_c, self.ws)
         torch.cuda.current_stream().wait_stream(side)
+        return g
+
+    def _kept_step_graph(self):
+        """The captured single step for the current problem struct (captured on first
+        use; at most four structs kept)."""
+        key = bytes(self.prob_c)
+        g = self._step_graphs.get(key)
+        if g is None:
+            if len(self._step_graphs) >= 4:
+                self._step_graphs.clear()
+            g = self._step_graphs[key] = self._capture_step()
         return g
 
     def _capture_chunk(self, k):
@@ -836,8 +850,11 @@ class NewtonMPC:
         HIP graph captured once per solve.  Returns dict(u, x, z, v, admm_iters, newton_iters,
         inner, rp, rd)."""
         dev = self.x.device
-        z = torch.zeros(self.B * self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
-        v = torch.zeros_like(z)
+        if self._admm_zv is None:   # kept, so that the captured step's pointers stay valid
+            self._admm_zv = torch.zeros(2, self.B * self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
+        z, v = self._admm_zv[0], self._admm_zv[1]
+        z.zero_()
+        v.zero_()
         self.prob_c.admm_rho = float(rho)
         self.prob_c.admm_z = _f64(z)
         self.prob_c.admm_v = _f64(v)
@@ -845,7 +862,7 @@ class NewtonMPC:
             # ADMM's inner levels average two to three Newton iterations: one step per
             # read-back with the level ended by the host (steps past a level's end
             # would cost more than the read-backs they save)
-            g = self._capture_step() if graph else None
+            g = self._kept_step_graph() if graph else None
             self.init(alpha0, nu0)
             nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
             host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
@@ -878,7 +895,7 @@ class NewtonMPC:
         for B = 1)."""
         B, n, m = self.B, self.p.nx, self.p.nu
         dev = self.x.device
-        g = self._capture_step() if graph else None
+        g = self._kept_step_graph() if graph else None
         x_init = self.x0.clone()
         x_cl = torch.empty(steps + 1, B * n, dtype=torch.float64, device=dev)
         u_cl = torch.empty(steps, B * m, dtype=torch.float64, device=dev)

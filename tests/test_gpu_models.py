@@ -227,12 +227,13 @@ def test_graph_replayed_solves_equal_eager(lq, name):
     assert np.array_equal(ea["rp"], ga["rp"]) and np.array_equal(ea["u"], ga["u"])
 
 
-def test_ip_solve_keeps_its_graph_while_the_problem_is_unchanged(lq):
+def test_solves_keep_their_graphs_while_the_problem_is_unchanged(lq):
     """ip_solve captures its chunk graph on the first solve and replays that graph
     on later solves of the same problem, bit for bit equal, also after an
-    admm_solve that changes the problem struct and restores it; a changed problem
-    struct (a model parameter here) is captured again, and its solve equals that
-    of a fresh solver built with the new parameter."""
+    admm_solve that changes the problem struct and restores it; admm_solve keeps
+    its single-step graph the same way.  A changed problem struct (a model
+    parameter here) is captured again, and its solve equals that of a fresh
+    solver built with the new parameter."""
     import dataclasses
     p = MODELS["pendulum"](60)
     args = dict(mu0=W.IP_MU0, zeta=W.IP_ZETA, mu_min=W.IP_MU_MIN, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
@@ -249,9 +250,13 @@ def test_ip_solve_keeps_its_graph_while_the_problem_is_unchanged(lq):
     g1 = s._chunk_graph
     same(a, s.ip_solve(**args))
     assert s._chunk_graph is g1
-    s.admm_solve(**aargs)
+    aa = s.admm_solve(**aargs)
     same(a, s.ip_solve(**args))
     assert s._chunk_graph is g1
+    ab = s.admm_solve(**aargs)
+    assert len(s._step_graphs) == 1
+    assert np.array_equal(aa["inner"], ab["inner"]) and np.array_equal(aa["rp"], ab["rp"])
+    assert np.array_equal(aa["u"], ab["u"]) and np.array_equal(aa["z"], ab["z"]) and np.array_equal(aa["v"], ab["v"])
     prm = np.array(p.param, dtype=np.float64)
     prm[0] *= 1.05
     s.prob_c.param[0] = float(prm[0])
