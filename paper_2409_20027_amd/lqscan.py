@@ -769,13 +769,23 @@ class NewtonMPC:
 
     def _kept_step_graph(self):
         """The captured single step for the current problem struct (captured on first
-        use; at most four structs kept)."""
-        key = bytes(self.prob_c)
+        use; a few structs kept)."""
+        key = (bytes(self.prob_c), 1)
         g = self._step_graphs.get(key)
         if g is None:
-            if len(self._step_graphs) >= 4:
+            if len(self._step_graphs) >= 8:
                 self._step_graphs.clear()
             g = self._step_graphs[key] = self._capture_step()
+        return g
+
+    def _kept_chunk_graph(self, k):
+        """_capture_chunk(k) for the current problem struct, kept like _kept_step_graph."""
+        key = (bytes(self.prob_c), int(k))
+        g = self._step_graphs.get(key)
+        if g is None:
+            if len(self._step_graphs) >= 8:
+                self._step_graphs.clear()
+            g = self._step_graphs[key] = self._capture_chunk(k)
         return g
 
     def _capture_chunk(self, k):
@@ -803,6 +813,9 @@ class NewtonMPC:
             return self._newton_level_device(mu, tol, max_iter, rows, graph)
         li = 0
         hv = host.view(self.B, NMPC_NSCAL)
+        # the host ends this level: no level control left on the device from an
+        # earlier level ended there (admm_solve mixes both)
+        self._sc[:, [NMPC_LEVEL_TOL, NMPC_LEVEL_DONE]] = 0.0
         while li < max_iter:
             self._sc[:, NMPC_MU] = mu
             if graph is not None:
@@ -842,13 +855,15 @@ class NewtonMPC:
                 break
         return int(hist[-1, :, NMPC_LEVEL_ITERS].max())
 
-    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True):
+    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True, chunk=3):
         """ADMM of Sec. II-C for the control box with newton_step as the inner solver:
         z = min(0, h(u0)), v = 0; repeat Newton iterations on J_AD to |dJ_AD/du|_inf <= tol
         (or max_iter), then nmpc_admm_update, until |r_p|_inf, |r_d|_inf <= eps or max_admm.
         rho is the weight of each stage's augmentation term.  graph: replay newton_step from a
-        HIP graph captured once per solve.  Returns dict(u, x, z, v, admm_iters, newton_iters,
-        inner, rp, rd)."""
+        captured HIP graph, kept for later solves of the same problem; chunk > 1 (at most
+        level_chunk): graphs of that many steps with the inner levels ended on the device,
+        as in ip_solve, instead of one step per read-back.  The results do not depend on
+        the chunk.  Returns dict(u, x, z, v, admm_iters, newton_iters, inner, rp, rd)."""
         dev = self.x.device
         if self._admm_zv is None:   # kept, so that the captured step's pointers stay valid
             self._admm_zv = torch.zeros(2, self.B * self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
@@ -862,7 +877,10 @@ class NewtonMPC:
             # ADMM's inner levels average two to three Newton iterations: one step per
             # read-back with the level ended by the host (steps past a level's end
             # would cost more than the read-backs they save)
-            g = self._kept_step_graph() if graph else None
+            k = max(1, min(int(chunk), self.level_chunk))
+            g = None
+            if graph:   # captured before init (a capture runs one eager step)
+                g = self._kept_step_graph() if k == 1 else self._kept_chunk_graph(k)
             self.init(alpha0, nu0)
             nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
             host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
