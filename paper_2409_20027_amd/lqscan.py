@@ -855,15 +855,18 @@ class NewtonMPC:
                 break
         return int(hist[-1, :, NMPC_LEVEL_ITERS].max())
 
-    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True, chunk=3):
+    def admm_solve(self, *, rho, eps, tol, max_iter, max_admm, alpha0, nu0, graph=True, chunk="auto"):
         """ADMM of Sec. II-C for the control box with newton_step as the inner solver:
         z = min(0, h(u0)), v = 0; repeat Newton iterations on J_AD to |dJ_AD/du|_inf <= tol
         (or max_iter), then nmpc_admm_update, until |r_p|_inf, |r_d|_inf <= eps or max_admm.
         rho is the weight of each stage's augmentation term.  graph: replay newton_step from a
         captured HIP graph, kept for later solves of the same problem; chunk > 1 (at most
         level_chunk): graphs of that many steps with the inner levels ended on the device,
-        as in ip_solve, instead of one step per read-back.  The results do not depend on
-        the chunk.  Returns dict(u, x, z, v, admm_iters, newton_iters, inner, rp, rd)."""
+        as in ip_solve, instead of one step per read-back; "auto": chunks of three while
+        the inner levels average at least five iterations, else one step per read-back
+        (steps past a short level's end cost more than the read-backs they save).  The
+        results do not depend on the chunk.  Returns dict(u, x, z, v, admm_iters,
+        newton_iters, inner, rp, rd)."""
         dev = self.x.device
         if self._admm_zv is None:   # kept, so that the captured step's pointers stay valid
             self._admm_zv = torch.zeros(2, self.B * self.p.T * 2 * self.p.nu, dtype=torch.float64, device=dev)
@@ -877,17 +880,19 @@ class NewtonMPC:
             # ADMM's inner levels average two to three Newton iterations: one step per
             # read-back with the level ended by the host (steps past a level's end
             # would cost more than the read-backs they save)
-            k = max(1, min(int(chunk), self.level_chunk))
-            g = None
+            sizes = (min(3, self.level_chunk), 1) if chunk == "auto" else (max(1, min(int(chunk), self.level_chunk)),)
+            graphs = {}
             if graph:   # captured before init (a capture runs one eager step)
-                g = self._kept_step_graph() if k == 1 else self._kept_chunk_graph(k)
+                for k in sizes:
+                    graphs[k] = self._kept_step_graph() if k == 1 else self._kept_chunk_graph(k)
             self.init(alpha0, nu0)
             nmpc_admm_update(self.plan, self.prob_c, self.state_c, 1)
             host = torch.empty(self.B * NMPC_NSCAL, dtype=torch.float64, pin_memory=True)
             hv = host.view(self.B, NMPC_NSCAL)
             inner, rps, rds = [], [], []
             for _ in range(max_admm):
-                inner.append(self._newton_level(0.0, tol, max_iter, host, None, g))
+                k = sizes[0] if not inner or sum(inner) >= 5 * len(inner) else sizes[-1]
+                inner.append(self._newton_level(0.0, tol, max_iter, host, None, graphs.get(k)))
                 nmpc_admm_update(self.plan, self.prob_c, self.state_c, 0)
                 host.copy_(self.scal, non_blocking=True)
                 torch.cuda.current_stream().synchronize()

@@ -223,7 +223,7 @@ def test_graph_replayed_solves_equal_eager(lq, name):
     aargs = dict(rho=W.ADMM_RHO[name] * p.h, eps=W.ADMM_EPS, tol=W.IP_TOL, max_iter=W.IP_MAX_ITER,
                  max_admm=40, alpha0=W.NMPC_ALPHA0, nu0=W.NMPC_NU0)
     ea = s.admm_solve(**aargs, graph=False)
-    for chunk in (3, 1, 2):
+    for chunk in ("auto", 1, 3):
         ga = s.admm_solve(**aargs, graph=True, chunk=chunk)
         assert ea["admm_iters"] == ga["admm_iters"] and np.array_equal(ea["inner"], ga["inner"])
         assert np.array_equal(ea["rp"], ga["rp"]) and np.array_equal(ea["u"], ga["u"])
