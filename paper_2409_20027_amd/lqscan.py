@@ -877,9 +877,7 @@ class NewtonMPC:
         self.prob_c.admm_z = _f64(z)
         self.prob_c.admm_v = _f64(v)
         try:
-            # ADMM's inner levels average two to three Newton iterations: one step per
-            # read-back with the level ended by the host (steps past a level's end
-            # would cost more than the read-backs they save)
+            # chunk sizes in use (auto: 3 for long inner levels, 1 for short ones)
             sizes = (min(3, self.level_chunk), 1) if chunk == "auto" else (max(1, min(int(chunk), self.level_chunk)),)
             graphs = {}
             if graph:   # captured before init (a capture runs one eager step)
